@@ -1,0 +1,222 @@
+"""FP64 CPU oracle for the FC-RKPM Poisson hot path -- TEST INFRASTRUCTURE ONLY.
+
+A thin ctypes wrapper around ``rkpm_oracle.c``: the traditional neighbour-loop
+RKPM (Galerkin, implicit gradients, direct nodal integration, strong Dirichlet
+values) written from the paper's definitions, with no FFT and no periodic
+wrap-around.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the product
+library never does, and this package never imports the product library.
+
+Every function works on numpy FP64 arrays in C order ``[nz][ny][nx]``
+(x fastest), 0/1 masks as uint8.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rkpm_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc + OpenMP into ``oracle/liborc.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    P = C.c_void_p
+    dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+    up = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+    lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+    ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+    lib.orc_phi1.restype = C.c_double
+    lib.orc_phi1.argtypes = [C.c_double]
+    lib.orc_basis_size.restype = C.c_int
+    lib.orc_basis_size.argtypes = [C.c_int, C.c_int]
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [C.c_int, ip, dp, dp, C.c_int, up, C.c_void_p]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_singular_node.restype = C.c_long
+    lib.orc_singular_node.argtypes = [P]
+    lib.orc_s.restype = C.c_int
+    lib.orc_s.argtypes = [P]
+    lib.orc_noff.restype = C.c_int
+    lib.orc_noff.argtypes = [P]
+    lib.orc_get_b0.argtypes = [P, dp]
+    lib.orc_get_ba.argtypes = [P, dp]
+    for name in ("orc_apply_k", "orc_apply_fr", "orc_apply_nt", "orc_apply_uh",
+                 "orc_apply_vn", "orc_apply_b"):
+        getattr(lib, name).argtypes = [P, dp, dp]
+    lib.orc_apply_k_at.argtypes = [P, dp, lp, C.c_long, dp]
+    lib.orc_cg.restype = C.c_int
+    lib.orc_cg.argtypes = [P, up, dp, dp, C.c_double, C.c_int, C.POINTER(C.c_double)]
+    lib.orc_solve.restype = C.c_int
+    lib.orc_solve.argtypes = [P, up, up, dp, C.c_void_p, dp, C.c_double, C.c_int,
+                              C.POINTER(C.c_double)]
+    lib.orc_adjoint.restype = C.c_int
+    lib.orc_adjoint.argtypes = [P, up, dp, dp, C.c_void_p, C.c_double, C.c_int,
+                                C.POINTER(C.c_double)]
+    _lib = lib
+    return lib
+
+
+def phi1(z: float) -> float:
+    """Cubic B-spline profile of Eq 7 at z = |x|/a."""
+    return _load().orc_phi1(float(z))
+
+
+def basis_size(dim: int, degree: int) -> int:
+    """s = (n+d)!/(d! n!) (Eq 5) as produced by the oracle's basis builder."""
+    return _load().orc_basis_size(dim, degree)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Traditional RKPM on the domain nodes of a uniform box grid.
+
+    dims: box nodes per active axis, in (x, y, z) order.
+    chi: 0/1 domain mask, shape ``dims[::-1]``.
+    vol: nodal quadrature weights V (same shape) or None (V = prod h on chi).
+    """
+
+    def __init__(self, dims, h, at, degree, chi, vol=None):
+        lib = _load()
+        self.dim = len(dims)
+        self.dims = tuple(int(v) for v in dims)
+        self.shape = tuple(reversed(self.dims))
+        n = np.ones(3, np.int32)
+        n[: self.dim] = self.dims
+        hh = np.ones(3)
+        hh[: self.dim] = h
+        aa = np.zeros(3)
+        aa[: self.dim] = at
+        self.chi = np.ascontiguousarray(chi, dtype=np.uint8).reshape(self.shape)
+        self._vol = None if vol is None else _f64(vol).reshape(self.shape)
+        vptr = None if self._vol is None else self._vol.ctypes.data_as(C.c_void_p)
+        self._h = lib.orc_create(self.dim, n, hh, aa, int(degree),
+                                 self.chi.reshape(-1), vptr)
+        if not self._h:
+            raise MemoryError("oracle allocation failed")
+        self.s = lib.orc_s(self._h)
+        self.noff = lib.orc_noff(self._h)
+        self.nn = int(np.prod(self.dims))
+        self.singular_node = lib.orc_singular_node(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    # --- coefficient fields -------------------------------------------------
+    def b0(self):
+        """b^0 (Eq 83) per node: array [s, *shape]."""
+        out = np.empty(self.nn * self.s)
+        _load().orc_get_b0(self._h, out)
+        return out.reshape(self.nn, self.s).T.reshape((self.s,) + self.shape).copy()
+
+    def balpha(self):
+        """b^alpha (Eq 84-85, per-axis, scaled basis): array [dim, s, *shape]."""
+        out = np.empty(self.nn * self.dim * self.s)
+        _load().orc_get_ba(self._h, out)
+        a = out.reshape(self.nn, self.dim, self.s).transpose(1, 2, 0)
+        return a.reshape((self.dim, self.s) + self.shape).copy()
+
+    # --- operators ----------------------------------------------------------
+    def _op(self, name, x):
+        x = _f64(x).reshape(-1)
+        out = np.empty(self.nn)
+        getattr(_load(), name)(self._h, x, out)
+        return out.reshape(self.shape)
+
+    def apply_k(self, d):
+        """Unmasked K d over the domain nodes (Eq 26 with nodal integration)."""
+        return self._op("orc_apply_k", d)
+
+    def apply_k_free(self, d, free):
+        """chi_Omega o K (chi_Omega o d): the operator CG works with."""
+        f = np.asarray(free).astype(bool)
+        return np.where(f, self.apply_k(np.where(f, d, 0.0)), 0.0)
+
+    def apply_fr(self, r):
+        """Load vector f^r (Eq 59)."""
+        return self._op("orc_apply_fr", r)
+
+    def apply_nt(self, y):
+        """N^T y."""
+        return self._op("orc_apply_nt", y)
+
+    def apply_uh(self, d):
+        """u^h = N d at the nodes (Eq 62)."""
+        return self._op("orc_apply_uh", d)
+
+    def apply_vn(self, z):
+        """V o N z."""
+        return self._op("orc_apply_vn", z)
+
+    def apply_b(self, d):
+        """Implicit-gradient field B d: array [dim, *shape]."""
+        x = _f64(d).reshape(-1)
+        out = np.empty(self.nn * self.dim)
+        _load().orc_apply_b(self._h, x, out)
+        return out.reshape((self.dim,) + self.shape)
+
+    def apply_k_at(self, d, idx):
+        """(K d)_I at flat node indices idx only."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1)
+        out = np.empty(idx.size)
+        _load().orc_apply_k_at(self._h, _f64(d).reshape(-1), idx, idx.size, out)
+        return out
+
+    # --- solvers ------------------------------------------------------------
+    def cg(self, free, rhs, x0=None, tol=1e-12, maxit=100000):
+        free = np.ascontiguousarray(free, dtype=np.uint8).reshape(-1)
+        x = np.zeros(self.nn) if x0 is None else _f64(x0).reshape(-1).copy()
+        rel = C.c_double(0.0)
+        it = _load().orc_cg(self._h, free, _f64(rhs).reshape(-1), x, tol, maxit,
+                            C.byref(rel))
+        return x.reshape(self.shape), it, rel.value
+
+    def solve(self, free, dirichlet, r, g=None, x0=None, tol=1e-12, maxit=100000):
+        """Strong-Dirichlet static solve; returns (d, iterations, rel. residual)."""
+        free = np.ascontiguousarray(free, dtype=np.uint8).reshape(-1)
+        dirm = np.ascontiguousarray(dirichlet, dtype=np.uint8).reshape(-1)
+        d = np.zeros(self.nn) if x0 is None else _f64(x0).reshape(-1).copy()
+        gg = None if g is None else _f64(g).reshape(-1)
+        gptr = None if gg is None else gg.ctypes.data_as(C.c_void_p)
+        rel = C.c_double(0.0)
+        it = _load().orc_solve(self._h, free, dirm, _f64(r).reshape(-1), gptr, d,
+                               tol, maxit, C.byref(rel))
+        return d.reshape(self.shape), it, rel.value
+
+    def adjoint(self, free, dl_du, tol=1e-12, maxit=100000):
+        """dL/dr = V o N K_ff^-1 chi_Omega o N^T dL/du^h; returns (grad, z, its)."""
+        free = np.ascontiguousarray(free, dtype=np.uint8).reshape(-1)
+        g = np.empty(self.nn)
+        z = np.empty(self.nn)
+        rel = C.c_double(0.0)
+        it = _load().orc_adjoint(self._h, free, _f64(dl_du).reshape(-1), g,
+                                 z.ctypes.data_as(C.c_void_p), tol, maxit, C.byref(rel))
+        return g.reshape(self.shape), z.reshape(self.shape), it
