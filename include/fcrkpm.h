@@ -1,0 +1,225 @@
+/*
+ * fcrkpm.h -- C ABI of the MI355X (gfx950) FC-RKPM Poisson library.
+ *
+ * The library evaluates the fast-convolving reproducing kernel particle method
+ * of arXiv 2403.19854 for the Galerkin Poisson problem (Sec 2.2, Eq 8-9) on a
+ * uniform periodic box grid that embeds the domain (Sec 4.1, Sec 5.1): every
+ * RK sum is a circular convolution computed with a hand-written 3D FFT on the
+ * GPU (Sec 3, Eq 34).
+ *
+ * Conventions shared by every call
+ *   - Arrays are DEVICE pointers owned by the caller; the library never frees
+ *     or retains them past the call (setup copies what it keeps).
+ *   - Node layout is C order [nz][ny][nx], x fastest; unused axes have n = 1.
+ *   - Every call enqueues its work on the caller's HIP stream `stream`
+ *     (NULL = the null stream).  fcrkpm_apply is asynchronous; setup, solve
+ *     and adjoint synchronise the stream before returning.
+ *   - A context is used from one stream at a time and is not thread-safe.
+ *   - No C++ exception crosses this boundary: every call returns a status;
+ *     fcrkpm_last_error(ctx) gives a message for the last failing call.
+ */
+#ifndef FCRKPM_H
+#define FCRKPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcrkpm_ctx fcrkpm_ctx;
+
+typedef enum {
+    FCRKPM_OK = 0,
+    FCRKPM_ERR_ARG = 1,         /* invalid argument or geometry             */
+    FCRKPM_ERR_SINGULAR = 2,    /* a moment matrix is not positive definite */
+    FCRKPM_ERR_NOCONV = 3,      /* solver hit maxit or broke down           */
+    FCRKPM_ERR_HIP = 4,         /* a HIP runtime call failed                */
+    FCRKPM_ERR_OOM = 5,         /* device allocation failed                 */
+    FCRKPM_ERR_UNSUPPORTED = 6  /* valid request not implemented            */
+} fcrkpm_status;
+
+/* Kernel functions (Sec 2.1). */
+enum { FCRKPM_KERNEL_CUBIC_BSPLINE = 0 }; /* Eq 6-7: tensor-product cubic B-spline */
+
+/* Operators of fcrkpm_apply. */
+enum {
+    FCRKPM_OP_K = 0,      /* chi_Omega o K (chi_Omega o d): the CG operator  (Eq 91, Alg 2, masks Eq 96) */
+    FCRKPM_OP_K_FULL = 1, /* f^int = K d over all domain nodes               (Eq 57, 91; Alg 2)          */
+    FCRKPM_OP_FR = 2,     /* f^r = N^T (V o r)                               (Eq 60, 92; Alg 4)          */
+    FCRKPM_OP_UH = 3,     /* u^h = N d at the nodes                          (Eq 63, 94; Alg 3)          */
+    FCRKPM_OP_NT = 4,     /* N^T y  (Eq 92 without V)                                                    */
+    FCRKPM_OP_VN = 5      /* V o (N z)                                                                   */
+};
+
+/* Number types. */
+enum { FCRKPM_F64 = 0, FCRKPM_F32 = 1 };
+
+/* Solver modes. */
+enum {
+    FCRKPM_MODE_F64 = 0,         /* FP64 CG on FP64 FFT products                           */
+    FCRKPM_MODE_F32_REFINED = 1  /* FP32 CG inside FP64 iterative refinement (FP64 residual) */
+};
+
+/* Coefficient fields readable with fcrkpm_get_coeffs. */
+enum {
+    FCRKPM_COEF_B0 = 0,     /* b^0_p, p < s: first row of M^-1 (Eq 45, 83); [s][nodes]            */
+    FCRKPM_COEF_BALPHA = 1, /* b^a_p: minus row a+1 of M^-1 (Eq 46-47, 84-85); [dim][s][nodes]    */
+    FCRKPM_COEF_FREE = 2    /* chi_Omega as 0/1 doubles (Eq 96); [nodes]                           */
+};
+
+typedef struct {
+    int32_t dim;              /* spatial dimension d: 1, 2 or 3                             */
+    int32_t n[3];             /* box nodes per axis (x, y, z); unused axes must be 1        */
+    double h[3];              /* nodal spacing per axis (Eq 70)                             */
+    const uint8_t* dirichlet; /* device: chi_Gamma_g per node (Eq 95), subset of the mask,
+                                 or NULL for no Dirichlet nodes                             */
+    const double* vol;        /* device: nodal volume V per node (Eq 87), or NULL for
+                                 V = h_x h_y h_z on every domain node                       */
+    int32_t flags;            /* reserved, must be 0                                        */
+} fcrkpm_grid;
+
+typedef struct {
+    int32_t iters;          /* CG iterations (sum over inner solves in refined mode)          */
+    int32_t outer_iters;    /* refinement steps (0 in FP64 mode)                              */
+    double rel_res;         /* final recursive relative residual                              */
+    double true_rel_res;    /* ||b - K d|| / ||b|| recomputed in FP64 at the end              */
+    int32_t fallback_used;  /* 1 if refined mode fell back to FP64 CG after stagnation        */
+    int32_t matvecs_f64;    /* FP64 K products issued                                         */
+    int32_t matvecs_f32;    /* FP32 K products issued                                         */
+} fcrkpm_info;
+
+/*
+ * fcrkpm_setup -- build a context for one box grid and domain.
+ *
+ * Runs the setup half of the method: kernel/basis spectra (Sec 5.2-5.3,
+ * Eq 68-79), the moment convolutions M_pq = (1-chi) delta_pq + chi o
+ * F^-1[F(chi) o F(H_p H_q^a)] (Sec 4.2.1, Eq 49, 80; Alg 1) and the per-node
+ * moment solves giving b^0 and b^a (Eq 83-85), all in FP64.
+ *
+ *   grid     box geometry, Dirichlet mask and volumes (copied)
+ *   mask     device: chi per node (Eq 40), 0/1 bytes (copied)
+ *   kernel   FCRKPM_KERNEL_CUBIC_BSPLINE
+ *   support  normalised support a~ per axis, a = a~ h (Eq 64); unused axes ignored
+ *   degree   monomial degree n of the basis (Eq 4): 1 or 2
+ *   stream   HIP stream (hipStream_t) the setup runs on
+ *   out      receives the new context (NULL on failure)
+ *
+ * Errors: FCRKPM_ERR_ARG for a bad dimension, box size (each active axis must
+ * factor into 2, 3, 5 and be at least 4 and at most 1024), support (1 <= a~,
+ * floor(a~) < n/2), degree, a Dirichlet node outside the mask, or a mask
+ * whose extent on an axis leaves a periodic gap under (floor(a~)+1) nodes
+ * (Sec 5.1, Eq 66: the wrap-around would couple the two ends).  A mask that
+ * occupies every index of an axis is periodic along that axis (the chi = 1
+ * special case of Sec 4.2.4);
+ * FCRKPM_ERR_SINGULAR if a moment matrix is not positive definite (the
+ * message names the first node); FCRKPM_ERR_OOM; FCRKPM_ERR_HIP.
+ */
+fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* mask, int32_t kernel,
+                           const double support[3], int32_t degree, void* stream,
+                           fcrkpm_ctx** out);
+
+/*
+ * fcrkpm_apply -- one operator on nrhs fields, asynchronously on `stream`.
+ *
+ *   op      FCRKPM_OP_*
+ *   dtype   FCRKPM_F64 (in/out are double*) or FCRKPM_F32 (float*): the
+ *           precision of the FFT products and pointwise arithmetic
+ *   nrhs    number of fields; field j starts at j * (nodes) in `in` and `out`
+ *   in,out  device arrays; must not overlap
+ *
+ * K uses 2(s+1) 3D transforms per field (Alg 2); FR, UH, NT, VN use s+1
+ * (Alg 3, Alg 4).  Errors: FCRKPM_ERR_ARG (bad op/dtype/nrhs, NULL or
+ * overlapping pointers), FCRKPM_ERR_HIP.
+ */
+fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t nrhs,
+                           const void* in, void* out, void* stream);
+
+/*
+ * fcrkpm_solve -- static strong-Dirichlet solve (Sec 2.4, Eq 29; Sec 5.4.3,
+ * Alg 5): d = g on Dirichlet nodes, f^r from r (Alg 4), right-hand side
+ * b = chi_Omega o (f^r - K d_Gamma), CG on the free nodes (Eq 96) until
+ * ||r_k||_2 / ||b||_2 <= tol on the recursive residual.
+ *
+ *   mode     FCRKPM_MODE_F64 or FCRKPM_MODE_F32_REFINED (FP32 inner CG,
+ *            FP64 outer residual b - K d; falls back to FP64 CG if the
+ *            refinement stagnates)
+ *   nrhs     number of independent problems (fields laid out back to back)
+ *   r        device FP64 source per node (Eq 8)
+ *   g        device FP64 Dirichlet values per node, or NULL for g = 0
+ *   d_inout  device FP64: initial guess on the free nodes in (zeros = the
+ *            paper's start), solution coefficients out
+ *   uh_out   device FP64 u^h = N d (Alg 3), or NULL
+ *   tol      relative residual target (> 0)
+ *   maxit    iteration cap (CG iterations in total per problem)
+ *   info     filled for the last problem solved (may be NULL)
+ *
+ * Returns FCRKPM_ERR_NOCONV with the best d written when maxit is reached or
+ * CG breaks down (p^T K p <= 0); FCRKPM_ERR_ARG for NaN/Inf in r or bad
+ * arguments.
+ */
+fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* r,
+                           const double* g, double* d_inout, double* uh_out, double tol,
+                           int32_t maxit, fcrkpm_info* info, void* stream);
+
+/*
+ * fcrkpm_adjoint -- gradient of a loss of u^h(r) with respect to the source.
+ *
+ * With u^h = N d(r) and d(r) the homogeneous solution of fcrkpm_solve,
+ * f^r = N^T V r (Eq 59) and u^h = N d (Eq 62) give
+ *     dL/dr = V o N z,   z = K_ff^-1 chi_Omega o N^T (dL/du^h),
+ * K being symmetric (Eq 26).
+ *
+ *   dl_duh   device FP64 dL/du^h per node
+ *   dl_dr    device FP64 result per node
+ * Other arguments and errors as fcrkpm_solve.
+ */
+fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* dl_duh,
+                             double* dl_dr, double tol, int32_t maxit, fcrkpm_info* info,
+                             void* stream);
+
+/*
+ * fcrkpm_get_coeffs -- copy a coefficient field into a caller buffer
+ * (device FP64), e.g. for checking the moment solves.  `which` is
+ * FCRKPM_COEF_*; sizes are given with the enum.  Asynchronous on `stream`.
+ */
+fcrkpm_status fcrkpm_get_coeffs(fcrkpm_ctx* ctx, int32_t which, double* out, void* stream);
+
+/*
+ * Measurement hooks (not part of the method).  fcrkpm_profile(ctx, 1) opens a
+ * sampling window: for every kernel kind the library launches, HIP events on
+ * the launch stream bracket the first 64 launches, and every launch is counted
+ * with its algorithmic bytes (the bytes the launch must read and write, from
+ * the array sizes).  fcrkpm_profile(ctx, 0) closes the window and keeps the
+ * samples.  fcrkpm_profile_read synchronises the device and returns, for one
+ * kind, the launches counted, the mean duration of the sampled launches in ms
+ * and the mean algorithmic bytes per launch.  Kinds are 0 ..
+ * fcrkpm_kernel_kinds()-1; fcrkpm_kernel_name names them ("" if out of range).
+ */
+fcrkpm_status fcrkpm_profile(fcrkpm_ctx* ctx, int32_t enable);
+fcrkpm_status fcrkpm_profile_read(fcrkpm_ctx* ctx, int32_t kind, int64_t* launches,
+                                  double* mean_ms, double* bytes_per_launch);
+int32_t fcrkpm_kernel_kinds(void);
+const char* fcrkpm_kernel_name(int32_t kind);
+
+/* Basis size s = (n+d)!/(d! n!) of the context (Eq 5), or -1 for NULL. */
+int32_t fcrkpm_basis_size(const fcrkpm_ctx* ctx);
+
+/* Release a context; NULL is a no-op. */
+void fcrkpm_destroy(fcrkpm_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none); ctx may be NULL for
+ * failures of fcrkpm_setup before a context existed. */
+const char* fcrkpm_last_error(const fcrkpm_ctx* ctx);
+
+/* Static name of a status code. */
+const char* fcrkpm_status_str(fcrkpm_status s);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t fcrkpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCRKPM_H */

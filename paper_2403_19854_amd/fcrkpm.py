@@ -1,0 +1,293 @@
+"""Python binding of the gfx950 FC-RKPM library (libfcrkpm.so).
+
+Argument marshalling only: every step of the method runs in the HIP library
+behind the C ABI of ``include/fcrkpm.h``.  Torch is used for device memory and
+the current stream.  If the shared library is missing this module raises; it
+has no CPU fallback.
+
+Arrays are torch tensors on a HIP device in C order ``[nz][ny][nx]`` (x
+fastest); masks are uint8, fields float64 (or float32 for FP32 applies).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfcrkpm.so")
+
+OK, ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = range(7)
+OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN = range(6)
+F64, F32 = 0, 1
+MODE_F64, MODE_F32_REFINED = 0, 1
+COEF_B0, COEF_BALPHA, COEF_FREE = 0, 1, 2
+KERNEL_CUBIC_BSPLINE = 0
+
+_OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN}
+_MODES = {"f64": MODE_F64, "f32_refined": MODE_F32_REFINED}
+
+EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
+           "fcrkpm_get_coeffs", "fcrkpm_basis_size", "fcrkpm_destroy",
+           "fcrkpm_last_error", "fcrkpm_status_str", "fcrkpm_version",
+           "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
+           "fcrkpm_kernel_name")
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
+                ("dirichlet", C.c_void_p), ("vol", C.c_void_p), ("flags", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("fallback_used", C.c_int32),
+                ("matvecs_f64", C.c_int32), ("matvecs_f32", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FcrkpmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_name(status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfcrkpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the FC-RKPM path has no CPU fallback)")
+    lib = C.CDLL(path)
+    V = C.c_void_p
+    lib.fcrkpm_setup.restype = C.c_int
+    lib.fcrkpm_setup.argtypes = [C.POINTER(Grid), V, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                 V, C.POINTER(V)]
+    lib.fcrkpm_apply.restype = C.c_int
+    lib.fcrkpm_apply.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, V, V, V]
+    lib.fcrkpm_solve.restype = C.c_int
+    lib.fcrkpm_solve.argtypes = [V, C.c_int32, C.c_int32, V, V, V, V, C.c_double, C.c_int32,
+                                 C.POINTER(Info), V]
+    lib.fcrkpm_adjoint.restype = C.c_int
+    lib.fcrkpm_adjoint.argtypes = [V, C.c_int32, C.c_int32, V, V, C.c_double, C.c_int32,
+                                   C.POINTER(Info), V]
+    lib.fcrkpm_get_coeffs.restype = C.c_int
+    lib.fcrkpm_get_coeffs.argtypes = [V, C.c_int32, V, V]
+    lib.fcrkpm_basis_size.restype = C.c_int32
+    lib.fcrkpm_basis_size.argtypes = [V]
+    lib.fcrkpm_destroy.restype = None
+    lib.fcrkpm_destroy.argtypes = [V]
+    lib.fcrkpm_last_error.restype = C.c_char_p
+    lib.fcrkpm_last_error.argtypes = [V]
+    lib.fcrkpm_status_str.restype = C.c_char_p
+    lib.fcrkpm_status_str.argtypes = [C.c_int]
+    lib.fcrkpm_version.restype = C.c_int32
+    lib.fcrkpm_version.argtypes = []
+    lib.fcrkpm_profile.restype = C.c_int
+    lib.fcrkpm_profile.argtypes = [V, C.c_int32]
+    lib.fcrkpm_profile_read.restype = C.c_int
+    lib.fcrkpm_profile_read.argtypes = [V, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+    lib.fcrkpm_kernel_kinds.restype = C.c_int32
+    lib.fcrkpm_kernel_kinds.argtypes = []
+    lib.fcrkpm_kernel_name.restype = C.c_char_p
+    lib.fcrkpm_kernel_name.argtypes = [C.c_int32]
+    _lib = lib
+    return lib
+
+
+def status_name(s: int) -> str:
+    try:
+        return load_library().fcrkpm_status_str(int(s)).decode()
+    except Exception:
+        return f"status {s}"
+
+
+def _stream_ptr(stream=None):
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+def _dev(x, dtype, device):
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device=device, dtype=dtype).contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Problem:
+    """One FC-RKPM context: a box grid, a domain and its RK coefficients.
+
+    dims: box nodes per active axis (x, y, z order); h, support: per axis;
+    degree: 1 or 2; mask/dirichlet: uint8 [nz][ny][nx]; vol: float64 or None.
+    """
+
+    def __init__(self, dims, h, support, degree, mask, dirichlet=None, vol=None, device="cuda",
+                 stream=None):
+        lib = load_library()
+        self.device = torch.device(device)
+        self.dim = len(dims)
+        self.dims = tuple(int(v) for v in dims)
+        self.shape = tuple(reversed(self.dims))
+        self.nn = int(np.prod(self.dims))
+        self._mask = _dev(mask, torch.uint8, self.device).reshape(self.shape)
+        self._dir = None if dirichlet is None else _dev(dirichlet, torch.uint8, self.device).reshape(self.shape)
+        self._vol = None if vol is None else _dev(vol, torch.float64, self.device).reshape(self.shape)
+        g = Grid()
+        g.dim = self.dim
+        for k in range(3):
+            g.n[k] = self.dims[k] if k < self.dim else 1
+            g.h[k] = float(h[k]) if k < self.dim else 1.0
+        g.dirichlet = _ptr(self._dir)
+        g.vol = _ptr(self._vol)
+        g.flags = 0
+        sup = (C.c_double * 3)(*[float(support[k]) if k < self.dim else 0.0 for k in range(3)])
+        h_ = C.c_void_p()
+        st = lib.fcrkpm_setup(C.byref(g), _ptr(self._mask), KERNEL_CUBIC_BSPLINE, sup, int(degree),
+                              _stream_ptr(stream), C.byref(h_))
+        if st != OK:
+            raise FcrkpmError(st, lib.fcrkpm_last_error(None).decode())
+        self._h = h_
+        self.s = lib.fcrkpm_basis_size(self._h)
+
+    @classmethod
+    def from_workload(cls, p, device="cuda"):
+        """Build from a ``workloads.Problem``."""
+        return cls(p.dims, p.h, p.at, p.degree, p.chi, p.dirichlet, p.vol, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fcrkpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise FcrkpmError(st, load_library().fcrkpm_last_error(self._h).decode())
+
+    # ------------------------------------------------------------------ ops
+    def apply(self, op, x, out=None, stream=None):
+        """Apply operator op ('K', 'K_FULL', 'FR', 'UH', 'NT', 'VN') to x.
+
+        x: float64 or float32 tensor of shape [..., nz, ny, nx]; leading
+        dimensions are independent fields.  The precision of x selects the
+        arithmetic."""
+        opc = _OPS[op] if isinstance(op, str) else int(op)
+        if x.dtype not in (torch.float64, torch.float32):
+            raise TypeError("x must be float64 or float32")
+        x = x.contiguous()
+        if x.device != self.device:
+            x = x.to(self.device)
+        nrhs = x.numel() // self.nn
+        if nrhs * self.nn != x.numel() or nrhs < 1:
+            raise ValueError("x does not hold whole fields")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(load_library().fcrkpm_apply(
+            self._h, opc, F64 if x.dtype == torch.float64 else F32, nrhs, _ptr(x), _ptr(out),
+            _stream_ptr(stream)))
+        return out
+
+    def solve(self, r, g=None, d0=None, mode="f64", tol=1e-12, maxit=20000, want_uh=True,
+              stream=None, raise_on_noconv=True):
+        """Strong-Dirichlet static solve; returns (d, u^h or None, info dict)."""
+        r = _dev(r, torch.float64, self.device)
+        nrhs = r.numel() // self.nn
+        g = None if g is None else _dev(g, torch.float64, self.device)
+        d = torch.zeros_like(r) if d0 is None else _dev(d0, torch.float64, self.device).clone()
+        uh = torch.empty_like(r) if want_uh else None
+        info = Info()
+        st = load_library().fcrkpm_solve(self._h, _MODES[mode], nrhs, _ptr(r), _ptr(g), _ptr(d),
+                                         _ptr(uh), float(tol), int(maxit), C.byref(info),
+                                         _stream_ptr(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            self._check(st)
+        out = info.as_dict()
+        out["status"] = st
+        return d, uh, out
+
+    def adjoint(self, dl_duh, mode="f64", tol=1e-12, maxit=20000, stream=None):
+        """dL/dr for a loss of u^h; returns (dL/dr, info dict)."""
+        y = _dev(dl_duh, torch.float64, self.device)
+        nrhs = y.numel() // self.nn
+        g = torch.empty_like(y)
+        info = Info()
+        self._check(load_library().fcrkpm_adjoint(self._h, _MODES[mode], nrhs, _ptr(y), _ptr(g),
+                                                  float(tol), int(maxit), C.byref(info),
+                                                  _stream_ptr(stream)))
+        return g, info.as_dict()
+
+    def coeffs(self, which="b0"):
+        """Copy of b^0 [s, *shape], b^alpha [dim, s, *shape] or chi_Omega [*shape]."""
+        code = {"b0": COEF_B0, "balpha": COEF_BALPHA, "free": COEF_FREE}[which]
+        shape = {"b0": (self.s,) + self.shape, "balpha": (self.dim, self.s) + self.shape,
+                 "free": self.shape}[which]
+        out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        self._check(load_library().fcrkpm_get_coeffs(self._h, code, _ptr(out), _stream_ptr()))
+        return out
+
+
+    # ------------------------------------------------------------ measurement
+    def profile(self, enable: bool):
+        """Open (True) or close (False) a kernel-duration sampling window."""
+        self._check(load_library().fcrkpm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel name: (launches, mean ms of sampled launches, bytes per launch)}."""
+        lib = load_library()
+        out = {}
+        for k in range(lib.fcrkpm_kernel_kinds()):
+            n = C.c_int64()
+            ms = C.c_double()
+            by = C.c_double()
+            self._check(lib.fcrkpm_profile_read(self._h, k, C.byref(n), C.byref(ms), C.byref(by)))
+            if n.value:
+                out[lib.fcrkpm_kernel_name(k).decode()] = (n.value, ms.value, by.value)
+        return out
+
+
+class FCRKPMSolve(torch.autograd.Function):
+    """u^h(r): forward = strong-Dirichlet solve, backward = adjoint solve."""
+
+    @staticmethod
+    def forward(ctx, r, problem: Problem, mode: str = "f64", tol: float = 1e-12,
+                maxit: int = 20000):
+        _, uh, _ = problem.solve(r.detach(), mode=mode, tol=tol, maxit=maxit, want_uh=True)
+        ctx.problem, ctx.mode, ctx.tol, ctx.maxit = problem, mode, tol, maxit
+        return uh
+
+    @staticmethod
+    def backward(ctx, grad_uh):
+        g, _ = ctx.problem.adjoint(grad_uh.contiguous(), mode=ctx.mode, tol=ctx.tol,
+                                   maxit=ctx.maxit)
+        return g, None, None, None, None
+
+
+@dataclass
+class Version:
+    code: int
+
+    def __str__(self):
+        return f"{self.code // 10000}.{self.code // 100 % 100}.{self.code % 100}"
+
+
+def version() -> Version:
+    return Version(load_library().fcrkpm_version())

@@ -1,0 +1,361 @@
+"""GPU parity: the HIP FC-RKPM path against the FP64 CPU oracle.
+
+FC-RKPM reproduces the traditional RKPM result up to rounding (Sec 6.1.1-6.1.3),
+so every operator, coefficient field and solve of the library is compared
+element by element with the oracle on the same seeded inputs.  Bars: FP64
+operators 1e-12 relative (max-norm over the domain), FP64 solves 1e-10
+relative L2, refined FP32 solves 1e-8 relative L2, FP32 operators 2e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2403_19854_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def lib_problem(p):
+    from paper_2403_19854_amd import fcrkpm
+    return fcrkpm.Problem.from_workload(p, device=DEV)
+
+
+def orc(p):
+    o = oracle.Oracle(p.dims, p.h, p.at, p.degree, p.chi, p.vol)
+    assert o.singular_node < 0
+    return o
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_max(a, b, mask=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if mask is not None:
+        a = np.where(mask, a, 0.0)
+        b = np.where(mask, b, 0.0)
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def rel_l2(a, b, mask=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if mask is not None:
+        a = a[mask]
+        b = b[mask]
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def rand_field(p, seed, mask=None):
+    m = p.chi if mask is None else mask
+    return np.where(m > 0, np.random.default_rng(seed).standard_normal(p.shape), 0.0)
+
+
+CASES = {
+    "c1_1d_256": lambda: W.config1(),
+    "1d_quadratic_96": lambda: W.cube(1, 96, 3.0, 2),
+    "2d_linear_40x40": lambda: W.cube(2, 40, 2.5, 1, source="eq101", lo=-1, hi=1),
+    "2d_quadratic_48": lambda: W.cube(2, 48, 2.5, 2),
+    "3d_linear_24": lambda: W.cube(3, 24, 2.5, 1),
+    "3d_linear_support2_20": lambda: W.cube(3, 20, 2.0, 1),
+    "3d_paper_eq106_16": lambda: W.paper_shape(16),
+    "sphere_quadratic_32": lambda: W.sphere(32, 0.4, 3.0, 2, seed=3),
+    "sphere_quadratic_support2p5_24": lambda: W.sphere(24, 0.4, 2.5, 2, seed=3),
+    "3d_radix35_48x40x30": lambda: _aniso(),
+}
+
+
+def _aniso():
+    # non-cubic box with radix-3 and radix-5 axes: 48 = 16*3, 40 = 8*5, 30 = 2*3*5
+    base = W.cube(3, 30, 2.5, 1, source="zero")
+    dims = (48, 40, 30)
+    h = base.h[0]
+    n_om = [d - 2 for d in dims]
+    chi = np.zeros(tuple(reversed(dims)), np.uint8)
+    chi[: n_om[2], : n_om[1], : n_om[0]] = 1
+    dirichlet = W.face_dirichlet(chi)
+    free = (chi - dirichlet).astype(np.uint8)
+    vol = np.where(chi > 0, h ** 3, 0.0)
+    r = rand_field(W.Problem("tmp", 3, dims, (h,) * 3, (2.5,) * 3, 1, chi, dirichlet, free, vol,
+                             np.zeros(chi.shape), tuple(h * np.arange(d) for d in dims)), 11)
+    return W.Problem("aniso", 3, dims, (h,) * 3, (2.5,) * 3, 1, chi, dirichlet, free, vol, r,
+                     tuple(h * np.arange(d) for d in dims))
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    p = CASES[request.param]()
+    print(f"\n[case {request.param}] dims={p.dims} degree={p.degree} support={p.at[0]}", flush=True)
+    return request.param, p, orc(p), lib_problem(p)
+
+
+def test_coefficients_match_oracle(case):
+    name, p, o, g = case
+    m = p.chi > 0
+    b0 = to_np(g.coeffs("b0"))
+    ba = to_np(g.coeffs("balpha"))
+    ob0, oba = o.b0(), o.balpha()
+    # components that vanish by symmetry are ~1e-14 noise on both sides, so the
+    # error of every component is measured against the largest one of its vector
+    s0 = np.abs(ob0[:, m]).max()
+    for q in range(o.s):
+        assert np.abs(b0[q] - ob0[q])[m].max() <= 1e-10 * s0, (name, q)
+    for a in range(p.dim):
+        sa = np.abs(oba[a][:, m]).max()
+        for q in range(o.s):
+            assert np.abs(ba[a, q] - oba[a, q])[m].max() <= 1e-10 * sa, (name, a, q)
+    # b0 reproduces the constant: sum_J Psi_J = 1 is checked through UH below
+    free = to_np(g.coeffs("free"))
+    np.testing.assert_array_equal(free, p.free.astype(float))
+
+
+@pytest.mark.parametrize("op", ["K_FULL", "K", "FR", "UH", "NT", "VN"])
+def test_fp64_operators_match_oracle(case, op):
+    name, p, o, g = case
+    x = rand_field(p, 100 + len(op))
+    got = to_np(g.apply(op, torch.from_numpy(x).to(DEV)))
+    ref = {"K_FULL": lambda: o.apply_k(x),
+           "K": lambda: o.apply_k_free(x, p.free),
+           "FR": lambda: o.apply_fr(x),
+           "UH": lambda: o.apply_uh(x),
+           "NT": lambda: o.apply_nt(x),
+           "VN": lambda: o.apply_vn(x)}[op]()
+    err = rel_max(got, ref)
+    print(f"  {name} {op} fp64 rel-max err {err:.2e}")
+    assert err <= 1e-11, (name, op, err)
+    # outside the domain the products vanish exactly
+    assert np.all(got[p.chi == 0] == 0.0)
+
+
+@pytest.mark.parametrize("op", ["K", "FR", "UH"])
+def test_fp32_operators_match_oracle(case, op):
+    name, p, o, g = case
+    x = rand_field(p, 7)
+    got = to_np(g.apply(op, torch.from_numpy(x).to(DEV).float())).astype(np.float64)
+    ref = {"K": lambda: o.apply_k_free(x, p.free), "FR": lambda: o.apply_fr(x),
+           "UH": lambda: o.apply_uh(x)}[op]()
+    err = rel_max(got, ref)
+    print(f"  {name} {op} fp32 rel-max err {err:.2e}")
+    assert err <= 2e-5 * (10 if p.degree == 2 else 1), (name, op, err)
+
+
+def test_multi_rhs_apply_equals_single(case):
+    name, p, o, g = case
+    xs = np.stack([rand_field(p, 300 + j) for j in range(3)])
+    t = torch.from_numpy(xs).to(DEV)
+    batched = to_np(g.apply("K", t))
+    for j in range(3):
+        single = to_np(g.apply("K", t[j].clone()))
+        np.testing.assert_array_equal(batched[j], single)
+
+
+def test_apply_deterministic(case):
+    name, p, o, g = case
+    x = torch.from_numpy(rand_field(p, 5)).to(DEV)
+    a = to_np(g.apply("K", x))
+    b = to_np(g.apply("K", x))
+    np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------------------ solves
+
+SOLVE_CASES = ["c1_1d_256", "3d_linear_24", "3d_paper_eq106_16", "2d_linear_40x40",
+               "sphere_quadratic_support2p5_24"]
+
+
+@pytest.mark.parametrize("name", SOLVE_CASES)
+def test_fp64_solve_matches_oracle(name):
+    p = CASES[name]()
+    print(f"\n[solve {name}] dims={p.dims}", flush=True)
+    o, g = orc(p), lib_problem(p)
+    d_ref, it_ref, _ = o.solve(p.free, p.dirichlet, p.r, tol=1e-14, maxit=20000)
+    d, uh, info = g.solve(torch.from_numpy(p.r).to(DEV), mode="f64", tol=1e-14, maxit=20000,
+                          raise_on_noconv=False)
+    d = to_np(d)
+    uh = to_np(uh)
+    uh_ref = o.apply_uh(d_ref)
+    m = p.chi > 0
+    e_d, e_u = rel_l2(d, d_ref, m), rel_l2(uh, uh_ref, m)
+    print(f"  iters gpu {info['iters']} oracle {it_ref}; rel-L2 d {e_d:.2e} u^h {e_u:.2e};"
+          f" true res {info['true_rel_res']:.2e}")
+    assert e_d <= 1e-10 and e_u <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["3d_linear_24", "sphere_quadratic_support2p5_24", "c1_1d_256"])
+def test_refined_fp32_solve_matches_oracle(name):
+    p = CASES[name]()
+    print(f"\n[refined {name}] dims={p.dims}", flush=True)
+    o, g = orc(p), lib_problem(p)
+    d_ref, _, _ = o.solve(p.free, p.dirichlet, p.r, tol=1e-14, maxit=20000)
+    d, uh, info = g.solve(torch.from_numpy(p.r).to(DEV), mode="f32_refined", tol=1e-12,
+                          maxit=20000)
+    d64, uh64, info64 = g.solve(torch.from_numpy(p.r).to(DEV), mode="f64", tol=1e-12, maxit=20000)
+    m = p.chi > 0
+    uh_ref = o.apply_uh(d_ref)
+    e_d = rel_l2(to_np(d), d_ref, m)
+    e_u = rel_l2(to_np(uh), uh_ref, m)
+    e_vs64 = rel_l2(to_np(d), to_np(d64), m)
+    print(f"  refined: outer {info['outer_iters']} inner {info['iters']} mv32 {info['matvecs_f32']}"
+          f" mv64 {info['matvecs_f64']} fallback {info['fallback_used']}; rel-L2 d {e_d:.2e}"
+          f" u^h {e_u:.2e}; vs gpu fp64 {e_vs64:.2e} ({info64['iters']} fp64 iters)")
+    assert e_d <= 1e-8 and e_u <= 1e-8
+
+
+@pytest.mark.parametrize("name,k", [("sphere_quadratic_32", 30), ("3d_linear_24", 40)])
+def test_cg_iterates_after_fixed_k_match_oracle(name, k):
+    # with support 3.0h the sphere's K has near-null DNI modes (condition number
+    # above 1e8), so plain CG does not reach a tight tolerance on either side;
+    # the iterates after k steps are identical in exact arithmetic
+    p = CASES[name]()
+    print(f"\n[fixed-k CG {name} k={k}] dims={p.dims}", flush=True)
+    o, g = orc(p), lib_problem(p)
+    d_ref, it_ref, _ = o.solve(p.free, p.dirichlet, p.r, tol=1e-300, maxit=k)
+    d, uh, info = g.solve(torch.from_numpy(p.r).to(DEV), mode="f64", tol=1e-300, maxit=k,
+                          raise_on_noconv=False)
+    assert it_ref == k and info["iters"] == k
+    e = rel_l2(to_np(d), d_ref, p.chi > 0)
+    print(f"  rel-L2 of d after {k} iterations: {e:.2e}")
+    assert e <= 1e-9
+
+
+def test_dirichlet_values_nonzero_g():
+    # linear field as Dirichlet data with r = 0 (Eq 29): compare with the oracle
+    p = W.cube(3, 16, 2.5, 1, source="linear")
+    o, g = orc(p), lib_problem(p)
+    d_ref, _, _ = o.solve(p.free, p.dirichlet, p.r, g=p.g, tol=1e-14)
+    d, uh, info = g.solve(torch.from_numpy(p.r).to(DEV), g=torch.from_numpy(p.g).to(DEV),
+                          mode="f64", tol=1e-14, raise_on_noconv=False)
+    assert rel_l2(to_np(d), d_ref, p.chi > 0) <= 1e-10
+
+
+def test_adjoint_matches_oracle_and_identities():
+    p = W.cube(3, 20, 2.5, 1)
+    o, g = orc(p), lib_problem(p)
+    ut = W.config5_target(p)
+    d, uh, _ = g.solve(torch.from_numpy(p.r).to(DEV), mode="f64", tol=1e-14,
+                       raise_on_noconv=False)
+    res = np.where(p.chi > 0, to_np(uh) - ut, 0.0)
+    grad, info = g.adjoint(torch.from_numpy(res).to(DEV), mode="f64", tol=1e-14)
+    grad_ref, _, _ = o.adjoint(p.free, res, tol=1e-14)
+    assert rel_l2(to_np(grad), grad_ref, p.chi > 0) <= 1e-9
+    # <N^T y, z> = <y, N z>
+    y = torch.from_numpy(rand_field(p, 1)).to(DEV)
+    z = torch.from_numpy(rand_field(p, 2)).to(DEV)
+    lhs = float((g.apply("NT", y) * z).sum())
+    rhs = float((y * g.apply("UH", z)).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_autograd_function_gradient():
+    from paper_2403_19854_amd.fcrkpm import FCRKPMSolve
+    p = W.cube(3, 16, 2.5, 1)
+    g = lib_problem(p)
+    ut = torch.from_numpy(W.config5_target(p)).to(DEV)
+    chi = torch.from_numpy(p.chi.astype(np.float64)).to(DEV)
+    r = torch.from_numpy(p.r).to(DEV).requires_grad_(True)
+
+    def loss_of(rr):
+        u = FCRKPMSolve.apply(rr, g, "f64", 1e-14, 20000)
+        return 0.5 * ((u - ut) * chi).pow(2).sum()
+
+    L = loss_of(r)
+    L.backward()
+    gr = r.grad.detach().clone()
+    eps = 1e-3
+    for j in range(3):
+        v = torch.from_numpy(np.where(p.free > 0, np.random.default_rng(5100 + j)
+                                      .standard_normal(p.shape), 0.0)).to(DEV)
+        with torch.no_grad():
+            fd = (loss_of(r + eps * v) - loss_of(r - eps * v)) / (2 * eps)
+        assert float(fd) == pytest.approx(float((gr * v).sum()), rel=1e-6)
+
+
+# ------------------------------------------------------------------ closed forms on the GPU
+
+def test_periodic_symbol_matches_closed_form():
+    # chi = 1 everywhere (periodic special case): K is circulant and a Fourier
+    # mode is multiplied by V sum_a |D(th_a)|^2 prod_{b!=a} S(th_b)^2
+    n = 32
+    at = 2.5
+    h = 0.1
+    chi = np.ones((n, n, n), np.uint8)
+    from paper_2403_19854_amd import fcrkpm
+    g = fcrkpm.Problem((n, n, n), (h,) * 3, (at,) * 3, 1, chi, None,
+                       np.full((n, n, n), h ** 3), device=DEV)
+    phi = {0: 250 / 375, 1: 106 / 375, 2: 4 / 375}
+    s0 = phi[0] + 2 * phi[1] + 2 * phi[2]
+    s2 = 2 * (phi[1] + 4 * phi[2])
+    k = (3, 5, 7)
+    th = [2 * math.pi * kk / n for kk in k]
+    Dh = [(2 * (1 * phi[1] * math.sin(t) + 2 * phi[2] * math.sin(2 * t)) / s2) / h for t in th]
+    Sh = [(phi[0] + 2 * phi[1] * math.cos(t) + 2 * phi[2] * math.cos(2 * t)) / s0 for t in th]
+    sym = h ** 3 * sum(Dh[a] ** 2 * np.prod([Sh[b] ** 2 for b in range(3) if b != a])
+                       for a in range(3))
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    mode = np.cos(th[0] * x + th[1] * y + th[2] * z)
+    out = to_np(g.apply("K_FULL", torch.from_numpy(mode).to(DEV)))
+    assert rel_max(out, sym * mode) <= 1e-12
+    # constant and Nyquist checkerboard modes are in the null space (DNI zero-energy modes)
+    for kk in [(0, 0, 0), (n // 2, 0, 0), (n // 2, n // 2, n // 2)]:
+        md = np.cos(2 * math.pi * (kk[0] * x + kk[1] * y + kk[2] * z) / n)
+        o2 = to_np(g.apply("K_FULL", torch.from_numpy(md).to(DEV)))
+        assert np.abs(o2).max() <= 1e-12 * abs(sym)
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def _sampled(p, seed, count=48):
+    rng = np.random.default_rng(seed)
+    dom = np.flatnonzero(p.chi.reshape(-1))
+    return np.sort(rng.choice(dom, size=count, replace=False))
+
+
+@pytest.mark.parametrize("which", ["c5", "c3"])
+def test_full_size_operator_parity_sampled(which):
+    p = W.config5() if which == "c5" else W.config3()
+    print(f"\n[full size {which}] dims={p.dims} s={p.degree}", flush=True)
+    g = lib_problem(p)
+    o = orc(p)
+    x = rand_field(p, 77)
+    idx = _sampled(p, 1)
+    got = to_np(g.apply("K_FULL", torch.from_numpy(x).to(DEV))).reshape(-1)[idx]
+    ref = o.apply_k_at(x, idx)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-11 * scale
+    got32 = to_np(g.apply("K_FULL", torch.from_numpy(x).to(DEV).float())).reshape(-1)[idx]
+    assert np.abs(got32 - ref).max() <= 2e-4 * scale
+    # full-field coefficient parity at this size
+    b0 = to_np(g.coeffs("b0"))
+    ob0 = o.b0()
+    assert rel_max(b0[0], ob0[0], p.chi > 0) <= 1e-10
+
+
+def test_full_size_refined_solve_c5():
+    p = W.config5()
+    print(f"\n[full size refined c5] dims={p.dims}", flush=True)
+    g = lib_problem(p)
+    r = torch.from_numpy(p.r).to(DEV)
+    d32, uh32, i32 = g.solve(r, mode="f32_refined", tol=1e-12, maxit=20000)
+    d64, uh64, i64 = g.solve(r, mode="f64", tol=1e-12, maxit=20000)
+    m = p.chi > 0
+    e = rel_l2(to_np(d32), to_np(d64), m)
+    print(f"  refined vs fp64: {e:.2e}; iters fp64 {i64['iters']}, refined outer "
+          f"{i32['outer_iters']} inner {i32['iters']}")
+    assert e <= 1e-8
+    # the oracle's own residual of the GPU solution (property at any size)
+    o = orc(p)
+    kd = o.apply_k_free(to_np(d32), p.free)
+    b = np.where(p.free > 0, o.apply_fr(p.r), 0.0)
+    assert np.linalg.norm(b - kd) / np.linalg.norm(b) <= 1e-10
+    # manufactured-solution error of u^h is small (support 2.5h: first order)
+    err = rel_l2(to_np(uh32), p.u_exact, m)
+    assert err <= 5e-3
