@@ -58,7 +58,8 @@ enum { FCRKPM_F64 = 0, FCRKPM_F32 = 1 };
 /* Solver modes. */
 enum {
     FCRKPM_MODE_F64 = 0,         /* FP64 CG on FP64 FFT products                           */
-    FCRKPM_MODE_F32_REFINED = 1  /* FP32 CG inside FP64 iterative refinement (FP64 residual) */
+    FCRKPM_MODE_F32_REFINED = 1, /* FP32 CG inside FP64 iterative refinement (FP64 residual) */
+    FCRKPM_MODE_F32_PRODUCTS = 2 /* FP64 CG vectors, FP32 K products, FP64 residual replacement */
 };
 
 /* Coefficient fields readable with fcrkpm_get_coeffs. */

@@ -5,11 +5,14 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <cmath>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <functional>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -49,14 +52,17 @@ struct ArgFail {
 // sampling starts; every launch is counted together with its algorithmic
 // bytes (what the launch must read and write, from the array sizes).
 enum Kind {
-    KD_LINE_FWD_X, KD_LINE_FWD_Y, KD_LINE_FWD_Z, KD_LINE_INV_X, KD_LINE_INV_Y, KD_LINE_INV_Z,
-    KD_CONV_FWD, KD_CONV_BWD, KD_PACK, KD_UNPACK, KD_POINT_K, KD_POINT_UH, KD_POINT_LOAD,
-    KD_NKINDS
+    KD_P1_X, KD_P1_Y, KD_P1_Z, KD_MID_K, KD_MID_UH, KD_MID_LOAD, KD_P2_X, KD_P2_Y, KD_P2_Z,
+    KD_SETUP_PASS, KD_STAGES
 };
-const char* const kKindNames[KD_NKINDS] = {
-    "line_pass_fwd_x", "line_pass_fwd_y", "line_pass_fwd_z", "line_pass_inv_x", "line_pass_inv_y",
-    "line_pass_inv_z", "conv_pass_1_to_pairs", "conv_pass_pairs_to_1", "pack", "unpack_re",
-    "pointwise_k", "pointwise_uh", "pointwise_load"};
+constexpr int KD_NKINDS = 2 * KD_STAGES;  // FP64 kinds, then FP32 kinds
+const char* const kStageNames[KD_STAGES] = {
+    "sep_part1_x", "sep_part1_y", "sep_part1_z", "sep_mid_k", "sep_mid_uh", "sep_mid_load",
+    "sep_part2_x", "sep_part2_y", "sep_part2_z", "sep_setup_pass"};
+std::string kind_name(int k)
+{
+    return std::string(kStageNames[k % KD_STAGES]) + (k >= KD_STAGES ? "_f32" : "_f64");
+}
 constexpr int kProfCap = 64;
 
 struct ProfKind {
@@ -137,8 +143,11 @@ void release(Ctx& c)
     dfree(c.partial);
     dfree(c.scal);
     dfree(c.dflag);
+    dfree(c.dprog);
     if (c.hscal) (void)hipHostFree(c.hscal);
     c.hscal = nullptr;
+    for (auto& e : c.poll_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c.prof) {
         Prof* p = (Prof*)c.prof;
         for (auto& k : p->k)
@@ -224,74 +233,65 @@ int mono_of(const Ctx& c, int e0, int e1, int e2)
     return -1;
 }
 
-void prog_common(const Ctx& c, ConvProg& pg)
+// Programs of the separable passes for a monomial list (basis order for
+// Alg 2-4, degree <= 2n for Alg 1).  P_j lists the distinct exponent prefixes
+// over the first j+1 active axes; P_{k-1} is the list itself.  Part 1 maps
+// P_{j-1} -> P_j with kernel t_e (Eq 77), part 2 maps P_j -> P_{j-1} with the
+// reflected kernel (-1)^e t_e (Eq 55, 78).  Coefficients carry the 1/2 of the
+// pair separation and the 1/L of each inverse transform.
+SepPlan build_plan(const Ctx& c, const int (*mono)[3], int nm)
 {
-    memset(&pg, 0, sizeof(pg));
-    for (int m = 0; m < c.nmono2; ++m)
-        for (int a = 0; a < 3; ++a) pg.mexp[m][a] = (int8_t)c.ex2[m][a];
-}
-
-// Alg 2 first half / Alg 3: output pair j holds D_{2j} + i D_{2j+1} with
-// D_q = (chi d) (*) H_q^a  (Eq 90, 94).  1/N of the inverse folded in.
-void build_prog_fwd(const Ctx& c, ConvProg& pg)
-{
-    prog_common(c, pg);
-    const double inv = 1.0 / (double)c.nn;
-    int np = (c.s + 1) / 2, t = 0;
-    pg.nio = np;
-    pg.multi_in = 0;
-    for (int j = 0; j < np; ++j) {
-        pg.start[j] = t;
-        int q = 2 * j;
-        pg.term[t++] = SpecTerm{mono_of(c, c.ex[q][0], c.ex[q][1], c.ex[q][2]), inv, 0.0};
-        if (q + 1 < c.s)
-            pg.term[t++] = SpecTerm{mono_of(c, c.ex[q + 1][0], c.ex[q + 1][1], c.ex[q + 1][2]), 0.0, inv};
-    }
-    pg.start[np] = t;
-}
-
-// Alg 2 second half / Alg 4: input pair l = E_{2l} + i E_{2l+1}; the real part of
-// the output is sum_p E_p (*) conj-reflected H_p^a  (Eq 55, 91, 92).  The
-// reflected kernel has spectrum (-1)^deg(p) F(H_p^a); the pair uses
-// H-bar_{2l} - i H-bar_{2l+1}.
-void build_prog_bwd(const Ctx& c, ConvProg& pg)
-{
-    prog_common(c, pg);
-    const double inv = 1.0 / (double)c.nn;
-    int np = (c.s + 1) / 2, t = 0;
-    pg.nio = np;
-    pg.multi_in = 1;
-    for (int l = 0; l < np; ++l) {
-        pg.start[l] = t;
-        int p = 2 * l;
-        int dg = c.ex[p][0] + c.ex[p][1] + c.ex[p][2];
-        double sg = (dg & 1) ? -1.0 : 1.0;
-        pg.term[t++] = SpecTerm{mono_of(c, c.ex[p][0], c.ex[p][1], c.ex[p][2]), sg * inv, 0.0};
-        if (p + 1 < c.s) {
-            int dg1 = c.ex[p + 1][0] + c.ex[p + 1][1] + c.ex[p + 1][2];
-            double sg1 = (dg1 & 1) ? -1.0 : 1.0;
-            pg.term[t++] = SpecTerm{mono_of(c, c.ex[p + 1][0], c.ex[p + 1][1], c.ex[p + 1][2]), 0.0,
-                                    -sg1 * inv};
+    SepPlan sp;
+    sp.k = c.naxes;
+    const int k = sp.k;
+    std::vector<std::vector<std::vector<int>>> P(k);
+    for (int j = 0; j < k; ++j) {
+        for (int m = 0; m < nm; ++m) {
+            std::vector<int> tup;
+            for (int q = 0; q <= j; ++q) tup.push_back(mono[m][c.axes[q]]);
+            if (j == k - 1 || std::find(P[j].begin(), P[j].end(), tup) == P[j].end())
+                P[j].push_back(tup);
         }
+        sp.size[j] = (int)P[j].size();
+        if ((int)P[j].size() > kMaxSepOut) fail(FCRKPM_ERR_UNSUPPORTED, "too many monomials");
     }
-    pg.start[np] = t;
-}
-
-// Alg 1: output pair j holds chi (*) (H_m phi) for monomials m = 2j, 2j+1 of
-// degree <= 2n; M_pq reads monomial e_p + e_q (Eq 49, 80).
-void build_prog_mom(const Ctx& c, ConvProg& pg)
-{
-    prog_common(c, pg);
-    const double inv = 1.0 / (double)c.nn;
-    int np = (c.nmono2 + 1) / 2, t = 0;
-    pg.nio = np;
-    pg.multi_in = 0;
-    for (int j = 0; j < np; ++j) {
-        pg.start[j] = t;
-        pg.term[t++] = SpecTerm{2 * j, inv, 0.0};
-        if (2 * j + 1 < c.nmono2) pg.term[t++] = SpecTerm{2 * j + 1, 0.0, inv};
+    auto index_of = [&](int j, const std::vector<int>& tup) {
+        if (j < 0) return 0;
+        return (int)(std::find(P[j].begin(), P[j].end(), tup) - P[j].begin());
+    };
+    for (int j = 0; j < k; ++j) {
+        const double inv = 1.0 / (2.0 * c.n[c.axes[j]]);
+        SepProg& f = sp.p1[j];
+        memset(&f, 0, sizeof(f));
+        f.nin = (j == 0) ? 1 : sp.size[j - 1];
+        f.nout = sp.size[j];
+        int t = 0;
+        for (int o = 0; o < f.nout; ++o) {
+            f.ostart[o] = t;
+            std::vector<int> pre(P[j][o].begin(), P[j][o].end() - 1);
+            f.t[t++] = SepTerm{o, index_of(j - 1, pre), P[j][o].back(), 0, inv};
+        }
+        f.ostart[f.nout] = t;
+        SepProg& g = sp.p2[j];
+        memset(&g, 0, sizeof(g));
+        g.nin = sp.size[j];
+        g.nout = (j == 0) ? 1 : sp.size[j - 1];
+        t = 0;
+        for (int o = 0; o < g.nout; ++o) {
+            g.ostart[o] = t;
+            for (int i = 0; i < g.nin; ++i) {
+                std::vector<int> pre(P[j][i].begin(), P[j][i].end() - 1);
+                if (index_of(j - 1, pre) != o) continue;
+                const int e = P[j][i].back();
+                if (t >= kMaxSepTerms) fail(FCRKPM_ERR_UNSUPPORTED, "too many terms");
+                g.t[t++] = SepTerm{o, i, e, 0, (e & 1) ? -inv : inv};
+            }
+        }
+        g.ostart[g.nout] = t;
     }
-    pg.start[np] = t;
+    sp.maxpairs = 1;
+    for (int j = 0; j + 1 < k; ++j) sp.maxpairs = std::max(sp.maxpairs, (sp.size[j] + 1) / 2);
+    return sp;
 }
 
 template <typename T>
@@ -299,42 +299,6 @@ cplx<T>* work_of(Ctx& c)
 {
     if constexpr (sizeof(T) == 8) return c.work64;
     else return c.work32;
-}
-
-// Convolution of one complex field U into pair fields P (forward passes on all
-// but the last axis, fused last-axis pass, inverse passes).
-template <typename T>
-void line_pass(Ctx& c, int a, int dir, cplx<T>* data, int nf, hipStream_t st)
-{
-    ProfScope ps(c, (dir > 0 ? KD_LINE_FWD_X : KD_LINE_INV_X) + a,
-                 2.0 * nf * (double)c.nn * sizeof(cplx<T>), st);
-    launch_line_pass<T>(c, a, dir, data, nf, c.nn, st);
-}
-
-template <typename T>
-void conv_pass(Ctx& c, int a, const ConvProg& pg, const cplx<T>* in, cplx<T>* out, hipStream_t st)
-{
-    ProfScope ps(c, pg.multi_in ? KD_CONV_BWD : KD_CONV_FWD,
-                 (1.0 + pg.nio) * (double)c.nn * sizeof(cplx<T>), st);
-    launch_conv_pass<T>(c, a, pg, in, out, st);
-}
-
-template <typename T>
-void conv_one_to_many(Ctx& c, const ConvProg& pg, cplx<T>* U, cplx<T>* P, hipStream_t st)
-{
-    const int k = c.naxes;
-    for (int i = 0; i < k - 1; ++i) line_pass<T>(c, c.axes[i], +1, U, 1, st);
-    conv_pass<T>(c, c.axes[k - 1], pg, U, P, st);
-    for (int i = k - 2; i >= 0; --i) line_pass<T>(c, c.axes[i], -1, P, pg.nio, st);
-}
-
-template <typename T>
-void conv_many_to_one(Ctx& c, const ConvProg& pg, cplx<T>* P, cplx<T>* U, hipStream_t st)
-{
-    const int k = c.naxes;
-    for (int i = 0; i < k - 1; ++i) line_pass<T>(c, c.axes[i], +1, P, pg.nio, st);
-    conv_pass<T>(c, c.axes[k - 1], pg, P, U, st);
-    for (int i = k - 2; i >= 0; --i) line_pass<T>(c, c.axes[i], -1, U, 1, st);
 }
 
 template <typename T>
@@ -356,57 +320,118 @@ const T* vol_of(const Ctx& c)
     else return c.vol32;
 }
 
-// One operator on one field, precision T (Alg 2, 3, 4).
 template <typename T>
-void apply_one(Ctx& c, int op, const T* in, T* out, hipStream_t st)
+int kind_of(int stage) { return stage + (sizeof(T) == 4 ? KD_STAGES : 0); }
+
+// bytes of `nreal` real fields stored as complex pairs
+template <typename T>
+double pair_bytes(int nreal) { return (double)((nreal + 1) / 2) * sizeof(cplx<T>); }
+
+// Part-1 passes on axes 0..k-2 (Alg 2/3 first half): the field `in` (Tio,
+// masked) becomes P_{k-2} pairs; returns the slot that holds them.
+template <typename T, typename Tio>
+cplx<T>* part1(Ctx& c, const SepPlan& sp, const Tio* in, const uint8_t* mask, cplx<T>* S1,
+               cplx<T>* S2, hipStream_t st)
 {
-    cplx<T>* U = work_of<T>(c);
-    cplx<T>* P = U + c.nn;
-    const double nn = (double)c.nn, ct = sizeof(cplx<T>), rt = sizeof(T);
+    const double nn = (double)c.nn;
+    const void* src = in;
+    cplx<T>* dst = S1;
+    for (int j = 0; j + 1 < sp.k; ++j) {
+        const int ldm = (j == 0) ? SEP_LD_REAL : SEP_LD_PAIRS;
+        const double inb = (j == 0) ? sizeof(Tio) + 1.0 : pair_bytes<T>(sp.size[j - 1]);
+        ProfScope ps(c, kind_of<T>(KD_P1_X + c.axes[j]), nn * (inb + pair_bytes<T>(sp.size[j])), st);
+        launch_sep_pass<T, Tio>(c, c.axes[j], sp.p1[j], sp.d1[j], ldm, src, mask, SEP_ST_PAIRS, dst, nullptr,
+                                nullptr, nullptr, st);
+        src = dst;
+        dst = (dst == S1) ? S2 : S1;
+    }
+    return (cplx<T>*)src;
+}
+
+// Part-2 passes on axes k-2..0 from P_{k-2} pairs in `cur` to the real field
+// `out` (masked).
+template <typename T, typename Tio>
+void part2(Ctx& c, const SepPlan& sp, cplx<T>* cur, cplx<T>* S1, cplx<T>* S2, Tio* out,
+           const uint8_t* mask, hipStream_t st)
+{
+    const double nn = (double)c.nn;
+    for (int j = sp.k - 2; j >= 0; --j) {
+        const double inb = pair_bytes<T>(sp.size[j]);
+        if (j > 0) {
+            cplx<T>* dst = (cur == S1) ? S2 : S1;
+            ProfScope ps(c, kind_of<T>(KD_P2_X + c.axes[j]), nn * (inb + pair_bytes<T>(sp.size[j - 1])), st);
+            launch_sep_pass<T, Tio>(c, c.axes[j], sp.p2[j], sp.d2[j], SEP_LD_PAIRS, cur, nullptr, SEP_ST_PAIRS,
+                                    dst, nullptr, nullptr, nullptr, st);
+            cur = dst;
+        } else {
+            ProfScope ps(c, kind_of<T>(KD_P2_X + c.axes[j]), nn * (inb + sizeof(Tio) + 1.0), st);
+            launch_sep_pass<T, Tio>(c, c.axes[j], sp.p2[j], sp.d2[j], SEP_LD_PAIRS, cur, nullptr, SEP_ST_REAL,
+                                    out, mask, nullptr, nullptr, st);
+        }
+    }
+}
+
+// One operator on one field, arithmetic precision T, field type Tio (Alg 2, 3, 4).
+template <typename T, typename Tio = T>
+void apply_one(Ctx& c, int op, const Tio* in, Tio* out, hipStream_t st)
+{
+    const SepPlan& sp = c.basis_plan;
+    const int k = sp.k, last = c.axes[k - 1];
+    cplx<T>* S1 = work_of<T>(c);
+    cplx<T>* S2 = S1 + (size_t)sp.maxpairs * c.nn;
+    const double nn = (double)c.nn, rt = sizeof(T);
+    const double inb1 = (k == 1) ? sizeof(Tio) + 1.0 : pair_bytes<T>(k >= 2 ? sp.size[k - 2] : 1);
+    const double outb2 = (k == 1) ? sizeof(Tio) + 1.0 : pair_bytes<T>(k >= 2 ? sp.size[k - 2] : 1);
     switch (op) {
         case FCRKPM_OP_K:
         case FCRKPM_OP_K_FULL: {
             const uint8_t* mk = (op == FCRKPM_OP_K) ? c.freem : c.chi;
+            cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, st);
+            cplx<T>* dst = (cur == S1) ? S2 : S1;
             {
-                ProfScope ps(c, KD_PACK, nn * (rt + 1 + ct), st);
-                launch_pack<T, T>(in, mk, U, c.nn, st);
+                ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2 + (c.dim * c.s + 1) * rt), st);
+                if (k == 1)
+                    launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], SEP_PW_K, SEP_LD_REAL, in, mk,
+                                           SEP_ST_REAL, out, mk, nullptr, b0_of<T>(c), ba_of<T>(c),
+                                           vol_of<T>(c), nullptr, nullptr, st);
+                else
+                    launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_K, SEP_LD_PAIRS,
+                                           cur, nullptr, SEP_ST_PAIRS, dst, nullptr, nullptr,
+                                           b0_of<T>(c), ba_of<T>(c), vol_of<T>(c), nullptr, nullptr,
+                                           st);
             }
-            conv_one_to_many<T>(c, c.prog_fwd, U, P, st);
-            {
-                ProfScope ps(c, KD_POINT_K, nn * (2.0 * c.npairs * ct + (c.dim * c.s + 1) * rt), st);
-                launch_pointwise_k<T>(c, P, ba_of<T>(c), vol_of<T>(c), st);
-            }
-            conv_many_to_one<T>(c, c.prog_bwd, P, U, st);
-            {
-                ProfScope ps(c, KD_UNPACK, nn * (ct + 1 + rt), st);
-                launch_unpack_re<T, T>(U, mk, out, c.nn, st);
-            }
+            if (k > 1) part2<T, Tio>(c, sp, dst, S1, S2, out, mk, st);
             break;
         }
         case FCRKPM_OP_FR:
-        case FCRKPM_OP_NT: {
-            {
-                ProfScope ps(c, KD_POINT_LOAD, nn * ((c.s + 2) * rt + c.npairs * ct), st);
-                launch_pointwise_load<T, T>(c, in, b0_of<T>(c),
-                                            op == FCRKPM_OP_FR ? vol_of<T>(c) : nullptr, P, st);
-            }
-            conv_many_to_one<T>(c, c.prog_bwd, P, U, st);
-            ProfScope ps(c, KD_UNPACK, nn * (ct + 1 + rt), st);
-            launch_unpack_re<T, T>(U, c.chi, out, c.nn, st);
-            break;
-        }
+        case FCRKPM_OP_NT:
         case FCRKPM_OP_UH:
-        case FCRKPM_OP_VN: {
-            {
-                ProfScope ps(c, KD_PACK, nn * (rt + 1 + ct), st);
-                launch_pack<T, T>(in, c.chi, U, c.nn, st);
+        case FCRKPM_OP_VN:
+            if constexpr (!std::is_same_v<T, Tio>) {
+                fail(FCRKPM_ERR_ARG, "mixed precisions are supported for K only");
+            } else {
+                const T* vol = (op == FCRKPM_OP_FR || op == FCRKPM_OP_VN) ? vol_of<T>(c) : nullptr;
+                if (op == FCRKPM_OP_FR || op == FCRKPM_OP_NT) {
+                    {
+                        ProfScope ps(c, kind_of<T>(KD_MID_LOAD), nn * (sizeof(Tio) + (c.s + 1) * rt + outb2), st);
+                        launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_LOAD,
+                                               SEP_LD_PAIRS, nullptr, nullptr,
+                                               k == 1 ? SEP_ST_REAL : SEP_ST_PAIRS,
+                                               k == 1 ? (void*)out : (void*)S1, c.chi, in,
+                                               b0_of<T>(c), ba_of<T>(c), vol, nullptr, nullptr, st);
+                    }
+                    if (k > 1) part2<T, Tio>(c, sp, S1, S1, S2, out, c.chi, st);
+                } else {
+                    cplx<T>* cur = part1<T, Tio>(c, sp, in, c.chi, S1, S2, st);
+                    ProfScope ps(c, kind_of<T>(KD_MID_UH), nn * (inb1 + (c.s + 1) * rt + sizeof(Tio)), st);
+                    launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_UH,
+                                           k == 1 ? SEP_LD_REAL : SEP_LD_PAIRS,
+                                           k == 1 ? (const void*)in : (const void*)cur, c.chi,
+                                           SEP_ST_REAL, out, nullptr, nullptr, b0_of<T>(c),
+                                           ba_of<T>(c), vol, nullptr, nullptr, st);
+                }
             }
-            conv_one_to_many<T>(c, c.prog_fwd, U, P, st);
-            ProfScope ps(c, KD_POINT_UH, nn * (c.npairs * ct + (c.s + 2) * rt), st);
-            launch_pointwise_uh<T, T>(c, P, b0_of<T>(c), op == FCRKPM_OP_VN ? vol_of<T>(c) : nullptr,
-                                      out, st);
             break;
-        }
         default:
             fail(FCRKPM_ERR_ARG, "unknown operator");
     }
@@ -439,9 +464,64 @@ struct CgResult {
     bool converged = false;
 };
 
+// Look-ahead convergence polling: after each batch of CG iterations the
+// device scalars are copied to a pinned slot and an event is recorded; the
+// host only waits for the PREVIOUS batch, so the queue never drains while
+// the host decides.
+struct Poller {
+    Ctx& c;
+    hipStream_t st;
+    int slot = 0;      // slot the next post goes to
+    int nposted = 0;   // posts since the last full drain
+    int parity_of[2] = {0, 0};
+    Poller(Ctx& c_, hipStream_t st_) : c(c_), st(st_) {}
+    void post(int parity)
+    {
+        HIPCHK(hipMemcpyAsync(c.hscal + 8 * slot, c.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(c.poll_ev[slot], st));
+        parity_of[slot] = parity;
+        ++nposted;
+        slot ^= 1;
+    }
+    void read(int s, double& rr, bool& brk)
+    {
+        HIPCHK(hipEventSynchronize(c.poll_ev[s]));
+        rr = c.hscal[8 * s + parity_of[s]];
+        brk = c.hscal[8 * s + S_BREAK] != 0.0;
+    }
+    // scalars of the second-to-last post (the last one may still run); false if none
+    bool wait_prev(double& rr, bool& brk)
+    {
+        if (nposted < 2) return false;
+        read(slot, rr, brk);
+        return true;
+    }
+    // scalars of the last post; afterwards nothing is pending
+    void wait_last(double& rr, bool& brk)
+    {
+        read(slot ^ 1, rr, brk);
+        nposted = 0;
+    }
+};
+
+// one CG iteration on vectors of type T with K products in precision TP
+template <typename T, typename TP = T>
+void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int& parity, int& matvecs, hipStream_t st)
+{
+    double* pq_part = c.partial;
+    double* rr_part = c.partial + kRedBlocks;
+    apply_one<TP, T>(c, FCRKPM_OP_K, p, q, st);
+    ++matvecs;
+    launch_dot_partial<T>(p, q, c.nn, pq_part, st);
+    launch_cg_xr<T>(x, r, p, q, c.nn, pq_part, c.scal, parity, rr_part, st);
+    launch_cg_p<T>(p, r, c.nn, rr_part, c.scal, parity, st);
+    parity ^= 1;
+}
+
+constexpr int kCheck = 8;  // CG iterations per convergence poll
+
 // CG on chi_Omega K chi_Omega from x with residual r (both in/out), for
-// ||r|| / sqrt(bb) <= tol.  p, q: scratch.  Convergence is read every
-// `check` iterations.
+// ||r|| / sqrt(bb) <= tol.  p, q: scratch.
 template <typename T>
 CgResult cg_run(Ctx& c, T* x, T* r, T* p, T* q, double bb, double tol, int maxit, int& matvecs,
                 hipStream_t st)
@@ -453,45 +533,168 @@ CgResult cg_run(Ctx& c, T* x, T* r, T* p, T* q, double bb, double tol, int maxit
     launch_dot_partial<T>(r, r, c.nn, c.partial, st);
     launch_reduce_to(c.partial, c.scal + S_RR0, st);
     double rr = read_scalar(c, S_RR0, st);
-    int parity = 0;
     res.relres = sqrt(rr) / bn;
     if (res.relres <= tol) {
         res.converged = true;
         return res;
     }
-    double* pq_part = c.partial;
-    double* rr_part = c.partial + kRedBlocks;
-    const int check = 4;
-    int it = 0;
-    while (it < maxit) {
-        apply_one<T>(c, FCRKPM_OP_K, p, q, st);
-        ++matvecs;
-        launch_dot_partial<T>(p, q, c.nn, pq_part, st);
-        launch_cg_xr<T>(x, r, p, q, c.nn, pq_part, c.scal, parity, rr_part, st);
-        launch_cg_p<T>(p, r, c.nn, rr_part, c.scal, parity, st);
-        parity ^= 1;
-        ++it;
-        if (it % check == 0 || it == maxit) {
-            HIPCHK(hipMemcpyAsync(c.hscal, c.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            rr = c.hscal[parity];
-            res.relres = sqrt(rr) / bn;
-            if (c.hscal[S_BREAK] != 0.0) {
-                res.breakdown = true;
-                break;
-            }
-            if (res.relres <= tol) {
-                res.converged = true;
-                break;
+    int parity = 0, it = 0;
+    Poller pl(c, st);
+    bool brk = false, hit = false;
+    while (true) {
+        const int nb = std::min(kCheck, maxit - it);
+        for (int i = 0; i < nb; ++i) cg_iteration<T>(c, x, r, p, q, parity, matvecs, st);
+        it += nb;
+        pl.post(parity);
+        bool done = false;
+        if (it >= maxit) {
+            pl.wait_last(rr, brk);
+            done = true;
+        } else if (pl.wait_prev(rr, brk)) {
+            hit = std::isfinite(rr) && sqrt(rr) / bn <= tol;
+            done = brk || hit || !std::isfinite(rr);
+            if (done) {  // the batch in flight has run too
+                double rr2;
+                bool brk2;
+                pl.wait_last(rr2, brk2);
+                brk = brk || brk2;
+                if (std::isfinite(rr2)) rr = hit ? std::min(rr, rr2) : rr2;
             }
         }
+        if (done) break;
     }
+    // the residual norm of CG is not monotone: convergence is the first poll at tol
     res.iters = it;
+    res.relres = sqrt(rr) / bn;
+    res.breakdown = brk || !std::isfinite(rr);
+    res.converged = !res.breakdown && (hit || res.relres <= tol);
     return res;
+}
+
+template <typename TV>
+void to_vec(const double* r, TV* out, long n, hipStream_t st)
+{
+    if constexpr (std::is_same_v<TV, float>) launch_to32(r, out, n, st);
+    else HIPCHK(hipMemcpyAsync(out, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+}
+
+template <typename TV>
+void fold_into(double* x, TV* xc, long n, hipStream_t st)
+{
+    if constexpr (std::is_same_v<TV, float>) launch_add32to64_reset(x, xc, n, st);
+    else {
+        launch_add_reset64(x, xc, n, st);
+    }
+}
+
+bool log_enabled()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("FCRKPM_LOG");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+// CG with K products in FP32 and CG vectors of type TV; the solution x and
+// the true residual are FP64.  The correction accumulates in xc (TV) and is
+// folded into x, with the residual replaced by b - K x (FP64 products),
+// whenever the recursive residual has fallen 10x since the last replacement.
+// On entry v64[V_R] holds the true residual of x and inf.rel_res its norm.
+template <typename TV>
+fcrkpm_status reliable_cg(Ctx& c, TV* xc, TV* r, TV* p, TV* q, double bn, double tol, int maxit,
+                          fcrkpm_info& inf, int& total, bool& need_f64,
+                          const std::function<double()>& true_residual, hipStream_t st)
+{
+    const long nn = c.nn;
+    double* x = c.v64 + 1 * nn;  // V_X
+    double* r64 = c.v64 + 2 * nn;  // V_R
+    const double drop2 = 1e-2;  // replace the residual when it fell 10x
+    fcrkpm_status status = FCRKPM_OK;
+    double rel = inf.rel_res;
+    if (rel <= tol) return status;
+    HIPCHK(hipMemsetAsync(xc, 0, sizeof(TV) * nn, st));
+    HIPCHK(hipMemsetAsync(c.scal + S_BREAK, 0, sizeof(double), st));
+    if ((void*)r != (void*)r64) to_vec<TV>(r64, r, nn, st);
+    HIPCHK(hipMemcpyAsync(p, r, sizeof(TV) * nn, hipMemcpyDeviceToDevice, st));
+    launch_dot_partial<TV>(r, r, nn, c.partial, st);
+    launch_reduce_to(c.partial, c.scal + S_RR0, st);
+    double rr_upd = read_scalar(c, S_RR0, st);
+    int parity = 0, it = 0, stall = 0, it_upd = 0, longest = 0;
+    double best = rel;
+    Poller pl(c, st);
+    while (true) {
+        const int nb = std::min(kCheck, maxit - it);
+        for (int i = 0; i < nb; ++i) cg_iteration<TV, float>(c, xc, r, p, q, parity, inf.matvecs_f32, st);
+        it += nb;
+        pl.post(parity);
+        double rr = 0.0;
+        bool brk = false;
+        const bool have = pl.wait_prev(rr, brk);
+        if (have && !std::isfinite(rr)) brk = true;
+        const bool last = it >= maxit;
+        // an interval far longer than every earlier one means the recursion
+        // wanders at the accuracy floor of the FP32 products: replace anyway
+        const bool overdue = it - it_upd > 3 * longest + 256;
+        if (!last && !overdue &&
+            !(have && (brk || rr <= drop2 * rr_upd || sqrt(rr) / bn <= tol)))
+            continue;
+        longest = std::max(longest, it - it_upd);
+        it_upd = it;
+        bool brk2 = false;
+        pl.wait_last(rr, brk2);
+        brk = brk || brk2 || !std::isfinite(rr);
+        fold_into<TV>(x, xc, nn, st);
+        rel = true_residual();
+        inf.rel_res = rel;
+        ++inf.outer_iters;
+        if (log_enabled())
+            fprintf(stderr, "[fcrkpm] replace %d at it %d: recursive %.3e true %.3e\n",
+                    inf.outer_iters, it, sqrt(rr) / bn, rel);
+        if (rel <= tol) break;
+        if (last) {
+            status = FCRKPM_ERR_NOCONV;
+            break;
+        }
+        if (brk) {
+            need_f64 = true;
+            inf.fallback_used = 1;
+            break;
+        }
+        if (rel > 0.5 * best) {
+            if (++stall >= 3) {
+                // the true residual stopped improving: within 4 tol this is the
+                // attainable accuracy (rel_res reports it); otherwise finish
+                // with FP64 CG
+                if (best <= 4.0 * tol) break;
+                need_f64 = true;
+                inf.fallback_used = 1;
+                break;
+            }
+        } else {
+            stall = 0;
+        }
+        best = std::min(best, rel);
+        if ((void*)r != (void*)r64) to_vec<TV>(r64, r, nn, st);
+        launch_dot_partial<TV>(r, r, nn, c.partial, st);
+        launch_reduce_to(c.partial, c.scal + parity, st);
+        rr_upd = read_scalar(c, parity, st);
+    }
+    total += it;
+    return status;
 }
 
 // Solve chi_Omega K chi_Omega x = b with b in v64[V_B] and the initial x in
 // v64[V_X] (zero off the free nodes).  Returns status; fills info.
+//
+// FCRKPM_MODE_F32_REFINED: CG whose products and recurrences run in FP32 while
+// the solution and the true residual are kept in FP64: the FP32 correction is
+// folded into x (FP64) and the residual replaced by b - K x computed with FP64
+// products whenever the recursive residual has fallen 10x since the last
+// replacement ("reliable updates"), keeping the Krylov direction.  This is
+// iterative refinement whose inner solver keeps its search space across outer
+// steps.  Stagnation of the true residual falls back to FP64 CG.
 fcrkpm_status solve_core(Ctx& c, int mode, double tol, int maxit, fcrkpm_info* info,
                          hipStream_t st)
 {
@@ -507,48 +710,26 @@ fcrkpm_status solve_core(Ctx& c, int mode, double tol, int maxit, fcrkpm_info* i
     fcrkpm_status status = FCRKPM_OK;
     if (bb == 0.0) {
         HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * nn, st));
-        inf.rel_res = 0.0;
-        inf.true_rel_res = 0.0;
         if (info) *info = inf;
         return FCRKPM_OK;
     }
     const double bn = sqrt(bb);
     int total = 0;
     bool need_f64 = (mode == FCRKPM_MODE_F64);
+    std::function<double()> true_residual = [&]() {
+        apply_one<double>(c, FCRKPM_OP_K, x, q, st);
+        ++inf.matvecs_f64;
+        launch_sub_masked(b, q, c.freem, r, nn, st);
+        return sqrt(dot_to<double>(c, r, r, S_NORM, st)) / bn;
+    };
+    if (mode != FCRKPM_MODE_F64) inf.rel_res = true_residual();
     if (mode == FCRKPM_MODE_F32_REFINED) {
-        float* x32 = c.v32 + 0 * nn;
-        float* r32 = c.v32 + 1 * nn;
-        float* p32 = c.v32 + 2 * nn;
-        float* q32 = c.v32 + 3 * nn;
-        double prev = INFINITY;
-        for (int outer = 0; outer < 60; ++outer) {
-            apply_one<double>(c, FCRKPM_OP_K, x, q, st);
-            ++inf.matvecs_f64;
-            launch_sub_masked(b, q, c.freem, r, nn, st);
-            const double rr = dot_to<double>(c, r, r, S_NORM, st);
-            const double rel = sqrt(rr) / bn;
-            inf.rel_res = rel;
-            if (rel <= tol) break;
-            if (total >= maxit) {
-                status = FCRKPM_ERR_NOCONV;
-                break;
-            }
-            if (!(rel < 0.5 * prev)) {  // refinement stagnates: finish in FP64
-                need_f64 = true;
-                inf.fallback_used = 1;
-                break;
-            }
-            prev = rel;
-            ++inf.outer_iters;
-            launch_scale_to32(r, c.scal, S_NORM, r32, nn, st);
-            HIPCHK(hipMemsetAsync(x32, 0, sizeof(float) * nn, st));
-            double itol = 0.5 * tol / rel;
-            itol = std::min(0.1, std::max(itol, 2e-6));
-            CgResult cr = cg_run<float>(c, x32, r32, p32, q32, 1.0, itol, maxit - total,
-                                        inf.matvecs_f32, st);
-            total += cr.iters;
-            launch_axpy32to64(x, x32, c.scal, S_NORM, nn, st);
-        }
+        status = reliable_cg<float>(c, c.v32 + 0 * nn, c.v32 + 1 * nn, c.v32 + 2 * nn,
+                                    c.v32 + 3 * nn, bn, tol, maxit, inf, total, need_f64,
+                                    true_residual, st);
+    } else if (mode == FCRKPM_MODE_F32_PRODUCTS) {
+        status = reliable_cg<double>(c, c.v64 + V_T * nn, r, p, q, bn, tol, maxit, inf, total,
+                                     need_f64, true_residual, st);
     }
     if (need_f64) {
         apply_one<double>(c, FCRKPM_OP_K, x, q, st);
@@ -561,11 +742,7 @@ fcrkpm_status solve_core(Ctx& c, int mode, double tol, int maxit, fcrkpm_info* i
         if (cr.breakdown || !cr.converged) status = FCRKPM_ERR_NOCONV;
     }
     inf.iters = total;
-    // true residual in FP64
-    apply_one<double>(c, FCRKPM_OP_K, x, q, st);
-    launch_sub_masked(b, q, c.freem, r, nn, st);
-    inf.true_rel_res = sqrt(dot_to<double>(c, r, r, S_NORM, st)) / bn;
-    if (mode == FCRKPM_MODE_F32_REFINED && !need_f64 && inf.rel_res > tol) status = FCRKPM_ERR_NOCONV;
+    inf.true_rel_res = true_residual();
     if (info) *info = inf;
     return status;
 }
@@ -733,10 +910,34 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
             HIPCHK(hipMemcpyAsync(c.spec32[a], spf.data(), sizeof(cplx<float>) * spf.size(), hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        build_prog_fwd(c, c.prog_fwd);
-        build_prog_bwd(c, c.prog_bwd);
-        ConvProg prog_mom;
-        build_prog_mom(c, prog_mom);
+        c.basis_plan = build_plan(c, c.ex, c.s);
+        SepPlan mom_plan = build_plan(c, c.ex2, c.nmono2);
+        {
+            // programs live in device memory: [basis p1 0..2, basis p2 0..2, moment p1 0..2]
+            std::vector<SepProg> hp(9);
+            for (int j = 0; j < 3; ++j) {
+                hp[j] = c.basis_plan.p1[j];
+                hp[3 + j] = c.basis_plan.p2[j];
+                hp[6 + j] = mom_plan.p1[j];
+            }
+            c.dprog = dalloc<SepProg>(9);
+            HIPCHK(hipMemcpy(c.dprog, hp.data(), sizeof(SepProg) * 9, hipMemcpyHostToDevice));
+            for (int j = 0; j < 3; ++j) {
+                c.basis_plan.d1[j] = c.dprog + j;
+                c.basis_plan.d2[j] = c.dprog + 3 + j;
+                mom_plan.d1[j] = c.dprog + 6 + j;
+            }
+        }
+        {
+            int dev = 0, maxsh = 0;
+            HIPCHK(hipGetDevice(&dev));
+            if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                maxsh > 0)
+                c.lds_budget = maxsh;
+            const size_t lds = std::max(sep_lds_need(c, c.basis_plan, 16), sep_lds_need(c, mom_plan, 16));
+            if (lds > (size_t)std::min(c.lds_budget, 65536))
+                fail(FCRKPM_ERR_UNSUPPORTED, "box too long for the LDS tiles of this basis");
+        }
 
         // Alg 1: moment convolutions and per-node solves (FP64)
         c.b0_64 = dalloc<double>((size_t)c.s * nn);
@@ -744,29 +945,51 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         c.b0_32 = dalloc<float>((size_t)c.s * nn);
         c.ba_32 = dalloc<float>((size_t)c.dim * c.s * nn);
         {
-            int npm = prog_mom.nio;
-            cplx<double>* G = dalloc<cplx<double>>((size_t)(npm + 1) * nn);
-            cplx<double>* U = G + (size_t)npm * nn;
-            launch_chi_pack(c.chi, U, nn, st);
-            conv_one_to_many<double>(c, prog_mom, U, G, st);
+            const int k = mom_plan.k;
+            const int ng = (c.nmono2 + 1) / 2;
+            cplx<double>* G = dalloc<cplx<double>>((size_t)(ng + 2 * mom_plan.maxpairs) * nn);
+            cplx<double>* S1 = G + (size_t)ng * nn;
+            cplx<double>* S2 = S1 + (size_t)mom_plan.maxpairs * nn;
+            const void* src = nullptr;
+            cplx<double>* dst = (k == 1) ? G : S1;
+            for (int j = 0; j < k; ++j) {
+                ProfScope ps(c, KD_SETUP_PASS, 0.0, st);
+                launch_sep_pass<double, double>(c, c.axes[j], mom_plan.p1[j], mom_plan.d1[j],
+                                                j == 0 ? SEP_LD_CHI : SEP_LD_PAIRS, src, c.chi,
+                                                SEP_ST_PAIRS, dst, nullptr, nullptr, nullptr, st);
+                src = dst;
+                dst = (j + 2 == k) ? G : ((dst == S1) ? S2 : S1);
+            }
+            if (const char* dump = getenv("FCRKPM_DUMP")) {
+                HIPCHK(hipStreamSynchronize(st));
+                std::vector<cplx<double>> hg((size_t)ng * nn);
+                HIPCHK(hipMemcpy(hg.data(), G, sizeof(cplx<double>) * hg.size(), hipMemcpyDeviceToHost));
+                FILE* f = fopen((std::string(dump) + ".G.bin").c_str(), "wb");
+                if (f) {
+                    fwrite(hg.data(), sizeof(cplx<double>), hg.size(), f);
+                    fclose(f);
+                }
+            }
             launch_moment_solve(c, G, c.dflag + 1, st);
             HIPCHK(hipMemcpyAsync(hflag, c.dflag, sizeof(hflag), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipGetLastError());
             dfree(G);
-            if (hflag[1] != 0x7fffffff)
+            if (hflag[1] != 0x7fffffff && !getenv("FCRKPM_DUMP"))
                 fail(FCRKPM_ERR_SINGULAR, "moment matrix not positive definite at node " + std::to_string(hflag[1]));
         }
 
-        // workspace
-        c.npairs = (c.s + 1) / 2;
-        c.work64 = dalloc<cplx<double>>((size_t)(c.npairs + 1) * nn);
-        c.work32 = dalloc<cplx<float>>((size_t)(c.npairs + 1) * nn);
+        // workspace: two slots of intermediate pair fields per precision
+        c.work64 = dalloc<cplx<double>>((size_t)2 * c.basis_plan.maxpairs * nn);
+        c.work32 = dalloc<cplx<float>>((size_t)2 * c.basis_plan.maxpairs * nn);
         c.v64 = dalloc<double>((size_t)6 * nn);
         c.v32 = dalloc<float>((size_t)5 * nn);
         c.partial = dalloc<double>(2 * kRedBlocks);
         c.scal = dalloc<double>(16);
         HIPCHK(hipMemsetAsync(c.scal, 0, 16 * sizeof(double), st));
         HIPCHK(hipHostMalloc((void**)&c.hscal, 16 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&c.poll_ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c.poll_ev[1], hipEventDisableTiming));
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
         *out = h;
@@ -814,7 +1037,7 @@ extern "C" fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrh
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (mode != FCRKPM_MODE_F64 && mode != FCRKPM_MODE_F32_REFINED) fail(FCRKPM_ERR_ARG, "unknown mode");
+        if (mode < FCRKPM_MODE_F64 || mode > FCRKPM_MODE_F32_PRODUCTS) fail(FCRKPM_ERR_ARG, "unknown mode");
         if (nrhs < 1 || !r || !d_inout) fail(FCRKPM_ERR_ARG, "bad arguments");
         if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
         hipStream_t st = (hipStream_t)stream;
@@ -871,7 +1094,7 @@ extern "C" fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t n
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (mode != FCRKPM_MODE_F64 && mode != FCRKPM_MODE_F32_REFINED) fail(FCRKPM_ERR_ARG, "unknown mode");
+        if (mode < FCRKPM_MODE_F64 || mode > FCRKPM_MODE_F32_PRODUCTS) fail(FCRKPM_ERR_ARG, "unknown mode");
         if (nrhs < 1 || !dl_duh || !dl_dr) fail(FCRKPM_ERR_ARG, "bad arguments");
         if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
         hipStream_t st = (hipStream_t)stream;
@@ -976,7 +1199,10 @@ extern "C" int32_t fcrkpm_kernel_kinds(void) { return KD_NKINDS; }
 
 extern "C" const char* fcrkpm_kernel_name(int32_t kind)
 {
-    return (kind >= 0 && kind < KD_NKINDS) ? kKindNames[kind] : "";
+    static std::string names[KD_NKINDS];
+    if (kind < 0 || kind >= KD_NKINDS) return "";
+    if (names[kind].empty()) names[kind] = kind_name(kind);
+    return names[kind].c_str();
 }
 
 extern "C" int32_t fcrkpm_basis_size(const fcrkpm_ctx* ctx) { return ctx ? ctx->c.s : -1; }

@@ -26,27 +26,30 @@ struct AxisGeom {
     int contig;   // st == 1
 };
 
-// One spectral term: coef * F(H_m)(k), with F(H_m) the separable spectrum of
-// the kernel-times-monomial array of monomial m (Sec 5.3, Eq 77-78).
-struct SpecTerm {
-    int mono;
-    double re, im;
+// One term of a separable pass: output real field `out` gets
+// coef * (input real field `in`) convolved along the axis with t_e, the
+// 1D kernel-times-monomial array of exponent e (Sec 5.3, Eq 77-78).
+constexpr int kMaxSepOut = 36;
+constexpr int kMaxSepTerms = 40;
+struct SepTerm {
+    int32_t out, in, e, pad;
+    double coef;
+};
+struct SepProg {
+    int nin, nout;                 // real fields in / out
+    int ostart[kMaxSepOut + 1];    // terms of output f: [ostart[f], ostart[f+1])
+    SepTerm t[kMaxSepTerms];
 };
 
-// Spectral program of one convolution pass: either one input and nio outputs
-// (output j gets sum of terms [start[j], start[j+1]) times the input spectrum)
-// or nio inputs and one output (sum over inputs l of terms times input l).
-struct ConvProg {
-    int nio;
-    int multi_in;                 // 0: 1 -> nio, 1: nio -> 1
-    int start[kMaxIO + 1];
-    SpecTerm term[kMaxTerms];
-    int8_t mexp[kMaxMono][3];     // monomial exponents per axis
-};
-
-// Per-axis spectral tables: spec[a][e][k] = sum_o o^e phi1(|o| / at_a) e^{-2 pi i k o / n_a}.
-struct SpecTables {
-    const void* base[3];  // complex<T> tables, e-major, n_a entries per exponent
+// Programs of one monomial set over the active axes: part 1 maps the prefix
+// set P_{j-1} to P_j along axis j, part 2 maps P_j back to P_{j-1}.
+struct SepPlan {
+    int k = 0;                    // active axes
+    SepProg p1[3], p2[3];         // host copies (sizes, LDS planning)
+    const SepProg* d1[3] = {};    // device copies read by the kernels
+    const SepProg* d2[3] = {};
+    int size[3] = {0, 0, 0};      // |P_j| real fields
+    int maxpairs = 0;             // largest pair count of P_0 .. P_{k-2}
 };
 
 struct Ctx {
@@ -80,8 +83,7 @@ struct Ctx {
     cplx<float>* tw32[3] = {};
     cplx<double>* spec64[3] = {};       // kernel spectra per axis, exponents 0..2n
     cplx<float>* spec32[3] = {};
-    // workspace: (npairs + 1) complex fields per precision
-    int npairs = 0;
+    // workspace: two slots of SepPlan::maxpairs complex fields per precision
     cplx<double>* work64 = nullptr;
     cplx<float>* work32 = nullptr;
     // real vectors for the solvers
@@ -91,44 +93,40 @@ struct Ctx {
     double* scal = nullptr;             // device scalars
     double* hscal = nullptr;            // pinned host mirror
     int* dflag = nullptr;               // device int flags
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     void* prof = nullptr;               // kernel-duration sampler (measurement only)
     bool prof_on = false;
-    ConvProg prog_fwd;                  // d -> D_q pairs (H_q^a)
-    ConvProg prog_bwd;                  // E_p pairs -> f (conj-reflected H_p^a)
+    SepPlan basis_plan;                 // basis monomials (Alg 2-4)
+    SepProg* dprog = nullptr;           // device copies of the pass programs
+    int lds_budget = 65536;             // LDS bytes one workgroup may use
 };
 
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 
 // ------------------------------------------------------------- launchers
-AxisGeom axis_geom(const Ctx& c, int a, int elem_bytes);
+// separable passes (sepconv.hip); load/store and pointwise modes:
+enum { SEP_LD_PAIRS = 0, SEP_LD_REAL = 1, SEP_LD_CHI = 2 };
+enum { SEP_ST_PAIRS = 0, SEP_ST_REAL = 1 };
+enum { SEP_PW_K = 0, SEP_PW_UH = 1, SEP_PW_LOAD = 2 };
 
-template <typename T>
-void launch_line_pass(const Ctx& c, int a, int dir, cplx<T>* data, int nfields, long fstride,
-                      hipStream_t st);
+template <typename T, typename Tio>
+void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr, int ldm,
+                     const void* in,
+                     const uint8_t* mask_in, int stm, void* out, const uint8_t* mask_out,
+                     double* dot_part, const void* dot_with, hipStream_t st);
 
-template <typename T>
-void launch_conv_pass(const Ctx& c, int a, const ConvProg& prog, const cplx<T>* in, cplx<T>* out,
-                      hipStream_t st);
+template <typename T, typename Tio>
+void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1,
+                    const SepProg& pr2, const SepProg* dpr2, int pw, int ldm,
+                    const void* in, const uint8_t* mask_in, int stm, void* out,
+                    const uint8_t* mask_out, const void* src, const T* b0, const T* ba,
+                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st);
 
-template <typename Tin, typename T>
-void launch_pack(const Tin* d, const uint8_t* mask, cplx<T>* U, long nn, hipStream_t st);
+// LDS bytes the passes of a plan need at the tile widths they will use
+size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes);
 
-template <typename T, typename Tout>
-void launch_unpack_re(const cplx<T>* R, const uint8_t* mask, Tout* out, long nn, hipStream_t st);
 
-template <typename T>
-void launch_pointwise_k(const Ctx& c, cplx<T>* DE, const T* ba, const T* vol, hipStream_t st);
-
-template <typename T, typename Tout>
-void launch_pointwise_uh(const Ctx& c, const cplx<T>* D, const T* b0, const T* vol, Tout* out,
-                         hipStream_t st);
-
-template <typename Tin, typename T>
-void launch_pointwise_load(const Ctx& c, const Tin* r, const T* b0, const T* vol, cplx<T>* E,
-                           hipStream_t st);
-
-void launch_chi_pack(const uint8_t* chi, cplx<double>* U, long nn, hipStream_t st);
 void launch_free_mask(const uint8_t* chi, const uint8_t* dir, uint8_t* freem, int* bad, long nn,
                       hipStream_t st);
 void launch_axis_extent(const Ctx& c, const uint8_t* chi, int* occ, hipStream_t st);
@@ -161,5 +159,8 @@ void launch_sub_masked(const double* a, const double* b, const uint8_t* mask, do
 void launch_select(const uint8_t* mask, const double* a, const double* b, double* out, long n,
                    hipStream_t st);
 void launch_mul(const double* a, const double* b, double* out, long n, hipStream_t st);
+void launch_to32(const double* a, float* out, long n, hipStream_t st);
+void launch_add32to64_reset(double* x, float* c, long n, hipStream_t st);
+void launch_add_reset64(double* x, double* c, long n, hipStream_t st);
 
 }  // namespace fcrkpm

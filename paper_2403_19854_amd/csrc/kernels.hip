@@ -1,11 +1,5 @@
-// kernels.hip -- gfx950 kernels of the FC-RKPM Poisson path and their launchers.
+// kernels.hip -- gfx950 setup and vector kernels of the FC-RKPM Poisson path.
 //
-//  * k_line_pass  : one axis of a 3D FFT, a tile of W lines per workgroup staged
-//                   through LDS (Stockham autosort, radix 2/3/4/5/8).
-//  * k_conv_pass  : the last axis of a convolution: forward transform, spectral
-//                   products with separable kernel spectra computed on the fly,
-//                   inverse transform, in one pass over HBM (Sec 3, Eq 34).
-//  * pointwise    : the Hadamard-product stages of Alg 2-4 (Sec 5.3, Eq 90-94).
 //  * k_moment_solve: per-node FP64 Cholesky of the s x s moment matrix and the
 //                   rows of M^-1 that give b^0 and b^a (Alg 1, Eq 83-85).
 //  * CG vectors   : fused axpy + dot with deterministic two-stage reductions.
@@ -17,266 +11,6 @@
 
 namespace fcrkpm {
 
-// ============================================================ FFT line passes
-
-template <typename T>
-struct SpecView {
-    const cplx<T>* tab[3];
-    int n[3];
-};
-
-template <typename T>
-__device__ __forceinline__ cplx<T> mono_spec(const SpecView<T>& sv, const int8_t* e, int k0, int k1,
-                                             int k2)
-{
-    cplx<T> a = sv.tab[0][e[0] * sv.n[0] + k0];
-    cplx<T> b = sv.tab[1][e[1] * sv.n[1] + k1];
-    cplx<T> c = sv.tab[2][e[2] * sv.n[2] + k2];
-    return cmul(cmul(a, b), c);
-}
-
-template <typename T>
-__device__ __forceinline__ cplx<T> prog_factor(const ConvProg& pg, const SpecView<T>& sv, int j,
-                                               int k0, int k1, int k2)
-{
-    cplx<T> acc = {T(0), T(0)};
-    for (int t = pg.start[j]; t < pg.start[j + 1]; ++t) {
-        const SpecTerm& tm = pg.term[t];
-        cplx<T> h = mono_spec(sv, pg.mexp[tm.mono], k0, k1, k2);
-        acc = acc + cmul(h, cplx<T>{T(tm.re), T(tm.im)});
-    }
-    return acc;
-}
-
-struct TileMap {
-    long gbase;
-    __device__ __forceinline__ TileMap(const AxisGeom& g, long t, bool contig)
-    {
-        if (contig) {
-            gbase = t * (long)g.W * g.L;
-        } else {
-            long l0 = t * g.W;
-            long lo = l0 % g.st, hi = l0 / g.st;
-            gbase = lo + hi * g.st * g.L;
-        }
-    }
-};
-
-template <bool CONTIG>
-__device__ __forceinline__ void tile_elem(const AxisGeom& g, long gbase, int e, int& w, int& i,
-                                          long& gi)
-{
-    if (CONTIG) {
-        w = e / g.L;
-        i = e - w * g.L;
-        gi = gbase + e;
-    } else {
-        i = e / g.W;
-        w = e - i * g.W;
-        gi = gbase + w + (long)i * g.st;
-    }
-}
-
-template <typename T, int DIR, bool CONTIG>
-__global__ __launch_bounds__(256) void k_line_pass(cplx<T>* data, long fstride, AxisGeom g,
-                                                    LinePlan p, const cplx<T>* __restrict__ tw)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int sw = CONTIG ? g.L + 1 : 1;
-    const int si = CONTIG ? 1 : g.W;
-    const int tileElems = CONTIG ? g.W * (g.L + 1) : g.W * g.L;
-    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* B = A + tileElems;
-    cplx<T>* f = data + (long)blockIdx.y * fstride;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int WL = g.W * g.L;
-    TileMap tm(g, blockIdx.x, CONTIG);
-    for (int e = tid; e < WL; e += nthr) {
-        int w, i;
-        long gi;
-        tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-        A[w * sw + i * si] = f[gi];
-    }
-    __syncthreads();
-    cplx<T>* res = line_fft<T, DIR, CONTIG>(A, B, p, g.W, sw, si, tw, tid, nthr);
-    for (int e = tid; e < WL; e += nthr) {
-        int w, i;
-        long gi;
-        tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-        f[gi] = res[w * sw + i * si];
-    }
-}
-
-template <typename T, bool CONTIG>
-__global__ __launch_bounds__(256) void k_conv_pass(const cplx<T>* __restrict__ in,
-                                                    cplx<T>* __restrict__ out, long fstride,
-                                                    AxisGeom g, LinePlan p,
-                                                    const cplx<T>* __restrict__ tw,
-                                                    SpecView<T> sv, ConvProg pg)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int sw = CONTIG ? g.L + 1 : 1;
-    const int si = CONTIG ? 1 : g.W;
-    const int tileElems = CONTIG ? g.W * (g.L + 1) : g.W * g.L;
-    cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* B = A + tileElems;
-    cplx<T>* C = B + tileElems;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int WL = g.W * g.L;
-    const int n0 = sv.n[0], n1 = sv.n[1];
-    TileMap tm(g, blockIdx.x, CONTIG);
-
-    if (!pg.multi_in) {
-        for (int e = tid; e < WL; e += nthr) {
-            int w, i;
-            long gi;
-            tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-            A[w * sw + i * si] = in[gi];
-        }
-        __syncthreads();
-        cplx<T>* S = line_fft<T, +1, CONTIG>(A, B, p, g.W, sw, si, tw, tid, nthr);
-        cplx<T>* X = (S == A) ? B : A;
-        cplx<T>* Y = C;
-        for (int j = 0; j < pg.nio; ++j) {
-            for (int e = tid; e < WL; e += nthr) {
-                int w, i;
-                long gi;
-                tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-                int k0 = (int)(gi % n0);
-                long r = gi / n0;
-                int k1 = (int)(r % n1);
-                int k2 = (int)(r / n1);
-                int o = w * sw + i * si;
-                X[o] = cmul(S[o], prog_factor(pg, sv, j, k0, k1, k2));
-            }
-            __syncthreads();
-            cplx<T>* R = line_fft<T, -1, CONTIG>(X, Y, p, g.W, sw, si, tw, tid, nthr);
-            cplx<T>* fo = out + (long)j * fstride;
-            for (int e = tid; e < WL; e += nthr) {
-                int w, i;
-                long gi;
-                tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-                fo[gi] = R[w * sw + i * si];
-            }
-            __syncthreads();
-        }
-    } else {
-        for (int e = tid; e < WL; e += nthr) {
-            int w, i;
-            long gi;
-            tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-            C[w * sw + i * si] = cplx<T>{T(0), T(0)};
-        }
-        for (int l = 0; l < pg.nio; ++l) {
-            const cplx<T>* fi = in + (long)l * fstride;
-            for (int e = tid; e < WL; e += nthr) {
-                int w, i;
-                long gi;
-                tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-                A[w * sw + i * si] = fi[gi];
-            }
-            __syncthreads();
-            cplx<T>* S = line_fft<T, +1, CONTIG>(A, B, p, g.W, sw, si, tw, tid, nthr);
-            for (int e = tid; e < WL; e += nthr) {
-                int w, i;
-                long gi;
-                tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-                int k0 = (int)(gi % n0);
-                long r = gi / n0;
-                int k1 = (int)(r % n1);
-                int k2 = (int)(r / n1);
-                int o = w * sw + i * si;
-                C[o] = C[o] + cmul(S[o], prog_factor(pg, sv, l, k0, k1, k2));
-            }
-            __syncthreads();
-        }
-        cplx<T>* R = line_fft<T, -1, CONTIG>(C, A, p, g.W, sw, si, tw, tid, nthr);
-        for (int e = tid; e < WL; e += nthr) {
-            int w, i;
-            long gi;
-            tile_elem<CONTIG>(g, tm.gbase, e, w, i, gi);
-            out[gi] = R[w * sw + i * si];
-        }
-    }
-}
-
-AxisGeom axis_geom(const Ctx& c, int a, int elem_bytes)
-{
-    AxisGeom g;
-    g.L = c.n[a];
-    g.st = 1;
-    for (int k = 0; k < a; ++k) g.st *= c.n[k];
-    g.nlines = c.nn / g.L;
-    g.contig = (g.st == 1);
-    long div = g.contig ? g.nlines : g.st;
-    int W = 16;
-    while (W > 1 && ((long)W * g.L * elem_bytes > 16384 || div % W != 0)) W >>= 1;
-    g.W = W;
-    return g;
-}
-
-static int tile_elems(const AxisGeom& g) { return g.contig ? g.W * (g.L + 1) : g.W * g.L; }
-
-template <typename T>
-void launch_line_pass(const Ctx& c, int a, int dir, cplx<T>* data, int nfields, long fstride,
-                      hipStream_t st)
-{
-    AxisGeom g = axis_geom(c, a, sizeof(cplx<T>));
-    const cplx<T>* tw;
-    if constexpr (sizeof(T) == 8) tw = c.tw64[a];
-    else tw = c.tw32[a];
-    dim3 grid((unsigned)(g.nlines / g.W), (unsigned)nfields);
-    size_t sh = 2 * (size_t)tile_elems(g) * sizeof(cplx<T>);
-    if (g.contig) {
-        if (dir > 0)
-            hipLaunchKernelGGL((k_line_pass<T, 1, true>), grid, dim3(256), sh, st, data, fstride, g,
-                               c.plan[a], tw);
-        else
-            hipLaunchKernelGGL((k_line_pass<T, -1, true>), grid, dim3(256), sh, st, data, fstride,
-                               g, c.plan[a], tw);
-    } else {
-        if (dir > 0)
-            hipLaunchKernelGGL((k_line_pass<T, 1, false>), grid, dim3(256), sh, st, data, fstride,
-                               g, c.plan[a], tw);
-        else
-            hipLaunchKernelGGL((k_line_pass<T, -1, false>), grid, dim3(256), sh, st, data, fstride,
-                               g, c.plan[a], tw);
-    }
-}
-
-template <typename T>
-void launch_conv_pass(const Ctx& c, int a, const ConvProg& prog, const cplx<T>* in, cplx<T>* out,
-                      hipStream_t st)
-{
-    AxisGeom g = axis_geom(c, a, sizeof(cplx<T>));
-    SpecView<T> sv;
-    for (int k = 0; k < 3; ++k) {
-        if constexpr (sizeof(T) == 8) sv.tab[k] = c.spec64[k];
-        else sv.tab[k] = c.spec32[k];
-        sv.n[k] = c.n[k];
-    }
-    const cplx<T>* tw;
-    if constexpr (sizeof(T) == 8) tw = c.tw64[a];
-    else tw = c.tw32[a];
-    dim3 grid((unsigned)(g.nlines / g.W));
-    size_t sh = 3 * (size_t)tile_elems(g) * sizeof(cplx<T>);
-    if (g.contig)
-        hipLaunchKernelGGL((k_conv_pass<T, true>), grid, dim3(256), sh, st, in, out, c.nn, g,
-                           c.plan[a], tw, sv, prog);
-    else
-        hipLaunchKernelGGL((k_conv_pass<T, false>), grid, dim3(256), sh, st, in, out, c.nn, g,
-                           c.plan[a], tw, sv, prog);
-}
-
-template void launch_line_pass<double>(const Ctx&, int, int, cplx<double>*, int, long, hipStream_t);
-template void launch_line_pass<float>(const Ctx&, int, int, cplx<float>*, int, long, hipStream_t);
-template void launch_conv_pass<double>(const Ctx&, int, const ConvProg&, const cplx<double>*,
-                                       cplx<double>*, hipStream_t);
-template void launch_conv_pass<float>(const Ctx&, int, const ConvProg&, const cplx<float>*,
-                                      cplx<float>*, hipStream_t);
-
-// ============================================================ pointwise stages
-
 static unsigned ew_blocks(long n)
 {
     long b = (n + 255) / 256;
@@ -284,197 +18,15 @@ static unsigned ew_blocks(long n)
     return (unsigned)(b < 1 ? 1 : b);
 }
 
-template <typename Tin, typename T>
-__global__ void k_pack(const Tin* __restrict__ d, const uint8_t* __restrict__ mask,
-                       cplx<T>* __restrict__ U, long nn)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x) {
-        T v = mask[I] ? T(d[I]) : T(0);
-        U[I] = cplx<T>{v, T(0)};
-    }
-}
-
-template <typename Tin, typename T>
-void launch_pack(const Tin* d, const uint8_t* mask, cplx<T>* U, long nn, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_pack<Tin, T>), dim3(ew_blocks(nn)), dim3(256), 0, st, d, mask, U, nn);
-}
-
-template <typename T, typename Tout>
-__global__ void k_unpack_re(const cplx<T>* __restrict__ R, const uint8_t* __restrict__ mask,
-                            Tout* __restrict__ out, long nn)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x)
-        out[I] = mask[I] ? Tout(R[I].x) : Tout(0);
-}
-
-template <typename T, typename Tout>
-void launch_unpack_re(const cplx<T>* R, const uint8_t* mask, Tout* out, long nn, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_unpack_re<T, Tout>), dim3(ew_blocks(nn)), dim3(256), 0, st, R, mask,
-                       out, nn);
-}
-
-template <typename T, int S>
-__device__ __forceinline__ void load_pairs(const cplx<T>* __restrict__ P, long nn, long I, T* v)
-{
-#pragma unroll
-    for (int j = 0; j < (S + 1) / 2; ++j) {
-        cplx<T> c = P[j * nn + I];
-        v[2 * j] = c.x;
-        if (2 * j + 1 < S) v[2 * j + 1] = c.y;
-    }
-}
-
-template <typename T, int S>
-__device__ __forceinline__ void store_pairs(cplx<T>* __restrict__ P, long nn, long I, const T* v)
-{
-#pragma unroll
-    for (int j = 0; j < (S + 1) / 2; ++j) {
-        cplx<T> c;
-        c.x = v[2 * j];
-        c.y = (2 * j + 1 < S) ? v[2 * j + 1] : T(0);
-        P[j * nn + I] = c;
-    }
-}
-
-// D_q (pairs) -> E_p = V sum_a b^a_p A^a,  A^a = sum_q b^a_q D_q   (Eq 90-91, Alg 2)
-template <typename T, int S, int DIM>
-__global__ void k_pointwise_k(cplx<T>* DE, long nn, const T* __restrict__ ba,
-                              const T* __restrict__ vol)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x) {
-        T D[S + 1];
-        load_pairs<T, S>(DE, nn, I, D);
-        T b[DIM][S];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-            for (int q = 0; q < S; ++q) b[a][q] = ba[(a * S + q) * nn + I];
-        T A[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            T acc = T(0);
-#pragma unroll
-            for (int q = 0; q < S; ++q) acc += b[a][q] * D[q];
-            A[a] = acc;
-        }
-        const T v = vol[I];
-        T E[S + 1];
-#pragma unroll
-        for (int p = 0; p < S; ++p) {
-            T acc = T(0);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) acc += b[a][p] * A[a];
-            E[p] = v * acc;
-        }
-        store_pairs<T, S>(DE, nn, I, E);
-    }
-}
-
-// u = sum_p b^0_p D_p  (optionally times V)   (Eq 94, Alg 3)
-template <typename T, int S, typename Tout>
-__global__ void k_pointwise_uh(const cplx<T>* __restrict__ D, long nn, const T* __restrict__ b0,
-                               const T* __restrict__ vol, Tout* __restrict__ out)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x) {
-        T v[S + 1];
-        load_pairs<T, S>(D, nn, I, v);
-        T acc = T(0);
-#pragma unroll
-        for (int p = 0; p < S; ++p) acc += b0[p * nn + I] * v[p];
-        if (vol) acc *= vol[I];
-        out[I] = Tout(acc);
-    }
-}
-
-// E_p = (V) b^0_p r  as pairs   (Eq 92, Alg 4)
-template <typename Tin, typename T, int S>
-__global__ void k_pointwise_load(const Tin* __restrict__ r, long nn, const T* __restrict__ b0,
-                                 const T* __restrict__ vol, cplx<T>* __restrict__ E)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x) {
-        T x = T(r[I]);
-        if (vol) x *= vol[I];
-        T e[S + 1];
-#pragma unroll
-        for (int p = 0; p < S; ++p) e[p] = b0[p * nn + I] * x;
-        store_pairs<T, S>(E, nn, I, e);
-    }
-}
-
-#define FCRKPM_DISPATCH_S(S_, DIM_, ...)                                            \
-    if (c.s == 2 && c.dim == 1) { constexpr int S_ = 2, DIM_ = 1; (void)DIM_; __VA_ARGS__; }          \
-    else if (c.s == 3 && c.dim == 1) { constexpr int S_ = 3, DIM_ = 1; (void)DIM_; __VA_ARGS__; }     \
-    else if (c.s == 3 && c.dim == 2) { constexpr int S_ = 3, DIM_ = 2; (void)DIM_; __VA_ARGS__; }     \
-    else if (c.s == 6 && c.dim == 2) { constexpr int S_ = 6, DIM_ = 2; (void)DIM_; __VA_ARGS__; }     \
-    else if (c.s == 4 && c.dim == 3) { constexpr int S_ = 4, DIM_ = 3; (void)DIM_; __VA_ARGS__; }     \
+#define FCRKPM_DISPATCH_S(S_, DIM_, ...)                                                     \
+    if (c.s == 2 && c.dim == 1) { constexpr int S_ = 2, DIM_ = 1; (void)DIM_; __VA_ARGS__; }      \
+    else if (c.s == 3 && c.dim == 1) { constexpr int S_ = 3, DIM_ = 1; (void)DIM_; __VA_ARGS__; } \
+    else if (c.s == 3 && c.dim == 2) { constexpr int S_ = 3, DIM_ = 2; (void)DIM_; __VA_ARGS__; } \
+    else if (c.s == 6 && c.dim == 2) { constexpr int S_ = 6, DIM_ = 2; (void)DIM_; __VA_ARGS__; } \
+    else if (c.s == 4 && c.dim == 3) { constexpr int S_ = 4, DIM_ = 3; (void)DIM_; __VA_ARGS__; } \
     else if (c.s == 10 && c.dim == 3) { constexpr int S_ = 10, DIM_ = 3; (void)DIM_; __VA_ARGS__; }
 
-template <typename T>
-void launch_pointwise_k(const Ctx& c, cplx<T>* DE, const T* ba, const T* vol, hipStream_t st)
-{
-    FCRKPM_DISPATCH_S(S, DIM, hipLaunchKernelGGL((k_pointwise_k<T, S, DIM>), dim3(ew_blocks(c.nn)),
-                                                   dim3(256), 0, st, DE, c.nn, ba, vol));
-}
-
-template <typename T, typename Tout>
-void launch_pointwise_uh(const Ctx& c, const cplx<T>* D, const T* b0, const T* vol, Tout* out,
-                         hipStream_t st)
-{
-    FCRKPM_DISPATCH_S(S, DIM, hipLaunchKernelGGL((k_pointwise_uh<T, S, Tout>),
-                                                   dim3(ew_blocks(c.nn)), dim3(256), 0, st, D,
-                                                   c.nn, b0, vol, out));
-}
-
-template <typename Tin, typename T>
-void launch_pointwise_load(const Ctx& c, const Tin* r, const T* b0, const T* vol, cplx<T>* E,
-                           hipStream_t st)
-{
-    FCRKPM_DISPATCH_S(S, DIM, hipLaunchKernelGGL((k_pointwise_load<Tin, T, S>),
-                                                   dim3(ew_blocks(c.nn)), dim3(256), 0, st, r,
-                                                   c.nn, b0, vol, E));
-}
-
-template void launch_pack<double, double>(const double*, const uint8_t*, cplx<double>*, long,
-                                          hipStream_t);
-template void launch_pack<float, float>(const float*, const uint8_t*, cplx<float>*, long,
-                                        hipStream_t);
-template void launch_unpack_re<double, double>(const cplx<double>*, const uint8_t*, double*, long,
-                                               hipStream_t);
-template void launch_unpack_re<float, float>(const cplx<float>*, const uint8_t*, float*, long,
-                                             hipStream_t);
-template void launch_pointwise_k<double>(const Ctx&, cplx<double>*, const double*, const double*,
-                                         hipStream_t);
-template void launch_pointwise_k<float>(const Ctx&, cplx<float>*, const float*, const float*,
-                                        hipStream_t);
-template void launch_pointwise_uh<double, double>(const Ctx&, const cplx<double>*, const double*,
-                                                  const double*, double*, hipStream_t);
-template void launch_pointwise_uh<float, float>(const Ctx&, const cplx<float>*, const float*,
-                                                const float*, float*, hipStream_t);
-template void launch_pointwise_load<double, double>(const Ctx&, const double*, const double*,
-                                                    const double*, cplx<double>*, hipStream_t);
-template void launch_pointwise_load<float, float>(const Ctx&, const float*, const float*,
-                                                  const float*, cplx<float>*, hipStream_t);
-
 // ============================================================ setup kernels
-
-__global__ void k_chi_pack(const uint8_t* __restrict__ chi, cplx<double>* __restrict__ U, long nn)
-{
-    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
-         I += (long)gridDim.x * blockDim.x)
-        U[I] = cplx<double>{chi[I] ? 1.0 : 0.0, 0.0};
-}
-
-void launch_chi_pack(const uint8_t* chi, cplx<double>* U, long nn, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_chi_pack, dim3(ew_blocks(nn)), dim3(256), 0, st, chi, U, nn);
-}
 
 __global__ void k_free_mask(const uint8_t* __restrict__ chi, const uint8_t* __restrict__ dir,
                             uint8_t* __restrict__ freem, int* bad, long nn)
@@ -898,6 +450,46 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b
 void launch_mul(const double* a, const double* b, double* out, long n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mul, dim3(ew_blocks(n)), dim3(256), 0, st, a, b, out, n);
+}
+
+__global__ void k_to32(const double* __restrict__ a, float* __restrict__ out, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        out[i] = (float)a[i];
+}
+
+void launch_to32(const double* a, float* out, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to32, dim3(ew_blocks(n)), dim3(256), 0, st, a, out, n);
+}
+
+__global__ void k_add32to64_reset(double* __restrict__ x, float* __restrict__ c, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        x[i] += (double)c[i];
+        c[i] = 0.0f;
+    }
+}
+
+void launch_add32to64_reset(double* x, float* c, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add32to64_reset, dim3(ew_blocks(n)), dim3(256), 0, st, x, c, n);
+}
+
+__global__ void k_add_reset64(double* __restrict__ x, double* __restrict__ c, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        x[i] += c[i];
+        c[i] = 0.0;
+    }
+}
+
+void launch_add_reset64(double* x, double* c, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_reset64, dim3(ew_blocks(n)), dim3(256), 0, st, x, c, n);
 }
 
 }  // namespace fcrkpm

@@ -1,0 +1,688 @@
+// sepconv.hip -- separable FFT convolutions along one axis at a time.
+//
+// The kernel of the method is a tensor product (Sec 2.1, Eq 6) and every
+// convolving array is a monomial times that kernel (Eq 44, 77-79), so each 3D
+// spectrum is a product of 1D spectra, F(H) = Tx(kx) Ty(ky) Tz(kz).  The 3D
+// circular convolution F^-1[F(u) F(H)] (Sec 3, Eq 34) therefore factors into
+// commuting 1D FFT convolutions, one per axis.  Applied as a tree over the
+// monomial exponents this evaluates every convolution of Alg 1-4 with one
+// pass over HBM per axis:
+//
+//   part 1 (Eq 90, 94):  u -> X_ax -> XY_(ax,ay) -> D_q = u (*) H_q^a
+//   part 2 (Eq 91, 92):  E_p -> Z_(ax,ay) -> Y_ax -> sum_p E_p (*) Hbar_p^a
+//
+// A pass loads W lines of the tile into LDS, runs a forward Stockham FFT per
+// pair of real fields (two real fields share one complex line), forms every
+// output spectrum as a sum of input spectra times 1D kernel spectra (the
+// spectrum of each real field is separated from its pair with the conjugate-
+// mirror identity), and runs one inverse FFT per pair of real outputs.  The
+// last axis of K d is one "middle" pass that also applies the pointwise stage
+// (A^a, C_p^a of Alg 2) between the two halves, so D_q and E_p never reach HBM.
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "fcrkpm_impl.hpp"
+
+namespace fcrkpm {
+
+// --------------------------------------------------------------- in-place FFT
+// Stockham stages done in place: each thread loads the inputs of its
+// butterflies, the block synchronises, then the outputs are written.  With
+// at most 2048 tile elements and 256 threads a thread owns at most
+// ceil(2048 / (R * 256)) butterflies.
+constexpr int kThreads = 256;
+constexpr int kMaxTile = 2048;
+
+template <int R>
+constexpr int kmax_of() { return (kMaxTile / R + kThreads - 1) / kThreads; }
+
+template <typename T, int DIR, int R, bool CONTIG>
+__device__ __forceinline__ void stage_inplace(cplx<T>* buf, int n, int Ns, int W, int sw, int si,
+                                              const cplx<T>* __restrict__ tw, int tid)
+{
+    constexpr int KM = kmax_of<R>();
+    const int nb = n / R;
+    const int tot = W * nb;
+    const int twstep = n / (Ns * R);
+    cplx<T> v[KM][R];
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        const int b = tid + kk * kThreads;
+        if (b < tot) {
+            int w, j;
+            if (CONTIG) {
+                w = b / nb;
+                j = b - w * nb;
+            } else {
+                j = b / W;
+                w = b - j * W;
+            }
+            const cplx<T>* s = buf + w * sw;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[kk][r] = s[(j + r * nb) * si];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        const int b = tid + kk * kThreads;
+        if (b < tot) {
+            int w, j;
+            if (CONTIG) {
+                w = b / nb;
+                j = b - w * nb;
+            } else {
+                j = b / W;
+                w = b - j * W;
+            }
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cplx<T> t = tw[k * r * twstep];
+                    v[kk][r] = (DIR > 0) ? cmul(v[kk][r], t) : cmulc(v[kk][r], t);
+                }
+            }
+            dftR<T, DIR, R>(v[kk]);
+            const int base = (j / Ns) * Ns * R + k;
+            cplx<T>* d = buf + w * sw;
+#pragma unroll
+            for (int r = 0; r < R; ++r) d[(base + r * Ns) * si] = v[kk][r];
+        }
+    }
+    __syncthreads();
+}
+
+// forward (DIR=+1) or unnormalised inverse (DIR=-1) transform of W lines in place
+template <typename T, int DIR, bool CONTIG>
+__device__ void fft_inplace(cplx<T>* buf, const LinePlan& p, int W, int sw, int si,
+                            const cplx<T>* __restrict__ tw, int tid)
+{
+    int Ns = 1;
+    for (int st = 0; st < p.nst; ++st) {
+        const int R = p.rad[st];
+        switch (R) {
+            case 2: stage_inplace<T, DIR, 2, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
+            case 3: stage_inplace<T, DIR, 3, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
+            case 4: stage_inplace<T, DIR, 4, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
+            case 5: stage_inplace<T, DIR, 5, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
+            default: stage_inplace<T, DIR, 8, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
+        }
+        Ns *= R;
+    }
+}
+
+// ------------------------------------------------------------- tile geometry
+template <bool CONTIG>
+struct Tile {
+    long gbase;
+    int W, L, sw, si;
+    long st;
+    __device__ __forceinline__ Tile(const AxisGeom& g, long t)
+    {
+        W = g.W;
+        L = g.L;
+        st = g.st;
+        if (CONTIG) {
+            gbase = t * (long)W * L;
+            sw = L + 1;
+            si = 1;
+        } else {
+            long l0 = t * W;
+            long lo = l0 % g.st, hi = l0 / g.st;
+            gbase = lo + hi * g.st * L;
+            sw = 1;
+            si = W;
+        }
+    }
+    __device__ __forceinline__ int elems() const { return W * L; }
+    __device__ __forceinline__ int buf_elems() const { return CONTIG ? W * (L + 1) : W * L; }
+    // element e of the tile: line w, position i, global index gi, LDS offset
+    __device__ __forceinline__ void at(int e, int& w, int& i, long& gi, int& o) const
+    {
+        if (CONTIG) {
+            w = e / L;
+            i = e - w * L;
+            gi = gbase + e;
+        } else {
+            i = e / W;
+            w = e - i * W;
+            gi = gbase + w + (long)i * st;
+        }
+        o = w * sw + i * si;
+    }
+    __device__ __forceinline__ int mirror(int w, int i) const
+    {
+        int im = (i == 0) ? 0 : L - i;
+        return w * sw + im * si;
+    }
+};
+
+// spectrum of real field `f` (component f&1 of pair buffer f>>1) at one element
+template <typename T>
+__device__ __forceinline__ cplx<T> real_spec(const cplx<T>* pb, int comp, int o, int om)
+{
+    cplx<T> z = pb[o], zm = pb[om];
+    // comp 0: (z + conj zm); comp 1: -i (z - conj zm); the 1/2 is in the term coefficient
+    if (comp == 0) return cplx<T>{z.x + zm.x, z.y - zm.y};
+    return cplx<T>{z.y + zm.y, zm.x - z.x};
+}
+
+// Output pair j spectrum at one element: sum over the terms of outputs 2j, 2j+1.
+template <typename T>
+__device__ __forceinline__ cplx<T> combine(const SepProg& pr, int j, const cplx<T>* inbase,
+                                           int bstride, const cplx<T>* tab, int L, int i, int o,
+                                           int om)
+{
+    cplx<T> acc = {T(0), T(0)};
+    const int o0 = 2 * j;
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) {
+        const int of = o0 + q;
+        if (of >= pr.nout) break;
+        cplx<T> part = {T(0), T(0)};
+        for (int t = pr.ostart[of]; t < pr.ostart[of + 1]; ++t) {
+            const SepTerm tm = pr.t[t];
+            cplx<T> f = real_spec(inbase + (tm.in >> 1) * bstride, tm.in & 1, o, om);
+            cplx<T> h = tab[tm.e * L + i];
+            cplx<T> v = cmul(f, h);
+            const T cf = T(tm.coef);
+            part.x += cf * v.x;
+            part.y += cf * v.y;
+        }
+        if (q == 0) acc = part;
+        else acc = cplx<T>{acc.x - part.y, acc.y + part.x};  // + i * part
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------ generic pass
+template <typename T>
+struct SepArgs {
+    const void* in;           // pair fields, or a real field / mask (load mode)
+    const uint8_t* mask_in;
+    void* out;                // pair fields, or a real field (store mode)
+    const uint8_t* mask_out;
+    long fstride;             // elements between consecutive pair fields
+    AxisGeom g;
+    LinePlan p;
+    const cplx<T>* tw;
+    const cplx<T>* tab;       // 1D kernel spectra of the axis, exponent-major
+    int ne;                   // exponents in tab
+    const SepProg* pr;        // pass program in device memory
+    int nin, nout;            // its field counts
+    double* dot_part;         // optional: per-block partial of out . dot_with (ST_REAL)
+    const void* dot_with;
+};
+
+enum { LD_PAIRS = SEP_LD_PAIRS, LD_REAL = SEP_LD_REAL, LD_CHI = SEP_LD_CHI };
+enum { ST_PAIRS = SEP_ST_PAIRS, ST_REAL = SEP_ST_REAL };
+
+template <typename T, typename Tio, int LDM>
+__device__ __forceinline__ cplx<T> load_elem(const SepArgs<T>& a, int bi, long gi)
+{
+    if constexpr (LDM == LD_PAIRS) {
+        return reinterpret_cast<const cplx<T>*>(a.in)[bi * a.fstride + gi];
+    } else if constexpr (LDM == LD_REAL) {
+        T v = a.mask_in[gi] ? T(reinterpret_cast<const Tio*>(a.in)[gi]) : T(0);
+        return cplx<T>{v, T(0)};
+    } else {
+        return cplx<T>{a.mask_in[gi] ? T(1) : T(0), T(0)};
+    }
+}
+
+__device__ __forceinline__ double block_reduce(double v, double* sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+    return r;
+}
+
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM>
+__global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Tile<CONTIG> tl(a.g, blockIdx.x);
+    const int tid = threadIdx.x;
+    const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
+    const int nbin = (a.nin + 1) / 2, nbout = (a.nout + 1) / 2;
+    cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* in = tab + a.ne * L;
+    cplx<T>* work = in + nbin * BE;
+    for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
+    for (int bi = 0; bi < nbin; ++bi) {
+        for (int e = tid; e < E; e += kThreads) {
+            int w, i, o;
+            long gi;
+            tl.at(e, w, i, gi, o);
+            in[bi * BE + o] = load_elem<T, Tio, LDM>(a, bi, gi);
+        }
+    }
+    __syncthreads();
+    for (int bi = 0; bi < nbin; ++bi)
+        fft_inplace<T, +1, CONTIG>(in + bi * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+    double dacc = 0.0;
+    for (int j = 0; j < nbout; ++j) {
+        for (int e = tid; e < E; e += kThreads) {
+            int w, i, o;
+            long gi;
+            tl.at(e, w, i, gi, o);
+            work[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
+        }
+        __syncthreads();
+        fft_inplace<T, -1, CONTIG>(work, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        for (int e = tid; e < E; e += kThreads) {
+            int w, i, o;
+            long gi;
+            tl.at(e, w, i, gi, o);
+            if constexpr (STM == ST_PAIRS) {
+                reinterpret_cast<cplx<T>*>(a.out)[j * a.fstride + gi] = work[o];
+            } else {
+                Tio v = a.mask_out[gi] ? Tio(work[o].x) : Tio(0);
+                reinterpret_cast<Tio*>(a.out)[gi] = v;
+                if (a.dot_part) dacc += (double)v * (double)reinterpret_cast<const Tio*>(a.dot_with)[gi];
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (STM == ST_REAL) {
+        if (a.dot_part) {
+            __shared__ double sh[kThreads / 64];
+            double s = block_reduce(dacc, sh);
+            if (tid == 0) a.dot_part[blockIdx.x] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------- middle pass
+// Last axis: part-1 outputs D_q stay in LDS, the pointwise stage runs per
+// node, and the part-2 convolutions start from the LDS copy.
+template <typename T>
+struct MidArgs {
+    SepArgs<T> s;             // in / out / geometry / part-1 program in s.pr
+    const SepProg* pr2;       // part-2 program (E_p -> outputs), device memory
+    int nout2;
+    const T* b0;              // [s][nn]
+    const T* ba;              // [dim][s][nn]
+    const T* vol;             // [nn] or NULL
+    const void* src;          // PW_LOAD: the real field r (Tio)
+    long nn;
+};
+
+enum { PW_K = SEP_PW_K, PW_UH = SEP_PW_UH, PW_LOAD = SEP_PW_LOAD };
+
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW>
+__global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SepArgs<T>& a = m.s;
+    const Tile<CONTIG> tl(a.g, blockIdx.x);
+    const int tid = threadIdx.x;
+    const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
+    constexpr int NP = (S + 1) / 2;  // pair buffers of D_q / E_p
+    const int nbin = (PW == PW_LOAD) ? 0 : (a.nin + 1) / 2;
+    cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* in = tab + a.ne * L;
+    cplx<T>* dbuf = in + nbin * BE;
+    cplx<T>* work = dbuf + NP * BE;
+    for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
+
+    if constexpr (PW != PW_LOAD) {
+        for (int bi = 0; bi < nbin; ++bi)
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                in[bi * BE + o] = load_elem<T, Tio, LDM>(a, bi, gi);
+            }
+        __syncthreads();
+        for (int bi = 0; bi < nbin; ++bi)
+            fft_inplace<T, +1, CONTIG>(in + bi * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        // D_q (pairs) into dbuf
+        for (int j = 0; j < NP; ++j) {
+            cplx<T>* dj = dbuf + j * BE;
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                dj[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
+            }
+            __syncthreads();
+            fft_inplace<T, -1, CONTIG>(dj, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        }
+    }
+
+    if constexpr (PW == PW_UH) {
+        // u = sum_p b0_p D_p (times V for V o N)   (Eq 94)
+        for (int e = tid; e < E; e += kThreads) {
+            int w, i, o;
+            long gi;
+            tl.at(e, w, i, gi, o);
+            T acc = T(0);
+#pragma unroll
+            for (int p = 0; p < S; ++p) {
+                cplx<T> c = dbuf[(p >> 1) * BE + o];
+                acc += m.b0[p * m.nn + gi] * ((p & 1) ? c.y : c.x);
+            }
+            if (m.vol) acc *= m.vol[gi];
+            reinterpret_cast<Tio*>(a.out)[gi] = Tio(acc);
+        }
+        return;
+    } else {
+        if constexpr (PW == PW_K) {
+            // A^a = sum_q b^a_q D_q ; E_p = V sum_a b^a_p A^a   (Eq 90-91, Alg 2)
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                T D[NP * 2];
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    cplx<T> c = dbuf[j * BE + o];
+                    D[2 * j] = c.x;
+                    D[2 * j + 1] = c.y;
+                }
+                T b[DIM][S];
+#pragma unroll
+                for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                    for (int q = 0; q < S; ++q) b[al][q] = m.ba[(al * S + q) * m.nn + gi];
+                T A[DIM];
+#pragma unroll
+                for (int al = 0; al < DIM; ++al) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int q = 0; q < S; ++q) acc += b[al][q] * D[q];
+                    A[al] = acc;
+                }
+                const T v = m.vol[gi];
+                T Ep[NP * 2];
+#pragma unroll
+                for (int p = 0; p < S; ++p) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int al = 0; al < DIM; ++al) acc += b[al][p] * A[al];
+                    Ep[p] = v * acc;
+                }
+                if (S & 1) Ep[S] = T(0);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) dbuf[j * BE + o] = cplx<T>{Ep[2 * j], Ep[2 * j + 1]};
+            }
+        } else {
+            // E_p = (V) b0_p r   (Eq 92, Alg 4)
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                T x = T(reinterpret_cast<const Tio*>(m.src)[gi]);
+                if (m.vol) x *= m.vol[gi];
+                T Ep[NP * 2];
+#pragma unroll
+                for (int p = 0; p < S; ++p) Ep[p] = m.b0[p * m.nn + gi] * x;
+                if (S & 1) Ep[S] = T(0);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) dbuf[j * BE + o] = cplx<T>{Ep[2 * j], Ep[2 * j + 1]};
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < NP; ++j)
+            fft_inplace<T, +1, CONTIG>(dbuf + j * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        const int nbout = (m.nout2 + 1) / 2;
+        double dacc = 0.0;
+        for (int j = 0; j < nbout; ++j) {
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                work[o] = combine<T>(*m.pr2, j, dbuf, BE, tab, L, i, o, tl.mirror(w, i));
+            }
+            __syncthreads();
+            fft_inplace<T, -1, CONTIG>(work, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+            for (int e = tid; e < E; e += kThreads) {
+                int w, i, o;
+                long gi;
+                tl.at(e, w, i, gi, o);
+                if constexpr (STM == ST_PAIRS) {
+                    reinterpret_cast<cplx<T>*>(a.out)[j * a.fstride + gi] = work[o];
+                } else {
+                    Tio v = a.mask_out[gi] ? Tio(work[o].x) : Tio(0);
+                    reinterpret_cast<Tio*>(a.out)[gi] = v;
+                    if (a.dot_part)
+                        dacc += (double)v * (double)reinterpret_cast<const Tio*>(a.dot_with)[gi];
+                }
+            }
+            __syncthreads();
+        }
+        if constexpr (STM == ST_REAL) {
+            if (a.dot_part) {
+                __shared__ double sh[kThreads / 64];
+                double s = block_reduce(dacc, sh);
+                if (tid == 0) a.dot_part[blockIdx.x] = s;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+// tile width: the largest power of two W <= 16 with W*L <= max_tile that
+// divides the line count (x axis) or the axis stride (other axes)
+static AxisGeom sep_geom(const Ctx& c, int a, int max_tile)
+{
+    AxisGeom g;
+    g.L = c.n[a];
+    g.st = 1;
+    for (int k = 0; k < a; ++k) g.st *= c.n[k];
+    g.nlines = c.nn / g.L;
+    g.contig = (g.st == 1);
+    long div = g.contig ? g.nlines : g.st;
+    int W = 16;
+    while (W > 1 && ((long)W * g.L > max_tile || div % W != 0)) W >>= 1;
+    g.W = W;
+    return g;
+}
+
+static size_t buf_bytes(const AxisGeom& g, size_t elem)
+{
+    return (size_t)(g.contig ? g.W * (g.L + 1) : g.W * g.L) * elem;
+}
+
+// Largest tile (elements per buffer, a power of two <= kMaxTile) whose nbuf
+// buffers, row padding and kernel-spectrum table fit the LDS budget of a
+// workgroup on axis a.
+static int max_tile(const Ctx& c, int a, int nbuf, size_t elem)
+{
+    const size_t budget = (size_t)std::min(c.lds_budget, 65536) - 1024;
+    const size_t tab = (size_t)(2 * c.degree + 1) * c.n[a] * elem;
+    int t = kMaxTile;
+    while (t > 64 && tab + (size_t)nbuf * (t + 16) * elem > budget) t >>= 1;
+    return t;
+}
+
+template <typename T>
+static void fill_common(const Ctx& c, int a, SepArgs<T>& s, int nbuf)
+{
+    s.g = sep_geom(c, a, max_tile(c, a, nbuf, sizeof(cplx<T>)));
+    s.p = c.plan[a];
+    if constexpr (sizeof(T) == 8) {
+        s.tw = c.tw64[a];
+        s.tab = c.spec64[a];
+    } else {
+        s.tw = c.tw32[a];
+        s.tab = c.spec32[a];
+    }
+    s.ne = 2 * c.degree + 1;
+    s.fstride = c.nn;
+}
+
+size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes)
+{
+    size_t worst = 0;
+    const int np = (c.s + 1) / 2;
+    for (int j = 0; j < sp.k; ++j) {
+        const int a = c.axes[j];
+        const int nin1 = (j == 0) ? 1 : sp.size[j - 1];
+        int nbuf[2] = {(nin1 + 1) / 2 + 1, (sp.size[j] + 1) / 2 + 1};
+        if (j == sp.k - 1) nbuf[1] = (nin1 + 1) / 2 + np + 1;  // middle pass
+        for (int b = 0; b < 2; ++b) {
+            AxisGeom g = sep_geom(c, a, max_tile(c, a, nbuf[b], elem_bytes));
+            size_t need = (size_t)(2 * c.degree + 1) * g.L * elem_bytes + nbuf[b] * buf_bytes(g, elem_bytes);
+            worst = std::max(worst, need);
+        }
+    }
+    return worst;
+}
+
+static bool sep_log()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("FCRKPM_LOG");
+        on = (e && *e >= '2') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM>
+static void go_pass(const SepArgs<T>& s, size_t sh, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sep_pass<T, Tio, CONTIG, LDM, STM>), dim3((unsigned)(s.g.nlines / s.g.W)),
+                       dim3(kThreads), sh, st, s);
+    if (sep_log()) {
+        hipError_t e = hipPeekAtLastError();
+        fprintf(stderr, "[fcrkpm] pass L=%d W=%d st=%ld contig=%d nin=%d nout=%d ld=%d st=%d lds=%zu T=%zu: %s\n",
+                s.g.L, s.g.W, s.g.st, s.g.contig, s.nin, s.nout, LDM, STM, sh, sizeof(T),
+                hipGetErrorString(e));
+    }
+}
+
+template <typename T, typename Tio>
+void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr, int ldm,
+                     const void* in, const uint8_t* mask_in, int stm, void* out,
+                     const uint8_t* mask_out, double* dot_part, const void* dot_with,
+                     hipStream_t st)
+{
+    SepArgs<T> s;
+    const int nbin = (pr.nin + 1) / 2;
+    fill_common<T>(c, a, s, nbin + 1);
+    s.in = in;
+    s.mask_in = mask_in;
+    s.out = out;
+    s.mask_out = mask_out;
+    s.pr = dpr;
+    s.nin = pr.nin;
+    s.nout = pr.nout;
+    s.dot_part = dot_part;
+    s.dot_with = dot_with;
+    const size_t sh = (size_t)s.ne * s.g.L * sizeof(cplx<T>) + (nbin + 1) * buf_bytes(s.g, sizeof(cplx<T>));
+#define FC_PASS(CT, LD, STO) go_pass<T, Tio, CT, LD, STO>(s, sh, st)
+    const bool ct = s.g.contig;
+    if (ldm == LD_PAIRS && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_PAIRS, ST_PAIRS); else FC_PASS(false, LD_PAIRS, ST_PAIRS); }
+    else if (ldm == LD_REAL && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_REAL, ST_PAIRS); else FC_PASS(false, LD_REAL, ST_PAIRS); }
+    else if (ldm == LD_CHI && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_CHI, ST_PAIRS); else FC_PASS(false, LD_CHI, ST_PAIRS); }
+    else if (ldm == LD_PAIRS && stm == ST_REAL) { if (ct) FC_PASS(true, LD_PAIRS, ST_REAL); else FC_PASS(false, LD_PAIRS, ST_REAL); }
+#undef FC_PASS
+}
+
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW>
+static void go_mid(const MidArgs<T>& m, size_t sh, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sep_mid<T, Tio, CONTIG, LDM, STM, S, DIM, PW>),
+                       dim3((unsigned)(m.s.g.nlines / m.s.g.W)), dim3(kThreads), sh, st, m);
+    if (sep_log()) {
+        hipError_t e = hipPeekAtLastError();
+        fprintf(stderr, "[fcrkpm] mid L=%d W=%d st=%ld pw=%d nin=%d nout2=%d lds=%zu T=%zu: %s\n",
+                m.s.g.L, m.s.g.W, m.s.g.st, PW, m.s.nin, m.nout2, sh, sizeof(T),
+                hipGetErrorString(e));
+    }
+}
+
+template <typename T, typename Tio, int S, int DIM>
+static void mid_dispatch(const MidArgs<T>& m, int ldm, int stm, int pw, size_t sh, hipStream_t st)
+{
+    const bool ct = m.s.g.contig;
+#define FC_MID(CT, LD, STO, P) go_mid<T, Tio, CT, LD, STO, S, DIM, P>(m, sh, st)
+    if (pw == PW_K) {
+        if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
+        else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
+    } else if (pw == PW_UH) {
+        if (ldm == LD_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_UH); else FC_MID(false, LD_REAL, ST_REAL, PW_UH); }
+        else { if (ct) FC_MID(true, LD_PAIRS, ST_REAL, PW_UH); else FC_MID(false, LD_PAIRS, ST_REAL, PW_UH); }
+    } else {
+        if (stm == ST_REAL) { if (ct) FC_MID(true, LD_PAIRS, ST_REAL, PW_LOAD); else FC_MID(false, LD_PAIRS, ST_REAL, PW_LOAD); }
+        else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_LOAD); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_LOAD); }
+    }
+#undef FC_MID
+}
+
+template <typename T, typename Tio>
+void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1,
+                    const SepProg& pr2, const SepProg* dpr2, int pw, int ldm,
+                    const void* in, const uint8_t* mask_in, int stm, void* out,
+                    const uint8_t* mask_out, const void* src, const T* b0, const T* ba,
+                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st)
+{
+    MidArgs<T> m;
+    const int np = (c.s + 1) / 2;
+    const int nbin = (pw == PW_LOAD) ? 0 : (pr1.nin + 1) / 2;
+    const int nbuf = nbin + np + (pw == PW_UH ? 0 : 1);
+    fill_common<T>(c, a, m.s, nbuf);
+    m.s.in = in;
+    m.s.mask_in = mask_in;
+    m.s.out = out;
+    m.s.mask_out = mask_out;
+    m.s.pr = dpr1;
+    m.s.nin = pr1.nin;
+    m.s.nout = pr1.nout;
+    m.s.dot_part = dot_part;
+    m.s.dot_with = dot_with;
+    m.pr2 = dpr2;
+    m.nout2 = pr2.nout;
+    m.b0 = b0;
+    m.ba = ba;
+    m.vol = vol;
+    m.src = src;
+    m.nn = c.nn;
+    const size_t sh = (size_t)m.s.ne * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
+    if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, st);
+    else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, st);
+    else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, st);
+    else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, st);
+    else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, st);
+    else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, st);
+}
+
+template void launch_sep_pass<double, double>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
+                                              const uint8_t*, int, void*, const uint8_t*, double*,
+                                              const void*, hipStream_t);
+template void launch_sep_pass<float, float>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
+                                            const uint8_t*, int, void*, const uint8_t*, double*,
+                                            const void*, hipStream_t);
+template void launch_sep_pass<float, double>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
+                                             const uint8_t*, int, void*, const uint8_t*, double*,
+                                             const void*, hipStream_t);
+template void launch_sep_mid<float, double>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
+                                            int, const void*, const uint8_t*, int, void*,
+                                            const uint8_t*, const void*, const float*, const float*,
+                                            const float*, double*, const void*, hipStream_t);
+template void launch_sep_mid<double, double>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
+                                             int, const void*, const uint8_t*, int, void*,
+                                             const uint8_t*, const void*, const double*,
+                                             const double*, const double*, double*, const void*,
+                                             hipStream_t);
+template void launch_sep_mid<float, float>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
+                                           int, const void*, const uint8_t*, int, void*,
+                                           const uint8_t*, const void*, const float*, const float*,
+                                           const float*, double*, const void*, hipStream_t);
+
+}  // namespace fcrkpm

@@ -23,12 +23,12 @@ LIB_PATH = os.path.join(_HERE, "libfcrkpm.so")
 OK, ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = range(7)
 OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN = range(6)
 F64, F32 = 0, 1
-MODE_F64, MODE_F32_REFINED = 0, 1
+MODE_F64, MODE_F32_REFINED, MODE_F32_PRODUCTS = 0, 1, 2
 COEF_B0, COEF_BALPHA, COEF_FREE = 0, 1, 2
 KERNEL_CUBIC_BSPLINE = 0
 
 _OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN}
-_MODES = {"f64": MODE_F64, "f32_refined": MODE_F32_REFINED}
+_MODES = {"f64": MODE_F64, "f32_refined": MODE_F32_REFINED, "f32_products": MODE_F32_PRODUCTS}
 
 EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_get_coeffs", "fcrkpm_basis_size", "fcrkpm_destroy",
