@@ -22,7 +22,8 @@ struct AxisGeom {
     int L;        // line length (box nodes on the axis)
     long st;      // element stride of the axis
     long nlines;  // lines in a field (nodes / L)
-    int W;        // lines per tile (one workgroup)
+    int W;        // lines per tile (one workgroup), a power of two
+    int wl;       // log2 W
     int contig;   // st == 1
 };
 

@@ -29,103 +29,22 @@
 
 namespace fcrkpm {
 
-// --------------------------------------------------------------- in-place FFT
-// Stockham stages done in place: each thread loads the inputs of its
-// butterflies, the block synchronises, then the outputs are written.  With
-// at most 2048 tile elements and 256 threads a thread owns at most
-// ceil(2048 / (R * 256)) butterflies.
+// ------------------------------------------------------------- tile geometry
+// A workgroup owns W lines (W a power of two) of length L along the axis.
+// LC > 0 fixes L at compile time (the hot sizes), LC = 0 reads it at run time.
 constexpr int kThreads = 256;
 constexpr int kMaxTile = 2048;
 
-template <int R>
-constexpr int kmax_of() { return (kMaxTile / R + kThreads - 1) / kThreads; }
-
-template <typename T, int DIR, int R, bool CONTIG>
-__device__ __forceinline__ void stage_inplace(cplx<T>* buf, int n, int Ns, int W, int sw, int si,
-                                              const cplx<T>* __restrict__ tw, int tid)
-{
-    constexpr int KM = kmax_of<R>();
-    const int nb = n / R;
-    const int tot = W * nb;
-    const int twstep = n / (Ns * R);
-    cplx<T> v[KM][R];
-#pragma unroll
-    for (int kk = 0; kk < KM; ++kk) {
-        const int b = tid + kk * kThreads;
-        if (b < tot) {
-            int w, j;
-            if (CONTIG) {
-                w = b / nb;
-                j = b - w * nb;
-            } else {
-                j = b / W;
-                w = b - j * W;
-            }
-            const cplx<T>* s = buf + w * sw;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[kk][r] = s[(j + r * nb) * si];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KM; ++kk) {
-        const int b = tid + kk * kThreads;
-        if (b < tot) {
-            int w, j;
-            if (CONTIG) {
-                w = b / nb;
-                j = b - w * nb;
-            } else {
-                j = b / W;
-                w = b - j * W;
-            }
-            const int k = j % Ns;
-            if (Ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cplx<T> t = tw[k * r * twstep];
-                    v[kk][r] = (DIR > 0) ? cmul(v[kk][r], t) : cmulc(v[kk][r], t);
-                }
-            }
-            dftR<T, DIR, R>(v[kk]);
-            const int base = (j / Ns) * Ns * R + k;
-            cplx<T>* d = buf + w * sw;
-#pragma unroll
-            for (int r = 0; r < R; ++r) d[(base + r * Ns) * si] = v[kk][r];
-        }
-    }
-    __syncthreads();
-}
-
-// forward (DIR=+1) or unnormalised inverse (DIR=-1) transform of W lines in place
-template <typename T, int DIR, bool CONTIG>
-__device__ void fft_inplace(cplx<T>* buf, const LinePlan& p, int W, int sw, int si,
-                            const cplx<T>* __restrict__ tw, int tid)
-{
-    int Ns = 1;
-    for (int st = 0; st < p.nst; ++st) {
-        const int R = p.rad[st];
-        switch (R) {
-            case 2: stage_inplace<T, DIR, 2, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
-            case 3: stage_inplace<T, DIR, 3, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
-            case 4: stage_inplace<T, DIR, 4, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
-            case 5: stage_inplace<T, DIR, 5, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
-            default: stage_inplace<T, DIR, 8, CONTIG>(buf, p.n, Ns, W, sw, si, tw, tid); break;
-        }
-        Ns *= R;
-    }
-}
-
-// ------------------------------------------------------------- tile geometry
-template <bool CONTIG>
+template <bool CONTIG, int LC>
 struct Tile {
     long gbase;
-    int W, L, sw, si;
     long st;
+    int W, wl, L, sw, si;
     __device__ __forceinline__ Tile(const AxisGeom& g, long t)
     {
         W = g.W;
-        L = g.L;
+        wl = g.wl;
+        L = LC > 0 ? LC : g.L;
         st = g.st;
         if (CONTIG) {
             gbase = t * (long)W * L;
@@ -141,7 +60,7 @@ struct Tile {
     }
     __device__ __forceinline__ int elems() const { return W * L; }
     __device__ __forceinline__ int buf_elems() const { return CONTIG ? W * (L + 1) : W * L; }
-    // element e of the tile: line w, position i, global index gi, LDS offset
+    // element e of the tile: line w, position i, global index gi, LDS offset o
     __device__ __forceinline__ void at(int e, int& w, int& i, long& gi, int& o) const
     {
         if (CONTIG) {
@@ -149,18 +68,158 @@ struct Tile {
             i = e - w * L;
             gi = gbase + e;
         } else {
-            i = e / W;
-            w = e - i * W;
+            i = e >> wl;
+            w = e & (W - 1);
             gi = gbase + w + (long)i * st;
         }
         o = w * sw + i * si;
     }
     __device__ __forceinline__ int mirror(int w, int i) const
     {
-        int im = (i == 0) ? 0 : L - i;
+        const int im = (i == 0) ? 0 : L - i;
         return w * sw + im * si;
     }
 };
+
+// --------------------------------------------------------------- in-place FFT
+// Stockham stages done in place: each thread loads the inputs of its
+// butterflies, the workgroup synchronises, then the outputs are written.
+// With at most 2048 tile elements and 256 threads a thread owns at most
+// ceil(2048 / (R * 256)) butterflies.  twl is the LDS copy of
+// e^{-2 pi i k / L}, k < L.
+template <int R>
+constexpr int kmax_of() { return (kMaxTile / R + kThreads - 1) / kThreads; }
+
+template <typename T, int DIR, int R, bool CONTIG, int LC, int NSC>
+__device__ __forceinline__ void stage_inplace(cplx<T>* buf, const Tile<CONTIG, LC>& tl, int Ns_rt,
+                                              const cplx<T>* __restrict__ twl, int tid)
+{
+    constexpr int KM = kmax_of<R>();
+    const int L = tl.L;
+    const int Ns = (NSC > 0) ? NSC : Ns_rt;
+    const int nb = L / R;
+    const int tot = tl.W * nb;
+    const int twstep = L / (Ns * R);
+    cplx<T> v[KM][R];
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        const int b = tid + kk * kThreads;
+        if (b < tot) {
+            int w, j;
+            if (CONTIG) {
+                w = b / nb;
+                j = b - w * nb;
+            } else {
+                j = b >> tl.wl;
+                w = b & (tl.W - 1);
+            }
+            const cplx<T>* s = buf + w * tl.sw;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[kk][r] = s[(j + r * nb) * tl.si];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        const int b = tid + kk * kThreads;
+        if (b < tot) {
+            int w, j;
+            if (CONTIG) {
+                w = b / nb;
+                j = b - w * nb;
+            } else {
+                j = b >> tl.wl;
+                w = b & (tl.W - 1);
+            }
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cplx<T> t = twl[k * r * twstep];
+                    v[kk][r] = (DIR > 0) ? cmul(v[kk][r], t) : cmulc(v[kk][r], t);
+                }
+            }
+            dftR<T, DIR, R>(v[kk]);
+            const int base = (j / Ns) * Ns * R + k;
+            cplx<T>* d = buf + w * tl.sw;
+#pragma unroll
+            for (int r = 0; r < R; ++r) d[(base + r * Ns) * tl.si] = v[kk][r];
+        }
+    }
+    __syncthreads();
+}
+
+// radix plan of a compile-time length: 8s first, then 4s, 2, 3, 5
+struct CPlan {
+    int nst;
+    int rad[12];
+};
+constexpr CPlan cplan(int n)
+{
+    CPlan p{0, {}};
+    int r = n, p2 = 0;
+    while (r % 2 == 0) {
+        r /= 2;
+        ++p2;
+    }
+    int n8 = p2 / 3, rem = p2 % 3, n4 = 0, n2 = 0;
+    if (rem == 2) n4 = 1;
+    if (rem == 1) {
+        if (n8 > 0) {
+            --n8;
+            n4 = 2;
+        } else {
+            n2 = 1;
+        }
+    }
+    for (int i = 0; i < n8; ++i) p.rad[p.nst++] = 8;
+    for (int i = 0; i < n4; ++i) p.rad[p.nst++] = 4;
+    for (int i = 0; i < n2; ++i) p.rad[p.nst++] = 2;
+    while (r % 3 == 0) {
+        r /= 3;
+        p.rad[p.nst++] = 3;
+    }
+    while (r % 5 == 0) {
+        r /= 5;
+        p.rad[p.nst++] = 5;
+    }
+    return p;
+}
+
+template <typename T, int DIR, bool CONTIG, int LC, int ST, int NS>
+__device__ __forceinline__ void fft_ct(cplx<T>* buf, const Tile<CONTIG, LC>& tl,
+                                       const cplx<T>* __restrict__ twl, int tid)
+{
+    constexpr CPlan P = cplan(LC);
+    if constexpr (ST < P.nst) {
+        constexpr int R = P.rad[ST];
+        stage_inplace<T, DIR, R, CONTIG, LC, NS>(buf, tl, NS, twl, tid);
+        fft_ct<T, DIR, CONTIG, LC, ST + 1, NS * R>(buf, tl, twl, tid);
+    }
+}
+
+// forward (DIR=+1) or unnormalised inverse (DIR=-1) transform of the W lines
+template <typename T, int DIR, bool CONTIG, int LC>
+__device__ void fft_line(cplx<T>* buf, const LinePlan& p, const Tile<CONTIG, LC>& tl,
+                         const cplx<T>* __restrict__ twl, int tid)
+{
+    if constexpr (LC > 0) {
+        fft_ct<T, DIR, CONTIG, LC, 0, 1>(buf, tl, twl, tid);
+    } else {
+        int Ns = 1;
+        for (int s = 0; s < p.nst; ++s) {
+            const int R = p.rad[s];
+            switch (R) {
+                case 2: stage_inplace<T, DIR, 2, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+                case 3: stage_inplace<T, DIR, 3, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+                case 4: stage_inplace<T, DIR, 4, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+                case 5: stage_inplace<T, DIR, 5, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+                default: stage_inplace<T, DIR, 8, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+            }
+            Ns *= R;
+        }
+    }
+}
 
 // spectrum of real field `f` (component f&1 of pair buffer f>>1) at one element
 template <typename T>
@@ -248,18 +307,20 @@ __device__ __forceinline__ double block_reduce(double v, double* sh)
     return r;
 }
 
-template <typename T, typename Tio, bool CONTIG, int LDM, int STM>
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int LC>
 __global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Tile<CONTIG> tl(a.g, blockIdx.x);
+    const Tile<CONTIG, LC> tl(a.g, blockIdx.x);
     const int tid = threadIdx.x;
     const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
     const int nbin = (a.nin + 1) / 2, nbout = (a.nout + 1) / 2;
     cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* in = tab + a.ne * L;
+    cplx<T>* twl = tab + a.ne * L;
+    cplx<T>* in = twl + L;
     cplx<T>* work = in + nbin * BE;
     for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
+    for (int e = tid; e < L; e += kThreads) twl[e] = a.tw[e];
     for (int bi = 0; bi < nbin; ++bi) {
         for (int e = tid; e < E; e += kThreads) {
             int w, i, o;
@@ -269,8 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
         }
     }
     __syncthreads();
-    for (int bi = 0; bi < nbin; ++bi)
-        fft_inplace<T, +1, CONTIG>(in + bi * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+    for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, CONTIG, LC>(in + bi * BE, a.p, tl, twl, tid);
     double dacc = 0.0;
     for (int j = 0; j < nbout; ++j) {
         for (int e = tid; e < E; e += kThreads) {
@@ -280,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
             work[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
         }
         __syncthreads();
-        fft_inplace<T, -1, CONTIG>(work, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        fft_line<T, -1, CONTIG, LC>(work, a.p, tl, twl, tid);
         for (int e = tid; e < E; e += kThreads) {
             int w, i, o;
             long gi;
@@ -321,21 +381,23 @@ struct MidArgs {
 
 enum { PW_K = SEP_PW_K, PW_UH = SEP_PW_UH, PW_LOAD = SEP_PW_LOAD };
 
-template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW>
+template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW, int LC>
 __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SepArgs<T>& a = m.s;
-    const Tile<CONTIG> tl(a.g, blockIdx.x);
+    const Tile<CONTIG, LC> tl(a.g, blockIdx.x);
     const int tid = threadIdx.x;
     const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
     constexpr int NP = (S + 1) / 2;  // pair buffers of D_q / E_p
     const int nbin = (PW == PW_LOAD) ? 0 : (a.nin + 1) / 2;
     cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* in = tab + a.ne * L;
+    cplx<T>* twl = tab + a.ne * L;
+    cplx<T>* in = twl + L;
     cplx<T>* dbuf = in + nbin * BE;
     cplx<T>* work = dbuf + NP * BE;
     for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
+    for (int e = tid; e < L; e += kThreads) twl[e] = a.tw[e];
 
     if constexpr (PW != PW_LOAD) {
         for (int bi = 0; bi < nbin; ++bi)
@@ -346,8 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 in[bi * BE + o] = load_elem<T, Tio, LDM>(a, bi, gi);
             }
         __syncthreads();
-        for (int bi = 0; bi < nbin; ++bi)
-            fft_inplace<T, +1, CONTIG>(in + bi * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, CONTIG, LC>(in + bi * BE, a.p, tl, twl, tid);
         // D_q (pairs) into dbuf
         for (int j = 0; j < NP; ++j) {
             cplx<T>* dj = dbuf + j * BE;
@@ -358,7 +419,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 dj[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
             }
             __syncthreads();
-            fft_inplace<T, -1, CONTIG>(dj, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+            fft_line<T, -1, CONTIG, LC>(dj, a.p, tl, twl, tid);
         }
     }
 
@@ -435,8 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
             }
         }
         __syncthreads();
-        for (int j = 0; j < NP; ++j)
-            fft_inplace<T, +1, CONTIG>(dbuf + j * BE, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+        for (int j = 0; j < NP; ++j) fft_line<T, +1, CONTIG, LC>(dbuf + j * BE, a.p, tl, twl, tid);
         const int nbout = (m.nout2 + 1) / 2;
         double dacc = 0.0;
         for (int j = 0; j < nbout; ++j) {
@@ -447,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 work[o] = combine<T>(*m.pr2, j, dbuf, BE, tab, L, i, o, tl.mirror(w, i));
             }
             __syncthreads();
-            fft_inplace<T, -1, CONTIG>(work, a.p, tl.W, tl.sw, tl.si, a.tw, tid);
+            fft_line<T, -1, CONTIG, LC>(work, a.p, tl, twl, tid);
             for (int e = tid; e < E; e += kThreads) {
                 int w, i, o;
                 long gi;
@@ -489,6 +549,8 @@ static AxisGeom sep_geom(const Ctx& c, int a, int max_tile)
     int W = 16;
     while (W > 1 && ((long)W * g.L > max_tile || div % W != 0)) W >>= 1;
     g.W = W;
+    g.wl = 0;
+    while ((1 << g.wl) < W) ++g.wl;
     return g;
 }
 
@@ -503,7 +565,7 @@ static size_t buf_bytes(const AxisGeom& g, size_t elem)
 static int max_tile(const Ctx& c, int a, int nbuf, size_t elem)
 {
     const size_t budget = (size_t)std::min(c.lds_budget, 65536) - 1024;
-    const size_t tab = (size_t)(2 * c.degree + 1) * c.n[a] * elem;
+    const size_t tab = (size_t)(2 * c.degree + 2) * c.n[a] * elem;  // spectra + twiddles
     int t = kMaxTile;
     while (t > 64 && tab + (size_t)nbuf * (t + 16) * elem > budget) t >>= 1;
     return t;
@@ -536,7 +598,7 @@ size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes)
         if (j == sp.k - 1) nbuf[1] = (nin1 + 1) / 2 + np + 1;  // middle pass
         for (int b = 0; b < 2; ++b) {
             AxisGeom g = sep_geom(c, a, max_tile(c, a, nbuf[b], elem_bytes));
-            size_t need = (size_t)(2 * c.degree + 1) * g.L * elem_bytes + nbuf[b] * buf_bytes(g, elem_bytes);
+            size_t need = (size_t)(2 * c.degree + 2) * g.L * elem_bytes + nbuf[b] * buf_bytes(g, elem_bytes);
             worst = std::max(worst, need);
         }
     }
@@ -556,8 +618,11 @@ static bool sep_log()
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM>
 static void go_pass(const SepArgs<T>& s, size_t sh, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_sep_pass<T, Tio, CONTIG, LDM, STM>), dim3((unsigned)(s.g.nlines / s.g.W)),
-                       dim3(kThreads), sh, st, s);
+    const dim3 grid((unsigned)(s.g.nlines / s.g.W));
+    if (s.g.L == 128)
+        hipLaunchKernelGGL((k_sep_pass<T, Tio, CONTIG, LDM, STM, 128>), grid, dim3(kThreads), sh, st, s);
+    else
+        hipLaunchKernelGGL((k_sep_pass<T, Tio, CONTIG, LDM, STM, 0>), grid, dim3(kThreads), sh, st, s);
     if (sep_log()) {
         hipError_t e = hipPeekAtLastError();
         fprintf(stderr, "[fcrkpm] pass L=%d W=%d st=%ld contig=%d nin=%d nout=%d ld=%d st=%d lds=%zu T=%zu: %s\n",
@@ -584,7 +649,7 @@ void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr,
     s.nout = pr.nout;
     s.dot_part = dot_part;
     s.dot_with = dot_with;
-    const size_t sh = (size_t)s.ne * s.g.L * sizeof(cplx<T>) + (nbin + 1) * buf_bytes(s.g, sizeof(cplx<T>));
+    const size_t sh = (size_t)(s.ne + 1) * s.g.L * sizeof(cplx<T>) + (nbin + 1) * buf_bytes(s.g, sizeof(cplx<T>));
 #define FC_PASS(CT, LD, STO) go_pass<T, Tio, CT, LD, STO>(s, sh, st)
     const bool ct = s.g.contig;
     if (ldm == LD_PAIRS && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_PAIRS, ST_PAIRS); else FC_PASS(false, LD_PAIRS, ST_PAIRS); }
@@ -597,8 +662,17 @@ void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr,
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW>
 static void go_mid(const MidArgs<T>& m, size_t sh, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_sep_mid<T, Tio, CONTIG, LDM, STM, S, DIM, PW>),
-                       dim3((unsigned)(m.s.g.nlines / m.s.g.W)), dim3(kThreads), sh, st, m);
+    const dim3 grid((unsigned)(m.s.g.nlines / m.s.g.W));
+    // the 128-point lines of the 3D workloads get the compile-time plan
+    if constexpr (DIM == 3 && !CONTIG) {
+        if (m.s.g.L == 128) {
+            hipLaunchKernelGGL((k_sep_mid<T, Tio, CONTIG, LDM, STM, S, DIM, PW, 128>), grid,
+                               dim3(kThreads), sh, st, m);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sep_mid<T, Tio, CONTIG, LDM, STM, S, DIM, PW, 0>), grid, dim3(kThreads),
+                       sh, st, m);
     if (sep_log()) {
         hipError_t e = hipPeekAtLastError();
         fprintf(stderr, "[fcrkpm] mid L=%d W=%d st=%ld pw=%d nin=%d nout2=%d lds=%zu T=%zu: %s\n",
@@ -653,7 +727,7 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.vol = vol;
     m.src = src;
     m.nn = c.nn;
-    const size_t sh = (size_t)m.s.ne * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
+    const size_t sh = (size_t)(m.s.ne + 1) * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
     if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, st);
     else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, st);
     else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, st);
