@@ -30,37 +30,50 @@
 namespace fcrkpm {
 
 // ------------------------------------------------------------- tile geometry
-// A workgroup owns W lines (W a power of two) of length L along the axis.
-// LC > 0 fixes L at compile time (the hot sizes), LC = 0 reads it at run time.
+// A workgroup owns W lines (W a power of two) of length L along the axis and
+// keeps them line-contiguous in LDS with pitch L+1.  Loads, stores and the
+// pointwise stage use the cooperative mapping (consecutive threads touch
+// consecutive global addresses); FFT stages and spectral combinations run
+// wave-locally when W is a multiple of the 4 waves (each wave owns W/4 whole
+// lines), otherwise the whole workgroup cooperates.  LC > 0 fixes L at
+// compile time (the hot sizes), LC = 0 reads it at run time.
 constexpr int kThreads = 256;
+constexpr int kWave = 64;
 constexpr int kMaxTile = 2048;
+constexpr int kLoadChunk = 8;   // tile elements per thread whose loads are in flight together
+constexpr int kPwChunk = 4;     // the same for the pointwise stage (more loads per element)
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
+// XCD walks a contiguous run of tiles and neighbouring tiles share its L2.
+__device__ __forceinline__ long xcd_tile(long b, long nblocks)
+{
+    if (nblocks % 8 != 0) return b;
+    return (b & 7) * (nblocks >> 3) + (b >> 3);
+}
 
 template <bool CONTIG, int LC>
 struct Tile {
     long gbase;
     long st;
-    int W, wl, L, sw, si;
+    int W, wl, L, P;
     __device__ __forceinline__ Tile(const AxisGeom& g, long t)
     {
         W = g.W;
         wl = g.wl;
         L = LC > 0 ? LC : g.L;
+        P = L + 1;
         st = g.st;
         if (CONTIG) {
             gbase = t * (long)W * L;
-            sw = L + 1;
-            si = 1;
         } else {
             long l0 = t * W;
             long lo = l0 % g.st, hi = l0 / g.st;
             gbase = lo + hi * g.st * L;
-            sw = 1;
-            si = W;
         }
     }
     __device__ __forceinline__ int elems() const { return W * L; }
-    __device__ __forceinline__ int buf_elems() const { return CONTIG ? W * (L + 1) : W * L; }
-    // element e of the tile: line w, position i, global index gi, LDS offset o
+    __device__ __forceinline__ int buf_elems() const { return W * P; }
+    // cooperative mapping of tile element e: line w, position i, global gi, LDS o
     __device__ __forceinline__ void at(int e, int& w, int& i, long& gi, int& o) const
     {
         if (CONTIG) {
@@ -72,65 +85,83 @@ struct Tile {
             w = e & (W - 1);
             gi = gbase + w + (long)i * st;
         }
-        o = w * sw + i * si;
-    }
-    __device__ __forceinline__ int mirror(int w, int i) const
-    {
-        const int im = (i == 0) ? 0 : L - i;
-        return w * sw + im * si;
+        o = w * P + i;
     }
 };
 
+// The lines one wave (or the whole workgroup) works on in the local phases.
+struct Crew {
+    int w0, nl;    // first line and line count
+    int id, n;     // thread id within the crew and crew size
+    bool wave;     // wave-local (true) or workgroup-wide
+};
+
+__device__ __forceinline__ Crew make_crew(int W, int tid)
+{
+    Crew c;
+    c.wave = (W % 4) == 0;
+    if (c.wave) {
+        c.nl = W / 4;
+        c.w0 = (tid / kWave) * c.nl;
+        c.id = tid % kWave;
+        c.n = kWave;
+    } else {
+        c.nl = W;
+        c.w0 = 0;
+        c.id = tid;
+        c.n = kThreads;
+    }
+    return c;
+}
+
+// Orders LDS accesses of the crew: a wave runs in lockstep, so a wave-scope
+// fence and scheduling barrier suffice; otherwise a workgroup barrier.
+__device__ __forceinline__ void crew_sync(const Crew& c)
+{
+    if (c.wave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // --------------------------------------------------------------- in-place FFT
-// Stockham stages done in place: each thread loads the inputs of its
-// butterflies, the workgroup synchronises, then the outputs are written.
-// With at most 2048 tile elements and 256 threads a thread owns at most
-// ceil(2048 / (R * 256)) butterflies.  twl is the LDS copy of
+// Stockham stages done in place on the crew's lines: every thread loads the
+// inputs of its butterflies, the crew synchronises, then the outputs are
+// written.  A crew holds at most 8 elements per thread (W*L <= 2048 over
+// 256 threads, or W/4 lines over one wave).  twl is the LDS copy of
 // e^{-2 pi i k / L}, k < L.
 template <int R>
-constexpr int kmax_of() { return (kMaxTile / R + kThreads - 1) / kThreads; }
+constexpr int kmax_of() { return (8 + R - 1) / R; }
 
-template <typename T, int DIR, int R, bool CONTIG, int LC, int NSC>
-__device__ __forceinline__ void stage_inplace(cplx<T>* buf, const Tile<CONTIG, LC>& tl, int Ns_rt,
-                                              const cplx<T>* __restrict__ twl, int tid)
+template <typename T, int DIR, int R, int NSC>
+__device__ __forceinline__ void stage(cplx<T>* buf, int L, int P, const Crew& cr, int Ns_rt,
+                                      const cplx<T>* __restrict__ twl)
 {
     constexpr int KM = kmax_of<R>();
-    const int L = tl.L;
     const int Ns = (NSC > 0) ? NSC : Ns_rt;
     const int nb = L / R;
-    const int tot = tl.W * nb;
+    const int tot = cr.nl * nb;
     const int twstep = L / (Ns * R);
     cplx<T> v[KM][R];
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) {
-        const int b = tid + kk * kThreads;
+        const int b = cr.id + kk * cr.n;
         if (b < tot) {
-            int w, j;
-            if (CONTIG) {
-                w = b / nb;
-                j = b - w * nb;
-            } else {
-                j = b >> tl.wl;
-                w = b & (tl.W - 1);
-            }
-            const cplx<T>* s = buf + w * tl.sw;
+            const int wl = b / nb, j = b - wl * nb;
+            const cplx<T>* s = buf + (cr.w0 + wl) * P + j;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[kk][r] = s[(j + r * nb) * tl.si];
+            for (int r = 0; r < R; ++r) v[kk][r] = s[r * nb];
         }
     }
-    __syncthreads();
+    crew_sync(cr);
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) {
-        const int b = tid + kk * kThreads;
+        const int b = cr.id + kk * cr.n;
         if (b < tot) {
-            int w, j;
-            if (CONTIG) {
-                w = b / nb;
-                j = b - w * nb;
-            } else {
-                j = b >> tl.wl;
-                w = b & (tl.W - 1);
-            }
+            const int wl = b / nb, j = b - wl * nb;
             const int k = j % Ns;
             if (Ns > 1) {
 #pragma unroll
@@ -140,13 +171,12 @@ __device__ __forceinline__ void stage_inplace(cplx<T>* buf, const Tile<CONTIG, L
                 }
             }
             dftR<T, DIR, R>(v[kk]);
-            const int base = (j / Ns) * Ns * R + k;
-            cplx<T>* d = buf + w * tl.sw;
+            cplx<T>* d = buf + (cr.w0 + wl) * P + (j / Ns) * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) d[(base + r * Ns) * tl.si] = v[kk][r];
+            for (int r = 0; r < R; ++r) d[r * Ns] = v[kk][r];
         }
     }
-    __syncthreads();
+    crew_sync(cr);
 }
 
 // radix plan of a compile-time length: 8s first, then 4s, 2, 3, 5
@@ -186,35 +216,35 @@ constexpr CPlan cplan(int n)
     return p;
 }
 
-template <typename T, int DIR, bool CONTIG, int LC, int ST, int NS>
-__device__ __forceinline__ void fft_ct(cplx<T>* buf, const Tile<CONTIG, LC>& tl,
-                                       const cplx<T>* __restrict__ twl, int tid)
+template <typename T, int DIR, int LC, int ST, int NS>
+__device__ __forceinline__ void fft_ct(cplx<T>* buf, int P, const Crew& cr,
+                                       const cplx<T>* __restrict__ twl)
 {
-    constexpr CPlan P = cplan(LC);
-    if constexpr (ST < P.nst) {
-        constexpr int R = P.rad[ST];
-        stage_inplace<T, DIR, R, CONTIG, LC, NS>(buf, tl, NS, twl, tid);
-        fft_ct<T, DIR, CONTIG, LC, ST + 1, NS * R>(buf, tl, twl, tid);
+    constexpr CPlan PL = cplan(LC);
+    if constexpr (ST < PL.nst) {
+        constexpr int R = PL.rad[ST];
+        stage<T, DIR, R, NS>(buf, LC, P, cr, NS, twl);
+        fft_ct<T, DIR, LC, ST + 1, NS * R>(buf, P, cr, twl);
     }
 }
 
-// forward (DIR=+1) or unnormalised inverse (DIR=-1) transform of the W lines
-template <typename T, int DIR, bool CONTIG, int LC>
-__device__ void fft_line(cplx<T>* buf, const LinePlan& p, const Tile<CONTIG, LC>& tl,
-                         const cplx<T>* __restrict__ twl, int tid)
+// forward (DIR=+1) or unnormalised inverse (DIR=-1) transform of the crew's lines
+template <typename T, int DIR, int LC>
+__device__ void fft_line(cplx<T>* buf, const LinePlan& p, int L, int P, const Crew& cr,
+                         const cplx<T>* __restrict__ twl)
 {
     if constexpr (LC > 0) {
-        fft_ct<T, DIR, CONTIG, LC, 0, 1>(buf, tl, twl, tid);
+        fft_ct<T, DIR, LC, 0, 1>(buf, P, cr, twl);
     } else {
         int Ns = 1;
         for (int s = 0; s < p.nst; ++s) {
             const int R = p.rad[s];
             switch (R) {
-                case 2: stage_inplace<T, DIR, 2, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
-                case 3: stage_inplace<T, DIR, 3, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
-                case 4: stage_inplace<T, DIR, 4, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
-                case 5: stage_inplace<T, DIR, 5, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
-                default: stage_inplace<T, DIR, 8, CONTIG, LC, 0>(buf, tl, Ns, twl, tid); break;
+                case 2: stage<T, DIR, 2, 0>(buf, L, P, cr, Ns, twl); break;
+                case 3: stage<T, DIR, 3, 0>(buf, L, P, cr, Ns, twl); break;
+                case 4: stage<T, DIR, 4, 0>(buf, L, P, cr, Ns, twl); break;
+                case 5: stage<T, DIR, 5, 0>(buf, L, P, cr, Ns, twl); break;
+                default: stage<T, DIR, 8, 0>(buf, L, P, cr, Ns, twl); break;
             }
             Ns *= R;
         }
@@ -259,6 +289,22 @@ __device__ __forceinline__ cplx<T> combine(const SepProg& pr, int j, const cplx<
     return acc;
 }
 
+// out_buf <- spectrum of output pair j for the crew's lines
+template <typename T>
+__device__ __forceinline__ void combine_lines(const SepProg& pr, int j, const cplx<T>* in, int BE,
+                                              const cplx<T>* tab, int L, int P, const Crew& cr,
+                                              cplx<T>* out_buf)
+{
+    const int tot = cr.nl * L;
+    for (int e = cr.id; e < tot; e += cr.n) {
+        const int wl = e / L, i = e - wl * L;
+        const int w = cr.w0 + wl;
+        const int o = w * P + i;
+        const int om = w * P + (i == 0 ? 0 : L - i);
+        out_buf[o] = combine<T>(pr, j, in, BE, tab, L, i, o, om);
+    }
+}
+
 // ------------------------------------------------------------ generic pass
 template <typename T>
 struct SepArgs {
@@ -287,8 +333,10 @@ __device__ __forceinline__ cplx<T> load_elem(const SepArgs<T>& a, int bi, long g
     if constexpr (LDM == LD_PAIRS) {
         return reinterpret_cast<const cplx<T>*>(a.in)[bi * a.fstride + gi];
     } else if constexpr (LDM == LD_REAL) {
-        T v = a.mask_in[gi] ? T(reinterpret_cast<const Tio*>(a.in)[gi]) : T(0);
-        return cplx<T>{v, T(0)};
+        // both loads issue together; the mask only selects
+        const uint8_t mk = a.mask_in[gi];
+        const T x = T(reinterpret_cast<const Tio*>(a.in)[gi]);
+        return cplx<T>{mk ? x : T(0), T(0)};
     } else {
         return cplx<T>{a.mask_in[gi] ? T(1) : T(0), T(0)};
     }
@@ -307,52 +355,100 @@ __device__ __forceinline__ double block_reduce(double v, double* sh)
     return r;
 }
 
+// cooperative load of nb pair buffers of the tile
+template <typename T, typename Tio, bool CONTIG, int LDM, int LC>
+__device__ __forceinline__ void load_tile(const SepArgs<T>& a, const Tile<CONTIG, LC>& tl, int nb,
+                                          cplx<T>* in, int BE, int tid)
+{
+    // All loads of a chunk are issued before the first LDS write.  Lanes past
+    // the tile end repeat its last element, which writes the same value twice.
+    const int E = tl.elems();
+    for (int bi = 0; bi < nb; ++bi)
+        for (int base = 0; base < E; base += kLoadChunk * kThreads) {
+            cplx<T> v[kLoadChunk];
+            int o[kLoadChunk];
+#pragma unroll
+            for (int kk = 0; kk < kLoadChunk; ++kk) {
+                const int e = min(base + tid + kk * kThreads, E - 1);
+                int w, i;
+                long gi;
+                tl.at(e, w, i, gi, o[kk]);
+                v[kk] = load_elem<T, Tio, LDM>(a, bi, gi);
+            }
+#pragma unroll
+            for (int kk = 0; kk < kLoadChunk; ++kk) in[bi * BE + o[kk]] = v[kk];
+        }
+}
+
+// cooperative store of one output pair; returns this thread's dot partial
+template <typename T, typename Tio, bool CONTIG, int STM, int LC>
+__device__ __forceinline__ double store_tile(const SepArgs<T>& a, const Tile<CONTIG, LC>& tl, int j,
+                                             const cplx<T>* src, int tid)
+{
+    const int E = tl.elems();
+    double dacc = 0.0;
+    if constexpr (STM == ST_PAIRS) {
+        for (int e = tid; e < E; e += kThreads) {
+            int w, i, o;
+            long gi;
+            tl.at(e, w, i, gi, o);
+            reinterpret_cast<cplx<T>*>(a.out)[j * a.fstride + gi] = src[o];
+        }
+    } else {
+        // masks (and the dot operand) of a chunk are loaded before any store
+        const bool dot = a.dot_part != nullptr;
+        for (int base = 0; base < E; base += kLoadChunk * kThreads) {
+            uint8_t mk[kLoadChunk];
+            Tio dw[kLoadChunk];
+            long g[kLoadChunk];
+            int o[kLoadChunk];
+#pragma unroll
+            for (int kk = 0; kk < kLoadChunk; ++kk) {
+                const int e = min(base + tid + kk * kThreads, E - 1);
+                int w, i;
+                tl.at(e, w, i, g[kk], o[kk]);
+                mk[kk] = a.mask_out[g[kk]];
+                dw[kk] = dot ? reinterpret_cast<const Tio*>(a.dot_with)[g[kk]] : Tio(0);
+            }
+#pragma unroll
+            for (int kk = 0; kk < kLoadChunk; ++kk) {
+                if (base + tid + kk * kThreads < E) {
+                    const Tio v = mk[kk] ? Tio(src[o[kk]].x) : Tio(0);
+                    reinterpret_cast<Tio*>(a.out)[g[kk]] = v;
+                    dacc += (double)v * (double)dw[kk];
+                }
+            }
+        }
+    }
+    return dacc;
+}
+
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int LC>
 __global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Tile<CONTIG, LC> tl(a.g, blockIdx.x);
+    const Tile<CONTIG, LC> tl(a.g, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x;
-    const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
+    const int L = tl.L, P = tl.P, BE = tl.buf_elems();
     const int nbin = (a.nin + 1) / 2, nbout = (a.nout + 1) / 2;
+    const SepProg& pr = *a.pr;
     cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* twl = tab + a.ne * L;
     cplx<T>* in = twl + L;
     cplx<T>* work = in + nbin * BE;
     for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
     for (int e = tid; e < L; e += kThreads) twl[e] = a.tw[e];
-    for (int bi = 0; bi < nbin; ++bi) {
-        for (int e = tid; e < E; e += kThreads) {
-            int w, i, o;
-            long gi;
-            tl.at(e, w, i, gi, o);
-            in[bi * BE + o] = load_elem<T, Tio, LDM>(a, bi, gi);
-        }
-    }
+    load_tile<T, Tio, CONTIG, LDM, LC>(a, tl, nbin, in, BE, tid);
     __syncthreads();
-    for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, CONTIG, LC>(in + bi * BE, a.p, tl, twl, tid);
+    const Crew cr = make_crew(tl.W, tid);
+    for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, LC>(in + bi * BE, a.p, L, P, cr, twl);
     double dacc = 0.0;
     for (int j = 0; j < nbout; ++j) {
-        for (int e = tid; e < E; e += kThreads) {
-            int w, i, o;
-            long gi;
-            tl.at(e, w, i, gi, o);
-            work[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
-        }
+        combine_lines<T>(pr, j, in, BE, tab, L, P, cr, work);
+        crew_sync(cr);
+        fft_line<T, -1, LC>(work, a.p, L, P, cr, twl);
         __syncthreads();
-        fft_line<T, -1, CONTIG, LC>(work, a.p, tl, twl, tid);
-        for (int e = tid; e < E; e += kThreads) {
-            int w, i, o;
-            long gi;
-            tl.at(e, w, i, gi, o);
-            if constexpr (STM == ST_PAIRS) {
-                reinterpret_cast<cplx<T>*>(a.out)[j * a.fstride + gi] = work[o];
-            } else {
-                Tio v = a.mask_out[gi] ? Tio(work[o].x) : Tio(0);
-                reinterpret_cast<Tio*>(a.out)[gi] = v;
-                if (a.dot_part) dacc += (double)v * (double)reinterpret_cast<const Tio*>(a.dot_with)[gi];
-            }
-        }
+        dacc += store_tile<T, Tio, CONTIG, STM, LC>(a, tl, j, work, tid);
         __syncthreads();
     }
     if constexpr (STM == ST_REAL) {
@@ -386,9 +482,9 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SepArgs<T>& a = m.s;
-    const Tile<CONTIG, LC> tl(a.g, blockIdx.x);
+    const Tile<CONTIG, LC> tl(a.g, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x;
-    const int L = tl.L, E = tl.elems(), BE = tl.buf_elems();
+    const int L = tl.L, P = tl.P, E = tl.elems(), BE = tl.buf_elems();
     constexpr int NP = (S + 1) / 2;  // pair buffers of D_q / E_p
     const int nbin = (PW == PW_LOAD) ? 0 : (a.nin + 1) / 2;
     cplx<T>* tab = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -398,54 +494,73 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
     cplx<T>* work = dbuf + NP * BE;
     for (int e = tid; e < a.ne * L; e += kThreads) tab[e] = a.tab[e];
     for (int e = tid; e < L; e += kThreads) twl[e] = a.tw[e];
+    const Crew cr = make_crew(tl.W, tid);
 
     if constexpr (PW != PW_LOAD) {
-        for (int bi = 0; bi < nbin; ++bi)
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
-                long gi;
-                tl.at(e, w, i, gi, o);
-                in[bi * BE + o] = load_elem<T, Tio, LDM>(a, bi, gi);
-            }
+        load_tile<T, Tio, CONTIG, LDM, LC>(a, tl, nbin, in, BE, tid);
         __syncthreads();
-        for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, CONTIG, LC>(in + bi * BE, a.p, tl, twl, tid);
+        for (int bi = 0; bi < nbin; ++bi) fft_line<T, +1, LC>(in + bi * BE, a.p, L, P, cr, twl);
         // D_q (pairs) into dbuf
+        const SepProg& pr1 = *a.pr;
         for (int j = 0; j < NP; ++j) {
-            cplx<T>* dj = dbuf + j * BE;
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
-                long gi;
-                tl.at(e, w, i, gi, o);
-                dj[o] = combine<T>(*a.pr, j, in, BE, tab, L, i, o, tl.mirror(w, i));
-            }
-            __syncthreads();
-            fft_line<T, -1, CONTIG, LC>(dj, a.p, tl, twl, tid);
+            combine_lines<T>(pr1, j, in, BE, tab, L, P, cr, dbuf + j * BE);
+            crew_sync(cr);
+            fft_line<T, -1, LC>(dbuf + j * BE, a.p, L, P, cr, twl);
         }
+        __syncthreads();
     }
 
     if constexpr (PW == PW_UH) {
         // u = sum_p b0_p D_p (times V for V o N)   (Eq 94)
-        for (int e = tid; e < E; e += kThreads) {
-            int w, i, o;
-            long gi;
-            tl.at(e, w, i, gi, o);
-            T acc = T(0);
+        for (int base = 0; base < E; base += kPwChunk * kThreads) {
+            T b[kPwChunk][S], v[kPwChunk];
+            long g[kPwChunk];
+            int o[kPwChunk];
 #pragma unroll
-            for (int p = 0; p < S; ++p) {
-                cplx<T> c = dbuf[(p >> 1) * BE + o];
-                acc += m.b0[p * m.nn + gi] * ((p & 1) ? c.y : c.x);
+            for (int kk = 0; kk < kPwChunk; ++kk) {
+                const int e = min(base + tid + kk * kThreads, E - 1);
+                int w, i;
+                tl.at(e, w, i, g[kk], o[kk]);
+#pragma unroll
+                for (int p = 0; p < S; ++p) b[kk][p] = m.b0[p * m.nn + g[kk]];
+                v[kk] = m.vol ? m.vol[g[kk]] : T(1);
             }
-            if (m.vol) acc *= m.vol[gi];
-            reinterpret_cast<Tio*>(a.out)[gi] = Tio(acc);
+#pragma unroll
+            for (int kk = 0; kk < kPwChunk; ++kk) {
+                if (base + tid + kk * kThreads < E) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int p = 0; p < S; ++p) {
+                        cplx<T> c = dbuf[(p >> 1) * BE + o[kk]];
+                        acc += b[kk][p] * ((p & 1) ? c.y : c.x);
+                    }
+                    reinterpret_cast<Tio*>(a.out)[g[kk]] = Tio(acc * v[kk]);
+                }
+            }
         }
         return;
     } else {
         if constexpr (PW == PW_K) {
             // A^a = sum_q b^a_q D_q ; E_p = V sum_a b^a_p A^a   (Eq 90-91, Alg 2)
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
+            for (int base = 0; base < E; base += kPwChunk * kThreads) {
+              T bb[kPwChunk][DIM][S], vv[kPwChunk];
+              int oo[kPwChunk];
+#pragma unroll
+              for (int kk = 0; kk < kPwChunk; ++kk) {
+                const int e = min(base + tid + kk * kThreads, E - 1);
+                int w, i;
                 long gi;
-                tl.at(e, w, i, gi, o);
+                tl.at(e, w, i, gi, oo[kk]);
+#pragma unroll
+                for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                    for (int q = 0; q < S; ++q) bb[kk][al][q] = m.ba[(al * S + q) * m.nn + gi];
+                vv[kk] = m.vol[gi];
+              }
+#pragma unroll
+              for (int kk = 0; kk < kPwChunk; ++kk) {
+                if (base + tid + kk * kThreads >= E) continue;
+                const int o = oo[kk];
                 T D[NP * 2];
 #pragma unroll
                 for (int j = 0; j < NP; ++j) {
@@ -453,11 +568,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                     D[2 * j] = c.x;
                     D[2 * j + 1] = c.y;
                 }
-                T b[DIM][S];
-#pragma unroll
-                for (int al = 0; al < DIM; ++al)
-#pragma unroll
-                    for (int q = 0; q < S; ++q) b[al][q] = m.ba[(al * S + q) * m.nn + gi];
+                T (&b)[DIM][S] = bb[kk];
                 T A[DIM];
 #pragma unroll
                 for (int al = 0; al < DIM; ++al) {
@@ -466,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                     for (int q = 0; q < S; ++q) acc += b[al][q] * D[q];
                     A[al] = acc;
                 }
-                const T v = m.vol[gi];
+                const T v = vv[kk];
                 T Ep[NP * 2];
 #pragma unroll
                 for (int p = 0; p < S; ++p) {
@@ -478,49 +589,46 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 if (S & 1) Ep[S] = T(0);
 #pragma unroll
                 for (int j = 0; j < NP; ++j) dbuf[j * BE + o] = cplx<T>{Ep[2 * j], Ep[2 * j + 1]};
+              }
             }
         } else {
             // E_p = (V) b0_p r   (Eq 92, Alg 4)
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
-                long gi;
-                tl.at(e, w, i, gi, o);
-                T x = T(reinterpret_cast<const Tio*>(m.src)[gi]);
-                if (m.vol) x *= m.vol[gi];
-                T Ep[NP * 2];
+            for (int base = 0; base < E; base += kPwChunk * kThreads) {
+                T b[kPwChunk][S], x[kPwChunk];
+                int o[kPwChunk];
 #pragma unroll
-                for (int p = 0; p < S; ++p) Ep[p] = m.b0[p * m.nn + gi] * x;
-                if (S & 1) Ep[S] = T(0);
+                for (int kk = 0; kk < kPwChunk; ++kk) {
+                    const int e = min(base + tid + kk * kThreads, E - 1);
+                    int w, i;
+                    long gi;
+                    tl.at(e, w, i, gi, o[kk]);
+                    x[kk] = T(reinterpret_cast<const Tio*>(m.src)[gi]) * (m.vol ? m.vol[gi] : T(1));
 #pragma unroll
-                for (int j = 0; j < NP; ++j) dbuf[j * BE + o] = cplx<T>{Ep[2 * j], Ep[2 * j + 1]};
+                    for (int p = 0; p < S; ++p) b[kk][p] = m.b0[p * m.nn + gi];
+                }
+#pragma unroll
+                for (int kk = 0; kk < kPwChunk; ++kk) {
+                    if (base + tid + kk * kThreads >= E) continue;
+                    T Ep[NP * 2];
+#pragma unroll
+                    for (int p = 0; p < S; ++p) Ep[p] = b[kk][p] * x[kk];
+                    if (S & 1) Ep[S] = T(0);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) dbuf[j * BE + o[kk]] = cplx<T>{Ep[2 * j], Ep[2 * j + 1]};
+                }
             }
         }
         __syncthreads();
-        for (int j = 0; j < NP; ++j) fft_line<T, +1, CONTIG, LC>(dbuf + j * BE, a.p, tl, twl, tid);
+        for (int j = 0; j < NP; ++j) fft_line<T, +1, LC>(dbuf + j * BE, a.p, L, P, cr, twl);
         const int nbout = (m.nout2 + 1) / 2;
+        const SepProg& pr2 = *m.pr2;
         double dacc = 0.0;
         for (int j = 0; j < nbout; ++j) {
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
-                long gi;
-                tl.at(e, w, i, gi, o);
-                work[o] = combine<T>(*m.pr2, j, dbuf, BE, tab, L, i, o, tl.mirror(w, i));
-            }
+            combine_lines<T>(pr2, j, dbuf, BE, tab, L, P, cr, work);
+            crew_sync(cr);
+            fft_line<T, -1, LC>(work, a.p, L, P, cr, twl);
             __syncthreads();
-            fft_line<T, -1, CONTIG, LC>(work, a.p, tl, twl, tid);
-            for (int e = tid; e < E; e += kThreads) {
-                int w, i, o;
-                long gi;
-                tl.at(e, w, i, gi, o);
-                if constexpr (STM == ST_PAIRS) {
-                    reinterpret_cast<cplx<T>*>(a.out)[j * a.fstride + gi] = work[o];
-                } else {
-                    Tio v = a.mask_out[gi] ? Tio(work[o].x) : Tio(0);
-                    reinterpret_cast<Tio*>(a.out)[gi] = v;
-                    if (a.dot_part)
-                        dacc += (double)v * (double)reinterpret_cast<const Tio*>(a.dot_with)[gi];
-                }
-            }
+            dacc += store_tile<T, Tio, CONTIG, STM, LC>(a, tl, j, work, tid);
             __syncthreads();
         }
         if constexpr (STM == ST_REAL) {
@@ -556,7 +664,7 @@ static AxisGeom sep_geom(const Ctx& c, int a, int max_tile)
 
 static size_t buf_bytes(const AxisGeom& g, size_t elem)
 {
-    return (size_t)(g.contig ? g.W * (g.L + 1) : g.W * g.L) * elem;
+    return (size_t)g.W * (g.L + 1) * elem;
 }
 
 // Largest tile (elements per buffer, a power of two <= kMaxTile) whose nbuf
