@@ -145,23 +145,46 @@ fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t n
  *   mode     FCRKPM_MODE_F64 or FCRKPM_MODE_F32_REFINED (FP32 inner CG,
  *            FP64 outer residual b - K d; falls back to FP64 CG if the
  *            refinement stagnates)
- *   nrhs     number of independent problems (fields laid out back to back)
+ *   nrhs     number of right-hand sides (fields laid out back to back); they
+ *            iterate together, every pass and CG kernel covering all of
+ *            them in one launch, and each stops on its own tolerance
  *   r        device FP64 source per node (Eq 8)
  *   g        device FP64 Dirichlet values per node, or NULL for g = 0
  *   d_inout  device FP64: initial guess on the free nodes in (zeros = the
  *            paper's start), solution coefficients out
  *   uh_out   device FP64 u^h = N d (Alg 3), or NULL
  *   tol      relative residual target (> 0)
- *   maxit    iteration cap (CG iterations in total per problem)
- *   info     filled for the last problem solved (may be NULL)
+ *   maxit    iteration cap (CG iterations in total, shared by the
+ *            right-hand sides of the call)
+ *   info     array of nrhs records, one per right-hand side (may be NULL)
  *
+ * Blocks of 8 CG iterations are captured once into a HIP graph and replayed
+ * (see FCRKPM_OPT_GRAPHS); the host polls convergence between blocks.
  * Returns FCRKPM_ERR_NOCONV with the best d written when maxit is reached or
- * CG breaks down (p^T K p <= 0); FCRKPM_ERR_ARG for NaN/Inf in r or bad
- * arguments.
+ * CG breaks down (p^T K p <= 0) for any right-hand side; FCRKPM_ERR_ARG for
+ * NaN/Inf in r, g or the initial guess, or bad arguments.
  */
 fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* r,
                            const double* g, double* d_inout, double* uh_out, double tol,
                            int32_t maxit, fcrkpm_info* info, void* stream);
+
+/*
+ * fcrkpm_solve_batch -- fcrkpm_solve for a ragged batch of problems: nprob
+ * contexts (distinct; box sizes may differ), problem p with nrhs[p]
+ * right-hand sides r[p], Dirichlet values g[p] (g or g[p] may be NULL),
+ * d_inout[p] and uh_out[p] (uh_out or uh_out[p] may be NULL), as in
+ * fcrkpm_solve.  All problems iterate together on `stream`: each block of 8
+ * CG iterations of every unfinished problem is one captured HIP graph whose
+ * per-problem branches run concurrently, re-captured only when a problem
+ * finishes or changes phase.  info, if not NULL, holds sum(nrhs) records,
+ * problem by problem.  Status: the worst of the problems; the message is set
+ * on every context of the batch.
+ */
+fcrkpm_status fcrkpm_solve_batch(fcrkpm_ctx* const* ctxs, int32_t nprob, int32_t mode,
+                                 const int32_t* nrhs, const double* const* r,
+                                 const double* const* g, double* const* d_inout,
+                                 double* const* uh_out, double tol, int32_t maxit,
+                                 fcrkpm_info* info, void* stream);
 
 /*
  * fcrkpm_adjoint -- gradient of a loss of u^h(r) with respect to the source.
@@ -202,6 +225,13 @@ fcrkpm_status fcrkpm_profile_read(fcrkpm_ctx* ctx, int32_t kind, int64_t* launch
                                   double* mean_ms, double* bytes_per_launch);
 int32_t fcrkpm_kernel_kinds(void);
 const char* fcrkpm_kernel_name(int32_t kind);
+
+/* Options of a context, set with fcrkpm_set_option. */
+enum {
+    FCRKPM_OPT_GRAPHS = 1 /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
+                             launches.  Graphs are never used while profiling is on. */
+};
+fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);
 
 /* Basis size s = (n+d)!/(d! n!) of the context (Eq 5), or -1 for NULL. */
 int32_t fcrkpm_basis_size(const fcrkpm_ctx* ctx);

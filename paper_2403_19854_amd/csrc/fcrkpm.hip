@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <memory>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -82,7 +83,7 @@ struct ProfScope {
     hipStream_t st;
     bool rec = false;
     ProfScope(Ctx& c, int kind_, double bytes, hipStream_t st_)
-        : p(c.prof_on ? (Prof*)c.prof : nullptr), kind(kind_), st(st_)
+        : p(c.prof_on && !c.capturing ? (Prof*)c.prof : nullptr), kind(kind_), st(st_)
     {
         if (!p) return;
         ProfKind& k = p->k[kind];
@@ -142,12 +143,13 @@ void release(Ctx& c)
     dfree(c.v32);
     dfree(c.partial);
     dfree(c.scal);
+    dfree(c.act);
     dfree(c.dflag);
+    if (c.aux) (void)hipStreamDestroy(c.aux);
+    c.aux = nullptr;
     dfree(c.dprog);
     if (c.hscal) (void)hipHostFree(c.hscal);
     c.hscal = nullptr;
-    for (auto& e : c.poll_ev)
-        if (e) (void)hipEventDestroy(e);
     if (c.prof) {
         Prof* p = (Prof*)c.prof;
         for (auto& k : p->k)
@@ -327,80 +329,107 @@ int kind_of(int stage) { return stage + (sizeof(T) == 4 ? KD_STAGES : 0); }
 template <typename T>
 double pair_bytes(int nreal) { return (double)((nreal + 1) / 2) * sizeof(cplx<T>); }
 
-// Part-1 passes on axes 0..k-2 (Alg 2/3 first half): the field `in` (Tio,
-// masked) becomes P_{k-2} pairs; returns the slot that holds them.
+// Pass workspace for nrhs right-hand sides (both precisions).
+void ensure_work(Ctx& c, int nrhs)
+{
+    if (nrhs <= c.cap_work) return;
+    if (c.capturing) fail(FCRKPM_ERR_ARG, "workspace cannot grow during graph capture");
+    HIPCHK(hipDeviceSynchronize());
+    dfree(c.work64);
+    dfree(c.work32);
+    c.cap_work = 0;
+    const size_t per = (size_t)2 * c.basis_plan.maxpairs * c.nn;
+    c.work64 = dalloc<cplx<double>>(per * nrhs);
+    c.work32 = dalloc<cplx<float>>(per * nrhs);
+    c.cap_work = nrhs;
+}
+
+// bytes between right-hand sides of a pair-field slot and of a real field
+template <typename T>
+long pair_rstride(const Ctx& c) { return (long)c.basis_plan.maxpairs * c.nn * (long)sizeof(cplx<T>); }
+template <typename Tio>
+long real_rstride(const Ctx& c) { return c.nn * (long)sizeof(Tio); }
+
+// Part-1 passes on axes 0..k-2 (Alg 2/3 first half): the fields `in` (Tio,
+// masked) become P_{k-2} pairs; returns the slot that holds them.
 template <typename T, typename Tio>
 cplx<T>* part1(Ctx& c, const SepPlan& sp, const Tio* in, const uint8_t* mask, cplx<T>* S1,
-               cplx<T>* S2, hipStream_t st)
+               cplx<T>* S2, int nrhs, hipStream_t st)
 {
-    const double nn = (double)c.nn;
+    const double nn = (double)c.nn * nrhs;
     const void* src = in;
     cplx<T>* dst = S1;
     for (int j = 0; j + 1 < sp.k; ++j) {
         const int ldm = (j == 0) ? SEP_LD_REAL : SEP_LD_PAIRS;
         const double inb = (j == 0) ? sizeof(Tio) + 1.0 : pair_bytes<T>(sp.size[j - 1]);
+        RhsBatch rb{nrhs, j == 0 ? real_rstride<Tio>(c) : pair_rstride<T>(c), pair_rstride<T>(c), 0};
         ProfScope ps(c, kind_of<T>(KD_P1_X + c.axes[j]), nn * (inb + pair_bytes<T>(sp.size[j])), st);
         launch_sep_pass<T, Tio>(c, c.axes[j], sp.p1[j], sp.d1[j], ldm, src, mask, SEP_ST_PAIRS, dst, nullptr,
-                                nullptr, nullptr, st);
+                                nullptr, nullptr, st, rb);
         src = dst;
         dst = (dst == S1) ? S2 : S1;
     }
     return (cplx<T>*)src;
 }
 
-// Part-2 passes on axes k-2..0 from P_{k-2} pairs in `cur` to the real field
+// Part-2 passes on axes k-2..0 from P_{k-2} pairs in `cur` to the real fields
 // `out` (masked).
 template <typename T, typename Tio>
 void part2(Ctx& c, const SepPlan& sp, cplx<T>* cur, cplx<T>* S1, cplx<T>* S2, Tio* out,
-           const uint8_t* mask, hipStream_t st)
+           const uint8_t* mask, int nrhs, hipStream_t st)
 {
-    const double nn = (double)c.nn;
+    const double nn = (double)c.nn * nrhs;
     for (int j = sp.k - 2; j >= 0; --j) {
         const double inb = pair_bytes<T>(sp.size[j]);
         if (j > 0) {
             cplx<T>* dst = (cur == S1) ? S2 : S1;
+            RhsBatch rb{nrhs, pair_rstride<T>(c), pair_rstride<T>(c), 0};
             ProfScope ps(c, kind_of<T>(KD_P2_X + c.axes[j]), nn * (inb + pair_bytes<T>(sp.size[j - 1])), st);
             launch_sep_pass<T, Tio>(c, c.axes[j], sp.p2[j], sp.d2[j], SEP_LD_PAIRS, cur, nullptr, SEP_ST_PAIRS,
-                                    dst, nullptr, nullptr, nullptr, st);
+                                    dst, nullptr, nullptr, nullptr, st, rb);
             cur = dst;
         } else {
+            RhsBatch rb{nrhs, pair_rstride<T>(c), real_rstride<Tio>(c), 0};
             ProfScope ps(c, kind_of<T>(KD_P2_X + c.axes[j]), nn * (inb + sizeof(Tio) + 1.0), st);
             launch_sep_pass<T, Tio>(c, c.axes[j], sp.p2[j], sp.d2[j], SEP_LD_PAIRS, cur, nullptr, SEP_ST_REAL,
-                                    out, mask, nullptr, nullptr, st);
+                                    out, mask, nullptr, nullptr, st, rb);
         }
     }
 }
 
-// One operator on one field, arithmetic precision T, field type Tio (Alg 2, 3, 4).
+// One operator on nrhs consecutive fields, arithmetic precision T, field type
+// Tio (Alg 2, 3, 4); every pass covers all fields in one launch.
 template <typename T, typename Tio = T>
-void apply_one(Ctx& c, int op, const Tio* in, Tio* out, hipStream_t st)
+void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st)
 {
+    ensure_work(c, nrhs);
     const SepPlan& sp = c.basis_plan;
     const int k = sp.k, last = c.axes[k - 1];
     cplx<T>* S1 = work_of<T>(c);
-    cplx<T>* S2 = S1 + (size_t)sp.maxpairs * c.nn;
-    const double nn = (double)c.nn, rt = sizeof(T);
+    cplx<T>* S2 = S1 + (size_t)sp.maxpairs * c.nn * c.cap_work;
+    const double nn = (double)c.nn * nrhs, rt = sizeof(T);
+    const long prs = pair_rstride<T>(c), rrs = real_rstride<Tio>(c);
     const double inb1 = (k == 1) ? sizeof(Tio) + 1.0 : pair_bytes<T>(k >= 2 ? sp.size[k - 2] : 1);
     const double outb2 = (k == 1) ? sizeof(Tio) + 1.0 : pair_bytes<T>(k >= 2 ? sp.size[k - 2] : 1);
     switch (op) {
         case FCRKPM_OP_K:
         case FCRKPM_OP_K_FULL: {
             const uint8_t* mk = (op == FCRKPM_OP_K) ? c.freem : c.chi;
-            cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, st);
+            cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, nrhs, st);
             cplx<T>* dst = (cur == S1) ? S2 : S1;
             {
                 ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2 + (c.dim * c.s + 1) * rt), st);
                 if (k == 1)
                     launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], SEP_PW_K, SEP_LD_REAL, in, mk,
                                            SEP_ST_REAL, out, mk, nullptr, b0_of<T>(c), ba_of<T>(c),
-                                           vol_of<T>(c), nullptr, nullptr, st);
+                                           vol_of<T>(c), nullptr, nullptr, st, RhsBatch{nrhs, rrs, rrs, 0});
                 else
                     launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_K, SEP_LD_PAIRS,
                                            cur, nullptr, SEP_ST_PAIRS, dst, nullptr, nullptr,
                                            b0_of<T>(c), ba_of<T>(c), vol_of<T>(c), nullptr, nullptr,
-                                           st);
+                                           st, RhsBatch{nrhs, prs, prs, 0});
             }
-            if (k > 1) part2<T, Tio>(c, sp, dst, S1, S2, out, mk, st);
+            if (k > 1) part2<T, Tio>(c, sp, dst, S1, S2, out, mk, nrhs, st);
             break;
         }
         case FCRKPM_OP_FR:
@@ -418,17 +447,19 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, hipStream_t st)
                                                SEP_LD_PAIRS, nullptr, nullptr,
                                                k == 1 ? SEP_ST_REAL : SEP_ST_PAIRS,
                                                k == 1 ? (void*)out : (void*)S1, c.chi, in,
-                                               b0_of<T>(c), ba_of<T>(c), vol, nullptr, nullptr, st);
+                                               b0_of<T>(c), ba_of<T>(c), vol, nullptr, nullptr, st,
+                                               RhsBatch{nrhs, 0, k == 1 ? rrs : prs, rrs});
                     }
-                    if (k > 1) part2<T, Tio>(c, sp, S1, S1, S2, out, c.chi, st);
+                    if (k > 1) part2<T, Tio>(c, sp, S1, S1, S2, out, c.chi, nrhs, st);
                 } else {
-                    cplx<T>* cur = part1<T, Tio>(c, sp, in, c.chi, S1, S2, st);
+                    cplx<T>* cur = part1<T, Tio>(c, sp, in, c.chi, S1, S2, nrhs, st);
                     ProfScope ps(c, kind_of<T>(KD_MID_UH), nn * (inb1 + (c.s + 1) * rt + sizeof(Tio)), st);
                     launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_UH,
                                            k == 1 ? SEP_LD_REAL : SEP_LD_PAIRS,
                                            k == 1 ? (const void*)in : (const void*)cur, c.chi,
                                            SEP_ST_REAL, out, nullptr, nullptr, b0_of<T>(c),
-                                           ba_of<T>(c), vol, nullptr, nullptr, st);
+                                           ba_of<T>(c), vol, nullptr, nullptr, st,
+                                           RhsBatch{nrhs, k == 1 ? rrs : prs, rrs, 0});
                 }
             }
             break;
@@ -438,154 +469,76 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, hipStream_t st)
 }
 
 // ---------------------------------------------------------------- solvers
+//
+// Every solver works on nrhs right-hand sides at once: vector v of rhs j
+// lives at v + j*nn inside blocks of cap_rhs fields, its device scalars at
+// scal + j*kScal, and each launch covers all of them (blockIdx.y).  A rhs
+// that has finished is frozen on the device (act[j] = 0) while the others
+// keep iterating.
 
 enum { V_B = 0, V_X = 1, V_R = 2, V_P = 3, V_Q = 4, V_T = 5 };
 enum { S_RR0 = 0, S_RR1 = 1, S_BREAK = 3, S_NORM = 4, S_BB = 5 };
 
-double read_scalar(Ctx& c, int idx, hipStream_t st)
+// Solver buffers for nrhs right-hand sides.  Never called during capture.
+void ensure_rhs(Ctx& c, int nrhs)
 {
-    HIPCHK(hipMemcpyAsync(c.hscal, c.scal + idx, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (nrhs <= c.cap_rhs) return;
+    if (c.capturing) fail(FCRKPM_ERR_ARG, "solver buffers cannot grow during graph capture");
+    HIPCHK(hipDeviceSynchronize());
+    dfree(c.v64);
+    dfree(c.v32);
+    dfree(c.partial);
+    dfree(c.scal);
+    dfree(c.act);
+    if (c.hscal) (void)hipHostFree(c.hscal);
+    c.hscal = nullptr;
+    c.cap_rhs = 0;
+    const size_t nn = (size_t)c.nn;
+    c.v64 = dalloc<double>(6 * nn * nrhs);
+    c.v32 = dalloc<float>(5 * nn * nrhs);
+    c.partial = dalloc<double>((size_t)2 * kRedBlocks * nrhs);
+    c.scal = dalloc<double>((size_t)kScal * nrhs);
+    c.act = dalloc<int>(nrhs);
+    HIPCHK(hipMemset(c.scal, 0, sizeof(double) * kScal * nrhs));
+    HIPCHK(hipMemset(c.act, 0, sizeof(int) * nrhs));
+    HIPCHK(hipHostMalloc((void**)&c.hscal, sizeof(double) * 3 * kScal * nrhs, hipHostMallocDefault));
+    c.cap_rhs = nrhs;
+}
+
+double* vec64(Ctx& c, int which) { return c.v64 + (size_t)which * c.nn * c.cap_rhs; }
+float* vec32(Ctx& c, int which) { return c.v32 + (size_t)which * c.nn * c.cap_rhs; }
+
+// scalars of all right-hand sides, read back synchronously
+const double* read_scalars(Ctx& c, int nrhs, hipStream_t st)
+{
+    double* h = c.hscal + (size_t)2 * kScal * c.cap_rhs;
+    HIPCHK(hipMemcpyAsync(h, c.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    return c.hscal[0];
+    return h;
 }
 
+// scal[j*kScal + idx] = a_j . b_j for every right-hand side
 template <typename T>
-double dot_to(Ctx& c, const T* a, const T* b, int idx, hipStream_t st)
+void dots(Ctx& c, const T* a, const T* b, int nrhs, int idx, hipStream_t st)
 {
-    launch_dot_partial<T>(a, b, c.nn, c.partial, st);
-    launch_reduce_to(c.partial, c.scal + idx, st);
-    return read_scalar(c, idx, st);
+    launch_dot_partial<T>(a, b, c.nn, nrhs, c.partial, nullptr, st);
+    launch_reduce_to(c.partial, c.nn, nrhs, c.scal + idx, st);
 }
 
-struct CgResult {
-    int iters = 0;
-    double relres = 0.0;
-    bool breakdown = false;
-    bool converged = false;
-};
-
-// Look-ahead convergence polling: after each batch of CG iterations the
-// device scalars are copied to a pinned slot and an event is recorded; the
-// host only waits for the PREVIOUS batch, so the queue never drains while
-// the host decides.
-struct Poller {
-    Ctx& c;
-    hipStream_t st;
-    int slot = 0;      // slot the next post goes to
-    int nposted = 0;   // posts since the last full drain
-    int parity_of[2] = {0, 0};
-    Poller(Ctx& c_, hipStream_t st_) : c(c_), st(st_) {}
-    void post(int parity)
-    {
-        HIPCHK(hipMemcpyAsync(c.hscal + 8 * slot, c.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(c.poll_ev[slot], st));
-        parity_of[slot] = parity;
-        ++nposted;
-        slot ^= 1;
-    }
-    void read(int s, double& rr, bool& brk)
-    {
-        HIPCHK(hipEventSynchronize(c.poll_ev[s]));
-        rr = c.hscal[8 * s + parity_of[s]];
-        brk = c.hscal[8 * s + S_BREAK] != 0.0;
-    }
-    // scalars of the second-to-last post (the last one may still run); false if none
-    bool wait_prev(double& rr, bool& brk)
-    {
-        if (nposted < 2) return false;
-        read(slot, rr, brk);
-        return true;
-    }
-    // scalars of the last post; afterwards nothing is pending
-    void wait_last(double& rr, bool& brk)
-    {
-        read(slot ^ 1, rr, brk);
-        nposted = 0;
-    }
-};
-
-// one CG iteration on vectors of type T with K products in precision TP
+// one CG iteration for all active right-hand sides: vectors of type T, K
+// products in precision TP
 template <typename T, typename TP = T>
-void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int& parity, int& matvecs, hipStream_t st)
+void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStream_t st)
 {
     double* pq_part = c.partial;
-    double* rr_part = c.partial + kRedBlocks;
-    apply_one<TP, T>(c, FCRKPM_OP_K, p, q, st);
-    ++matvecs;
-    launch_dot_partial<T>(p, q, c.nn, pq_part, st);
-    launch_cg_xr<T>(x, r, p, q, c.nn, pq_part, c.scal, parity, rr_part, st);
-    launch_cg_p<T>(p, r, c.nn, rr_part, c.scal, parity, st);
-    parity ^= 1;
+    double* rr_part = c.partial + (size_t)kRedBlocks * c.cap_rhs;
+    apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
+    launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
+    launch_cg_xr<T>(x, r, p, q, c.nn, nrhs, pq_part, c.scal, parity, rr_part, c.act, st);
+    launch_cg_p<T>(p, r, c.nn, nrhs, rr_part, c.scal, parity, c.act, st);
 }
 
-constexpr int kCheck = 8;  // CG iterations per convergence poll
-
-// CG on chi_Omega K chi_Omega from x with residual r (both in/out), for
-// ||r|| / sqrt(bb) <= tol.  p, q: scratch.
-template <typename T>
-CgResult cg_run(Ctx& c, T* x, T* r, T* p, T* q, double bb, double tol, int maxit, int& matvecs,
-                hipStream_t st)
-{
-    CgResult res;
-    const double bn = sqrt(bb > 0.0 ? bb : 1.0);
-    HIPCHK(hipMemcpyAsync(p, r, sizeof(T) * c.nn, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(c.scal + S_BREAK, 0, sizeof(double), st));
-    launch_dot_partial<T>(r, r, c.nn, c.partial, st);
-    launch_reduce_to(c.partial, c.scal + S_RR0, st);
-    double rr = read_scalar(c, S_RR0, st);
-    res.relres = sqrt(rr) / bn;
-    if (res.relres <= tol) {
-        res.converged = true;
-        return res;
-    }
-    int parity = 0, it = 0;
-    Poller pl(c, st);
-    bool brk = false, hit = false;
-    while (true) {
-        const int nb = std::min(kCheck, maxit - it);
-        for (int i = 0; i < nb; ++i) cg_iteration<T>(c, x, r, p, q, parity, matvecs, st);
-        it += nb;
-        pl.post(parity);
-        bool done = false;
-        if (it >= maxit) {
-            pl.wait_last(rr, brk);
-            done = true;
-        } else if (pl.wait_prev(rr, brk)) {
-            hit = std::isfinite(rr) && sqrt(rr) / bn <= tol;
-            done = brk || hit || !std::isfinite(rr);
-            if (done) {  // the batch in flight has run too
-                double rr2;
-                bool brk2;
-                pl.wait_last(rr2, brk2);
-                brk = brk || brk2;
-                if (std::isfinite(rr2)) rr = hit ? std::min(rr, rr2) : rr2;
-            }
-        }
-        if (done) break;
-    }
-    // the residual norm of CG is not monotone: convergence is the first poll at tol
-    res.iters = it;
-    res.relres = sqrt(rr) / bn;
-    res.breakdown = brk || !std::isfinite(rr);
-    res.converged = !res.breakdown && (hit || res.relres <= tol);
-    return res;
-}
-
-template <typename TV>
-void to_vec(const double* r, TV* out, long n, hipStream_t st)
-{
-    if constexpr (std::is_same_v<TV, float>) launch_to32(r, out, n, st);
-    else HIPCHK(hipMemcpyAsync(out, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-}
-
-template <typename TV>
-void fold_into(double* x, TV* xc, long n, hipStream_t st)
-{
-    if constexpr (std::is_same_v<TV, float>) launch_add32to64_reset(x, xc, n, st);
-    else {
-        launch_add_reset64(x, xc, n, st);
-    }
-}
+constexpr int kCheck = 8;  // CG iterations per convergence poll (even: parity returns)
 
 bool log_enabled()
 {
@@ -597,154 +550,536 @@ bool log_enabled()
     return on == 1;
 }
 
-// CG with K products in FP32 and CG vectors of type TV; the solution x and
-// the true residual are FP64.  The correction accumulates in xc (TV) and is
-// folded into x, with the residual replaced by b - K x (FP64 products),
-// whenever the recursive residual has fallen 10x since the last replacement.
-// On entry v64[V_R] holds the true residual of x and inf.rel_res its norm.
-template <typename TV>
-fcrkpm_status reliable_cg(Ctx& c, TV* xc, TV* r, TV* p, TV* q, double bn, double tol, int maxit,
-                          fcrkpm_info& inf, int& total, bool& need_f64,
-                          const std::function<double()>& true_residual, hipStream_t st)
-{
-    const long nn = c.nn;
-    double* x = c.v64 + 1 * nn;  // V_X
-    double* r64 = c.v64 + 2 * nn;  // V_R
+struct RhsState {
+    double bn = 1.0;       // ||b_j||
+    double rel = 0.0;      // relative residual reported (true one in refinement)
+    double best = 0.0;     // best true residual seen by refinement
+    double rr_upd = 0.0;   // recursive r.r right after the last replacement
+    double rr_poll = 0.0;  // r.r of the last look-ahead poll
+    double rr_last = 0.0;  // recursive r.r when the last block ended
+    int iters = 0, outer = 0, stall = 0, it_upd = 0, longest = 0;
+    int mv32 = 0, mv64 = 0;
+    bool active = false;   // iterating in the current phase
+    bool want = false;     // asked for service at the last poll
+    bool hit = false;      // FP64 phase: recursive residual at tol at the last poll
+    bool brk = false;
+    bool conv = false;
+    bool need64 = false;   // refinement handed it to FP64 CG
+    bool fallback = false;
+    bool zero = false;     // b = 0
+};
+
+enum Phase { PH_REFINED, PH_F64, PH_DONE };
+
+// Strong-Dirichlet CG on chi_Omega K chi_Omega x = b for nrhs right-hand
+// sides (Alg 5), b in vec64(V_B), the initial x in vec64(V_X).
+//
+// FCRKPM_MODE_F32_REFINED: CG whose products and recurrences run in FP32
+// while the solution and the true residual are kept in FP64: the FP32
+// correction is folded into x (FP64) and the residual replaced by b - K x
+// computed with FP64 products whenever the recursive residual has fallen 10x
+// since the last replacement ("reliable updates"), keeping the Krylov
+// direction.  This is iterative refinement whose inner solver keeps its
+// search space across outer steps.  A right-hand side whose true residual
+// stagnates finishes with FP64 CG.
+// FCRKPM_MODE_F32_PRODUCTS: the same with FP64 vectors and FP32 products.
+// FCRKPM_MODE_F64: plain FP64 CG.
+//
+// The driver (run_solvers) enqueues blocks of kCheck iterations, posts the
+// scalars after each block and calls wants()/service() from the host.
+struct Solver {
+    Ctx& c;
+    int nrhs, mode, maxit;
+    double tol;
+    Phase ph = PH_DONE;
+    int it = 0;           // iterations in the current phase
+    int it_base = 0;      // iterations spent before the current phase
+    int parity = 0;       // slot of r.r the next iteration reads
+    int parity_of[2] = {0, 0};
+    std::vector<RhsState> R;
+    hipEvent_t join = nullptr;
     const double drop2 = 1e-2;  // replace the residual when it fell 10x
-    fcrkpm_status status = FCRKPM_OK;
-    double rel = inf.rel_res;
-    if (rel <= tol) return status;
-    HIPCHK(hipMemsetAsync(xc, 0, sizeof(TV) * nn, st));
-    HIPCHK(hipMemsetAsync(c.scal + S_BREAK, 0, sizeof(double), st));
-    if ((void*)r != (void*)r64) to_vec<TV>(r64, r, nn, st);
-    HIPCHK(hipMemcpyAsync(p, r, sizeof(TV) * nn, hipMemcpyDeviceToDevice, st));
-    launch_dot_partial<TV>(r, r, nn, c.partial, st);
-    launch_reduce_to(c.partial, c.scal + S_RR0, st);
-    double rr_upd = read_scalar(c, S_RR0, st);
-    int parity = 0, it = 0, stall = 0, it_upd = 0, longest = 0;
-    double best = rel;
-    Poller pl(c, st);
-    while (true) {
-        const int nb = std::min(kCheck, maxit - it);
-        for (int i = 0; i < nb; ++i) cg_iteration<TV, float>(c, xc, r, p, q, parity, inf.matvecs_f32, st);
+
+    Solver(Ctx& c_, int nrhs_, int mode_, double tol_, int maxit_)
+        : c(c_), nrhs(nrhs_), mode(mode_), maxit(maxit_), tol(tol_), R(nrhs_)
+    {
+        HIPCHK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    }
+    ~Solver()
+    {
+        if (join) (void)hipEventDestroy(join);
+    }
+
+    int phase_maxit() const { return std::max(1, maxit - it_base); }
+    bool any_active() const
+    {
+        for (const auto& s : R)
+            if (s.active) return true;
+        return false;
+    }
+
+    // b - K x into vec64(V_R) for all rhs; returns after reading the norms
+    void true_residual(hipStream_t st)
+    {
+        double* b = vec64(c, V_B);
+        double* x = vec64(c, V_X);
+        double* r = vec64(c, V_R);
+        double* q = vec64(c, V_Q);
+        apply_one<double>(c, FCRKPM_OP_K, x, q, nrhs, st);
+        launch_sub_masked(b, q, c.freem, r, c.nn, nrhs, st);
+        dots<double>(c, r, r, nrhs, S_NORM, st);
+        const double* h = read_scalars(c, nrhs, st);
+        for (int j = 0; j < nrhs; ++j) {
+            ++R[j].mv64;
+            R[j].rel = R[j].zero ? 0.0 : sqrt(h[j * kScal + S_NORM]) / R[j].bn;
+        }
+    }
+
+    void set_flags(hipStream_t st)
+    {
+        for (int j = 0; j < nrhs; ++j) launch_set_flag(c.act, j, R[j].active ? 1 : 0, st);
+    }
+
+    void begin(hipStream_t st)
+    {
+        const long nn = c.nn;
+        dots<double>(c, vec64(c, V_B), vec64(c, V_B), nrhs, S_BB, st);
+        const double* h = read_scalars(c, nrhs, st);
+        for (int j = 0; j < nrhs; ++j) {
+            const double bb = h[j * kScal + S_BB];
+            R[j].zero = !(bb > 0.0);
+            R[j].bn = R[j].zero ? 1.0 : sqrt(bb);
+            if (R[j].zero) {
+                HIPCHK(hipMemsetAsync(vec64(c, V_X) + j * nn, 0, sizeof(double) * nn, st));
+                R[j].conv = true;
+            }
+        }
+        true_residual(st);
+        if (mode == FCRKPM_MODE_F64) {
+            for (auto& s : R) s.need64 = !s.zero;
+            start_f64(st);
+            return;
+        }
+        bool any = false;
+        for (auto& s : R) {
+            s.best = s.rel;
+            s.active = !s.zero && s.rel > tol;
+            if (!s.zero && !s.active) s.conv = true;
+            any = any || s.active;
+        }
+        if (!any) {
+            ph = PH_DONE;
+            return;
+        }
+        ph = PH_REFINED;
+        it = 0;
+        parity = 0;
+        launch_set_scalar(c.scal, S_BREAK, 0.0, nrhs, st);
+        if (mode == FCRKPM_MODE_F32_REFINED) {
+            HIPCHK(hipMemsetAsync(vec32(c, 0), 0, sizeof(float) * nn * nrhs, st));
+            launch_to32(vec64(c, V_R), vec32(c, 1), nn * nrhs, st);
+            HIPCHK(hipMemcpyAsync(vec32(c, 2), vec32(c, 1), sizeof(float) * nn * nrhs,
+                                  hipMemcpyDeviceToDevice, st));
+            dots<float>(c, vec32(c, 1), vec32(c, 1), nrhs, S_RR0, st);
+        } else {
+            HIPCHK(hipMemsetAsync(vec64(c, V_T), 0, sizeof(double) * nn * nrhs, st));
+            HIPCHK(hipMemcpyAsync(vec64(c, V_P), vec64(c, V_R), sizeof(double) * nn * nrhs,
+                                  hipMemcpyDeviceToDevice, st));
+            dots<double>(c, vec64(c, V_R), vec64(c, V_R), nrhs, S_RR0, st);
+        }
+        h = read_scalars(c, nrhs, st);
+        for (int j = 0; j < nrhs; ++j) R[j].rr_upd = h[j * kScal + S_RR0];
+        set_flags(st);
+    }
+
+    // FP64 CG from the current x with r = b - K x already in vec64(V_R), for
+    // the rhs marked need64
+    void start_f64(hipStream_t st)
+    {
+        const long nn = c.nn;
+        it_base += it;
+        it = 0;
+        parity = 0;
+        ph = PH_F64;
+        HIPCHK(hipMemcpyAsync(vec64(c, V_P), vec64(c, V_R), sizeof(double) * nn * nrhs,
+                              hipMemcpyDeviceToDevice, st));
+        launch_set_scalar(c.scal, S_BREAK, 0.0, nrhs, st);
+        dots<double>(c, vec64(c, V_R), vec64(c, V_R), nrhs, S_RR0, st);
+        const double* h = read_scalars(c, nrhs, st);
+        bool any = false;
+        for (int j = 0; j < nrhs; ++j) {
+            RhsState& s = R[j];
+            s.active = false;
+            if (!s.need64) continue;
+            s.rel = sqrt(h[j * kScal + S_RR0]) / s.bn;
+            if (s.rel <= tol) {
+                s.conv = true;
+                continue;
+            }
+            s.active = true;
+            any = true;
+        }
+        if (!any) {
+            ph = PH_DONE;
+            return;
+        }
+        set_flags(st);
+    }
+
+    // kCheck (or fewer) iterations of the current phase: kernel launches only,
+    // so the block can be captured into a graph and replayed
+    void enqueue(int nb, hipStream_t st)
+    {
+        int par = parity;
+        for (int i = 0; i < nb; ++i, par ^= 1) {
+            if (ph == PH_F64)
+                cg_iteration<double>(c, vec64(c, V_X), vec64(c, V_R), vec64(c, V_P), vec64(c, V_Q),
+                                     nrhs, par, st);
+            else if (mode == FCRKPM_MODE_F32_REFINED)
+                cg_iteration<float, float>(c, vec32(c, 0), vec32(c, 1), vec32(c, 2), vec32(c, 3),
+                                           nrhs, par, st);
+            else
+                cg_iteration<double, float>(c, vec64(c, V_T), vec64(c, V_R), vec64(c, V_P),
+                                            vec64(c, V_Q), nrhs, par, st);
+        }
+    }
+
+    // bookkeeping of an enqueued block
+    void advance(int nb)
+    {
         it += nb;
-        pl.post(parity);
-        double rr = 0.0;
-        bool brk = false;
-        const bool have = pl.wait_prev(rr, brk);
-        if (have && !std::isfinite(rr)) brk = true;
-        const bool last = it >= maxit;
-        // an interval far longer than every earlier one means the recursion
-        // wanders at the accuracy floor of the FP32 products: replace anyway
-        const bool overdue = it - it_upd > 3 * longest + 256;
-        if (!last && !overdue &&
-            !(have && (brk || rr <= drop2 * rr_upd || sqrt(rr) / bn <= tol)))
-            continue;
-        longest = std::max(longest, it - it_upd);
-        it_upd = it;
-        bool brk2 = false;
-        pl.wait_last(rr, brk2);
-        brk = brk || brk2 || !std::isfinite(rr);
-        fold_into<TV>(x, xc, nn, st);
-        rel = true_residual();
-        inf.rel_res = rel;
-        ++inf.outer_iters;
-        if (log_enabled())
-            fprintf(stderr, "[fcrkpm] replace %d at it %d: recursive %.3e true %.3e\n",
-                    inf.outer_iters, it, sqrt(rr) / bn, rel);
-        if (rel <= tol) break;
-        if (last) {
-            status = FCRKPM_ERR_NOCONV;
-            break;
+        parity ^= (nb & 1);
+        for (auto& s : R)
+            if (s.active) {
+                s.iters += nb;
+                if (ph == PH_F64) s.mv64 += nb;
+                else s.mv32 += nb;
+            }
+    }
+
+    void post(int slot, hipStream_t st)
+    {
+        HIPCHK(hipMemcpyAsync(c.hscal + (size_t)slot * kScal * c.cap_rhs, c.scal,
+                              sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
+        parity_of[slot] = parity;
+    }
+
+    // from the scalars of a completed post: does any rhs need the host?
+    bool wants(int slot)
+    {
+        const double* h = c.hscal + (size_t)slot * kScal * c.cap_rhs;
+        const int pp = parity_of[slot];
+        bool any = it >= phase_maxit();
+        for (int j = 0; j < nrhs; ++j) {
+            RhsState& s = R[j];
+            s.want = false;
+            if (!s.active) continue;
+            const double rr = h[j * kScal + pp];
+            const bool brk = h[j * kScal + S_BREAK] != 0.0 || !std::isfinite(rr);
+            s.rr_poll = rr;
+            if (ph == PH_REFINED) {
+                const bool overdue = it - s.it_upd > 3 * s.longest + 256;
+                s.want = brk || rr <= drop2 * s.rr_upd || sqrt(rr) / s.bn <= tol || overdue;
+                s.brk = brk;
+            } else {
+                s.hit = std::isfinite(rr) && sqrt(rr) / s.bn <= tol;
+                s.brk = brk;
+                s.want = brk || s.hit;
+            }
+            any = any || s.want;
         }
-        if (brk) {
-            need_f64 = true;
-            inf.fallback_used = 1;
-            break;
-        }
-        if (rel > 0.5 * best) {
-            if (++stall >= 3) {
-                // the true residual stopped improving: within 4 tol this is the
-                // attainable accuracy (rel_res reports it); otherwise finish
-                // with FP64 CG
-                if (best <= 4.0 * tol) break;
-                need_f64 = true;
-                inf.fallback_used = 1;
-                break;
+        return any;
+    }
+
+    // host work after every posted block has completed; `slot` holds the
+    // scalars of the last one
+    void service(int slot, hipStream_t st)
+    {
+        const double* h = c.hscal + (size_t)slot * kScal * c.cap_rhs;
+        const int pp = parity_of[slot];
+        const bool last = it >= phase_maxit();
+        bool any_want = false;
+        for (const auto& s : R) any_want = any_want || (s.active && s.want);
+        if (!any_want && !last) return;
+        const long nn = c.nn;
+        if (ph == PH_REFINED) {
+            for (int j = 0; j < nrhs; ++j) {
+                RhsState& s = R[j];
+                if (!s.active) continue;
+                const double rr2 = h[j * kScal + pp];
+                s.rr_last = rr2;
+                s.brk = s.brk || h[j * kScal + S_BREAK] != 0.0 || !std::isfinite(rr2);
+            }
+            if (mode == FCRKPM_MODE_F32_REFINED)
+                launch_add32to64_reset(vec64(c, V_X), vec32(c, 0), nn * nrhs, st);
+            else
+                launch_add_reset64(vec64(c, V_X), vec64(c, V_T), nn * nrhs, st);
+            std::vector<double> before(nrhs);
+            for (int j = 0; j < nrhs; ++j) before[j] = R[j].rel;
+            true_residual(st);
+            bool any = false, need64 = false;
+            std::vector<int> restart;
+            for (int j = 0; j < nrhs; ++j) {
+                RhsState& s = R[j];
+                if (!s.active) {
+                    s.rel = before[j];  // frozen: keep what it finished with
+                    continue;
+                }
+                // the FP32 recursion has left the true residual far behind (its
+                // search direction no longer fits): restart it from the new
+                // residual instead of keeping the direction
+                const double true_rr = (s.rel * s.bn) * (s.rel * s.bn);
+                const bool drifted = true_rr > 100.0 * s.rr_last;
+                ++s.outer;
+                if (s.want || last) s.longest = std::max(s.longest, it - s.it_upd);
+                s.it_upd = it;
+                if (log_enabled())
+                    fprintf(stderr, "[fcrkpm] rhs %d replace %d at it %d: true %.3e\n", j, s.outer,
+                            it, s.rel);
+                if (s.rel <= tol) {
+                    s.conv = true;
+                    s.active = false;
+                } else if (last) {
+                    s.active = false;
+                } else if (s.brk || s.rel > 10.0 * s.best) {
+                    // breakdown, or the FP32 iteration diverged: finish in FP64
+                    s.need64 = s.fallback = true;
+                    s.active = false;
+                } else if (s.want && s.rel > 0.5 * s.best) {
+                    if (++s.stall >= 3) {
+                        // the true residual stopped improving: within 4 tol this is
+                        // the attainable accuracy; otherwise finish with FP64 CG
+                        if (s.best <= 4.0 * tol) s.conv = true;
+                        else s.need64 = s.fallback = true;
+                        s.active = false;
+                    }
+                } else if (s.want) {
+                    s.stall = 0;
+                }
+                s.best = std::min(s.best, s.rel);
+                s.want = false;
+                if (s.active && drifted) restart.push_back(j);
+                any = any || s.active;
+                need64 = need64 || s.need64;
+            }
+            if (any) {
+                if (mode == FCRKPM_MODE_F32_REFINED) {
+                    launch_to32(vec64(c, V_R), vec32(c, 1), nn * nrhs, st);
+                    for (int j : restart)
+                        HIPCHK(hipMemcpyAsync(vec32(c, 2) + j * nn, vec32(c, 1) + j * nn,
+                                              sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+                    dots<float>(c, vec32(c, 1), vec32(c, 1), nrhs, parity, st);
+                } else {
+                    for (int j : restart)
+                        HIPCHK(hipMemcpyAsync(vec64(c, V_P) + j * nn, vec64(c, V_R) + j * nn,
+                                              sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+                    dots<double>(c, vec64(c, V_R), vec64(c, V_R), nrhs, parity, st);
+                }
+                if (log_enabled())
+                    for (int j : restart) fprintf(stderr, "[fcrkpm] rhs %d restarts at it %d\n", j, it);
+                const double* hr = read_scalars(c, nrhs, st);
+                for (int j = 0; j < nrhs; ++j)
+                    if (R[j].active) R[j].rr_upd = hr[j * kScal + parity];
+                set_flags(st);
+            } else if (need64 && !last) {
+                start_f64(st);
+            } else {
+                ph = PH_DONE;
             }
         } else {
-            stall = 0;
+            bool any = false;
+            for (int j = 0; j < nrhs; ++j) {
+                RhsState& s = R[j];
+                if (!s.active) continue;
+                if (s.want || last) {
+                    const double rr2 = h[j * kScal + pp];
+                    const bool brk2 = h[j * kScal + S_BREAK] != 0.0;
+                    s.brk = s.brk || brk2 || (!s.hit && !std::isfinite(rr2));
+                    double rr = s.want ? s.rr_poll : rr2;
+                    if (std::isfinite(rr2)) rr = s.hit ? std::min(s.rr_poll, rr2) : rr2;
+                    // the residual norm of CG is not monotone: convergence is the
+                    // first poll at tol
+                    s.rel = sqrt(rr) / s.bn;
+                    s.conv = !s.brk && (s.hit || s.rel <= tol);
+                    s.active = false;
+                }
+                s.want = false;
+                any = any || s.active;
+            }
+            if (any) set_flags(st);
+            else ph = PH_DONE;
         }
-        best = std::min(best, rel);
-        if ((void*)r != (void*)r64) to_vec<TV>(r64, r, nn, st);
-        launch_dot_partial<TV>(r, r, nn, c.partial, st);
-        launch_reduce_to(c.partial, c.scal + parity, st);
-        rr_upd = read_scalar(c, parity, st);
     }
-    total += it;
-    return status;
+
+    // final true residuals and info; status of the worst rhs
+    fcrkpm_status finish(fcrkpm_info* info, hipStream_t st)
+    {
+        std::vector<double> rel(nrhs);
+        for (int j = 0; j < nrhs; ++j) rel[j] = R[j].rel;
+        true_residual(st);
+        fcrkpm_status status = FCRKPM_OK;
+        for (int j = 0; j < nrhs; ++j) {
+            const RhsState& s = R[j];
+            if (!s.conv) status = FCRKPM_ERR_NOCONV;
+            if (info) {
+                fcrkpm_info& f = info[j];
+                memset(&f, 0, sizeof(f));
+                f.iters = s.iters;
+                f.outer_iters = s.outer;
+                f.rel_res = rel[j];
+                f.true_rel_res = s.rel;
+                f.fallback_used = s.fallback ? 1 : 0;
+                f.matvecs_f64 = s.mv64;
+                f.matvecs_f32 = s.mv32;
+            }
+        }
+        return status;
+    }
+};
+
+bool graphs_enabled(const Ctx& c)
+{
+    if (c.prof_on || !c.use_graphs) return false;
+    static int env = -1;
+    if (env < 0) {
+        const char* e = getenv("FCRKPM_GRAPHS");
+        env = (e && *e == '0') ? 0 : 1;
+    }
+    return env == 1;
 }
 
-// Solve chi_Omega K chi_Omega x = b with b in v64[V_B] and the initial x in
-// v64[V_X] (zero off the free nodes).  Returns status; fills info.
-//
-// FCRKPM_MODE_F32_REFINED: CG whose products and recurrences run in FP32 while
-// the solution and the true residual are kept in FP64: the FP32 correction is
-// folded into x (FP64) and the residual replaced by b - K x computed with FP64
-// products whenever the recursive residual has fallen 10x since the last
-// replacement ("reliable updates"), keeping the Krylov direction.  This is
-// iterative refinement whose inner solver keeps its search space across outer
-// steps.  Stagnation of the true residual falls back to FP64 CG.
-fcrkpm_status solve_core(Ctx& c, int mode, double tol, int maxit, fcrkpm_info* info,
-                         hipStream_t st)
+// Enqueue one block for every solver in `act`: a single one on `st`, several
+// on their own streams forked from and joined back into `st`.
+void enqueue_all(const std::vector<Solver*>& act, int nb, hipEvent_t fork, hipStream_t st)
 {
-    const long nn = c.nn;
-    double* b = c.v64 + V_B * nn;
-    double* x = c.v64 + V_X * nn;
-    double* r = c.v64 + V_R * nn;
-    double* p = c.v64 + V_P * nn;
-    double* q = c.v64 + V_Q * nn;
-    fcrkpm_info inf;
-    memset(&inf, 0, sizeof(inf));
-    const double bb = dot_to<double>(c, b, b, S_BB, st);
-    fcrkpm_status status = FCRKPM_OK;
-    if (bb == 0.0) {
-        HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * nn, st));
-        if (info) *info = inf;
-        return FCRKPM_OK;
+    if (act.size() == 1) {
+        act[0]->enqueue(nb, st);
+        return;
     }
-    const double bn = sqrt(bb);
-    int total = 0;
-    bool need_f64 = (mode == FCRKPM_MODE_F64);
-    std::function<double()> true_residual = [&]() {
-        apply_one<double>(c, FCRKPM_OP_K, x, q, st);
-        ++inf.matvecs_f64;
-        launch_sub_masked(b, q, c.freem, r, nn, st);
-        return sqrt(dot_to<double>(c, r, r, S_NORM, st)) / bn;
+    HIPCHK(hipEventRecord(fork, st));
+    for (Solver* s : act) {
+        if (!s->c.aux) HIPCHK(hipStreamCreateWithFlags(&s->c.aux, hipStreamNonBlocking));
+        HIPCHK(hipStreamWaitEvent(s->c.aux, fork, 0));
+        s->enqueue(nb, s->c.aux);
+        HIPCHK(hipEventRecord(s->join, s->c.aux));
+    }
+    for (Solver* s : act) HIPCHK(hipStreamWaitEvent(st, s->join, 0));
+}
+
+// Drive solvers to completion.  Blocks of kCheck iterations of every
+// unfinished solver are enqueued together -- replayed from one captured HIP
+// graph while the set of solvers and their phases stay the same -- and after
+// each block the device scalars are copied to a pinned slot and an event is
+// recorded.  The host only waits for the block before the one in flight
+// (look-ahead), so the queue does not drain while it decides.
+void run_solvers_on(const std::vector<Solver*>& all, bool graphs, hipStream_t st);
+
+void run_solvers(const std::vector<Solver*>& all, bool graphs, hipStream_t st)
+{
+    if (!graphs || st != nullptr) {
+        run_solvers_on(all, graphs, st);
+        return;
+    }
+    // the legacy null stream cannot be captured: run on a private stream
+    // ordered after everything enqueued so far
+    HIPCHK(hipStreamSynchronize(st));
+    hipStream_t own = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    try {
+        run_solvers_on(all, graphs, own);
+    } catch (...) {
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+        throw;
+    }
+    HIPCHK(hipStreamSynchronize(own));
+    HIPCHK(hipStreamDestroy(own));
+}
+
+void run_solvers_on(const std::vector<Solver*>& all, bool graphs, hipStream_t st)
+{
+    for (Solver* s : all) s->begin(st);
+    hipEvent_t ev[2] = {nullptr, nullptr}, fork = nullptr;
+    hipGraphExec_t ge = nullptr;
+    std::vector<std::pair<Solver*, int>> gkey;
+    auto cleanup = [&]() {
+        for (Solver* s : all) s->c.capturing = false;
+        if (ge) (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        ev[0] = ev[1] = fork = nullptr;
     };
-    if (mode != FCRKPM_MODE_F64) inf.rel_res = true_residual();
-    if (mode == FCRKPM_MODE_F32_REFINED) {
-        status = reliable_cg<float>(c, c.v32 + 0 * nn, c.v32 + 1 * nn, c.v32 + 2 * nn,
-                                    c.v32 + 3 * nn, bn, tol, maxit, inf, total, need_f64,
-                                    true_residual, st);
-    } else if (mode == FCRKPM_MODE_F32_PRODUCTS) {
-        status = reliable_cg<double>(c, c.v64 + V_T * nn, r, p, q, bn, tol, maxit, inf, total,
-                                     need_f64, true_residual, st);
+    try {
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        int slot = 0, nposted = 0;
+        while (true) {
+            std::vector<Solver*> act;
+            for (Solver* s : all)
+                if (s->ph != PH_DONE) act.push_back(s);
+            if (act.empty()) break;
+            int nb = kCheck;
+            for (Solver* s : act) nb = std::min(nb, s->phase_maxit() - s->it);
+            nb = std::max(nb, 1);
+            if (graphs && nb == kCheck) {
+                std::vector<std::pair<Solver*, int>> key;
+                for (Solver* s : act) key.emplace_back(s, (int)s->ph * 2 + s->parity);
+                if (key != gkey || !ge) {
+                    if (ge) {
+                        HIPCHK(hipStreamSynchronize(st));
+                        HIPCHK(hipGraphExecDestroy(ge));
+                    }
+                    ge = nullptr;
+                    hipGraph_t g = nullptr;
+                    for (Solver* s : act) s->c.capturing = true;
+                    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    try {
+                        enqueue_all(act, nb, fork, st);
+                    } catch (...) {
+                        (void)hipStreamEndCapture(st, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    HIPCHK(hipStreamEndCapture(st, &g));
+                    for (Solver* s : act) s->c.capturing = false;
+                    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    HIPCHK(e);
+                    gkey = key;
+                }
+                HIPCHK(hipGraphLaunch(ge, st));
+            } else {
+                enqueue_all(act, nb, fork, st);
+            }
+            for (Solver* s : act) {
+                s->advance(nb);
+                s->post(slot, st);
+            }
+            HIPCHK(hipEventRecord(ev[slot], st));
+            slot ^= 1;
+            ++nposted;
+            bool need = false;
+            if (nposted >= 2) {
+                HIPCHK(hipEventSynchronize(ev[slot]));  // the block before the one in flight
+                for (Solver* s : act) need = s->wants(slot) || need;
+            } else {
+                for (Solver* s : act) need = need || s->it >= s->phase_maxit();
+            }
+            if (need) {
+                HIPCHK(hipEventSynchronize(ev[slot ^ 1]));
+                for (Solver* s : act) s->service(slot ^ 1, st);
+                nposted = 0;
+            }
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        cleanup();
+        throw;
     }
-    if (need_f64) {
-        apply_one<double>(c, FCRKPM_OP_K, x, q, st);
-        ++inf.matvecs_f64;
-        launch_sub_masked(b, q, c.freem, r, nn, st);
-        CgResult cr = cg_run<double>(c, x, r, p, q, bb, tol, std::max(1, maxit - total),
-                                     inf.matvecs_f64, st);
-        total += cr.iters;
-        inf.rel_res = cr.relres;
-        if (cr.breakdown || !cr.converged) status = FCRKPM_ERR_NOCONV;
-    }
-    inf.iters = total;
-    inf.true_rel_res = true_residual();
-    if (info) *info = inf;
-    return status;
+    cleanup();
 }
 
 }  // namespace
@@ -979,18 +1314,10 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 fail(FCRKPM_ERR_SINGULAR, "moment matrix not positive definite at node " + std::to_string(hflag[1]));
         }
 
-        // workspace: two slots of intermediate pair fields per precision
-        c.work64 = dalloc<cplx<double>>((size_t)2 * c.basis_plan.maxpairs * nn);
-        c.work32 = dalloc<cplx<float>>((size_t)2 * c.basis_plan.maxpairs * nn);
-        c.v64 = dalloc<double>((size_t)6 * nn);
-        c.v32 = dalloc<float>((size_t)5 * nn);
-        c.partial = dalloc<double>(2 * kRedBlocks);
-        c.scal = dalloc<double>(16);
-        HIPCHK(hipMemsetAsync(c.scal, 0, 16 * sizeof(double), st));
-        HIPCHK(hipHostMalloc((void**)&c.hscal, 16 * sizeof(double), hipHostMallocDefault));
-        HIPCHK(hipEventCreateWithFlags(&c.poll_ev[0], hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&c.poll_ev[1], hipEventDisableTiming));
+        // workspace and solver buffers for one right-hand side; both grow on demand
         HIPCHK(hipStreamSynchronize(st));
+        ensure_work(c, 1);
+        ensure_rhs(c, 1);
         HIPCHK(hipGetLastError());
         *out = h;
         h = nullptr;
@@ -1003,6 +1330,63 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
     return s;
 }
 
+namespace {
+// b = chi_Omega (f^r - K d_Gamma) and x = chi_Omega d0 for nrhs fields (Eq 29, Alg 5)
+void prepare_solve(Ctx& c, int nrhs, const double* r, const double* g, const double* d0,
+                   hipStream_t st)
+{
+    ensure_rhs(c, nrhs);
+    ensure_work(c, nrhs);
+    const long nn = c.nn;
+    HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+    launch_check_finite(r, nn * nrhs, c.dflag + 2, st);
+    if (g) launch_check_finite(g, nn * nrhs, c.dflag + 2, st);
+    if (d0) launch_check_finite(d0, nn * nrhs, c.dflag + 2, st);
+    int hf = 0;
+    HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, g or the initial guess");
+    double* b = vec64(c, V_B);
+    double* x = vec64(c, V_X);
+    double* t = vec64(c, V_T);
+    double* p = vec64(c, V_P);
+    double* q = vec64(c, V_Q);
+    apply_one<double>(c, FCRKPM_OP_FR, r, t, nrhs, st);  // f^r (Alg 4)
+    if (g) {
+        launch_masked_copy<double>(g, c.dirm, p, nn, nrhs, st);  // d_Gamma
+        apply_one<double>(c, FCRKPM_OP_K_FULL, p, q, nrhs, st);
+        launch_sub_masked(t, q, c.freem, b, nn, nrhs, st);
+    } else {
+        launch_masked_copy<double>(t, c.freem, b, nn, nrhs, st);
+    }
+    if (d0) launch_masked_copy<double>(d0, c.freem, x, nn, nrhs, st);
+    else HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * nn * nrhs, st));
+}
+
+// d = chi_Omega x + chi_Gamma_g g, and u^h = N d when asked (Alg 3)
+void finish_solve(Ctx& c, int nrhs, const double* g, double* d_out, double* uh_out,
+                  hipStream_t st)
+{
+    const long nn = c.nn;
+    double* x = vec64(c, V_X);
+    if (g) {
+        double* p = vec64(c, V_P);
+        launch_masked_copy<double>(g, c.dirm, p, nn, nrhs, st);
+        launch_select(c.freem, x, p, d_out, nn, nrhs, st);
+    } else {
+        HIPCHK(hipMemcpyAsync(d_out, x, sizeof(double) * nn * nrhs, hipMemcpyDeviceToDevice, st));
+    }
+    if (uh_out) apply_one<double>(c, FCRKPM_OP_UH, d_out, uh_out, nrhs, st);
+}
+
+void check_solve_args(int mode, int nrhs, double tol, int maxit)
+{
+    if (mode < FCRKPM_MODE_F64 || mode > FCRKPM_MODE_F32_PRODUCTS) fail(FCRKPM_ERR_ARG, "unknown mode");
+    if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
+    if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
+}
+}  // namespace
+
 extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t nrhs,
                                       const void* in, void* out, void* stream)
 {
@@ -1011,7 +1395,7 @@ extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype
     return run_guarded(c.err, [&]() -> fcrkpm_status {
         if (op < FCRKPM_OP_K || op > FCRKPM_OP_VN) fail(FCRKPM_ERR_ARG, "unknown operator");
         if (dtype != FCRKPM_F64 && dtype != FCRKPM_F32) fail(FCRKPM_ERR_ARG, "unknown dtype");
-        if (nrhs < 1) fail(FCRKPM_ERR_ARG, "nrhs must be >= 1");
+        if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
         if (!in || !out) fail(FCRKPM_ERR_ARG, "NULL array");
         const size_t es = dtype == FCRKPM_F64 ? 8 : 4;
         const char* a0 = (const char*)in;
@@ -1019,12 +1403,10 @@ extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype
         const size_t bytes = es * (size_t)c.nn * nrhs;
         if (a0 < b0 + bytes && b0 < a0 + bytes) fail(FCRKPM_ERR_ARG, "in and out overlap");
         hipStream_t st = (hipStream_t)stream;
-        for (int j = 0; j < nrhs; ++j) {
-            if (dtype == FCRKPM_F64)
-                apply_one<double>(c, op, (const double*)in + (size_t)j * c.nn, (double*)out + (size_t)j * c.nn, st);
-            else
-                apply_one<float>(c, op, (const float*)in + (size_t)j * c.nn, (float*)out + (size_t)j * c.nn, st);
-        }
+        if (dtype == FCRKPM_F64)
+            apply_one<double>(c, op, (const double*)in, (double*)out, nrhs, st);
+        else
+            apply_one<float>(c, op, (const float*)in, (float*)out, nrhs, st);
         HIPCHK(hipGetLastError());
         return FCRKPM_OK;
     });
@@ -1037,54 +1419,73 @@ extern "C" fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrh
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (mode < FCRKPM_MODE_F64 || mode > FCRKPM_MODE_F32_PRODUCTS) fail(FCRKPM_ERR_ARG, "unknown mode");
-        if (nrhs < 1 || !r || !d_inout) fail(FCRKPM_ERR_ARG, "bad arguments");
-        if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
+        check_solve_args(mode, nrhs, tol, maxit);
+        if (!r || !d_inout) fail(FCRKPM_ERR_ARG, "NULL array");
         hipStream_t st = (hipStream_t)stream;
-        const long nn = c.nn;
-        fcrkpm_status worst = FCRKPM_OK;
-        for (int j = 0; j < nrhs; ++j) {
-            const double* rj = r + (size_t)j * nn;
-            const double* gj = g ? g + (size_t)j * nn : nullptr;
-            double* dj = d_inout + (size_t)j * nn;
-            HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
-            launch_check_finite(rj, nn, c.dflag + 2, st);
-            if (gj) launch_check_finite(gj, nn, c.dflag + 2, st);
-            int hf = 0;
-            HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r or g");
-            double* b = c.v64 + V_B * nn;
-            double* x = c.v64 + V_X * nn;
-            double* t = c.v64 + V_T * nn;
-            double* p = c.v64 + V_P * nn;
-            double* q = c.v64 + V_Q * nn;
-            apply_one<double>(c, FCRKPM_OP_FR, rj, t, st);  // f^r (Alg 4)
-            if (gj) {
-                launch_masked_copy<double>(gj, c.dirm, p, nn, st);  // d_Gamma
-                apply_one<double>(c, FCRKPM_OP_K_FULL, p, q, st);
-                launch_sub_masked(t, q, c.freem, b, nn, st);
-            } else {
-                launch_masked_copy<double>(t, c.freem, b, nn, st);
-            }
-            launch_masked_copy<double>(dj, c.freem, x, nn, st);
-            fcrkpm_info inf;
-            fcrkpm_status s = solve_core(c, mode, tol, maxit, &inf, st);
-            if (s != FCRKPM_OK) worst = s;
-            if (gj) {
-                launch_masked_copy<double>(gj, c.dirm, p, nn, st);
-                launch_select(c.freem, x, p, dj, nn, st);
-            } else {
-                HIPCHK(hipMemcpyAsync(dj, x, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
-            }
-            if (uh_out) apply_one<double>(c, FCRKPM_OP_UH, dj, uh_out + (size_t)j * nn, st);
-            if (info) *info = inf;
-        }
+        prepare_solve(c, nrhs, r, g, d_inout, st);
+        Solver S(c, nrhs, mode, tol, maxit);
+        run_solvers({&S}, graphs_enabled(c), st);
+        const fcrkpm_status worst = S.finish(info, st);
+        finish_solve(c, nrhs, g, d_inout, uh_out, st);
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
         if (worst != FCRKPM_OK) c.err = "solver did not reach the tolerance";
         return worst;
     });
+}
+
+extern "C" fcrkpm_status fcrkpm_solve_batch(fcrkpm_ctx* const* ctxs, int32_t nprob, int32_t mode,
+                                            const int32_t* nrhs, const double* const* r,
+                                            const double* const* g, double* const* d_inout,
+                                            double* const* uh_out, double tol, int32_t maxit,
+                                            fcrkpm_info* info, void* stream)
+{
+    if (!ctxs || nprob < 1 || !ctxs[0]) {
+        g_setup_err = "fcrkpm_solve_batch: no problems";
+        return FCRKPM_ERR_ARG;
+    }
+    std::string err;
+    fcrkpm_status s = run_guarded(err, [&]() -> fcrkpm_status {
+        if (!nrhs || !r || !d_inout) fail(FCRKPM_ERR_ARG, "NULL array");
+        for (int p = 0; p < nprob; ++p) {
+            if (!ctxs[p]) fail(FCRKPM_ERR_ARG, "NULL context in the batch");
+            for (int q = 0; q < p; ++q)
+                if (ctxs[q] == ctxs[p]) fail(FCRKPM_ERR_ARG, "a context appears twice in the batch");
+            check_solve_args(mode, nrhs[p], tol, maxit);
+            if (!r[p] || !d_inout[p]) fail(FCRKPM_ERR_ARG, "NULL array in the batch");
+        }
+        hipStream_t st = (hipStream_t)stream;
+        bool graphs = true;
+        for (int p = 0; p < nprob; ++p) {
+            Ctx& c = ctxs[p]->c;
+            prepare_solve(c, nrhs[p], r[p], g ? g[p] : nullptr, d_inout[p], st);
+            graphs = graphs && graphs_enabled(c);
+        }
+        std::vector<std::unique_ptr<Solver>> S;
+        std::vector<Solver*> ptr;
+        for (int p = 0; p < nprob; ++p) {
+            S.emplace_back(new Solver(ctxs[p]->c, nrhs[p], mode, tol, maxit));
+            ptr.push_back(S.back().get());
+        }
+        run_solvers(ptr, graphs, st);
+        fcrkpm_status worst = FCRKPM_OK;
+        long off = 0;
+        for (int p = 0; p < nprob; ++p) {
+            const fcrkpm_status sp = S[p]->finish(info ? info + off : nullptr, st);
+            if (sp != FCRKPM_OK) worst = sp;
+            off += nrhs[p];
+        }
+        for (int p = 0; p < nprob; ++p)
+            finish_solve(ctxs[p]->c, nrhs[p], g ? g[p] : nullptr, d_inout[p],
+                         uh_out ? uh_out[p] : nullptr, st);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        if (worst != FCRKPM_OK) err = "a problem of the batch did not reach the tolerance";
+        return worst;
+    });
+    for (int p = 0; p < nprob; ++p)
+        if (ctxs[p]) ctxs[p]->c.err = err;
+    return s;
 }
 
 extern "C" fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs,
@@ -1094,29 +1495,43 @@ extern "C" fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t n
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (mode < FCRKPM_MODE_F64 || mode > FCRKPM_MODE_F32_PRODUCTS) fail(FCRKPM_ERR_ARG, "unknown mode");
-        if (nrhs < 1 || !dl_duh || !dl_dr) fail(FCRKPM_ERR_ARG, "bad arguments");
-        if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
+        check_solve_args(mode, nrhs, tol, maxit);
+        if (!dl_duh || !dl_dr) fail(FCRKPM_ERR_ARG, "NULL array");
         hipStream_t st = (hipStream_t)stream;
+        ensure_rhs(c, nrhs);
+        ensure_work(c, nrhs);
         const long nn = c.nn;
-        fcrkpm_status worst = FCRKPM_OK;
-        for (int j = 0; j < nrhs; ++j) {
-            double* b = c.v64 + V_B * nn;
-            double* x = c.v64 + V_X * nn;
-            double* t = c.v64 + V_T * nn;
-            apply_one<double>(c, FCRKPM_OP_NT, dl_duh + (size_t)j * nn, t, st);
-            launch_masked_copy<double>(t, c.freem, b, nn, st);
-            HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * nn, st));
-            fcrkpm_info inf;
-            fcrkpm_status s = solve_core(c, mode, tol, maxit, &inf, st);
-            if (s != FCRKPM_OK) worst = s;
-            apply_one<double>(c, FCRKPM_OP_VN, x, dl_dr + (size_t)j * nn, st);
-            if (info) *info = inf;
-        }
+        double* b = vec64(c, V_B);
+        double* x = vec64(c, V_X);
+        double* t = vec64(c, V_T);
+        apply_one<double>(c, FCRKPM_OP_NT, dl_duh, t, nrhs, st);
+        launch_masked_copy<double>(t, c.freem, b, nn, nrhs, st);
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * nn * nrhs, st));
+        Solver S(c, nrhs, mode, tol, maxit);
+        run_solvers({&S}, graphs_enabled(c), st);
+        const fcrkpm_status worst = S.finish(info, st);
+        apply_one<double>(c, FCRKPM_OP_VN, x, dl_dr, nrhs, st);
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipGetLastError());
         if (worst != FCRKPM_OK) c.err = "adjoint solve did not reach the tolerance";
         return worst;
+    });
+}
+
+extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        switch (option) {
+            case FCRKPM_OPT_GRAPHS:
+                if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_GRAPHS takes 0 or 1");
+                c.use_graphs = value == 1;
+                break;
+            default:
+                fail(FCRKPM_ERR_ARG, "unknown option");
+        }
+        return FCRKPM_OK;
     });
 }
 

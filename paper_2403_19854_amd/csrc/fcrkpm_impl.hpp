@@ -85,25 +85,39 @@ struct Ctx {
     cplx<double>* spec64[3] = {};       // kernel spectra per axis, exponents 0..2n
     cplx<float>* spec32[3] = {};
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
+    // and right-hand side (cap_work of them)
     cplx<double>* work64 = nullptr;
     cplx<float>* work32 = nullptr;
     // real vectors for the solvers
-    double* v64 = nullptr;              // 6 FP64 vectors
-    float* v32 = nullptr;               // 5 FP32 vectors
-    double* partial = nullptr;          // reduction partials (2 x kRedBlocks)
-    double* scal = nullptr;             // device scalars
-    double* hscal = nullptr;            // pinned host mirror
+    double* v64 = nullptr;              // 6 FP64 vectors of cap_rhs fields
+    float* v32 = nullptr;               // 5 FP32 vectors of cap_rhs fields
+    double* partial = nullptr;          // reduction partials (2 x cap_rhs x kRedBlocks)
+    double* scal = nullptr;             // device scalars (cap_rhs x kScal)
+    double* hscal = nullptr;            // pinned host mirror (2 poll slots + 1 read slot)
+    int* act = nullptr;                 // per right-hand side: still iterating
+    int cap_rhs = 0;                    // right-hand sides the solver buffers hold
+    int cap_work = 0;                   // right-hand sides the pass workspace holds
+    bool capturing = false;             // a graph capture is recording this context's work
+    hipStream_t aux = nullptr;          // stream of this problem inside a batched solve
     int* dflag = nullptr;               // device int flags
-    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     void* prof = nullptr;               // kernel-duration sampler (measurement only)
     bool prof_on = false;
+    bool use_graphs = true;             // replay CG blocks from captured graphs
     SepPlan basis_plan;                 // basis monomials (Alg 2-4)
     SepProg* dprog = nullptr;           // device copies of the pass programs
     int lds_budget = 65536;             // LDS bytes one workgroup may use
 };
 
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 1024;   // reduction partials per right-hand side (at most)
 constexpr int kRedThreads = 256;
+constexpr int kScal = 8;           // device scalars per right-hand side
+
+// Right-hand sides of one launch (blockIdx.y) and the byte strides between
+// their input, output and source fields.
+struct RhsBatch {
+    int n = 1;
+    long in_bytes = 0, out_bytes = 0, src_bytes = 0;
+};
 
 // ------------------------------------------------------------- launchers
 // separable passes (sepconv.hip); load/store and pointwise modes:
@@ -115,14 +129,16 @@ template <typename T, typename Tio>
 void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr, int ldm,
                      const void* in,
                      const uint8_t* mask_in, int stm, void* out, const uint8_t* mask_out,
-                     double* dot_part, const void* dot_with, hipStream_t st);
+                     double* dot_part, const void* dot_with, hipStream_t st,
+                     const RhsBatch& rb = RhsBatch{});
 
 template <typename T, typename Tio>
 void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1,
                     const SepProg& pr2, const SepProg* dpr2, int pw, int ldm,
                     const void* in, const uint8_t* mask_in, int stm, void* out,
                     const uint8_t* mask_out, const void* src, const T* b0, const T* ba,
-                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st);
+                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st,
+                    const RhsBatch& rb = RhsBatch{});
 
 // LDS bytes the passes of a plan need at the tile widths they will use
 size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes);
@@ -137,29 +153,30 @@ void launch_vol(const uint8_t* chi, const double* vol_in, double hv, double* vol
 void launch_mask_to_double(const uint8_t* m, double* out, long nn, hipStream_t st);
 void launch_check_finite(const double* x, long nn, int* flag, hipStream_t st);
 
-// CG / vector kernels (deterministic two-stage reductions)
+// CG / vector kernels (deterministic two-stage reductions), batched over
+// nrhs right-hand sides: vectors of rhs j start at j*n, its scalars at
+// j*kScal, its reduction partials at j*kRedBlocks; act[j] == 0 freezes it.
+int red_blocks(long n);
 template <typename T>
-void launch_dot_partial(const T* a, const T* b, long n, double* part, hipStream_t st);
-void launch_reduce_to(const double* part, double* dst, hipStream_t st);
+void launch_dot_partial(const T* a, const T* b, long n, int nrhs, double* part, const int* act,
+                        hipStream_t st);
+void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStream_t st);
 template <typename T>
-void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, const double* pq_part,
-                  double* scal, int parity, double* rr_part, hipStream_t st);
+void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, int nrhs, const double* pq_part,
+                  double* scal, int parity, double* rr_part, const int* act, hipStream_t st);
 template <typename T>
-void launch_cg_p(T* p, const T* r, long n, const double* rr_part, double* scal, int parity,
-                 hipStream_t st);
+void launch_cg_p(T* p, const T* r, long n, int nrhs, const double* rr_part, double* scal,
+                 int parity, const int* act, hipStream_t st);
+void launch_set_scalar(double* scal, int idx, double v, int nrhs, hipStream_t st);
+void launch_set_flag(int* act, int j, int v, hipStream_t st);
 template <typename T>
-void launch_masked_copy(const T* src, const uint8_t* mask, T* dst, long n, hipStream_t st);
-void launch_residual64(const double* b, const double* kx, const uint8_t* mask, double* r, long n,
-                       hipStream_t st);
-void launch_scale_to32(const double* r, const double* scal, int idx, float* out, long n,
-                       hipStream_t st);
-void launch_axpy32to64(double* x, const float* c, const double* scal, int idx, long n,
-                       hipStream_t st);
+void launch_masked_copy(const T* src, const uint8_t* mask, T* dst, long n, int nrhs,
+                        hipStream_t st);
 void launch_sub_masked(const double* a, const double* b, const uint8_t* mask, double* out,
-                       long n, hipStream_t st);
+                       long n, int nrhs, hipStream_t st);
 void launch_select(const uint8_t* mask, const double* a, const double* b, double* out, long n,
-                   hipStream_t st);
-void launch_mul(const double* a, const double* b, double* out, long n, hipStream_t st);
+                   int nrhs, hipStream_t st);
+// flat over all elements (n = nodes * nrhs)
 void launch_to32(const double* a, float* out, long n, hipStream_t st);
 void launch_add32to64_reset(double* x, float* c, long n, hipStream_t st);
 void launch_add_reset64(double* x, double* c, long n, hipStream_t st);

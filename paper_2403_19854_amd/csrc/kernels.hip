@@ -245,59 +245,87 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return r;
 }
 
-// every block sums the kRedBlocks partials in the same fixed order
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, double* sh)
+// Batched reductions: right-hand side j = blockIdx.y owns vectors at offset
+// j*n, nb partials at j*kRedBlocks and kScal scalars at j*kScal.  The number
+// of partials nb depends on n only, and every block sums them in the same
+// fixed order, so results are bitwise reproducible.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb, double* sh)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
     return block_sum(v, sh);
+}
+
+int red_blocks(long n)
+{
+    const long per = (long)kRedThreads * 4;
+    return (int)std::max(1L, std::min((long)kRedBlocks, (n + per - 1) / per));
 }
 
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_dot_partial(const T* __restrict__ a,
                                                              const T* __restrict__ b, long n,
-                                                             double* __restrict__ part)
+                                                             double* __restrict__ part,
+                                                             const int* __restrict__ act)
 {
     __shared__ double sh[16];
+    const int j = blockIdx.y;
+    if (act && !act[j]) return;
+    a += j * n;
+    b += j * n;
     double acc = 0.0;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x)
         acc += (double)a[i] * (double)b[i];
     double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[(long)j * kRedBlocks + blockIdx.x] = s;
 }
 
 template <typename T>
-void launch_dot_partial(const T* a, const T* b, long n, double* part, hipStream_t st)
+void launch_dot_partial(const T* a, const T* b, long n, int nrhs, double* part, const int* act,
+                        hipStream_t st)
 {
-    hipLaunchKernelGGL((k_dot_partial<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, n,
-                       part);
+    hipLaunchKernelGGL((k_dot_partial<T>), dim3(red_blocks(n), nrhs), dim3(kRedThreads), 0, st,
+                       a, b, n, part, act);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce_to(const double* __restrict__ part,
+__global__ __launch_bounds__(kRedThreads) void k_reduce_to(const double* __restrict__ part, int nb,
                                                            double* dst)
 {
     __shared__ double sh[16];
-    double s = sum_partials(part, sh);
-    if (threadIdx.x == 0) *dst = s;
+    const int j = blockIdx.y;
+    double s = sum_partials(part + (long)j * kRedBlocks, nb, sh);
+    if (threadIdx.x == 0) dst[j * kScal] = s;
 }
 
-void launch_reduce_to(const double* part, double* dst, hipStream_t st)
+void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kRedThreads), 0, st, part, dst);
+    hipLaunchKernelGGL(k_reduce_to, dim3(1, nrhs), dim3(kRedThreads), 0, st, part, red_blocks(n),
+                       dst);
 }
 
-// scal layout: [0], [1] = r.r (double-buffered by parity), [3] = breakdown flag
+// scalars of one right-hand side: [0], [1] = r.r (double-buffered by
+// parity), [3] = breakdown flag.  Right-hand sides with act[j] == 0 are
+// frozen: x, r, p and their scalars stay as they are.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __restrict__ r,
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q, long n,
                                                        const double* __restrict__ pq_part,
                                                        double* scal, int parity,
-                                                       double* __restrict__ rr_part)
+                                                       double* __restrict__ rr_part,
+                                                       const int* __restrict__ act)
 {
     __shared__ double sh[16];
-    const double pq = sum_partials(pq_part, sh);
+    const int j = blockIdx.y;
+    if (!act[j]) return;
+    const long off = j * n;
+    x += off;
+    r += off;
+    p += off;
+    q += off;
+    scal += j * kScal;
+    const double pq = sum_partials(pq_part + (long)j * kRedBlocks, gridDim.x, sh);
     const double rr = scal[parity];
     const bool good = pq > 0.0 && rr > 0.0;
     const T alpha = good ? T(rr / pq) : T(0);
@@ -312,24 +340,30 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __r
         acc += (double)ri * (double)ri;
     }
     double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
+    if (threadIdx.x == 0) rr_part[(long)j * kRedBlocks + blockIdx.x] = s;
 }
 
 template <typename T>
-void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, const double* pq_part, double* scal,
-                  int parity, double* rr_part, hipStream_t st)
+void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, int nrhs, const double* pq_part,
+                  double* scal, int parity, double* rr_part, const int* act, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_cg_xr<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, r, p, q, n,
-                       pq_part, scal, parity, rr_part);
+    hipLaunchKernelGGL((k_cg_xr<T>), dim3(red_blocks(n), nrhs), dim3(kRedThreads), 0, st, x, r, p,
+                       q, n, pq_part, scal, parity, rr_part, act);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_cg_p(T* __restrict__ p, const T* __restrict__ r,
                                                       long n, const double* __restrict__ rr_part,
-                                                      double* scal, int parity)
+                                                      double* scal, int parity,
+                                                      const int* __restrict__ act)
 {
     __shared__ double sh[16];
-    const double rr_new = sum_partials(rr_part, sh);
+    const int j = blockIdx.y;
+    if (!act[j]) return;
+    p += j * n;
+    r += j * n;
+    scal += j * kScal;
+    const double rr_new = sum_partials(rr_part + (long)j * kRedBlocks, gridDim.x, sh);
     const double rr_old = scal[parity];
     const T beta = rr_old > 0.0 ? T(rr_new / rr_old) : T(0);
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
@@ -339,117 +373,99 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_p(T* __restrict__ p, const T
 }
 
 template <typename T>
-void launch_cg_p(T* p, const T* r, long n, const double* rr_part, double* scal, int parity,
-                 hipStream_t st)
+void launch_cg_p(T* p, const T* r, long n, int nrhs, const double* rr_part, double* scal,
+                 int parity, const int* act, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_cg_p<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, r, n, rr_part,
-                       scal, parity);
+    hipLaunchKernelGGL((k_cg_p<T>), dim3(red_blocks(n), nrhs), dim3(kRedThreads), 0, st, p, r, n,
+                       rr_part, scal, parity, act);
 }
 
-template void launch_dot_partial<double>(const double*, const double*, long, double*, hipStream_t);
-template void launch_dot_partial<float>(const float*, const float*, long, double*, hipStream_t);
-template void launch_cg_xr<double>(double*, double*, const double*, const double*, long,
-                                   const double*, double*, int, double*, hipStream_t);
-template void launch_cg_xr<float>(float*, float*, const float*, const float*, long, const double*,
-                                  double*, int, double*, hipStream_t);
-template void launch_cg_p<double>(double*, const double*, long, const double*, double*, int,
-                                  hipStream_t);
-template void launch_cg_p<float>(float*, const float*, long, const double*, double*, int,
-                                 hipStream_t);
+template void launch_dot_partial<double>(const double*, const double*, long, int, double*,
+                                         const int*, hipStream_t);
+template void launch_dot_partial<float>(const float*, const float*, long, int, double*,
+                                        const int*, hipStream_t);
+template void launch_cg_xr<double>(double*, double*, const double*, const double*, long, int,
+                                   const double*, double*, int, double*, const int*, hipStream_t);
+template void launch_cg_xr<float>(float*, float*, const float*, const float*, long, int,
+                                  const double*, double*, int, double*, const int*, hipStream_t);
+template void launch_cg_p<double>(double*, const double*, long, int, const double*, double*, int,
+                                  const int*, hipStream_t);
+template void launch_cg_p<float>(float*, const float*, long, int, const double*, double*, int,
+                                 const int*, hipStream_t);
 
+// scal[j*kScal + idx] = v for every right-hand side
+__global__ void k_set_scalar(double* scal, int idx, double v, int nrhs)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nrhs) scal[j * kScal + idx] = v;
+}
+
+void launch_set_scalar(double* scal, int idx, double v, int nrhs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_scalar, dim3((nrhs + 63) / 64), dim3(64), 0, st, scal, idx, v, nrhs);
+}
+
+__global__ void k_set_flag(int* act, int j, int v)
+{
+    if (threadIdx.x == 0) act[j] = v;
+}
+
+void launch_set_flag(int* act, int j, int v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, act, j, v);
+}
+
+// masked element-wise kernels: field j = blockIdx.y of nrhs fields of n nodes
 template <typename T>
 __global__ void k_masked_copy(const T* __restrict__ src, const uint8_t* __restrict__ mask,
                               T* __restrict__ dst, long n)
 {
+    const long off = blockIdx.y * n;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x)
-        dst[i] = mask[i] ? src[i] : T(0);
+        dst[off + i] = mask[i] ? src[off + i] : T(0);
 }
 
 template <typename T>
-void launch_masked_copy(const T* src, const uint8_t* mask, T* dst, long n, hipStream_t st)
+void launch_masked_copy(const T* src, const uint8_t* mask, T* dst, long n, int nrhs, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_masked_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, st, src, mask, dst, n);
+    hipLaunchKernelGGL((k_masked_copy<T>), dim3(ew_blocks(n), nrhs), dim3(256), 0, st, src, mask,
+                       dst, n);
 }
-template void launch_masked_copy<double>(const double*, const uint8_t*, double*, long, hipStream_t);
-template void launch_masked_copy<float>(const float*, const uint8_t*, float*, long, hipStream_t);
+template void launch_masked_copy<double>(const double*, const uint8_t*, double*, long, int,
+                                         hipStream_t);
+template void launch_masked_copy<float>(const float*, const uint8_t*, float*, long, int,
+                                        hipStream_t);
 
 __global__ void k_sub_masked(const double* __restrict__ a, const double* __restrict__ b,
                              const uint8_t* __restrict__ mask, double* __restrict__ out, long n)
 {
+    const long off = blockIdx.y * n;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x)
-        out[i] = mask[i] ? a[i] - b[i] : 0.0;
+        out[off + i] = mask[i] ? a[off + i] - b[off + i] : 0.0;
 }
 
 void launch_sub_masked(const double* a, const double* b, const uint8_t* mask, double* out, long n,
-                       hipStream_t st)
+                       int nrhs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sub_masked, dim3(ew_blocks(n)), dim3(256), 0, st, a, b, mask, out, n);
-}
-
-void launch_residual64(const double* b, const double* kx, const uint8_t* mask, double* r, long n,
-                       hipStream_t st)
-{
-    launch_sub_masked(b, kx, mask, r, n, st);
-}
-
-__global__ void k_scale_to32(const double* __restrict__ r, const double* scal, int idx,
-                             float* __restrict__ out, long n)
-{
-    const double nr = sqrt(scal[idx]);
-    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x)
-        out[i] = (float)(r[i] * inv);
-}
-
-void launch_scale_to32(const double* r, const double* scal, int idx, float* out, long n,
-                       hipStream_t st)
-{
-    hipLaunchKernelGGL(k_scale_to32, dim3(ew_blocks(n)), dim3(256), 0, st, r, scal, idx, out, n);
-}
-
-__global__ void k_axpy32to64(double* __restrict__ x, const float* __restrict__ c,
-                             const double* scal, int idx, long n)
-{
-    const double nr = sqrt(scal[idx]);
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x)
-        x[i] += nr * (double)c[i];
-}
-
-void launch_axpy32to64(double* x, const float* c, const double* scal, int idx, long n,
-                       hipStream_t st)
-{
-    hipLaunchKernelGGL(k_axpy32to64, dim3(ew_blocks(n)), dim3(256), 0, st, x, c, scal, idx, n);
+    hipLaunchKernelGGL(k_sub_masked, dim3(ew_blocks(n), nrhs), dim3(256), 0, st, a, b, mask, out,
+                       n);
 }
 
 __global__ void k_select(const uint8_t* __restrict__ mask, const double* __restrict__ a,
                          const double* __restrict__ b, double* __restrict__ out, long n)
 {
+    const long off = blockIdx.y * n;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x)
-        out[i] = mask[i] ? a[i] : b[i];
+        out[off + i] = mask[i] ? a[off + i] : b[off + i];
 }
 
 void launch_select(const uint8_t* mask, const double* a, const double* b, double* out, long n,
-                   hipStream_t st)
+                   int nrhs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select, dim3(ew_blocks(n)), dim3(256), 0, st, mask, a, b, out, n);
-}
-
-__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ out, long n)
-{
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x)
-        out[i] = a[i] * b[i];
-}
-
-void launch_mul(const double* a, const double* b, double* out, long n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_mul, dim3(ew_blocks(n)), dim3(256), 0, st, a, b, out, n);
+    hipLaunchKernelGGL(k_select, dim3(ew_blocks(n), nrhs), dim3(256), 0, st, mask, a, b, out, n);
 }
 
 __global__ void k_to32(const double* __restrict__ a, float* __restrict__ out, long n)

@@ -322,7 +322,23 @@ struct SepArgs {
     int nin, nout;            // its field counts
     double* dot_part;         // optional: per-block partial of out . dot_with (ST_REAL)
     const void* dot_with;
+    long in_rb, out_rb;       // bytes between right-hand sides (blockIdx.y) of in / out
 };
+
+// the arguments of right-hand side blockIdx.y
+template <typename T>
+__device__ __forceinline__ SepArgs<T> rhs_args(const SepArgs<T>& a0)
+{
+    SepArgs<T> a = a0;
+    const long j = blockIdx.y;
+    a.in = (const char*)a0.in + j * a0.in_rb;
+    a.out = (char*)a0.out + j * a0.out_rb;
+    if (a0.dot_part) {
+        a.dot_part = a0.dot_part + j * gridDim.x;
+        a.dot_with = (const char*)a0.dot_with + j * a0.out_rb;
+    }
+    return a;
+}
 
 enum { LD_PAIRS = SEP_LD_PAIRS, LD_REAL = SEP_LD_REAL, LD_CHI = SEP_LD_CHI };
 enum { ST_PAIRS = SEP_ST_PAIRS, ST_REAL = SEP_ST_REAL };
@@ -424,8 +440,9 @@ __device__ __forceinline__ double store_tile(const SepArgs<T>& a, const Tile<CON
 }
 
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int LC>
-__global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a)
+__global__ __launch_bounds__(kThreads) void k_sep_pass(SepArgs<T> a0)
 {
+    const SepArgs<T> a = rhs_args(a0);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Tile<CONTIG, LC> tl(a.g, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x;
@@ -473,6 +490,7 @@ struct MidArgs {
     const T* vol;             // [nn] or NULL
     const void* src;          // PW_LOAD: the real field r (Tio)
     long nn;
+    long src_rb;              // bytes between right-hand sides of src
 };
 
 enum { PW_K = SEP_PW_K, PW_UH = SEP_PW_UH, PW_LOAD = SEP_PW_LOAD };
@@ -481,7 +499,8 @@ template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DI
 __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const SepArgs<T>& a = m.s;
+    const SepArgs<T> a = rhs_args(m.s);
+    const void* const msrc = (const char*)m.src + (long)blockIdx.y * m.src_rb;
     const Tile<CONTIG, LC> tl(a.g, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x;
     const int L = tl.L, P = tl.P, E = tl.elems(), BE = tl.buf_elems();
@@ -602,7 +621,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                     int w, i;
                     long gi;
                     tl.at(e, w, i, gi, o[kk]);
-                    x[kk] = T(reinterpret_cast<const Tio*>(m.src)[gi]) * (m.vol ? m.vol[gi] : T(1));
+                    x[kk] = T(reinterpret_cast<const Tio*>(msrc)[gi]) * (m.vol ? m.vol[gi] : T(1));
 #pragma unroll
                     for (int p = 0; p < S; ++p) b[kk][p] = m.b0[p * m.nn + gi];
                 }
@@ -724,9 +743,9 @@ static bool sep_log()
 }
 
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM>
-static void go_pass(const SepArgs<T>& s, size_t sh, hipStream_t st)
+static void go_pass(const SepArgs<T>& s, size_t sh, int nrhs, hipStream_t st)
 {
-    const dim3 grid((unsigned)(s.g.nlines / s.g.W));
+    const dim3 grid((unsigned)(s.g.nlines / s.g.W), (unsigned)nrhs);
     if (s.g.L == 128)
         hipLaunchKernelGGL((k_sep_pass<T, Tio, CONTIG, LDM, STM, 128>), grid, dim3(kThreads), sh, st, s);
     else
@@ -743,9 +762,11 @@ template <typename T, typename Tio>
 void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr, int ldm,
                      const void* in, const uint8_t* mask_in, int stm, void* out,
                      const uint8_t* mask_out, double* dot_part, const void* dot_with,
-                     hipStream_t st)
+                     hipStream_t st, const RhsBatch& rb)
 {
     SepArgs<T> s;
+    s.in_rb = rb.in_bytes;
+    s.out_rb = rb.out_bytes;
     const int nbin = (pr.nin + 1) / 2;
     fill_common<T>(c, a, s, nbin + 1);
     s.in = in;
@@ -758,7 +779,7 @@ void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr,
     s.dot_part = dot_part;
     s.dot_with = dot_with;
     const size_t sh = (size_t)(s.ne + 1) * s.g.L * sizeof(cplx<T>) + (nbin + 1) * buf_bytes(s.g, sizeof(cplx<T>));
-#define FC_PASS(CT, LD, STO) go_pass<T, Tio, CT, LD, STO>(s, sh, st)
+#define FC_PASS(CT, LD, STO) go_pass<T, Tio, CT, LD, STO>(s, sh, rb.n, st)
     const bool ct = s.g.contig;
     if (ldm == LD_PAIRS && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_PAIRS, ST_PAIRS); else FC_PASS(false, LD_PAIRS, ST_PAIRS); }
     else if (ldm == LD_REAL && stm == ST_PAIRS) { if (ct) FC_PASS(true, LD_REAL, ST_PAIRS); else FC_PASS(false, LD_REAL, ST_PAIRS); }
@@ -768,9 +789,9 @@ void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr,
 }
 
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW>
-static void go_mid(const MidArgs<T>& m, size_t sh, hipStream_t st)
+static void go_mid(const MidArgs<T>& m, size_t sh, int nrhs, hipStream_t st)
 {
-    const dim3 grid((unsigned)(m.s.g.nlines / m.s.g.W));
+    const dim3 grid((unsigned)(m.s.g.nlines / m.s.g.W), (unsigned)nrhs);
     // the 128-point lines of the 3D workloads get the compile-time plan
     if constexpr (DIM == 3 && !CONTIG) {
         if (m.s.g.L == 128) {
@@ -790,10 +811,11 @@ static void go_mid(const MidArgs<T>& m, size_t sh, hipStream_t st)
 }
 
 template <typename T, typename Tio, int S, int DIM>
-static void mid_dispatch(const MidArgs<T>& m, int ldm, int stm, int pw, size_t sh, hipStream_t st)
+static void mid_dispatch(const MidArgs<T>& m, int ldm, int stm, int pw, size_t sh, int nrhs,
+                         hipStream_t st)
 {
     const bool ct = m.s.g.contig;
-#define FC_MID(CT, LD, STO, P) go_mid<T, Tio, CT, LD, STO, S, DIM, P>(m, sh, st)
+#define FC_MID(CT, LD, STO, P) go_mid<T, Tio, CT, LD, STO, S, DIM, P>(m, sh, nrhs, st)
     if (pw == PW_K) {
         if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
         else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
@@ -812,9 +834,13 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
                     const SepProg& pr2, const SepProg* dpr2, int pw, int ldm,
                     const void* in, const uint8_t* mask_in, int stm, void* out,
                     const uint8_t* mask_out, const void* src, const T* b0, const T* ba,
-                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st)
+                    const T* vol, double* dot_part, const void* dot_with, hipStream_t st,
+                    const RhsBatch& rb)
 {
     MidArgs<T> m;
+    m.s.in_rb = rb.in_bytes;
+    m.s.out_rb = rb.out_bytes;
+    m.src_rb = rb.src_bytes;
     const int np = (c.s + 1) / 2;
     const int nbin = (pw == PW_LOAD) ? 0 : (pr1.nin + 1) / 2;
     const int nbuf = nbin + np + (pw == PW_UH ? 0 : 1);
@@ -836,35 +862,35 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.src = src;
     m.nn = c.nn;
     const size_t sh = (size_t)(m.s.ne + 1) * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
-    if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, st);
-    else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, st);
-    else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, st);
-    else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, st);
-    else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, st);
-    else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, st);
+    if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, rb.n, st);
 }
 
 template void launch_sep_pass<double, double>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
                                               const uint8_t*, int, void*, const uint8_t*, double*,
-                                              const void*, hipStream_t);
+                                              const void*, hipStream_t, const RhsBatch&);
 template void launch_sep_pass<float, float>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
                                             const uint8_t*, int, void*, const uint8_t*, double*,
-                                            const void*, hipStream_t);
+                                            const void*, hipStream_t, const RhsBatch&);
 template void launch_sep_pass<float, double>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,
                                              const uint8_t*, int, void*, const uint8_t*, double*,
-                                             const void*, hipStream_t);
+                                             const void*, hipStream_t, const RhsBatch&);
 template void launch_sep_mid<float, double>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
                                             int, const void*, const uint8_t*, int, void*,
                                             const uint8_t*, const void*, const float*, const float*,
-                                            const float*, double*, const void*, hipStream_t);
+                                            const float*, double*, const void*, hipStream_t, const RhsBatch&);
 template void launch_sep_mid<double, double>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
                                              int, const void*, const uint8_t*, int, void*,
                                              const uint8_t*, const void*, const double*,
                                              const double*, const double*, double*, const void*,
-                                             hipStream_t);
+                                             hipStream_t, const RhsBatch&);
 template void launch_sep_mid<float, float>(const Ctx&, int, const SepProg&, const SepProg*, const SepProg&, const SepProg*, int,
                                            int, const void*, const uint8_t*, int, void*,
                                            const uint8_t*, const void*, const float*, const float*,
-                                           const float*, double*, const void*, hipStream_t);
+                                           const float*, double*, const void*, hipStream_t, const RhsBatch&);
 
 }  // namespace fcrkpm

@@ -34,7 +34,8 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_get_coeffs", "fcrkpm_basis_size", "fcrkpm_destroy",
            "fcrkpm_last_error", "fcrkpm_status_str", "fcrkpm_version",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
-           "fcrkpm_kernel_name")
+           "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option")
+OPT_GRAPHS = 1
 
 
 class Grid(C.Structure):
@@ -49,6 +50,21 @@ class Info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _infos_dict(infos, status):
+    """Aggregate of per-rhs records (worst case; the rhs iterate in lockstep)
+    with the records themselves under "per_rhs"."""
+    per = [i.as_dict() for i in infos]
+    out = {"iters": max(d["iters"] for d in per),
+           "outer_iters": max(d["outer_iters"] for d in per),
+           "rel_res": max(d["rel_res"] for d in per),
+           "true_rel_res": max(d["true_rel_res"] for d in per),
+           "fallback_used": int(any(d["fallback_used"] for d in per)),
+           "matvecs_f64": max(d["matvecs_f64"] for d in per),
+           "matvecs_f32": max(d["matvecs_f32"] for d in per),
+           "status": status, "per_rhs": per}
+    return out
 
 
 class FcrkpmError(RuntimeError):
@@ -102,6 +118,12 @@ def load_library(path: str = LIB_PATH):
     lib.fcrkpm_kernel_kinds.argtypes = []
     lib.fcrkpm_kernel_name.restype = C.c_char_p
     lib.fcrkpm_kernel_name.argtypes = [C.c_int32]
+    lib.fcrkpm_solve_batch.restype = C.c_int
+    lib.fcrkpm_solve_batch.argtypes = [C.POINTER(V), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V),
+                                       C.c_double, C.c_int32, C.POINTER(Info), V]
+    lib.fcrkpm_set_option.restype = C.c_int
+    lib.fcrkpm_set_option.argtypes = [V, C.c_int32, C.c_int64]
     _lib = lib
     return lib
 
@@ -208,32 +230,37 @@ class Problem:
 
     def solve(self, r, g=None, d0=None, mode="f64", tol=1e-12, maxit=20000, want_uh=True,
               stream=None, raise_on_noconv=True):
-        """Strong-Dirichlet static solve; returns (d, u^h or None, info dict)."""
+        """Strong-Dirichlet static solve of one or more right-hand sides (leading
+        dimensions of r); returns (d, u^h or None, info dict)."""
         r = _dev(r, torch.float64, self.device)
         nrhs = r.numel() // self.nn
+        if nrhs < 1 or nrhs * self.nn != r.numel():
+            raise ValueError("r does not hold whole fields")
         g = None if g is None else _dev(g, torch.float64, self.device)
         d = torch.zeros_like(r) if d0 is None else _dev(d0, torch.float64, self.device).clone()
         uh = torch.empty_like(r) if want_uh else None
-        info = Info()
+        infos = (Info * nrhs)()
         st = load_library().fcrkpm_solve(self._h, _MODES[mode], nrhs, _ptr(r), _ptr(g), _ptr(d),
-                                         _ptr(uh), float(tol), int(maxit), C.byref(info),
+                                         _ptr(uh), float(tol), int(maxit), infos,
                                          _stream_ptr(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             self._check(st)
-        out = info.as_dict()
-        out["status"] = st
-        return d, uh, out
+        return d, uh, _infos_dict(infos, st)
 
     def adjoint(self, dl_duh, mode="f64", tol=1e-12, maxit=20000, stream=None):
         """dL/dr for a loss of u^h; returns (dL/dr, info dict)."""
         y = _dev(dl_duh, torch.float64, self.device)
         nrhs = y.numel() // self.nn
         g = torch.empty_like(y)
-        info = Info()
+        infos = (Info * nrhs)()
         self._check(load_library().fcrkpm_adjoint(self._h, _MODES[mode], nrhs, _ptr(y), _ptr(g),
-                                                  float(tol), int(maxit), C.byref(info),
+                                                  float(tol), int(maxit), infos,
                                                   _stream_ptr(stream)))
-        return g, info.as_dict()
+        return g, _infos_dict(infos, OK)
+
+    def set_graphs(self, on: bool):
+        """Replay CG blocks from captured HIP graphs (default) or launch directly."""
+        self._check(load_library().fcrkpm_set_option(self._h, OPT_GRAPHS, 1 if on else 0))
 
     def coeffs(self, which="b0"):
         """Copy of b^0 [s, *shape], b^alpha [dim, s, *shape] or chi_Omega [*shape]."""
@@ -262,6 +289,42 @@ class Problem:
             if n.value:
                 out[lib.fcrkpm_kernel_name(k).decode()] = (n.value, ms.value, by.value)
         return out
+
+
+def solve_batch(problems, rs, gs=None, mode="f32_refined", tol=1e-12, maxit=20000,
+                want_uh=True, stream=None, raise_on_noconv=True):
+    """Ragged batch: problem p (its own box) with right-hand sides rs[p]; all
+    problems iterate together (fcrkpm_solve_batch).  Returns a list of
+    (d, u^h or None, info dict) per problem and the batch status."""
+    n = len(problems)
+    if n < 1 or len(rs) != n:
+        raise ValueError("one r per problem")
+    rr, gg, dd, uu, nr = [], [], [], [], []
+    for p, r, g in zip(problems, rs, gs if gs is not None else [None] * n):
+        r = _dev(r, torch.float64, p.device)
+        k = r.numel() // p.nn
+        if k < 1 or k * p.nn != r.numel():
+            raise ValueError("r does not hold whole fields")
+        rr.append(r)
+        gg.append(None if g is None else _dev(g, torch.float64, p.device))
+        dd.append(torch.zeros_like(r))
+        uu.append(torch.empty_like(r) if want_uh else None)
+        nr.append(k)
+    V = C.c_void_p
+    arr = lambda ts: (V * n)(*[t.data_ptr() if t is not None else None for t in ts])
+    ctxs = (V * n)(*[p._h for p in problems])
+    infos = (Info * sum(nr))()
+    st = load_library().fcrkpm_solve_batch(ctxs, n, _MODES[mode], (C.c_int32 * n)(*nr), arr(rr),
+                                           arr(gg) if gs is not None else None, arr(dd),
+                                           arr(uu) if want_uh else None, float(tol), int(maxit),
+                                           infos, _stream_ptr(stream))
+    if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+        problems[0]._check(st)
+    out, off = [], 0
+    for p in range(n):
+        out.append((dd[p], uu[p], _infos_dict(infos[off:off + nr[p]], st)))
+        off += nr[p]
+    return out, st
 
 
 class FCRKPMSolve(torch.autograd.Function):
