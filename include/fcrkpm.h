@@ -228,8 +228,11 @@ const char* fcrkpm_kernel_name(int32_t kind);
 
 /* Options of a context, set with fcrkpm_set_option. */
 enum {
-    FCRKPM_OPT_GRAPHS = 1 /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
-                             launches.  Graphs are never used while profiling is on. */
+    FCRKPM_OPT_GRAPHS = 1,  /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
+                               launches.  Graphs are never used while profiling is on. */
+    FCRKPM_OPT_REGPATH = 2  /* 1 (default): FP32 K products on 64^3 and 128^3 boxes with the
+                               linear basis use register-resident line transforms; 0: the
+                               LDS-tiled passes used everywhere else */
 };
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfcrkpm.so")
-SOURCES = ["kernels.hip", "sepconv.hip", "fcrkpm.hip"]
+SOURCES = ["kernels.hip", "sepconv.hip", "regpass.hip", "fcrkpm.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -70,6 +70,7 @@ struct ProfKind {
     long launches = 0;
     double bytes = 0.0;
     int nrec = 0;
+    bool open = false;  // a begin event was recorded and awaits its end
     hipEvent_t ev[2 * kProfCap];
 };
 
@@ -102,6 +103,28 @@ struct ProfScope {
         ++k.nrec;
     }
 };
+
+// begin/end form of the sampler for launches made outside this file
+void prof_begin(Ctx& c, int kind, double bytes, hipStream_t st)
+{
+    if (!c.prof_on || c.capturing) return;
+    ProfKind& k = ((Prof*)c.prof)->k[kind];
+    ++k.launches;
+    k.bytes += bytes;
+    if (k.nrec < kProfCap) {
+        (void)hipEventRecord(k.ev[2 * k.nrec], st);
+        k.open = true;
+    }
+}
+void prof_end(Ctx& c, int kind, hipStream_t st)
+{
+    if (!c.prof_on || c.capturing) return;
+    ProfKind& k = ((Prof*)c.prof)->k[kind];
+    if (!k.open) return;
+    (void)hipEventRecord(k.ev[2 * k.nrec + 1], st);
+    ++k.nrec;
+    k.open = false;
+}
 
 template <typename T>
 T* dalloc(size_t count)
@@ -136,6 +159,7 @@ void release(Ctx& c)
         dfree(c.tw32[a]);
         dfree(c.spec64[a]);
         dfree(c.spec32[a]);
+        dfree(c.rtab32[a]);
     }
     dfree(c.work64);
     dfree(c.work32);
@@ -397,6 +421,47 @@ void part2(Ctx& c, const SepPlan& sp, cplx<T>* cur, cplx<T>* S1, cplx<T>* S2, Ti
     }
 }
 
+// The register-resident FP32 K product applies to 64^3 and 128^3 boxes with
+// the linear basis (the choice never depends on nrhs, so a batched product
+// equals the single ones bit for bit).
+bool use_reg_path(const Ctx& c, int /*nrhs*/)
+{
+    static int env = -1;
+    if (env < 0) {
+        const char* e = getenv("FCRKPM_REGPATH");
+        env = (e && *e == '0') ? 0 : 1;
+    }
+    return env == 1 && c.use_regpath && reg_path_ok(c);
+}
+
+void regprof_begin(const void* cv, int k, hipStream_t st)
+{
+    Ctx& c = *(Ctx*)cv;
+    static const int kinds[5] = {KD_P1_X, KD_P1_Y, KD_MID_K, KD_P2_Y, KD_P2_X};
+    // algorithmic bytes per node of each pass (FP32 real fields; masks 1 B)
+    static const double bytes[5] = {4 + 1 + 2 * 4, 2 * 4 + 3 * 4, 3 * 4 + 12 * 4 + 4 + 3 * 4,
+                                    3 * 4 + 2 * 4, 2 * 4 + 1 + 4};
+    prof_begin(c, kind_of<float>(kinds[k]), bytes[k] * (double)c.nn * c.prof_rhs, st);
+}
+void regprof_end(const void* cv, int k, hipStream_t st)
+{
+    Ctx& c = *(Ctx*)cv;
+    static const int kinds[5] = {KD_P1_X, KD_P1_Y, KD_MID_K, KD_P2_Y, KD_P2_X};
+    prof_end(c, kind_of<float>(kinds[k]), st);
+}
+
+void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, hipStream_t st)
+{
+    RegProf rp;
+    if (c.prof_on && !c.capturing) {
+        rp.c = &c;
+        rp.begin_fn = regprof_begin;
+        rp.end_fn = regprof_end;
+        c.prof_rhs = nrhs;
+    }
+    launch_reg_k(c, in, out, mask, nrhs, nullptr, nullptr, st, rp);
+}
+
 // One operator on nrhs consecutive fields, arithmetic precision T, field type
 // Tio (Alg 2, 3, 4); every pass covers all fields in one launch.
 template <typename T, typename Tio = T>
@@ -415,6 +480,12 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
         case FCRKPM_OP_K:
         case FCRKPM_OP_K_FULL: {
             const uint8_t* mk = (op == FCRKPM_OP_K) ? c.freem : c.chi;
+            if constexpr (std::is_same_v<T, float> && std::is_same_v<Tio, float>) {
+                if (use_reg_path(c, nrhs)) {
+                    reg_k(c, in, out, mk, nrhs, st);
+                    break;
+                }
+            }
             cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, nrhs, st);
             cplx<T>* dst = (cur == S1) ? S2 : S1;
             {
@@ -1241,6 +1312,19 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 }
             c.spec64[a] = dalloc<cplx<double>>(sp.size());
             c.spec32[a] = dalloc<cplx<float>>(spf.size());
+            {
+                // t_e is even (e even) or odd (e odd) in its offset, so its
+                // spectrum is real or imaginary: keep that part alone
+                std::vector<float> rt((size_t)ne * L);
+                for (int e = 0; e < ne; ++e)
+                    for (int kk = 0; kk < L; ++kk)
+                        rt[(size_t)e * L + kk] = (e & 1) ? (float)sp[(size_t)e * L + kk].y
+                                                         : (float)sp[(size_t)e * L + kk].x;
+                c.rtab32[a] = dalloc<float>(rt.size());
+                HIPCHK(hipMemcpyAsync(c.rtab32[a], rt.data(), sizeof(float) * rt.size(),
+                                      hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
             HIPCHK(hipMemcpyAsync(c.spec64[a], sp.data(), sizeof(cplx<double>) * sp.size(), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(c.spec32[a], spf.data(), sizeof(cplx<float>) * spf.size(), hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -1527,6 +1611,10 @@ extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int6
             case FCRKPM_OPT_GRAPHS:
                 if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_GRAPHS takes 0 or 1");
                 c.use_graphs = value == 1;
+                break;
+            case FCRKPM_OPT_REGPATH:
+                if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGPATH takes 0 or 1");
+                c.use_regpath = value == 1;
                 break;
             default:
                 fail(FCRKPM_ERR_ARG, "unknown option");

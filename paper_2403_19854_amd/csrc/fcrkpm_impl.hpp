@@ -84,6 +84,8 @@ struct Ctx {
     cplx<float>* tw32[3] = {};
     cplx<double>* spec64[3] = {};       // kernel spectra per axis, exponents 0..2n
     cplx<float>* spec32[3] = {};
+    float* rtab32[3] = {};              // per axis [2n+1][n]: Re (even e) or Im (odd e) of spec32
+    bool use_regpath = true;            // register-resident passes where they apply
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
     // and right-hand side (cap_work of them)
     cplx<double>* work64 = nullptr;
@@ -102,6 +104,7 @@ struct Ctx {
     int* dflag = nullptr;               // device int flags
     void* prof = nullptr;               // kernel-duration sampler (measurement only)
     bool prof_on = false;
+    int prof_rhs = 1;                   // right-hand sides of the launch being sampled
     bool use_graphs = true;             // replay CG blocks from captured graphs
     SepPlan basis_plan;                 // basis monomials (Alg 2-4)
     SepProg* dprog = nullptr;           // device copies of the pass programs
@@ -139,6 +142,27 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
                     const uint8_t* mask_out, const void* src, const T* b0, const T* ba,
                     const T* vol, double* dot_part, const void* dot_with, hipStream_t st,
                     const RhsBatch& rb = RhsBatch{});
+
+// Register-resident passes of the FP32 K product (regpass.hip) for 3D boxes
+// of 64^3 or 128^3 nodes and the linear basis.  `prof` brackets the five
+// launches (x, y, middle z, y, x) for the kernel-duration sampler.
+struct RegProf {
+    const void* c = nullptr;
+    void (*begin_fn)(const void*, int, hipStream_t) = nullptr;
+    void (*end_fn)(const void*, int, hipStream_t) = nullptr;
+    void begin(int k, hipStream_t st) const
+    {
+        if (begin_fn) begin_fn(c, k, st);
+    }
+    void end(int k, hipStream_t st) const
+    {
+        if (end_fn) end_fn(c, k, st);
+    }
+};
+bool reg_path_ok(const Ctx& c);
+int reg_path_blocks(const Ctx& c);
+void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
+                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof);
 
 // LDS bytes the passes of a plan need at the tile widths they will use
 size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes);

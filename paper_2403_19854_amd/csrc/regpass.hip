@@ -1,0 +1,508 @@
+// regpass.hip -- register-resident separable passes of the FP32 stiffness
+// product K d (Alg 2) on 3D boxes whose axes are 64 or 128 nodes long, for
+// the linear basis.
+//
+// A complex line packs two adjacent real lines of one field: the real part is
+// line w, the imaginary part line w+1.  Every 1D kernel array t_e is real
+// (Eq 77-78), so one complex convolution convolves both lines at once and no
+// spectral separation is needed; t_e is even or odd in its offset, so its
+// spectrum is real or imaginary and one float per frequency describes it.
+//
+// A complex line of L = 8 R points is owned by 8 lanes; lane t holds points
+// t + 8m (m < R) in registers.  A transform is a DFT-R in registers, a
+// twiddle, one transpose through LDS and DFT-8s in registers (four-step
+// FFT), so the data crosses LDS once per transform instead of once per
+// radix stage, and the spectral products, the inverse transforms and the
+// pointwise stage of the middle pass all act on registers.
+#include <hip/hip_runtime.h>
+
+#include "fcrkpm_impl.hpp"
+
+namespace fcrkpm {
+namespace {
+
+typedef cplx<float> cf;
+
+constexpr int kRT = 256;             // threads per workgroup
+constexpr int kGrp = 8;              // lanes per complex line
+constexpr int kGroups = kRT / kGrp;  // complex lines per workgroup
+constexpr int kRMaxE = 3;            // kernel exponents 0 .. 2n for n = 1
+
+// LDS stride of a group's transpose buffer: rows of 9 (8 points + pad); the
+// group stride is 8 mod 32 so the 8 groups of a wave spread over the banks
+template <int R>
+constexpr int xstride() { return R == 16 ? 168 : 72; }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// a * e^{-DIR 2 pi i j / 16}, j a compile-time constant after unrolling
+template <int DIR>
+__device__ __forceinline__ cf mul_w16(cf a, int j)
+{
+    constexpr float C[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                             0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+    const float c = C[j & 15], s = C[(j + 12) & 15];  // sin(x) = cos(x - pi/2)
+    const float ds = DIR > 0 ? s : -s;
+    return cf{a.x * c + a.y * ds, a.y * c - a.x * ds};
+}
+
+// in-place DFT-16 in natural order, as 4 x 4 with internal twiddles
+template <int DIR>
+__device__ __forceinline__ void dft16(cf* v)
+{
+    cf a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+        dft4<float, DIR>(a[n2]);
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1)
+            if (n2 > 0) a[n2][k1] = mul_w16<DIR>(a[n2][k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cf b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<float, DIR>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dftR_reg(cf* v)
+{
+    if constexpr (R == 16) dft16<DIR>(v);
+    else dft8<float, DIR>(v);
+}
+
+template <int DIR>
+__device__ __forceinline__ cf twid(const cf* tw, int j)
+{
+    const cf w = tw[j];
+    return DIR > 0 ? w : cf{w.x, -w.y};
+}
+
+// Forward transform of the group's line.  In: v[m] = x[t + 8m].  Out:
+// v[8j + k2] = X[t + 8j + R k2] (j < R/8, k2 < 8).
+template <int R>
+__device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
+{
+    constexpr int KPL = R / 8;
+    dftR_reg<R, +1>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], twid<+1>(tw, t * k1));
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) xb[k1 * 9 + t] = v[k1];
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < KPL; ++j)
+#pragma unroll
+        for (int n = 0; n < 8; ++n) v[8 * j + n] = xb[(t + 8 * j) * 9 + n];
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) dft8<float, +1>(v + 8 * j);
+}
+
+// Unnormalised inverse: the layout of fwd's output in, x[t + 8m] in v[m] out.
+template <int R>
+__device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const cf* tw)
+{
+    constexpr int KPL = R / 8;
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+        dft8<float, -1>(v + 8 * j);
+#pragma unroll
+        for (int n1 = 1; n1 < 8; ++n1) v[8 * j + n1] = cmul(v[8 * j + n1], twid<-1>(tw, n1 * (t + 8 * j)));
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) xb[(t + 8 * j) * 9 + n1] = v[8 * j + n1];
+    }
+    wave_sync();
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) v[k1] = xb[k1 * 9 + t];
+    wave_sync();
+    dftR_reg<R, -1>(v);
+}
+
+// Y <- sum over the terms of output o of 2 coef T_e o Z_in (spectra in fwd's
+// layout).  The factor 2 undoes the 1/2 that the pair-separating passes keep
+// in the coefficients; the 1/L of the inverse transform stays in coef.
+template <int R, int NIN>
+__device__ __forceinline__ void combine(const SepProg& pr, int o, const cf (&Z)[NIN][R], cf (&Y)[R],
+                                        const float* trl, int t)
+{
+    constexpr int L = 8 * R;
+#pragma unroll
+    for (int i = 0; i < R; ++i) Y[i] = cf{0.0f, 0.0f};
+    const int t0 = pr.ostart[o], t1 = pr.ostart[o + 1];
+    for (int tt = t0; tt < t1; ++tt) {
+        const SepTerm tm = pr.t[tt];
+        const float c2 = float(2.0 * tm.coef);
+        const float* T = trl + tm.e * L;
+        const bool odd = tm.e & 1;
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) {
+            if (f != tm.in) continue;
+#pragma unroll
+            for (int j = 0; j < R / 8; ++j)
+#pragma unroll
+                for (int k2 = 0; k2 < 8; ++k2) {
+                    const int i = 8 * j + k2;
+                    const float s = c2 * T[t + 8 * j + R * k2];
+                    const cf z = Z[f][i];
+                    if (odd) Y[i] = cf{Y[i].x - s * z.y, Y[i].y + s * z.x};
+                    else Y[i] = cf{Y[i].x + s * z.x, Y[i].y + s * z.y};
+                }
+        }
+    }
+}
+
+struct RArgs {
+    const float* in;          // real fields fstride apart (or the field masked by mask_in)
+    const uint8_t* mask_in;
+    float* out;
+    const uint8_t* mask_out;  // masked single-field store (and dot), else NULL
+    long fstride;             // floats between fields
+    long in_rb, out_rb;       // floats between right-hand sides (blockIdx.y)
+    long st;                  // element stride of the axis; 1 for x
+    const SepProg* pr;        // pass program (the middle pass: part 1)
+    const SepProg* pr2;       // middle pass: part 2
+    const float* tr;          // [ne][L] real or imaginary part of each kernel spectrum
+    const cf* tw;             // [L] e^{-2 pi i j / L}
+    int ne;
+    const float* ba;          // middle pass: b^a [3][4][nn]
+    const float* vol;         // middle pass: V [nn]
+    long nn;
+    double* dot_part;         // masked store: per-workgroup partial of out . dot_with
+    const float* dot_with;
+};
+
+// Position of the workgroup's 64 real lines: for a strided axis the float
+// index of line l0 at point 0 (lines l0 .. l0+63 are adjacent in memory),
+// for x the index of line l0's first point.
+template <int L, bool CONTIG>
+__device__ __forceinline__ long tile_base(long tile, long st)
+{
+    const long l0 = tile * (2 * kGroups);
+    if (CONTIG) return l0 * L;
+    const long lo = l0 % st, hi = l0 / st;
+    return lo + hi * st * L;
+}
+
+// complex element m of group g: lines (2g, 2g+1) of the tile at point t + 8m
+template <int L, bool CONTIG>
+__device__ __forceinline__ long elem_index(long base, int g, int t, int m, long st)
+{
+    const int i = t + 8 * m;
+    if (CONTIG) return base + (long)(2 * g) * L + i;
+    return base + 2 * g + (long)i * st;
+}
+
+template <int L, bool CONTIG>
+__device__ __forceinline__ cf load_pair(const float* p, long idx)
+{
+    if (CONTIG) return cf{p[idx], p[idx + L]};
+    const float2 v = *reinterpret_cast<const float2*>(p + idx);
+    return cf{v.x, v.y};
+}
+
+template <int L, bool CONTIG>
+__device__ __forceinline__ void store_pair(float* p, long idx, cf v)
+{
+    if (CONTIG) {
+        p[idx] = v.x;
+        p[idx + L] = v.y;
+    } else {
+        *reinterpret_cast<float2*>(p + idx) = float2{v.x, v.y};
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRT / 64; ++i) r += sh[i];
+    return r;
+}
+
+__device__ __forceinline__ long xcd_tile(long b, long nblocks)
+{
+    if (nblocks % 8 != 0) return b;
+    return (b & 7) * (nblocks >> 3) + (b >> 3);
+}
+
+template <int R>
+__device__ __forceinline__ void stage_tables(const RArgs& a, cf* tw, float* trl)
+{
+    constexpr int L = 8 * R;
+    for (int e = threadIdx.x; e < L; e += kRT) tw[e] = a.tw[e];
+    for (int e = threadIdx.x; e < a.ne * L; e += kRT) trl[e] = a.tr[e];
+    __syncthreads();
+}
+
+// One separable pass: NIN real fields -> NOUT real fields along the axis.
+// LMASK: the single input is masked by mask_in.  SMASK: the single output is
+// masked by mask_out and, if dot_part is set, dotted with dot_with.
+template <int R, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT>
+__global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
+{
+    constexpr int L = 8 * R;
+    __shared__ cf tw[L];
+    __shared__ float trl[kRMaxE * L];
+    __shared__ cf xbuf[kGroups * xstride<R>()];
+    __shared__ double sh[kRT / 64];
+    const int tid = threadIdx.x, g = tid >> 3, t = tid & 7;
+    const long rhs = blockIdx.y;
+    const float* in = a.in + rhs * a.in_rb;
+    float* out = a.out + rhs * a.out_rb;
+    const long base = tile_base<L, CONTIG>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    stage_tables<R>(a, tw, trl);
+    cf* xb = xbuf + g * xstride<R>();
+
+    cf Z[NIN][R];
+#pragma unroll
+    for (int f = 0; f < NIN; ++f)
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const long idx = elem_index<L, CONTIG>(base, g, t, m, a.st);
+            if constexpr (LMASK) {
+                const cf v = load_pair<L, CONTIG>(in, idx);
+                const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
+                Z[f][m] = cf{m0 ? v.x : 0.0f, m1 ? v.y : 0.0f};
+            } else {
+                Z[f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
+            }
+        }
+#pragma unroll
+    for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
+    const SepProg& pr = *a.pr;
+    double dacc = 0.0;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        cf Y[R];
+        combine<R, NIN>(pr, o, Z, Y, trl, t);
+        inv<R>(Y, t, xb, tw);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const long idx = elem_index<L, CONTIG>(base, g, t, m, a.st);
+            if constexpr (SMASK) {
+                const long idx1 = idx + (CONTIG ? L : 1);
+                const float v0 = a.mask_out[idx] ? Y[m].x : 0.0f;
+                const float v1 = a.mask_out[idx1] ? Y[m].y : 0.0f;
+                store_pair<L, CONTIG>(out, idx, cf{v0, v1});
+                if (a.dot_part) {
+                    const float* dw = a.dot_with + rhs * a.out_rb;
+                    dacc += (double)v0 * (double)dw[idx] + (double)v1 * (double)dw[idx1];
+                }
+            } else {
+                store_pair<L, CONTIG>(out + o * a.fstride, idx, Y[m]);
+            }
+        }
+    }
+    if constexpr (SMASK) {
+        if (a.dot_part) {
+            const double s = block_sum(dacc, sh);
+            if (tid == 0) a.dot_part[rhs * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// Middle pass of K d along the last axis (strided), linear basis in 3D
+// (s = 4): the part-1 convolutions give D_q, the pointwise stage forms
+// A^a = sum_q b^a_q D_q and E_p = V sum_a b^a_p A^a at every node (Eq 90-91,
+// Alg 2), and the part-2 convolutions of E_p follow -- all in registers.
+template <int R, int NIN, int NOUT>
+__global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
+{
+    constexpr int L = 8 * R;
+    constexpr int S = 4;
+    __shared__ cf tw[L];
+    __shared__ float trl[kRMaxE * L];
+    __shared__ cf xbuf[kGroups * xstride<R>()];
+    const int tid = threadIdx.x, g = tid >> 3, t = tid & 7;
+    const long rhs = blockIdx.y;
+    const float* in = a.in + rhs * a.in_rb;
+    float* out = a.out + rhs * a.out_rb;
+    const long base = tile_base<L, false>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    stage_tables<R>(a, tw, trl);
+    cf* xb = xbuf + g * xstride<R>();
+
+    cf D[S][R];
+    {
+        cf Z[NIN][R];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f)
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                Z[f][m] = load_pair<L, false>(in + f * a.fstride,
+                                              elem_index<L, false>(base, g, t, m, a.st));
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
+        const SepProg& pr = *a.pr;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            combine<R, NIN>(pr, q, Z, D[q], trl, t);
+            inv<R>(D[q], t, xb, tw);
+        }
+    }
+    // pointwise stage on both lines of every complex element
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const long idx = elem_index<L, false>(base, g, t, m, a.st);
+        float2 b[3][S];
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                b[al][q] = *reinterpret_cast<const float2*>(a.ba + (al * S + q) * a.nn + idx);
+        const float2 v = *reinterpret_cast<const float2*>(a.vol + idx);
+        float A0[3], A1[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                s0 += b[al][q].x * D[q][m].x;
+                s1 += b[al][q].y * D[q][m].y;
+            }
+            A0[al] = s0;
+            A1[al] = s1;
+        }
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            float e0 = 0.0f, e1 = 0.0f;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                e0 += b[al][p].x * A0[al];
+                e1 += b[al][p].y * A1[al];
+            }
+            D[p][m] = cf{v.x * e0, v.y * e1};
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < S; ++p) fwd<R>(D[p], t, xb, tw);
+    const SepProg& pr2 = *a.pr2;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        cf Y[R];
+        combine<R, S>(pr2, o, D, Y, trl, t);
+        inv<R>(Y, t, xb, tw);
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            store_pair<L, false>(out + o * a.fstride, elem_index<L, false>(base, g, t, m, a.st), Y[m]);
+    }
+}
+
+template <int R>
+void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
+           double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
+{
+    constexpr int L = 8 * R;
+    const SepPlan& sp = c.basis_plan;
+    const long nn = c.nn;
+    const long slot_rb = 2L * sp.maxpairs * nn;  // floats between rhs in a workspace slot
+    float* S1 = reinterpret_cast<float*>(c.work32);
+    float* S2 = S1 + slot_rb * c.cap_work;
+    const unsigned nblk = (unsigned)(nn / L / (2 * kGroups));
+    const dim3 grid(nblk, (unsigned)nrhs), block(kRT);
+    auto args = [&](int axis, const float* i, long irb, float* o, long orb) {
+        RArgs a{};
+        a.in = i;
+        a.in_rb = irb;
+        a.out = o;
+        a.out_rb = orb;
+        a.fstride = nn;
+        a.st = axis == 0 ? 1 : (axis == 1 ? (long)c.n[0] : (long)c.n[0] * c.n[1]);
+        a.tr = c.rtab32[axis];
+        a.tw = c.tw32[axis];
+        a.ne = 2 * c.degree + 1;
+        a.nn = nn;
+        return a;
+    };
+    // x: u (masked) -> X
+    {
+        RArgs a = args(0, in, nn, S1, slot_rb);
+        a.mask_in = mask;
+        a.pr = sp.d1[0];
+        prof.begin(0, st);
+        hipLaunchKernelGGL((k_rpass<R, true, true, false, 1, 2>), grid, block, 0, st, a);
+        prof.end(0, st);
+    }
+    // y: X -> XY
+    {
+        RArgs a = args(1, S1, slot_rb, S2, slot_rb);
+        a.pr = sp.d1[1];
+        prof.begin(1, st);
+        hipLaunchKernelGGL((k_rpass<R, false, false, false, 2, 3>), grid, block, 0, st, a);
+        prof.end(1, st);
+    }
+    // z: XY -> D -> E -> part-2 XY
+    {
+        RArgs a = args(2, S2, slot_rb, S1, slot_rb);
+        a.pr = sp.d1[2];
+        a.pr2 = sp.d2[2];
+        a.ba = c.ba_32;
+        a.vol = c.vol32;
+        prof.begin(2, st);
+        hipLaunchKernelGGL((k_rmid<R, 3, 3>), grid, block, 0, st, a);
+        prof.end(2, st);
+    }
+    // y: XY -> X
+    {
+        RArgs a = args(1, S1, slot_rb, S2, slot_rb);
+        a.pr = sp.d2[1];
+        prof.begin(3, st);
+        hipLaunchKernelGGL((k_rpass<R, false, false, false, 3, 2>), grid, block, 0, st, a);
+        prof.end(3, st);
+    }
+    // x: X -> f (masked), with the optional dot partials
+    {
+        RArgs a = args(0, S2, slot_rb, out, nn);
+        a.mask_out = mask;
+        a.pr = sp.d2[0];
+        a.dot_part = dot_part;
+        a.dot_with = dot_with;
+        prof.begin(4, st);
+        hipLaunchKernelGGL((k_rpass<R, true, false, true, 2, 1>), grid, block, 0, st, a);
+        prof.end(4, st);
+    }
+}
+
+}  // namespace
+
+bool reg_path_ok(const Ctx& c)
+{
+    if (c.dim != 3 || c.degree != 1 || c.naxes != 3 || c.s != 4) return false;
+    const SepPlan& sp = c.basis_plan;
+    if (sp.size[0] != 2 || sp.size[1] != 3 || sp.size[2] != 4) return false;
+    for (int j = 0; j < 3; ++j) {
+        if (sp.p1[j].nin != (j == 0 ? 1 : sp.size[j - 1]) || sp.p1[j].nout != sp.size[j]) return false;
+        if (sp.p2[j].nin != sp.size[j] || sp.p2[j].nout != (j == 0 ? 1 : sp.size[j - 1])) return false;
+    }
+    const int L = c.n[0];
+    if (L != 64 && L != 128) return false;
+    return c.n[1] == L && c.n[2] == L;
+}
+
+int reg_path_blocks(const Ctx& c) { return (int)(c.nn / c.n[0] / (2 * kGroups)); }
+
+void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
+                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
+{
+    if (c.n[0] == 128) run_k<16>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else run_k<8>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+}
+
+}  // namespace fcrkpm

@@ -36,6 +36,7 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option")
 OPT_GRAPHS = 1
+OPT_REGPATH = 2
 
 
 class Grid(C.Structure):
@@ -257,6 +258,10 @@ class Problem:
                                                   float(tol), int(maxit), infos,
                                                   _stream_ptr(stream)))
         return g, _infos_dict(infos, OK)
+
+    def set_regpath(self, on: bool):
+        """Use the register-resident FP32 K passes where they apply (default)."""
+        self._check(load_library().fcrkpm_set_option(self._h, OPT_REGPATH, 1 if on else 0))
 
     def set_graphs(self, on: bool):
         """Replay CG blocks from captured HIP graphs (default) or launch directly."""

@@ -66,6 +66,7 @@ CASES = {
     "2d_linear_40x40": lambda: W.cube(2, 40, 2.5, 1, source="eq101", lo=-1, hi=1),
     "2d_quadratic_48": lambda: W.cube(2, 48, 2.5, 2),
     "3d_linear_24": lambda: W.cube(3, 24, 2.5, 1),
+    "3d_linear_64": lambda: W.cube(3, 64, 2.5, 1),
     "3d_linear_support2_20": lambda: W.cube(3, 20, 2.0, 1),
     "3d_paper_eq106_16": lambda: W.paper_shape(16),
     "sphere_quadratic_32": lambda: W.sphere(32, 0.4, 3.0, 2, seed=3),
@@ -359,3 +360,28 @@ def test_full_size_refined_solve_c5():
     # manufactured-solution error of u^h is small (support 2.5h: first order)
     err = rel_l2(to_np(uh32), p.u_exact, m)
     assert err <= 5e-3
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_register_path_matches_lds_path_and_oracle(n):
+    """The register-resident FP32 K passes (64^3 and 128^3 boxes, linear
+    basis) against the LDS-tiled FP32 passes and the FP64 oracle."""
+    p = W.cube(3, n, 2.5, 1)
+    print(f"\n[register path {n}^3]", flush=True)
+    g = lib_problem(p)
+    x = rand_field(p, 31)
+    xt = torch.from_numpy(x).to(DEV).float()
+    reg = to_np(g.apply("K", xt)).astype(np.float64)
+    g.set_regpath(False)
+    lds = to_np(g.apply("K", xt)).astype(np.float64)
+    g.set_regpath(True)
+    scale = np.abs(lds).max()
+    d = np.abs(reg - lds).max() / scale
+    print(f"  register vs LDS path rel-max {d:.2e}")
+    assert d <= 2e-5
+    assert np.all(reg[p.free == 0] == 0.0)
+    o = orc(p)
+    idx = _sampled(p, 3, 64)
+    ref = o.apply_k_at(np.where(p.free > 0, x, 0.0), idx)
+    got = np.where(p.free > 0, reg, 0.0).reshape(-1)[idx]
+    assert np.abs(got - np.where(p.free.reshape(-1)[idx] > 0, ref, 0.0)).max() <= 2e-5 * scale
