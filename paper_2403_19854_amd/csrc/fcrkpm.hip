@@ -168,6 +168,8 @@ void release(Ctx& c)
     dfree(c.partial);
     dfree(c.scal);
     dfree(c.act);
+    dfree(c.nbits);
+    dfree(c.nctab);
     dfree(c.dflag);
     if (c.aux) (void)hipStreamDestroy(c.aux);
     c.aux = nullptr;
@@ -450,8 +452,10 @@ void regprof_end(const void* cv, int k, hipStream_t st)
     prof_end(c, kind_of<float>(kinds[k]), st);
 }
 
-void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, hipStream_t st)
+void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, hipStream_t st,
+           double* dot_part = nullptr, const float* dot_with = nullptr)
 {
+    ensure_work(c, nrhs);
     RegProf rp;
     if (c.prof_on && !c.capturing) {
         rp.c = &c;
@@ -459,7 +463,7 @@ void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, h
         rp.end_fn = regprof_end;
         c.prof_rhs = nrhs;
     }
-    launch_reg_k(c, in, out, mask, nrhs, nullptr, nullptr, st, rp);
+    launch_reg_k(c, in, out, mask, nrhs, dot_part, dot_with, st, rp);
 }
 
 // One operator on nrhs consecutive fields, arithmetic precision T, field type
@@ -603,9 +607,21 @@ void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStrea
 {
     double* pq_part = c.partial;
     double* rr_part = c.partial + (size_t)kRedBlocks * c.cap_rhs;
-    apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
-    launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
-    launch_cg_xr<T>(x, r, p, q, c.nn, nrhs, pq_part, c.scal, parity, rr_part, c.act, st);
+    int npq = red_blocks(c.nn);
+    if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>) {
+        if (use_reg_path(c, nrhs) && reg_path_blocks(c) <= kRedBlocks) {
+            // the last pass of the product also leaves the p.q partials
+            reg_k(c, p, q, c.freem, nrhs, st, pq_part, p);
+            npq = reg_path_blocks(c);
+        } else {
+            apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
+            launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
+        }
+    } else {
+        apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
+        launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
+    }
+    launch_cg_xr<T>(x, r, p, q, c.nn, nrhs, pq_part, npq, c.scal, parity, rr_part, c.act, st);
     launch_cg_p<T>(p, r, c.nn, nrhs, rr_part, c.scal, parity, c.act, st);
 }
 
@@ -1396,6 +1412,37 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
             dfree(G);
             if (hflag[1] != 0x7fffffff && !getenv("FCRKPM_DUMP"))
                 fail(FCRKPM_ERR_SINGULAR, "moment matrix not positive definite at node " + std::to_string(hflag[1]));
+        }
+
+        // node classes of the register-resident K passes: interior nodes share
+        // one set of coefficients, so their pointwise stage reads no arrays
+        if (reg_path_ok(c) && c.dim * c.s <= kMaxNodeConst) {
+            int big = 0x7fffffff, ref = 0;
+            HIPCHK(hipMemcpyAsync(c.dflag + 3, &big, sizeof(int), hipMemcpyHostToDevice, st));
+            launch_first_interior(c, c.dflag + 3, st);
+            HIPCHK(hipMemcpyAsync(&ref, c.dflag + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (ref != 0x7fffffff) {
+                NodeConst nc = {};
+                const int nb = c.dim * c.s;
+                for (int q = 0; q < nb; ++q)
+                    HIPCHK(hipMemcpy(&nc.b[q], c.ba_32 + (size_t)q * nn + ref, sizeof(float),
+                                     hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(&nc.v, c.vol32 + ref, sizeof(float), hipMemcpyDeviceToHost));
+                for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabsf(nc.b[q]));
+                c.nconst = nc;
+                uint8_t* cls = dalloc<uint8_t>(nn);
+                launch_node_class(c, nc, cls, st);
+                c.nbits = dalloc<uint32_t>(reg_bits_words(c));
+                launch_reg_bits(c, cls, c.nbits, st);
+                float tab[2 * kMaxNodeConst + 2];
+                for (int q = 0; q < nb; ++q) tab[2 * q] = tab[2 * q + 1] = nc.b[q];
+                tab[2 * nb] = tab[2 * nb + 1] = nc.v;
+                c.nctab = dalloc<float>(2 * nb + 2);
+                HIPCHK(hipMemcpy(c.nctab, tab, sizeof(float) * (2 * nb + 2), hipMemcpyHostToDevice));
+                HIPCHK(hipStreamSynchronize(st));
+                dfree(cls);
+            }
         }
 
         // workspace and solver buffers for one right-hand side; both grow on demand

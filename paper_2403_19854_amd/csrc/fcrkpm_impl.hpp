@@ -53,6 +53,14 @@ struct SepPlan {
     int maxpairs = 0;             // largest pair count of P_0 .. P_{k-2}
 };
 
+// Coefficients shared by the interior nodes (class 1) of the FP32 K product.
+constexpr int kMaxNodeConst = 12;  // dim * s for the linear basis in 3D
+struct NodeConst {
+    float b[kMaxNodeConst];        // b^a_q, a-major
+    float v;                       // V
+    float bmax;                    // max |b|
+};
+
 struct Ctx {
     int dim = 0;
     int n[3] = {1, 1, 1};
@@ -86,6 +94,9 @@ struct Ctx {
     cplx<float>* spec32[3] = {};
     float* rtab32[3] = {};              // per axis [2n+1][n]: Re (even e) or Im (odd e) of spec32
     bool use_regpath = true;            // register-resident passes where they apply
+    uint32_t* nbits = nullptr;          // register path: interior bits per middle-pass lane
+    NodeConst nconst = {};              // values of the interior nodes
+    float* nctab = nullptr;             // the same on the device, each value twice (a float2)
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
     // and right-hand side (cap_work of them)
     cplx<double>* work64 = nullptr;
@@ -161,6 +172,8 @@ struct RegProf {
 };
 bool reg_path_ok(const Ctx& c);
 int reg_path_blocks(const Ctx& c);
+long reg_bits_words(const Ctx& c);
+void launch_reg_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st);
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof);
 
@@ -172,6 +185,8 @@ void launch_free_mask(const uint8_t* chi, const uint8_t* dir, uint8_t* freem, in
                       hipStream_t st);
 void launch_axis_extent(const Ctx& c, const uint8_t* chi, int* occ, hipStream_t st);
 void launch_moment_solve(const Ctx& c, const cplx<double>* G, int* bad, hipStream_t st);
+void launch_first_interior(const Ctx& c, int* ref, hipStream_t st);
+void launch_node_class(const Ctx& c, const NodeConst& ref, uint8_t* cls, hipStream_t st);
 void launch_vol(const uint8_t* chi, const double* vol_in, double hv, double* vol64, float* vol32,
                 long nn, hipStream_t st);
 void launch_mask_to_double(const uint8_t* m, double* out, long nn, hipStream_t st);
@@ -187,7 +202,8 @@ void launch_dot_partial(const T* a, const T* b, long n, int nrhs, double* part, 
 void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStream_t st);
 template <typename T>
 void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, int nrhs, const double* pq_part,
-                  double* scal, int parity, double* rr_part, const int* act, hipStream_t st);
+                  int npq, double* scal, int parity, double* rr_part, const int* act,
+                  hipStream_t st);
 template <typename T>
 void launch_cg_p(T* p, const T* r, long n, int nrhs, const double* rr_part, double* scal,
                  int parity, const int* act, hipStream_t st);

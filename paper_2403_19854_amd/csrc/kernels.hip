@@ -70,6 +70,66 @@ void launch_axis_extent(const Ctx& c, const uint8_t* chi, int* occ, hipStream_t 
                        c.n[1], c.n[2], occ, c.nn);
 }
 
+// Node classes for the pointwise stage of the FP32 K product: 0 outside the
+// domain, 1 a node whose whole support neighbourhood (periodic, as the
+// convolutions see it) lies in the domain and whose b^a and V equal the
+// reference interior values to FP32 precision, 2 any other domain node.
+__device__ __forceinline__ bool full_support(const uint8_t* __restrict__ chi, long I, int n0, int n1,
+                                             int n2, int m0, int m1, int m2)
+{
+    const int i0 = (int)(I % n0);
+    const long r = I / n0;
+    const int i1 = (int)(r % n1), i2 = (int)(r / n1);
+    for (int o2 = -m2; o2 <= m2; ++o2) {
+        const int j2 = (i2 + o2 + n2) % n2;
+        for (int o1 = -m1; o1 <= m1; ++o1) {
+            const int j1 = (i1 + o1 + n1) % n1;
+            const long row = ((long)j2 * n1 + j1) * n0;
+            for (int o0 = -m0; o0 <= m0; ++o0)
+                if (!chi[row + (i0 + o0 + n0) % n0]) return false;
+        }
+    }
+    return true;
+}
+
+__global__ void k_first_interior(const uint8_t* __restrict__ chi, int n0, int n1, int n2, int m0,
+                                 int m1, int m2, long nn, int* ref)
+{
+    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
+         I += (long)gridDim.x * blockDim.x)
+        if (chi[I] && full_support(chi, I, n0, n1, n2, m0, m1, m2)) atomicMin(ref, (int)I);
+}
+
+void launch_first_interior(const Ctx& c, int* ref, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_first_interior, dim3(ew_blocks(c.nn)), dim3(256), 0, st, c.chi, c.n[0],
+                       c.n[1], c.n[2], c.m[0], c.m[1], c.m[2], c.nn, ref);
+}
+
+__global__ void k_node_class(const uint8_t* __restrict__ chi, const float* __restrict__ ba,
+                             const float* __restrict__ vol, int nb, NodeConst ref, int n0, int n1,
+                             int n2, int m0, int m1, int m2, long nn, uint8_t* __restrict__ cls)
+{
+    for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
+         I += (long)gridDim.x * blockDim.x) {
+        uint8_t k = 0;
+        if (chi[I]) {
+            bool same = vol[I] == ref.v && full_support(chi, I, n0, n1, n2, m0, m1, m2);
+            for (int q = 0; same && q < nb; ++q)
+                same = fabsf(ba[(long)q * nn + I] - ref.b[q]) <= 1e-6f * ref.bmax;
+            k = same ? 1 : 2;
+        }
+        cls[I] = k;
+    }
+}
+
+void launch_node_class(const Ctx& c, const NodeConst& ref, uint8_t* cls, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_node_class, dim3(ew_blocks(c.nn)), dim3(256), 0, st, c.chi, c.ba_32,
+                       c.vol32, c.dim * c.s, ref, c.n[0], c.n[1], c.n[2], c.m[0], c.m[1], c.m[2],
+                       c.nn, cls);
+}
+
 __global__ void k_vol(const uint8_t* __restrict__ chi, const double* __restrict__ vin, double hv,
                       double* __restrict__ v64, float* __restrict__ v32, long nn)
 {
@@ -307,11 +367,51 @@ void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStre
 // scalars of one right-hand side: [0], [1] = r.r (double-buffered by
 // parity), [3] = breakdown flag.  Right-hand sides with act[j] == 0 are
 // frozen: x, r, p and their scalars stay as they are.
+// Four consecutive elements per thread and step: FP32 vectors move as float4
+// when the field length allows it (n % 4 == 0, fields then stay 16-byte
+// aligned), otherwise one element at a time.
+template <typename T>
+struct Vec4 {
+    T v[4];
+};
+template <typename T>
+__device__ __forceinline__ Vec4<T> ld4(const T* p)
+{
+    Vec4<T> o;
+    if constexpr (sizeof(T) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(p);
+        o.v[0] = f.x;
+        o.v[1] = f.y;
+        o.v[2] = f.z;
+        o.v[3] = f.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        o.v[0] = a.x;
+        o.v[1] = a.y;
+        o.v[2] = b.x;
+        o.v[3] = b.y;
+    }
+    return o;
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const Vec4<T>& o)
+{
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = float4{o.v[0], o.v[1], o.v[2], o.v[3]};
+    } else {
+        *reinterpret_cast<double2*>(p) = double2{o.v[0], o.v[1]};
+        *reinterpret_cast<double2*>(p + 2) = double2{o.v[2], o.v[3]};
+    }
+}
+
+// npq: the number of p.q partials of each right-hand side (written by
+// k_dot_partial, or by the last pass of the K product)
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __restrict__ r,
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ q, long n,
-                                                       const double* __restrict__ pq_part,
+                                                       const double* __restrict__ pq_part, int npq,
                                                        double* scal, int parity,
                                                        double* __restrict__ rr_part,
                                                        const int* __restrict__ act)
@@ -325,19 +425,35 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __r
     p += off;
     q += off;
     scal += j * kScal;
-    const double pq = sum_partials(pq_part + (long)j * kRedBlocks, gridDim.x, sh);
+    const double pq = sum_partials(pq_part + (long)j * kRedBlocks, npq, sh);
     const double rr = scal[parity];
     const bool good = pq > 0.0 && rr > 0.0;
     const T alpha = good ? T(rr / pq) : T(0);
     if (!good && blockIdx.x == 0 && threadIdx.x == 0 && rr > 0.0) scal[3] = 1.0;
     double acc = 0.0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        T xi = x[i] + alpha * p[i];
-        T ri = r[i] - alpha * q[i];
-        x[i] = xi;
-        r[i] = ri;
-        acc += (double)ri * (double)ri;
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long first = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (n % 4 == 0) {
+        for (long i = 4 * first; i < n; i += 4 * stride) {
+            Vec4<T> xv = ld4(x + i), rv = ld4(r + i);
+            const Vec4<T> pv = ld4(p + i), qv = ld4(q + i);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv.v[u] = xv.v[u] + alpha * pv.v[u];
+                rv.v[u] = rv.v[u] - alpha * qv.v[u];
+                acc += (double)rv.v[u] * (double)rv.v[u];
+            }
+            st4(x + i, xv);
+            st4(r + i, rv);
+        }
+    } else {
+        for (long i = first; i < n; i += stride) {
+            T xi = x[i] + alpha * p[i];
+            T ri = r[i] - alpha * q[i];
+            x[i] = xi;
+            r[i] = ri;
+            acc += (double)ri * (double)ri;
+        }
     }
     double s = block_sum(acc, sh);
     if (threadIdx.x == 0) rr_part[(long)j * kRedBlocks + blockIdx.x] = s;
@@ -345,10 +461,11 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __r
 
 template <typename T>
 void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, int nrhs, const double* pq_part,
-                  double* scal, int parity, double* rr_part, const int* act, hipStream_t st)
+                  int npq, double* scal, int parity, double* rr_part, const int* act,
+                  hipStream_t st)
 {
     hipLaunchKernelGGL((k_cg_xr<T>), dim3(red_blocks(n), nrhs), dim3(kRedThreads), 0, st, x, r, p,
-                       q, n, pq_part, scal, parity, rr_part, act);
+                       q, n, pq_part, npq, scal, parity, rr_part, act);
 }
 
 template <typename T>
@@ -366,9 +483,19 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_p(T* __restrict__ p, const T
     const double rr_new = sum_partials(rr_part + (long)j * kRedBlocks, gridDim.x, sh);
     const double rr_old = scal[parity];
     const T beta = rr_old > 0.0 ? T(rr_new / rr_old) : T(0);
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * p[i];
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long first = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (n % 4 == 0) {
+        for (long i = 4 * first; i < n; i += 4 * stride) {
+            const Vec4<T> rv = ld4(r + i);
+            Vec4<T> pv = ld4(p + i);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pv.v[u] = rv.v[u] + beta * pv.v[u];
+            st4(p + i, pv);
+        }
+    } else {
+        for (long i = first; i < n; i += stride) p[i] = r[i] + beta * p[i];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[1 - parity] = rr_new;
 }
 
@@ -385,9 +512,11 @@ template void launch_dot_partial<double>(const double*, const double*, long, int
 template void launch_dot_partial<float>(const float*, const float*, long, int, double*,
                                         const int*, hipStream_t);
 template void launch_cg_xr<double>(double*, double*, const double*, const double*, long, int,
-                                   const double*, double*, int, double*, const int*, hipStream_t);
+                                   const double*, int, double*, int, double*, const int*,
+                                   hipStream_t);
 template void launch_cg_xr<float>(float*, float*, const float*, const float*, long, int,
-                                  const double*, double*, int, double*, const int*, hipStream_t);
+                                  const double*, int, double*, int, double*, const int*,
+                                  hipStream_t);
 template void launch_cg_p<double>(double*, const double*, long, int, const double*, double*, int,
                                   const int*, hipStream_t);
 template void launch_cg_p<float>(float*, const float*, long, int, const double*, double*, int,

@@ -182,6 +182,9 @@ struct RArgs {
     long nn;
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
     const float* dot_with;
+    const uint32_t* nbits;    // middle pass: per lane, bit 2m+c set if node c of element m
+                              // takes the interior values (NULL: every node loads)
+    const float* ctab;        // middle pass: interior b^a_q and V, each stored twice (26 floats)
 };
 
 // Position of the workgroup's 64 real lines: for a strided axis the float
@@ -243,14 +246,44 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks)
     return (b & 7) * (nblocks >> 3) + (b >> 3);
 }
 
+// The twiddle and spectrum tables of the axis: each thread loads its share
+// into registers (fetch) and writes it to LDS later (put), so the loads of
+// the tables and of the input lines are in flight together.
 template <int R>
-__device__ __forceinline__ void stage_tables(const RArgs& a, cf* tw, float* trl)
-{
-    constexpr int L = 8 * R;
-    for (int e = threadIdx.x; e < L; e += kRT) tw[e] = a.tw[e];
-    for (int e = threadIdx.x; e < a.ne * L; e += kRT) trl[e] = a.tr[e];
-    __syncthreads();
-}
+struct Tables {
+    static constexpr int L = 8 * R;
+    static constexpr int NT = (L + kRT - 1) / kRT;             // twiddles per thread
+    static constexpr int NS = (kRMaxE * L + kRT - 1) / kRT;    // spectrum values per thread
+    cf w[NT];
+    float s[NS];
+    __device__ __forceinline__ void fetch(const RArgs& a)
+    {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            const int e = threadIdx.x + i * kRT;
+            if (e < L) w[i] = a.tw[e];
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int e = threadIdx.x + i * kRT;
+            if (e < a.ne * L) s[i] = a.tr[e];
+        }
+    }
+    __device__ __forceinline__ void put(const RArgs& a, cf* tw, float* trl) const
+    {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            const int e = threadIdx.x + i * kRT;
+            if (e < L) tw[e] = w[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int e = threadIdx.x + i * kRT;
+            if (e < a.ne * L) trl[e] = s[i];
+        }
+        __syncthreads();
+    }
+};
 
 // One separable pass: NIN real fields -> NOUT real fields along the axis.
 // LMASK: the single input is masked by mask_in.  SMASK: the single output is
@@ -268,8 +301,9 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
     const long base = tile_base<L, CONTIG>(xcd_tile(blockIdx.x, gridDim.x), a.st);
-    stage_tables<R>(a, tw, trl);
     cf* xb = xbuf + g * xstride<R>();
+    Tables<R> tabs;
+    tabs.fetch(a);
 
     cf Z[NIN][R];
 #pragma unroll
@@ -285,6 +319,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
                 Z[f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
             }
         }
+    tabs.put(a, tw, trl);
 #pragma unroll
     for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
     const SepProg& pr = *a.pr;
@@ -314,7 +349,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     if constexpr (SMASK) {
         if (a.dot_part) {
             const double s = block_sum(dacc, sh);
-            if (tid == 0) a.dot_part[rhs * gridDim.x + blockIdx.x] = s;
+            if (tid == 0) a.dot_part[rhs * kRedBlocks + blockIdx.x] = s;
         }
     }
 }
@@ -336,8 +371,9 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
     const long base = tile_base<L, false>(xcd_tile(blockIdx.x, gridDim.x), a.st);
-    stage_tables<R>(a, tw, trl);
     cf* xb = xbuf + g * xstride<R>();
+    Tables<R> tabs;
+    tabs.fetch(a);
 
     cf D[S][R];
     {
@@ -348,6 +384,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
             for (int m = 0; m < R; ++m)
                 Z[f][m] = load_pair<L, false>(in + f * a.fstride,
                                               elem_index<L, false>(base, g, t, m, a.st));
+        tabs.put(a, tw, trl);
 #pragma unroll
         for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
         const SepProg& pr = *a.pr;
@@ -357,17 +394,25 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
             inv<R>(D[q], t, xb, tw);
         }
     }
-    // pointwise stage on both lines of every complex element
+    // pointwise stage on both lines of every complex element; an element whose
+    // two nodes are interior takes the shared values and reads no arrays
+    // (outside the domain b = 0, so those nodes read zeros)
+    const uint32_t bits = a.nbits ? a.nbits[xcd_tile(blockIdx.x, gridDim.x) * kRT + tid] : 0u;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const long idx = elem_index<L, false>(base, g, t, m, a.st);
+        // interior elements read the 26-float table of shared values (one
+        // cache line for the whole wave) instead of the coefficient arrays
+        const bool inner = ((bits >> (2 * m)) & 3u) == 3u;
+        const float* bp = inner ? a.ctab : a.ba + idx;
+        const long bs = inner ? 2 : a.nn;
         float2 b[3][S];
 #pragma unroll
         for (int al = 0; al < 3; ++al)
 #pragma unroll
             for (int q = 0; q < S; ++q)
-                b[al][q] = *reinterpret_cast<const float2*>(a.ba + (al * S + q) * a.nn + idx);
-        const float2 v = *reinterpret_cast<const float2*>(a.vol + idx);
+                b[al][q] = *reinterpret_cast<const float2*>(bp + (al * S + q) * bs);
+        const float2 v = *reinterpret_cast<const float2*>(inner ? a.ctab + 2 * 3 * S : a.vol + idx);
         float A0[3], A1[3];
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
@@ -455,6 +500,8 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.pr2 = sp.d2[2];
         a.ba = c.ba_32;
         a.vol = c.vol32;
+        a.nbits = c.nbits;
+        a.ctab = c.nctab;
         prof.begin(2, st);
         hipLaunchKernelGGL((k_rmid<R, 3, 3>), grid, block, 0, st, a);
         prof.end(2, st);
@@ -480,7 +527,41 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     }
 }
 
+// Interior bits of every lane of the middle pass, in its own tile geometry.
+template <int R>
+__global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
+                            uint32_t* __restrict__ bits)
+{
+    constexpr int L = 8 * R;
+    const long n = nblk * kRT;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n;
+         s += (long)gridDim.x * blockDim.x) {
+        const long tile = s / kRT;
+        const int lane = (int)(s % kRT), g = lane >> 3, t = lane & 7;
+        const long base = tile_base<L, false>(tile, st);
+        uint32_t w = 0;
+        for (int m = 0; m < R; ++m) {
+            const long idx = elem_index<L, false>(base, g, t, m, st);
+            if (cls[idx] == 1) w |= 1u << (2 * m);
+            if (cls[idx + 1] == 1) w |= 2u << (2 * m);
+        }
+        bits[s] = w;
+    }
+}
+
 }  // namespace
+
+long reg_bits_words(const Ctx& c) { return (c.nn / c.n[2] / (2 * kGroups)) * kRT; }
+
+void launch_reg_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+{
+    const long nblk = c.nn / c.n[2] / (2 * kGroups);
+    const long str = (long)c.n[0] * c.n[1];
+    if (c.n[2] == 128)
+        hipLaunchKernelGGL((k_rmid_bits<16>), dim3(256), dim3(256), 0, st, cls, str, nblk, bits);
+    else
+        hipLaunchKernelGGL((k_rmid_bits<8>), dim3(256), dim3(256), 0, st, cls, str, nblk, bits);
+}
 
 bool reg_path_ok(const Ctx& c)
 {
