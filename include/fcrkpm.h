@@ -230,11 +230,19 @@ const char* fcrkpm_kernel_name(int32_t kind);
 enum {
     FCRKPM_OPT_GRAPHS = 1,  /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
                                launches.  Graphs are never used while profiling is on. */
-    FCRKPM_OPT_REGPATH = 2  /* 1 (default): FP32 K products on 64^3 and 128^3 boxes with the
-                               linear basis use register-resident line transforms; 0: the
-                               LDS-tiled passes used everywhere else */
+    FCRKPM_OPT_REGPATH = 2,  /* 1 (default): FP32 K products on 64^3 and 128^3 boxes with the
+                                linear basis use register-resident line transforms; 0: the
+                                LDS-tiled passes used everywhere else */
+    FCRKPM_OPT_REGLAYOUT = 3, /* line layout of those transforms: 0 = 8 lanes per line, 1 = 16
+                                 lanes (128-point lines only).  Setup times a K product with
+                                 each and keeps the faster. */
+    FCRKPM_OPT_TUNE_NS0 = 4, /* read only: setup's time of one K product with layout 0, ns */
+    FCRKPM_OPT_TUNE_NS1 = 5  /* read only: the same with layout 1 (0 where not timed) */
 };
+/* Set an option; FCRKPM_ERR_ARG for an unknown option or a value out of range. */
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);
+/* Read an option into *value. */
+fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Basis size s = (n+d)!/(d! n!) of the context (Eq 5), or -1 for NULL. */
 int32_t fcrkpm_basis_size(const fcrkpm_ctx* ctx);

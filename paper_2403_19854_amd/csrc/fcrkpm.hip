@@ -168,7 +168,8 @@ void release(Ctx& c)
     dfree(c.partial);
     dfree(c.scal);
     dfree(c.act);
-    dfree(c.nbits);
+    dfree(c.nbits[0]);
+    dfree(c.nbits[1]);
     dfree(c.nctab);
     dfree(c.dflag);
     if (c.aux) (void)hipStreamDestroy(c.aux);
@@ -1196,6 +1197,51 @@ fcrkpm_status run_guarded(std::string& err, const std::function<fcrkpm_status()>
 }
 }  // namespace
 
+namespace {
+// Autotuner of the register-resident K passes: where a box admits more than
+// one line layout, time a few FP32 K products with each on this device and
+// keep the fastest (FCRKPM_REGLAYOUT=0/1 in the environment forces one).
+void tune_reg_layout(Ctx& c, hipStream_t st)
+{
+    if (!reg_path_ok(c) || reg_layouts(c) < 2) return;
+    if (const char* e = getenv("FCRKPM_REGLAYOUT")) {
+        if (*e) {
+            c.reg_layout = (*e == '0') ? 0 : 1;
+            return;
+        }
+    }
+    float* x = vec32(c, 2);
+    float* y = vec32(c, 3);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(float) * c.nn, st));
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    float best = 0.0f;
+    int pick = 0;
+    for (int lay = 0; lay < reg_layouts(c); ++lay) {
+        c.reg_layout = lay;
+        reg_k(c, x, y, c.freem, 1, st);
+        HIPCHK(hipEventRecord(ev[0], st));
+        for (int r = 0; r < 5; ++r) reg_k(c, x, y, c.freem, 1, st);
+        HIPCHK(hipEventRecord(ev[1], st));
+        HIPCHK(hipEventSynchronize(ev[1]));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        c.tune_ms[lay] = ms / 5.0f;
+        if (lay == 0 || ms < best) {
+            best = ms;
+            pick = lay;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    c.reg_layout = pick;
+    if (log_enabled())
+        fprintf(stderr, "[fcrkpm] register layouts: %.1f us (8 lanes), %.1f us (16 lanes); using %d\n",
+                1e3 * c.tune_ms[0], 1e3 * c.tune_ms[1], pick);
+}
+}  // namespace
+
 extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* mask, int32_t kernel,
                                       const double support[3], int32_t degree, void* stream,
                                       fcrkpm_ctx** out)
@@ -1433,8 +1479,10 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 c.nconst = nc;
                 uint8_t* cls = dalloc<uint8_t>(nn);
                 launch_node_class(c, nc, cls, st);
-                c.nbits = dalloc<uint32_t>(reg_bits_words(c));
-                launch_reg_bits(c, cls, c.nbits, st);
+                for (int lay = 0; lay < reg_layouts(c); ++lay) {
+                    c.nbits[lay] = dalloc<uint32_t>(reg_bits_words(c, lay));
+                    launch_reg_bits(c, lay, cls, c.nbits[lay], st);
+                }
                 float tab[2 * kMaxNodeConst + 2];
                 for (int q = 0; q < nb; ++q) tab[2 * q] = tab[2 * q + 1] = nc.b[q];
                 tab[2 * nb] = tab[2 * nb + 1] = nc.v;
@@ -1449,6 +1497,7 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         HIPCHK(hipStreamSynchronize(st));
         ensure_work(c, 1);
         ensure_rhs(c, 1);
+        tune_reg_layout(c, st);
         HIPCHK(hipGetLastError());
         *out = h;
         h = nullptr;
@@ -1649,6 +1698,24 @@ extern "C" fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t n
     });
 }
 
+extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int64_t* value)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (!value) fail(FCRKPM_ERR_ARG, "NULL value");
+        switch (option) {
+            case FCRKPM_OPT_GRAPHS: *value = c.use_graphs ? 1 : 0; break;
+            case FCRKPM_OPT_REGPATH: *value = (c.use_regpath && reg_path_ok(c)) ? 1 : 0; break;
+            case FCRKPM_OPT_REGLAYOUT: *value = c.reg_layout; break;
+            case FCRKPM_OPT_TUNE_NS0: *value = (int64_t)(1e6 * c.tune_ms[0]); break;
+            case FCRKPM_OPT_TUNE_NS1: *value = (int64_t)(1e6 * c.tune_ms[1]); break;
+            default: fail(FCRKPM_ERR_ARG, "unknown option");
+        }
+        return FCRKPM_OK;
+    });
+}
+
 extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value)
 {
     if (!ctx) return FCRKPM_ERR_ARG;
@@ -1662,6 +1729,11 @@ extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int6
             case FCRKPM_OPT_REGPATH:
                 if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGPATH takes 0 or 1");
                 c.use_regpath = value == 1;
+                break;
+            case FCRKPM_OPT_REGLAYOUT:
+                if (value < 0 || value >= (reg_path_ok(c) ? reg_layouts(c) : 1))
+                    fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGLAYOUT out of range for this box");
+                c.reg_layout = (int)value;
                 break;
             default:
                 fail(FCRKPM_ERR_ARG, "unknown option");

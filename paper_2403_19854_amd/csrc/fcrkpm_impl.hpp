@@ -94,7 +94,9 @@ struct Ctx {
     cplx<float>* spec32[3] = {};
     float* rtab32[3] = {};              // per axis [2n+1][n]: Re (even e) or Im (odd e) of spec32
     bool use_regpath = true;            // register-resident passes where they apply
-    uint32_t* nbits = nullptr;          // register path: interior bits per middle-pass lane
+    uint32_t* nbits[2] = {};            // register path: interior bits per middle-pass lane, per layout
+    int reg_layout = 0;                 // register path: line layout (0: 8 lanes, 1: 16 lanes)
+    float tune_ms[2] = {0.0f, 0.0f};    // register path: measured K product per layout (0: untimed)
     NodeConst nconst = {};              // values of the interior nodes
     float* nctab = nullptr;             // the same on the device, each value twice (a float2)
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
@@ -172,8 +174,9 @@ struct RegProf {
 };
 bool reg_path_ok(const Ctx& c);
 int reg_path_blocks(const Ctx& c);
-long reg_bits_words(const Ctx& c);
-void launch_reg_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st);
+int reg_layouts(const Ctx& c);
+long reg_bits_words(const Ctx& c, int layout);
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, hipStream_t st);
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof);
 

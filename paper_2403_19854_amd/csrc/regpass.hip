@@ -8,10 +8,17 @@
 // spectral separation is needed; t_e is even or odd in its offset, so its
 // spectrum is real or imaginary and one float per frequency describes it.
 //
-// A complex line of L = 8 R points is owned by 8 lanes; lane t holds points
-// t + 8m (m < R) in registers.  A transform is a DFT-R in registers, a
-// twiddle, one transpose through LDS and DFT-8s in registers (four-step
-// FFT), so the data crosses LDS once per transform instead of once per
+// A complex line of L points is owned by a group of lanes that hold it in
+// registers, in one of two layouts:
+//   G8<R>: 8 lanes, lane t holds points t + 8m (m < R, L = 8R).  A transform
+//          is a DFT-R in registers, a twiddle, one transpose through LDS and
+//          DFT-8s in registers (four-step FFT).
+//   G16:   16 lanes, lane t holds points t + 16m (m < 8, L = 128): a DFT-8,
+//          a twiddle, one transpose through LDS, a radix-2 step between the
+//          two lane halves by a DPP row rotation, a twiddle and a DFT-8.
+//          Twice the waves of G8<16> at half the registers, so more latency
+//          is hidden; a setup-time measurement picks between the two.
+// Either way the data crosses LDS once per transform instead of once per
 // radix stage, and the spectral products, the inverse transforms and the
 // pointwise stage of the middle pass all act on registers.
 #include <hip/hip_runtime.h>
@@ -24,14 +31,7 @@ namespace {
 typedef cplx<float> cf;
 
 constexpr int kRT = 256;             // threads per workgroup
-constexpr int kGrp = 8;              // lanes per complex line
-constexpr int kGroups = kRT / kGrp;  // complex lines per workgroup
 constexpr int kRMaxE = 3;            // kernel exponents 0 .. 2n for n = 1
-
-// LDS stride of a group's transpose buffer: rows of 9 (8 points + pad); the
-// group stride is 8 mod 32 so the 8 groups of a wave spread over the banks
-template <int R>
-constexpr int xstride() { return R == 16 ? 168 : 72; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -93,7 +93,7 @@ __device__ __forceinline__ cf twid(const cf* tw, int j)
 // Forward transform of the group's line.  In: v[m] = x[t + 8m].  Out:
 // v[8j + k2] = X[t + 8j + R k2] (j < R/8, k2 < 8).
 template <int R>
-__device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
+__device__ __forceinline__ void g8_fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
 {
     constexpr int KPL = R / 8;
     dftR_reg<R, +1>(v);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
 
 // Unnormalised inverse: the layout of fwd's output in, x[t + 8m] in v[m] out.
 template <int R>
-__device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const cf* tw)
+__device__ __forceinline__ void g8_inv(cf (&v)[R], int t, cf* xb, const cf* tw)
 {
     constexpr int KPL = R / 8;
 #pragma unroll
@@ -131,14 +131,102 @@ __device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const cf* tw)
     dftR_reg<R, -1>(v);
 }
 
+// the value of lane t ^ 8 within the lane's row of 16 (DPP row rotation by 8)
+__device__ __forceinline__ float swap8(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+}
+
+// G16 forward transform (L = 128).  In: v[m] = x[t + 16m].  Out: v[i] =
+// X[t + 16i].  With t = k1 + 8h the steps are a DFT-8 over m, the twiddle
+// W_128^{t k1}, a transpose giving lane (k1, h) the values of lanes
+// 8h .. 8h+7 at k1, a radix-2 step across h, the twiddle W_16^{tl h} and a
+// DFT-8 over the lane offset tl.
+__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const cf* tw)
+{
+    dft8<float, +1>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], twid<+1>(tw, t * k1));
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) xb[k1 * 17 + t] = v[k1];
+    wave_sync();
+    const int k1 = t & 7, h = t >> 3;
+#pragma unroll
+    for (int tl = 0; tl < 8; ++tl) v[tl] = xb[k1 * 17 + 8 * h + tl];
+    wave_sync();
+    const float s = h ? -1.0f : 1.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const cf u = {swap8(v[i].x), swap8(v[i].y)};
+        v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
+    }
+#pragma unroll
+    for (int tl = 1; tl < 8; ++tl) {
+        const cf w = mul_w16<+1>(v[tl], tl);
+        v[tl] = h ? w : v[tl];
+    }
+    dft8<float, +1>(v);
+}
+
+// G16 unnormalised inverse: v[i] = X[t + 16i] in, v[m] = x[t + 16m] out (the
+// steps of g16_fwd reversed, with conjugate twiddles).
+__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const cf* tw)
+{
+    const int k1 = t & 7, h = t >> 3;
+    dft8<float, -1>(v);
+#pragma unroll
+    for (int tl = 1; tl < 8; ++tl) {
+        const cf w = mul_w16<-1>(v[tl], tl);
+        v[tl] = h ? w : v[tl];
+    }
+    const float s = h ? -1.0f : 1.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const cf u = {swap8(v[i].x), swap8(v[i].y)};
+        v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
+    }
+#pragma unroll
+    for (int tl = 0; tl < 8; ++tl) {
+        const int tt = tl + 8 * h;
+        xb[k1 * 17 + tt] = cmul(v[tl], twid<-1>(tw, tt * k1));
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = xb[j * 17 + t];
+    wave_sync();
+    dft8<float, -1>(v);
+}
+
+// Line layouts: lanes per complex line, points per lane, the spatial row of
+// point m and the frequency of spectral slot i held by lane t, and the LDS
+// complex values of one group's transpose buffer (the group stride is 8 mod
+// 32 so the groups of a wave spread over the banks).
+template <int R>
+struct G8 {
+    static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
+    static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
+    static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const cf* tw) { g8_fwd<R>(v, t, xb, tw); }
+    static __device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const cf* tw) { g8_inv<R>(v, t, xb, tw); }
+};
+struct G16 {
+    static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
+    static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
+    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const cf* tw) { g16_fwd(v, t, xb, tw); }
+    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const cf* tw) { g16_inv(v, t, xb, tw); }
+};
+
 // Y <- sum over the terms of output o of 2 coef T_e o Z_in (spectra in fwd's
 // layout).  The factor 2 undoes the 1/2 that the pair-separating passes keep
 // in the coefficients; the 1/L of the inverse transform stays in coef.
-template <int R, int NIN>
+template <class Lay, int NIN, int R = Lay::PTS>
 __device__ __forceinline__ void combine(const SepProg& pr, int o, const cf (&Z)[NIN][R], cf (&Y)[R],
                                         const float* trl, int t)
 {
-    constexpr int L = 8 * R;
+    constexpr int L = Lay::L;
 #pragma unroll
     for (int i = 0; i < R; ++i) Y[i] = cf{0.0f, 0.0f};
     const int t0 = pr.ostart[o], t1 = pr.ostart[o + 1];
@@ -151,15 +239,12 @@ __device__ __forceinline__ void combine(const SepProg& pr, int o, const cf (&Z)[
         for (int f = 0; f < NIN; ++f) {
             if (f != tm.in) continue;
 #pragma unroll
-            for (int j = 0; j < R / 8; ++j)
-#pragma unroll
-                for (int k2 = 0; k2 < 8; ++k2) {
-                    const int i = 8 * j + k2;
-                    const float s = c2 * T[t + 8 * j + R * k2];
-                    const cf z = Z[f][i];
-                    if (odd) Y[i] = cf{Y[i].x - s * z.y, Y[i].y + s * z.x};
-                    else Y[i] = cf{Y[i].x + s * z.x, Y[i].y + s * z.y};
-                }
+            for (int i = 0; i < R; ++i) {
+                const float s = c2 * T[Lay::freq(t, i)];
+                const cf z = Z[f][i];
+                if (odd) Y[i] = cf{Y[i].x - s * z.y, Y[i].y + s * z.x};
+                else Y[i] = cf{Y[i].x + s * z.x, Y[i].y + s * z.y};
+            }
         }
     }
 }
@@ -187,24 +272,24 @@ struct RArgs {
     const float* ctab;        // middle pass: interior b^a_q and V, each stored twice (26 floats)
 };
 
-// Position of the workgroup's 64 real lines: for a strided axis the float
-// index of line l0 at point 0 (lines l0 .. l0+63 are adjacent in memory),
-// for x the index of line l0's first point.
-template <int L, bool CONTIG>
+// Position of the workgroup's Lay::LINES real lines: for a strided axis the
+// float index of line l0 at point 0 (the lines are adjacent in memory), for
+// x the index of line l0's first point.
+template <class Lay, bool CONTIG>
 __device__ __forceinline__ long tile_base(long tile, long st)
 {
-    const long l0 = tile * (2 * kGroups);
-    if (CONTIG) return l0 * L;
+    const long l0 = tile * Lay::LINES;
+    if (CONTIG) return l0 * Lay::L;
     const long lo = l0 % st, hi = l0 / st;
-    return lo + hi * st * L;
+    return lo + hi * st * Lay::L;
 }
 
-// complex element m of group g: lines (2g, 2g+1) of the tile at point t + 8m
-template <int L, bool CONTIG>
+// complex element m of group g: lines (2g, 2g+1) of the tile at point row(t, m)
+template <class Lay, bool CONTIG>
 __device__ __forceinline__ long elem_index(long base, int g, int t, int m, long st)
 {
-    const int i = t + 8 * m;
-    if (CONTIG) return base + (long)(2 * g) * L + i;
+    const int i = Lay::row(t, m);
+    if (CONTIG) return base + (long)(2 * g) * Lay::L + i;
     return base + 2 * g + (long)i * st;
 }
 
@@ -249,9 +334,8 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks)
 // The twiddle and spectrum tables of the axis: each thread loads its share
 // into registers (fetch) and writes it to LDS later (put), so the loads of
 // the tables and of the input lines are in flight together.
-template <int R>
+template <int L>
 struct Tables {
-    static constexpr int L = 8 * R;
     static constexpr int NT = (L + kRT - 1) / kRT;             // twiddles per thread
     static constexpr int NS = (kRMaxE * L + kRT - 1) / kRT;    // spectrum values per thread
     cf w[NT];
@@ -288,21 +372,21 @@ struct Tables {
 // One separable pass: NIN real fields -> NOUT real fields along the axis.
 // LMASK: the single input is masked by mask_in.  SMASK: the single output is
 // masked by mask_out and, if dot_part is set, dotted with dot_with.
-template <int R, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT>
+template <class Lay, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT>
 __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 {
-    constexpr int L = 8 * R;
+    constexpr int L = Lay::L, R = Lay::PTS;
     __shared__ cf tw[L];
     __shared__ float trl[kRMaxE * L];
-    __shared__ cf xbuf[kGroups * xstride<R>()];
+    __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
-    const int tid = threadIdx.x, g = tid >> 3, t = tid & 7;
+    const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
-    const long base = tile_base<L, CONTIG>(xcd_tile(blockIdx.x, gridDim.x), a.st);
-    cf* xb = xbuf + g * xstride<R>();
-    Tables<R> tabs;
+    const long base = tile_base<Lay, CONTIG>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    cf* xb = xbuf + g * Lay::XS;
+    Tables<L> tabs;
     tabs.fetch(a);
 
     cf Z[NIN][R];
@@ -310,7 +394,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     for (int f = 0; f < NIN; ++f)
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            const long idx = elem_index<L, CONTIG>(base, g, t, m, a.st);
+            const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
             if constexpr (LMASK) {
                 const cf v = load_pair<L, CONTIG>(in, idx);
                 const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
@@ -321,17 +405,17 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
         }
     tabs.put(a, tw, trl);
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
+    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[f], t, xb, tw);
     const SepProg& pr = *a.pr;
     double dacc = 0.0;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<R, NIN>(pr, o, Z, Y, trl, t);
-        inv<R>(Y, t, xb, tw);
+        combine<Lay, NIN>(pr, o, Z, Y, trl, t);
+        Lay::inv(Y, t, xb, tw);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            const long idx = elem_index<L, CONTIG>(base, g, t, m, a.st);
+            const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
             if constexpr (SMASK) {
                 const long idx1 = idx + (CONTIG ? L : 1);
                 const float v0 = a.mask_out[idx] ? Y[m].x : 0.0f;
@@ -358,21 +442,21 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 // (s = 4): the part-1 convolutions give D_q, the pointwise stage forms
 // A^a = sum_q b^a_q D_q and E_p = V sum_a b^a_p A^a at every node (Eq 90-91,
 // Alg 2), and the part-2 convolutions of E_p follow -- all in registers.
-template <int R, int NIN, int NOUT>
+template <class Lay, int NIN, int NOUT>
 __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 {
-    constexpr int L = 8 * R;
+    constexpr int L = Lay::L, R = Lay::PTS;
     constexpr int S = 4;
     __shared__ cf tw[L];
     __shared__ float trl[kRMaxE * L];
-    __shared__ cf xbuf[kGroups * xstride<R>()];
-    const int tid = threadIdx.x, g = tid >> 3, t = tid & 7;
+    __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
+    const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
-    const long base = tile_base<L, false>(xcd_tile(blockIdx.x, gridDim.x), a.st);
-    cf* xb = xbuf + g * xstride<R>();
-    Tables<R> tabs;
+    const long base = tile_base<Lay, false>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    cf* xb = xbuf + g * Lay::XS;
+    Tables<L> tabs;
     tabs.fetch(a);
 
     cf D[S][R];
@@ -383,26 +467,25 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 #pragma unroll
             for (int m = 0; m < R; ++m)
                 Z[f][m] = load_pair<L, false>(in + f * a.fstride,
-                                              elem_index<L, false>(base, g, t, m, a.st));
+                                              elem_index<Lay, false>(base, g, t, m, a.st));
         tabs.put(a, tw, trl);
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) fwd<R>(Z[f], t, xb, tw);
+        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[f], t, xb, tw);
         const SepProg& pr = *a.pr;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            combine<R, NIN>(pr, q, Z, D[q], trl, t);
-            inv<R>(D[q], t, xb, tw);
+            combine<Lay, NIN>(pr, q, Z, D[q], trl, t);
+            Lay::inv(D[q], t, xb, tw);
         }
     }
     // pointwise stage on both lines of every complex element; an element whose
-    // two nodes are interior takes the shared values and reads no arrays
+    // two nodes are interior reads the 26-float table of shared values (one
+    // cache line for the whole wave) instead of the coefficient arrays
     // (outside the domain b = 0, so those nodes read zeros)
     const uint32_t bits = a.nbits ? a.nbits[xcd_tile(blockIdx.x, gridDim.x) * kRT + tid] : 0u;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const long idx = elem_index<L, false>(base, g, t, m, a.st);
-        // interior elements read the 26-float table of shared values (one
-        // cache line for the whole wave) instead of the coefficient arrays
+        const long idx = elem_index<Lay, false>(base, g, t, m, a.st);
         const bool inner = ((bits >> (2 * m)) & 3u) == 3u;
         const float* bp = inner ? a.ctab : a.ba + idx;
         const long bs = inner ? 2 : a.nn;
@@ -437,31 +520,32 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
         }
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p) fwd<R>(D[p], t, xb, tw);
+    for (int p = 0; p < S; ++p) Lay::fwd(D[p], t, xb, tw);
     const SepProg& pr2 = *a.pr2;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<R, S>(pr2, o, D, Y, trl, t);
-        inv<R>(Y, t, xb, tw);
+        combine<Lay, S>(pr2, o, D, Y, trl, t);
+        Lay::inv(Y, t, xb, tw);
 #pragma unroll
         for (int m = 0; m < R; ++m)
-            store_pair<L, false>(out + o * a.fstride, elem_index<L, false>(base, g, t, m, a.st), Y[m]);
+            store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, g, t, m, a.st), Y[m]);
     }
 }
 
-template <int R>
+template <class Lay>
+long blocks_of(const Ctx& c) { return c.nn / Lay::L / Lay::LINES; }
+
+template <class Lay>
 void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
            double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
 {
-    constexpr int L = 8 * R;
     const SepPlan& sp = c.basis_plan;
     const long nn = c.nn;
     const long slot_rb = 2L * sp.maxpairs * nn;  // floats between rhs in a workspace slot
     float* S1 = reinterpret_cast<float*>(c.work32);
     float* S2 = S1 + slot_rb * c.cap_work;
-    const unsigned nblk = (unsigned)(nn / L / (2 * kGroups));
-    const dim3 grid(nblk, (unsigned)nrhs), block(kRT);
+    const dim3 grid((unsigned)blocks_of<Lay>(c), (unsigned)nrhs), block(kRT);
     auto args = [&](int axis, const float* i, long irb, float* o, long orb) {
         RArgs a{};
         a.in = i;
@@ -482,7 +566,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.mask_in = mask;
         a.pr = sp.d1[0];
         prof.begin(0, st);
-        hipLaunchKernelGGL((k_rpass<R, true, true, false, 1, 2>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, true, true, false, 1, 2>), grid, block, 0, st, a);
         prof.end(0, st);
     }
     // y: X -> XY
@@ -490,7 +574,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
         a.pr = sp.d1[1];
         prof.begin(1, st);
-        hipLaunchKernelGGL((k_rpass<R, false, false, false, 2, 3>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, false, false, false, 2, 3>), grid, block, 0, st, a);
         prof.end(1, st);
     }
     // z: XY -> D -> E -> part-2 XY
@@ -500,10 +584,10 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.pr2 = sp.d2[2];
         a.ba = c.ba_32;
         a.vol = c.vol32;
-        a.nbits = c.nbits;
+        a.nbits = c.nbits[c.reg_layout];
         a.ctab = c.nctab;
         prof.begin(2, st);
-        hipLaunchKernelGGL((k_rmid<R, 3, 3>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rmid<Lay, 3, 3>), grid, block, 0, st, a);
         prof.end(2, st);
     }
     // y: XY -> X
@@ -511,7 +595,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
         a.pr = sp.d2[1];
         prof.begin(3, st);
-        hipLaunchKernelGGL((k_rpass<R, false, false, false, 3, 2>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, false, false, false, 3, 2>), grid, block, 0, st, a);
         prof.end(3, st);
     }
     // x: X -> f (masked), with the optional dot partials
@@ -522,26 +606,25 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.dot_part = dot_part;
         a.dot_with = dot_with;
         prof.begin(4, st);
-        hipLaunchKernelGGL((k_rpass<R, true, false, true, 2, 1>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, true, false, true, 2, 1>), grid, block, 0, st, a);
         prof.end(4, st);
     }
 }
 
 // Interior bits of every lane of the middle pass, in its own tile geometry.
-template <int R>
+template <class Lay>
 __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
                             uint32_t* __restrict__ bits)
 {
-    constexpr int L = 8 * R;
     const long n = nblk * kRT;
     for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n;
          s += (long)gridDim.x * blockDim.x) {
         const long tile = s / kRT;
-        const int lane = (int)(s % kRT), g = lane >> 3, t = lane & 7;
-        const long base = tile_base<L, false>(tile, st);
+        const int lane = (int)(s % kRT), g = lane / Lay::LANES, t = lane % Lay::LANES;
+        const long base = tile_base<Lay, false>(tile, st);
         uint32_t w = 0;
-        for (int m = 0; m < R; ++m) {
-            const long idx = elem_index<L, false>(base, g, t, m, st);
+        for (int m = 0; m < Lay::PTS; ++m) {
+            const long idx = elem_index<Lay, false>(base, g, t, m, st);
             if (cls[idx] == 1) w |= 1u << (2 * m);
             if (cls[idx + 1] == 1) w |= 2u << (2 * m);
         }
@@ -549,18 +632,33 @@ __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
     }
 }
 
+template <class Lay>
+void build_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+{
+    const long str = (long)c.n[0] * c.n[1];
+    hipLaunchKernelGGL((k_rmid_bits<Lay>), dim3(256), dim3(256), 0, st, cls, str, blocks_of<Lay>(c),
+                       bits);
+}
+
 }  // namespace
 
-long reg_bits_words(const Ctx& c) { return (c.nn / c.n[2] / (2 * kGroups)) * kRT; }
+// layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only)
+int reg_layouts(const Ctx& c) { return c.n[0] == 128 ? 2 : 1; }
 
-void launch_reg_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+long reg_bits_words(const Ctx& c, int layout)
 {
-    const long nblk = c.nn / c.n[2] / (2 * kGroups);
-    const long str = (long)c.n[0] * c.n[1];
-    if (c.n[2] == 128)
-        hipLaunchKernelGGL((k_rmid_bits<16>), dim3(256), dim3(256), 0, st, cls, str, nblk, bits);
-    else
-        hipLaunchKernelGGL((k_rmid_bits<8>), dim3(256), dim3(256), 0, st, cls, str, nblk, bits);
+    if (c.n[0] == 128) return (layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c)) * kRT;
+    return blocks_of<G8<8>>(c) * kRT;
+}
+
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+{
+    if (c.n[0] == 128) {
+        if (layout) build_bits<G16>(c, cls, bits, st);
+        else build_bits<G8<16>>(c, cls, bits, st);
+    } else {
+        build_bits<G8<8>>(c, cls, bits, st);
+    }
 }
 
 bool reg_path_ok(const Ctx& c)
@@ -577,13 +675,21 @@ bool reg_path_ok(const Ctx& c)
     return c.n[1] == L && c.n[2] == L;
 }
 
-int reg_path_blocks(const Ctx& c) { return (int)(c.nn / c.n[0] / (2 * kGroups)); }
+int reg_path_blocks(const Ctx& c)
+{
+    if (c.n[0] == 128) return (int)(c.reg_layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c));
+    return (int)blocks_of<G8<8>>(c);
+}
 
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
 {
-    if (c.n[0] == 128) run_k<16>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
-    else run_k<8>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    if (c.n[0] == 128) {
+        if (c.reg_layout) run_k<G16>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+        else run_k<G8<16>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    } else {
+        run_k<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    }
 }
 
 }  // namespace fcrkpm

@@ -34,9 +34,13 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_get_coeffs", "fcrkpm_basis_size", "fcrkpm_destroy",
            "fcrkpm_last_error", "fcrkpm_status_str", "fcrkpm_version",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
-           "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option")
+           "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
+           "fcrkpm_get_option")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
+OPT_REGLAYOUT = 3
+OPT_TUNE_NS0 = 4
+OPT_TUNE_NS1 = 5
 
 
 class Grid(C.Structure):
@@ -125,6 +129,8 @@ def load_library(path: str = LIB_PATH):
                                        C.c_double, C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_set_option.restype = C.c_int
     lib.fcrkpm_set_option.argtypes = [V, C.c_int32, C.c_int64]
+    lib.fcrkpm_get_option.restype = C.c_int
+    lib.fcrkpm_get_option.argtypes = [V, C.c_int32, C.POINTER(C.c_int64)]
     _lib = lib
     return lib
 
@@ -262,6 +268,14 @@ class Problem:
     def set_regpath(self, on: bool):
         """Use the register-resident FP32 K passes where they apply (default)."""
         self._check(load_library().fcrkpm_set_option(self._h, OPT_REGPATH, 1 if on else 0))
+
+    def set_option(self, option: int, value: int):
+        self._check(load_library().fcrkpm_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = C.c_int64()
+        self._check(load_library().fcrkpm_get_option(self._h, int(option), C.byref(v)))
+        return v.value
 
     def set_graphs(self, on: bool):
         """Replay CG blocks from captured HIP graphs (default) or launch directly."""

@@ -368,20 +368,32 @@ def test_register_path_matches_lds_path_and_oracle(n):
     basis) against the LDS-tiled FP32 passes and the FP64 oracle."""
     p = W.cube(3, n, 2.5, 1)
     print(f"\n[register path {n}^3]", flush=True)
+    from paper_2403_19854_amd import fcrkpm
     g = lib_problem(p)
     x = rand_field(p, 31)
     xt = torch.from_numpy(x).to(DEV).float()
-    reg = to_np(g.apply("K", xt)).astype(np.float64)
     g.set_regpath(False)
     lds = to_np(g.apply("K", xt)).astype(np.float64)
     g.set_regpath(True)
     scale = np.abs(lds).max()
-    d = np.abs(reg - lds).max() / scale
-    print(f"  register vs LDS path rel-max {d:.2e}")
-    assert d <= 2e-5
-    assert np.all(reg[p.free == 0] == 0.0)
     o = orc(p)
     idx = _sampled(p, 3, 64)
     ref = o.apply_k_at(np.where(p.free > 0, x, 0.0), idx)
-    got = np.where(p.free > 0, reg, 0.0).reshape(-1)[idx]
-    assert np.abs(got - np.where(p.free.reshape(-1)[idx] > 0, ref, 0.0)).max() <= 2e-5 * scale
+    ref = np.where(p.free.reshape(-1)[idx] > 0, ref, 0.0)
+    chosen = g.get_option(fcrkpm.OPT_REGLAYOUT)
+    layouts = [0, 1] if n == 128 else [0]
+    print(f"  autotuned layout {chosen}; setup times (ns) "
+          f"{g.get_option(fcrkpm.OPT_TUNE_NS0)} {g.get_option(fcrkpm.OPT_TUNE_NS1)}")
+    for lay in layouts:
+        g.set_option(fcrkpm.OPT_REGLAYOUT, lay)
+        reg = to_np(g.apply("K", xt)).astype(np.float64)
+        d = np.abs(reg - lds).max() / scale
+        print(f"  layout {lay}: register vs LDS path rel-max {d:.2e}")
+        assert d <= 2e-5
+        assert np.all(reg[p.free == 0] == 0.0)
+        got = np.where(p.free > 0, reg, 0.0).reshape(-1)[idx]
+        assert np.abs(got - ref).max() <= 2e-5 * scale
+        # batched products in one launch equal the single ones bit for bit
+        two = to_np(g.apply("K", torch.stack([xt, 2 * xt])))
+        np.testing.assert_array_equal(two[0], reg.astype(np.float32))
+    g.set_option(fcrkpm.OPT_REGLAYOUT, chosen)
