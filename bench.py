@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5", choices=["c5", "paper", "c3", "c4"])
     ap.add_argument("--c4-iters", type=int, default=240)
+    ap.add_argument("--probe", type=int, default=0,
+                    help="counter probe: setup, a refined solve capped at N CG iterations "
+                         "(direct launches), then a 256 MiB device copy that calibrates the "
+                         "memory counters; prints one line and exits")
     ap.add_argument("--mode", default="f32_refined", choices=["f32_refined", "f64"])
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--maxit", type=int, default=100000)
@@ -63,12 +67,15 @@ def main():
     import torch
 
     from paper_2403_19854_amd import fcrkpm
+    from paper_2403_19854_amd import traffic
     from paper_2403_19854_amd import workloads as W
 
     fcrkpm.load_library()
     if a.workload == "c4":
         return bench_c4(a)
     wl = {"c5": W.config5, "paper": W.paper_shape, "c3": W.config3}[a.workload]()
+    if a.probe:
+        return probe(a, wl)
     dev = torch.device("cuda:0")
     chi = torch.from_numpy(wl.chi).to(dev)
     dirm = torch.from_numpy(wl.dirichlet).to(dev)
@@ -81,6 +88,7 @@ def main():
         if profile:
             pb.profile(True)
         d, uh, info = pb.solve(r, mode=mode, tol=a.tol, maxit=a.maxit, want_uh=True)
+        info["layout"] = pb.get_option(fcrkpm.OPT_REGLAYOUT)
         prof = None
         if profile:
             pb.profile(False)
@@ -141,7 +149,8 @@ def main():
                   "fallback_used": infos[-1]["fallback_used"],
                   "uh_rel_l2_vs_exact": uh_err},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic.load(wl.name, dom, infos[-1]["layout"]),
                      "mean_ms": dk["mean_ms"], "bytes_per_launch": dk["bytes_per_launch"]},
         "kernels": kernels,
     }
@@ -177,6 +186,35 @@ def main():
                                "sample": f"{n} oracle K products (neighbour-loop RKPM, FP64) on the "
                                          f"same {wl.name} grid, {tc:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def probe(a, wl):
+    """A short run for counter collection (see paper_2403_19854_amd/traffic.py)."""
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    dev = torch.device("cuda:0")
+    pb = fcrkpm.Problem.from_workload(wl, device=dev)
+    pb.set_graphs(False)
+    # counter collection distorts setup's layout timing: measure the layout an
+    # ordinary run picks on MI355X (16 lanes per 128-point line) where it exists
+    try:
+        pb.set_option(fcrkpm.OPT_REGLAYOUT, 1)
+    except fcrkpm.FcrkpmError:
+        pass
+    layout = pb.get_option(fcrkpm.OPT_REGLAYOUT)
+    r = torch.from_numpy(wl.r).to(dev)
+    _, _, info = pb.solve(r, mode=a.mode, tol=1e-300, maxit=a.probe, want_uh=False,
+                          raise_on_noconv=False)
+    torch.cuda.synchronize()
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": wl.name, "cg_iterations": info["iters"], "layout": layout,
+                      "calibration_copy_bytes": 4 * src.numel()}), flush=True)
+    pb.close()
 
 
 def bench_c4(a):

@@ -170,7 +170,10 @@ void release(Ctx& c)
     dfree(c.act);
     dfree(c.nbits[0]);
     dfree(c.nbits[1]);
-    dfree(c.nctab);
+    dfree(c.noff[0]);
+    dfree(c.noff[1]);
+    dfree(c.nrec[0]);
+    dfree(c.nrec[1]);
     dfree(c.dflag);
     if (c.aux) (void)hipStreamDestroy(c.aux);
     c.aux = nullptr;
@@ -434,17 +437,35 @@ bool use_reg_path(const Ctx& c, int /*nrhs*/)
         const char* e = getenv("FCRKPM_REGPATH");
         env = (e && *e == '0') ? 0 : 1;
     }
-    return env == 1 && c.use_regpath && reg_path_ok(c);
+    return env == 1 && c.use_regpath && reg_path_ok(c) && c.nrec[c.reg_layout] != nullptr;
+}
+
+// Algorithmic bytes of one launch of each register-resident pass: the FP32
+// fields it must read and write (masks 1 B per node), and in the middle pass
+// the interior bits and record offsets (4 B each per lane) and the records of
+// the elements that are not interior (28 floats each; interior elements read
+// one shared record that stays in cache).
+double reg_pass_bytes(const Ctx& c, int k)
+{
+    const double nn = (double)c.nn;
+    switch (k) {
+        case 0: return nn * (4 + 1 + 2 * 4);
+        case 1: return nn * (2 * 4 + 3 * 4);
+        case 2: {
+            const double words = (double)reg_bits_words(c, c.reg_layout);
+            return nn * (3 * 4 + 3 * 4) + 2 * 4.0 * words +
+                   (double)c.nload[c.reg_layout] * reg_record_floats() * 4;
+        }
+        case 3: return nn * (3 * 4 + 2 * 4);
+        default: return nn * (2 * 4 + 1 + 4 + (c.prof_dot ? 4 : 0));
+    }
 }
 
 void regprof_begin(const void* cv, int k, hipStream_t st)
 {
     Ctx& c = *(Ctx*)cv;
     static const int kinds[5] = {KD_P1_X, KD_P1_Y, KD_MID_K, KD_P2_Y, KD_P2_X};
-    // algorithmic bytes per node of each pass (FP32 real fields; masks 1 B)
-    static const double bytes[5] = {4 + 1 + 2 * 4, 2 * 4 + 3 * 4, 3 * 4 + 12 * 4 + 4 + 3 * 4,
-                                    3 * 4 + 2 * 4, 2 * 4 + 1 + 4};
-    prof_begin(c, kind_of<float>(kinds[k]), bytes[k] * (double)c.nn * c.prof_rhs, st);
+    prof_begin(c, kind_of<float>(kinds[k]), reg_pass_bytes(c, k) * c.prof_rhs, st);
 }
 void regprof_end(const void* cv, int k, hipStream_t st)
 {
@@ -463,6 +484,7 @@ void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, h
         rp.begin_fn = regprof_begin;
         rp.end_fn = regprof_end;
         c.prof_rhs = nrhs;
+        c.prof_dot = dot_part != nullptr;
     }
     launch_reg_k(c, in, out, mask, nrhs, dot_part, dot_with, st, rp);
 }
@@ -1461,36 +1483,64 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         }
 
         // node classes of the register-resident K passes: interior nodes share
-        // one set of coefficients, so their pointwise stage reads no arrays
+        // one set of coefficients, so their pointwise stage reads one cached
+        // record; every other element gets its own record, packed lane by lane
         if (reg_path_ok(c) && c.dim * c.s <= kMaxNodeConst) {
             int big = 0x7fffffff, ref = 0;
             HIPCHK(hipMemcpyAsync(c.dflag + 3, &big, sizeof(int), hipMemcpyHostToDevice, st));
             launch_first_interior(c, c.dflag + 3, st);
             HIPCHK(hipMemcpyAsync(&ref, c.dflag + 3, sizeof(int), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            const int nb = c.dim * c.s;
+            NodeConst nc = {};
+            uint8_t* cls = dalloc<uint8_t>(nn);
             if (ref != 0x7fffffff) {
-                NodeConst nc = {};
-                const int nb = c.dim * c.s;
                 for (int q = 0; q < nb; ++q)
                     HIPCHK(hipMemcpy(&nc.b[q], c.ba_32 + (size_t)q * nn + ref, sizeof(float),
                                      hipMemcpyDeviceToHost));
                 HIPCHK(hipMemcpy(&nc.v, c.vol32 + ref, sizeof(float), hipMemcpyDeviceToHost));
                 for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabsf(nc.b[q]));
-                c.nconst = nc;
-                uint8_t* cls = dalloc<uint8_t>(nn);
                 launch_node_class(c, nc, cls, st);
-                for (int lay = 0; lay < reg_layouts(c); ++lay) {
-                    c.nbits[lay] = dalloc<uint32_t>(reg_bits_words(c, lay));
-                    launch_reg_bits(c, lay, cls, c.nbits[lay], st);
-                }
-                float tab[2 * kMaxNodeConst + 2];
-                for (int q = 0; q < nb; ++q) tab[2 * q] = tab[2 * q + 1] = nc.b[q];
-                tab[2 * nb] = tab[2 * nb + 1] = nc.v;
-                c.nctab = dalloc<float>(2 * nb + 2);
-                HIPCHK(hipMemcpy(c.nctab, tab, sizeof(float) * (2 * nb + 2), hipMemcpyHostToDevice));
-                HIPCHK(hipStreamSynchronize(st));
-                dfree(cls);
+            } else {
+                HIPCHK(hipMemsetAsync(cls, 2, nn, st));  // no interior node: every element reads
             }
+            c.nconst = nc;
+            const int rf = reg_record_floats();
+            std::vector<float> tab(rf, 0.0f);  // record 0: the interior values
+            for (int q = 0; q < nb; ++q) tab[2 * q] = tab[2 * q + 1] = nc.b[q];
+            tab[2 * nb] = tab[2 * nb + 1] = nc.v;
+            unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c.dflag + 4);
+            for (int lay = 0; lay < reg_layouts(c); ++lay) {
+                const long words = reg_bits_words(c, lay);
+                c.nbits[lay] = dalloc<uint32_t>(words);
+                c.noff[lay] = dalloc<uint32_t>(words);
+                unsigned long long zero = 0, got = 0;
+                HIPCHK(hipMemcpyAsync(cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+                launch_reg_bits(c, lay, cls, c.nbits[lay], c.noff[lay], cnt, st);
+                HIPCHK(hipMemcpyAsync(&got, cnt, sizeof(got), hipMemcpyDeviceToHost, st));
+                std::vector<uint32_t> off(words);
+                HIPCHK(hipMemcpyAsync(off.data(), c.noff[lay], sizeof(uint32_t) * words,
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                c.nload[lay] = (long)got;
+                // per-lane counts -> first record of each lane (exclusive prefix
+                // sum after record 0)
+                uint64_t run = 1;
+                for (long s = 0; s < words; ++s) {
+                    const uint32_t n1 = off[s];
+                    off[s] = (uint32_t)run;
+                    run += n1;
+                }
+                if (run != got + 1 || run > 0xffffffffull) fail(FCRKPM_ERR_HIP, "record count mismatch");
+                HIPCHK(hipMemcpyAsync(c.noff[lay], off.data(), sizeof(uint32_t) * words,
+                                      hipMemcpyHostToDevice, st));
+                c.nrec[lay] = dalloc<float>((size_t)run * rf);
+                HIPCHK(hipMemcpyAsync(c.nrec[lay], tab.data(), sizeof(float) * rf,
+                                      hipMemcpyHostToDevice, st));
+                launch_reg_recs(c, lay, c.nbits[lay], c.noff[lay], c.nrec[lay], st);
+                HIPCHK(hipStreamSynchronize(st));
+            }
+            dfree(cls);
         }
 
         // workspace and solver buffers for one right-hand side; both grow on demand

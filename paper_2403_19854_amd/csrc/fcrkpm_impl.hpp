@@ -95,10 +95,13 @@ struct Ctx {
     float* rtab32[3] = {};              // per axis [2n+1][n]: Re (even e) or Im (odd e) of spec32
     bool use_regpath = true;            // register-resident passes where they apply
     uint32_t* nbits[2] = {};            // register path: interior bits per middle-pass lane, per layout
+    uint32_t* noff[2] = {};             // register path: first record of each lane, per layout
+    float* nrec[2] = {};                // register path: coefficient records (0: interior), per layout
     int reg_layout = 0;                 // register path: line layout (0: 8 lanes, 1: 16 lanes)
     float tune_ms[2] = {0.0f, 0.0f};    // register path: measured K product per layout (0: untimed)
+    long nload[2] = {-1, -1};           // register path: middle-pass elements reading the arrays
+    bool prof_dot = false;              // the sampled K product carries the fused p.q
     NodeConst nconst = {};              // values of the interior nodes
-    float* nctab = nullptr;             // the same on the device, each value twice (a float2)
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
     // and right-hand side (cap_work of them)
     cplx<double>* work64 = nullptr;
@@ -176,7 +179,11 @@ bool reg_path_ok(const Ctx& c);
 int reg_path_blocks(const Ctx& c);
 int reg_layouts(const Ctx& c);
 long reg_bits_words(const Ctx& c, int layout);
-void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, hipStream_t st);
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+                     unsigned long long* nload, hipStream_t st);
+void launch_reg_recs(const Ctx& c, int layout, const uint32_t* bits, const uint32_t* off,
+                     float* rec, hipStream_t st);
+int reg_record_floats();
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof);
 

@@ -268,9 +268,15 @@ struct RArgs {
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
     const float* dot_with;
     const uint32_t* nbits;    // middle pass: per lane, bit 2m+c set if node c of element m
-                              // takes the interior values (NULL: every node loads)
-    const float* ctab;        // middle pass: interior b^a_q and V, each stored twice (26 floats)
+                              // takes the interior values
+    const uint32_t* noff;     // middle pass: per lane, first record of its other elements
+    const float4* rec;        // middle pass: records of kRec floats (record 0: interior values)
 };
+
+// A record holds b^a_q (a-major, q minor) and V of the two nodes of one
+// element interleaved -- b_0(n0), b_0(n1), b_1(n0), ... , V(n0), V(n1) --
+// padded to 7 float4 so a lane reads it with 16-byte loads.
+constexpr int kRec = 28;
 
 // Position of the workgroup's Lay::LINES real lines: for a strided axis the
 // float index of line l0 at point 0 (the lines are adjacent in memory), for
@@ -482,20 +488,35 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     // two nodes are interior reads the 26-float table of shared values (one
     // cache line for the whole wave) instead of the coefficient arrays
     // (outside the domain b = 0, so those nodes read zeros)
-    const uint32_t bits = a.nbits ? a.nbits[xcd_tile(blockIdx.x, gridDim.x) * kRT + tid] : 0u;
+    const long lane = xcd_tile(blockIdx.x, gridDim.x) * kRT + tid;
+    const uint32_t bits = a.nbits[lane];
+    const uint32_t off = a.noff[lane];
+    uint32_t outer = 0;  // bit m: element m is not interior and reads its record
+#pragma unroll
+    for (int m = 0; m < R; ++m) outer |= (((bits >> (2 * m)) & 3u) != 3u ? 1u : 0u) << m;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const long idx = elem_index<Lay, false>(base, g, t, m, a.st);
-        const bool inner = ((bits >> (2 * m)) & 3u) == 3u;
-        const float* bp = inner ? a.ctab : a.ba + idx;
-        const long bs = inner ? 2 : a.nn;
+        // record 0 holds the interior values; one base pointer with a chosen
+        // index (not a choice of pointers) keeps the load single
+        const bool inner = !((outer >> m) & 1u);
+        const uint32_t km = __popc(outer & ((1u << m) - 1u));
+        const float4* src = a.rec + (size_t)(inner ? 0u : off + km) * (kRec / 4);
+        float rv[kRec];
+#pragma unroll
+        for (int j = 0; j < kRec / 4; ++j) {
+            const float4 f = src[j];
+            rv[4 * j] = f.x;
+            rv[4 * j + 1] = f.y;
+            rv[4 * j + 2] = f.z;
+            rv[4 * j + 3] = f.w;
+        }
         float2 b[3][S];
 #pragma unroll
         for (int al = 0; al < 3; ++al)
 #pragma unroll
             for (int q = 0; q < S; ++q)
-                b[al][q] = *reinterpret_cast<const float2*>(bp + (al * S + q) * bs);
-        const float2 v = *reinterpret_cast<const float2*>(inner ? a.ctab + 2 * 3 * S : a.vol + idx);
+                b[al][q] = float2{rv[2 * (al * S + q)], rv[2 * (al * S + q) + 1]};
+        const float2 v = float2{rv[2 * 3 * S], rv[2 * 3 * S + 1]};
         float A0[3], A1[3];
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
@@ -585,7 +606,8 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.ba = c.ba_32;
         a.vol = c.vol32;
         a.nbits = c.nbits[c.reg_layout];
-        a.ctab = c.nctab;
+        a.noff = c.noff[c.reg_layout];
+        a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         prof.begin(2, st);
         hipLaunchKernelGGL((k_rmid<Lay, 3, 3>), grid, block, 0, st, a);
         prof.end(2, st);
@@ -614,7 +636,8 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
 // Interior bits of every lane of the middle pass, in its own tile geometry.
 template <class Lay>
 __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
-                            uint32_t* __restrict__ bits)
+                            uint32_t* __restrict__ bits, uint32_t* __restrict__ count,
+                            unsigned long long* __restrict__ nload)
 {
     const long n = nblk * kRT;
     for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n;
@@ -629,15 +652,60 @@ __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
             if (cls[idx + 1] == 1) w |= 2u << (2 * m);
         }
         bits[s] = w;
+        int loads = 0;  // elements that read a record
+        for (int m = 0; m < Lay::PTS; ++m) loads += ((w >> (2 * m)) & 3u) != 3u;
+        count[s] = (uint32_t)loads;
+        if (loads) atomicAdd(nload, (unsigned long long)loads);
+    }
+}
+
+// The records of every lane's non-interior elements, in lane order.
+template <class Lay>
+__global__ void k_rmid_recs(const uint32_t* __restrict__ bits, const uint32_t* __restrict__ off,
+                            const float* __restrict__ ba, const float* __restrict__ vol, long st,
+                            long nblk, long nn, float* __restrict__ rec)
+{
+    constexpr int S = 4;
+    const long n = nblk * kRT;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n;
+         s += (long)gridDim.x * blockDim.x) {
+        const long tile = s / kRT;
+        const int lane = (int)(s % kRT), g = lane / Lay::LANES, t = lane % Lay::LANES;
+        const long base = tile_base<Lay, false>(tile, st);
+        const uint32_t w = bits[s];
+        long r = off[s];
+        for (int m = 0; m < Lay::PTS; ++m) {
+            if (((w >> (2 * m)) & 3u) == 3u) continue;
+            const long idx = elem_index<Lay, false>(base, g, t, m, st);
+            float* o = rec + r * kRec;
+            for (int q = 0; q < 3 * S; ++q) {
+                o[2 * q] = ba[q * nn + idx];
+                o[2 * q + 1] = ba[q * nn + idx + 1];
+            }
+            o[2 * 3 * S] = vol[idx];
+            o[2 * 3 * S + 1] = vol[idx + 1];
+            o[2 * 3 * S + 2] = 0.0f;
+            o[2 * 3 * S + 3] = 0.0f;
+            ++r;
+        }
     }
 }
 
 template <class Lay>
-void build_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+void build_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+                unsigned long long* nload, hipStream_t st)
 {
     const long str = (long)c.n[0] * c.n[1];
     hipLaunchKernelGGL((k_rmid_bits<Lay>), dim3(256), dim3(256), 0, st, cls, str, blocks_of<Lay>(c),
-                       bits);
+                       bits, count, nload);
+}
+
+template <class Lay>
+void build_recs(const Ctx& c, const uint32_t* bits, const uint32_t* off, float* rec, hipStream_t st)
+{
+    const long str = (long)c.n[0] * c.n[1];
+    hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_32, c.vol32,
+                       str, blocks_of<Lay>(c), c.nn, rec);
 }
 
 }  // namespace
@@ -651,15 +719,29 @@ long reg_bits_words(const Ctx& c, int layout)
     return blocks_of<G8<8>>(c) * kRT;
 }
 
-void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, hipStream_t st)
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+                     unsigned long long* nload, hipStream_t st)
 {
     if (c.n[0] == 128) {
-        if (layout) build_bits<G16>(c, cls, bits, st);
-        else build_bits<G8<16>>(c, cls, bits, st);
+        if (layout) build_bits<G16>(c, cls, bits, count, nload, st);
+        else build_bits<G8<16>>(c, cls, bits, count, nload, st);
     } else {
-        build_bits<G8<8>>(c, cls, bits, st);
+        build_bits<G8<8>>(c, cls, bits, count, nload, st);
     }
 }
+
+void launch_reg_recs(const Ctx& c, int layout, const uint32_t* bits, const uint32_t* off,
+                     float* rec, hipStream_t st)
+{
+    if (c.n[0] == 128) {
+        if (layout) build_recs<G16>(c, bits, off, rec, st);
+        else build_recs<G8<16>>(c, bits, off, rec, st);
+    } else {
+        build_recs<G8<8>>(c, bits, off, rec, st);
+    }
+}
+
+int reg_record_floats() { return kRec; }
 
 bool reg_path_ok(const Ctx& c)
 {
