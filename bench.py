@@ -47,6 +47,9 @@ def parse():
                     help="counter probe: setup, a refined solve capped at N CG iterations "
                          "(direct launches), then a 256 MiB device copy that calibrates the "
                          "memory counters; prints one line and exits")
+    ap.add_argument("--probe-variant", type=int, default=1,
+                    help="register-path variant for --probe (layout + 2 (tiles - 1)); the "
+                         "default is the one setup's autotuner picks for 128^3 on MI355X")
     ap.add_argument("--mode", default="f32_refined", choices=["f32_refined", "f64"])
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--maxit", type=int, default=100000)
@@ -197,10 +200,10 @@ def probe(a, wl):
     dev = torch.device("cuda:0")
     pb = fcrkpm.Problem.from_workload(wl, device=dev)
     pb.set_graphs(False)
-    # counter collection distorts setup's layout timing: measure the layout an
-    # ordinary run picks on MI355X (16 lanes per 128-point line) where it exists
+    # counter collection distorts setup's variant timing: measure the variant
+    # an ordinary run picks (--probe-variant), where the box has it
     try:
-        pb.set_option(fcrkpm.OPT_REGLAYOUT, 1)
+        pb.set_option(fcrkpm.OPT_REGLAYOUT, a.probe_variant)
     except fcrkpm.FcrkpmError:
         pass
     layout = pb.get_option(fcrkpm.OPT_REGLAYOUT)

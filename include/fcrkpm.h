@@ -233,11 +233,15 @@ enum {
     FCRKPM_OPT_REGPATH = 2,  /* 1 (default): FP32 K products on 64^3 and 128^3 boxes with the
                                 linear basis use register-resident line transforms; 0: the
                                 LDS-tiled passes used everywhere else */
-    FCRKPM_OPT_REGLAYOUT = 3, /* line layout of those transforms: 0 = 8 lanes per line, 1 = 16
-                                 lanes (128-point lines only).  Setup times a K product with
-                                 each and keeps the faster. */
-    FCRKPM_OPT_TUNE_NS0 = 4, /* read only: setup's time of one K product with layout 0, ns */
-    FCRKPM_OPT_TUNE_NS1 = 5  /* read only: the same with layout 1 (0 where not timed) */
+    FCRKPM_OPT_REGLAYOUT = 3, /* variant of those transforms, layout + 2 (tiles - 1): layout 0 =
+                                 8 lanes per line, 1 = 16 lanes (128-point lines only); tiles =
+                                 1 or 2 tiles per workgroup (the second tile's loads overlap the
+                                 first tile's work).  Setup times a K product with each variant
+                                 and keeps the fastest. */
+    FCRKPM_OPT_TUNE_NS0 = 4, /* read only: setup's time of one K product with variant 0, ns */
+    FCRKPM_OPT_TUNE_NS1 = 5, /* read only: the same with variant 1 (0 where not timed) */
+    FCRKPM_OPT_TUNE_NS2 = 6, /* read only: the same with variant 2 */
+    FCRKPM_OPT_TUNE_NS3 = 7  /* read only: the same with variant 3 */
 };
 /* Set an option; FCRKPM_ERR_ARG for an unknown option or a value out of range. */
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);

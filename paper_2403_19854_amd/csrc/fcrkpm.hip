@@ -449,7 +449,7 @@ double reg_pass_bytes(const Ctx& c, int k)
 {
     const double nn = (double)c.nn;
     switch (k) {
-        case 0: return nn * (4 + 1 + 2 * 4);
+        case 0: return nn * (4 + 1 + 2 * 4 + (c.prof_pupd ? 4 + 4 : 0));
         case 1: return nn * (2 * 4 + 3 * 4);
         case 2: {
             const double words = (double)reg_bits_words(c, c.reg_layout);
@@ -475,7 +475,7 @@ void regprof_end(const void* cv, int k, hipStream_t st)
 }
 
 void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, hipStream_t st,
-           double* dot_part = nullptr, const float* dot_with = nullptr)
+           double* dot_part = nullptr, const float* dot_with = nullptr, const RegPupd* pu = nullptr)
 {
     ensure_work(c, nrhs);
     RegProf rp;
@@ -486,7 +486,8 @@ void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, h
         c.prof_rhs = nrhs;
         c.prof_dot = dot_part != nullptr;
     }
-    launch_reg_k(c, in, out, mask, nrhs, dot_part, dot_with, st, rp);
+    c.prof_pupd = pu != nullptr;
+    launch_reg_k(c, in, out, mask, nrhs, dot_part, dot_with, st, rp, pu);
 }
 
 // One operator on nrhs consecutive fields, arithmetic precision T, field type
@@ -623,18 +624,33 @@ void dots(Ctx& c, const T* a, const T* b, int nrhs, int idx, hipStream_t st)
     launch_reduce_to(c.partial, c.nn, nrhs, c.scal + idx, st);
 }
 
+// the register-resident product can fold the CG direction update into its
+// first pass (FP32 vectors and products only)
+template <typename T, typename TP>
+bool fused_cg(Ctx& c, int nrhs)
+{
+    if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>)
+        return use_reg_path(c, nrhs) && reg_path_blocks(c) <= kRedBlocks;
+    else
+        return false;
+}
+
 // one CG iteration for all active right-hand sides: vectors of type T, K
-// products in precision TP
+// products in precision TP.  With `fused`, the product's first pass applies
+// the direction update left pending by the previous iteration (pend) and this
+// iteration leaves its own update pending unless `last`.
 template <typename T, typename TP = T>
-void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStream_t st)
+void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStream_t st,
+                  bool fused = false, bool pend = false, bool last = true)
 {
     double* pq_part = c.partial;
     double* rr_part = c.partial + (size_t)kRedBlocks * c.cap_rhs;
     int npq = red_blocks(c.nn);
     if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>) {
-        if (use_reg_path(c, nrhs) && reg_path_blocks(c) <= kRedBlocks) {
+        if (fused) {
             // the last pass of the product also leaves the p.q partials
-            reg_k(c, p, q, c.freem, nrhs, st, pq_part, p);
+            RegPupd pu{r, rr_part, red_blocks(c.nn), c.scal, parity ^ 1, c.act};
+            reg_k(c, p, q, c.freem, nrhs, st, pq_part, p, pend ? &pu : nullptr);
             npq = reg_path_blocks(c);
         } else {
             apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
@@ -645,7 +661,7 @@ void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStrea
         launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
     }
     launch_cg_xr<T>(x, r, p, q, c.nn, nrhs, pq_part, npq, c.scal, parity, rr_part, c.act, st);
-    launch_cg_p<T>(p, r, c.nn, nrhs, rr_part, c.scal, parity, c.act, st);
+    if (!fused || last) launch_cg_p<T>(p, r, c.nn, nrhs, rr_part, c.scal, parity, c.act, st);
 }
 
 constexpr int kCheck = 8;  // CG iterations per convergence poll (even: parity returns)
@@ -841,13 +857,17 @@ struct Solver {
     void enqueue(int nb, hipStream_t st)
     {
         int par = parity;
+        const bool fused = ph == PH_REFINED && mode == FCRKPM_MODE_F32_REFINED &&
+                           fused_cg<float, float>(c, nrhs);
         for (int i = 0; i < nb; ++i, par ^= 1) {
             if (ph == PH_F64)
                 cg_iteration<double>(c, vec64(c, V_X), vec64(c, V_R), vec64(c, V_P), vec64(c, V_Q),
                                      nrhs, par, st);
             else if (mode == FCRKPM_MODE_F32_REFINED)
+                // within a block the direction update of iteration i runs in the
+                // first pass of iteration i+1; the block ends with it applied
                 cg_iteration<float, float>(c, vec32(c, 0), vec32(c, 1), vec32(c, 2), vec32(c, 3),
-                                           nrhs, par, st);
+                                           nrhs, par, st, fused, i > 0, i == nb - 1);
             else
                 cg_iteration<double, float>(c, vec64(c, V_T), vec64(c, V_R), vec64(c, V_P),
                                             vec64(c, V_Q), nrhs, par, st);
@@ -1220,15 +1240,23 @@ fcrkpm_status run_guarded(std::string& err, const std::function<fcrkpm_status()>
 }  // namespace
 
 namespace {
-// Autotuner of the register-resident K passes: where a box admits more than
-// one line layout, time a few FP32 K products with each on this device and
-// keep the fastest (FCRKPM_REGLAYOUT=0/1 in the environment forces one).
+// Autotuner of the register-resident K passes: time a few FP32 K products
+// with each variant -- line layout (8 or 16 lanes) times tiles per workgroup
+// (1 or 2) -- on this device and keep the fastest.  FCRKPM_REGLAYOUT=v in the
+// environment forces variant v = layout + 2 (tiles - 1).
+void set_reg_variant(Ctx& c, int v)
+{
+    c.reg_layout = v & 1;
+    c.reg_tpw = (v >> 1) + 1;
+}
+
 void tune_reg_layout(Ctx& c, hipStream_t st)
 {
-    if (!reg_path_ok(c) || reg_layouts(c) < 2) return;
+    if (!reg_path_ok(c)) return;
     if (const char* e = getenv("FCRKPM_REGLAYOUT")) {
-        if (*e) {
-            c.reg_layout = (*e == '0') ? 0 : 1;
+        if (*e >= '0' && *e <= '3') {
+            const int v = *e - '0';
+            if (reg_variant_ok(c, v)) set_reg_variant(c, v);
             return;
         }
     }
@@ -1240,8 +1268,10 @@ void tune_reg_layout(Ctx& c, hipStream_t st)
     HIPCHK(hipEventCreate(&ev[1]));
     float best = 0.0f;
     int pick = 0;
-    for (int lay = 0; lay < reg_layouts(c); ++lay) {
-        c.reg_layout = lay;
+    for (int v = 0; v < 4; ++v) {
+        if (!reg_variant_ok(c, v)) continue;
+        const int lay = v;
+        set_reg_variant(c, v);
         reg_k(c, x, y, c.freem, 1, st);
         HIPCHK(hipEventRecord(ev[0], st));
         for (int r = 0; r < 5; ++r) reg_k(c, x, y, c.freem, 1, st);
@@ -1250,17 +1280,18 @@ void tune_reg_layout(Ctx& c, hipStream_t st)
         float ms = 0.0f;
         HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
         c.tune_ms[lay] = ms / 5.0f;
-        if (lay == 0 || ms < best) {
+        if (best == 0.0f || ms < best) {
             best = ms;
             pick = lay;
         }
     }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
-    c.reg_layout = pick;
+    set_reg_variant(c, pick);
     if (log_enabled())
-        fprintf(stderr, "[fcrkpm] register layouts: %.1f us (8 lanes), %.1f us (16 lanes); using %d\n",
-                1e3 * c.tune_ms[0], 1e3 * c.tune_ms[1], pick);
+        fprintf(stderr, "[fcrkpm] register variants (8 lanes, 16 lanes; x2 tiles): %.1f %.1f %.1f %.1f us;"
+                " using %d\n", 1e3 * c.tune_ms[0], 1e3 * c.tune_ms[1], 1e3 * c.tune_ms[2],
+                1e3 * c.tune_ms[3], pick);
 }
 }  // namespace
 
@@ -1757,9 +1788,11 @@ extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int6
         switch (option) {
             case FCRKPM_OPT_GRAPHS: *value = c.use_graphs ? 1 : 0; break;
             case FCRKPM_OPT_REGPATH: *value = (c.use_regpath && reg_path_ok(c)) ? 1 : 0; break;
-            case FCRKPM_OPT_REGLAYOUT: *value = c.reg_layout; break;
+            case FCRKPM_OPT_REGLAYOUT: *value = c.reg_layout + 2 * (c.reg_tpw - 1); break;
             case FCRKPM_OPT_TUNE_NS0: *value = (int64_t)(1e6 * c.tune_ms[0]); break;
             case FCRKPM_OPT_TUNE_NS1: *value = (int64_t)(1e6 * c.tune_ms[1]); break;
+            case FCRKPM_OPT_TUNE_NS2: *value = (int64_t)(1e6 * c.tune_ms[2]); break;
+            case FCRKPM_OPT_TUNE_NS3: *value = (int64_t)(1e6 * c.tune_ms[3]); break;
             default: fail(FCRKPM_ERR_ARG, "unknown option");
         }
         return FCRKPM_OK;
@@ -1781,9 +1814,9 @@ extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int6
                 c.use_regpath = value == 1;
                 break;
             case FCRKPM_OPT_REGLAYOUT:
-                if (value < 0 || value >= (reg_path_ok(c) ? reg_layouts(c) : 1))
+                if (!(reg_path_ok(c) ? reg_variant_ok(c, (int)value) : value == 0))
                     fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGLAYOUT out of range for this box");
-                c.reg_layout = (int)value;
+                set_reg_variant(c, (int)value);
                 break;
             default:
                 fail(FCRKPM_ERR_ARG, "unknown option");

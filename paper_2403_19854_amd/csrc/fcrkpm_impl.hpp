@@ -98,9 +98,12 @@ struct Ctx {
     uint32_t* noff[2] = {};             // register path: first record of each lane, per layout
     float* nrec[2] = {};                // register path: coefficient records (0: interior), per layout
     int reg_layout = 0;                 // register path: line layout (0: 8 lanes, 1: 16 lanes)
-    float tune_ms[2] = {0.0f, 0.0f};    // register path: measured K product per layout (0: untimed)
+    int reg_tpw = 1;                    // register path: tiles per workgroup (1 or 2)
+    float tune_ms[4] = {};              // register path: measured K product per variant
+                                        // (layout + 2 (tiles - 1)); 0: untimed
     long nload[2] = {-1, -1};           // register path: middle-pass elements reading the arrays
     bool prof_dot = false;              // the sampled K product carries the fused p.q
+    bool prof_pupd = false;             // ... and the fused direction update
     NodeConst nconst = {};              // values of the interior nodes
     // workspace: two slots of SepPlan::maxpairs complex fields per precision
     // and right-hand side (cap_work of them)
@@ -175,9 +178,21 @@ struct RegProf {
         if (end_fn) end_fn(c, k, st);
     }
 };
+// The CG direction update p = r + beta p that the first x pass of a K product
+// may apply to its input p before transforming it (beta from the r.r partials
+// of the previous x/r update, as the stand-alone update kernel computes it).
+struct RegPupd {
+    const float* r;
+    const double* rr_part;
+    int nrr;
+    double* scal;
+    int parity;
+    const int* act;
+};
 bool reg_path_ok(const Ctx& c);
 int reg_path_blocks(const Ctx& c);
 int reg_layouts(const Ctx& c);
+bool reg_variant_ok(const Ctx& c, int v);
 long reg_bits_words(const Ctx& c, int layout);
 void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, uint32_t* count,
                      unsigned long long* nload, hipStream_t st);
@@ -185,7 +200,8 @@ void launch_reg_recs(const Ctx& c, int layout, const uint32_t* bits, const uint3
                      float* rec, hipStream_t st);
 int reg_record_floats();
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
-                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof);
+                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
+                  const RegPupd* pu = nullptr);
 
 // LDS bytes the passes of a plan need at the tile widths they will use
 size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes);

@@ -271,6 +271,14 @@ struct RArgs {
                               // takes the interior values
     const uint32_t* noff;     // middle pass: per lane, first record of its other elements
     const float4* rec;        // middle pass: records of kRec floats (record 0: interior values)
+    // first x pass inside CG (PUPD): the pending direction update p = r + beta p
+    // with beta = (sum of rr_part) / scal[parity], written back to `in`
+    const float* rvec;
+    const double* rr_part;
+    int nrr;
+    double* scal;
+    int parity;
+    const int* act;
 };
 
 // A record holds b^a_q (a-major, q minor) and V of the two nodes of one
@@ -323,6 +331,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double r = 0.0;
@@ -378,7 +387,10 @@ struct Tables {
 // One separable pass: NIN real fields -> NOUT real fields along the axis.
 // LMASK: the single input is masked by mask_in.  SMASK: the single output is
 // masked by mask_out and, if dot_part is set, dotted with dot_with.
-template <class Lay, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT>
+// TPW tiles per workgroup: the inputs of all of them are loaded up front, so
+// the later tiles' loads overlap the earlier tiles' transforms and stores.
+template <class Lay, int TPW, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT,
+          bool PUPD = false>
 __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 {
     constexpr int L = Lay::L, R = Lay::PTS;
@@ -390,34 +402,65 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
-    const long base = tile_base<Lay, CONTIG>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
     Tables<L> tabs;
     tabs.fetch(a);
 
-    cf Z[NIN][R];
-#pragma unroll
-    for (int f = 0; f < NIN; ++f)
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
-            if constexpr (LMASK) {
-                const cf v = load_pair<L, CONTIG>(in, idx);
-                const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
-                Z[f][m] = cf{m0 ? v.x : 0.0f, m1 ? v.y : 0.0f};
-            } else {
-                Z[f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
-            }
+    // the pending CG direction update: the same reduction and arithmetic as
+    // the stand-alone update kernel, so the iterates are bit for bit the same
+    float beta = 0.0f;
+    bool upd = false;
+    if constexpr (PUPD) {
+        upd = a.act[rhs] != 0;
+        if (upd) {
+            double v = 0.0;
+            const double* part = a.rr_part + rhs * kRedBlocks;
+            for (int i = tid; i < a.nrr; i += kRT) v += part[i];
+            const double rr_new = block_sum(v, sh);
+            const double rr_old = a.scal[rhs * kScal + a.parity];
+            beta = rr_old > 0.0 ? float(rr_new / rr_old) : 0.0f;
+            if (blockIdx.x == 0 && tid == 0) a.scal[rhs * kScal + 1 - a.parity] = rr_new;
         }
-    tabs.put(a, tw, trl);
+    }
+
+    cf Z[TPW][NIN][R];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[f], t, xb, tw);
+    for (int tt = 0; tt < TPW; ++tt) {
+        const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
+#pragma unroll
+        for (int f = 0; f < NIN; ++f)
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
+                if constexpr (LMASK) {
+                    cf v = load_pair<L, CONTIG>(in, idx);
+                    if constexpr (PUPD) {
+                        if (upd) {
+                            const cf rv = load_pair<L, CONTIG>(a.rvec + rhs * a.in_rb, idx);
+                            v = cf{rv.x + beta * v.x, rv.y + beta * v.y};
+                            store_pair<L, CONTIG>(const_cast<float*>(in), idx, v);
+                        }
+                    }
+                    const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
+                    Z[tt][f][m] = cf{m0 ? v.x : 0.0f, m1 ? v.y : 0.0f};
+                } else {
+                    Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
+                }
+            }
+    }
+    tabs.put(a, tw, trl);
     const SepProg& pr = *a.pr;
     double dacc = 0.0;
 #pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+    const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
+#pragma unroll
+    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, tw);
+#pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<Lay, NIN>(pr, o, Z, Y, trl, t);
+        combine<Lay, NIN>(pr, o, Z[tt], Y, trl, t);
         Lay::inv(Y, t, xb, tw);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -436,6 +479,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
             }
         }
     }
+    }
     if constexpr (SMASK) {
         if (a.dot_part) {
             const double s = block_sum(dacc, sh);
@@ -448,7 +492,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 // (s = 4): the part-1 convolutions give D_q, the pointwise stage forms
 // A^a = sum_q b^a_q D_q and E_p = V sum_a b^a_p A^a at every node (Eq 90-91,
 // Alg 2), and the part-2 convolutions of E_p follow -- all in registers.
-template <class Lay, int NIN, int NOUT>
+template <class Lay, int TPW, int NIN, int NOUT>
 __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 {
     constexpr int L = Lay::L, R = Lay::PTS;
@@ -460,27 +504,34 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
-    const long base = tile_base<Lay, false>(xcd_tile(blockIdx.x, gridDim.x), a.st);
+    const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
     Tables<L> tabs;
     tabs.fetch(a);
 
-    cf D[S][R];
-    {
-        cf Z[NIN][R];
+    cf Z[TPW][NIN][R];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const long base = tile_base<Lay, false>(tile0 + tt, a.st);
 #pragma unroll
         for (int f = 0; f < NIN; ++f)
 #pragma unroll
             for (int m = 0; m < R; ++m)
-                Z[f][m] = load_pair<L, false>(in + f * a.fstride,
-                                              elem_index<Lay, false>(base, g, t, m, a.st));
-        tabs.put(a, tw, trl);
+                Z[tt][f][m] = load_pair<L, false>(in + f * a.fstride,
+                                                  elem_index<Lay, false>(base, g, t, m, a.st));
+    }
+    tabs.put(a, tw, trl);
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[f], t, xb, tw);
+    for (int tt = 0; tt < TPW; ++tt) {
+    const long base = tile_base<Lay, false>(tile0 + tt, a.st);
+    cf D[S][R];
+    {
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, tw);
         const SepProg& pr = *a.pr;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            combine<Lay, NIN>(pr, q, Z, D[q], trl, t);
+            combine<Lay, NIN>(pr, q, Z[tt], D[q], trl, t);
             Lay::inv(D[q], t, xb, tw);
         }
     }
@@ -488,7 +539,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     // two nodes are interior reads the 26-float table of shared values (one
     // cache line for the whole wave) instead of the coefficient arrays
     // (outside the domain b = 0, so those nodes read zeros)
-    const long lane = xcd_tile(blockIdx.x, gridDim.x) * kRT + tid;
+    const long lane = (tile0 + tt) * kRT + tid;
     const uint32_t bits = a.nbits[lane];
     const uint32_t off = a.noff[lane];
     uint32_t outer = 0;  // bit m: element m is not interior and reads its record
@@ -552,21 +603,23 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
         for (int m = 0; m < R; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, g, t, m, a.st), Y[m]);
     }
+    }
 }
 
 template <class Lay>
 long blocks_of(const Ctx& c) { return c.nn / Lay::L / Lay::LINES; }
 
-template <class Lay>
+template <class Lay, int TPW>
 void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
-           double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
+           double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
+           const RegPupd* pu)
 {
     const SepPlan& sp = c.basis_plan;
     const long nn = c.nn;
     const long slot_rb = 2L * sp.maxpairs * nn;  // floats between rhs in a workspace slot
     float* S1 = reinterpret_cast<float*>(c.work32);
     float* S2 = S1 + slot_rb * c.cap_work;
-    const dim3 grid((unsigned)blocks_of<Lay>(c), (unsigned)nrhs), block(kRT);
+    const dim3 grid((unsigned)(blocks_of<Lay>(c) / TPW), (unsigned)nrhs), block(kRT);
     auto args = [&](int axis, const float* i, long irb, float* o, long orb) {
         RArgs a{};
         a.in = i;
@@ -581,13 +634,23 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.nn = nn;
         return a;
     };
-    // x: u (masked) -> X
+    // x: u (masked) -> X, in CG with the pending direction update of u = p
     {
         RArgs a = args(0, in, nn, S1, slot_rb);
         a.mask_in = mask;
         a.pr = sp.d1[0];
         prof.begin(0, st);
-        hipLaunchKernelGGL((k_rpass<Lay, true, true, false, 1, 2>), grid, block, 0, st, a);
+        if (pu) {
+            a.rvec = pu->r;
+            a.rr_part = pu->rr_part;
+            a.nrr = pu->nrr;
+            a.scal = pu->scal;
+            a.parity = pu->parity;
+            a.act = pu->act;
+            hipLaunchKernelGGL((k_rpass<Lay, TPW, true, true, false, 1, 2, true>), grid, block, 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_rpass<Lay, TPW, true, true, false, 1, 2>), grid, block, 0, st, a);
+        }
         prof.end(0, st);
     }
     // y: X -> XY
@@ -595,7 +658,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
         a.pr = sp.d1[1];
         prof.begin(1, st);
-        hipLaunchKernelGGL((k_rpass<Lay, false, false, false, 2, 3>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 2, 3>), grid, block, 0, st, a);
         prof.end(1, st);
     }
     // z: XY -> D -> E -> part-2 XY
@@ -609,7 +672,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.noff = c.noff[c.reg_layout];
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         prof.begin(2, st);
-        hipLaunchKernelGGL((k_rmid<Lay, 3, 3>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rmid<Lay, TPW, 3, 3>), grid, block, 0, st, a);
         prof.end(2, st);
     }
     // y: XY -> X
@@ -617,7 +680,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
         a.pr = sp.d2[1];
         prof.begin(3, st);
-        hipLaunchKernelGGL((k_rpass<Lay, false, false, false, 3, 2>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 3, 2>), grid, block, 0, st, a);
         prof.end(3, st);
     }
     // x: X -> f (masked), with the optional dot partials
@@ -628,7 +691,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.dot_part = dot_part;
         a.dot_with = dot_with;
         prof.begin(4, st);
-        hipLaunchKernelGGL((k_rpass<Lay, true, false, true, 2, 1>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_rpass<Lay, TPW, true, false, true, 2, 1>), grid, block, 0, st, a);
         prof.end(4, st);
     }
 }
@@ -713,6 +776,14 @@ void build_recs(const Ctx& c, const uint32_t* bits, const uint32_t* off, float* 
 // layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only)
 int reg_layouts(const Ctx& c) { return c.n[0] == 128 ? 2 : 1; }
 
+// variant v = layout + 2 (tiles - 1); 8-lane 128-point lines with 2 tiles
+// per workgroup need more registers than a wave has, so that one is absent
+bool reg_variant_ok(const Ctx& c, int v)
+{
+    if (v < 0 || v > 3 || (v & 1) >= reg_layouts(c)) return false;
+    return !(c.n[0] == 128 && v == 2);
+}
+
 long reg_bits_words(const Ctx& c, int layout)
 {
     if (c.n[0] == 128) return (layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c)) * kRT;
@@ -757,21 +828,31 @@ bool reg_path_ok(const Ctx& c)
     return c.n[1] == L && c.n[2] == L;
 }
 
+// workgroups of one launch (each covers reg_tpw tiles)
 int reg_path_blocks(const Ctx& c)
 {
-    if (c.n[0] == 128) return (int)(c.reg_layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c));
-    return (int)blocks_of<G8<8>>(c);
+    long b;
+    if (c.n[0] == 128) b = c.reg_layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c);
+    else b = blocks_of<G8<8>>(c);
+    return (int)(b / c.reg_tpw);
 }
 
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
-                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof)
+                  double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
+                  const RegPupd* pu)
 {
+#define FC_RUN(LAY)                                                                       \
+    do {                                                                                  \
+        if (c.reg_tpw == 2) run_k<LAY, 2>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu); \
+        else run_k<LAY, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);        \
+    } while (0)
     if (c.n[0] == 128) {
-        if (c.reg_layout) run_k<G16>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
-        else run_k<G8<16>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+        if (c.reg_layout) FC_RUN(G16);
+        else run_k<G8<16>, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);  // 2 tiles spill
     } else {
-        run_k<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+        FC_RUN(G8<8>);
     }
+#undef FC_RUN
 }
 
 }  // namespace fcrkpm

@@ -41,6 +41,8 @@ OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
 OPT_TUNE_NS0 = 4
 OPT_TUNE_NS1 = 5
+OPT_TUNE_NS2 = 6
+OPT_TUNE_NS3 = 7
 
 
 class Grid(C.Structure):

@@ -27,11 +27,19 @@ COPY_BYTES = 256 << 20
 # demangled kernel name -> the kind name the library's sampler reports
 _KINDS = [
     (r"k_rmid<", "sep_mid_k_f32"),
-    (r"k_rpass<[^,]+, true, true, false, 1, 2>", "sep_part1_x_f32"),
-    (r"k_rpass<[^,]+, false, false, false, 2, 3>", "sep_part1_y_f32"),
-    (r"k_rpass<[^,]+, false, false, false, 3, 2>", "sep_part2_y_f32"),
-    (r"k_rpass<[^,]+, true, false, true, 2, 1>", "sep_part2_x_f32"),
+    (r"k_rpass<[^,]+, \d, true, true, false, 1, 2(, (true|false))?>", "sep_part1_x_f32"),
+    (r"k_rpass<[^,]+, \d, false, false, false, 2, 3(, (true|false))?>", "sep_part1_y_f32"),
+    (r"k_rpass<[^,]+, \d, false, false, false, 3, 2(, (true|false))?>", "sep_part2_y_f32"),
+    (r"k_rpass<[^,]+, \d, true, false, true, 2, 1(, (true|false))?>", "sep_part2_x_f32"),
 ]
+
+
+def _variant(name):
+    """Register-path variant of a kernel name: layout + 2 (tiles - 1)."""
+    m = re.search(r"k_r(?:pass|mid)<[^,]*?(G16|G8<\d+>), (\d)", name)
+    if not m:
+        return None
+    return (1 if m.group(1) == "G16" else 0) + 2 * (int(m.group(2)) - 1)
 
 
 def source_hash() -> str:
@@ -76,7 +84,7 @@ def summarize(fetch_csv, write_csv, out_json, workload, command):
                 if kind in kinds and kinds[kind]["dispatches"] >= len(fv[name]):
                     continue  # keep the layout the solve ran (most dispatches)
                 kinds[kind] = {"kernel": re.sub(r"\(.*", "", name.replace("(anonymous namespace)::", "")),
-                               "layout": 1 if "G16" in name else 0,
+                               "layout": _variant(name),
                                "dispatches": len(fv[name]), "fetch_bytes": f, "write_bytes": w,
                                "bytes_per_launch": f + w}
     out = {"workload": workload, "source_hash": source_hash(), "copy_bytes": COPY_BYTES,

@@ -381,9 +381,11 @@ def test_register_path_matches_lds_path_and_oracle(n):
     ref = o.apply_k_at(np.where(p.free > 0, x, 0.0), idx)
     ref = np.where(p.free.reshape(-1)[idx] > 0, ref, 0.0)
     chosen = g.get_option(fcrkpm.OPT_REGLAYOUT)
-    layouts = [0, 1] if n == 128 else [0]
-    print(f"  autotuned layout {chosen}; setup times (ns) "
-          f"{g.get_option(fcrkpm.OPT_TUNE_NS0)} {g.get_option(fcrkpm.OPT_TUNE_NS1)}")
+    layouts = [0, 1, 3] if n == 128 else [0, 2]
+    print(f"  autotuned variant {chosen}; setup times (ns) "
+          f"{[g.get_option(o) for o in (fcrkpm.OPT_TUNE_NS0, fcrkpm.OPT_TUNE_NS1, fcrkpm.OPT_TUNE_NS2, fcrkpm.OPT_TUNE_NS3)]}")
+    with pytest.raises(fcrkpm.FcrkpmError):
+        g.set_option(fcrkpm.OPT_REGLAYOUT, 2 if n == 128 else 1)
     for lay in layouts:
         g.set_option(fcrkpm.OPT_REGLAYOUT, lay)
         reg = to_np(g.apply("K", xt)).astype(np.float64)
