@@ -137,16 +137,36 @@ __device__ __forceinline__ float swap8(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
 }
 
+// The twiddles one G16 lane needs, fixed for the whole kernel: the forward
+// W_128^{t k1} (k1 = 1..7), the W_16^{tl h} of its half (1 on h = 0) and the
+// inverse W_128^{-(tl + 8h) (t & 7)} (tl = 0..7).  Computed once per lane from
+// the LDS table, so the transforms read no twiddles and select nothing.
+struct G16Tw {
+    cf f[7], h[7], i[8];
+    __device__ __forceinline__ void make(int t, const cf* tw)
+    {
+        const int k1 = t & 7, hh = t >> 3;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            f[j - 1] = tw[t * j];
+            const cf w = mul_w16<+1>(cf{1.0f, 0.0f}, j);
+            h[j - 1] = hh ? w : cf{1.0f, 0.0f};
+        }
+#pragma unroll
+        for (int tl = 0; tl < 8; ++tl) i[tl] = twid<-1>(tw, (tl + 8 * hh) * k1);
+    }
+};
+
 // G16 forward transform (L = 128).  In: v[m] = x[t + 16m].  Out: v[i] =
 // X[t + 16i].  With t = k1 + 8h the steps are a DFT-8 over m, the twiddle
 // W_128^{t k1}, a transpose giving lane (k1, h) the values of lanes
 // 8h .. 8h+7 at k1, a radix-2 step across h, the twiddle W_16^{tl h} and a
 // DFT-8 over the lane offset tl.
-__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const cf* tw)
+__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const G16Tw& w)
 {
     dft8<float, +1>(v);
 #pragma unroll
-    for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], twid<+1>(tw, t * k1));
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], w.f[k1 - 1]);
 #pragma unroll
     for (int k1 = 0; k1 < 8; ++k1) xb[k1 * 17 + t] = v[k1];
     wave_sync();
@@ -161,24 +181,18 @@ __device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const cf* tw)
         v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
     }
 #pragma unroll
-    for (int tl = 1; tl < 8; ++tl) {
-        const cf w = mul_w16<+1>(v[tl], tl);
-        v[tl] = h ? w : v[tl];
-    }
+    for (int tl = 1; tl < 8; ++tl) v[tl] = cmul(v[tl], w.h[tl - 1]);
     dft8<float, +1>(v);
 }
 
 // G16 unnormalised inverse: v[i] = X[t + 16i] in, v[m] = x[t + 16m] out (the
 // steps of g16_fwd reversed, with conjugate twiddles).
-__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const cf* tw)
+__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const G16Tw& w)
 {
     const int k1 = t & 7, h = t >> 3;
     dft8<float, -1>(v);
 #pragma unroll
-    for (int tl = 1; tl < 8; ++tl) {
-        const cf w = mul_w16<-1>(v[tl], tl);
-        v[tl] = h ? w : v[tl];
-    }
+    for (int tl = 1; tl < 8; ++tl) v[tl] = cmulc(v[tl], w.h[tl - 1]);
     const float s = h ? -1.0f : 1.0f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -186,10 +200,7 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const cf* tw)
         v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
     }
 #pragma unroll
-    for (int tl = 0; tl < 8; ++tl) {
-        const int tt = tl + 8 * h;
-        xb[k1 * 17 + tt] = cmul(v[tl], twid<-1>(tw, tt * k1));
-    }
+    for (int tl = 0; tl < 8; ++tl) xb[k1 * 17 + tl + 8 * h] = cmul(v[tl], w.i[tl]);
     wave_sync();
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = xb[j * 17 + t];
@@ -201,22 +212,30 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const cf* tw)
 // point m and the frequency of spectral slot i held by lane t, and the LDS
 // complex values of one group's transpose buffer (the group stride is 8 mod
 // 32 so the groups of a wave spread over the banks).
+// G8 reads its twiddles from the LDS table as it goes
+struct LdsTw {
+    const cf* tw;
+    __device__ __forceinline__ void make(int, const cf* table) { tw = table; }
+};
+
 template <int R>
 struct G8 {
     static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    typedef LdsTw Tw;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
-    static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const cf* tw) { g8_fwd<R>(v, t, xb, tw); }
-    static __device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const cf* tw) { g8_inv<R>(v, t, xb, tw); }
+    static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_fwd<R>(v, t, xb, w.tw); }
+    static __device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_inv<R>(v, t, xb, w.tw); }
 };
 struct G16 {
     static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    typedef G16Tw Tw;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
-    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const cf* tw) { g16_fwd(v, t, xb, tw); }
-    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const cf* tw) { g16_inv(v, t, xb, tw); }
+    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
+    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
 };
 
 // Y <- sum over the terms of output o of 2 coef T_e o Z_in (spectra in fwd's
@@ -450,18 +469,20 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
             }
     }
     tabs.put(a, tw, trl);
+    typename Lay::Tw lw;
+    lw.make(t, tw);
     const SepProg& pr = *a.pr;
     double dacc = 0.0;
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
     const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, tw);
+    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, lw);
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
         combine<Lay, NIN>(pr, o, Z[tt], Y, trl, t);
-        Lay::inv(Y, t, xb, tw);
+        Lay::inv(Y, t, xb, lw);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
@@ -521,18 +542,20 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
                                                   elem_index<Lay, false>(base, g, t, m, a.st));
     }
     tabs.put(a, tw, trl);
+    typename Lay::Tw lw;
+    lw.make(t, tw);
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
     const long base = tile_base<Lay, false>(tile0 + tt, a.st);
     cf D[S][R];
     {
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, tw);
+        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, lw);
         const SepProg& pr = *a.pr;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             combine<Lay, NIN>(pr, q, Z[tt], D[q], trl, t);
-            Lay::inv(D[q], t, xb, tw);
+            Lay::inv(D[q], t, xb, lw);
         }
     }
     // pointwise stage on both lines of every complex element; an element whose
@@ -592,13 +615,13 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
         }
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p) Lay::fwd(D[p], t, xb, tw);
+    for (int p = 0; p < S; ++p) Lay::fwd(D[p], t, xb, lw);
     const SepProg& pr2 = *a.pr2;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
         combine<Lay, S>(pr2, o, D, Y, trl, t);
-        Lay::inv(Y, t, xb, tw);
+        Lay::inv(Y, t, xb, lw);
 #pragma unroll
         for (int m = 0; m < R; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, g, t, m, a.st), Y[m]);
