@@ -94,10 +94,11 @@ def summarize(fetch_csv, write_csv, out_json, workload, command):
     return out
 
 
-def load(workload, kind, layout=None):
+def load(workload, kind, layout=None, path=None):
     """Measured bytes per launch of `kind`, or None if not measured for the
-    current kernel sources (and, if given, the same line layout)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    current kernel sources (and, if given, the same register variant)."""
+    if path is None:
+        path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
