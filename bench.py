@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="run exactly N CG iterations per step instead of solving to --tol "
+                         "(throughput of workloads whose CG converges too slowly, e.g. c3)")
     return ap.parse_args()
 
 
@@ -90,7 +93,11 @@ def main():
         pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
         if profile:
             pb.profile(True)
-        d, uh, info = pb.solve(r, mode=mode, tol=a.tol, maxit=a.maxit, want_uh=True)
+        if a.fixed_iters:
+            d, uh, info = pb.solve(r, mode=mode, tol=1e-300, maxit=a.fixed_iters, want_uh=True,
+                                   raise_on_noconv=False)
+        else:
+            d, uh, info = pb.solve(r, mode=mode, tol=a.tol, maxit=a.maxit, want_uh=True)
         info["layout"] = pb.get_option(fcrkpm.OPT_REGLAYOUT)
         prof = None
         if profile:
@@ -142,8 +149,10 @@ def main():
         "dtype": "f32+f64" if a.mode == "f32_refined" else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "box": list(wl.dims), "support": wl.at[0],
-                   "degree": wl.degree, "free_unknowns": n_free, "mode": a.mode, "tol": a.tol,
-                   "step": "setup + f^r + CG to tol + u^h"},
+                   "degree": wl.degree, "free_unknowns": n_free, "mode": a.mode,
+                   "tol": None if a.fixed_iters else a.tol,
+                   "step": (f"setup + f^r + {a.fixed_iters} CG iterations + u^h" if a.fixed_iters
+                            else "setup + f^r + CG to tol + u^h")},
         "dof_per_s": value * n_free,
         "solve": {"iters": infos[-1]["iters"], "outer_iters": infos[-1]["outer_iters"],
                   "matvecs_f32": infos[-1]["matvecs_f32"],
@@ -251,7 +260,8 @@ def bench_c4(a):
         torch.cuda.synchronize()
         return node_mv / (time.perf_counter() - t0), (time.perf_counter() - t0) / steps
 
-    run(True, a.warmup)
+    if a.warmup > 0:
+        run(True, a.warmup)
     v_graph, t_graph = run(True, a.steps)
     v_direct, t_direct = run(False, a.steps)
     out = {
