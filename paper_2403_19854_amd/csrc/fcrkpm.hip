@@ -1428,13 +1428,14 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
             c.spec64[a] = dalloc<cplx<double>>(sp.size());
             c.spec32[a] = dalloc<cplx<float>>(spf.size());
             {
-                // t_e is even (e even) or odd (e odd) in its offset, so its
-                // spectrum is real or imaginary: keep that part alone
-                std::vector<float> rt((size_t)ne * L);
-                for (int e = 0; e < ne; ++e)
+                // t_0 is even and t_1 odd in the offset, so T_0 is real and T_1
+                // imaginary: the register passes take Re T_0 and Im T_1, each
+                // with the 1/L of the inverse transform folded in
+                std::vector<float> rt((size_t)2 * L, 0.0f);
+                for (int e = 0; e < 2 && e < ne; ++e)
                     for (int kk = 0; kk < L; ++kk)
-                        rt[(size_t)e * L + kk] = (e & 1) ? (float)sp[(size_t)e * L + kk].y
-                                                         : (float)sp[(size_t)e * L + kk].x;
+                        rt[(size_t)e * L + kk] = (float)((e ? sp[(size_t)e * L + kk].y
+                                                            : sp[(size_t)e * L + kk].x) / L);
                 c.rtab32[a] = dalloc<float>(rt.size());
                 HIPCHK(hipMemcpyAsync(c.rtab32[a], rt.data(), sizeof(float) * rt.size(),
                                       hipMemcpyHostToDevice, st));

@@ -92,7 +92,7 @@ struct Ctx {
     cplx<float>* tw32[3] = {};
     cplx<double>* spec64[3] = {};       // kernel spectra per axis, exponents 0..2n
     cplx<float>* spec32[3] = {};
-    float* rtab32[3] = {};              // per axis [2n+1][n]: Re (even e) or Im (odd e) of spec32
+    float* rtab32[3] = {};              // per axis [2][n]: Re T_0 / n, Im T_1 / n (register passes)
     bool use_regpath = true;            // register-resident passes where they apply
     uint32_t* nbits[2] = {};            // register path: interior bits per middle-pass lane, per layout
     uint32_t* noff[2] = {};             // register path: first record of each lane, per layout

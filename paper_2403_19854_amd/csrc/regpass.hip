@@ -23,6 +23,9 @@
 // pointwise stage of the middle pass all act on registers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "fcrkpm_impl.hpp"
 
 namespace fcrkpm {
@@ -31,7 +34,6 @@ namespace {
 typedef cplx<float> cf;
 
 constexpr int kRT = 256;             // threads per workgroup
-constexpr int kRMaxE = 3;            // kernel exponents 0 .. 2n for n = 1
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -131,10 +133,11 @@ __device__ __forceinline__ void g8_inv(cf (&v)[R], int t, cf* xb, const cf* tw)
     dftR_reg<R, -1>(v);
 }
 
-// the value of lane t ^ 8 within the lane's row of 16 (DPP row rotation by 8)
+// the value of lane t ^ 8 within the lane's row of 16 (DPP row rotation by 8;
+// every lane has a source, so no old value is needed)
 __device__ __forceinline__ float swap8(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x128, 0xF, 0xF, true));
 }
 
 // The twiddles one G16 lane needs, fixed for the whole kernel: the forward
@@ -208,6 +211,45 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const G16Tw& 
     dft8<float, -1>(v);
 }
 
+// The lane's values of the axis's two kernel spectra, each divided by L (the
+// 1/L of the inverse transform): T_0 is real (t_0 even) and T_1 imaginary
+// (t_1 odd), so one float per frequency describes each.  G16 holds its 8
+// frequencies of both in registers; G8 reads them from the LDS copy.
+struct SpecRegs {
+    float s0[8], s1[8];
+    template <class Lay>
+    __device__ __forceinline__ void fetch(const float* tab, int t)
+    {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            s0[i] = tab[Lay::freq(t, i)];
+            s1[i] = tab[Lay::L + Lay::freq(t, i)];
+        }
+    }
+    template <class Lay>
+    __device__ __forceinline__ void bind(const float*, int) {}
+    template <class Lay>
+    __device__ __forceinline__ float e0(int i) const { return s0[i]; }
+    template <class Lay>
+    __device__ __forceinline__ float e1(int i) const { return s1[i]; }
+};
+struct SpecLds {
+    const float* trl;
+    int t;
+    template <class Lay>
+    __device__ __forceinline__ void fetch(const float*, int) {}
+    template <class Lay>
+    __device__ __forceinline__ void bind(const float* tab, int lane)
+    {
+        trl = tab;
+        t = lane;
+    }
+    template <class Lay>
+    __device__ __forceinline__ float e0(int i) const { return trl[Lay::freq(t, i)]; }
+    template <class Lay>
+    __device__ __forceinline__ float e1(int i) const { return trl[Lay::L + Lay::freq(t, i)]; }
+};
+
 // Line layouts: lanes per complex line, points per lane, the spatial row of
 // point m and the frequency of spectral slot i held by lane t, and the LDS
 // complex values of one group's transpose buffer (the group stride is 8 mod
@@ -223,6 +265,7 @@ struct G8 {
     static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     typedef LdsTw Tw;
+    typedef SpecLds Spec;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
     static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_fwd<R>(v, t, xb, w.tw); }
@@ -232,40 +275,75 @@ struct G16 {
     static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     typedef G16Tw Tw;
+    typedef SpecRegs Spec;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
     static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
     static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
 };
 
-// Y <- sum over the terms of output o of 2 coef T_e o Z_in (spectra in fwd's
-// layout).  The factor 2 undoes the 1/2 that the pair-separating passes keep
-// in the coefficients; the 1/L of the inverse transform stays in coef.
-template <class Lay, int NIN, int R = Lay::PTS>
-__device__ __forceinline__ void combine(const SepProg& pr, int o, const cf (&Z)[NIN][R], cf (&Y)[R],
-                                        const float* trl, int t)
+// Term structure of the K d passes for the linear basis in 3D, monomials in
+// graded order (1, x, y, z).  Part 1 along axis j forms output o from input
+// kP1In[j][o] with the kernel t_{kP1E[j][o]}; part 2 forms output o from input
+// kP2A[j][o] with t_0 and, where kP2B[j][o] >= 0, from input kP2B[j][o] with
+// the reflected t_1 (Eq 55, 77-78).  reg_path_ok checks the pass programs of
+// the basis against these tables before the register path is used.
+constexpr int kP1In[3][4] = {{0, 0, -1, -1}, {0, 1, 0, -1}, {0, 1, 2, 0}};
+constexpr int kP1E[3][4] = {{0, 1, -1, -1}, {0, 0, 1, -1}, {0, 0, 0, 1}};
+constexpr int kP2A[3][3] = {{0, -1, -1}, {0, 1, -1}, {0, 1, 2}};
+constexpr int kP2B[3][3] = {{1, -1, -1}, {2, -1, -1}, {3, -1, -1}};
+
+// Spectra of output O (in fwd's layout) from the input spectra Z.  Part 1
+// (more outputs than inputs): Y = T_e Z_in.  Part 2: Y = T_0 Z_a - T_1 Z_b
+// (the reflected odd kernel has the conjugate spectrum).
+template <class Lay, int NIN, int NOUT, int O, int R, class Sp>
+__device__ __forceinline__ void combine_o(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp)
 {
-    constexpr int L = Lay::L;
+    if constexpr (NOUT > NIN) {
+        constexpr int J = NOUT - 2, IN = kP1In[J][O];
+        static_assert(IN >= 0 && IN < NIN, "part-1 term");
 #pragma unroll
-    for (int i = 0; i < R; ++i) Y[i] = cf{0.0f, 0.0f};
-    const int t0 = pr.ostart[o], t1 = pr.ostart[o + 1];
-    for (int tt = t0; tt < t1; ++tt) {
-        const SepTerm tm = pr.t[tt];
-        const float c2 = float(2.0 * tm.coef);
-        const float* T = trl + tm.e * L;
-        const bool odd = tm.e & 1;
+        for (int i = 0; i < R; ++i) {
+            const cf z = Z[IN][i];
+            if constexpr (kP1E[J][O] == 0) {
+                const float a = sp.template e0<Lay>(i);
+                Y[i] = cf{a * z.x, a * z.y};
+            } else {
+                const float b = sp.template e1<Lay>(i);
+                Y[i] = cf{-b * z.y, b * z.x};
+            }
+        }
+    } else {
+        constexpr int J = NIN - 2, A = kP2A[J][O], B = kP2B[J][O];
+        static_assert(A >= 0 && A < NIN && B < NIN, "part-2 terms");
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) {
-            if (f != tm.in) continue;
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const float s = c2 * T[Lay::freq(t, i)];
-                const cf z = Z[f][i];
-                if (odd) Y[i] = cf{Y[i].x - s * z.y, Y[i].y + s * z.x};
-                else Y[i] = cf{Y[i].x + s * z.x, Y[i].y + s * z.y};
+        for (int i = 0; i < R; ++i) {
+            const float a = sp.template e0<Lay>(i);
+            const cf za = Z[A][i];
+            if constexpr (B >= 0) {
+                const float b = sp.template e1<Lay>(i);
+                const cf zb = Z[B][i];
+                Y[i] = cf{a * za.x + b * zb.y, a * za.y - b * zb.x};
+            } else {
+                Y[i] = cf{a * za.x, a * za.y};
             }
         }
     }
+}
+
+template <class Lay, int NIN, int NOUT, int R, class Sp, int... O>
+__device__ __forceinline__ void combine_sel(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp,
+                                            std::integer_sequence<int, O...>)
+{
+    ((o == O ? combine_o<Lay, NIN, NOUT, O>(Z, Y, sp) : void()), ...);
+}
+
+// o is constant once the caller's loop over the outputs is unrolled, so the
+// selection folds away
+template <class Lay, int NIN, int NOUT, int R, class Sp>
+__device__ __forceinline__ void combine(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp)
+{
+    combine_sel<Lay, NIN, NOUT>(Z, o, Y, sp, std::make_integer_sequence<int, NOUT>{});
 }
 
 struct RArgs {
@@ -276,11 +354,8 @@ struct RArgs {
     long fstride;             // floats between fields
     long in_rb, out_rb;       // floats between right-hand sides (blockIdx.y)
     long st;                  // element stride of the axis; 1 for x
-    const SepProg* pr;        // pass program (the middle pass: part 1)
-    const SepProg* pr2;       // middle pass: part 2
-    const float* tr;          // [ne][L] real or imaginary part of each kernel spectrum
+    const float* tr;          // [2][L]: Re T_0 / L, Im T_1 / L of the axis
     const cf* tw;             // [L] e^{-2 pi i j / L}
-    int ne;
     const float* ba;          // middle pass: b^a [3][4][nn]
     const float* vol;         // middle pass: V [nn]
     long nn;
@@ -365,15 +440,19 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks)
     return (b & 7) * (nblocks >> 3) + (b >> 3);
 }
 
-// The twiddle and spectrum tables of the axis: each thread loads its share
-// into registers (fetch) and writes it to LDS later (put), so the loads of
-// the tables and of the input lines are in flight together.
-template <int L>
+// The twiddle table of the axis and, for layouts that read the spectra from
+// LDS, the spectra: each thread loads its share into registers (fetch) and
+// writes it to LDS later (put), so these loads and those of the input lines
+// are in flight together.
+template <class Lay>
 struct Tables {
-    static constexpr int NT = (L + kRT - 1) / kRT;             // twiddles per thread
-    static constexpr int NS = (kRMaxE * L + kRT - 1) / kRT;    // spectrum values per thread
+    static constexpr int L = Lay::L;
+    static constexpr bool SPEC = std::is_same<typename Lay::Spec, SpecLds>::value;
+    static constexpr int NT = (L + kRT - 1) / kRT;                    // twiddles per thread
+    static constexpr int NS = SPEC ? (2 * L + kRT - 1) / kRT : 0;     // spectrum values per thread
+    static constexpr int LDS_SPEC = SPEC ? 2 * L : 1;                 // floats of the LDS copy
     cf w[NT];
-    float s[NS];
+    float s[NS > 0 ? NS : 1];
     __device__ __forceinline__ void fetch(const RArgs& a)
     {
 #pragma unroll
@@ -384,10 +463,10 @@ struct Tables {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             const int e = threadIdx.x + i * kRT;
-            if (e < a.ne * L) s[i] = a.tr[e];
+            if (e < 2 * L) s[i] = a.tr[e];
         }
     }
-    __device__ __forceinline__ void put(const RArgs& a, cf* tw, float* trl) const
+    __device__ __forceinline__ void put(cf* tw, float* trl) const
     {
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
@@ -397,7 +476,7 @@ struct Tables {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             const int e = threadIdx.x + i * kRT;
-            if (e < a.ne * L) trl[e] = s[i];
+            if (e < 2 * L) trl[e] = s[i];
         }
         __syncthreads();
     }
@@ -414,7 +493,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 {
     constexpr int L = Lay::L, R = Lay::PTS;
     __shared__ cf tw[L];
-    __shared__ float trl[kRMaxE * L];
+    __shared__ float trl[Tables<Lay>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
@@ -423,8 +502,10 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     float* out = a.out + rhs * a.out_rb;
     const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
-    Tables<L> tabs;
+    Tables<Lay> tabs;
     tabs.fetch(a);
+    typename Lay::Spec sp;
+    sp.template fetch<Lay>(a.tr, t);
 
     // the pending CG direction update: the same reduction and arithmetic as
     // the stand-alone update kernel, so the iterates are bit for bit the same
@@ -468,10 +549,10 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
                 }
             }
     }
-    tabs.put(a, tw, trl);
+    tabs.put(tw, trl);
+    sp.template bind<Lay>(trl, t);
     typename Lay::Tw lw;
     lw.make(t, tw);
-    const SepProg& pr = *a.pr;
     double dacc = 0.0;
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
@@ -481,7 +562,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<Lay, NIN>(pr, o, Z[tt], Y, trl, t);
+        combine<Lay, NIN, NOUT>(Z[tt], o, Y, sp);
         Lay::inv(Y, t, xb, lw);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -519,7 +600,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     constexpr int L = Lay::L, R = Lay::PTS;
     constexpr int S = 4;
     __shared__ cf tw[L];
-    __shared__ float trl[kRMaxE * L];
+    __shared__ float trl[Tables<Lay>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
     const long rhs = blockIdx.y;
@@ -527,8 +608,10 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     float* out = a.out + rhs * a.out_rb;
     const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
-    Tables<L> tabs;
+    Tables<Lay> tabs;
     tabs.fetch(a);
+    typename Lay::Spec sp;
+    sp.template fetch<Lay>(a.tr, t);
 
     cf Z[TPW][NIN][R];
 #pragma unroll
@@ -541,7 +624,8 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
                 Z[tt][f][m] = load_pair<L, false>(in + f * a.fstride,
                                                   elem_index<Lay, false>(base, g, t, m, a.st));
     }
-    tabs.put(a, tw, trl);
+    tabs.put(tw, trl);
+    sp.template bind<Lay>(trl, t);
     typename Lay::Tw lw;
     lw.make(t, tw);
 #pragma unroll
@@ -551,12 +635,10 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     {
 #pragma unroll
         for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, lw);
-        const SepProg& pr = *a.pr;
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            combine<Lay, NIN>(pr, q, Z[tt], D[q], trl, t);
-            Lay::inv(D[q], t, xb, lw);
-        }
+        for (int q = 0; q < S; ++q) combine<Lay, NIN, S>(Z[tt], q, D[q], sp);
+#pragma unroll
+        for (int q = 0; q < S; ++q) Lay::inv(D[q], t, xb, lw);
     }
     // pointwise stage on both lines of every complex element; an element whose
     // two nodes are interior reads the 26-float table of shared values (one
@@ -616,11 +698,10 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     }
 #pragma unroll
     for (int p = 0; p < S; ++p) Lay::fwd(D[p], t, xb, lw);
-    const SepProg& pr2 = *a.pr2;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<Lay, S>(pr2, o, D, Y, trl, t);
+        combine<Lay, S, NOUT>(D, o, Y, sp);
         Lay::inv(Y, t, xb, lw);
 #pragma unroll
         for (int m = 0; m < R; ++m)
@@ -637,9 +718,8 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
            double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
            const RegPupd* pu)
 {
-    const SepPlan& sp = c.basis_plan;
     const long nn = c.nn;
-    const long slot_rb = 2L * sp.maxpairs * nn;  // floats between rhs in a workspace slot
+    const long slot_rb = 2L * c.basis_plan.maxpairs * nn;  // floats between rhs in a workspace slot
     float* S1 = reinterpret_cast<float*>(c.work32);
     float* S2 = S1 + slot_rb * c.cap_work;
     const dim3 grid((unsigned)(blocks_of<Lay>(c) / TPW), (unsigned)nrhs), block(kRT);
@@ -653,7 +733,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.st = axis == 0 ? 1 : (axis == 1 ? (long)c.n[0] : (long)c.n[0] * c.n[1]);
         a.tr = c.rtab32[axis];
         a.tw = c.tw32[axis];
-        a.ne = 2 * c.degree + 1;
         a.nn = nn;
         return a;
     };
@@ -661,7 +740,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     {
         RArgs a = args(0, in, nn, S1, slot_rb);
         a.mask_in = mask;
-        a.pr = sp.d1[0];
         prof.begin(0, st);
         if (pu) {
             a.rvec = pu->r;
@@ -679,7 +757,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     // y: X -> XY
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        a.pr = sp.d1[1];
         prof.begin(1, st);
         hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 2, 3>), grid, block, 0, st, a);
         prof.end(1, st);
@@ -687,8 +764,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     // z: XY -> D -> E -> part-2 XY
     {
         RArgs a = args(2, S2, slot_rb, S1, slot_rb);
-        a.pr = sp.d1[2];
-        a.pr2 = sp.d2[2];
         a.ba = c.ba_32;
         a.vol = c.vol32;
         a.nbits = c.nbits[c.reg_layout];
@@ -701,7 +776,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     // y: XY -> X
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        a.pr = sp.d2[1];
         prof.begin(3, st);
         hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 3, 2>), grid, block, 0, st, a);
         prof.end(3, st);
@@ -710,7 +784,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     {
         RArgs a = args(0, S2, slot_rb, out, nn);
         a.mask_out = mask;
-        a.pr = sp.d2[0];
         a.dot_part = dot_part;
         a.dot_with = dot_with;
         prof.begin(4, st);
@@ -848,7 +921,31 @@ bool reg_path_ok(const Ctx& c)
     }
     const int L = c.n[0];
     if (L != 64 && L != 128) return false;
-    return c.n[1] == L && c.n[2] == L;
+    if (c.n[1] != L || c.n[2] != L) return false;
+    // the kernels hard-wire the terms of the passes (kP1In .. kP2B) and the
+    // coefficient +-1/(2L) of every term
+    for (int j = 0; j < 3; ++j) {
+        if (c.axes[j] != j) return false;
+        const double inv = 1.0 / (2.0 * c.n[j]);
+        const SepProg& f = sp.p1[j];
+        for (int o = 0; o < f.nout; ++o) {
+            if (f.ostart[o + 1] - f.ostart[o] != 1) return false;
+            const SepTerm& tm = f.t[f.ostart[o]];
+            if (tm.in != kP1In[j][o] || tm.e != kP1E[j][o] || tm.coef != inv) return false;
+        }
+        const SepProg& g = sp.p2[j];
+        for (int o = 0; o < g.nout; ++o) {
+            const int nt = g.ostart[o + 1] - g.ostart[o];
+            if (nt != (kP2B[j][o] >= 0 ? 2 : 1)) return false;
+            for (int k = g.ostart[o]; k < g.ostart[o + 1]; ++k) {
+                const SepTerm& tm = g.t[k];
+                const bool ok0 = tm.e == 0 && tm.in == kP2A[j][o] && tm.coef == inv;
+                const bool ok1 = tm.e == 1 && tm.in == kP2B[j][o] && tm.coef == -inv;
+                if (!ok0 && !ok1) return false;
+            }
+        }
+    }
+    return true;
 }
 
 // workgroups of one launch (each covers reg_tpw tiles)
