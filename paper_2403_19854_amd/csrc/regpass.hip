@@ -251,9 +251,10 @@ struct SpecLds {
 };
 
 // Line layouts: lanes per complex line, points per lane, the spatial row of
-// point m and the frequency of spectral slot i held by lane t, and the LDS
+// point m and the frequency of spectral slot i held by lane t, the LDS
 // complex values of one group's transpose buffer (the group stride is 8 mod
-// 32 so the groups of a wave spread over the banks).
+// 32 so the groups of a wave spread over the banks), and the geometry of the
+// staging buffer of strided passes (TP, SS, STAGE; see stage_move).
 // G8 reads its twiddles from the LDS table as it goes
 struct LdsTw {
     const cf* tw;
@@ -264,6 +265,7 @@ template <int R>
 struct G8 {
     static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     typedef LdsTw Tw;
     typedef SpecLds Spec;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
@@ -274,6 +276,7 @@ struct G8 {
 struct G16 {
     static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     typedef G16Tw Tw;
     typedef SpecRegs Spec;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
@@ -482,6 +485,26 @@ struct Tables {
     }
 };
 
+// Strided passes move global memory in a row-major map: thread (gc, tc) =
+// (tid % GROUPS, tid / GROUPS) loads and stores the values of layout lane
+// (gc, tc), so GROUPS consecutive threads cover a whole row segment of the
+// tile (128 bytes) instead of each wave touching LANES rows with a few
+// bytes each.  The values cross LDS once between that thread and the lane
+// that transforms them: v holds lane (gw, tw)'s values on entry and lane
+// (gr, tr)'s on return.  The TP = GROUPS + 1 pitch keeps both the writes
+// (consecutive threads vary g) and the reads (consecutive lanes vary t) free
+// of bank conflicts.  Callers alternate two buffers, so the barrier of one
+// move also orders the reads of the move before it against the next writes.
+template <class Lay>
+__device__ __forceinline__ void stage_move(cf (&v)[Lay::PTS], cf* buf, int gw, int tw, int gr, int tr)
+{
+#pragma unroll
+    for (int m = 0; m < Lay::PTS; ++m) buf[m * Lay::SS + tw * Lay::TP + gw] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < Lay::PTS; ++m) v[m] = buf[m * Lay::SS + tr * Lay::TP + gr];
+}
+
 // One separable pass: NIN real fields -> NOUT real fields along the axis.
 // LMASK: the single input is masked by mask_in.  SMASK: the single output is
 // masked by mask_out and, if dot_part is set, dotted with dot_with.
@@ -496,7 +519,9 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     __shared__ float trl[Tables<Lay>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
+    __shared__ cf stage[CONTIG ? 1 : 2][CONTIG ? 1 : Lay::STAGE];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
+    const int gc = CONTIG ? g : tid % Lay::GROUPS, tc = CONTIG ? t : tid / Lay::GROUPS;
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
@@ -544,8 +569,11 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
                     }
                     const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
                     Z[tt][f][m] = cf{m0 ? v.x : 0.0f, m1 ? v.y : 0.0f};
-                } else {
+                } else if constexpr (CONTIG) {
                     Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
+                } else {
+                    Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride,
+                                                       elem_index<Lay, CONTIG>(base, gc, tc, m, a.st));
                 }
             }
     }
@@ -558,15 +586,19 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     for (int tt = 0; tt < TPW; ++tt) {
     const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, lw);
+    for (int f = 0; f < NIN; ++f) {
+        if constexpr (!CONTIG) stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) & 1], gc, tc, g, t);
+        Lay::fwd(Z[tt][f], t, xb, lw);
+    }
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
         combine<Lay, NIN, NOUT>(Z[tt], o, Y, sp);
         Lay::inv(Y, t, xb, lw);
+        if constexpr (!CONTIG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
+            const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
             if constexpr (SMASK) {
                 const long idx1 = idx + (CONTIG ? L : 1);
                 const float v0 = a.mask_out[idx] ? Y[m].x : 0.0f;
@@ -602,7 +634,9 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     __shared__ cf tw[L];
     __shared__ float trl[Tables<Lay>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
+    __shared__ cf stage[2][Lay::STAGE];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
+    const int gc = tid % Lay::GROUPS, tc = tid / Lay::GROUPS;
     const long rhs = blockIdx.y;
     const float* in = a.in + rhs * a.in_rb;
     float* out = a.out + rhs * a.out_rb;
@@ -622,7 +656,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 #pragma unroll
             for (int m = 0; m < R; ++m)
                 Z[tt][f][m] = load_pair<L, false>(in + f * a.fstride,
-                                                  elem_index<Lay, false>(base, g, t, m, a.st));
+                                                  elem_index<Lay, false>(base, gc, tc, m, a.st));
     }
     tabs.put(tw, trl);
     sp.template bind<Lay>(trl, t);
@@ -634,7 +668,10 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     cf D[S][R];
     {
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) Lay::fwd(Z[tt][f], t, xb, lw);
+        for (int f = 0; f < NIN; ++f) {
+            stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) & 1], gc, tc, g, t);
+            Lay::fwd(Z[tt][f], t, xb, lw);
+        }
 #pragma unroll
         for (int q = 0; q < S; ++q) combine<Lay, NIN, S>(Z[tt], q, D[q], sp);
 #pragma unroll
@@ -703,9 +740,10 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
         cf Y[R];
         combine<Lay, S, NOUT>(D, o, Y, sp);
         Lay::inv(Y, t, xb, lw);
+        stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < R; ++m)
-            store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, g, t, m, a.st), Y[m]);
+            store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[m]);
     }
     }
 }
