@@ -316,6 +316,30 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return block_sum(v, sh);
 }
 
+// sum_partials in two steps for blocks of kRedThreads threads over a
+// right-hand side's kRedBlocks partial slots: load (all slots, without
+// branches, so that loads issued after them do not delay the sum), then sum
+// (the first nb slots, in the order of sum_partials)
+struct Partials {
+    double v[kRedBlocks / kRedThreads];
+    __device__ __forceinline__ void load(const double* __restrict__ part)
+    {
+#pragma unroll
+        for (int k = 0; k < kRedBlocks / kRedThreads; ++k) v[k] = part[threadIdx.x + k * kRedThreads];
+    }
+    __device__ __forceinline__ double sum(int nb, double* sh) const
+    {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRedBlocks / kRedThreads; ++k)
+            if ((int)threadIdx.x + k * kRedThreads < nb) s += v[k];
+        return block_sum(s, sh);
+    }
+};
+
+// chunks of four a CG update thread loads ahead of its block's reduction
+constexpr int kPre = 2;
+
 int red_blocks(long n)
 {
     const long per = (long)kRedThreads * 4;
@@ -425,16 +449,48 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_xr(T* __restrict__ x, T* __r
     p += off;
     q += off;
     scal += j * kScal;
-    const double pq = sum_partials(pq_part + (long)j * kRedBlocks, npq, sh);
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long first = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    // the partials of p.q, then the thread's first kPre chunks are loaded
+    // before the reduction, so the chunks' latency overlaps it
+    Partials pp;
+    pp.load(pq_part + (long)j * kRedBlocks);
+    Vec4<T> xs[kPre], rs[kPre], ps[kPre], qs[kPre];
+    if (n % 4 == 0) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const long i = 4 * (first + u * stride);
+            if (i < n) {
+                xs[u] = ld4(x + i);
+                rs[u] = ld4(r + i);
+                ps[u] = ld4(p + i);
+                qs[u] = ld4(q + i);
+            }
+        }
+    }
+    const double pq = pp.sum(npq, sh);
     const double rr = scal[parity];
     const bool good = pq > 0.0 && rr > 0.0;
     const T alpha = good ? T(rr / pq) : T(0);
     if (!good && blockIdx.x == 0 && threadIdx.x == 0 && rr > 0.0) scal[3] = 1.0;
     double acc = 0.0;
-    const long stride = (long)gridDim.x * blockDim.x;
-    const long first = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (n % 4 == 0) {
-        for (long i = 4 * first; i < n; i += 4 * stride) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const long i = 4 * (first + u * stride);
+            if (i < n) {
+                Vec4<T> xv = xs[u], rv = rs[u];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xv.v[e] = xv.v[e] + alpha * ps[u].v[e];
+                    rv.v[e] = rv.v[e] - alpha * qs[u].v[e];
+                    acc += (double)rv.v[e] * (double)rv.v[e];
+                }
+                st4(x + i, xv);
+                st4(r + i, rv);
+            }
+        }
+        for (long i = 4 * (first + kPre * stride); i < n; i += 4 * stride) {
             Vec4<T> xv = ld4(x + i), rv = ld4(r + i);
             const Vec4<T> pv = ld4(p + i), qv = ld4(q + i);
 #pragma unroll
@@ -480,13 +536,36 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_p(T* __restrict__ p, const T
     p += j * n;
     r += j * n;
     scal += j * kScal;
-    const double rr_new = sum_partials(rr_part + (long)j * kRedBlocks, gridDim.x, sh);
-    const double rr_old = scal[parity];
-    const T beta = rr_old > 0.0 ? T(rr_new / rr_old) : T(0);
     const long stride = (long)gridDim.x * blockDim.x;
     const long first = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    Partials pp;
+    pp.load(rr_part + (long)j * kRedBlocks);
+    Vec4<T> rs[kPre], ps[kPre];
     if (n % 4 == 0) {
-        for (long i = 4 * first; i < n; i += 4 * stride) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const long i = 4 * (first + u * stride);
+            if (i < n) {
+                rs[u] = ld4(r + i);
+                ps[u] = ld4(p + i);
+            }
+        }
+    }
+    const double rr_new = pp.sum(gridDim.x, sh);
+    const double rr_old = scal[parity];
+    const T beta = rr_old > 0.0 ? T(rr_new / rr_old) : T(0);
+    if (n % 4 == 0) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const long i = 4 * (first + u * stride);
+            if (i < n) {
+                Vec4<T> pv = ps[u];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pv.v[e] = rs[u].v[e] + beta * pv.v[e];
+                st4(p + i, pv);
+            }
+        }
+        for (long i = 4 * (first + kPre * stride); i < n; i += 4 * stride) {
             const Vec4<T> rv = ld4(r + i);
             Vec4<T> pv = ld4(p + i);
 #pragma unroll

@@ -527,29 +527,22 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     float* out = a.out + rhs * a.out_rb;
     const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
+    // the partials of the pending update's r.r are loaded first (all
+    // kRedBlocks slots, without branches): loads complete in order, so the
+    // reduction then waits for them alone
+    constexpr int NPART = PUPD ? kRedBlocks / kRT : 1;
+    double part[NPART];
+    if constexpr (PUPD) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) part[k] = a.rr_part[rhs * kRedBlocks + tid + k * kRT];
+    }
     Tables<Lay> tabs;
     tabs.fetch(a);
     typename Lay::Spec sp;
     sp.template fetch<Lay>(a.tr, t);
 
-    // the pending CG direction update: the same reduction and arithmetic as
-    // the stand-alone update kernel, so the iterates are bit for bit the same
-    float beta = 0.0f;
-    bool upd = false;
-    if constexpr (PUPD) {
-        upd = a.act[rhs] != 0;
-        if (upd) {
-            double v = 0.0;
-            const double* part = a.rr_part + rhs * kRedBlocks;
-            for (int i = tid; i < a.nrr; i += kRT) v += part[i];
-            const double rr_new = block_sum(v, sh);
-            const double rr_old = a.scal[rhs * kScal + a.parity];
-            beta = rr_old > 0.0 ? float(rr_new / rr_old) : 0.0f;
-            if (blockIdx.x == 0 && tid == 0) a.scal[rhs * kScal + 1 - a.parity] = rr_new;
-        }
-    }
-
     cf Z[TPW][NIN][R];
+    uint8_t mk[LMASK ? TPW : 1][LMASK ? R : 1][2];
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
         const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
@@ -557,25 +550,62 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
         for (int f = 0; f < NIN; ++f)
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const long idx = elem_index<Lay, CONTIG>(base, g, t, m, a.st);
+                const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
+                Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
                 if constexpr (LMASK) {
-                    cf v = load_pair<L, CONTIG>(in, idx);
-                    if constexpr (PUPD) {
-                        if (upd) {
-                            const cf rv = load_pair<L, CONTIG>(a.rvec + rhs * a.in_rb, idx);
-                            v = cf{rv.x + beta * v.x, rv.y + beta * v.y};
-                            store_pair<L, CONTIG>(const_cast<float*>(in), idx, v);
-                        }
-                    }
-                    const uint8_t m0 = a.mask_in[idx], m1 = a.mask_in[idx + (CONTIG ? L : 1)];
-                    Z[tt][f][m] = cf{m0 ? v.x : 0.0f, m1 ? v.y : 0.0f};
-                } else if constexpr (CONTIG) {
-                    Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
-                } else {
-                    Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride,
-                                                       elem_index<Lay, CONTIG>(base, gc, tc, m, a.st));
+                    mk[tt][m][0] = a.mask_in[idx];
+                    mk[tt][m][1] = a.mask_in[idx + (CONTIG ? L : 1)];
                 }
             }
+    }
+
+    // the pending CG direction update p = r + beta p of the masked input: the
+    // same reduction and arithmetic as the stand-alone update kernel, so the
+    // iterates are bit for bit the same.  p and r are loaded before the
+    // reduction, so their latency overlaps it.
+    if constexpr (PUPD) {
+        static_assert(LMASK && NIN == 1, "the update applies to the masked single input");
+        cf Rv[TPW][R];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                Rv[tt][m] = load_pair<L, CONTIG>(a.rvec + rhs * a.in_rb,
+                                                 elem_index<Lay, CONTIG>(base, gc, tc, m, a.st));
+        }
+        if (a.act[rhs] != 0) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < NPART; ++k)
+                if (tid + k * kRT < a.nrr) v += part[k];
+            const double rr_new = block_sum(v, sh);
+            const double rr_old = a.scal[rhs * kScal + a.parity];
+            const float beta = rr_old > 0.0 ? float(rr_new / rr_old) : 0.0f;
+            if (blockIdx.x == 0 && tid == 0) a.scal[rhs * kScal + 1 - a.parity] = rr_new;
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) {
+                const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const cf pv = Z[tt][0][m], rv = Rv[tt][m];
+                    Z[tt][0][m] = cf{rv.x + beta * pv.x, rv.y + beta * pv.y};
+                    store_pair<L, CONTIG>(const_cast<float*>(in), elem_index<Lay, CONTIG>(base, gc, tc, m, a.st),
+                                          Z[tt][0][m]);
+                }
+            }
+        }
+    }
+    if constexpr (LMASK) {
+        static_assert(NIN == 1, "a masked input is a single field");
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const cf v = Z[tt][0][m];
+                Z[tt][0][m] = cf{mk[tt][m][0] ? v.x : 0.0f, mk[tt][m][1] ? v.y : 0.0f};
+            }
+        }
     }
     tabs.put(tw, trl);
     sp.template bind<Lay>(trl, t);
