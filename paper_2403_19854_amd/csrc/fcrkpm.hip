@@ -442,9 +442,9 @@ bool use_reg_path(const Ctx& c, int /*nrhs*/)
 
 // Algorithmic bytes of one launch of each register-resident pass: the FP32
 // fields it must read and write (masks 1 B per node), and in the middle pass
-// the interior bits and record offsets (4 B each per lane) and the records of
-// the elements that are not interior (28 floats each; interior elements read
-// one shared record that stays in cache).
+// the node-class bits and record offset (8 + 4 B per lane) and the records of
+// the elements that are neither interior nor outside the domain (20 floats
+// each).
 double reg_pass_bytes(const Ctx& c, int k)
 {
     const double nn = (double)c.nn;
@@ -453,7 +453,7 @@ double reg_pass_bytes(const Ctx& c, int k)
         case 1: return nn * (2 * 4 + 3 * 4);
         case 2: {
             const double words = (double)reg_bits_words(c, c.reg_layout);
-            return nn * (3 * 4 + 3 * 4) + 2 * 4.0 * words +
+            return nn * (3 * 4 + 3 * 4) + 12.0 * words +
                    (double)c.nload[c.reg_layout] * reg_record_floats() * 4;
         }
         case 3: return nn * (3 * 4 + 2 * 4);
@@ -1537,14 +1537,27 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 HIPCHK(hipMemsetAsync(cls, 2, nn, st));  // no interior node: every element reads
             }
             c.nconst = nc;
+            if (ref != 0x7fffffff) {
+                // M = V B^T B of the interior nodes, in FP64 from the reference node
+                std::vector<double> b(nb);
+                double v = 0.0;
+                for (int q = 0; q < nb; ++q)
+                    HIPCHK(hipMemcpy(&b[q], c.ba_64 + (size_t)q * nn + ref, sizeof(double),
+                                     hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(&v, c.vol64 + ref, sizeof(double), hipMemcpyDeviceToHost));
+                int k = 0;
+                for (int p = 0; p < c.s; ++p)
+                    for (int q = p; q < c.s; ++q) {
+                        double acc = 0.0;
+                        for (int al = 0; al < c.dim; ++al) acc += b[al * c.s + p] * b[al * c.s + q];
+                        c.reg_mi[k++] = (float)(v * acc);
+                    }
+            }
             const int rf = reg_record_floats();
-            std::vector<float> tab(rf, 0.0f);  // record 0: the interior values
-            for (int q = 0; q < nb; ++q) tab[2 * q] = tab[2 * q + 1] = nc.b[q];
-            tab[2 * nb] = tab[2 * nb + 1] = nc.v;
             unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c.dflag + 4);
             for (int lay = 0; lay < reg_layouts(c); ++lay) {
                 const long words = reg_bits_words(c, lay);
-                c.nbits[lay] = dalloc<uint32_t>(words);
+                c.nbits[lay] = dalloc<uint2>(words);
                 c.noff[lay] = dalloc<uint32_t>(words);
                 unsigned long long zero = 0, got = 0;
                 HIPCHK(hipMemcpyAsync(cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
@@ -1555,20 +1568,17 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                                       hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
                 c.nload[lay] = (long)got;
-                // per-lane counts -> first record of each lane (exclusive prefix
-                // sum after record 0)
-                uint64_t run = 1;
+                // per-lane counts -> first record of each lane (exclusive prefix sum)
+                uint64_t run = 0;
                 for (long s = 0; s < words; ++s) {
                     const uint32_t n1 = off[s];
                     off[s] = (uint32_t)run;
                     run += n1;
                 }
-                if (run != got + 1 || run > 0xffffffffull) fail(FCRKPM_ERR_HIP, "record count mismatch");
+                if (run != got || run > 0xffffffffull) fail(FCRKPM_ERR_HIP, "record count mismatch");
                 HIPCHK(hipMemcpyAsync(c.noff[lay], off.data(), sizeof(uint32_t) * words,
                                       hipMemcpyHostToDevice, st));
-                c.nrec[lay] = dalloc<float>((size_t)run * rf);
-                HIPCHK(hipMemcpyAsync(c.nrec[lay], tab.data(), sizeof(float) * rf,
-                                      hipMemcpyHostToDevice, st));
+                c.nrec[lay] = dalloc<float>((size_t)std::max<uint64_t>(run, 1) * rf);
                 launch_reg_recs(c, lay, c.nbits[lay], c.noff[lay], c.nrec[lay], st);
                 HIPCHK(hipStreamSynchronize(st));
             }

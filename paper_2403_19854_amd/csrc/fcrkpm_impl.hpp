@@ -94,7 +94,8 @@ struct Ctx {
     cplx<float>* spec32[3] = {};
     float* rtab32[3] = {};              // per axis [2][n]: Re T_0 / n, Im T_1 / n (register passes)
     bool use_regpath = true;            // register-resident passes where they apply
-    uint32_t* nbits[2] = {};            // register path: interior bits per middle-pass lane, per layout
+    uint2* nbits[2] = {};               // register path: node-class bits per middle-pass lane, per layout
+    float reg_mi[10] = {};              // register path: M = V B^T B of the interior nodes
     uint32_t* noff[2] = {};             // register path: first record of each lane, per layout
     float* nrec[2] = {};                // register path: coefficient records (0: interior), per layout
     int reg_layout = 0;                 // register path: line layout (0: 8 lanes, 1: 16 lanes)
@@ -194,9 +195,9 @@ int reg_path_blocks(const Ctx& c);
 int reg_layouts(const Ctx& c);
 bool reg_variant_ok(const Ctx& c, int v);
 long reg_bits_words(const Ctx& c, int layout);
-void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint2* bits, uint32_t* count,
                      unsigned long long* nload, hipStream_t st);
-void launch_reg_recs(const Ctx& c, int layout, const uint32_t* bits, const uint32_t* off,
+void launch_reg_recs(const Ctx& c, int layout, const uint2* bits, const uint32_t* off,
                      float* rec, hipStream_t st);
 int reg_record_floats();
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,

@@ -359,15 +359,14 @@ struct RArgs {
     long st;                  // element stride of the axis; 1 for x
     const float* tr;          // [2][L]: Re T_0 / L, Im T_1 / L of the axis
     const cf* tw;             // [L] e^{-2 pi i j / L}
-    const float* ba;          // middle pass: b^a [3][4][nn]
-    const float* vol;         // middle pass: V [nn]
     long nn;
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
     const float* dot_with;
-    const uint32_t* nbits;    // middle pass: per lane, bit 2m+c set if node c of element m
-                              // takes the interior values
-    const uint32_t* noff;     // middle pass: per lane, first record of its other elements
-    const float4* rec;        // middle pass: records of kRec floats (record 0: interior values)
+    const uint2* nbits;       // middle pass, per lane: .x bit 2m+c set if node c of element
+                              // m is interior, .y bit m set if element m reads a record
+    const uint32_t* noff;     // middle pass: per lane, its first record
+    const float4* rec;        // middle pass: records of kRec floats
+    float mi[10];             // middle pass: M of the interior nodes (kSym order)
     // first x pass inside CG (PUPD): the pending direction update p = r + beta p
     // with beta = (sum of rr_part) / scal[parity], written back to `in`
     const float* rvec;
@@ -378,10 +377,30 @@ struct RArgs {
     const int* act;
 };
 
-// A record holds b^a_q (a-major, q minor) and V of the two nodes of one
-// element interleaved -- b_0(n0), b_0(n1), b_1(n0), ... , V(n0), V(n1) --
-// padded to 7 float4 so a lane reads it with 16-byte loads.
-constexpr int kRec = 28;
+// The pointwise stage of the middle pass (Eq 90-91) regrouped: with B the
+// 3 x 4 matrix b^a_q of a node, E_p = V sum_a b^a_p sum_q b^a_q D_q equals
+// sum_q M_pq D_q for the symmetric M = V B^T B, whose 10 distinct entries are
+// kept in the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3).
+// Interior nodes share one M; nodes outside the domain have M = 0 (b = 0
+// there); every other element has a record with the M of its two nodes
+// interleaved -- M_0(n0), M_0(n1), M_1(n0), ... -- 5 float4 per record.
+constexpr int kRec = 20;
+
+// position of M_pq (p <= q) in that order
+__host__ __device__ constexpr int sym_index(int p, int q)
+{
+    return 4 * p - p * (p - 1) / 2 + (q - p);
+}
+
+// e = M d for the symmetric M of one node
+__device__ __forceinline__ void sym4_apply(const float (&M)[10], float d0, float d1, float d2, float d3,
+                                           float (&e)[4])
+{
+    e[0] = M[0] * d0 + M[1] * d1 + M[2] * d2 + M[3] * d3;
+    e[1] = M[1] * d0 + M[4] * d1 + M[5] * d2 + M[6] * d3;
+    e[2] = M[2] * d0 + M[5] * d1 + M[7] * d2 + M[8] * d3;
+    e[3] = M[3] * d0 + M[6] * d1 + M[8] * d2 + M[9] * d3;
+}
 
 // Position of the workgroup's Lay::LINES real lines: for a strided axis the
 // float index of line l0 at point 0 (the lines are adjacent in memory), for
@@ -688,6 +707,16 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
                 Z[tt][f][m] = load_pair<L, false>(in + f * a.fstride,
                                                   elem_index<Lay, false>(base, gc, tc, m, a.st));
     }
+    // the pointwise stage's node classes, loaded after the fields (loads
+    // complete in order, so the first transforms do not wait for them)
+    uint2 bw[TPW];
+    uint32_t offv[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const long lane = (tile0 + tt) * kRT + tid;
+        bw[tt] = a.nbits[lane];
+        offv[tt] = a.noff[lane];
+    }
     tabs.put(tw, trl);
     sp.template bind<Lay>(trl, t);
     typename Lay::Tw lw;
@@ -707,61 +736,49 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 #pragma unroll
         for (int q = 0; q < S; ++q) Lay::inv(D[q], t, xb, lw);
     }
-    // pointwise stage on both lines of every complex element; an element whose
-    // two nodes are interior reads the 26-float table of shared values (one
-    // cache line for the whole wave) instead of the coefficient arrays
-    // (outside the domain b = 0, so those nodes read zeros)
-    const long lane = (tile0 + tt) * kRT + tid;
-    const uint32_t bits = a.nbits[lane];
-    const uint32_t off = a.noff[lane];
-    uint32_t outer = 0;  // bit m: element m is not interior and reads its record
+    // pointwise stage on both lines of every complex element: E = M D per
+    // node.  Only lanes whose element reads a record issue loads, so a wave
+    // with none (deep interior, or all outside) skips them.  Elements go in
+    // pairs m, R-1-m (the rows nearest the two ends of the line first, where
+    // the boundary lies), each pair's records loaded together; the empty asm
+    // makes the next pair's record index depend on this pair's results, so
+    // the compiler cannot hoist every pair's loads to the top and hold all of
+    // them in registers at once.
+    uint32_t roff = offv[tt];
 #pragma unroll
-    for (int m = 0; m < R; ++m) outer |= (((bits >> (2 * m)) & 3u) != 3u ? 1u : 0u) << m;
+    for (int h = 0; h < R / 2; ++h) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        // record 0 holds the interior values; one base pointer with a chosen
-        // index (not a choice of pointers) keeps the load single
-        const bool inner = !((outer >> m) & 1u);
-        const uint32_t km = __popc(outer & ((1u << m) - 1u));
-        const float4* src = a.rec + (size_t)(inner ? 0u : off + km) * (kRec / 4);
-        float rv[kRec];
+        for (int u = 0; u < 2; ++u) {
+            const int m = u ? R - 1 - h : h;
+            // interior nodes: the shared M (uniform); outside the domain: 0
+            float e0[S], e1[S];
+            sym4_apply(a.mi, D[0][m].x, D[1][m].x, D[2][m].x, D[3][m].x, e0);
+            sym4_apply(a.mi, D[0][m].y, D[1][m].y, D[2][m].y, D[3][m].y, e1);
+            const bool i0 = (bw[tt].x >> (2 * m)) & 1u, i1 = (bw[tt].x >> (2 * m + 1)) & 1u;
 #pragma unroll
-        for (int j = 0; j < kRec / 4; ++j) {
-            const float4 f = src[j];
-            rv[4 * j] = f.x;
-            rv[4 * j + 1] = f.y;
-            rv[4 * j + 2] = f.z;
-            rv[4 * j + 3] = f.w;
-        }
-        float2 b[3][S];
-#pragma unroll
-        for (int al = 0; al < 3; ++al)
-#pragma unroll
-            for (int q = 0; q < S; ++q)
-                b[al][q] = float2{rv[2 * (al * S + q)], rv[2 * (al * S + q) + 1]};
-        const float2 v = float2{rv[2 * 3 * S], rv[2 * 3 * S + 1]};
-        float A0[3], A1[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-            float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                s0 += b[al][q].x * D[q][m].x;
-                s1 += b[al][q].y * D[q][m].y;
+            for (int p = 0; p < S; ++p) {
+                e0[p] = i0 ? e0[p] : 0.0f;
+                e1[p] = i1 ? e1[p] : 0.0f;
             }
-            A0[al] = s0;
-            A1[al] = s1;
-        }
+            if ((bw[tt].y >> m) & 1u) {
+                const uint32_t km = __popc(bw[tt].y & ((1u << m) - 1u));
+                const float4* src = a.rec + (size_t)(roff + km) * (kRec / 4);
+                float M0[10], M1[10];
 #pragma unroll
-        for (int p = 0; p < S; ++p) {
-            float e0 = 0.0f, e1 = 0.0f;
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                e0 += b[al][p].x * A0[al];
-                e1 += b[al][p].y * A1[al];
+                for (int j = 0; j < kRec / 4; ++j) {
+                    const float4 f = src[j];
+                    M0[2 * j] = f.x;
+                    M1[2 * j] = f.y;
+                    M0[2 * j + 1] = f.z;
+                    M1[2 * j + 1] = f.w;
+                }
+                sym4_apply(M0, D[0][m].x, D[1][m].x, D[2][m].x, D[3][m].x, e0);
+                sym4_apply(M1, D[0][m].y, D[1][m].y, D[2][m].y, D[3][m].y, e1);
             }
-            D[p][m] = cf{v.x * e0, v.y * e1};
+#pragma unroll
+            for (int p = 0; p < S; ++p) D[p][m] = cf{e0[p], e1[p]};
         }
+        asm volatile("" : "+v"(roff) : "v"(D[0][h].x), "v"(D[0][R - 1 - h].x));
     }
 #pragma unroll
     for (int p = 0; p < S; ++p) Lay::fwd(D[p], t, xb, lw);
@@ -832,11 +849,10 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     // z: XY -> D -> E -> part-2 XY
     {
         RArgs a = args(2, S2, slot_rb, S1, slot_rb);
-        a.ba = c.ba_32;
-        a.vol = c.vol32;
         a.nbits = c.nbits[c.reg_layout];
         a.noff = c.noff[c.reg_layout];
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
+        for (int k = 0; k < 10; ++k) a.mi[k] = c.reg_mi[k];
         prof.begin(2, st);
         hipLaunchKernelGGL((k_rmid<Lay, TPW, 3, 3>), grid, block, 0, st, a);
         prof.end(2, st);
@@ -860,10 +876,13 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     }
 }
 
-// Interior bits of every lane of the middle pass, in its own tile geometry.
+// Node classes of every lane of the middle pass, in its own tile geometry
+// (cls: 0 outside the domain, 1 interior, 2 other): the interior bits, the
+// elements that need a record (unless both nodes are interior or both
+// outside) and their count.
 template <class Lay>
 __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
-                            uint32_t* __restrict__ bits, uint32_t* __restrict__ count,
+                            uint2* __restrict__ bits, uint32_t* __restrict__ count,
                             unsigned long long* __restrict__ nload)
 {
     const long n = nblk * kRT;
@@ -872,24 +891,26 @@ __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
         const long tile = s / kRT;
         const int lane = (int)(s % kRT), g = lane / Lay::LANES, t = lane % Lay::LANES;
         const long base = tile_base<Lay, false>(tile, st);
-        uint32_t w = 0;
+        uint32_t w = 0, need = 0;
         for (int m = 0; m < Lay::PTS; ++m) {
             const long idx = elem_index<Lay, false>(base, g, t, m, st);
-            if (cls[idx] == 1) w |= 1u << (2 * m);
-            if (cls[idx + 1] == 1) w |= 2u << (2 * m);
+            const uint8_t c0 = cls[idx], c1 = cls[idx + 1];
+            if (c0 == 1) w |= 1u << (2 * m);
+            if (c1 == 1) w |= 2u << (2 * m);
+            if (!(c0 == c1 && c0 != 2)) need |= 1u << m;
         }
-        bits[s] = w;
-        int loads = 0;  // elements that read a record
-        for (int m = 0; m < Lay::PTS; ++m) loads += ((w >> (2 * m)) & 3u) != 3u;
+        bits[s] = uint2{w, need};
+        const int loads = __popc(need);
         count[s] = (uint32_t)loads;
         if (loads) atomicAdd(nload, (unsigned long long)loads);
     }
 }
 
-// The records of every lane's non-interior elements, in lane order.
+// The records of every lane's record elements, in lane order, with M formed
+// in FP64 from b^a (a-major, [3][4][nn]) and V and rounded once.
 template <class Lay>
-__global__ void k_rmid_recs(const uint32_t* __restrict__ bits, const uint32_t* __restrict__ off,
-                            const float* __restrict__ ba, const float* __restrict__ vol, long st,
+__global__ void k_rmid_recs(const uint2* __restrict__ bits, const uint32_t* __restrict__ off,
+                            const double* __restrict__ ba, const double* __restrict__ vol, long st,
                             long nblk, long nn, float* __restrict__ rec)
 {
     constexpr int S = 4;
@@ -899,27 +920,30 @@ __global__ void k_rmid_recs(const uint32_t* __restrict__ bits, const uint32_t* _
         const long tile = s / kRT;
         const int lane = (int)(s % kRT), g = lane / Lay::LANES, t = lane % Lay::LANES;
         const long base = tile_base<Lay, false>(tile, st);
-        const uint32_t w = bits[s];
+        const uint32_t need = bits[s].y;
         long r = off[s];
         for (int m = 0; m < Lay::PTS; ++m) {
-            if (((w >> (2 * m)) & 3u) == 3u) continue;
+            if (!((need >> m) & 1u)) continue;
             const long idx = elem_index<Lay, false>(base, g, t, m, st);
             float* o = rec + r * kRec;
-            for (int q = 0; q < 3 * S; ++q) {
-                o[2 * q] = ba[q * nn + idx];
-                o[2 * q + 1] = ba[q * nn + idx + 1];
+            for (int c = 0; c < 2; ++c) {
+                const long node = idx + c;
+                const double v = vol[node];
+                for (int p = 0; p < S; ++p)
+                    for (int q = p; q < S; ++q) {
+                        double acc = 0.0;
+                        for (int al = 0; al < 3; ++al)
+                            acc += ba[(long)(al * S + p) * nn + node] * ba[(long)(al * S + q) * nn + node];
+                        o[2 * sym_index(p, q) + c] = (float)(v * acc);
+                    }
             }
-            o[2 * 3 * S] = vol[idx];
-            o[2 * 3 * S + 1] = vol[idx + 1];
-            o[2 * 3 * S + 2] = 0.0f;
-            o[2 * 3 * S + 3] = 0.0f;
             ++r;
         }
     }
 }
 
 template <class Lay>
-void build_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+void build_bits(const Ctx& c, const uint8_t* cls, uint2* bits, uint32_t* count,
                 unsigned long long* nload, hipStream_t st)
 {
     const long str = (long)c.n[0] * c.n[1];
@@ -928,10 +952,10 @@ void build_bits(const Ctx& c, const uint8_t* cls, uint32_t* bits, uint32_t* coun
 }
 
 template <class Lay>
-void build_recs(const Ctx& c, const uint32_t* bits, const uint32_t* off, float* rec, hipStream_t st)
+void build_recs(const Ctx& c, const uint2* bits, const uint32_t* off, float* rec, hipStream_t st)
 {
     const long str = (long)c.n[0] * c.n[1];
-    hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_32, c.vol32,
+    hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_64, c.vol64,
                        str, blocks_of<Lay>(c), c.nn, rec);
 }
 
@@ -954,7 +978,7 @@ long reg_bits_words(const Ctx& c, int layout)
     return blocks_of<G8<8>>(c) * kRT;
 }
 
-void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bits, uint32_t* count,
+void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint2* bits, uint32_t* count,
                      unsigned long long* nload, hipStream_t st)
 {
     if (c.n[0] == 128) {
@@ -965,7 +989,7 @@ void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint32_t* bit
     }
 }
 
-void launch_reg_recs(const Ctx& c, int layout, const uint32_t* bits, const uint32_t* off,
+void launch_reg_recs(const Ctx& c, int layout, const uint2* bits, const uint32_t* off,
                      float* rec, hipStream_t st)
 {
     if (c.n[0] == 128) {
