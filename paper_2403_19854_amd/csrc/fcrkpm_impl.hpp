@@ -166,17 +166,17 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
 // Register-resident passes of the FP32 K product (regpass.hip) for 3D boxes
 // of 64^3 or 128^3 nodes and the linear basis.  `prof` brackets the five
 // launches (x, y, middle z, y, x) for the kernel-duration sampler.
+// Duration sampling of the register passes: for pass k (0..4) of a launch,
+// events() counts the launch and either leaves both events null or hands out
+// the pair that the launch itself records (hipExtLaunchKernelGGL), so the
+// sampled span is the kernel's own, without separate event packets around it.
 struct RegProf {
     const void* c = nullptr;
-    void (*begin_fn)(const void*, int, hipStream_t) = nullptr;
-    void (*end_fn)(const void*, int, hipStream_t) = nullptr;
-    void begin(int k, hipStream_t st) const
+    void (*events_fn)(const void*, int, hipEvent_t*, hipEvent_t*) = nullptr;
+    void events(int k, hipEvent_t* e0, hipEvent_t* e1) const
     {
-        if (begin_fn) begin_fn(c, k, st);
-    }
-    void end(int k, hipStream_t st) const
-    {
-        if (end_fn) end_fn(c, k, st);
+        *e0 = *e1 = nullptr;
+        if (events_fn) events_fn(c, k, e0, e1);
     }
 };
 // The CG direction update p = r + beta p that the first x pass of a K product

@@ -21,6 +21,7 @@
 // Either way the data crosses LDS once per transform instead of once per
 // radix stage, and the spectral products, the inverse transforms and the
 // pointwise stage of the middle pass all act on registers.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -798,6 +799,16 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 template <class Lay>
 long blocks_of(const Ctx& c) { return c.nn / Lay::L / Lay::LINES; }
 
+// launch of pass k, with the sampler's events recorded by the launch itself
+template <typename K>
+void rlaunch(const RegProf& prof, int k, K kern, dim3 grid, dim3 block, hipStream_t st, const RArgs& a)
+{
+    hipEvent_t e0, e1;
+    prof.events(k, &e0, &e1);
+    if (e0) hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, a);
+    else hipLaunchKernelGGL(kern, grid, block, 0, st, a);
+}
+
 template <class Lay, int TPW>
 void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
            double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
@@ -825,7 +836,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
     {
         RArgs a = args(0, in, nn, S1, slot_rb);
         a.mask_in = mask;
-        prof.begin(0, st);
         if (pu) {
             a.rvec = pu->r;
             a.rr_part = pu->rr_part;
@@ -833,18 +843,15 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
             a.scal = pu->scal;
             a.parity = pu->parity;
             a.act = pu->act;
-            hipLaunchKernelGGL((k_rpass<Lay, TPW, true, true, false, 1, 2, true>), grid, block, 0, st, a);
+            rlaunch(prof, 0, k_rpass<Lay, TPW, true, true, false, 1, 2, true>, grid, block, st, a);
         } else {
-            hipLaunchKernelGGL((k_rpass<Lay, TPW, true, true, false, 1, 2>), grid, block, 0, st, a);
+            rlaunch(prof, 0, k_rpass<Lay, TPW, true, true, false, 1, 2>, grid, block, st, a);
         }
-        prof.end(0, st);
     }
     // y: X -> XY
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        prof.begin(1, st);
-        hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 2, 3>), grid, block, 0, st, a);
-        prof.end(1, st);
+        rlaunch(prof, 1, k_rpass<Lay, TPW, false, false, false, 2, 3>, grid, block, st, a);
     }
     // z: XY -> D -> E -> part-2 XY
     {
@@ -853,16 +860,12 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.noff = c.noff[c.reg_layout];
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         for (int k = 0; k < 10; ++k) a.mi[k] = c.reg_mi[k];
-        prof.begin(2, st);
-        hipLaunchKernelGGL((k_rmid<Lay, TPW, 3, 3>), grid, block, 0, st, a);
-        prof.end(2, st);
+        rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
     }
     // y: XY -> X
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        prof.begin(3, st);
-        hipLaunchKernelGGL((k_rpass<Lay, TPW, false, false, false, 3, 2>), grid, block, 0, st, a);
-        prof.end(3, st);
+        rlaunch(prof, 3, k_rpass<Lay, TPW, false, false, false, 3, 2>, grid, block, st, a);
     }
     // x: X -> f (masked), with the optional dot partials
     {
@@ -870,9 +873,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.mask_out = mask;
         a.dot_part = dot_part;
         a.dot_with = dot_with;
-        prof.begin(4, st);
-        hipLaunchKernelGGL((k_rpass<Lay, TPW, true, false, true, 2, 1>), grid, block, 0, st, a);
-        prof.end(4, st);
+        rlaunch(prof, 4, k_rpass<Lay, TPW, true, false, true, 2, 1>, grid, block, st, a);
     }
 }
 
