@@ -362,12 +362,15 @@ def test_full_size_refined_solve_c5():
     assert err <= 5e-3
 
 
-@pytest.mark.parametrize("n", [64, 128])
-def test_register_path_matches_lds_path_and_oracle(n):
+@pytest.mark.parametrize("shape,n", [("cube", 64), ("cube", 128), ("sphere", 64), ("sphere", 128)])
+def test_register_path_matches_lds_path_and_oracle(shape, n):
     """The register-resident FP32 K passes (64^3 and 128^3 boxes, linear
-    basis) against the LDS-tiled FP32 passes and the FP64 oracle."""
-    p = W.cube(3, n, 2.5, 1)
-    print(f"\n[register path {n}^3]", flush=True)
+    basis) against the LDS-tiled FP32 passes and the FP64 oracle.  The ball
+    (radius 0.4) puts nodes outside the domain and boundary elements along
+    every line, so both node classes without a record and the records
+    themselves are exercised."""
+    p = W.cube(3, n, 2.5, 1) if shape == "cube" else W.sphere(n, 0.4, 2.5, 1)
+    print(f"\n[register path {shape} {n}^3]", flush=True)
     from paper_2403_19854_amd import fcrkpm
     g = lib_problem(p)
     x = rand_field(p, 31)
