@@ -146,6 +146,7 @@ void dfree(T*& p)
 void release(Ctx& c)
 {
     dfree(c.chi);
+    dfree(c.cls);
     dfree(c.freem);
     dfree(c.dirm);
     dfree(c.vol64);
@@ -517,7 +518,10 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
             cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, nrhs, st);
             cplx<T>* dst = (cur == S1) ? S2 : S1;
             {
-                ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2 + (c.dim * c.s + 1) * rt), st);
+                // coefficients are read only at class-2 nodes (1 B of class per node)
+                const double coef = c.cls ? (double)c.ncls2 * (c.dim * c.s + 1) * rt + nn
+                                          : nn * (c.dim * c.s + 1) * rt;
+                ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2) + coef, st);
                 if (k == 1)
                     launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], SEP_PW_K, SEP_LD_REAL, in, mk,
                                            SEP_ST_REAL, out, mk, nullptr, b0_of<T>(c), ba_of<T>(c),
@@ -1519,10 +1523,10 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 fail(FCRKPM_ERR_SINGULAR, "moment matrix not positive definite at node " + std::to_string(hflag[1]));
         }
 
-        // node classes of the register-resident K passes: interior nodes share
-        // one set of coefficients, so their pointwise stage reads one cached
-        // record; every other element gets its own record, packed lane by lane
-        if (reg_path_ok(c) && c.dim * c.s <= kMaxNodeConst) {
+        // node classes (0 outside the domain, 1 interior, 2 other) for the
+        // pointwise stage of the K products: interior nodes share the first
+        // interior node's b^a and V, nodes outside have V = 0
+        if (c.dim * c.s <= kMaxNodeConst) {
             int big = 0x7fffffff, ref = 0;
             HIPCHK(hipMemcpyAsync(c.dflag + 3, &big, sizeof(int), hipMemcpyHostToDevice, st));
             launch_first_interior(c, c.dflag + 3, st);
@@ -1530,32 +1534,44 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
             HIPCHK(hipStreamSynchronize(st));
             const int nb = c.dim * c.s;
             NodeConst nc = {};
-            uint8_t* cls = dalloc<uint8_t>(nn);
+            nc.bmax = -1.0;  // no interior node: every domain node is class 2
             if (ref != 0x7fffffff) {
                 for (int q = 0; q < nb; ++q)
-                    HIPCHK(hipMemcpy(&nc.b[q], c.ba_32 + (size_t)q * nn + ref, sizeof(float),
+                    HIPCHK(hipMemcpy(&nc.b[q], c.ba_64 + (size_t)q * nn + ref, sizeof(double),
                                      hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(&nc.v, c.vol32 + ref, sizeof(float), hipMemcpyDeviceToHost));
-                for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabsf(nc.b[q]));
-                launch_node_class(c, nc, cls, st);
-            } else {
-                HIPCHK(hipMemsetAsync(cls, 2, nn, st));  // no interior node: every element reads
+                HIPCHK(hipMemcpy(&nc.v, c.vol64 + ref, sizeof(double), hipMemcpyDeviceToHost));
+                nc.bmax = 0.0;
+                for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabs(nc.b[q]));
+            }
+            c.cls = dalloc<uint8_t>(nn);
+            launch_node_class(c, nc, c.cls, st);
+            {
+                std::vector<uint8_t> hc(nn);
+                HIPCHK(hipMemcpyAsync(hc.data(), c.cls, nn, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                c.ncls2 = (long)std::count(hc.begin(), hc.end(), (uint8_t)2);
             }
             c.nconst = nc;
-            if (ref != 0x7fffffff) {
-                // M = V B^T B of the interior nodes, in FP64 from the reference node
-                std::vector<double> b(nb);
-                double v = 0.0;
-                for (int q = 0; q < nb; ++q)
-                    HIPCHK(hipMemcpy(&b[q], c.ba_64 + (size_t)q * nn + ref, sizeof(double),
-                                     hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(&v, c.vol64 + ref, sizeof(double), hipMemcpyDeviceToHost));
+            for (int q = 0; q < nb; ++q) {
+                c.cint64[q] = nc.b[q];
+                c.cint32[q] = (float)nc.b[q];
+            }
+            c.cint64[nb] = nc.v;
+            c.cint32[nb] = (float)nc.v;
+        }
+        // node classes of the register-resident K passes: interior nodes share
+        // one M = V B^T B (a kernel argument), nodes outside the domain give
+        // zero, and every other element gets its own record, packed lane by lane
+        if (reg_path_ok(c) && c.cls) {
+            const uint8_t* cls = c.cls;
+            const NodeConst& nc = c.nconst;
+            if (nc.bmax >= 0.0) {
                 int k = 0;
                 for (int p = 0; p < c.s; ++p)
                     for (int q = p; q < c.s; ++q) {
                         double acc = 0.0;
-                        for (int al = 0; al < c.dim; ++al) acc += b[al * c.s + p] * b[al * c.s + q];
-                        c.reg_mi[k++] = (float)(v * acc);
+                        for (int al = 0; al < c.dim; ++al) acc += nc.b[al * c.s + p] * nc.b[al * c.s + q];
+                        c.reg_mi[k++] = (float)(nc.v * acc);
                     }
             }
             const int rf = reg_record_floats();
@@ -1587,7 +1603,6 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 launch_reg_recs(c, lay, c.nbits[lay], c.noff[lay], c.nrec[lay], st);
                 HIPCHK(hipStreamSynchronize(st));
             }
-            dfree(cls);
         }
 
         // workspace and solver buffers for one right-hand side; both grow on demand

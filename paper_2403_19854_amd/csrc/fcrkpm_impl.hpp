@@ -53,12 +53,14 @@ struct SepPlan {
     int maxpairs = 0;             // largest pair count of P_0 .. P_{k-2}
 };
 
-// Coefficients shared by the interior nodes (class 1) of the FP32 K product.
-constexpr int kMaxNodeConst = 12;  // dim * s for the linear basis in 3D
+// Coefficients shared by the interior nodes (class 1): nodes whose support
+// neighbourhood lies in the domain have the full-grid moment matrix, so b^a
+// and V agree with those of the first such node (checked to 1e-12 of max |b|).
+constexpr int kMaxNodeConst = 30;  // dim * s up to the quadratic basis in 3D
 struct NodeConst {
-    float b[kMaxNodeConst];        // b^a_q, a-major
-    float v;                       // V
-    float bmax;                    // max |b|
+    double b[kMaxNodeConst];       // b^a_q, a-major
+    double v;                      // V
+    double bmax;                   // max |b|; negative: no interior node
 };
 
 struct Ctx {
@@ -94,6 +96,10 @@ struct Ctx {
     cplx<float>* spec32[3] = {};
     float* rtab32[3] = {};              // per axis [2][n]: Re T_0 / n, Im T_1 / n (register passes)
     bool use_regpath = true;            // register-resident passes where they apply
+    uint8_t* cls = nullptr;             // node class: 0 outside the domain, 1 interior, 2 other
+    long ncls2 = 0;                     // class-2 nodes
+    double cint64[kMaxNodeConst + 1] = {};  // interior b^a (a-major) and V
+    float cint32[kMaxNodeConst + 1] = {};
     uint2* nbits[2] = {};               // register path: node-class bits per middle-pass lane, per layout
     float reg_mi[10] = {};              // register path: M = V B^T B of the interior nodes
     uint32_t* noff[2] = {};             // register path: first record of each lane, per layout

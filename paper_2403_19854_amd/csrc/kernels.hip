@@ -106,17 +106,17 @@ void launch_first_interior(const Ctx& c, int* ref, hipStream_t st)
                        c.n[1], c.n[2], c.m[0], c.m[1], c.m[2], c.nn, ref);
 }
 
-__global__ void k_node_class(const uint8_t* __restrict__ chi, const float* __restrict__ ba,
-                             const float* __restrict__ vol, int nb, NodeConst ref, int n0, int n1,
+__global__ void k_node_class(const uint8_t* __restrict__ chi, const double* __restrict__ ba,
+                             const double* __restrict__ vol, int nb, NodeConst ref, int n0, int n1,
                              int n2, int m0, int m1, int m2, long nn, uint8_t* __restrict__ cls)
 {
     for (long I = blockIdx.x * (long)blockDim.x + threadIdx.x; I < nn;
          I += (long)gridDim.x * blockDim.x) {
         uint8_t k = 0;
         if (chi[I]) {
-            bool same = vol[I] == ref.v && full_support(chi, I, n0, n1, n2, m0, m1, m2);
+            bool same = ref.bmax >= 0.0 && vol[I] == ref.v && full_support(chi, I, n0, n1, n2, m0, m1, m2);
             for (int q = 0; same && q < nb; ++q)
-                same = fabsf(ba[(long)q * nn + I] - ref.b[q]) <= 1e-6f * ref.bmax;
+                same = fabs(ba[(long)q * nn + I] - ref.b[q]) <= 1e-12 * ref.bmax;
             k = same ? 1 : 2;
         }
         cls[I] = k;
@@ -125,8 +125,8 @@ __global__ void k_node_class(const uint8_t* __restrict__ chi, const float* __res
 
 void launch_node_class(const Ctx& c, const NodeConst& ref, uint8_t* cls, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_node_class, dim3(ew_blocks(c.nn)), dim3(256), 0, st, c.chi, c.ba_32,
-                       c.vol32, c.dim * c.s, ref, c.n[0], c.n[1], c.n[2], c.m[0], c.m[1], c.m[2],
+    hipLaunchKernelGGL(k_node_class, dim3(ew_blocks(c.nn)), dim3(256), 0, st, c.chi, c.ba_64,
+                       c.vol64, c.dim * c.s, ref, c.n[0], c.n[1], c.n[2], c.m[0], c.m[1], c.m[2],
                        c.nn, cls);
 }
 

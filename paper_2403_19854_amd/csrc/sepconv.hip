@@ -20,6 +20,8 @@
 // (A^a, C_p^a of Alg 2) between the two halves, so D_q and E_p never reach HBM.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -488,6 +490,8 @@ struct MidArgs {
     const T* b0;              // [s][nn]
     const T* ba;              // [dim][s][nn]
     const T* vol;             // [nn] or NULL
+    const uint8_t* cls;       // PW_K: node class (0 outside, 1 interior, 2 other) or NULL
+    T cint[kMaxNodeConst + 1];  // PW_K: b^a (a-major) and V of the interior nodes
     const void* src;          // PW_LOAD: the real field r (Tio)
     long nn;
     long src_rb;              // bytes between right-hand sides of src
@@ -560,7 +564,9 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
         return;
     } else {
         if constexpr (PW == PW_K) {
-            // A^a = sum_q b^a_q D_q ; E_p = V sum_a b^a_p A^a   (Eq 90-91, Alg 2)
+            // A^a = sum_q b^a_q D_q ; E_p = V sum_a b^a_p A^a   (Eq 90-91, Alg 2).
+            // Interior nodes take the shared b^a and V (kernel argument) and
+            // nodes outside the domain V = 0; only the others read the arrays.
             for (int base = 0; base < E; base += kPwChunk * kThreads) {
               T bb[kPwChunk][DIM][S], vv[kPwChunk];
               int oo[kPwChunk];
@@ -570,11 +576,19 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 int w, i;
                 long gi;
                 tl.at(e, w, i, gi, oo[kk]);
+                const uint8_t k = m.cls ? m.cls[gi] : uint8_t(2);
 #pragma unroll
                 for (int al = 0; al < DIM; ++al)
 #pragma unroll
-                    for (int q = 0; q < S; ++q) bb[kk][al][q] = m.ba[(al * S + q) * m.nn + gi];
-                vv[kk] = m.vol[gi];
+                    for (int q = 0; q < S; ++q) bb[kk][al][q] = m.cint[al * S + q];
+                vv[kk] = k == 1 ? m.cint[DIM * S] : T(0);
+                if (k == 2) {
+#pragma unroll
+                    for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                        for (int q = 0; q < S; ++q) bb[kk][al][q] = m.ba[(al * S + q) * m.nn + gi];
+                    vv[kk] = m.vol[gi];
+                }
               }
 #pragma unroll
               for (int kk = 0; kk < kPwChunk; ++kk) {
@@ -859,6 +873,11 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.b0 = b0;
     m.ba = ba;
     m.vol = vol;
+    m.cls = c.cls;
+    for (int q = 0; q <= kMaxNodeConst; ++q) {
+        if constexpr (std::is_same<T, double>::value) m.cint[q] = c.cint64[q];
+        else m.cint[q] = c.cint32[q];
+    }
     m.src = src;
     m.nn = c.nn;
     const size_t sh = (size_t)(m.s.ne + 1) * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
