@@ -154,6 +154,7 @@ def main():
                    "step": (f"setup + f^r + {a.fixed_iters} CG iterations + u^h" if a.fixed_iters
                             else "setup + f^r + CG to tol + u^h")},
         "dof_per_s": value * n_free,
+        "box_nodes_per_s": value * float(np.prod(wl.dims)),
         "solve": {"iters": infos[-1]["iters"], "outer_iters": infos[-1]["outer_iters"],
                   "matvecs_f32": infos[-1]["matvecs_f32"],
                   "matvecs_f64": infos[-1]["matvecs_f64"],
@@ -180,6 +181,10 @@ def main():
                             "speedup_refined_vs_fp64": (t3 - t2) / (elapsed / a.steps),
                             "uh_rel_l2_refined_vs_fp64": e}
 
+    if not a.no_fp64_compare and a.mode != "f64" and not a.fixed_iters:
+        out["time_to_solution"] = time_to_solution(a, wl, chi, dirm, vol, r, dev)
+        out["apply_loop"] = apply_loop(wl, chi, dirm, vol, dev)
+
     if not a.no_cpu_baseline:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -198,6 +203,66 @@ def main():
                                "sample": f"{n} oracle K products (neighbour-loop RKPM, FP64) on the "
                                          f"same {wl.name} grid, {tc:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def time_to_solution(a, wl, chi, dirm, vol, r, dev):
+    """Solve-call wall time (setup excluded) of the refined and the plain FP64
+    solve on one context, both to the bench tolerance, and how far apart their
+    solutions are."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    res = {"tol": a.tol}
+    ds = {}
+    for mode in ("f32_refined", "f64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, info = pb.solve(r, mode=mode, tol=a.tol, maxit=a.maxit, want_uh=False)
+        torch.cuda.synchronize()
+        res[mode + "_ms"] = 1e3 * (time.perf_counter() - t0)
+        res[mode + "_iters"] = info["iters"]
+        ds[mode] = d.cpu().numpy()
+    pb.close()
+    m = wl.free > 0
+    res["speedup"] = res["f64_ms"] / res["f32_refined_ms"]
+    res["d_rel_l2_refined_vs_f64"] = float(np.linalg.norm((ds["f32_refined"] - ds["f64"])[m]) /
+                                           np.linalg.norm(ds["f64"][m]))
+    return res
+
+
+def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5):
+    """Standalone K products: median over `reps` single launches (HIP events on
+    the launch stream) after `warm` warm-ups, FP32 and FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    x = torch.from_numpy(np.where(wl.free > 0, np.random.default_rng(0).standard_normal(wl.shape),
+                                  0.0)).to(dev)
+    res = {"reps": reps, "warmup": warm}
+    st = torch.cuda.current_stream()
+    for name, xt in (("f32", x.float()), ("f64", x)):
+        y = torch.empty_like(xt)
+        for _ in range(warm):
+            pb.apply("K", xt, out=y, stream=st)
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            pb.apply("K", xt, out=y, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        med = float(np.median(ts))
+        res[name] = {"median_ms": med, "matvecs_per_s": 1e3 / med}
+    pb.close()
+    return res
 
 
 def probe(a, wl):
