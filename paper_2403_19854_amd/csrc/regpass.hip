@@ -674,8 +674,9 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 
 // Middle pass of K d along the last axis (strided), linear basis in 3D
 // (s = 4): the part-1 convolutions give D_q, the pointwise stage forms
-// A^a = sum_q b^a_q D_q and E_p = V sum_a b^a_p A^a at every node (Eq 90-91,
-// Alg 2), and the part-2 convolutions of E_p follow -- all in registers.
+// E_p = V sum_a b^a_p sum_q b^a_q D_q at every node (Eq 90-91, Alg 2) as
+// sum_q M_pq D_q, and the part-2 convolutions of E_p follow -- all in
+// registers.
 template <class Lay, int TPW, int NIN, int NOUT>
 __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 {
