@@ -735,9 +735,23 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
         }
 #pragma unroll
         for (int q = 0; q < S; ++q) combine<Lay, NIN, S>(Z[tt], q, D[q], sp);
-#pragma unroll
-        for (int q = 0; q < S; ++q) Lay::inv(D[q], t, xb, lw);
     }
+    // the records of the first element pair (the rows at the two ends of the
+    // line, where the boundary lies) are requested before the inverse
+    // transforms, which hide their latency
+    float4 pre[2][kRec / 4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int m = u ? R - 1 : 0;
+        if ((bw[tt].y >> m) & 1u) {
+            const uint32_t km = __popc(bw[tt].y & ((1u << m) - 1u));
+            const float4* src = a.rec + (size_t)(offv[tt] + km) * (kRec / 4);
+#pragma unroll
+            for (int j = 0; j < kRec / 4; ++j) pre[u][j] = src[j];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) Lay::inv(D[q], t, xb, lw);
     // pointwise stage on both lines of every complex element: E = M D per
     // node.  Only lanes whose element reads a record issue loads, so a wave
     // with none (deep interior, or all outside) skips them.  Elements go in
@@ -768,7 +782,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
                 float M0[10], M1[10];
 #pragma unroll
                 for (int j = 0; j < kRec / 4; ++j) {
-                    const float4 f = src[j];
+                    const float4 f = h == 0 ? pre[u][j] : src[j];
                     M0[2 * j] = f.x;
                     M1[2 * j] = f.y;
                     M0[2 * j + 1] = f.z;
