@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=["c5", "paper", "c3", "c4"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "paper", "c3", "c4", "c1", "c2"])
     ap.add_argument("--c4-iters", type=int, default=240)
     ap.add_argument("--probe", type=int, default=0,
                     help="counter probe: setup, a refined solve capped at N CG iterations "
@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--probe-variant", type=int, default=1,
                     help="register-path variant for --probe (layout + 2 (tiles - 1)); the "
                          "default is the one setup's autotuner picks for 128^3 on MI355X")
-    ap.add_argument("--mode", default="f32_refined", choices=["f32_refined", "f64"])
+    ap.add_argument("--mode", default=None, choices=["f32_refined", "f64"],
+                    help="default: f64 for c1 and c2 (plain FP64 configurations), else f32_refined")
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--maxit", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -77,9 +78,12 @@ def main():
     from paper_2403_19854_amd import workloads as W
 
     fcrkpm.load_library()
+    if a.mode is None:
+        a.mode = "f64" if a.workload in ("c1", "c2") else "f32_refined"
     if a.workload == "c4":
         return bench_c4(a)
-    wl = {"c5": W.config5, "paper": W.paper_shape, "c3": W.config3}[a.workload]()
+    wl = {"c5": W.config5, "paper": W.paper_shape, "c3": W.config3, "c1": W.config1,
+          "c2": W.config2}[a.workload]()
     if a.probe:
         return probe(a, wl)
     dev = torch.device("cuda:0")
@@ -136,7 +140,9 @@ def main():
                    np.linalg.norm(wl.u_exact[m])) if wl.u_exact is not None else None
 
     out = {
-        "metric": "CG matvecs/s at 128^3 (K products of the refined-FP32 solve, FP64 outer residual)",
+        "metric": ("CG matvecs/s at 128^3 (K products of the refined-FP32 solve, FP64 outer residual)"
+                   if a.workload == "c5" and a.mode == "f32_refined" else
+                   f"CG matvecs/s, {wl.name} ({'refined FP32' if a.mode == 'f32_refined' else 'FP64'})"),
         "value": value,
         "unit": "matvec/s",
         "n_gpus": 1,
@@ -154,6 +160,7 @@ def main():
                    "step": (f"setup + f^r + {a.fixed_iters} CG iterations + u^h" if a.fixed_iters
                             else "setup + f^r + CG to tol + u^h")},
         "dof_per_s": value * n_free,
+        "us_per_matvec": 1e6 / value,
         "box_nodes_per_s": value * float(np.prod(wl.dims)),
         "solve": {"iters": infos[-1]["iters"], "outer_iters": infos[-1]["outer_iters"],
                   "matvecs_f32": infos[-1]["matvecs_f32"],
