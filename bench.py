@@ -191,6 +191,8 @@ def main():
     if not a.no_fp64_compare and a.mode != "f64" and not a.fixed_iters:
         out["time_to_solution"] = time_to_solution(a, wl, chi, dirm, vol, r, dev)
         out["apply_loop"] = apply_loop(wl, chi, dirm, vol, dev)
+        if a.workload == "c5":
+            out["adjoint"] = adjoint_time(a, wl, chi, dirm, vol, r, dev)
 
     if not a.no_cpu_baseline:
         import oracle
@@ -238,6 +240,33 @@ def time_to_solution(a, wl, chi, dirm, vol, r, dev):
     res["d_rel_l2_refined_vs_f64"] = float(np.linalg.norm((ds["f32_refined"] - ds["f64"])[m]) /
                                            np.linalg.norm(ds["f64"][m]))
     return res
+
+
+def adjoint_time(a, wl, chi, dirm, vol, r, dev):
+    """The gradient of L = 0.5 |u^h - u_t|^2 with respect to r (config 5): the
+    forward solve for u^h, then the adjoint (N^T, a solve with K, V o N), both
+    refined FP32 to the bench tolerance; wall times of the two calls."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+    from paper_2403_19854_amd import workloads as W
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    ut = torch.from_numpy(W.config5_target(wl)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, uh, info_f = pb.solve(r, mode="f32_refined", tol=a.tol, maxit=a.maxit, want_uh=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, info_a = pb.adjoint(uh - ut, mode="f32_refined", tol=a.tol, maxit=a.maxit)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pb.close()
+    return {"forward_ms": 1e3 * (t1 - t0), "adjoint_ms": 1e3 * (t2 - t1),
+            "adjoint_iters": info_a["iters"],
+            "adjoint_matvecs_per_s": (info_a["matvecs_f32"] + info_a["matvecs_f64"]) / (t2 - t1),
+            "grad_norm": float(torch.linalg.vector_norm(g).item())}
 
 
 def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5):
