@@ -627,6 +627,28 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
             }
         }
     }
+    // the masked store's mask bytes and the dot's other vector, loaded after
+    // the fields (loads complete in order) so they arrive during the transforms
+    uint8_t mo[SMASK ? TPW : 1][SMASK ? R : 1][2];
+    float dwv[SMASK ? TPW : 1][SMASK ? R : 1][2];
+    if constexpr (SMASK) {
+        const float* dw = a.dot_with + rhs * a.out_rb;
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
+                const long idx1 = idx + (CONTIG ? L : 1);
+                mo[tt][m][0] = a.mask_out[idx];
+                mo[tt][m][1] = a.mask_out[idx1];
+                if (a.dot_part) {
+                    dwv[tt][m][0] = dw[idx];
+                    dwv[tt][m][1] = dw[idx1];
+                }
+            }
+        }
+    }
     tabs.put(tw, trl);
     sp.template bind<Lay>(trl, t);
     typename Lay::Tw lw;
@@ -650,14 +672,11 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
         for (int m = 0; m < R; ++m) {
             const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
             if constexpr (SMASK) {
-                const long idx1 = idx + (CONTIG ? L : 1);
-                const float v0 = a.mask_out[idx] ? Y[m].x : 0.0f;
-                const float v1 = a.mask_out[idx1] ? Y[m].y : 0.0f;
+                const float v0 = mo[tt][m][0] ? Y[m].x : 0.0f;
+                const float v1 = mo[tt][m][1] ? Y[m].y : 0.0f;
                 store_pair<L, CONTIG>(out, idx, cf{v0, v1});
-                if (a.dot_part) {
-                    const float* dw = a.dot_with + rhs * a.out_rb;
-                    dacc += (double)v0 * (double)dw[idx] + (double)v1 * (double)dw[idx1];
-                }
+                if (a.dot_part)
+                    dacc += (double)v0 * (double)dwv[tt][m][0] + (double)v1 * (double)dwv[tt][m][1];
             } else {
                 store_pair<L, CONTIG>(out + o * a.fstride, idx, Y[m]);
             }
