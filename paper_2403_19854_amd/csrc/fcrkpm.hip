@@ -49,9 +49,11 @@ struct ArgFail {
 [[noreturn]] void fail(fcrkpm_status st, const std::string& msg) { throw ArgFail{st, msg}; }
 
 // ------------------------------------------------------ kernel-duration sampler
-// For each kernel kind, HIP events bracket the first kProfCap launches after
-// sampling starts; every launch is counted together with its algorithmic
-// bytes (what the launch must read and write, from the array sizes).
+// For each kernel kind, HIP events time the first kProfCap launches after
+// sampling starts (recorded around the launch, or by the launch itself for
+// the register passes); every launch is counted together with its
+// algorithmic bytes (what the launch must read and write, from the array
+// sizes).
 enum Kind {
     KD_P1_X, KD_P1_Y, KD_P1_Z, KD_MID_K, KD_MID_UH, KD_MID_LOAD, KD_P2_X, KD_P2_Y, KD_P2_Z,
     KD_SETUP_PASS, KD_STAGES
@@ -70,7 +72,6 @@ struct ProfKind {
     long launches = 0;
     double bytes = 0.0;
     int nrec = 0;
-    bool open = false;  // a begin event was recorded and awaits its end
     hipEvent_t ev[2 * kProfCap];
 };
 
@@ -103,28 +104,6 @@ struct ProfScope {
         ++k.nrec;
     }
 };
-
-// begin/end form of the sampler for launches made outside this file
-void prof_begin(Ctx& c, int kind, double bytes, hipStream_t st)
-{
-    if (!c.prof_on || c.capturing) return;
-    ProfKind& k = ((Prof*)c.prof)->k[kind];
-    ++k.launches;
-    k.bytes += bytes;
-    if (k.nrec < kProfCap) {
-        (void)hipEventRecord(k.ev[2 * k.nrec], st);
-        k.open = true;
-    }
-}
-void prof_end(Ctx& c, int kind, hipStream_t st)
-{
-    if (!c.prof_on || c.capturing) return;
-    ProfKind& k = ((Prof*)c.prof)->k[kind];
-    if (!k.open) return;
-    (void)hipEventRecord(k.ev[2 * k.nrec + 1], st);
-    ++k.nrec;
-    k.open = false;
-}
 
 template <typename T>
 T* dalloc(size_t count)
