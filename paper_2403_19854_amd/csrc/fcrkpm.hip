@@ -428,16 +428,17 @@ bool use_reg_path(const Ctx& c, int /*nrhs*/)
 double reg_pass_bytes(const Ctx& c, int k)
 {
     const double nn = (double)c.nn;
+    const double p0 = c.basis_plan.size[0], p1 = c.basis_plan.size[1];  // fields after x, after y
     switch (k) {
-        case 0: return nn * (4 + 1 + 2 * 4 + (c.prof_pupd ? 4 + 4 : 0));
-        case 1: return nn * (2 * 4 + 3 * 4);
+        case 0: return nn * (4 + 1 + p0 * 4 + (c.prof_pupd ? 4 + 4 : 0));
+        case 1: return nn * (p0 * 4 + p1 * 4);
         case 2: {
             const double words = (double)reg_bits_words(c, c.reg_layout);
-            return nn * (3 * 4 + 3 * 4) + 12.0 * words +
-                   (double)c.nload[c.reg_layout] * reg_record_floats() * 4;
+            return nn * (p1 * 4 + p1 * 4) + 12.0 * words +
+                   (double)c.nload[c.reg_layout] * reg_record_floats(c) * 4;
         }
-        case 3: return nn * (3 * 4 + 2 * 4);
-        default: return nn * (2 * 4 + 1 + 4 + (c.prof_dot ? 4 : 0));
+        case 3: return nn * (p1 * 4 + p0 * 4);
+        default: return nn * (p0 * 4 + 1 + 4 + (c.prof_dot ? 4 : 0));
     }
 }
 
@@ -1416,14 +1417,14 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
             c.spec64[a] = dalloc<cplx<double>>(sp.size());
             c.spec32[a] = dalloc<cplx<float>>(spf.size());
             {
-                // t_0 is even and t_1 odd in the offset, so T_0 is real and T_1
-                // imaginary: the register passes take Re T_0 and Im T_1, each
-                // with the 1/L of the inverse transform folded in
-                std::vector<float> rt((size_t)2 * L, 0.0f);
-                for (int e = 0; e < 2 && e < ne; ++e)
+                // t_e is even or odd in the offset with e, so T_e is real or
+                // imaginary: the register passes take Re T_0, Im T_1, Re T_2,
+                // each with the 1/L of the inverse transform folded in
+                std::vector<float> rt((size_t)3 * L, 0.0f);
+                for (int e = 0; e < 3 && e < ne; ++e)
                     for (int kk = 0; kk < L; ++kk)
-                        rt[(size_t)e * L + kk] = (float)((e ? sp[(size_t)e * L + kk].y
-                                                            : sp[(size_t)e * L + kk].x) / L);
+                        rt[(size_t)e * L + kk] = (float)(((e & 1) ? sp[(size_t)e * L + kk].y
+                                                                  : sp[(size_t)e * L + kk].x) / L);
                 c.rtab32[a] = dalloc<float>(rt.size());
                 HIPCHK(hipMemcpyAsync(c.rtab32[a], rt.data(), sizeof(float) * rt.size(),
                                       hipMemcpyHostToDevice, st));
@@ -1544,7 +1545,7 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         if (reg_path_ok(c) && c.cls) {
             const uint8_t* cls = c.cls;
             const NodeConst& nc = c.nconst;
-            if (nc.bmax >= 0.0) {
+            if (nc.bmax >= 0.0 && c.degree == 1) {
                 int k = 0;
                 for (int p = 0; p < c.s; ++p)
                     for (int q = p; q < c.s; ++q) {
@@ -1553,7 +1554,7 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                         c.reg_mi[k++] = (float)(nc.v * acc);
                     }
             }
-            const int rf = reg_record_floats();
+            const int rf = reg_record_floats(c);
             unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c.dflag + 4);
             for (int lay = 0; lay < reg_layouts(c); ++lay) {
                 const long words = reg_bits_words(c, lay);

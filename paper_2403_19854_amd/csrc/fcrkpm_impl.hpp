@@ -205,7 +205,7 @@ void launch_reg_bits(const Ctx& c, int layout, const uint8_t* cls, uint2* bits, 
                      unsigned long long* nload, hipStream_t st);
 void launch_reg_recs(const Ctx& c, int layout, const uint2* bits, const uint32_t* off,
                      float* rec, hipStream_t st);
-int reg_record_floats();
+int reg_record_floats(const Ctx& c);
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
                   const RegPupd* pu = nullptr);

@@ -146,19 +146,41 @@ __device__ __forceinline__ float swap8(float x)
 // inverse W_128^{-(tl + 8h) (t & 7)} (tl = 0..7).  Computed once per lane from
 // the LDS table, so the transforms read no twiddles and select nothing.
 struct G16Tw {
-    cf f[7], h[7], i[8];
+    cf f_[7], h_[7], i_[8];
     __device__ __forceinline__ void make(int t, const cf* tw)
     {
         const int k1 = t & 7, hh = t >> 3;
 #pragma unroll
         for (int j = 1; j < 8; ++j) {
-            f[j - 1] = tw[t * j];
+            f_[j - 1] = tw[t * j];
             const cf w = mul_w16<+1>(cf{1.0f, 0.0f}, j);
-            h[j - 1] = hh ? w : cf{1.0f, 0.0f};
+            h_[j - 1] = hh ? w : cf{1.0f, 0.0f};
         }
 #pragma unroll
-        for (int tl = 0; tl < 8; ++tl) i[tl] = twid<-1>(tw, (tl + 8 * hh) * k1);
+        for (int tl = 0; tl < 8; ++tl) i_[tl] = twid<-1>(tw, (tl + 8 * hh) * k1);
     }
+    __device__ __forceinline__ cf f(int j) const { return f_[j - 1]; }
+    __device__ __forceinline__ cf h(int j) const { return h_[j - 1]; }
+    __device__ __forceinline__ cf i(int tl) const { return i_[tl]; }
+};
+
+// The same twiddles read from the LDS table when needed (fewer registers, for
+// kernels that hold many fields)
+struct G16TwL {
+    const cf* tw;
+    int t;
+    __device__ __forceinline__ void make(int lane, const cf* table)
+    {
+        tw = table;
+        t = lane;
+    }
+    __device__ __forceinline__ cf f(int j) const { return tw[t * j]; }
+    __device__ __forceinline__ cf h(int j) const
+    {
+        const cf w = mul_w16<+1>(cf{1.0f, 0.0f}, j);
+        return (t >> 3) ? w : cf{1.0f, 0.0f};
+    }
+    __device__ __forceinline__ cf i(int tl) const { return twid<-1>(tw, (tl + 8 * (t >> 3)) * (t & 7)); }
 };
 
 // G16 forward transform (L = 128).  In: v[m] = x[t + 16m].  Out: v[i] =
@@ -166,11 +188,12 @@ struct G16Tw {
 // W_128^{t k1}, a transpose giving lane (k1, h) the values of lanes
 // 8h .. 8h+7 at k1, a radix-2 step across h, the twiddle W_16^{tl h} and a
 // DFT-8 over the lane offset tl.
-__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const G16Tw& w)
+template <class TW>
+__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const TW& w)
 {
     dft8<float, +1>(v);
 #pragma unroll
-    for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], w.f[k1 - 1]);
+    for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], w.f(k1));
 #pragma unroll
     for (int k1 = 0; k1 < 8; ++k1) xb[k1 * 17 + t] = v[k1];
     wave_sync();
@@ -185,18 +208,19 @@ __device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const G16Tw& 
         v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
     }
 #pragma unroll
-    for (int tl = 1; tl < 8; ++tl) v[tl] = cmul(v[tl], w.h[tl - 1]);
+    for (int tl = 1; tl < 8; ++tl) v[tl] = cmul(v[tl], w.h(tl));
     dft8<float, +1>(v);
 }
 
 // G16 unnormalised inverse: v[i] = X[t + 16i] in, v[m] = x[t + 16m] out (the
 // steps of g16_fwd reversed, with conjugate twiddles).
-__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const G16Tw& w)
+template <class TW>
+__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const TW& w)
 {
     const int k1 = t & 7, h = t >> 3;
     dft8<float, -1>(v);
 #pragma unroll
-    for (int tl = 1; tl < 8; ++tl) v[tl] = cmulc(v[tl], w.h[tl - 1]);
+    for (int tl = 1; tl < 8; ++tl) v[tl] = cmulc(v[tl], w.h(tl));
     const float s = h ? -1.0f : 1.0f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -204,7 +228,7 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const G16Tw& 
         v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
     }
 #pragma unroll
-    for (int tl = 0; tl < 8; ++tl) xb[k1 * 17 + tl + 8 * h] = cmul(v[tl], w.i[tl]);
+    for (int tl = 0; tl < 8; ++tl) xb[k1 * 17 + tl + 8 * h] = cmul(v[tl], w.i(tl));
     wave_sync();
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = xb[j * 17 + t];
@@ -212,27 +236,26 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const G16Tw& 
     dft8<float, -1>(v);
 }
 
-// The lane's values of the axis's two kernel spectra, each divided by L (the
-// 1/L of the inverse transform): T_0 is real (t_0 even) and T_1 imaginary
-// (t_1 odd), so one float per frequency describes each.  G16 holds its 8
-// frequencies of both in registers; G8 reads them from the LDS copy.
+// The lane's values of the axis's kernel spectra T_e (e < NE), each divided
+// by L (the 1/L of the inverse transform): T_e is real for even e and
+// imaginary for odd e (t_e is even or odd), so one float per frequency
+// describes it.  G16 holds its 8 frequencies of each in registers; G8 reads
+// them from the LDS copy.
+template <int NE>
 struct SpecRegs {
-    float s0[8], s1[8];
+    float s[NE][8];
     template <class Lay>
     __device__ __forceinline__ void fetch(const float* tab, int t)
     {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            s0[i] = tab[Lay::freq(t, i)];
-            s1[i] = tab[Lay::L + Lay::freq(t, i)];
-        }
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s[e][i] = tab[e * Lay::L + Lay::freq(t, i)];
     }
     template <class Lay>
     __device__ __forceinline__ void bind(const float*, int) {}
-    template <class Lay>
-    __device__ __forceinline__ float e0(int i) const { return s0[i]; }
-    template <class Lay>
-    __device__ __forceinline__ float e1(int i) const { return s1[i]; }
+    template <class Lay, int E>
+    __device__ __forceinline__ float e(int i) const { return s[E][i]; }
 };
 struct SpecLds {
     const float* trl;
@@ -245,10 +268,8 @@ struct SpecLds {
         trl = tab;
         t = lane;
     }
-    template <class Lay>
-    __device__ __forceinline__ float e0(int i) const { return trl[Lay::freq(t, i)]; }
-    template <class Lay>
-    __device__ __forceinline__ float e1(int i) const { return trl[Lay::L + Lay::freq(t, i)]; }
+    template <class Lay, int E>
+    __device__ __forceinline__ float e(int i) const { return trl[E * Lay::L + Lay::freq(t, i)]; }
 };
 
 // Line layouts: lanes per complex line, points per lane, the spatial row of
@@ -268,7 +289,8 @@ struct G8 {
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     typedef LdsTw Tw;
-    typedef SpecLds Spec;
+    template <int NE>
+    using Spec = SpecLds;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
     static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_fwd<R>(v, t, xb, w.tw); }
@@ -279,75 +301,132 @@ struct G16 {
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     typedef G16Tw Tw;
-    typedef SpecRegs Spec;
+    template <int NE>
+    using Spec = SpecRegs<NE>;
+    static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
+    static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
+    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
+    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
+};
+// G16 geometry with twiddles and spectra read from LDS (for the kernel that
+// holds the most fields)
+struct G16L {
+    static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
+    typedef G16TwL Tw;
+    template <int NE>
+    using Spec = SpecLds;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
     static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
     static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
 };
 
-// Term structure of the K d passes for the linear basis in 3D, monomials in
-// graded order (1, x, y, z).  Part 1 along axis j forms output o from input
-// kP1In[j][o] with the kernel t_{kP1E[j][o]}; part 2 forms output o from input
-// kP2A[j][o] with t_0 and, where kP2B[j][o] >= 0, from input kP2B[j][o] with
-// the reflected t_1 (Eq 55, 77-78).  reg_path_ok checks the pass programs of
-// the basis against these tables before the register path is used.
-constexpr int kP1In[3][4] = {{0, 0, -1, -1}, {0, 1, 0, -1}, {0, 1, 2, 0}};
-constexpr int kP1E[3][4] = {{0, 1, -1, -1}, {0, 0, 1, -1}, {0, 0, 0, 1}};
-constexpr int kP2A[3][3] = {{0, -1, -1}, {0, 1, -1}, {0, 1, 2}};
-constexpr int kP2B[3][3] = {{1, -1, -1}, {2, -1, -1}, {3, -1, -1}};
+// Term structure of the K d passes (Eq 55, 77-78): each term convolves input
+// `in` of a pass with the kernel t_e (part 1) or the reflected t_e (part 2)
+// and adds the result to output `out`.  One table per basis (3D, monomials in
+// graded order); reg_path_ok checks the pass programs of the basis against
+// the table before the register path is used.
+struct RTerm {
+    int out, in, e;
+};
+struct RPass {
+    int nin, nout, nterm;
+    RTerm t[10];
+};
+// linear basis: 1, x, y, z
+struct Lin3 {
+    static constexpr int S = 4, NE = 2, DEGREE = 1;
+    static constexpr RPass p1[3] = {
+        {1, 2, 2, {{0, 0, 0}, {1, 0, 1}}},
+        {2, 3, 3, {{0, 0, 0}, {1, 1, 0}, {2, 0, 1}}},
+        {3, 4, 4, {{0, 0, 0}, {1, 1, 0}, {2, 2, 0}, {3, 0, 1}}}};
+    static constexpr RPass p2[3] = {
+        {2, 1, 2, {{0, 0, 0}, {0, 1, 1}}},
+        {3, 2, 3, {{0, 0, 0}, {0, 2, 1}, {1, 1, 0}}},
+        {4, 3, 4, {{0, 0, 0}, {0, 3, 1}, {1, 1, 0}, {2, 2, 0}}}};
+};
+// quadratic basis: 1, x, y, z, x^2, xy, xz, y^2, yz, z^2
+struct Quad3 {
+    static constexpr int S = 10, NE = 3, DEGREE = 2;
+    static constexpr RPass p1[3] = {
+        {1, 3, 3, {{0, 0, 0}, {1, 0, 1}, {2, 0, 2}}},
+        {3, 6, 6, {{0, 0, 0}, {1, 1, 0}, {2, 0, 1}, {3, 2, 0}, {4, 1, 1}, {5, 0, 2}}},
+        {6, 10, 10, {{0, 0, 0}, {1, 1, 0}, {2, 2, 0}, {3, 0, 1}, {4, 3, 0}, {5, 4, 0}, {6, 1, 1},
+                     {7, 5, 0}, {8, 2, 1}, {9, 0, 2}}}};
+    static constexpr RPass p2[3] = {
+        {3, 1, 3, {{0, 0, 0}, {0, 1, 1}, {0, 2, 2}}},
+        {6, 3, 6, {{0, 0, 0}, {0, 2, 1}, {0, 5, 2}, {1, 1, 0}, {1, 4, 1}, {2, 3, 0}}},
+        {10, 6, 10, {{0, 0, 0}, {0, 3, 1}, {0, 9, 2}, {1, 1, 0}, {1, 6, 1}, {2, 2, 0}, {2, 8, 1},
+                     {3, 4, 0}, {4, 5, 0}, {5, 7, 0}}}};
+};
 
-// Spectra of output O (in fwd's layout) from the input spectra Z.  Part 1
-// (more outputs than inputs): Y = T_e Z_in.  Part 2: Y = T_0 Z_a - T_1 Z_b
-// (the reflected odd kernel has the conjugate spectrum).
-template <class Lay, int NIN, int NOUT, int O, int R, class Sp>
-__device__ __forceinline__ void combine_o(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp)
+template <class B, int PART, int J>
+constexpr const RPass& rpass() { return PART == 1 ? B::p1[J] : B::p2[J]; }
+
+// index of the N-th term of output O in the pass (-1 past the last)
+template <class B, int PART, int J, int O, int N>
+constexpr int term_of()
 {
-    if constexpr (NOUT > NIN) {
-        constexpr int J = NOUT - 2, IN = kP1In[J][O];
-        static_assert(IN >= 0 && IN < NIN, "part-1 term");
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const cf z = Z[IN][i];
-            if constexpr (kP1E[J][O] == 0) {
-                const float a = sp.template e0<Lay>(i);
-                Y[i] = cf{a * z.x, a * z.y};
-            } else {
-                const float b = sp.template e1<Lay>(i);
-                Y[i] = cf{-b * z.y, b * z.x};
-            }
+    const RPass& P = rpass<B, PART, J>();
+    int n = 0;
+    for (int k = 0; k < P.nterm; ++k)
+        if (P.t[k].out == O) {
+            if (n == N) return k;
+            ++n;
         }
-    } else {
-        constexpr int J = NIN - 2, A = kP2A[J][O], B = kP2B[J][O];
-        static_assert(A >= 0 && A < NIN && B < NIN, "part-2 terms");
+    return -1;
+}
+
+// Y (+)= the spectrum of term K applied to its input: T_e Z for part 1, the
+// reflected kernel's spectrum (T_e for even e, its conjugate for odd e) for
+// part 2.  T_e is real for even e and imaginary for odd e (one float each).
+template <class Lay, class B, int PART, int J, int K, bool FIRST, int NIN, int R, class Sp>
+__device__ __forceinline__ void apply_term(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp)
+{
+    constexpr RTerm tm = rpass<B, PART, J>().t[K];
+    static_assert(tm.in >= 0 && tm.in < NIN, "term input");
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const float a = sp.template e0<Lay>(i);
-            const cf za = Z[A][i];
-            if constexpr (B >= 0) {
-                const float b = sp.template e1<Lay>(i);
-                const cf zb = Z[B][i];
-                Y[i] = cf{a * za.x + b * zb.y, a * za.y - b * zb.x};
-            } else {
-                Y[i] = cf{a * za.x, a * za.y};
-            }
-        }
+    for (int i = 0; i < R; ++i) {
+        const float a = sp.template e<Lay, tm.e>(i);
+        const cf z = Z[tm.in][i];
+        cf v;
+        if constexpr ((tm.e & 1) == 0) v = cf{a * z.x, a * z.y};
+        else if constexpr (PART == 1) v = cf{-a * z.y, a * z.x};
+        else v = cf{a * z.y, -a * z.x};
+        if constexpr (FIRST) Y[i] = v;
+        else Y[i] = cf{Y[i].x + v.x, Y[i].y + v.y};
     }
 }
 
-template <class Lay, int NIN, int NOUT, int R, class Sp, int... O>
+template <class Lay, class B, int PART, int J, int O, int NIN, int R, class Sp, int... N>
+__device__ __forceinline__ void combine_o(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp,
+                                          std::integer_sequence<int, N...>)
+{
+    static_assert(term_of<B, PART, J, O, 0>() >= 0, "every output has a term");
+    ((term_of<B, PART, J, O, N>() >= 0
+          ? apply_term<Lay, B, PART, J, (term_of<B, PART, J, O, N>() >= 0 ? term_of<B, PART, J, O, N>() : 0),
+                       N == 0>(Z, Y, sp)
+          : void()),
+     ...);
+}
+
+template <class Lay, class B, int PART, int J, int NIN, int R, class Sp, int... O>
 __device__ __forceinline__ void combine_sel(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp,
                                             std::integer_sequence<int, O...>)
 {
-    ((o == O ? combine_o<Lay, NIN, NOUT, O>(Z, Y, sp) : void()), ...);
+    ((o == O ? combine_o<Lay, B, PART, J, O>(Z, Y, sp, std::make_integer_sequence<int, 3>{}) : void()),
+     ...);
 }
 
-// o is constant once the caller's loop over the outputs is unrolled, so the
-// selection folds away
-template <class Lay, int NIN, int NOUT, int R, class Sp>
+// Spectra of output o of pass (PART, J) from the input spectra Z (fwd's
+// layout).  o is constant once the caller's loop over the outputs is
+// unrolled, so the selection folds away.
+template <class Lay, class B, int PART, int J, int NIN, int R, class Sp>
 __device__ __forceinline__ void combine(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp)
 {
-    combine_sel<Lay, NIN, NOUT>(Z, o, Y, sp, std::make_integer_sequence<int, NOUT>{});
+    combine_sel<Lay, B, PART, J>(Z, o, Y, sp, std::make_integer_sequence<int, rpass<B, PART, J>().nout>{});
 }
 
 struct RArgs {
@@ -358,16 +437,16 @@ struct RArgs {
     long fstride;             // floats between fields
     long in_rb, out_rb;       // floats between right-hand sides (blockIdx.y)
     long st;                  // element stride of the axis; 1 for x
-    const float* tr;          // [2][L]: Re T_0 / L, Im T_1 / L of the axis
+    const float* tr;          // [3][L]: Re T_0 / L, Im T_1 / L, Re T_2 / L of the axis
     const cf* tw;             // [L] e^{-2 pi i j / L}
-    long nn;
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
     const float* dot_with;
     const uint2* nbits;       // middle pass, per lane: .x bit 2m+c set if node c of element
                               // m is interior, .y bit m set if element m reads a record
     const uint32_t* noff;     // middle pass: per lane, its first record
     const float4* rec;        // middle pass: records of kRec floats
-    float mi[10];             // middle pass: M of the interior nodes (kSym order)
+    float ci[kMaxNodeConst + 1];  // middle pass, interior nodes: M (linear basis, sym_index
+                                  // order) or b^a (a-major) and V (quadratic basis)
     // first x pass inside CG (PUPD): the pending direction update p = r + beta p
     // with beta = (sum of rr_part) / scal[parity], written back to `in`
     const float* rvec;
@@ -394,7 +473,7 @@ __host__ __device__ constexpr int sym_index(int p, int q)
 }
 
 // e = M d for the symmetric M of one node
-__device__ __forceinline__ void sym4_apply(const float (&M)[10], float d0, float d1, float d2, float d3,
+__device__ __forceinline__ void sym4_apply(const float* M, float d0, float d1, float d2, float d3,
                                            float (&e)[4])
 {
     e[0] = M[0] * d0 + M[1] * d1 + M[2] * d2 + M[3] * d3;
@@ -464,16 +543,16 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks)
 }
 
 // The twiddle table of the axis and, for layouts that read the spectra from
-// LDS, the spectra: each thread loads its share into registers (fetch) and
-// writes it to LDS later (put), so these loads and those of the input lines
-// are in flight together.
-template <class Lay>
+// LDS, the NE spectra: each thread loads its share into registers (fetch)
+// and writes it to LDS later (put), so these loads and those of the input
+// lines are in flight together.
+template <class Lay, int NE>
 struct Tables {
     static constexpr int L = Lay::L;
-    static constexpr bool SPEC = std::is_same<typename Lay::Spec, SpecLds>::value;
-    static constexpr int NT = (L + kRT - 1) / kRT;                    // twiddles per thread
-    static constexpr int NS = SPEC ? (2 * L + kRT - 1) / kRT : 0;     // spectrum values per thread
-    static constexpr int LDS_SPEC = SPEC ? 2 * L : 1;                 // floats of the LDS copy
+    static constexpr bool SPEC = std::is_same<typename Lay::template Spec<NE>, SpecLds>::value;
+    static constexpr int NT = (L + kRT - 1) / kRT;                     // twiddles per thread
+    static constexpr int NS = SPEC ? (NE * L + kRT - 1) / kRT : 0;     // spectrum values per thread
+    static constexpr int LDS_SPEC = SPEC ? NE * L : 1;                 // floats of the LDS copy
     cf w[NT];
     float s[NS > 0 ? NS : 1];
     __device__ __forceinline__ void fetch(const RArgs& a)
@@ -486,7 +565,7 @@ struct Tables {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             const int e = threadIdx.x + i * kRT;
-            if (e < 2 * L) s[i] = a.tr[e];
+            if (e < NE * L) s[i] = a.tr[e];
         }
     }
     __device__ __forceinline__ void put(cf* tw, float* trl) const
@@ -499,7 +578,7 @@ struct Tables {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             const int e = threadIdx.x + i * kRT;
-            if (e < 2 * L) trl[e] = s[i];
+            if (e < NE * L) trl[e] = s[i];
         }
         __syncthreads();
     }
@@ -530,13 +609,14 @@ __device__ __forceinline__ void stage_move(cf (&v)[Lay::PTS], cf* buf, int gw, i
 // masked by mask_out and, if dot_part is set, dotted with dot_with.
 // TPW tiles per workgroup: the inputs of all of them are loaded up front, so
 // the later tiles' loads overlap the earlier tiles' transforms and stores.
-template <class Lay, int TPW, bool CONTIG, bool LMASK, bool SMASK, int NIN, int NOUT,
+template <class Lay, class B, int TPW, bool CONTIG, bool LMASK, bool SMASK, int PART, int J,
           bool PUPD = false>
 __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 {
     constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr int NIN = rpass<B, PART, J>().nin, NOUT = rpass<B, PART, J>().nout;
     __shared__ cf tw[L];
-    __shared__ float trl[Tables<Lay>::LDS_SPEC];
+    __shared__ float trl[Tables<Lay, B::NE>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
     __shared__ cf stage[CONTIG ? 1 : 2][CONTIG ? 1 : Lay::STAGE];
@@ -556,9 +636,9 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 #pragma unroll
         for (int k = 0; k < NPART; ++k) part[k] = a.rr_part[rhs * kRedBlocks + tid + k * kRT];
     }
-    Tables<Lay> tabs;
+    Tables<Lay, B::NE> tabs;
     tabs.fetch(a);
-    typename Lay::Spec sp;
+    typename Lay::template Spec<B::NE> sp;
     sp.template fetch<Lay>(a.tr, t);
 
     cf Z[TPW][NIN][R];
@@ -665,7 +745,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<Lay, NIN, NOUT>(Z[tt], o, Y, sp);
+        combine<Lay, B, PART, J>(Z[tt], o, Y, sp);
         Lay::inv(Y, t, xb, lw);
         if constexpr (!CONTIG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
@@ -702,7 +782,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     constexpr int L = Lay::L, R = Lay::PTS;
     constexpr int S = 4;
     __shared__ cf tw[L];
-    __shared__ float trl[Tables<Lay>::LDS_SPEC];
+    __shared__ float trl[Tables<Lay, Lin3::NE>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ cf stage[2][Lay::STAGE];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
@@ -712,9 +792,9 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
     float* out = a.out + rhs * a.out_rb;
     const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
-    Tables<Lay> tabs;
+    Tables<Lay, Lin3::NE> tabs;
     tabs.fetch(a);
-    typename Lay::Spec sp;
+    typename Lay::template Spec<Lin3::NE> sp;
     sp.template fetch<Lay>(a.tr, t);
 
     cf Z[TPW][NIN][R];
@@ -753,7 +833,7 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
             Lay::fwd(Z[tt][f], t, xb, lw);
         }
 #pragma unroll
-        for (int q = 0; q < S; ++q) combine<Lay, NIN, S>(Z[tt], q, D[q], sp);
+        for (int q = 0; q < S; ++q) combine<Lay, Lin3, 1, 2>(Z[tt], q, D[q], sp);
     }
     // the records of the first element pair (the rows at the two ends of the
     // line, where the boundary lies) are requested before the inverse
@@ -787,8 +867,8 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
             const int m = u ? R - 1 - h : h;
             // interior nodes: the shared M (uniform); outside the domain: 0
             float e0[S], e1[S];
-            sym4_apply(a.mi, D[0][m].x, D[1][m].x, D[2][m].x, D[3][m].x, e0);
-            sym4_apply(a.mi, D[0][m].y, D[1][m].y, D[2][m].y, D[3][m].y, e1);
+            sym4_apply(a.ci, D[0][m].x, D[1][m].x, D[2][m].x, D[3][m].x, e0);
+            sym4_apply(a.ci, D[0][m].y, D[1][m].y, D[2][m].y, D[3][m].y, e1);
             const bool i0 = (bw[tt].x >> (2 * m)) & 1u, i1 = (bw[tt].x >> (2 * m + 1)) & 1u;
 #pragma unroll
             for (int p = 0; p < S; ++p) {
@@ -820,13 +900,242 @@ __global__ __launch_bounds__(kRT) void k_rmid(RArgs a)
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
         cf Y[R];
-        combine<Lay, S, NOUT>(D, o, Y, sp);
+        combine<Lay, Lin3, 2, 2>(D, o, Y, sp);
         Lay::inv(Y, t, xb, lw);
         stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < R; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[m]);
     }
+    }
+}
+
+// Middle pass for the quadratic basis in 3D (s = 10).  The 10 fields D_q do
+// not fit in registers at once, so the pointwise stage streams: as each D_q
+// leaves its inverse transform, A^a += b^a_q D_q (Eq 90); then each E_p =
+// V sum_a b^a_p A^a is formed, transformed and added to the one output it
+// feeds (Eq 91, Alg 2).  The D_q are taken in an order that retires the
+// inputs early (an input is dead after its last term).  Interior nodes take
+// b^a and V from the kernel argument, nodes outside the domain give zero,
+// and the other elements read records of kRec2 floats: b^a_q of the two
+// nodes interleaved, q-major then a ([q][a][node], 60 floats), then V of both.
+constexpr int kRec2 = 64;
+constexpr int kQOrder[10] = {4, 5, 7, 1, 6, 2, 8, 0, 3, 9};
+
+// A^a += b^a_Q d for element m (d: its two nodes).  Interior nodes use the
+// kernel argument, nodes outside the domain add nothing, record elements
+// read b^a_Q of both nodes from their record.  The uniform products are
+// selected after they are formed, so the compiler has no reason to compute
+// them ahead for every element.
+template <int Q, int R>
+__device__ __forceinline__ void quad_acc(const RArgs& a, uint2 bw, uint32_t off, int m, cf d,
+                                         cf (&A)[3][R], bool first)
+{
+    const bool i0 = (bw.x >> (2 * m)) & 1u, i1 = (bw.x >> (2 * m + 1)) & 1u;
+    cf add[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const float bq = a.ci[al * 10 + Q];
+        add[al] = cf{i0 ? bq * d.x : 0.0f, i1 ? bq * d.y : 0.0f};
+    }
+    if ((bw.y >> m) & 1u) {
+        const uint32_t km = __popc(bw.y & ((1u << m) - 1u));
+        const float2* r2 = reinterpret_cast<const float2*>(a.rec) + (size_t)(off + km) * (kRec2 / 2);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const float2 b = r2[Q * 3 + al];
+            add[al] = cf{b.x * d.x, b.y * d.y};
+        }
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al) A[al][m] = first ? add[al] : cf{A[al][m].x + add[al].x, A[al][m].y + add[al].y};
+}
+
+// E_P = V sum_a b^a_P A^a for element m's two nodes; A^a of element m is
+// As[(a R + m) kRT] (this lane's values, parked in LDS)
+template <int P, int R>
+__device__ __forceinline__ cf quad_e(const RArgs& a, uint2 bw, uint32_t off, int m, const cf* As)
+{
+    const cf A[3][1] = {{As[(0 * R + m) * kRT]}, {As[(1 * R + m) * kRT]}, {As[(2 * R + m) * kRT]}};
+    const bool i0 = (bw.x >> (2 * m)) & 1u, i1 = (bw.x >> (2 * m + 1)) & 1u;
+    float e0 = a.ci[P] * A[0][0].x, e1 = a.ci[P] * A[0][0].y;
+#pragma unroll
+    for (int al = 1; al < 3; ++al) {
+        e0 += a.ci[al * 10 + P] * A[al][0].x;
+        e1 += a.ci[al * 10 + P] * A[al][0].y;
+    }
+    cf e = cf{i0 ? a.ci[30] * e0 : 0.0f, i1 ? a.ci[30] * e1 : 0.0f};
+    if ((bw.y >> m) & 1u) {
+        const uint32_t km = __popc(bw.y & ((1u << m) - 1u));
+        const float2* r2 = reinterpret_cast<const float2*>(a.rec) + (size_t)(off + km) * (kRec2 / 2);
+        float2 b[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) b[al] = r2[P * 3 + al];
+        const float2 v = r2[30];
+        float f0 = b[0].x * A[0][0].x, f1 = b[0].y * A[0][0].y;
+#pragma unroll
+        for (int al = 1; al < 3; ++al) {
+            f0 += b[al].x * A[al][0].x;
+            f1 += b[al].y * A[al][0].y;
+        }
+        e = cf{v.x * f0, v.y * f1};
+    }
+    return e;
+}
+
+// one part-2 term of the quadratic middle pass: E_p from A, its forward
+// transform, and Y (+)= the reflected kernel's spectrum times it
+template <class Lay, int O, int N, int TPW_UNUSED = 0>
+__device__ __forceinline__ void quad_out_term(const RArgs& a, uint2 bw, uint32_t off, const cf* A,
+                                              cf (&Y)[Lay::PTS], int t, cf* xb, const typename Lay::Tw& lw,
+                                              const typename Lay::template Spec<Quad3::NE>& sp)
+{
+    constexpr int K = term_of<Quad3, 2, 2, O, N>();
+    if constexpr (K >= 0) {
+        constexpr int P = Quad3::p2[2].t[K].in;
+        cf E[1][Lay::PTS];
+        uint32_t roff = off;
+#pragma unroll
+        for (int m = 0; m < Lay::PTS; ++m) {
+            E[0][m] = quad_e<P, Lay::PTS>(a, bw, roff, m, A);
+            // the next element's record index depends on this result, so the
+            // compiler cannot hoist every element's loads and hold them all
+            if (m & 1) asm volatile("" : "+v"(roff) : "v"(E[0][m].x));
+        }
+        Lay::fwd(E[0], t, xb, lw);
+        // the term reads input 0 of this one-field view
+        constexpr RTerm tm = Quad3::p2[2].t[K];
+#pragma unroll
+        for (int i = 0; i < Lay::PTS; ++i) {
+            const float c = sp.template e<Lay, tm.e>(i);
+            const cf z = E[0][i];
+            cf w;
+            if constexpr ((tm.e & 1) == 0) w = cf{c * z.x, c * z.y};
+            else w = cf{c * z.y, -c * z.x};
+            if constexpr (N == 0) Y[i] = w;
+            else Y[i] = cf{Y[i].x + w.x, Y[i].y + w.y};
+        }
+    }
+}
+
+template <class Lay, int TPW>
+__global__ __launch_bounds__(kRT) void k_rmid2(RArgs a)
+{
+    using B = Quad3;
+    constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr int NIN = B::p1[2].nin, NOUT = B::p2[2].nout;
+    static_assert(B::p1[2].nout == B::S && B::p2[2].nin == B::S, "middle pass fields");
+    static_assert(TPW == 1, "one tile per workgroup");
+    __shared__ cf tw[L];
+    __shared__ float trl[Tables<Lay, B::NE>::LDS_SPEC];
+    __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
+    // every input waits in its own staging slot until its first term, so only
+    // the inputs in use occupy registers; the outputs reuse the first two slots
+    __shared__ cf slot[NIN][Lay::STAGE];
+    const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
+    const int gc = tid % Lay::GROUPS, tc = tid / Lay::GROUPS;
+    const long rhs = blockIdx.y;
+    const float* in = a.in + rhs * a.in_rb;
+    float* out = a.out + rhs * a.out_rb;
+    const long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const long base = tile_base<Lay, false>(tile, a.st);
+    cf* xb = xbuf + g * Lay::XS;
+    Tables<Lay, B::NE> tabs;
+    tabs.fetch(a);
+    typename Lay::template Spec<B::NE> sp;
+    sp.template fetch<Lay>(a.tr, t);
+    {
+        cf raw[NIN][R];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f)
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                raw[f][m] = load_pair<L, false>(in + f * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st));
+#pragma unroll
+        for (int f = 0; f < NIN; ++f)
+#pragma unroll
+            for (int m = 0; m < R; ++m) slot[f][m * Lay::SS + tc * Lay::TP + gc] = raw[f][m];
+    }
+    const long lane = tile * kRT + tid;
+    const uint2 bw = a.nbits[lane];
+    const uint32_t off = a.noff[lane];
+    tabs.put(tw, trl);  // its barrier also orders the slot writes before the reads
+    sp.template bind<Lay>(trl, t);
+    typename Lay::Tw lw;
+    lw.make(t, tw);
+
+    // input f in the transform layout, forward transformed
+    auto take = [&](int f, cf (&Zf)[R]) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) Zf[m] = slot[f][m * Lay::SS + t * Lay::TP + g];
+        Lay::fwd(Zf, t, xb, lw);
+    };
+    cf Z[NIN][R];
+    cf A[3][R];
+#pragma unroll
+    for (int k = 0; k < B::S; ++k) {
+        const int q = kQOrder[k];
+        // the first use of an input brings it in from its slot
+        if (k == 0) take(3, Z[3]);
+        if (k == 1) take(4, Z[4]);
+        if (k == 2) take(5, Z[5]);
+        if (k == 3) take(1, Z[1]);
+        if (k == 5) take(2, Z[2]);
+        if (k == 7) take(0, Z[0]);
+        cf D[R];
+        combine<Lay, B, 1, 2>(Z, q, D, sp);
+        Lay::inv(D, t, xb, lw);
+        uint32_t roff = off;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            // q is constant after unrolling; quad_acc takes it as a template argument
+            switch (q) {
+                case 0: quad_acc<0>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 1: quad_acc<1>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 2: quad_acc<2>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 3: quad_acc<3>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 4: quad_acc<4>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 5: quad_acc<5>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 6: quad_acc<6>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 7: quad_acc<7>(a, bw, roff, m, D[m], A, k == 0); break;
+                case 8: quad_acc<8>(a, bw, roff, m, D[m], A, k == 0); break;
+                default: quad_acc<9>(a, bw, roff, m, D[m], A, k == 0); break;
+            }
+            if (m & 1) asm volatile("" : "+v"(roff) : "v"(A[0][m].x));
+        }
+        // keep the scheduler from computing later D_q early (each would hold
+        // another field of registers)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // every input has been read from its slot before the outputs reuse them;
+    // A waits in the slots after the first two (this lane's own values, so
+    // program order suffices), leaving the registers to the output transforms
+    __syncthreads();
+    cf* As = &slot[2][0] + tid;
+    static_assert(3 * R * kRT <= (NIN - 2) * Lay::STAGE, "A fits the free slots");
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int m = 0; m < R; ++m) As[(al * R + m) * kRT] = A[al][m];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        cf Y[R];
+        switch (o) {
+#define FC_OUT(OO)                                                          \
+    case OO:                                                                \
+        quad_out_term<Lay, OO, 0>(a, bw, off, As, Y, t, xb, lw, sp);       \
+        quad_out_term<Lay, OO, 1>(a, bw, off, As, Y, t, xb, lw, sp);       \
+        quad_out_term<Lay, OO, 2>(a, bw, off, As, Y, t, xb, lw, sp);       \
+        break;
+            FC_OUT(0) FC_OUT(1) FC_OUT(2) FC_OUT(3) FC_OUT(4) default: FC_OUT(5)
+#undef FC_OUT
+        }
+        Lay::inv(Y, t, xb, lw);
+        stage_move<Lay>(Y, slot[o & 1], g, t, gc, tc);
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[m]);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -843,7 +1152,7 @@ void rlaunch(const RegProf& prof, int k, K kern, dim3 grid, dim3 block, hipStrea
     else hipLaunchKernelGGL(kern, grid, block, 0, st, a);
 }
 
-template <class Lay, int TPW>
+template <class Lay, class B, int TPW>
 void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
            double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
            const RegPupd* pu)
@@ -863,7 +1172,6 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.st = axis == 0 ? 1 : (axis == 1 ? (long)c.n[0] : (long)c.n[0] * c.n[1]);
         a.tr = c.rtab32[axis];
         a.tw = c.tw32[axis];
-        a.nn = nn;
         return a;
     };
     // x: u (masked) -> X, in CG with the pending direction update of u = p
@@ -877,15 +1185,15 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
             a.scal = pu->scal;
             a.parity = pu->parity;
             a.act = pu->act;
-            rlaunch(prof, 0, k_rpass<Lay, TPW, true, true, false, 1, 2, true>, grid, block, st, a);
+            rlaunch(prof, 0, k_rpass<Lay, B, TPW, true, true, false, 1, 0, true>, grid, block, st, a);
         } else {
-            rlaunch(prof, 0, k_rpass<Lay, TPW, true, true, false, 1, 2>, grid, block, st, a);
+            rlaunch(prof, 0, k_rpass<Lay, B, TPW, true, true, false, 1, 0>, grid, block, st, a);
         }
     }
     // y: X -> XY
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        rlaunch(prof, 1, k_rpass<Lay, TPW, false, false, false, 2, 3>, grid, block, st, a);
+        rlaunch(prof, 1, k_rpass<Lay, B, TPW, false, false, false, 1, 1>, grid, block, st, a);
     }
     // z: XY -> D -> E -> part-2 XY
     {
@@ -893,13 +1201,20 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.nbits = c.nbits[c.reg_layout];
         a.noff = c.noff[c.reg_layout];
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
-        for (int k = 0; k < 10; ++k) a.mi[k] = c.reg_mi[k];
-        rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
+        if constexpr (B::DEGREE == 1) {
+            for (int k = 0; k < 10; ++k) a.ci[k] = c.reg_mi[k];
+            rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
+        } else {
+            for (int k = 0; k <= kMaxNodeConst; ++k) a.ci[k] = c.cint32[k];
+            // same tile geometry; 16-lane lines read their twiddles and spectra from LDS here
+            using MidLay = typename std::conditional<std::is_same<Lay, G16>::value, G16L, Lay>::type;
+            rlaunch(prof, 2, k_rmid2<MidLay, TPW>, grid, block, st, a);
+        }
     }
     // y: XY -> X
     {
         RArgs a = args(1, S1, slot_rb, S2, slot_rb);
-        rlaunch(prof, 3, k_rpass<Lay, TPW, false, false, false, 3, 2>, grid, block, st, a);
+        rlaunch(prof, 3, k_rpass<Lay, B, TPW, false, false, false, 2, 1>, grid, block, st, a);
     }
     // x: X -> f (masked), with the optional dot partials
     {
@@ -907,7 +1222,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.mask_out = mask;
         a.dot_part = dot_part;
         a.dot_with = dot_with;
-        rlaunch(prof, 4, k_rpass<Lay, TPW, true, false, true, 2, 1>, grid, block, st, a);
+        rlaunch(prof, 4, k_rpass<Lay, B, TPW, true, false, true, 2, 0>, grid, block, st, a);
     }
 }
 
@@ -977,6 +1292,39 @@ __global__ void k_rmid_recs(const uint2* __restrict__ bits, const uint32_t* __re
     }
 }
 
+// The records of the quadratic basis: b^a_q of the two nodes, [q][a][node],
+// then V of both (kRec2 floats, FP32 copies of the FP64 arrays).
+template <class Lay>
+__global__ void k_rmid_recs2(const uint2* __restrict__ bits, const uint32_t* __restrict__ off,
+                             const double* __restrict__ ba, const double* __restrict__ vol, long st,
+                             long nblk, long nn, float* __restrict__ rec)
+{
+    constexpr int S = 10;
+    const long n = nblk * kRT;
+    for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n;
+         s += (long)gridDim.x * blockDim.x) {
+        const long tile = s / kRT;
+        const int lane = (int)(s % kRT), g = lane / Lay::LANES, t = lane % Lay::LANES;
+        const long base = tile_base<Lay, false>(tile, st);
+        const uint32_t need = bits[s].y;
+        long r = off[s];
+        for (int m = 0; m < Lay::PTS; ++m) {
+            if (!((need >> m) & 1u)) continue;
+            const long idx = elem_index<Lay, false>(base, g, t, m, st);
+            float* o = rec + r * kRec2;
+            for (int c = 0; c < 2; ++c) {
+                const long node = idx + c;
+                for (int q = 0; q < S; ++q)
+                    for (int al = 0; al < 3; ++al)
+                        o[(q * 3 + al) * 2 + c] = (float)ba[(long)(al * S + q) * nn + node];
+                o[60 + c] = (float)vol[node];
+                o[62 + c] = 0.0f;
+            }
+            ++r;
+        }
+    }
+}
+
 template <class Lay>
 void build_bits(const Ctx& c, const uint8_t* cls, uint2* bits, uint32_t* count,
                 unsigned long long* nload, hipStream_t st)
@@ -990,8 +1338,38 @@ template <class Lay>
 void build_recs(const Ctx& c, const uint2* bits, const uint32_t* off, float* rec, hipStream_t st)
 {
     const long str = (long)c.n[0] * c.n[1];
-    hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_64, c.vol64,
-                       str, blocks_of<Lay>(c), c.nn, rec);
+    if (c.degree == 2)
+        hipLaunchKernelGGL((k_rmid_recs2<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_64,
+                           c.vol64, str, blocks_of<Lay>(c), c.nn, rec);
+    else
+        hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_64,
+                           c.vol64, str, blocks_of<Lay>(c), c.nn, rec);
+}
+
+// the pass programs of the basis are exactly the table's terms (in order)
+// with coefficient 1/(2L), and -1/(2L) for the odd reflected kernels of part 2
+template <class B>
+bool plan_matches(const Ctx& c)
+{
+    if (c.s != B::S) return false;
+    const SepPlan& sp = c.basis_plan;
+    for (int j = 0; j < 3; ++j) {
+        if (c.axes[j] != j) return false;
+        const double inv = 1.0 / (2.0 * c.n[j]);
+        for (int part = 1; part <= 2; ++part) {
+            const SepProg& f = part == 1 ? sp.p1[j] : sp.p2[j];
+            const RPass& T = part == 1 ? B::p1[j] : B::p2[j];
+            if (f.nin != T.nin || f.nout != T.nout || f.ostart[f.nout] != T.nterm) return false;
+            for (int k = 0; k < T.nterm; ++k) {
+                const SepTerm& tm = f.t[k];
+                const RTerm& want = T.t[k];
+                const double coef = (part == 2 && (want.e & 1)) ? -inv : inv;
+                if (tm.out != want.out || tm.in != want.in || tm.e != want.e || tm.coef != coef) return false;
+                if (k < f.ostart[tm.out] || k >= f.ostart[tm.out + 1]) return false;
+            }
+        }
+    }
+    return true;
 }
 
 }  // namespace
@@ -1000,10 +1378,13 @@ void build_recs(const Ctx& c, const uint2* bits, const uint32_t* off, float* rec
 int reg_layouts(const Ctx& c) { return c.n[0] == 128 ? 2 : 1; }
 
 // variant v = layout + 2 (tiles - 1); 8-lane 128-point lines with 2 tiles
-// per workgroup need more registers than a wave has, so that one is absent
+// per workgroup need more registers than a wave has, so that one is absent.
+// The quadratic basis holds twice the fields: one tile per workgroup, and
+// 16 lanes per line at 128 points.
 bool reg_variant_ok(const Ctx& c, int v)
 {
     if (v < 0 || v > 3 || (v & 1) >= reg_layouts(c)) return false;
+    if (c.degree == 2) return c.n[0] == 128 ? v == 1 : v == 0;
     return !(c.n[0] == 128 && v == 2);
 }
 
@@ -1035,44 +1416,16 @@ void launch_reg_recs(const Ctx& c, int layout, const uint2* bits, const uint32_t
     }
 }
 
-int reg_record_floats() { return kRec; }
+int reg_record_floats(const Ctx& c) { return c.degree == 2 ? kRec2 : kRec; }
 
 bool reg_path_ok(const Ctx& c)
 {
-    if (c.dim != 3 || c.degree != 1 || c.naxes != 3 || c.s != 4) return false;
-    const SepPlan& sp = c.basis_plan;
-    if (sp.size[0] != 2 || sp.size[1] != 3 || sp.size[2] != 4) return false;
-    for (int j = 0; j < 3; ++j) {
-        if (sp.p1[j].nin != (j == 0 ? 1 : sp.size[j - 1]) || sp.p1[j].nout != sp.size[j]) return false;
-        if (sp.p2[j].nin != sp.size[j] || sp.p2[j].nout != (j == 0 ? 1 : sp.size[j - 1])) return false;
-    }
+    if (c.dim != 3 || c.naxes != 3 || (c.degree != 1 && c.degree != 2)) return false;
     const int L = c.n[0];
     if (L != 64 && L != 128) return false;
     if (c.n[1] != L || c.n[2] != L) return false;
-    // the kernels hard-wire the terms of the passes (kP1In .. kP2B) and the
-    // coefficient +-1/(2L) of every term
-    for (int j = 0; j < 3; ++j) {
-        if (c.axes[j] != j) return false;
-        const double inv = 1.0 / (2.0 * c.n[j]);
-        const SepProg& f = sp.p1[j];
-        for (int o = 0; o < f.nout; ++o) {
-            if (f.ostart[o + 1] - f.ostart[o] != 1) return false;
-            const SepTerm& tm = f.t[f.ostart[o]];
-            if (tm.in != kP1In[j][o] || tm.e != kP1E[j][o] || tm.coef != inv) return false;
-        }
-        const SepProg& g = sp.p2[j];
-        for (int o = 0; o < g.nout; ++o) {
-            const int nt = g.ostart[o + 1] - g.ostart[o];
-            if (nt != (kP2B[j][o] >= 0 ? 2 : 1)) return false;
-            for (int k = g.ostart[o]; k < g.ostart[o + 1]; ++k) {
-                const SepTerm& tm = g.t[k];
-                const bool ok0 = tm.e == 0 && tm.in == kP2A[j][o] && tm.coef == inv;
-                const bool ok1 = tm.e == 1 && tm.in == kP2B[j][o] && tm.coef == -inv;
-                if (!ok0 && !ok1) return false;
-            }
-        }
-    }
-    return true;
+    // the kernels hard-wire the terms of the passes and their coefficients
+    return c.degree == 1 ? plan_matches<Lin3>(c) : plan_matches<Quad3>(c);
 }
 
 // workgroups of one launch (each covers reg_tpw tiles)
@@ -1088,14 +1441,17 @@ void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
                   const RegPupd* pu)
 {
-#define FC_RUN(LAY)                                                                       \
-    do {                                                                                  \
-        if (c.reg_tpw == 2) run_k<LAY, 2>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu); \
-        else run_k<LAY, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);        \
+#define FC_RUN(LAY)                                                                               \
+    do {                                                                                          \
+        if (c.reg_tpw == 2) run_k<LAY, Lin3, 2>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu); \
+        else run_k<LAY, Lin3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);        \
     } while (0)
-    if (c.n[0] == 128) {
+    if (c.degree == 2) {
+        if (c.n[0] == 128) run_k<G16, Quad3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);
+        else run_k<G8<8>, Quad3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);
+    } else if (c.n[0] == 128) {
         if (c.reg_layout) FC_RUN(G16);
-        else run_k<G8<16>, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);  // 2 tiles spill
+        else run_k<G8<16>, Lin3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);  // 2 tiles spill
     } else {
         FC_RUN(G8<8>);
     }

@@ -362,14 +362,21 @@ def test_full_size_refined_solve_c5():
     assert err <= 5e-3
 
 
-@pytest.mark.parametrize("shape,n", [("cube", 64), ("cube", 128), ("sphere", 64), ("sphere", 128)])
+@pytest.mark.parametrize("shape,n", [("cube", 64), ("cube", 128), ("sphere", 64), ("sphere", 128),
+                                     ("sphere_quadratic", 64), ("sphere_quadratic", 128)])
 def test_register_path_matches_lds_path_and_oracle(shape, n):
-    """The register-resident FP32 K passes (64^3 and 128^3 boxes, linear
-    basis) against the LDS-tiled FP32 passes and the FP64 oracle.  The ball
-    (radius 0.4) puts nodes outside the domain and boundary elements along
-    every line, so both node classes without a record and the records
-    themselves are exercised."""
-    p = W.cube(3, n, 2.5, 1) if shape == "cube" else W.sphere(n, 0.4, 2.5, 1)
+    """The register-resident FP32 K passes (64^3 and 128^3 boxes, linear and
+    quadratic basis) against the LDS-tiled FP32 passes and the FP64 oracle.
+    The ball (radius 0.4) puts nodes outside the domain and boundary elements
+    along every line, so both node classes without a record and the records
+    themselves are exercised; the quadratic case is config 3's basis and
+    support (3.0h)."""
+    if shape == "cube":
+        p = W.cube(3, n, 2.5, 1)
+    elif shape == "sphere":
+        p = W.sphere(n, 0.4, 2.5, 1)
+    else:
+        p = W.sphere(n, 0.4, 3.0, 2)
     print(f"\n[register path {shape} {n}^3]", flush=True)
     from paper_2403_19854_amd import fcrkpm
     g = lib_problem(p)
@@ -384,7 +391,10 @@ def test_register_path_matches_lds_path_and_oracle(shape, n):
     ref = o.apply_k_at(np.where(p.free > 0, x, 0.0), idx)
     ref = np.where(p.free.reshape(-1)[idx] > 0, ref, 0.0)
     chosen = g.get_option(fcrkpm.OPT_REGLAYOUT)
-    layouts = [0, 1, 3] if n == 128 else [0, 2]
+    if p.degree == 2:
+        layouts = [1] if n == 128 else [0]
+    else:
+        layouts = [0, 1, 3] if n == 128 else [0, 2]
     print(f"  autotuned variant {chosen}; setup times (ns) "
           f"{[g.get_option(o) for o in (fcrkpm.OPT_TUNE_NS0, fcrkpm.OPT_TUNE_NS1, fcrkpm.OPT_TUNE_NS2, fcrkpm.OPT_TUNE_NS3)]}")
     with pytest.raises(fcrkpm.FcrkpmError):
