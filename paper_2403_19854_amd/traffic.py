@@ -26,20 +26,22 @@ COPY_BYTES = 256 << 20
 
 # demangled kernel name -> the kind name the library's sampler reports
 _KINDS = [
-    (r"k_rmid<", "sep_mid_k_f32"),
-    (r"k_rpass<[^,]+, \d, true, true, false, 1, 2(, (true|false))?>", "sep_part1_x_f32"),
-    (r"k_rpass<[^,]+, \d, false, false, false, 2, 3(, (true|false))?>", "sep_part1_y_f32"),
-    (r"k_rpass<[^,]+, \d, false, false, false, 3, 2(, (true|false))?>", "sep_part2_y_f32"),
-    (r"k_rpass<[^,]+, \d, true, false, true, 2, 1(, (true|false))?>", "sep_part2_x_f32"),
+    (r"k_rmid2?<", "sep_mid_k_f32"),
+    (r"k_rpass<[^,]+, [^,]+, \d, true, true, false, 1, 0(, (true|false))?>", "sep_part1_x_f32"),
+    (r"k_rpass<[^,]+, [^,]+, \d, false, false, false, 1, 1(, (true|false))?>", "sep_part1_y_f32"),
+    (r"k_rpass<[^,]+, [^,]+, \d, false, false, false, 2, 1(, (true|false))?>", "sep_part2_y_f32"),
+    (r"k_rpass<[^,]+, [^,]+, \d, true, false, true, 2, 0(, (true|false))?>", "sep_part2_x_f32"),
 ]
 
 
 def _variant(name):
-    """Register-path variant of a kernel name: layout + 2 (tiles - 1)."""
-    m = re.search(r"k_r(?:pass|mid)<[^,]*?(G16|G8<\d+>), (\d)", name)
+    """Register-path variant of a kernel name: layout + 2 (tiles - 1).  The pass
+    kernels carry the basis after the layout; the middle passes do not."""
+    m = re.search(r"k_rpass<[^,]*?(G16L?|G8<\d+>), [^,]+, (\d)", name) or \
+        re.search(r"k_rmid2?<[^,]*?(G16L?|G8<\d+>), (\d)", name)
     if not m:
         return None
-    return (1 if m.group(1) == "G16" else 0) + 2 * (int(m.group(2)) - 1)
+    return (1 if m.group(1).startswith("G16") else 0) + 2 * (int(m.group(2)) - 1)
 
 
 def source_hash() -> str:

@@ -12,10 +12,10 @@ HEAD = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "
         "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Counter_Name",
         "Counter_Value", "Start_Timestamp", "End_Timestamp"]
 MID = "void fcrkpm::(anonymous namespace)::k_rmid<fcrkpm::(anonymous namespace)::G16, 1, 3, 3>(x)"
-X1 = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G16, 1, true, "
-      "true, false, 1, 2, true>(x)")
-Y1_G8 = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G8<16>, 1, "
-         "false, false, false, 2, 3, false>(x)")
+X1 = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G16, "
+      "fcrkpm::(anonymous namespace)::Lin3, 1, true, true, false, 1, 0, true>(x)")
+Y1_G8 = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G8<16>, "
+         "fcrkpm::(anonymous namespace)::Lin3, 1, false, false, false, 1, 1, false>(x)")
 
 
 def _csv(path, counter, rows):
@@ -72,4 +72,5 @@ def test_variant_parsing():
     assert traffic._variant(MID.replace("(anonymous namespace)::", "")) == 1
     assert traffic._variant(Y1_G8) == 0
     assert traffic._variant("k_rmid<fcrkpm::G16, 2, 3, 3>") == 3
+    assert traffic._variant("k_rmid2<fcrkpm::G16L, 1>") == 1
     assert traffic._variant("k_cg_xr<float>") is None
