@@ -7,12 +7,17 @@ wrap-around.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package; the product
 library never does, and this package never imports the product library.
 
+The time-dependent part (App. C: consistent and lumped mass, implicit and
+explicit time stepping of the diffusion equation) is plain numpy on top of the
+same neighbour-loop operators.
+
 Every function works on numpy FP64 arrays in C order ``[nz][ny][nx]``
 (x fastest), 0/1 masks as uint8.
 """
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -220,3 +225,79 @@ class Oracle:
         it = _load().orc_adjoint(self._h, free, _f64(dl_du).reshape(-1), g,
                                  z.ctypes.data_as(C.c_void_p), tol, maxit, C.byref(rel))
         return g.reshape(self.shape), z.reshape(self.shape), it
+
+    # --- time-dependent problems (App. C) -----------------------------------
+    def apply_m(self, d):
+        """Consistent mass product f^m = M d with M = int N^T N dOmega under
+        direct nodal integration (Eq C.5, C.7): N^T (V o N d), i.e.
+        f_I = sum_K V_K Psi_I(x_K) sum_J Psi_J(x_K) d_J over domain nodes."""
+        return self.apply_fr(self.apply_uh(d))
+
+    def lumped_mass(self):
+        """Lumped mass M^l_II = sum_P M_IP (Eq C.9): M applied to ones on the
+        domain nodes."""
+        return self.apply_m(self.chi.astype(np.float64))
+
+    def transient(self, free, dirichlet, d0, nu, dt, nsteps, r=None, g=None,
+                  scheme="implicit", theta=1.0, tol=1e-13, maxit=100000):
+        """Time stepping of M d' + nu K d = f^r (Eq C.1-C.4) with d = g held on
+        the Dirichlet nodes and r constant in time.
+
+        scheme "implicit" (Alg C.4): the theta method on the free rows,
+            (M + theta dt nu K) x1 = (M - (1-theta) dt nu K) x0 + dt (f^r - nu K d_G),
+          each step solved by CG from x0 to a relative residual of tol;
+          theta = 1 is backward Euler, theta = 1/2 Crank-Nicolson.
+        scheme "explicit" (Alg C.3): forward Euler with the lumped mass,
+            x1 = x0 + dt (f^r - nu K (x0 + d_G)) / M^l  on the free rows.
+        Returns (d at t = nsteps dt, CG iterations summed over the steps)."""
+        shape = self.shape
+        f = np.asarray(free).reshape(shape).astype(bool)
+        dG = np.zeros(shape)
+        if g is not None:
+            dG = np.where(np.asarray(dirichlet).reshape(shape).astype(bool),
+                          _f64(g).reshape(shape), 0.0)
+        fr = self.apply_fr(r) if r is not None else np.zeros(shape)
+        c0 = np.where(f, dt * (fr - nu * self.apply_k(dG)), 0.0)
+        x = np.where(f, _f64(d0).reshape(shape), 0.0)
+        its = 0
+        if scheme == "explicit":
+            ml = self.lumped_mass()
+            for _ in range(nsteps):
+                x = np.where(f, x + (c0 - dt * nu * self.apply_k(x)) / np.where(f, ml, 1.0), 0.0)
+            return x + dG, 0
+        if scheme != "implicit" or not (0.0 < theta <= 1.0):
+            raise ValueError("scheme must be 'implicit' (0 < theta <= 1) or 'explicit'")
+
+        def op(v):
+            return np.where(f, self.apply_m(v) + theta * dt * nu * self.apply_k(v), 0.0)
+
+        for _ in range(nsteps):
+            rhs = self.apply_m(x)
+            if theta < 1.0:
+                rhs = rhs - (1.0 - theta) * dt * nu * self.apply_k(x)
+            b = np.where(f, rhs, 0.0) + c0
+            x, k = _cg(op, b, x.copy(), tol, maxit)
+            its += k
+        return x + dG, its
+
+
+def _cg(op, b, x, tol, maxit):
+    """Plain conjugate gradients on a symmetric positive definite operator,
+    stopping when ||b - A x|| (recursive) <= tol ||b||."""
+    bn = math.sqrt(float(np.vdot(b, b)))
+    if bn == 0.0:
+        return np.zeros_like(b), 0
+    r = b - op(x)
+    p = r.copy()
+    rr = float(np.vdot(r, r))
+    for it in range(maxit):
+        if math.sqrt(rr) <= tol * bn:
+            return x, it
+        q = op(p)
+        alpha = rr / float(np.vdot(p, q))
+        x = x + alpha * p
+        r = r - alpha * q
+        rr1 = float(np.vdot(r, r))
+        p = r + (rr1 / rr) * p
+        rr = rr1
+    return x, maxit
