@@ -49,7 +49,9 @@ enum {
     FCRKPM_OP_FR = 2,     /* f^r = N^T (V o r)                               (Eq 60, 92; Alg 4)          */
     FCRKPM_OP_UH = 3,     /* u^h = N d at the nodes                          (Eq 63, 94; Alg 3)          */
     FCRKPM_OP_NT = 4,     /* N^T y  (Eq 92 without V)                                                    */
-    FCRKPM_OP_VN = 5      /* V o (N z)                                                                   */
+    FCRKPM_OP_VN = 5,     /* V o (N z)                                                                   */
+    FCRKPM_OP_M = 6       /* f^m = M d, consistent mass (Eq C.5, C.8, C.11; Alg C.1), domain mask
+                             in and out; the first call builds its coefficients (synchronous)           */
 };
 
 /* Number types. */
@@ -66,8 +68,24 @@ enum {
 enum {
     FCRKPM_COEF_B0 = 0,     /* b^0_p, p < s: first row of M^-1 (Eq 45, 83); [s][nodes]            */
     FCRKPM_COEF_BALPHA = 1, /* b^a_p: minus row a+1 of M^-1 (Eq 46-47, 84-85); [dim][s][nodes]    */
-    FCRKPM_COEF_FREE = 2    /* chi_Omega as 0/1 doubles (Eq 96); [nodes]                           */
+    FCRKPM_COEF_FREE = 2,   /* chi_Omega as 0/1 doubles (Eq 96); [nodes]                           */
+    FCRKPM_COEF_LUMPED_MASS = 3 /* M^l, row sums of M (Eq C.9-C.10, C.13; Alg C.2); [nodes]        */
 };
+
+/* Time schemes of fcrkpm_transient (App. C.3). */
+enum {
+    FCRKPM_TIME_IMPLICIT = 0,        /* theta method, one CG solve per step (Alg C.4) */
+    FCRKPM_TIME_EXPLICIT_LUMPED = 1  /* forward Euler with the lumped mass (Alg C.3)  */
+};
+
+typedef struct {
+    int32_t scheme;  /* FCRKPM_TIME_*                                                     */
+    int32_t nsteps;  /* time steps, >= 0                                                  */
+    double dt;       /* step size, > 0                                                    */
+    double nu;       /* diffusivity nu of Eq C.1, > 0                                     */
+    double theta;    /* implicit scheme: 0 < theta <= 1 (1 backward Euler, 0.5 Crank-
+                        Nicolson); ignored by the explicit scheme                         */
+} fcrkpm_time;
 
 typedef struct {
     int32_t dim;              /* spatial dimension d: 1, 2 or 3                             */
@@ -167,6 +185,45 @@ fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t n
 fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* r,
                            const double* g, double* d_inout, double* uh_out, double tol,
                            int32_t maxit, fcrkpm_info* info, void* stream);
+
+/*
+ * fcrkpm_transient -- time stepping of the diffusion problem (App. C, Eq C.1-
+ * C.4): M d' + nu K d = f^r with strong Dirichlet values d = g held on the
+ * Dirichlet nodes and a source r constant in time.  With x the free part of d
+ * and c0 = dt (f^r - nu K d_Gamma), every step solves on the free nodes
+ *   FCRKPM_TIME_IMPLICIT:        (M + theta dt nu K) x1 = (M - (1-theta) dt nu K) x0 + c0
+ *                                by CG from x0 (the solver of fcrkpm_solve, mode
+ *                                F64 or F32_REFINED, on the shifted operator, whose
+ *                                products run the K passes with the coefficient rows
+ *                                sqrt(theta dt nu) b^a and b^0; Alg C.1, C.4);
+ *   FCRKPM_TIME_EXPLICIT_LUMPED: x1 = x0 + (c0 - dt nu K x0) / M^l   (Alg C.2, C.3;
+ *                                FP64 products; stable for dt nu lambda_max < 2).
+ *
+ *   tp       scheme, nsteps, dt, nu, theta (fcrkpm_time)
+ *   mode     FCRKPM_MODE_F64 or FCRKPM_MODE_F32_REFINED (implicit); F64 (explicit)
+ *   nrhs     fields stepped together, laid out back to back
+ *   r        device FP64 source per node, or NULL for r = 0
+ *   g        device FP64 Dirichlet values per node, or NULL for g = 0
+ *   d_inout  device FP64 coefficients at t = 0 in (values on the Dirichlet nodes
+ *            are replaced by g), coefficients at t = nsteps dt out
+ *   uh_out   device FP64 u^h = N d at the final time (Alg 3), or NULL
+ *   tol      relative residual target of every step's solve (> 0)
+ *   maxit    CG iteration cap of every step's solve
+ *   info     nrhs records (may be NULL): iterations and products summed over
+ *            the steps, the largest residuals of any step
+ *
+ * Allocates a work field of nrhs x nodes doubles for the call; the coefficient
+ * rows of M and of the shifted operator stay with the context (the latter is
+ * rebuilt when theta dt nu changes).  Errors: FCRKPM_ERR_ARG (bad scheme,
+ * dt, nu, theta, nsteps, tol, maxit, NULL pointers, non-finite inputs);
+ * FCRKPM_ERR_UNSUPPORTED (explicit scheme in another mode);
+ * FCRKPM_ERR_SINGULAR (a lumped mass entry <= 0 on a free node);
+ * FCRKPM_ERR_NOCONV (a step's solve missed tol: stepping stops there and d
+ * holds that step's best iterate).
+ */
+fcrkpm_status fcrkpm_transient(fcrkpm_ctx* ctx, const fcrkpm_time* tp, int32_t mode, int32_t nrhs,
+                               const double* r, const double* g, double* d_inout, double* uh_out,
+                               double tol, int32_t maxit, fcrkpm_info* info, void* stream);
 
 /*
  * fcrkpm_solve_batch -- fcrkpm_solve for a ragged batch of problems: nprob

@@ -15,6 +15,7 @@
 #include <memory>
 #include <type_traits>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/fcrkpm.h"
@@ -122,8 +123,25 @@ void dfree(T*& p)
     p = nullptr;
 }
 
+void free_set(OpSet*& s)
+{
+    if (!s) return;
+    dfree(s->ba_64);
+    dfree(s->ba_32);
+    dfree(s->cls);
+    for (int l = 0; l < 2; ++l) {
+        dfree(s->nbits[l]);
+        dfree(s->noff[l]);
+        dfree(s->nrec[l]);
+    }
+    delete s;
+    s = nullptr;
+}
+
 void release(Ctx& c)
 {
+    free_set(c.mass_set);
+    free_set(c.shift_set);
     dfree(c.chi);
     dfree(c.cls);
     dfree(c.freem);
@@ -471,8 +489,85 @@ void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, h
     launch_reg_k(c, in, out, mask, nrhs, dot_part, dot_with, st, rp, pu);
 }
 
+void build_pointwise(Ctx& c, hipStream_t st);
+
+// Exchanges the pointwise data of the K-type product in use with `s`.
+void swap_set(Ctx& c, OpSet& s)
+{
+    std::swap(c.krows, s.krows);
+    std::swap(c.ba_64, s.ba_64);
+    std::swap(c.ba_32, s.ba_32);
+    std::swap(c.cls, s.cls);
+    std::swap(c.ncls2, s.ncls2);
+    std::swap(c.cint64, s.cint64);
+    std::swap(c.cint32, s.cint32);
+    std::swap(c.nbits, s.nbits);
+    std::swap(c.reg_mi, s.reg_mi);
+    std::swap(c.noff, s.noff);
+    std::swap(c.nrec, s.nrec);
+    std::swap(c.nload, s.nload);
+    std::swap(c.nconst, s.nconst);
+}
+
+// The products of a scope use the set `s` (kernels take their arguments at
+// launch, so the arrays only have to outlive the set).
+struct SetScope {
+    Ctx& c;
+    OpSet* s;
+    SetScope(Ctx& c_, OpSet* s_) : c(c_), s(s_) { if (s) swap_set(c, *s); }
+    ~SetScope() { if (s) swap_set(c, *s); }
+    SetScope(const SetScope&) = delete;
+    SetScope& operator=(const SetScope&) = delete;
+};
+
+// Pointwise data of c_m M + c_k K (App. C): the rows sqrt(c_k) b^a of the
+// stiffness (Eq 91) and sqrt(c_m) b^0 of the mass (Eq C.8), so that
+// V sum_rows c_p c_q = V (c_k B^T B + c_m b^0 b^0T).  Synchronous.
+OpSet* make_set(Ctx& c, double ck, double cm, hipStream_t st)
+{
+    if (c.capturing) fail(FCRKPM_ERR_ARG, "operator coefficients cannot be built during graph capture");
+    if (!(ck >= 0.0) || !(cm >= 0.0) || !(ck > 0.0 || cm > 0.0) || !std::isfinite(ck) || !std::isfinite(cm))
+        fail(FCRKPM_ERR_ARG, "operator weights must be finite, non-negative and not both zero");
+    OpSet* s = new OpSet();
+    s->krows = (ck > 0.0 ? c.dim : 0) + (cm > 0.0 ? 1 : 0);
+    try {
+        const size_t cnt = (size_t)s->krows * c.s * c.nn;
+        s->ba_64 = dalloc<double>(cnt);
+        s->ba_32 = dalloc<float>(cnt);
+        launch_op_rows(c, ck, cm, s->ba_64, s->ba_32, st);
+        HIPCHK(hipGetLastError());
+        SetScope use(c, s);
+        build_pointwise(c, st);
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        free_set(s);
+        throw;
+    }
+    return s;
+}
+
+// the consistent mass M (Eq C.8), built on first use
+OpSet* mass_set(Ctx& c, hipStream_t st)
+{
+    if (!c.mass_set) c.mass_set = make_set(c, 0.0, 1.0, st);
+    return c.mass_set;
+}
+
+// c_m M + c_k K, rebuilt when the weights change
+OpSet* shift_set(Ctx& c, double cm, double ck, hipStream_t st)
+{
+    if (!c.shift_set || c.shift_w[0] != cm || c.shift_w[1] != ck) {
+        HIPCHK(hipStreamSynchronize(st));
+        free_set(c.shift_set);
+        c.shift_set = make_set(c, ck, cm, st);
+        c.shift_w[0] = cm;
+        c.shift_w[1] = ck;
+    }
+    return c.shift_set;
+}
+
 // One operator on nrhs consecutive fields, arithmetic precision T, field type
-// Tio (Alg 2, 3, 4); every pass covers all fields in one launch.
+// Tio (Alg 2, 3, 4, C.1); every pass covers all fields in one launch.
 template <typename T, typename Tio = T>
 void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st)
 {
@@ -499,8 +594,8 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
             cplx<T>* dst = (cur == S1) ? S2 : S1;
             {
                 // coefficients are read only at class-2 nodes (1 B of class per node)
-                const double coef = c.cls ? (double)c.ncls2 * (c.dim * c.s + 1) * rt + nn
-                                          : nn * (c.dim * c.s + 1) * rt;
+                const double coef = c.cls ? (double)c.ncls2 * (c.krows * c.s + 1) * rt + nn
+                                          : nn * (c.krows * c.s + 1) * rt;
                 ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2) + coef, st);
                 if (k == 1)
                     launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], SEP_PW_K, SEP_LD_REAL, in, mk,
@@ -513,6 +608,13 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
                                            st, RhsBatch{nrhs, prs, prs, 0});
             }
             if (k > 1) part2<T, Tio>(c, sp, dst, S1, S2, out, mk, nrhs, st);
+            break;
+        }
+        case FCRKPM_OP_M: {
+            // f^m = M d (Eq C.8, C.11; Alg C.1): the passes of K with the single
+            // coefficient row b^0 and the domain mask on both sides
+            SetScope use(c, mass_set(c, st));
+            apply_one<T, Tio>(c, FCRKPM_OP_K_FULL, in, out, nrhs, st);
             break;
         }
         case FCRKPM_OP_FR:
@@ -770,6 +872,10 @@ struct Solver {
             start_f64(st);
             return;
         }
+        // FP32 refinement keeps its best iterate in vec64(V_T)
+        if (mode == FCRKPM_MODE_F32_REFINED)
+            HIPCHK(hipMemcpyAsync(vec64(c, V_T), vec64(c, V_X), sizeof(double) * nn * nrhs,
+                                  hipMemcpyDeviceToDevice, st));
         bool any = false;
         for (auto& s : R) {
             s.best = s.rel;
@@ -932,13 +1038,18 @@ struct Solver {
             for (int j = 0; j < nrhs; ++j) before[j] = R[j].rel;
             true_residual(st);
             bool any = false, need64 = false;
-            std::vector<int> restart;
+            std::vector<int> restart, restore;
+            const bool keep = mode == FCRKPM_MODE_F32_REFINED;
             for (int j = 0; j < nrhs; ++j) {
                 RhsState& s = R[j];
                 if (!s.active) {
                     s.rel = before[j];  // frozen: keep what it finished with
                     continue;
                 }
+                const bool improved = s.rel < s.best;
+                if (keep && improved)
+                    HIPCHK(hipMemcpyAsync(vec64(c, V_T) + j * nn, vec64(c, V_X) + j * nn,
+                                          sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
                 // the FP32 recursion has left the true residual far behind (its
                 // search direction no longer fits): restart it from the new
                 // residual instead of keeping the direction
@@ -970,11 +1081,30 @@ struct Solver {
                 } else if (s.want) {
                     s.stall = 0;
                 }
+                // stopping (converged by stall, handed to FP64 or out of
+                // iterations) on an iterate worse than the best: go back to it
+                if (keep && !s.active && !improved && s.rel > s.best) restore.push_back(j);
                 s.best = std::min(s.best, s.rel);
                 s.want = false;
                 if (s.active && drifted) restart.push_back(j);
                 any = any || s.active;
                 need64 = need64 || s.need64;
+            }
+            if (!restore.empty()) {
+                for (int j : restore)
+                    HIPCHK(hipMemcpyAsync(vec64(c, V_X) + j * nn, vec64(c, V_T) + j * nn,
+                                          sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+                std::vector<double> kept(nrhs);
+                for (int j = 0; j < nrhs; ++j) kept[j] = R[j].rel;
+                true_residual(st);  // V_R = b - K x for the FP64 phase
+                std::vector<bool> back(nrhs, false);
+                for (int j : restore) back[j] = true;
+                for (int j = 0; j < nrhs; ++j)
+                    if (!back[j]) R[j].rel = kept[j];
+                if (log_enabled())
+                    for (int j : restore)
+                        fprintf(stderr, "[fcrkpm] rhs %d back to its best iterate: true %.3e\n", j,
+                                R[j].rel);
             }
             if (any) {
                 if (mode == FCRKPM_MODE_F32_REFINED) {
@@ -1033,7 +1163,10 @@ struct Solver {
         true_residual(st);
         fcrkpm_status status = FCRKPM_OK;
         for (int j = 0; j < nrhs; ++j) {
-            const RhsState& s = R[j];
+            RhsState& s = R[j];
+            // refinement converges on the true residual: a final one far above
+            // tol (an FP64 finish whose recursion lost it) is not convergence
+            if (mode != FCRKPM_MODE_F64 && s.conv && !(s.rel <= 100.0 * tol)) s.conv = false;
             if (!s.conv) status = FCRKPM_ERR_NOCONV;
             if (info) {
                 fcrkpm_info& f = info[j];
@@ -1198,6 +1331,8 @@ void run_solvers_on(const std::vector<Solver*>& all, bool graphs, hipStream_t st
 
 }  // namespace
 
+[[noreturn]] void fcrkpm::raise_unsupported(const char* msg) { fail(FCRKPM_ERR_UNSUPPORTED, msg); }
+
 // ========================================================================= ABI
 
 namespace {
@@ -1228,6 +1363,97 @@ namespace {
 // with each variant -- line layout (8 or 16 lanes) times tiles per workgroup
 // (1 or 2) -- on this device and keep the fastest.  FCRKPM_REGLAYOUT=v in the
 // environment forces variant v = layout + 2 (tiles - 1).
+// Node classes and the pointwise data of the K-type product whose coefficient
+// rows c.ba_64 (c.krows of them) are in place: classes 0 outside the domain,
+// 1 interior, 2 other; the interior constants; and the register-path bits and
+// records.  The quadratic register records hold the rows b^a themselves, so
+// they serve K alone.
+void build_pointwise(Ctx& c, hipStream_t st)
+{
+    const long nn = c.nn;
+    // node classes (0 outside the domain, 1 interior, 2 other) for the
+    // pointwise stage of the K products: interior nodes share the first
+    // interior node's b^a and V, nodes outside have V = 0
+    if (c.krows * c.s <= kMaxNodeConst) {
+        int big = 0x7fffffff, ref = 0;
+        HIPCHK(hipMemcpyAsync(c.dflag + 3, &big, sizeof(int), hipMemcpyHostToDevice, st));
+        launch_first_interior(c, c.dflag + 3, st);
+        HIPCHK(hipMemcpyAsync(&ref, c.dflag + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int nb = c.krows * c.s;
+        NodeConst nc = {};
+        nc.bmax = -1.0;  // no interior node: every domain node is class 2
+        if (ref != 0x7fffffff) {
+            for (int q = 0; q < nb; ++q)
+                HIPCHK(hipMemcpy(&nc.b[q], c.ba_64 + (size_t)q * nn + ref, sizeof(double),
+                                 hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&nc.v, c.vol64 + ref, sizeof(double), hipMemcpyDeviceToHost));
+            nc.bmax = 0.0;
+            for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabs(nc.b[q]));
+        }
+        c.cls = dalloc<uint8_t>(nn);
+        launch_node_class(c, nc, c.cls, st);
+        {
+            std::vector<uint8_t> hc(nn);
+            HIPCHK(hipMemcpyAsync(hc.data(), c.cls, nn, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            c.ncls2 = (long)std::count(hc.begin(), hc.end(), (uint8_t)2);
+        }
+        c.nconst = nc;
+        for (int q = 0; q < nb; ++q) {
+            c.cint64[q] = nc.b[q];
+            c.cint32[q] = (float)nc.b[q];
+        }
+        c.cint64[nb] = nc.v;
+        c.cint32[nb] = (float)nc.v;
+    }
+    // node classes of the register-resident K passes: interior nodes share
+    // one M = V B^T B (a kernel argument), nodes outside the domain give
+    // zero, and every other element gets its own record, packed lane by lane
+    if (reg_path_ok(c) && c.cls && (c.degree == 1 || c.krows == c.dim)) {
+        const uint8_t* cls = c.cls;
+        const NodeConst& nc = c.nconst;
+        if (nc.bmax >= 0.0 && c.degree == 1) {
+            int k = 0;
+            for (int p = 0; p < c.s; ++p)
+                for (int q = p; q < c.s; ++q) {
+                    double acc = 0.0;
+                    for (int al = 0; al < c.krows; ++al) acc += nc.b[al * c.s + p] * nc.b[al * c.s + q];
+                    c.reg_mi[k++] = (float)(nc.v * acc);
+                }
+        }
+        const int rf = reg_record_floats(c);
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c.dflag + 4);
+        for (int lay = 0; lay < reg_layouts(c); ++lay) {
+            const long words = reg_bits_words(c, lay);
+            c.nbits[lay] = dalloc<uint2>(words);
+            c.noff[lay] = dalloc<uint32_t>(words);
+            unsigned long long zero = 0, got = 0;
+            HIPCHK(hipMemcpyAsync(cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+            launch_reg_bits(c, lay, cls, c.nbits[lay], c.noff[lay], cnt, st);
+            HIPCHK(hipMemcpyAsync(&got, cnt, sizeof(got), hipMemcpyDeviceToHost, st));
+            std::vector<uint32_t> off(words);
+            HIPCHK(hipMemcpyAsync(off.data(), c.noff[lay], sizeof(uint32_t) * words,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            c.nload[lay] = (long)got;
+            // per-lane counts -> first record of each lane (exclusive prefix sum)
+            uint64_t run = 0;
+            for (long s = 0; s < words; ++s) {
+                const uint32_t n1 = off[s];
+                off[s] = (uint32_t)run;
+                run += n1;
+            }
+            if (run != got || run > 0xffffffffull) fail(FCRKPM_ERR_HIP, "record count mismatch");
+            HIPCHK(hipMemcpyAsync(c.noff[lay], off.data(), sizeof(uint32_t) * words,
+                                  hipMemcpyHostToDevice, st));
+            c.nrec[lay] = dalloc<float>((size_t)std::max<uint64_t>(run, 1) * rf);
+            launch_reg_recs(c, lay, c.nbits[lay], c.noff[lay], c.nrec[lay], st);
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    }
+}
+
 void set_reg_variant(Ctx& c, int v)
 {
     c.reg_layout = v & 1;
@@ -1503,87 +1729,8 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 fail(FCRKPM_ERR_SINGULAR, "moment matrix not positive definite at node " + std::to_string(hflag[1]));
         }
 
-        // node classes (0 outside the domain, 1 interior, 2 other) for the
-        // pointwise stage of the K products: interior nodes share the first
-        // interior node's b^a and V, nodes outside have V = 0
-        if (c.dim * c.s <= kMaxNodeConst) {
-            int big = 0x7fffffff, ref = 0;
-            HIPCHK(hipMemcpyAsync(c.dflag + 3, &big, sizeof(int), hipMemcpyHostToDevice, st));
-            launch_first_interior(c, c.dflag + 3, st);
-            HIPCHK(hipMemcpyAsync(&ref, c.dflag + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            const int nb = c.dim * c.s;
-            NodeConst nc = {};
-            nc.bmax = -1.0;  // no interior node: every domain node is class 2
-            if (ref != 0x7fffffff) {
-                for (int q = 0; q < nb; ++q)
-                    HIPCHK(hipMemcpy(&nc.b[q], c.ba_64 + (size_t)q * nn + ref, sizeof(double),
-                                     hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(&nc.v, c.vol64 + ref, sizeof(double), hipMemcpyDeviceToHost));
-                nc.bmax = 0.0;
-                for (int q = 0; q < nb; ++q) nc.bmax = std::max(nc.bmax, fabs(nc.b[q]));
-            }
-            c.cls = dalloc<uint8_t>(nn);
-            launch_node_class(c, nc, c.cls, st);
-            {
-                std::vector<uint8_t> hc(nn);
-                HIPCHK(hipMemcpyAsync(hc.data(), c.cls, nn, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                c.ncls2 = (long)std::count(hc.begin(), hc.end(), (uint8_t)2);
-            }
-            c.nconst = nc;
-            for (int q = 0; q < nb; ++q) {
-                c.cint64[q] = nc.b[q];
-                c.cint32[q] = (float)nc.b[q];
-            }
-            c.cint64[nb] = nc.v;
-            c.cint32[nb] = (float)nc.v;
-        }
-        // node classes of the register-resident K passes: interior nodes share
-        // one M = V B^T B (a kernel argument), nodes outside the domain give
-        // zero, and every other element gets its own record, packed lane by lane
-        if (reg_path_ok(c) && c.cls) {
-            const uint8_t* cls = c.cls;
-            const NodeConst& nc = c.nconst;
-            if (nc.bmax >= 0.0 && c.degree == 1) {
-                int k = 0;
-                for (int p = 0; p < c.s; ++p)
-                    for (int q = p; q < c.s; ++q) {
-                        double acc = 0.0;
-                        for (int al = 0; al < c.dim; ++al) acc += nc.b[al * c.s + p] * nc.b[al * c.s + q];
-                        c.reg_mi[k++] = (float)(nc.v * acc);
-                    }
-            }
-            const int rf = reg_record_floats(c);
-            unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c.dflag + 4);
-            for (int lay = 0; lay < reg_layouts(c); ++lay) {
-                const long words = reg_bits_words(c, lay);
-                c.nbits[lay] = dalloc<uint2>(words);
-                c.noff[lay] = dalloc<uint32_t>(words);
-                unsigned long long zero = 0, got = 0;
-                HIPCHK(hipMemcpyAsync(cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
-                launch_reg_bits(c, lay, cls, c.nbits[lay], c.noff[lay], cnt, st);
-                HIPCHK(hipMemcpyAsync(&got, cnt, sizeof(got), hipMemcpyDeviceToHost, st));
-                std::vector<uint32_t> off(words);
-                HIPCHK(hipMemcpyAsync(off.data(), c.noff[lay], sizeof(uint32_t) * words,
-                                      hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                c.nload[lay] = (long)got;
-                // per-lane counts -> first record of each lane (exclusive prefix sum)
-                uint64_t run = 0;
-                for (long s = 0; s < words; ++s) {
-                    const uint32_t n1 = off[s];
-                    off[s] = (uint32_t)run;
-                    run += n1;
-                }
-                if (run != got || run > 0xffffffffull) fail(FCRKPM_ERR_HIP, "record count mismatch");
-                HIPCHK(hipMemcpyAsync(c.noff[lay], off.data(), sizeof(uint32_t) * words,
-                                      hipMemcpyHostToDevice, st));
-                c.nrec[lay] = dalloc<float>((size_t)std::max<uint64_t>(run, 1) * rf);
-                launch_reg_recs(c, lay, c.nbits[lay], c.noff[lay], c.nrec[lay], st);
-                HIPCHK(hipStreamSynchronize(st));
-            }
-        }
+        c.krows = c.dim;
+        build_pointwise(c, st);
 
         // workspace and solver buffers for one right-hand side; both grow on demand
         HIPCHK(hipStreamSynchronize(st));
@@ -1665,7 +1812,7 @@ extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (op < FCRKPM_OP_K || op > FCRKPM_OP_VN) fail(FCRKPM_ERR_ARG, "unknown operator");
+        if (op < FCRKPM_OP_K || op > FCRKPM_OP_M) fail(FCRKPM_ERR_ARG, "unknown operator");
         if (dtype != FCRKPM_F64 && dtype != FCRKPM_F32) fail(FCRKPM_ERR_ARG, "unknown dtype");
         if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
         if (!in || !out) fail(FCRKPM_ERR_ARG, "NULL array");
@@ -1790,6 +1937,127 @@ extern "C" fcrkpm_status fcrkpm_adjoint(fcrkpm_ctx* ctx, int32_t mode, int32_t n
     });
 }
 
+// Time stepping of the diffusion problem M d' + nu K d = f^r (App. C, Eq C.1-
+// C.4) with d = g held on the Dirichlet nodes and r constant in time.  On the
+// free rows, with x the free part of d and c0 = dt (f^r - nu K d_Gamma):
+//   implicit (Alg C.4): (M + theta dt nu K) x1 = (M - (1-theta) dt nu K) x0 + c0,
+//     one CG solve per step (the solver of fcrkpm_solve on the shifted
+//     operator, warm-started from x0);
+//   explicit (Alg C.3): x1 = x0 + (c0 - dt nu K x0) / M^l.
+extern "C" fcrkpm_status fcrkpm_transient(fcrkpm_ctx* ctx, const fcrkpm_time* tp, int32_t mode,
+                                          int32_t nrhs, const double* r, const double* g,
+                                          double* d_inout, double* uh_out, double tol,
+                                          int32_t maxit, fcrkpm_info* info, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (!tp || !d_inout) fail(FCRKPM_ERR_ARG, "NULL argument");
+        const fcrkpm_time T = *tp;
+        const bool implicit = T.scheme == FCRKPM_TIME_IMPLICIT;
+        if (!implicit && T.scheme != FCRKPM_TIME_EXPLICIT_LUMPED) fail(FCRKPM_ERR_ARG, "unknown time scheme");
+        if (T.nsteps < 0) fail(FCRKPM_ERR_ARG, "nsteps must be >= 0");
+        if (!(T.dt > 0.0) || !std::isfinite(T.dt) || !(T.nu > 0.0) || !std::isfinite(T.nu))
+            fail(FCRKPM_ERR_ARG, "dt and nu must be finite and > 0");
+        if (implicit && !(T.theta > 0.0 && T.theta <= 1.0)) fail(FCRKPM_ERR_ARG, "theta must be in (0, 1]");
+        check_solve_args(mode, nrhs, tol, maxit);
+        if (!implicit && mode != FCRKPM_MODE_F64)
+            fail(FCRKPM_ERR_UNSUPPORTED, "the explicit scheme runs FP64 products only");
+        hipStream_t st = (hipStream_t)stream;
+        const long nn = c.nn;
+        ensure_rhs(c, nrhs);
+        ensure_work(c, nrhs);
+        HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+        if (r) launch_check_finite(r, nn * nrhs, c.dflag + 2, st);
+        if (g) launch_check_finite(g, nn * nrhs, c.dflag + 2, st);
+        launch_check_finite(d_inout, nn * nrhs, c.dflag + 2, st);
+        int hf = 0;
+        HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, g or d");
+
+        struct Buf {
+            double* p = nullptr;
+            ~Buf() { dfree(p); }
+        } c0b;
+        c0b.p = dalloc<double>((size_t)nn * nrhs);
+        double* c0 = c0b.p;
+        double* x = vec64(c, V_X);
+        double* t = vec64(c, V_T);
+        double* q = vec64(c, V_Q);
+        double* pv = vec64(c, V_P);
+        if (r) apply_one<double>(c, FCRKPM_OP_FR, r, t, nrhs, st);  // f^r (Alg 4)
+        else HIPCHK(hipMemsetAsync(t, 0, sizeof(double) * nn * nrhs, st));
+        if (g) {
+            launch_masked_copy<double>(g, c.dirm, pv, nn, nrhs, st);  // d_Gamma
+            apply_one<double>(c, FCRKPM_OP_K_FULL, pv, q, nrhs, st);
+            launch_lincomb_masked(t, T.dt, q, -T.dt * T.nu, nullptr, c.freem, c0, nn, nrhs, st);
+        } else {
+            launch_lincomb_masked(t, T.dt, nullptr, 0.0, nullptr, c.freem, c0, nn, nrhs, st);
+        }
+        launch_masked_copy<double>(d_inout, c.freem, x, nn, nrhs, st);
+
+        std::vector<fcrkpm_info> acc(nrhs);
+        memset(acc.data(), 0, sizeof(fcrkpm_info) * nrhs);
+        fcrkpm_status worst = FCRKPM_OK;
+        if (implicit) {
+            OpSet* ms = mass_set(c, st);
+            OpSet* as = shift_set(c, 1.0, T.theta * T.dt * T.nu, st);
+            std::vector<fcrkpm_info> inf(nrhs);
+            for (int step = 0; step < T.nsteps && worst == FCRKPM_OK; ++step) {
+                double* b = vec64(c, V_B);
+                {
+                    SetScope use(c, ms);
+                    apply_one<double>(c, FCRKPM_OP_K, x, t, nrhs, st);  // M x0 (Alg C.1)
+                }
+                if (T.theta < 1.0) {
+                    apply_one<double>(c, FCRKPM_OP_K, x, q, nrhs, st);
+                    launch_lincomb_masked(t, 1.0, q, -(1.0 - T.theta) * T.dt * T.nu, c0, c.freem, b,
+                                          nn, nrhs, st);
+                } else {
+                    launch_lincomb_masked(t, 1.0, nullptr, 0.0, c0, c.freem, b, nn, nrhs, st);
+                }
+                SetScope use(c, as);
+                Solver S(c, nrhs, mode, tol, maxit);
+                run_solvers({&S}, graphs_enabled(c), st);
+                worst = S.finish(inf.data(), st);
+                for (int j = 0; j < nrhs; ++j) {
+                    fcrkpm_info& a = acc[j];
+                    const fcrkpm_info& f = inf[j];
+                    a.iters += f.iters;
+                    a.outer_iters += f.outer_iters;
+                    a.rel_res = std::max(a.rel_res, f.rel_res);
+                    a.true_rel_res = std::max(a.true_rel_res, f.true_rel_res);
+                    a.fallback_used |= f.fallback_used;
+                    a.matvecs_f64 += f.matvecs_f64 + (T.theta < 1.0 ? 2 : 1);
+                    a.matvecs_f32 += f.matvecs_f32;
+                }
+            }
+        } else {
+            // M^l (Eq C.13, Alg C.2) in the first field of V_R
+            double* ml = vec64(c, V_R);
+            launch_mask_to_double(c.chi, q, nn, st);
+            apply_one<double>(c, FCRKPM_OP_FR, q, ml, 1, st);
+            HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+            launch_check_positive(ml, c.freem, nn, c.dflag + 2, st);
+            HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (hf) fail(FCRKPM_ERR_SINGULAR, "lumped mass not positive on a free node");
+            for (int step = 0; step < T.nsteps; ++step) {
+                apply_one<double>(c, FCRKPM_OP_K, x, t, nrhs, st);
+                launch_explicit_update(x, t, c0, ml, T.dt * T.nu, c.freem, nn, nrhs, st);
+            }
+            for (auto& a : acc) a.matvecs_f64 = T.nsteps;
+        }
+        finish_solve(c, nrhs, g, d_inout, uh_out, st);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        if (info) memcpy(info, acc.data(), sizeof(fcrkpm_info) * nrhs);
+        if (worst != FCRKPM_OK) c.err = "a time step's solve did not reach the tolerance";
+        return worst;
+    });
+}
+
 extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int64_t* value)
 {
     if (!ctx) return FCRKPM_ERR_ARG;
@@ -1853,6 +2121,16 @@ extern "C" fcrkpm_status fcrkpm_get_coeffs(fcrkpm_ctx* ctx, int32_t which, doubl
             case FCRKPM_COEF_FREE:
                 launch_mask_to_double(c.freem, out, c.nn, st);
                 break;
+            case FCRKPM_COEF_LUMPED_MASS: {
+                // M^l = chi o F^-1[sum_p F(chi o V o b^0_p) o F(conj H_p)] (Eq C.13,
+                // Alg C.2): the load vector of r = 1
+                ensure_rhs(c, 1);
+                ensure_work(c, 1);
+                double* one = vec64(c, V_T);
+                launch_mask_to_double(c.chi, one, c.nn, st);
+                apply_one<double>(c, FCRKPM_OP_FR, one, out, 1, st);
+                break;
+            }
             default:
                 fail(FCRKPM_ERR_ARG, "unknown coefficient field");
         }

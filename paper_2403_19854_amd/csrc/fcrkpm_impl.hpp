@@ -58,9 +58,30 @@ struct SepPlan {
 // and V agree with those of the first such node (checked to 1e-12 of max |b|).
 constexpr int kMaxNodeConst = 30;  // dim * s up to the quadratic basis in 3D
 struct NodeConst {
-    double b[kMaxNodeConst];       // b^a_q, a-major
+    double b[kMaxNodeConst];       // coefficient rows of the product, row-major (b^a_q for K)
     double v;                      // V
     double bmax;                   // max |b|; negative: no interior node
+};
+
+// Pointwise data of one K-type product, E_p = V sum_rows c_p (c . D): the
+// stiffness K takes the rows b^a (Eq 90-91), the consistent mass the single
+// row b^0 (Eq C.8, C.11) and c_m M + c_k K the rows sqrt(c_k) b^a followed by
+// sqrt(c_m) b^0.  The context holds the set in use; the others wait here and
+// are swapped in for the products they serve.
+struct OpSet {
+    int krows = 0;
+    double* ba_64 = nullptr;            // [krows][s][nn]
+    float* ba_32 = nullptr;
+    uint8_t* cls = nullptr;
+    long ncls2 = 0;
+    double cint64[kMaxNodeConst + 1] = {};
+    float cint32[kMaxNodeConst + 1] = {};
+    uint2* nbits[2] = {};
+    float reg_mi[10] = {};
+    uint32_t* noff[2] = {};
+    float* nrec[2] = {};
+    long nload[2] = {-1, -1};
+    NodeConst nconst = {};
 };
 
 struct Ctx {
@@ -87,7 +108,7 @@ struct Ctx {
     double* vol64 = nullptr;
     float* vol32 = nullptr;
     double* b0_64 = nullptr;            // [s][nn]
-    double* ba_64 = nullptr;            // [dim][s][nn]
+    double* ba_64 = nullptr;            // [krows][s][nn]: rows of the K-type product in use
     float* b0_32 = nullptr;
     float* ba_32 = nullptr;
     cplx<double>* tw64[3] = {};         // twiddles per axis
@@ -95,6 +116,10 @@ struct Ctx {
     cplx<double>* spec64[3] = {};       // kernel spectra per axis, exponents 0..2n
     cplx<float>* spec32[3] = {};
     float* rtab32[3] = {};              // per axis [2][n]: Re T_0 / n, Im T_1 / n (register passes)
+    int krows = 0;                      // coefficient rows of the K-type product in use (dim for K)
+    OpSet* mass_set = nullptr;          // consistent mass (built on first use)
+    OpSet* shift_set = nullptr;         // c_m M + c_k K of the last implicit time step
+    double shift_w[2] = {0.0, 0.0};     // its (c_m, c_k)
     bool use_regpath = true;            // register-resident passes where they apply
     uint8_t* cls = nullptr;             // node class: 0 outside the domain, 1 interior, 2 other
     long ncls2 = 0;                     // class-2 nodes
@@ -210,6 +235,9 @@ void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
                   const RegPupd* pu = nullptr);
 
+// throws the library's FCRKPM_ERR_UNSUPPORTED status with this message
+[[noreturn]] void raise_unsupported(const char* msg);
+
 // LDS bytes the passes of a plan need at the tile widths they will use
 size_t sep_lds_need(const Ctx& c, const SepPlan& sp, int elem_bytes);
 
@@ -224,6 +252,16 @@ void launch_vol(const uint8_t* chi, const double* vol_in, double hv, double* vol
                 long nn, hipStream_t st);
 void launch_mask_to_double(const uint8_t* m, double* out, long nn, hipStream_t st);
 void launch_check_finite(const double* x, long nn, int* flag, hipStream_t st);
+// rows of another K-type product: sqrt(ck) b^a (when ck > 0), then sqrt(cm) b^0 (when cm > 0)
+void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st);
+// out = mask ? wa a + wb b + c : 0 (b and c may be NULL) over nrhs fields
+void launch_lincomb_masked(const double* a, double wa, const double* b, double wb, const double* cc,
+                           const uint8_t* mask, double* out, long nn, int nrhs, hipStream_t st);
+// forward Euler with the lumped mass: x = mask ? x + (c0 - w kx) / ml : 0
+void launch_explicit_update(double* x, const double* kx, const double* c0, const double* ml,
+                            double w, const uint8_t* mask, long nn, int nrhs, hipStream_t st);
+// flag |= 1 where mask and !(v > 0)
+void launch_check_positive(const double* v, const uint8_t* mask, long nn, int* flag, hipStream_t st);
 
 // CG / vector kernels (deterministic two-stage reductions), batched over
 // nrhs right-hand sides: vectors of rhs j start at j*n, its scalars at

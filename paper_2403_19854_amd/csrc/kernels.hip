@@ -126,7 +126,7 @@ __global__ void k_node_class(const uint8_t* __restrict__ chi, const double* __re
 void launch_node_class(const Ctx& c, const NodeConst& ref, uint8_t* cls, hipStream_t st)
 {
     hipLaunchKernelGGL(k_node_class, dim3(ew_blocks(c.nn)), dim3(256), 0, st, c.chi, c.ba_64,
-                       c.vol64, c.dim * c.s, ref, c.n[0], c.n[1], c.n[2], c.m[0], c.m[1], c.m[2],
+                       c.vol64, c.krows * c.s, ref, c.n[0], c.n[1], c.n[2], c.m[0], c.m[1], c.m[2],
                        c.nn, cls);
 }
 
@@ -674,6 +674,82 @@ void launch_select(const uint8_t* mask, const double* a, const double* b, double
                    int nrhs, hipStream_t st)
 {
     hipLaunchKernelGGL(k_select, dim3(ew_blocks(n), nrhs), dim3(256), 0, st, mask, a, b, out, n);
+}
+
+// Coefficient rows of another K-type product (App. C): rows [0, nba) are
+// sqrt(ck) b^a, the row after them sqrt(cm) b^0, in the [row][s][nn] layout
+// of b^a.
+__global__ void k_op_rows(const double* __restrict__ ba, const double* __restrict__ b0, long nba,
+                          long total, double wk, double wm, double* __restrict__ o64,
+                          float* __restrict__ o32)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+         i += (long)gridDim.x * blockDim.x) {
+        const double v = i < nba ? wk * ba[i] : wm * b0[i - nba];
+        o64[i] = v;
+        o32[i] = (float)v;
+    }
+}
+
+void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st)
+{
+    const long per = (long)c.s * c.nn;
+    const long nba = ck > 0.0 ? (long)c.dim * per : 0;
+    const long total = nba + (cm > 0.0 ? per : 0);
+    hipLaunchKernelGGL(k_op_rows, dim3(ew_blocks(total)), dim3(256), 0, st, c.ba_64, c.b0_64, nba,
+                       total, sqrt(ck), sqrt(cm), o64, o32);
+}
+
+__global__ void k_lincomb_masked(const double* __restrict__ a, double wa,
+                                 const double* __restrict__ b, double wb,
+                                 const double* __restrict__ cc, const uint8_t* __restrict__ mask,
+                                 double* __restrict__ out, long n)
+{
+    const long off = blockIdx.y * n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        double v = wa * a[off + i];
+        if (b) v += wb * b[off + i];
+        if (cc) v += cc[off + i];
+        out[off + i] = mask[i] ? v : 0.0;
+    }
+}
+
+void launch_lincomb_masked(const double* a, double wa, const double* b, double wb, const double* cc,
+                           const uint8_t* mask, double* out, long nn, int nrhs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lincomb_masked, dim3(ew_blocks(nn), nrhs), dim3(256), 0, st, a, wa, b, wb,
+                       cc, mask, out, nn);
+}
+
+__global__ void k_explicit_update(double* __restrict__ x, const double* __restrict__ kx,
+                                  const double* __restrict__ c0, const double* __restrict__ ml,
+                                  double w, const uint8_t* __restrict__ mask, long n)
+{
+    const long off = blockIdx.y * n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        x[off + i] = mask[i] ? x[off + i] + (c0[off + i] - w * kx[off + i]) / ml[i] : 0.0;
+}
+
+void launch_explicit_update(double* x, const double* kx, const double* c0, const double* ml,
+                            double w, const uint8_t* mask, long nn, int nrhs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_explicit_update, dim3(ew_blocks(nn), nrhs), dim3(256), 0, st, x, kx, c0,
+                       ml, w, mask, nn);
+}
+
+__global__ void k_check_positive(const double* __restrict__ v, const uint8_t* __restrict__ mask,
+                                 long n, int* flag)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        if (mask[i] && !(v[i] > 0.0)) atomicOr(flag, 1);
+}
+
+void launch_check_positive(const double* v, const uint8_t* mask, long nn, int* flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_positive, dim3(ew_blocks(nn)), dim3(256), 0, st, v, mask, nn, flag);
 }
 
 __global__ void k_to32(const double* __restrict__ a, float* __restrict__ out, long n)

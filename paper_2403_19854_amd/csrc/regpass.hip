@@ -1257,11 +1257,12 @@ __global__ void k_rmid_bits(const uint8_t* __restrict__ cls, long st, long nblk,
 }
 
 // The records of every lane's record elements, in lane order, with M formed
-// in FP64 from b^a (a-major, [3][4][nn]) and V and rounded once.
+// in FP64 from the coefficient rows (row-major, [rows][4][nn]: b^a for K) and
+// V and rounded once.
 template <class Lay>
 __global__ void k_rmid_recs(const uint2* __restrict__ bits, const uint32_t* __restrict__ off,
                             const double* __restrict__ ba, const double* __restrict__ vol, long st,
-                            long nblk, long nn, float* __restrict__ rec)
+                            long nblk, long nn, int rows, float* __restrict__ rec)
 {
     constexpr int S = 4;
     const long n = nblk * kRT;
@@ -1282,7 +1283,7 @@ __global__ void k_rmid_recs(const uint2* __restrict__ bits, const uint32_t* __re
                 for (int p = 0; p < S; ++p)
                     for (int q = p; q < S; ++q) {
                         double acc = 0.0;
-                        for (int al = 0; al < 3; ++al)
+                        for (int al = 0; al < rows; ++al)
                             acc += ba[(long)(al * S + p) * nn + node] * ba[(long)(al * S + q) * nn + node];
                         o[2 * sym_index(p, q) + c] = (float)(v * acc);
                     }
@@ -1343,7 +1344,7 @@ void build_recs(const Ctx& c, const uint2* bits, const uint32_t* off, float* rec
                            c.vol64, str, blocks_of<Lay>(c), c.nn, rec);
     else
         hipLaunchKernelGGL((k_rmid_recs<Lay>), dim3(256), dim3(256), 0, st, bits, off, c.ba_64,
-                           c.vol64, str, blocks_of<Lay>(c), c.nn, rec);
+                           c.vol64, str, blocks_of<Lay>(c), c.nn, c.krows, rec);
 }
 
 // the pass programs of the basis are exactly the table's terms (in order)

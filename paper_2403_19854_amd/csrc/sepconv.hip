@@ -577,11 +577,21 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
                 long gi;
                 tl.at(e, w, i, gi, oo[kk]);
                 const uint8_t k = m.cls ? m.cls[gi] : uint8_t(2);
+                // row sets wider than the interior constants have no classes
+                // (cls NULL): every node reads the arrays
+                if constexpr (DIM * S <= kMaxNodeConst) {
 #pragma unroll
-                for (int al = 0; al < DIM; ++al)
+                    for (int al = 0; al < DIM; ++al)
 #pragma unroll
-                    for (int q = 0; q < S; ++q) bb[kk][al][q] = m.cint[al * S + q];
-                vv[kk] = k == 1 ? m.cint[DIM * S] : T(0);
+                        for (int q = 0; q < S; ++q) bb[kk][al][q] = m.cint[al * S + q];
+                    vv[kk] = k == 1 ? m.cint[DIM * S] : T(0);
+                } else {
+#pragma unroll
+                    for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                        for (int q = 0; q < S; ++q) bb[kk][al][q] = T(0);
+                    vv[kk] = T(0);
+                }
                 if (k == 2) {
 #pragma unroll
                     for (int al = 0; al < DIM; ++al)
@@ -806,8 +816,9 @@ template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DI
 static void go_mid(const MidArgs<T>& m, size_t sh, int nrhs, hipStream_t st)
 {
     const dim3 grid((unsigned)(m.s.g.nlines / m.s.g.W), (unsigned)nrhs);
-    // the 128-point lines of the 3D workloads get the compile-time plan
-    if constexpr (DIM == 3 && !CONTIG) {
+    // the 128-point lines of the 3D workloads (bases of 4 and 10 monomials)
+    // get the compile-time plan
+    if constexpr ((S == 4 || S == 10) && !CONTIG) {
         if (m.s.g.L == 128) {
             hipLaunchKernelGGL((k_sep_mid<T, Tio, CONTIG, LDM, STM, S, DIM, PW, 128>), grid,
                                dim3(kThreads), sh, st, m);
@@ -824,13 +835,20 @@ static void go_mid(const MidArgs<T>& m, size_t sh, int nrhs, hipStream_t st)
     }
 }
 
-template <typename T, typename Tio, int S, int DIM>
+// DIM is the number of coefficient rows of the K-type pointwise stage; KONLY
+// instantiates that stage alone (row counts other than the dimension: the
+// mass and shifted products of time-dependent problems)
+template <typename T, typename Tio, int S, int DIM, bool KONLY = false>
 static void mid_dispatch(const MidArgs<T>& m, int ldm, int stm, int pw, size_t sh, int nrhs,
                          hipStream_t st)
 {
     const bool ct = m.s.g.contig;
 #define FC_MID(CT, LD, STO, P) go_mid<T, Tio, CT, LD, STO, S, DIM, P>(m, sh, nrhs, st)
-    if (pw == PW_K) {
+    if constexpr (KONLY) {
+        if (pw != PW_K) raise_unsupported("internal: pointwise mode without its instantiation");
+        if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
+        else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
+    } else if (pw == PW_K) {
         if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
         else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
     } else if (pw == PW_UH) {
@@ -881,12 +899,29 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.src = src;
     m.nn = c.nn;
     const size_t sh = (size_t)(m.s.ne + 1) * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
-    if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, rb.n, st);
-    else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, rb.n, st);
-    else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, rb.n, st);
-    else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, rb.n, st);
-    else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, rb.n, st);
-    else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, rb.n, st);
+    const int rows = (pw == PW_K) ? c.krows : c.dim;
+    if (rows == c.dim) {
+        if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 3 && c.dim == 2) mid_dispatch<T, Tio, 3, 2>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, rb.n, st);
+        else raise_unsupported("basis size and dimension without a middle pass");
+        return;
+    }
+    // the consistent mass (one row) and c_m M + c_k K (dim + 1 rows)
+    if (c.s == 2 && rows == 2) mid_dispatch<T, Tio, 2, 2, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 3 && rows == 1) mid_dispatch<T, Tio, 3, 1, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 3 && rows == 2) mid_dispatch<T, Tio, 3, 2, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 3 && rows == 3) mid_dispatch<T, Tio, 3, 3, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 6 && rows == 1) mid_dispatch<T, Tio, 6, 1, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 6 && rows == 3) mid_dispatch<T, Tio, 6, 3, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 4 && rows == 1) mid_dispatch<T, Tio, 4, 1, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 4 && rows == 4) mid_dispatch<T, Tio, 4, 4, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 10 && rows == 1) mid_dispatch<T, Tio, 10, 1, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 10 && rows == 4) mid_dispatch<T, Tio, 10, 4, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else raise_unsupported("coefficient rows without a middle pass");
 }
 
 template void launch_sep_pass<double, double>(const Ctx&, int, const SepProg&, const SepProg*, int, const void*,

@@ -21,13 +21,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfcrkpm.so")
 
 OK, ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = range(7)
-OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN = range(6)
+OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN, OP_M = range(7)
 F64, F32 = 0, 1
 MODE_F64, MODE_F32_REFINED, MODE_F32_PRODUCTS = 0, 1, 2
-COEF_B0, COEF_BALPHA, COEF_FREE = 0, 1, 2
+COEF_B0, COEF_BALPHA, COEF_FREE, COEF_LUMPED_MASS = 0, 1, 2, 3
+TIME_IMPLICIT, TIME_EXPLICIT_LUMPED = 0, 1
 KERNEL_CUBIC_BSPLINE = 0
 
-_OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN}
+_OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN,
+        "M": OP_M}
 _MODES = {"f64": MODE_F64, "f32_refined": MODE_F32_REFINED, "f32_products": MODE_F32_PRODUCTS}
 
 EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
@@ -35,7 +37,7 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_last_error", "fcrkpm_status_str", "fcrkpm_version",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
-           "fcrkpm_get_option")
+           "fcrkpm_get_option", "fcrkpm_transient")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -48,6 +50,11 @@ OPT_TUNE_NS3 = 7
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
                 ("dirichlet", C.c_void_p), ("vol", C.c_void_p), ("flags", C.c_int32)]
+
+
+class Time(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("nsteps", C.c_int32), ("dt", C.c_double),
+                ("nu", C.c_double), ("theta", C.c_double)]
 
 
 class Info(C.Structure):
@@ -106,6 +113,9 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(Info), V]
     lib.fcrkpm_get_coeffs.restype = C.c_int
     lib.fcrkpm_get_coeffs.argtypes = [V, C.c_int32, V, V]
+    lib.fcrkpm_transient.restype = C.c_int
+    lib.fcrkpm_transient.argtypes = [V, C.POINTER(Time), C.c_int32, C.c_int32, V, V, V, V,
+                                     C.c_double, C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_basis_size.restype = C.c_int32
     lib.fcrkpm_basis_size.argtypes = [V]
     lib.fcrkpm_destroy.restype = None
@@ -216,7 +226,7 @@ class Problem:
 
     # ------------------------------------------------------------------ ops
     def apply(self, op, x, out=None, stream=None):
-        """Apply operator op ('K', 'K_FULL', 'FR', 'UH', 'NT', 'VN') to x.
+        """Apply operator op ('K', 'K_FULL', 'FR', 'UH', 'NT', 'VN', 'M') to x.
 
         x: float64 or float32 tensor of shape [..., nz, ny, nx]; leading
         dimensions are independent fields.  The precision of x selects the
@@ -267,6 +277,31 @@ class Problem:
                                                   _stream_ptr(stream)))
         return g, _infos_dict(infos, OK)
 
+    def transient(self, d0, nu, dt, nsteps, r=None, g=None, scheme="implicit", theta=1.0,
+                  mode="f64", tol=1e-12, maxit=20000, want_uh=False, stream=None,
+                  raise_on_noconv=True):
+        """Time stepping of M d' + nu K d = f^r from d0 (leading dimensions of
+        d0 are independent fields); scheme 'implicit' (theta method) or
+        'explicit' (forward Euler, lumped mass).  Returns (d, u^h or None,
+        info dict)."""
+        d = _dev(d0, torch.float64, self.device).clone()
+        nrhs = d.numel() // self.nn
+        if nrhs < 1 or nrhs * self.nn != d.numel():
+            raise ValueError("d0 does not hold whole fields")
+        r = None if r is None else _dev(r, torch.float64, self.device).expand_as(d).contiguous()
+        g = None if g is None else _dev(g, torch.float64, self.device).expand_as(d).contiguous()
+        uh = torch.empty_like(d) if want_uh else None
+        tp = Time(TIME_IMPLICIT if scheme == "implicit" else
+                  TIME_EXPLICIT_LUMPED if scheme == "explicit" else -1,
+                  int(nsteps), float(dt), float(nu), float(theta))
+        infos = (Info * nrhs)()
+        st = load_library().fcrkpm_transient(self._h, C.byref(tp), _MODES[mode], nrhs, _ptr(r),
+                                             _ptr(g), _ptr(d), _ptr(uh), float(tol), int(maxit),
+                                             infos, _stream_ptr(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            self._check(st)
+        return d, uh, _infos_dict(infos, st)
+
     def set_regpath(self, on: bool):
         """Use the register-resident FP32 K passes where they apply (default)."""
         self._check(load_library().fcrkpm_set_option(self._h, OPT_REGPATH, 1 if on else 0))
@@ -284,10 +319,12 @@ class Problem:
         self._check(load_library().fcrkpm_set_option(self._h, OPT_GRAPHS, 1 if on else 0))
 
     def coeffs(self, which="b0"):
-        """Copy of b^0 [s, *shape], b^alpha [dim, s, *shape] or chi_Omega [*shape]."""
-        code = {"b0": COEF_B0, "balpha": COEF_BALPHA, "free": COEF_FREE}[which]
+        """Copy of b^0 [s, *shape], b^alpha [dim, s, *shape], chi_Omega [*shape]
+        or the lumped mass M^l [*shape] ('lumped')."""
+        code = {"b0": COEF_B0, "balpha": COEF_BALPHA, "free": COEF_FREE,
+                "lumped": COEF_LUMPED_MASS}[which]
         shape = {"b0": (self.s,) + self.shape, "balpha": (self.dim, self.s) + self.shape,
-                 "free": self.shape}[which]
+                 "free": self.shape, "lumped": self.shape}[which]
         out = torch.empty(shape, dtype=torch.float64, device=self.device)
         self._check(load_library().fcrkpm_get_coeffs(self._h, code, _ptr(out), _stream_ptr()))
         return out
