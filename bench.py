@@ -193,6 +193,7 @@ def main():
         out["apply_loop"] = apply_loop(wl, chi, dirm, vol, dev)
         if a.workload == "c5":
             out["adjoint"] = adjoint_time(a, wl, chi, dirm, vol, r, dev)
+            out["transient"] = transient_time(a, wl, chi, dirm, vol, r, dev)
 
     if not a.no_cpu_baseline:
         import oracle
@@ -269,9 +270,51 @@ def adjoint_time(a, wl, chi, dirm, vol, r, dev):
             "grad_norm": float(torch.linalg.vector_norm(g).item())}
 
 
-def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5):
-    """Standalone K products: median over `reps` single launches (HIP events on
-    the launch stream) after `warm` warm-ups, FP32 and FP64."""
+def transient_time(a, wl, chi, dirm, vol, r, dev, steps=2, explicit_steps=50):
+    """Time-dependent diffusion on the same grid (App. C), source r, nu = 1,
+    from d = 0: `steps` backward-Euler steps with dt = 4 h^2 (one solve with
+    M + dt K each; refined FP32 and FP64, both to the bench tolerance), then
+    `explicit_steps` forward-Euler steps with the lumped mass and dt = 0.02 h^2,
+    and standalone mass products."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    h2 = min(wl.h) ** 2
+    d0 = torch.zeros(wl.shape, dtype=torch.float64, device=dev)
+    res = {"nu": 1.0, "implicit": {"theta": 1.0, "dt": 4.0 * h2, "steps": steps, "tol": a.tol}}
+    ds = {}
+    pb.transient(d0, 1.0, 4.0 * h2, 0, r=r, tol=a.tol)  # zero steps: builds the rows of M and M + dt K
+    for mode in ("f32_refined", "f64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, info = pb.transient(d0, 1.0, 4.0 * h2, steps, r=r, mode=mode, tol=a.tol, maxit=a.maxit)
+        torch.cuda.synchronize()
+        res["implicit"][mode + "_ms"] = 1e3 * (time.perf_counter() - t0)
+        res["implicit"][mode + "_iters"] = info["iters"]
+        ds[mode] = d.cpu().numpy()
+    m = wl.free > 0
+    res["implicit"]["speedup"] = res["implicit"]["f64_ms"] / res["implicit"]["f32_refined_ms"]
+    res["implicit"]["d_rel_l2_refined_vs_f64"] = float(
+        np.linalg.norm((ds["f32_refined"] - ds["f64"])[m]) / np.linalg.norm(ds["f64"][m]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.transient(d0, 1.0, 0.02 * h2, explicit_steps, r=r, scheme="explicit", mode="f64")
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    res["explicit"] = {"dt": 0.02 * h2, "steps": explicit_steps, "ms": 1e3 * te,
+                       "steps_per_s": explicit_steps / te}
+    pb.close()
+    res["mass_products"] = apply_loop(wl, chi, dirm, vol, dev, op="M")
+    return res
+
+
+def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5, op="K"):
+    """Standalone products of operator `op` (K, or M for the consistent mass):
+    median over `reps` single launches (HIP events on the launch stream) after
+    `warm` warm-ups, FP32 and FP64."""
     import numpy as np
     import torch
 
@@ -285,13 +328,13 @@ def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5):
     for name, xt in (("f32", x.float()), ("f64", x)):
         y = torch.empty_like(xt)
         for _ in range(warm):
-            pb.apply("K", xt, out=y, stream=st)
+            pb.apply(op, xt, out=y, stream=st)
         ts = []
         for _ in range(reps):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(st)
-            pb.apply("K", xt, out=y, stream=st)
+            pb.apply(op, xt, out=y, stream=st)
             e1.record(st)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
