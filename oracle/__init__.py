@@ -7,9 +7,10 @@ wrap-around.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package; the product
 library never does, and this package never imports the product library.
 
-The time-dependent part (App. C: consistent and lumped mass, implicit and
-explicit time stepping of the diffusion equation) is plain numpy on top of the
-same neighbour-loop operators.
+The boundary flux load (App. A) and the time-dependent part (App. C:
+consistent and lumped mass, implicit and explicit time stepping of the
+diffusion equation) are plain numpy on top of the same neighbour-loop
+operators.
 
 Every function works on numpy FP64 arrays in C order ``[nz][ny][nx]``
 (x fastest), 0/1 masks as uint8.
@@ -225,6 +226,26 @@ class Oracle:
         it = _load().orc_adjoint(self._h, free, _f64(dl_du).reshape(-1), g,
                                  z.ctypes.data_as(C.c_void_p), tol, maxit, C.byref(rel))
         return g.reshape(self.shape), z.reshape(self.shape), it
+
+    # --- boundary flux (App. A) ---------------------------------------------
+    def apply_fq(self, q, area):
+        """Boundary load f^q_I = sum_S A_S q_S Psi_I(x_S) over the domain nodes
+        (Eq 28 with direct nodal quadrature on the boundary, Eq A.2-A.3):
+        N^T (A o q)."""
+        return self.apply_nt(_f64(area).reshape(self.shape) * _f64(q).reshape(self.shape))
+
+    def solve_flux(self, free, dirichlet, r, q, area, g=None, tol=1e-12, maxit=100000):
+        """Static solve with a flux q on the boundary nodes of area A (Eq 8-9,
+        28-29): K_ff x = chi_Omega (f^r + f^q - K d_G), d = x + d_G.  Returns
+        (d, iterations, relative residual)."""
+        f = np.asarray(free).reshape(self.shape).astype(bool)
+        dG = np.zeros(self.shape)
+        if g is not None:
+            dG = np.where(np.asarray(dirichlet).reshape(self.shape).astype(bool),
+                          _f64(g).reshape(self.shape), 0.0)
+        rhs = np.where(f, self.apply_fr(r) + self.apply_fq(q, area) - self.apply_k(dG), 0.0)
+        x, it, rel = self.cg(f.astype(np.uint8), rhs, tol=tol, maxit=maxit)
+        return np.where(f, x, 0.0) + dG, it, rel
 
     # --- time-dependent problems (App. C) -----------------------------------
     def apply_m(self, d):

@@ -43,6 +43,8 @@ class Problem:
     u_exact: Optional[np.ndarray] = None
     g: Optional[np.ndarray] = None     # Dirichlet values (None = homogeneous)
     meta: dict = field(default_factory=dict)
+    area: Optional[np.ndarray] = None  # boundary areas A of the flux nodes (Gamma_q)
+    q: Optional[np.ndarray] = None     # flux grad u . n on the flux nodes
 
     @property
     def shape(self):
@@ -148,6 +150,37 @@ def cube(dim: int, n_box: int, at: float, degree: int, lo: float = 0.0,
                    vol=np.ascontiguousarray(vol), r=np.ascontiguousarray(r),
                    coords=coords, u_exact=u, g=g,
                    meta=dict(m=m, n_domain_axis=n_om, lo=lo, hi=hi, source=source))
+
+
+def cube_neumann(dim: int, n_box: int, at: float, degree: int) -> Problem:
+    """The 'sin' cube (u = prod sin(pi x_k) on [0, 1]^dim) with a flux boundary
+    on the face x = 1: its nodes that lie on no other face form Gamma_q, with
+    q = du/dx = -pi prod_{k>0} sin(pi x_k) and areas h^(dim-1) (1 in 1D); the
+    other faces keep u = 0 as Dirichlet values."""
+    p = cube(dim, n_box, at, degree, source="sin", name="cube_neumann")
+    n_om = p.meta["n_domain_axis"]
+    idx = [np.arange(n_box) for _ in range(dim)]
+    shape = p.chi.shape
+    on_x1 = np.zeros(shape, bool)
+    on_x1[..., n_om - 1] = True
+    other = np.zeros(shape, bool)
+    for k in range(1, dim):
+        ax = dim - 1 - k                    # axis k is array axis dim-1-k
+        face = (idx[k] == 0) | (idx[k] == n_om - 1)
+        sl = [None] * dim
+        sl[ax] = slice(None)
+        other |= np.broadcast_to(face[tuple(sl)], shape)
+    neu = (p.chi > 0) & on_x1 & ~other
+    X = _mesh(p.coords)
+    q = -math.pi * np.ones(shape)
+    for k in range(1, dim):
+        q = q * np.sin(math.pi * X[k])
+    h = p.h[0]
+    p.dirichlet = (p.dirichlet.astype(bool) & ~neu).astype(np.uint8)
+    p.free = (p.chi - p.dirichlet).astype(np.uint8)
+    p.area = np.where(neu, h ** (dim - 1), 0.0)
+    p.q = np.where(neu, q, 0.0)
+    return p
 
 
 def face_dirichlet(chi: np.ndarray) -> np.ndarray:
