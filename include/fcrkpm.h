@@ -50,8 +50,10 @@ enum {
     FCRKPM_OP_UH = 3,     /* u^h = N d at the nodes                          (Eq 63, 94; Alg 3)          */
     FCRKPM_OP_NT = 4,     /* N^T y  (Eq 92 without V)                                                    */
     FCRKPM_OP_VN = 5,     /* V o (N z)                                                                   */
-    FCRKPM_OP_M = 6       /* f^m = M d, consistent mass (Eq C.5, C.8, C.11; Alg C.1), domain mask
+    FCRKPM_OP_M = 6,      /* f^m = M d, consistent mass (Eq C.5, C.8, C.11; Alg C.1), domain mask
                              in and out; the first call builds its coefficients (synchronous)           */
+    FCRKPM_OP_FQ = 7      /* f^q = N^T (A o q), boundary flux load (Eq 28, A.4-A.5; Alg A.1) with the
+                             areas A of fcrkpm_set_boundary; FCRKPM_ERR_ARG without them                */
 };
 
 /* Number types. */
@@ -185,6 +187,33 @@ fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t n
 fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* r,
                            const double* g, double* d_inout, double* uh_out, double tol,
                            int32_t maxit, fcrkpm_info* info, void* stream);
+
+/*
+ * fcrkpm_set_boundary -- boundary areas A of the flux nodes Gamma_q (Eq 28,
+ * A.2, A.7): the quadrature weight of every boundary node that carries a flux,
+ * 0 elsewhere; nodes outside the domain are ignored.
+ *
+ *   area    device FP64 per node (copied), or NULL to remove the areas
+ *   stream  HIP stream the copy runs on (synchronised)
+ *
+ * Errors: FCRKPM_ERR_ARG (non-finite area), FCRKPM_ERR_OOM, FCRKPM_ERR_HIP.
+ */
+fcrkpm_status fcrkpm_set_boundary(fcrkpm_ctx* ctx, const double* area, void* stream);
+
+/*
+ * fcrkpm_solve_flux -- fcrkpm_solve with a flux boundary (Sec 2.2-2.4, Eq 8-9,
+ * 28-29; Alg A.1): right-hand side b = chi_Omega (f^r + f^q - K d_Gamma) with
+ * f^q = N^T (A o q) over the areas of fcrkpm_set_boundary.
+ *
+ *   q       device FP64 flux grad u . n per node (meaningful where A > 0), laid
+ *           out like r; every other argument as in fcrkpm_solve
+ *
+ * Errors: as fcrkpm_solve; FCRKPM_ERR_ARG without boundary areas or for NaN/Inf
+ * in q.
+ */
+fcrkpm_status fcrkpm_solve_flux(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, const double* r,
+                                const double* q, const double* g, double* d_inout, double* uh_out,
+                                double tol, int32_t maxit, fcrkpm_info* info, void* stream);
 
 /*
  * fcrkpm_transient -- time stepping of the diffusion problem (App. C, Eq C.1-

@@ -148,6 +148,8 @@ void release(Ctx& c)
     dfree(c.dirm);
     dfree(c.vol64);
     dfree(c.vol32);
+    dfree(c.area64);
+    dfree(c.area32);
     dfree(c.b0_64);
     dfree(c.ba_64);
     dfree(c.b0_32);
@@ -348,6 +350,13 @@ const T* vol_of(const Ctx& c)
 {
     if constexpr (sizeof(T) == 8) return c.vol64;
     else return c.vol32;
+}
+
+template <typename T>
+const T* area_of(const Ctx& c)
+{
+    if constexpr (sizeof(T) == 8) return c.area64;
+    else return c.area32;
 }
 
 template <typename T>
@@ -621,11 +630,18 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
         case FCRKPM_OP_NT:
         case FCRKPM_OP_UH:
         case FCRKPM_OP_VN:
+        case FCRKPM_OP_FQ:
             if constexpr (!std::is_same_v<T, Tio>) {
                 fail(FCRKPM_ERR_ARG, "mixed precisions are supported for K only");
             } else {
-                const T* vol = (op == FCRKPM_OP_FR || op == FCRKPM_OP_VN) ? vol_of<T>(c) : nullptr;
-                if (op == FCRKPM_OP_FR || op == FCRKPM_OP_NT) {
+                // f^q is the load pass of f^r with the boundary areas A in place
+                // of V (Eq A.5, Alg A.1)
+                if (op == FCRKPM_OP_FQ && !c.area64)
+                    fail(FCRKPM_ERR_ARG, "no boundary areas: call fcrkpm_set_boundary first");
+                const T* vol = (op == FCRKPM_OP_FR || op == FCRKPM_OP_VN) ? vol_of<T>(c)
+                               : op == FCRKPM_OP_FQ                      ? area_of<T>(c)
+                                                                         : nullptr;
+                if (op == FCRKPM_OP_FR || op == FCRKPM_OP_NT || op == FCRKPM_OP_FQ) {
                     {
                         ProfScope ps(c, kind_of<T>(KD_MID_LOAD), nn * (sizeof(Tio) + (c.s + 1) * rt + outb2), st);
                         launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_LOAD,
@@ -1750,9 +1766,10 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
 }
 
 namespace {
-// b = chi_Omega (f^r - K d_Gamma) and x = chi_Omega d0 for nrhs fields (Eq 29, Alg 5)
+// b = chi_Omega (f^r + f^q - K d_Gamma) and x = chi_Omega d0 for nrhs fields
+// (Eq 28-29, Alg 5, Alg A.1; f^q only with a flux q)
 void prepare_solve(Ctx& c, int nrhs, const double* r, const double* g, const double* d0,
-                   hipStream_t st)
+                   hipStream_t st, const double* qflux = nullptr)
 {
     ensure_rhs(c, nrhs);
     ensure_work(c, nrhs);
@@ -1761,16 +1778,21 @@ void prepare_solve(Ctx& c, int nrhs, const double* r, const double* g, const dou
     launch_check_finite(r, nn * nrhs, c.dflag + 2, st);
     if (g) launch_check_finite(g, nn * nrhs, c.dflag + 2, st);
     if (d0) launch_check_finite(d0, nn * nrhs, c.dflag + 2, st);
+    if (qflux) launch_check_finite(qflux, nn * nrhs, c.dflag + 2, st);
     int hf = 0;
     HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, g or the initial guess");
+    if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, q, g or the initial guess");
     double* b = vec64(c, V_B);
     double* x = vec64(c, V_X);
     double* t = vec64(c, V_T);
     double* p = vec64(c, V_P);
     double* q = vec64(c, V_Q);
     apply_one<double>(c, FCRKPM_OP_FR, r, t, nrhs, st);  // f^r (Alg 4)
+    if (qflux) {
+        apply_one<double>(c, FCRKPM_OP_FQ, qflux, q, nrhs, st);  // f^q (Alg A.1)
+        launch_lincomb_masked(t, 1.0, q, 1.0, nullptr, c.chi, t, nn, nrhs, st);
+    }
     if (g) {
         launch_masked_copy<double>(g, c.dirm, p, nn, nrhs, st);  // d_Gamma
         apply_one<double>(c, FCRKPM_OP_K_FULL, p, q, nrhs, st);
@@ -1812,7 +1834,7 @@ extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype
     if (!ctx) return FCRKPM_ERR_ARG;
     Ctx& c = ctx->c;
     return run_guarded(c.err, [&]() -> fcrkpm_status {
-        if (op < FCRKPM_OP_K || op > FCRKPM_OP_M) fail(FCRKPM_ERR_ARG, "unknown operator");
+        if (op < FCRKPM_OP_K || op > FCRKPM_OP_FQ) fail(FCRKPM_ERR_ARG, "unknown operator");
         if (dtype != FCRKPM_F64 && dtype != FCRKPM_F32) fail(FCRKPM_ERR_ARG, "unknown dtype");
         if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
         if (!in || !out) fail(FCRKPM_ERR_ARG, "NULL array");
@@ -1850,6 +1872,56 @@ extern "C" fcrkpm_status fcrkpm_solve(fcrkpm_ctx* ctx, int32_t mode, int32_t nrh
         HIPCHK(hipGetLastError());
         if (worst != FCRKPM_OK) c.err = "solver did not reach the tolerance";
         return worst;
+    });
+}
+
+extern "C" fcrkpm_status fcrkpm_solve_flux(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs,
+                                           const double* r, const double* q, const double* g,
+                                           double* d_inout, double* uh_out, double tol,
+                                           int32_t maxit, fcrkpm_info* info, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        check_solve_args(mode, nrhs, tol, maxit);
+        if (!r || !q || !d_inout) fail(FCRKPM_ERR_ARG, "NULL array");
+        if (!c.area64) fail(FCRKPM_ERR_ARG, "no boundary areas: call fcrkpm_set_boundary first");
+        hipStream_t st = (hipStream_t)stream;
+        prepare_solve(c, nrhs, r, g, d_inout, st, q);
+        Solver S(c, nrhs, mode, tol, maxit);
+        run_solvers({&S}, graphs_enabled(c), st);
+        const fcrkpm_status worst = S.finish(info, st);
+        finish_solve(c, nrhs, g, d_inout, uh_out, st);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        if (worst != FCRKPM_OK) c.err = "solver did not reach the tolerance";
+        return worst;
+    });
+}
+
+extern "C" fcrkpm_status fcrkpm_set_boundary(fcrkpm_ctx* ctx, const double* area, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        hipStream_t st = (hipStream_t)stream;
+        HIPCHK(hipStreamSynchronize(st));
+        dfree(c.area64);
+        dfree(c.area32);
+        if (!area) return FCRKPM_OK;
+        HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+        launch_check_finite(area, c.nn, c.dflag + 2, st);
+        int hf = 0;
+        HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hf) fail(FCRKPM_ERR_ARG, "non-finite boundary area");
+        c.area64 = dalloc<double>(c.nn);
+        c.area32 = dalloc<float>(c.nn);
+        HIPCHK(hipMemcpyAsync(c.area64, area, sizeof(double) * c.nn, hipMemcpyDeviceToDevice, st));
+        launch_to32(c.area64, c.area32, c.nn, st);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        return FCRKPM_OK;
     });
 }
 

@@ -107,6 +107,8 @@ struct Ctx {
     uint8_t* dirm = nullptr;            // chi_Gamma_g
     double* vol64 = nullptr;
     float* vol32 = nullptr;
+    double* area64 = nullptr;           // boundary areas A of the flux nodes (App. A), or NULL
+    float* area32 = nullptr;
     double* b0_64 = nullptr;            // [s][nn]
     double* ba_64 = nullptr;            // [krows][s][nn]: rows of the K-type product in use
     float* b0_32 = nullptr;

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfcrkpm.so")
 
 OK, ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = range(7)
-OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN, OP_M = range(7)
+OP_K, OP_K_FULL, OP_FR, OP_UH, OP_NT, OP_VN, OP_M, OP_FQ = range(8)
 F64, F32 = 0, 1
 MODE_F64, MODE_F32_REFINED, MODE_F32_PRODUCTS = 0, 1, 2
 COEF_B0, COEF_BALPHA, COEF_FREE, COEF_LUMPED_MASS = 0, 1, 2, 3
@@ -29,7 +29,7 @@ TIME_IMPLICIT, TIME_EXPLICIT_LUMPED = 0, 1
 KERNEL_CUBIC_BSPLINE = 0
 
 _OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN,
-        "M": OP_M}
+        "M": OP_M, "FQ": OP_FQ}
 _MODES = {"f64": MODE_F64, "f32_refined": MODE_F32_REFINED, "f32_products": MODE_F32_PRODUCTS}
 
 EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
@@ -37,7 +37,8 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_last_error", "fcrkpm_status_str", "fcrkpm_version",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
-           "fcrkpm_get_option", "fcrkpm_transient")
+           "fcrkpm_get_option", "fcrkpm_transient", "fcrkpm_set_boundary",
+           "fcrkpm_solve_flux")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -113,6 +114,11 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(Info), V]
     lib.fcrkpm_get_coeffs.restype = C.c_int
     lib.fcrkpm_get_coeffs.argtypes = [V, C.c_int32, V, V]
+    lib.fcrkpm_set_boundary.restype = C.c_int
+    lib.fcrkpm_set_boundary.argtypes = [V, V, V]
+    lib.fcrkpm_solve_flux.restype = C.c_int
+    lib.fcrkpm_solve_flux.argtypes = [V, C.c_int32, C.c_int32, V, V, V, V, V, C.c_double,
+                                      C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_transient.restype = C.c_int
     lib.fcrkpm_transient.argtypes = [V, C.POINTER(Time), C.c_int32, C.c_int32, V, V, V, V,
                                      C.c_double, C.c_int32, C.POINTER(Info), V]
@@ -226,7 +232,7 @@ class Problem:
 
     # ------------------------------------------------------------------ ops
     def apply(self, op, x, out=None, stream=None):
-        """Apply operator op ('K', 'K_FULL', 'FR', 'UH', 'NT', 'VN', 'M') to x.
+        """Apply operator op ('K', 'K_FULL', 'FR', 'UH', 'NT', 'VN', 'M', 'FQ') to x.
 
         x: float64 or float32 tensor of shape [..., nz, ny, nx]; leading
         dimensions are independent fields.  The precision of x selects the
@@ -247,10 +253,18 @@ class Problem:
             _stream_ptr(stream)))
         return out
 
+    def set_boundary(self, area=None, stream=None):
+        """Boundary areas A of the flux nodes (None removes them)."""
+        a = None if area is None else _dev(area, torch.float64, self.device)
+        if a is not None and a.numel() != self.nn:
+            raise ValueError("area must hold one value per node")
+        self._check(load_library().fcrkpm_set_boundary(self._h, _ptr(a), _stream_ptr(stream)))
+
     def solve(self, r, g=None, d0=None, mode="f64", tol=1e-12, maxit=20000, want_uh=True,
-              stream=None, raise_on_noconv=True):
+              stream=None, raise_on_noconv=True, q=None):
         """Strong-Dirichlet static solve of one or more right-hand sides (leading
-        dimensions of r); returns (d, u^h or None, info dict)."""
+        dimensions of r), with a boundary flux q on the areas of set_boundary
+        when q is given; returns (d, u^h or None, info dict)."""
         r = _dev(r, torch.float64, self.device)
         nrhs = r.numel() // self.nn
         if nrhs < 1 or nrhs * self.nn != r.numel():
@@ -259,9 +273,15 @@ class Problem:
         d = torch.zeros_like(r) if d0 is None else _dev(d0, torch.float64, self.device).clone()
         uh = torch.empty_like(r) if want_uh else None
         infos = (Info * nrhs)()
-        st = load_library().fcrkpm_solve(self._h, _MODES[mode], nrhs, _ptr(r), _ptr(g), _ptr(d),
-                                         _ptr(uh), float(tol), int(maxit), infos,
-                                         _stream_ptr(stream))
+        if q is not None:
+            q = _dev(q, torch.float64, self.device).expand_as(r).contiguous()
+            st = load_library().fcrkpm_solve_flux(self._h, _MODES[mode], nrhs, _ptr(r), _ptr(q),
+                                                  _ptr(g), _ptr(d), _ptr(uh), float(tol),
+                                                  int(maxit), infos, _stream_ptr(stream))
+        else:
+            st = load_library().fcrkpm_solve(self._h, _MODES[mode], nrhs, _ptr(r), _ptr(g),
+                                             _ptr(d), _ptr(uh), float(tol), int(maxit), infos,
+                                             _stream_ptr(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             self._check(st)
         return d, uh, _infos_dict(infos, st)
