@@ -194,6 +194,7 @@ def main():
         if a.workload == "c5":
             out["adjoint"] = adjoint_time(a, wl, chi, dirm, vol, r, dev)
             out["transient"] = transient_time(a, wl, chi, dirm, vol, r, dev)
+            out["flux"] = flux_time(a, wl, dev)
 
     if not a.no_cpu_baseline:
         import oracle
@@ -308,6 +309,50 @@ def transient_time(a, wl, chi, dirm, vol, r, dev, steps=2, explicit_steps=50):
                        "steps_per_s": explicit_steps / te}
     pb.close()
     res["mass_products"] = apply_loop(wl, chi, dirm, vol, dev, op="M")
+    return res
+
+
+def flux_time(a, wl, dev, reps=20):
+    """A flux boundary on the same box (App. A): the cube's x = 1 face carries
+    q = du/dx of the manufactured solution (areas h^2), the other faces keep
+    u = 0; the refined solve with f^q in its right-hand side, its u^h error,
+    and standalone flux loads (median over `reps`, HIP events)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+    from paper_2403_19854_amd import workloads as W
+
+    p = W.cube_neumann(wl.dim, wl.dims[0], wl.at[0], wl.degree)
+    pb = fcrkpm.Problem.from_workload(p, device=dev)
+    pb.set_boundary(torch.from_numpy(p.area))
+    r = torch.from_numpy(p.r).to(dev)
+    q = torch.from_numpy(p.q).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d, uh, info = pb.solve(r, q=q, mode="f32_refined", tol=a.tol, maxit=a.maxit)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    m = p.chi > 0
+    err = float(np.linalg.norm((uh.cpu().numpy() - p.u_exact)[m]) / np.linalg.norm(p.u_exact[m]))
+    st = torch.cuda.current_stream()
+    res = {"flux_nodes": int((p.area > 0).sum()), "solve_ms": 1e3 * ts, "iters": info["iters"],
+           "uh_rel_l2_vs_exact": err}
+    for name, qt in (("f32", q.float()), ("f64", q)):
+        y = torch.empty_like(qt)
+        for _ in range(5):
+            pb.apply("FQ", qt, out=y, stream=st)
+        tl = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            pb.apply("FQ", qt, out=y, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            tl.append(e0.elapsed_time(e1))
+        res["load_" + name + "_median_ms"] = float(np.median(tl))
+    pb.close()
     return res
 
 
