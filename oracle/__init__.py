@@ -7,7 +7,8 @@ wrap-around.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package; the product
 library never does, and this package never imports the product library.
 
-The boundary flux load (App. A) and the time-dependent part (App. C:
+The boundary flux load (App. A), the nonlinear force and Newton solve
+(App. B) and the time-dependent part (App. C:
 consistent and lumped mass, implicit and explicit time stepping of the
 diffusion equation) are plain numpy on top of the same neighbour-loop
 operators.
@@ -246,6 +247,45 @@ class Oracle:
         rhs = np.where(f, self.apply_fr(r) + self.apply_fq(q, area) - self.apply_k(dG), 0.0)
         x, it, rel = self.cg(f.astype(np.uint8), rhs, tol=tol, maxit=maxit)
         return np.where(f, x, 0.0) + dG, it, rel
+
+    # --- nonlinear problems (App. B) -----------------------------------------
+    def apply_fn(self, d, kappa):
+        """Nonlinear force f^N = int N^T N(u^h) dOmega with N(u) = kappa u^3
+        under nodal integration (Eq B.2, B.4): N^T (V o kappa (N d)^3)."""
+        u = self.apply_uh(d)
+        return self.apply_fr(kappa * u ** 3)
+
+    def solve_nonlinear(self, free, dirichlet, r, kappa, g=None, tol=1e-13, newton_tol=1e-11,
+                        maxnewton=50, maxit=100000):
+        """Static solve of -lap u + kappa u^3 = r (Eq 8 with the term of Eq B.1):
+        R(d) = K d + f^N(d) - f^r = 0 on the free rows with d = g on the
+        Dirichlet nodes, by Newton's method from d = d_G, each step solving
+        (K + N^T diag(3 kappa V u^2) N) delta = -R on the free rows by CG to tol.
+        Stops when ||R|| <= newton_tol ||chi_Omega f^r||.  Returns (d, Newton
+        steps, CG iterations)."""
+        f = np.asarray(free).reshape(self.shape).astype(bool)
+        dG = np.zeros(self.shape)
+        if g is not None:
+            dG = np.where(np.asarray(dirichlet).reshape(self.shape).astype(bool),
+                          _f64(g).reshape(self.shape), 0.0)
+        fr = self.apply_fr(r)
+        fn = float(np.linalg.norm(np.where(f, fr, 0.0)))
+        d = dG.copy()
+        its = 0
+        for step in range(maxnewton + 1):
+            u = self.apply_uh(d)
+            R = np.where(f, self.apply_k(d) + self.apply_fr(kappa * u ** 3) - fr, 0.0)
+            if float(np.linalg.norm(R)) <= newton_tol * fn or step == maxnewton:
+                return d, step, its
+            w = 3.0 * kappa * u ** 2
+
+            def jac(v, w=w):
+                return np.where(f, self.apply_k(v) + self.apply_fr(w * self.apply_uh(v)), 0.0)
+
+            delta, k = _cg(jac, -R, np.zeros(self.shape), tol, maxit)
+            its += k
+            d = d + np.where(f, delta, 0.0)
+        return d, maxnewton, its
 
     # --- time-dependent problems (App. C) -----------------------------------
     def apply_m(self, d):

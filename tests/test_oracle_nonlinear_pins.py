@@ -1,0 +1,75 @@
+"""Pins of the oracle's nonlinear part (App. B, N(u) = kappa u^3) against
+what the mathematics fixes: kappa = 0 is the linear solve, the Newton
+Jacobian is the derivative of the residual (central differences), the force
+of a constant field integrates exactly (partition of unity), and the solution
+converges at second order (support 2.0h) to a manufactured solution of
+-lap u + kappa u^3 = r, which a wrong sign or power of the nonlinearity
+breaks."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_19854_amd import workloads as W
+
+
+def make(p):
+    return oracle.Oracle(p.dims, p.h, p.at, p.degree, p.chi, p.vol)
+
+
+def test_kappa_zero_is_the_linear_solve():
+    p = W.cube(2, 20, 2.5, 1)
+    o = make(p)
+    d, steps, _ = o.solve_nonlinear(p.free, p.dirichlet, p.r, 0.0)
+    ref, _, _ = o.solve(p.free, p.dirichlet, p.r, tol=1e-13)
+    assert steps == 1
+    np.testing.assert_allclose(d, ref, atol=1e-10 * np.abs(ref).max())
+
+
+def test_force_of_a_constant_integrates_exactly():
+    # u^h = c for d = c on every domain node (zeroth reproducing condition), so
+    # sum_I f^N_I = kappa c^3 sum_K V_K
+    for p in (W.cube(3, 12, 2.5, 1), W.cube(2, 16, 3.0, 2)):
+        o = make(p)
+        fn = o.apply_fn(1.5 * p.chi.astype(float), 2.0)
+        assert fn.sum() == pytest.approx(2.0 * 1.5 ** 3 * p.vol.sum(), rel=1e-12)
+
+
+def test_jacobian_is_the_residual_derivative():
+    p = W.cube(2, 16, 2.5, 1)
+    o = make(p)
+    rng = np.random.default_rng(3)
+    d = np.where(p.chi > 0, rng.standard_normal(p.shape), 0.0)
+    v = np.where(p.chi > 0, rng.standard_normal(p.shape), 0.0)
+    kappa = 3.0
+
+    def R(x):
+        return o.apply_k(x) + o.apply_fn(x, kappa)
+
+    eps = 1e-5
+    fd = (R(d + eps * v) - R(d - eps * v)) / (2 * eps)
+    u = o.apply_uh(d)
+    jv = o.apply_k(v) + o.apply_fr(3.0 * kappa * u ** 2 * o.apply_uh(v))
+    np.testing.assert_allclose(jv, fd, atol=1e-7 * np.abs(jv).max())
+
+
+@pytest.mark.parametrize("dim,ns", [(1, (40, 80)), (2, (20, 40))])
+def test_manufactured_second_order(dim, ns):
+    kappa = 5.0
+    errs = []
+    for n in ns:
+        p = W.cube(dim, n, 2.0, 1)
+        o = make(p)
+        m = p.chi > 0
+        r = p.r + kappa * p.u_exact ** 3
+        d, steps, _ = o.solve_nonlinear(p.free, p.dirichlet, r, kappa)
+        assert steps <= 8
+        errs.append(np.linalg.norm((o.apply_uh(d) - p.u_exact)[m]) / np.linalg.norm(p.u_exact[m]))
+        if n == ns[0]:
+            # the nonlinear term with the wrong sign, or squared instead of cubed
+            d2, _, _ = o.solve_nonlinear(p.free, p.dirichlet, p.r - kappa * p.u_exact ** 3, kappa)
+            e2 = np.linalg.norm((o.apply_uh(d2) - p.u_exact)[m]) / np.linalg.norm(p.u_exact[m])
+            d3, _, _ = o.solve_nonlinear(p.free, p.dirichlet, p.r + kappa * p.u_exact ** 2, kappa)
+            e3 = np.linalg.norm((o.apply_uh(d3) - p.u_exact)[m]) / np.linalg.norm(p.u_exact[m])
+            assert e2 > 20 * errs[0] and e3 > 20 * errs[0]
+    assert errs[0] < 3e-3
+    assert errs[0] / errs[1] > 3.5
