@@ -216,6 +216,44 @@ fcrkpm_status fcrkpm_solve_flux(fcrkpm_ctx* ctx, int32_t mode, int32_t nrhs, con
                                 double tol, int32_t maxit, fcrkpm_info* info, void* stream);
 
 /*
+ * fcrkpm_nonlinear_force -- f^N = N^T (V o kappa (u^h)^3) with u^h = N d, the
+ * nonlinear force of N(u) = kappa u^3 (App. B, Eq B.2, B.4, B.9; Alg B.2), FP64,
+ * asynchronous on `stream`; d and out hold nrhs fields and may be the same array.
+ * Errors: FCRKPM_ERR_ARG (NULL arrays, nrhs, non-finite kappa), FCRKPM_ERR_HIP.
+ */
+fcrkpm_status fcrkpm_nonlinear_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs, const double* d,
+                                     double* out, void* stream);
+
+/*
+ * fcrkpm_solve_nonlinear -- static solve of -lap u + kappa u^3 = r with d = g on
+ * the Dirichlet nodes (Eq 8-9 with the term of Eq B.1; App. B.3): Newton's
+ * method on R(d) = K d + f^N(d) - f^r over the free rows from d_inout, every
+ * step solving (K + N^T diag(3 kappa V (u^h)^2) N) delta = -R to `tol` with the
+ * solver of fcrkpm_solve (mode F64 or F32_REFINED); the Jacobian runs the K
+ * passes with the rows b^a and the row b^0 weighted by sqrt(3 kappa) |u^h|.
+ *
+ *   kappa       coefficient of the cubic term, >= 0 (the energy stays convex)
+ *   r, g        device FP64 source and Dirichlet values (g may be NULL), one field
+ *   d_inout     device FP64 initial guess on the free nodes in, solution out
+ *   uh_out      device FP64 u^h = N d, or NULL
+ *   tol, maxit  tolerance and iteration cap of every Newton step's CG solve
+ *   newton_tol  stop when ||R|| <= newton_tol ||chi_Omega f^r||
+ *   maxnewton   Newton step cap (>= 1)
+ *   info        one record: iters = CG iterations of all steps, outer_iters =
+ *               Newton steps, rel_res = true_rel_res = final ||R|| / ||chi_Omega f^r||
+ *
+ * Allocates five node fields for the call and rebuilds the Jacobian's
+ * coefficient rows every step (freed at the end).  Errors: FCRKPM_ERR_ARG
+ * (bad mode, tol, maxit, kappa, newton_tol, maxnewton, NULL or non-finite
+ * inputs); FCRKPM_ERR_NOCONV when newton_tol is not reached within maxnewton
+ * steps (d holds the last iterate).
+ */
+fcrkpm_status fcrkpm_solve_nonlinear(fcrkpm_ctx* ctx, int32_t mode, double kappa, const double* r,
+                                     const double* g, double* d_inout, double* uh_out, double tol,
+                                     double newton_tol, int32_t maxnewton, int32_t maxit,
+                                     fcrkpm_info* info, void* stream);
+
+/*
  * fcrkpm_transient -- time stepping of the diffusion problem (App. C, Eq C.1-
  * C.4): M d' + nu K d = f^r with strong Dirichlet values d = g held on the
  * Dirichlet nodes and a source r constant in time.  With x the free part of d

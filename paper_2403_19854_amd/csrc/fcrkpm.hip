@@ -142,6 +142,7 @@ void release(Ctx& c)
 {
     free_set(c.mass_set);
     free_set(c.shift_set);
+    free_set(c.jac_set);
     dfree(c.chi);
     dfree(c.cls);
     dfree(c.freem);
@@ -532,7 +533,7 @@ struct SetScope {
 // Pointwise data of c_m M + c_k K (App. C): the rows sqrt(c_k) b^a of the
 // stiffness (Eq 91) and sqrt(c_m) b^0 of the mass (Eq C.8), so that
 // V sum_rows c_p c_q = V (c_k B^T B + c_m b^0 b^0T).  Synchronous.
-OpSet* make_set(Ctx& c, double ck, double cm, hipStream_t st)
+OpSet* make_set(Ctx& c, double ck, double cm, hipStream_t st, const double* wnode = nullptr)
 {
     if (c.capturing) fail(FCRKPM_ERR_ARG, "operator coefficients cannot be built during graph capture");
     if (!(ck >= 0.0) || !(cm >= 0.0) || !(ck > 0.0 || cm > 0.0) || !std::isfinite(ck) || !std::isfinite(cm))
@@ -543,7 +544,7 @@ OpSet* make_set(Ctx& c, double ck, double cm, hipStream_t st)
         const size_t cnt = (size_t)s->krows * c.s * c.nn;
         s->ba_64 = dalloc<double>(cnt);
         s->ba_32 = dalloc<float>(cnt);
-        launch_op_rows(c, ck, cm, s->ba_64, s->ba_32, st);
+        launch_op_rows(c, ck, cm, s->ba_64, s->ba_32, st, wnode);
         HIPCHK(hipGetLastError());
         SetScope use(c, s);
         build_pointwise(c, st);
@@ -2127,6 +2128,137 @@ extern "C" fcrkpm_status fcrkpm_transient(fcrkpm_ctx* ctx, const fcrkpm_time* tp
         if (info) memcpy(info, acc.data(), sizeof(fcrkpm_info) * nrhs);
         if (worst != FCRKPM_OK) c.err = "a time step's solve did not reach the tolerance";
         return worst;
+    });
+}
+
+// The nonlinear force of N(u) = kappa u^3 (App. B, Eq B.2, B.9; Alg B.2):
+// u^h = N d (Alg 3), the pointwise nonlinearity, then the load pass (Alg 4).
+extern "C" fcrkpm_status fcrkpm_nonlinear_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs,
+                                                const double* d, double* out, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (!d || !out) fail(FCRKPM_ERR_ARG, "NULL array");
+        if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
+        if (!std::isfinite(kappa)) fail(FCRKPM_ERR_ARG, "kappa must be finite");
+        hipStream_t st = (hipStream_t)stream;
+        ensure_rhs(c, nrhs);
+        ensure_work(c, nrhs);
+        double* u = vec64(c, V_T);
+        apply_one<double>(c, FCRKPM_OP_UH, d, u, nrhs, st);
+        launch_pow_scaled(u, kappa, 3, u, c.nn * nrhs, st);
+        apply_one<double>(c, FCRKPM_OP_FR, u, out, nrhs, st);
+        HIPCHK(hipGetLastError());
+        return FCRKPM_OK;
+    });
+}
+
+// -lap u + kappa u^3 = r with d = g on the Dirichlet nodes (Eq 8 with the term
+// of Eq B.1): Newton's method on R(d) = K d + f^N(d) - f^r over the free rows,
+// each step one solve of (K + N^T diag(3 kappa V u^2) N) delta = -R with the
+// solver of fcrkpm_solve.  The Jacobian is a K-type product: the rows b^a,
+// then b^0 weighted per node by sqrt(3 kappa) |u^h|.
+extern "C" fcrkpm_status fcrkpm_solve_nonlinear(fcrkpm_ctx* ctx, int32_t mode, double kappa,
+                                                const double* r, const double* g,
+                                                double* d_inout, double* uh_out, double tol,
+                                                double newton_tol, int32_t maxnewton,
+                                                int32_t maxit, fcrkpm_info* info, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        check_solve_args(mode, 1, tol, maxit);
+        if (!r || !d_inout) fail(FCRKPM_ERR_ARG, "NULL array");
+        if (!(kappa >= 0.0) || !std::isfinite(kappa)) fail(FCRKPM_ERR_ARG, "kappa must be finite and >= 0");
+        if (!(newton_tol > 0.0) || maxnewton < 1) fail(FCRKPM_ERR_ARG, "newton_tol must be > 0 and maxnewton >= 1");
+        hipStream_t st = (hipStream_t)stream;
+        const long nn = c.nn;
+        ensure_rhs(c, 1);
+        ensure_work(c, 1);
+        HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+        launch_check_finite(r, nn, c.dflag + 2, st);
+        if (g) launch_check_finite(g, nn, c.dflag + 2, st);
+        launch_check_finite(d_inout, nn, c.dflag + 2, st);
+        int hf = 0;
+        HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, g or d");
+
+        struct Buf {
+            double* p = nullptr;
+            ~Buf() { dfree(p); }
+        } bufs;
+        bufs.p = dalloc<double>((size_t)5 * nn);
+        double* fr = bufs.p;          // f^r
+        double* xn = fr + nn;         // free part of the Newton iterate
+        double* dG = xn + nn;         // d_Gamma
+        double* kd = dG + nn;         // chi_Omega f^r for its norm, then f^N
+        double* fnl = kd + nn;        // kappa u^3, then the Jacobian weights 3 kappa u^2
+        double* u = vec64(c, V_T);
+        apply_one<double>(c, FCRKPM_OP_FR, r, fr, 1, st);
+        if (g) launch_masked_copy<double>(g, c.dirm, dG, nn, 1, st);
+        else HIPCHK(hipMemsetAsync(dG, 0, sizeof(double) * nn, st));
+        launch_masked_copy<double>(d_inout, c.freem, xn, nn, 1, st);
+        launch_lincomb_masked(fr, 1.0, nullptr, 0.0, nullptr, c.freem, kd, nn, 1, st);
+        dots<double>(c, kd, kd, 1, S_BB, st);
+        const double fnorm = sqrt(read_scalars(c, 1, st)[S_BB]);
+        const double scale = fnorm > 0.0 ? fnorm : 1.0;
+
+        fcrkpm_info acc;
+        memset(&acc, 0, sizeof(acc));
+        fcrkpm_status inner = FCRKPM_OK;
+        bool conv = false;
+        double rel = 0.0;
+        for (int step = 0;; ++step) {
+            launch_select(c.freem, xn, dG, d_inout, nn, 1, st);  // d = chi_Omega x + d_Gamma
+            apply_one<double>(c, FCRKPM_OP_UH, d_inout, u, 1, st);
+            launch_pow_scaled(u, kappa, 3, fnl, nn, st);
+            apply_one<double>(c, FCRKPM_OP_FR, fnl, kd, 1, st);                  // f^N
+            apply_one<double>(c, FCRKPM_OP_K_FULL, d_inout, vec64(c, V_Q), 1, st);  // K d
+            double* b = vec64(c, V_B);  // -R = f^r - K d - f^N on the free rows
+            launch_lincomb_masked(vec64(c, V_Q), -1.0, kd, -1.0, fr, c.freem, b, nn, 1, st);
+            dots<double>(c, b, b, 1, S_NORM, st);
+            rel = sqrt(read_scalars(c, 1, st)[S_NORM]) / scale;
+            acc.outer_iters = step;
+            if (log_enabled()) fprintf(stderr, "[fcrkpm] newton %d: |R| / |f| = %.3e\n", step, rel);
+            if (rel <= newton_tol) {
+                conv = true;
+                break;
+            }
+            if (step == maxnewton) break;
+            launch_pow_scaled(u, 3.0 * kappa, 2, fnl, nn, st);  // weights 3 kappa u^2
+            HIPCHK(hipStreamSynchronize(st));
+            free_set(c.jac_set);
+            c.jac_set = make_set(c, 1.0, 1.0, st, fnl);
+            HIPCHK(hipMemsetAsync(vec64(c, V_X), 0, sizeof(double) * nn, st));
+            fcrkpm_info inf;
+            {
+                SetScope use(c, c.jac_set);
+                Solver S(c, 1, mode, tol, maxit);
+                run_solvers({&S}, graphs_enabled(c), st);
+                const fcrkpm_status w = S.finish(&inf, st);
+                if (w != FCRKPM_OK) inner = w;
+            }
+            acc.iters += inf.iters;
+            acc.fallback_used |= inf.fallback_used;
+            acc.matvecs_f64 += inf.matvecs_f64 + 1;
+            acc.matvecs_f32 += inf.matvecs_f32;
+            launch_lincomb_masked(xn, 1.0, vec64(c, V_X), 1.0, nullptr, c.freem, xn, nn, 1, st);
+        }
+        acc.rel_res = rel;
+        acc.true_rel_res = rel;
+        if (uh_out) apply_one<double>(c, FCRKPM_OP_UH, d_inout, uh_out, 1, st);
+        HIPCHK(hipStreamSynchronize(st));
+        free_set(c.jac_set);
+        HIPCHK(hipGetLastError());
+        if (info) *info = acc;
+        if (!conv) {
+            c.err = inner != FCRKPM_OK ? "a Newton step's linear solve did not reach the tolerance"
+                                       : "Newton's method did not reach newton_tol";
+            return FCRKPM_ERR_NOCONV;
+        }
+        return FCRKPM_OK;
     });
 }
 

@@ -122,6 +122,7 @@ struct Ctx {
     OpSet* mass_set = nullptr;          // consistent mass (built on first use)
     OpSet* shift_set = nullptr;         // c_m M + c_k K of the last implicit time step
     double shift_w[2] = {0.0, 0.0};     // its (c_m, c_k)
+    OpSet* jac_set = nullptr;           // K + N^T diag(w V) N of the last Newton step
     bool use_regpath = true;            // register-resident passes where they apply
     uint8_t* cls = nullptr;             // node class: 0 outside the domain, 1 interior, 2 other
     long ncls2 = 0;                     // class-2 nodes
@@ -254,8 +255,12 @@ void launch_vol(const uint8_t* chi, const double* vol_in, double hv, double* vol
                 long nn, hipStream_t st);
 void launch_mask_to_double(const uint8_t* m, double* out, long nn, hipStream_t st);
 void launch_check_finite(const double* x, long nn, int* flag, hipStream_t st);
-// rows of another K-type product: sqrt(ck) b^a (when ck > 0), then sqrt(cm) b^0 (when cm > 0)
-void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st);
+// rows of another K-type product: sqrt(ck) b^a (when ck > 0), then sqrt(cm) b^0 (when cm > 0),
+// the latter with sqrt(wnode) per node in place of sqrt(cm) when wnode is given
+void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st,
+                    const double* wnode = nullptr);
+// out = kappa u^pw (pw 2 or 3) over n values
+void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long n, hipStream_t st);
 // out = mask ? wa a + wb b + c : 0 (b and c may be NULL) over nrhs fields
 void launch_lincomb_masked(const double* a, double wa, const double* b, double wb, const double* cc,
                            const uint8_t* mask, double* out, long nn, int nrhs, hipStream_t st);

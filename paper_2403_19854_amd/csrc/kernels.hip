@@ -680,24 +680,47 @@ void launch_select(const uint8_t* mask, const double* a, const double* b, double
 // sqrt(ck) b^a, the row after them sqrt(cm) b^0, in the [row][s][nn] layout
 // of b^a.
 __global__ void k_op_rows(const double* __restrict__ ba, const double* __restrict__ b0, long nba,
-                          long total, double wk, double wm, double* __restrict__ o64,
-                          float* __restrict__ o32)
+                          long total, double wk, double wm, const double* __restrict__ wnode,
+                          long nn, double* __restrict__ o64, float* __restrict__ o32)
 {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
          i += (long)gridDim.x * blockDim.x) {
-        const double v = i < nba ? wk * ba[i] : wm * b0[i - nba];
+        double v;
+        if (i < nba) {
+            v = wk * ba[i];
+        } else {
+            const long j = i - nba;  // [s][nn]: node j % nn
+            v = (wnode ? sqrt(wnode[j % nn]) : wm) * b0[j];
+        }
         o64[i] = v;
         o32[i] = (float)v;
     }
 }
 
-void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st)
+void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32, hipStream_t st,
+                    const double* wnode)
 {
     const long per = (long)c.s * c.nn;
     const long nba = ck > 0.0 ? (long)c.dim * per : 0;
     const long total = nba + (cm > 0.0 ? per : 0);
     hipLaunchKernelGGL(k_op_rows, dim3(ew_blocks(total)), dim3(256), 0, st, c.ba_64, c.b0_64, nba,
-                       total, sqrt(ck), sqrt(cm), o64, o32);
+                       total, sqrt(ck), sqrt(cm), wnode, c.nn, o64, o32);
+}
+
+__global__ void k_pow_scaled(const double* __restrict__ u, double kappa, int cube,
+                             double* __restrict__ out, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double v = u[i];
+        out[i] = cube ? kappa * v * v * v : kappa * v * v;
+    }
+}
+
+void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pow_scaled, dim3(ew_blocks(n)), dim3(256), 0, st, u, kappa,
+                       pw == 3 ? 1 : 0, out, n);
 }
 
 __global__ void k_lincomb_masked(const double* __restrict__ a, double wa,

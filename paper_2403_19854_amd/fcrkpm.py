@@ -38,7 +38,7 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
            "fcrkpm_get_option", "fcrkpm_transient", "fcrkpm_set_boundary",
-           "fcrkpm_solve_flux")
+           "fcrkpm_solve_flux", "fcrkpm_nonlinear_force", "fcrkpm_solve_nonlinear")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -119,6 +119,11 @@ def load_library(path: str = LIB_PATH):
     lib.fcrkpm_solve_flux.restype = C.c_int
     lib.fcrkpm_solve_flux.argtypes = [V, C.c_int32, C.c_int32, V, V, V, V, V, C.c_double,
                                       C.c_int32, C.POINTER(Info), V]
+    lib.fcrkpm_nonlinear_force.restype = C.c_int
+    lib.fcrkpm_nonlinear_force.argtypes = [V, C.c_double, C.c_int32, V, V, V]
+    lib.fcrkpm_solve_nonlinear.restype = C.c_int
+    lib.fcrkpm_solve_nonlinear.argtypes = [V, C.c_int32, C.c_double, V, V, V, V, C.c_double,
+                                           C.c_double, C.c_int32, C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_transient.restype = C.c_int
     lib.fcrkpm_transient.argtypes = [V, C.POINTER(Time), C.c_int32, C.c_int32, V, V, V, V,
                                      C.c_double, C.c_int32, C.POINTER(Info), V]
@@ -321,6 +326,38 @@ class Problem:
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             self._check(st)
         return d, uh, _infos_dict(infos, st)
+
+    def nonlinear_force(self, d, kappa, out=None, stream=None):
+        """f^N = N^T (V o kappa (N d)^3) for one or more fields d (FP64)."""
+        d = _dev(d, torch.float64, self.device)
+        nrhs = d.numel() // self.nn
+        if nrhs < 1 or nrhs * self.nn != d.numel():
+            raise ValueError("d does not hold whole fields")
+        if out is None:
+            out = torch.empty_like(d)
+        self._check(load_library().fcrkpm_nonlinear_force(self._h, float(kappa), nrhs, _ptr(d),
+                                                          _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def solve_nonlinear(self, r, kappa, g=None, d0=None, mode="f64", tol=1e-12,
+                        newton_tol=1e-10, maxnewton=30, maxit=20000, want_uh=True, stream=None,
+                        raise_on_noconv=True):
+        """-lap u + kappa u^3 = r by Newton's method (one field); returns
+        (d, u^h or None, info dict with outer_iters = Newton steps)."""
+        r = _dev(r, torch.float64, self.device)
+        if r.numel() != self.nn:
+            raise ValueError("r must hold one field")
+        g = None if g is None else _dev(g, torch.float64, self.device)
+        d = torch.zeros_like(r) if d0 is None else _dev(d0, torch.float64, self.device).clone()
+        uh = torch.empty_like(r) if want_uh else None
+        info = (Info * 1)()
+        st = load_library().fcrkpm_solve_nonlinear(self._h, _MODES[mode], float(kappa), _ptr(r),
+                                                   _ptr(g), _ptr(d), _ptr(uh), float(tol),
+                                                   float(newton_tol), int(maxnewton), int(maxit),
+                                                   info, _stream_ptr(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            self._check(st)
+        return d, uh, _infos_dict(info, st)
 
     def set_regpath(self, on: bool):
         """Use the register-resident FP32 K passes where they apply (default)."""
