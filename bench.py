@@ -195,6 +195,7 @@ def main():
             out["adjoint"] = adjoint_time(a, wl, chi, dirm, vol, r, dev)
             out["transient"] = transient_time(a, wl, chi, dirm, vol, r, dev)
             out["flux"] = flux_time(a, wl, dev)
+            out["nonlinear"] = nonlinear_time(a, wl, chi, dirm, vol, dev)
 
     if not a.no_cpu_baseline:
         import oracle
@@ -354,6 +355,31 @@ def flux_time(a, wl, dev, reps=20):
         res["load_" + name + "_median_ms"] = float(np.median(tl))
     pb.close()
     return res
+
+
+def nonlinear_time(a, wl, chi, dirm, vol, dev, kappa=5.0):
+    """-lap u + kappa u^3 = r on the same grid (App. B), r manufactured from
+    the workload's u: the refined Newton solve from d = 0 (each step's CG to
+    the bench tolerance, Newton to 1e-10), its steps, CG iterations and u^h
+    error."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    r = torch.from_numpy(wl.r + kappa * wl.u_exact ** 3).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d, uh, info = pb.solve_nonlinear(r, kappa, mode="f32_refined", tol=a.tol, newton_tol=1e-10,
+                                     maxit=a.maxit)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    pb.close()
+    m = wl.chi > 0
+    err = float(np.linalg.norm((uh.cpu().numpy() - wl.u_exact)[m]) / np.linalg.norm(wl.u_exact[m]))
+    return {"kappa": kappa, "solve_ms": 1e3 * ts, "newton_steps": info["outer_iters"],
+            "cg_iters": info["iters"], "residual": info["rel_res"], "uh_rel_l2_vs_exact": err}
 
 
 def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5, op="K"):
