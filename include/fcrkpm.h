@@ -127,7 +127,7 @@ typedef struct {
  *   out      receives the new context (NULL on failure)
  *
  * Errors: FCRKPM_ERR_ARG for a bad dimension, box size (each active axis must
- * factor into 2, 3, 5 and be at least 4 and at most 1024), support (1 <= a~,
+ * factor into 2, 3, 5, 7 and be at least 4 and at most 1024), support (1 <= a~,
  * floor(a~) < n/2), degree, a Dirichlet node outside the mask, or a mask
  * whose extent on an axis leaves a periodic gap under (floor(a~)+1) nodes
  * (Sec 5.1, Eq 66: the wrap-around would couple the two ends).  A mask that

@@ -256,6 +256,10 @@ bool make_plan(int n, LinePlan& p)
         r /= 5;
         if (!push(5)) return false;
     }
+    while (r % 7 == 0) {
+        r /= 7;
+        if (!push(7)) return false;
+    }
     return r == 1;
 }
 
@@ -1554,7 +1558,7 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                 c.at[a] = support[a];
                 c.m[a] = (int)floor(support[a]);
                 if (2 * c.m[a] >= c.n[a]) fail(FCRKPM_ERR_ARG, "support too large for the box");
-                if (!make_plan(c.n[a], c.plan[a])) fail(FCRKPM_ERR_ARG, "box size must factor into 2, 3 and 5");
+                if (!make_plan(c.n[a], c.plan[a])) fail(FCRKPM_ERR_ARG, "box size must factor into 2, 3, 5 and 7");
             } else {
                 if (c.n[a] != 1) fail(FCRKPM_ERR_ARG, "unused axes must have n = 1");
                 c.h[a] = 1.0;

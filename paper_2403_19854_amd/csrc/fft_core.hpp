@@ -95,6 +95,33 @@ __device__ __forceinline__ void dft5(cplx<T>* v)
     v[3] = a2 - b2;
 }
 
+// seven points: conjugate-symmetric pairs t_k = v_k + v_(7-k), u_k = v_k - v_(7-k)
+template <typename T, int DIR>
+__device__ __forceinline__ void dft7(cplx<T>* v)
+{
+    const T c1 = T(0.62348980185873353052500488400424);   // cos(2 pi / 7)
+    const T c2 = T(-0.22252093395631440428890256449679);  // cos(4 pi / 7)
+    const T c3 = T(-0.90096886790241912623610231950745);  // cos(6 pi / 7)
+    const T s1 = T(0.78183148246802980870844452667406);   // sin(2 pi / 7)
+    const T s2 = T(0.97492791218182360701813168299393);   // sin(4 pi / 7)
+    const T s3 = T(0.43388373911755812047576833284836);   // sin(6 pi / 7)
+    const cplx<T> t1 = v[1] + v[6], t2 = v[2] + v[5], t3 = v[3] + v[4];
+    const cplx<T> u1 = v[1] - v[6], u2 = v[2] - v[5], u3 = v[3] - v[4];
+    const cplx<T> a1 = {v[0].x + c1 * t1.x + c2 * t2.x + c3 * t3.x, v[0].y + c1 * t1.y + c2 * t2.y + c3 * t3.y};
+    const cplx<T> a2 = {v[0].x + c2 * t1.x + c3 * t2.x + c1 * t3.x, v[0].y + c2 * t1.y + c3 * t2.y + c1 * t3.y};
+    const cplx<T> a3 = {v[0].x + c3 * t1.x + c1 * t2.x + c2 * t3.x, v[0].y + c3 * t1.y + c1 * t2.y + c2 * t3.y};
+    const cplx<T> b1 = rot90<T, DIR>(cplx<T>{s1 * u1.x + s2 * u2.x + s3 * u3.x, s1 * u1.y + s2 * u2.y + s3 * u3.y});
+    const cplx<T> b2 = rot90<T, DIR>(cplx<T>{s2 * u1.x - s3 * u2.x - s1 * u3.x, s2 * u1.y - s3 * u2.y - s1 * u3.y});
+    const cplx<T> b3 = rot90<T, DIR>(cplx<T>{s3 * u1.x - s1 * u2.x + s2 * u3.x, s3 * u1.y - s1 * u2.y + s2 * u3.y});
+    v[0] = v[0] + t1 + t2 + t3;
+    v[1] = a1 + b1;
+    v[6] = a1 - b1;
+    v[2] = a2 + b2;
+    v[5] = a2 - b2;
+    v[3] = a3 + b3;
+    v[4] = a3 - b3;
+}
+
 template <typename T, int DIR>
 __device__ __forceinline__ void dft8(cplx<T>* v)
 {
@@ -130,6 +157,7 @@ __device__ __forceinline__ void dftR(cplx<T>* v)
     else if constexpr (R == 3) dft3<T, DIR>(v);
     else if constexpr (R == 4) dft4<T, DIR>(v);
     else if constexpr (R == 5) dft5<T, DIR>(v);
+    else if constexpr (R == 7) dft7<T, DIR>(v);
     else dft8<T, DIR>(v);
 }
 
@@ -201,6 +229,7 @@ __device__ cplx<T>* line_fft(cplx<T>* a, cplx<T>* b, const LinePlan& p, int W, i
             case 3: stockham_stage<T, DIR, 3, CONTIG>(a, b, p.n, Ns, W, sw, si, tw, tid, nthr); break;
             case 4: stockham_stage<T, DIR, 4, CONTIG>(a, b, p.n, Ns, W, sw, si, tw, tid, nthr); break;
             case 5: stockham_stage<T, DIR, 5, CONTIG>(a, b, p.n, Ns, W, sw, si, tw, tid, nthr); break;
+            case 7: stockham_stage<T, DIR, 7, CONTIG>(a, b, p.n, Ns, W, sw, si, tw, tid, nthr); break;
             default: stockham_stage<T, DIR, 8, CONTIG>(a, b, p.n, Ns, W, sw, si, tw, tid, nthr); break;
         }
         __syncthreads();

@@ -181,7 +181,7 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int L, int P, const Crew& cr
     crew_sync(cr);
 }
 
-// radix plan of a compile-time length: 8s first, then 4s, 2, 3, 5
+// radix plan of a compile-time length: 8s first, then 4s, 2, 3, 5, 7
 struct CPlan {
     int nst;
     int rad[12];
@@ -215,6 +215,10 @@ constexpr CPlan cplan(int n)
         r /= 5;
         p.rad[p.nst++] = 5;
     }
+    while (r % 7 == 0) {
+        r /= 7;
+        p.rad[p.nst++] = 7;
+    }
     return p;
 }
 
@@ -246,6 +250,7 @@ __device__ void fft_line(cplx<T>* buf, const LinePlan& p, int L, int P, const Cr
                 case 3: stage<T, DIR, 3, 0>(buf, L, P, cr, Ns, twl); break;
                 case 4: stage<T, DIR, 4, 0>(buf, L, P, cr, Ns, twl); break;
                 case 5: stage<T, DIR, 5, 0>(buf, L, P, cr, Ns, twl); break;
+                case 7: stage<T, DIR, 7, 0>(buf, L, P, cr, Ns, twl); break;
                 default: stage<T, DIR, 8, 0>(buf, L, P, cr, Ns, twl); break;
             }
             Ns *= R;

@@ -67,7 +67,7 @@ def _setup(lib, dim=3, n=(16, 16, 16), h=(0.1, 0.1, 0.1), support=(2.5, 2.5, 2.5
     (dict(degree=3), "degree"),
     (dict(kernel=7), "kernel"),
     (dict(flags=1), "flags"),
-    (dict(n=(14 * 7, 16, 16)), "factor"),
+    (dict(n=(11 * 8, 16, 16)), "factor"),
     (dict(n=(2, 16, 16)), "box size"),
     (dict(support=(0.5, 2.5, 2.5)), "support"),
     (dict(n=(8, 8, 8), support=(4.5, 2.5, 2.5)), "support too large"),

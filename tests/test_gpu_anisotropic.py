@@ -1,6 +1,6 @@
 """GPU parity on anisotropic grids: per-axis spacing h_k and normalised
-support a~_k (Eq 6, 64, 70), box sizes mixing radix 2, 3 and 5, in 2D and 3D
-with the linear and quadratic basis.  Coefficients, FP64 and FP32 operators
+support a~_k (Eq 6, 64, 70), box sizes mixing radix 2, 3, 5 and 7, in 1D, 2D
+and 3D with the linear and quadratic basis.  Coefficients, FP64 and FP32 operators
 and the FP64 solve against the oracle, at the bars of the isotropic cases."""
 import math
 
@@ -39,6 +39,10 @@ CASES = {
     "3d_quadratic_16x12x15": lambda: _box((16, 12, 15), (0.05, 0.07, 0.06), (2.5, 2.5, 2.25), 2, 82),
     "2d_quadratic_30x24": lambda: _box((30, 24), (0.03, 0.05), (2.5, 2.25), 2, 83),
     "2d_linear_40x25": lambda: _box((40, 25), (0.025, 0.04), (1.5, 2.5), 1, 84),
+    # radix-7 axes: 28 = 4 7, 21 = 3 7, 14 = 2 7, 49 = 7 7, 35 = 5 7
+    "3d_linear_28x21x14_radix7": lambda: _box((28, 21, 14), (0.04, 0.05, 0.07), (2.5, 2.0, 2.5), 1, 85),
+    "2d_quadratic_49x35_radix7": lambda: _box((49, 35), (0.02, 0.03), (2.5, 2.75), 2, 86),
+    "1d_linear_56_radix7": lambda: _box((56,), (0.018,), (2.5,), 1, 87),
 }
 
 
