@@ -122,7 +122,7 @@ typedef struct {
  *   mask     device: chi per node (Eq 40), 0/1 bytes (copied)
  *   kernel   FCRKPM_KERNEL_CUBIC_BSPLINE
  *   support  normalised support a~ per axis, a = a~ h (Eq 64); unused axes ignored
- *   degree   monomial degree n of the basis (Eq 4): 1 or 2
+ *   degree   monomial degree n of the basis (Eq 4): 1 or 2, or 3 in 1D and 2D
  *   stream   HIP stream (hipStream_t) the setup runs on
  *   out      receives the new context (NULL on failure)
  *

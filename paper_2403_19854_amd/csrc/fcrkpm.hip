@@ -1541,7 +1541,8 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         if (!grid || !mask || !support || !out) fail(FCRKPM_ERR_ARG, "NULL argument");
         if (kernel != FCRKPM_KERNEL_CUBIC_BSPLINE) fail(FCRKPM_ERR_ARG, "unknown kernel");
         if (grid->dim < 1 || grid->dim > 3) fail(FCRKPM_ERR_ARG, "dim must be 1, 2 or 3");
-        if (degree < 1 || degree > 2) fail(FCRKPM_ERR_ARG, "degree must be 1 or 2");
+        if (degree < 1 || degree > 3 || (degree == 3 && grid->dim == 3))
+            fail(FCRKPM_ERR_ARG, "degree must be 1 or 2, or 3 in 1D and 2D");
         if (grid->flags != 0) fail(FCRKPM_ERR_ARG, "flags must be 0");
         hipStream_t st = (hipStream_t)stream;
         h = new fcrkpm_ctx();

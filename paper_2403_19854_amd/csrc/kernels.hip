@@ -24,7 +24,9 @@ static unsigned ew_blocks(long n)
     else if (c.s == 3 && c.dim == 2) { constexpr int S_ = 3, DIM_ = 2; (void)DIM_; __VA_ARGS__; } \
     else if (c.s == 6 && c.dim == 2) { constexpr int S_ = 6, DIM_ = 2; (void)DIM_; __VA_ARGS__; } \
     else if (c.s == 4 && c.dim == 3) { constexpr int S_ = 4, DIM_ = 3; (void)DIM_; __VA_ARGS__; } \
-    else if (c.s == 10 && c.dim == 3) { constexpr int S_ = 10, DIM_ = 3; (void)DIM_; __VA_ARGS__; }
+    else if (c.s == 10 && c.dim == 3) { constexpr int S_ = 10, DIM_ = 3; (void)DIM_; __VA_ARGS__; } \
+    else if (c.s == 4 && c.dim == 1) { constexpr int S_ = 4, DIM_ = 1; (void)DIM_; __VA_ARGS__; }   \
+    else if (c.s == 10 && c.dim == 2) { constexpr int S_ = 10, DIM_ = 2; (void)DIM_; __VA_ARGS__; }
 
 // ============================================================ setup kernels
 

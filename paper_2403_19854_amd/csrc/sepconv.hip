@@ -912,6 +912,8 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
         else if (c.s == 6 && c.dim == 2) mid_dispatch<T, Tio, 6, 2>(m, ldm, stm, pw, sh, rb.n, st);
         else if (c.s == 4 && c.dim == 3) mid_dispatch<T, Tio, 4, 3>(m, ldm, stm, pw, sh, rb.n, st);
         else if (c.s == 10 && c.dim == 3) mid_dispatch<T, Tio, 10, 3>(m, ldm, stm, pw, sh, rb.n, st);
+        else if (c.s == 4 && c.dim == 1) mid_dispatch<T, Tio, 4, 1>(m, ldm, stm, pw, sh, rb.n, st);   // cubic, 1D
+        else if (c.s == 10 && c.dim == 2) mid_dispatch<T, Tio, 10, 2>(m, ldm, stm, pw, sh, rb.n, st);  // cubic, 2D
         else raise_unsupported("basis size and dimension without a middle pass");
         return;
     }
@@ -926,6 +928,8 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     else if (c.s == 4 && rows == 4) mid_dispatch<T, Tio, 4, 4, true>(m, ldm, stm, pw, sh, rb.n, st);
     else if (c.s == 10 && rows == 1) mid_dispatch<T, Tio, 10, 1, true>(m, ldm, stm, pw, sh, rb.n, st);
     else if (c.s == 10 && rows == 4) mid_dispatch<T, Tio, 10, 4, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 4 && rows == 2) mid_dispatch<T, Tio, 4, 2, true>(m, ldm, stm, pw, sh, rb.n, st);
+    else if (c.s == 10 && rows == 3) mid_dispatch<T, Tio, 10, 3, true>(m, ldm, stm, pw, sh, rb.n, st);
     else raise_unsupported("coefficient rows without a middle pass");
 }
 

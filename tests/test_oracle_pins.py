@@ -205,7 +205,8 @@ def _reproduction_check(p, tol):
 
 
 @pytest.mark.parametrize("dim,n,at,deg", [(1, 30, 2.5, 1), (1, 30, 3.0, 2), (2, 18, 2.5, 1),
-                                          (2, 18, 2.5, 2), (3, 12, 2.0, 1), (3, 12, 2.5, 2)])
+                                          (2, 18, 2.5, 2), (3, 12, 2.0, 1), (3, 12, 2.5, 2),
+                                          (1, 30, 3.5, 3), (2, 18, 3.5, 3)])
 def test_reproducing_conditions_cube(dim, n, at, deg):
     _reproduction_check(W.cube(dim, n, at, deg, source="zero"), 1e-10)
 
