@@ -66,8 +66,8 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
-              "the single-GPU path is the whole workload", file=sys.stderr)
+        print(f"bench.py: the FC-RKPM path runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the single-GPU run is the whole workload", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
