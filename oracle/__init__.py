@@ -74,6 +74,7 @@ def _load():
                  "orc_apply_vn", "orc_apply_b"):
         getattr(lib, name).argtypes = [P, dp, dp]
     lib.orc_apply_k_at.argtypes = [P, dp, lp, C.c_long, dp]
+    lib.orc_apply_btv.argtypes = [P, dp, dp]
     lib.orc_cg.restype = C.c_int
     lib.orc_cg.argtypes = [P, up, dp, dp, C.c_double, C.c_int, C.POINTER(C.c_double)]
     lib.orc_solve.restype = C.c_int
@@ -254,6 +255,18 @@ class Oracle:
         under nodal integration (Eq B.2, B.4): N^T (V o kappa (N d)^3)."""
         u = self.apply_uh(d)
         return self.apply_fr(kappa * u ** 3)
+
+    def apply_btv(self, g):
+        """B^T (V o g) for a field g of shape [dim, *shape] (Eq B.6)."""
+        out = np.empty(self.nn)
+        _load().orc_apply_btv(self._h, _f64(g).reshape(-1), out)
+        return out.reshape(self.shape)
+
+    def apply_fn_grad(self, d, kappa):
+        """Force of the gradient nonlinearity N(grad u) = (1 + kappa |grad u|^2)
+        grad u under nodal integration (Eq B.5-B.8): B^T (V o N(B d))."""
+        g = self.apply_b(d)
+        return self.apply_btv((1.0 + kappa * (g ** 2).sum(axis=0)) * g)
 
     def solve_nonlinear(self, free, dirichlet, r, kappa, g=None, tol=1e-13, newton_tol=1e-11,
                         maxnewton=50, maxit=100000):

@@ -341,6 +341,10 @@ static void apply_bt_v(const orc_ctx *c, const double *g, double *f)
     }
 }
 
+/* B^T (V o g) for a dim x nn field g (the force of a gradient nonlinearity,
+ * Eq B.6-B.8). */
+void orc_apply_btv(const orc_ctx *c, const double *g, double *f) { apply_bt_v(c, g, f); }
+
 /* Unmasked stiffness product f = K d over all domain nodes (Eq 26, Eq 54). */
 void orc_apply_k(const orc_ctx *c, const double *d, double *f)
 {

@@ -73,3 +73,23 @@ def test_manufactured_second_order(dim, ns):
             assert e2 > 20 * errs[0] and e3 > 20 * errs[0]
     assert errs[0] < 3e-3
     assert errs[0] / errs[1] > 3.5
+
+
+def test_gradient_force_reduces_to_k_and_scales_linear_fields():
+    # N(g) = (1 + kappa |g|^2) g: kappa = 0 gives K d; for d the nodal values of
+    # a linear field the implicit gradient is its constant gradient c, so the
+    # force is (1 + kappa |c|^2) K d
+    p = W.cube(2, 16, 2.5, 1)
+    o = make(p)
+    d = np.where(p.chi > 0, np.random.default_rng(4).standard_normal(p.shape), 0.0)
+    np.testing.assert_allclose(o.apply_fn_grad(d, 0.0), o.apply_k(d), atol=1e-13 * np.abs(o.apply_k(d)).max())
+    X = W._mesh(p.coords)
+    c = (0.7, -1.3)
+    lin = np.where(p.chi > 0, 2.0 + c[0] * X[0] + c[1] * X[1], 0.0)
+    kappa = 0.8
+    ref = (1.0 + kappa * (c[0] ** 2 + c[1] ** 2)) * o.apply_k(lin)
+    np.testing.assert_allclose(o.apply_fn_grad(lin, kappa), ref, atol=1e-10 * np.abs(ref).max())
+    # and the cubic term enters with the third power: doubling d scales it by 8
+    f1 = o.apply_fn_grad(d, kappa) - o.apply_k(d)
+    f2 = o.apply_fn_grad(2.0 * d, kappa) - o.apply_k(2.0 * d)
+    np.testing.assert_allclose(f2, 8.0 * f1, atol=1e-12 * np.abs(f2).max())
