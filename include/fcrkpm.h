@@ -225,6 +225,18 @@ fcrkpm_status fcrkpm_nonlinear_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs
                                      double* out, void* stream);
 
 /*
+ * fcrkpm_gradient_force -- f^N = B^T (V o N(B d)) with the gradient
+ * nonlinearity N(g) = (1 + kappa |g|^2) g (App. B, Eq B.5-B.8, B.10; Alg B.1):
+ * the passes of K with N applied to the implicit gradient at every node, so
+ * kappa = 0 gives K d (domain mask in and out), FP64, asynchronous on `stream`;
+ * d and out hold nrhs fields and must not overlap.
+ * Errors: FCRKPM_ERR_ARG (NULL or overlapping arrays, nrhs, non-finite kappa),
+ * FCRKPM_ERR_HIP.
+ */
+fcrkpm_status fcrkpm_gradient_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs, const double* d,
+                                    double* out, void* stream);
+
+/*
  * fcrkpm_solve_nonlinear -- static solve of -lap u + kappa u^3 = r with d = g on
  * the Dirichlet nodes (Eq 8-9 with the term of Eq B.1; App. B.3): Newton's
  * method on R(d) = K d + f^N(d) - f^r over the free rows from d_inout, every

@@ -580,8 +580,12 @@ OpSet* shift_set(Ctx& c, double cm, double ck, hipStream_t st)
     return c.shift_set;
 }
 
+// internal operator: the passes of K_FULL with the gradient nonlinearity of
+// c.pw_kappa between the two halves (Alg B.1 with N(g) = (1 + kappa |g|^2) g)
+constexpr int OP_KN = 100;
+
 // One operator on nrhs consecutive fields, arithmetic precision T, field type
-// Tio (Alg 2, 3, 4, C.1); every pass covers all fields in one launch.
+// Tio (Alg 2, 3, 4, C.1, B.1); every pass covers all fields in one launch.
 template <typename T, typename Tio = T>
 void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st)
 {
@@ -596,10 +600,12 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
     const double outb2 = (k == 1) ? sizeof(Tio) + 1.0 : pair_bytes<T>(k >= 2 ? sp.size[k - 2] : 1);
     switch (op) {
         case FCRKPM_OP_K:
-        case FCRKPM_OP_K_FULL: {
+        case FCRKPM_OP_K_FULL:
+        case OP_KN: {
             const uint8_t* mk = (op == FCRKPM_OP_K) ? c.freem : c.chi;
+            const int pwk = (op == OP_KN) ? SEP_PW_KN : SEP_PW_K;
             if constexpr (std::is_same_v<T, float> && std::is_same_v<Tio, float>) {
-                if (use_reg_path(c, nrhs)) {
+                if (op != OP_KN && use_reg_path(c, nrhs)) {
                     reg_k(c, in, out, mk, nrhs, st);
                     break;
                 }
@@ -612,11 +618,11 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
                                           : nn * (c.krows * c.s + 1) * rt;
                 ProfScope ps(c, kind_of<T>(KD_MID_K), nn * (inb1 + outb2) + coef, st);
                 if (k == 1)
-                    launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], SEP_PW_K, SEP_LD_REAL, in, mk,
+                    launch_sep_mid<T, Tio>(c, last, sp.p1[0], sp.d1[0], sp.p2[0], sp.d2[0], pwk, SEP_LD_REAL, in, mk,
                                            SEP_ST_REAL, out, mk, nullptr, b0_of<T>(c), ba_of<T>(c),
                                            vol_of<T>(c), nullptr, nullptr, st, RhsBatch{nrhs, rrs, rrs, 0});
                 else
-                    launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], SEP_PW_K, SEP_LD_PAIRS,
+                    launch_sep_mid<T, Tio>(c, last, sp.p1[k - 1], sp.d1[k - 1], sp.p2[k - 1], sp.d2[k - 1], pwk, SEP_LD_PAIRS,
                                            cur, nullptr, SEP_ST_PAIRS, dst, nullptr, nullptr,
                                            b0_of<T>(c), ba_of<T>(c), vol_of<T>(c), nullptr, nullptr,
                                            st, RhsBatch{nrhs, prs, prs, 0});
@@ -2154,6 +2160,28 @@ extern "C" fcrkpm_status fcrkpm_nonlinear_force(fcrkpm_ctx* ctx, double kappa, i
         apply_one<double>(c, FCRKPM_OP_UH, d, u, nrhs, st);
         launch_pow_scaled(u, kappa, 3, u, c.nn * nrhs, st);
         apply_one<double>(c, FCRKPM_OP_FR, u, out, nrhs, st);
+        HIPCHK(hipGetLastError());
+        return FCRKPM_OK;
+    });
+}
+
+// Force of the gradient nonlinearity N(grad u) = (1 + kappa |grad u|^2) grad u
+// (App. B, Eq B.5-B.8, B.10; Alg B.1): the passes of K with the nonlinearity
+// applied to the implicit gradient A^a = sum_q b^a_q D_q before E_p is formed.
+extern "C" fcrkpm_status fcrkpm_gradient_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs,
+                                               const double* d, double* out, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (!d || !out) fail(FCRKPM_ERR_ARG, "NULL array");
+        if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
+        if (!std::isfinite(kappa)) fail(FCRKPM_ERR_ARG, "kappa must be finite");
+        const size_t bytes = sizeof(double) * (size_t)c.nn * nrhs;
+        if ((const char*)d < (const char*)out + bytes && (const char*)out < (const char*)d + bytes)
+            fail(FCRKPM_ERR_ARG, "d and out overlap");
+        c.pw_kappa = kappa;
+        apply_one<double>(c, OP_KN, d, out, nrhs, (hipStream_t)stream);
         HIPCHK(hipGetLastError());
         return FCRKPM_OK;
     });

@@ -122,6 +122,7 @@ struct Ctx {
     OpSet* mass_set = nullptr;          // consistent mass (built on first use)
     OpSet* shift_set = nullptr;         // c_m M + c_k K of the last implicit time step
     double shift_w[2] = {0.0, 0.0};     // its (c_m, c_k)
+    double pw_kappa = 0.0;              // kappa of the gradient nonlinearity (SEP_PW_KN middle passes)
     OpSet* jac_set = nullptr;           // K + N^T diag(w V) N of the last Newton step
     bool use_regpath = true;            // register-resident passes where they apply
     uint8_t* cls = nullptr;             // node class: 0 outside the domain, 1 interior, 2 other
@@ -180,7 +181,7 @@ struct RhsBatch {
 // separable passes (sepconv.hip); load/store and pointwise modes:
 enum { SEP_LD_PAIRS = 0, SEP_LD_REAL = 1, SEP_LD_CHI = 2 };
 enum { SEP_ST_PAIRS = 0, SEP_ST_REAL = 1 };
-enum { SEP_PW_K = 0, SEP_PW_UH = 1, SEP_PW_LOAD = 2 };
+enum { SEP_PW_K = 0, SEP_PW_UH = 1, SEP_PW_LOAD = 2, SEP_PW_KN = 3 };  // KN: K with A scaled by 1 + kappa |A|^2
 
 template <typename T, typename Tio>
 void launch_sep_pass(const Ctx& c, int a, const SepProg& pr, const SepProg* dpr, int ldm,

@@ -497,12 +497,13 @@ struct MidArgs {
     const T* vol;             // [nn] or NULL
     const uint8_t* cls;       // PW_K: node class (0 outside, 1 interior, 2 other) or NULL
     T cint[kMaxNodeConst + 1];  // PW_K: b^a (a-major) and V of the interior nodes
+    T kappa;                  // PW_KN: A^a -> (1 + kappa |A|^2) A^a
     const void* src;          // PW_LOAD: the real field r (Tio)
     long nn;
     long src_rb;              // bytes between right-hand sides of src
 };
 
-enum { PW_K = SEP_PW_K, PW_UH = SEP_PW_UH, PW_LOAD = SEP_PW_LOAD };
+enum { PW_K = SEP_PW_K, PW_UH = SEP_PW_UH, PW_LOAD = SEP_PW_LOAD, PW_KN = SEP_PW_KN };
 
 template <typename T, typename Tio, bool CONTIG, int LDM, int STM, int S, int DIM, int PW, int LC>
 __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
         }
         return;
     } else {
-        if constexpr (PW == PW_K) {
+        if constexpr (PW == PW_K || PW == PW_KN) {
             // A^a = sum_q b^a_q D_q ; E_p = V sum_a b^a_p A^a   (Eq 90-91, Alg 2).
             // Interior nodes take the shared b^a and V (kernel argument) and
             // nodes outside the domain V = 0; only the others read the arrays.
@@ -624,6 +625,15 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
 #pragma unroll
                     for (int q = 0; q < S; ++q) acc += b[al][q] * D[q];
                     A[al] = acc;
+                }
+                if constexpr (PW == PW_KN) {
+                    // gradient nonlinearity N(A) = (1 + kappa |A|^2) A (Eq B.8, B.10)
+                    T s2 = T(0);
+#pragma unroll
+                    for (int al = 0; al < DIM; ++al) s2 += A[al] * A[al];
+                    const T f = T(1) + m.kappa * s2;
+#pragma unroll
+                    for (int al = 0; al < DIM; ++al) A[al] *= f;
                 }
                 const T v = vv[kk];
                 T Ep[NP * 2];
@@ -853,6 +863,13 @@ static void mid_dispatch(const MidArgs<T>& m, int ldm, int stm, int pw, size_t s
         if (pw != PW_K) raise_unsupported("internal: pointwise mode without its instantiation");
         if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
         else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
+    } else if (pw == PW_KN) {
+        if constexpr (std::is_same<T, double>::value && std::is_same<Tio, double>::value) {
+            if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_KN); else FC_MID(false, LD_REAL, ST_REAL, PW_KN); }
+            else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_KN); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_KN); }
+        } else {
+            raise_unsupported("the gradient nonlinearity runs in FP64 only");
+        }
     } else if (pw == PW_K) {
         if (ldm == LD_REAL && stm == ST_REAL) { if (ct) FC_MID(true, LD_REAL, ST_REAL, PW_K); else FC_MID(false, LD_REAL, ST_REAL, PW_K); }
         else { if (ct) FC_MID(true, LD_PAIRS, ST_PAIRS, PW_K); else FC_MID(false, LD_PAIRS, ST_PAIRS, PW_K); }
@@ -897,6 +914,7 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.ba = ba;
     m.vol = vol;
     m.cls = c.cls;
+    m.kappa = (T)c.pw_kappa;
     for (int q = 0; q <= kMaxNodeConst; ++q) {
         if constexpr (std::is_same<T, double>::value) m.cint[q] = c.cint64[q];
         else m.cint[q] = c.cint32[q];
@@ -904,7 +922,7 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
     m.src = src;
     m.nn = c.nn;
     const size_t sh = (size_t)(m.s.ne + 1) * m.s.g.L * sizeof(cplx<T>) + nbuf * buf_bytes(m.s.g, sizeof(cplx<T>));
-    const int rows = (pw == PW_K) ? c.krows : c.dim;
+    const int rows = (pw == PW_K || pw == PW_KN) ? c.krows : c.dim;
     if (rows == c.dim) {
         if (c.s == 2 && c.dim == 1) mid_dispatch<T, Tio, 2, 1>(m, ldm, stm, pw, sh, rb.n, st);
         else if (c.s == 3 && c.dim == 1) mid_dispatch<T, Tio, 3, 1>(m, ldm, stm, pw, sh, rb.n, st);

@@ -38,7 +38,8 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_profile", "fcrkpm_profile_read", "fcrkpm_kernel_kinds",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
            "fcrkpm_get_option", "fcrkpm_transient", "fcrkpm_set_boundary",
-           "fcrkpm_solve_flux", "fcrkpm_nonlinear_force", "fcrkpm_solve_nonlinear")
+           "fcrkpm_solve_flux", "fcrkpm_nonlinear_force", "fcrkpm_solve_nonlinear",
+           "fcrkpm_gradient_force")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -121,6 +122,8 @@ def load_library(path: str = LIB_PATH):
                                       C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_nonlinear_force.restype = C.c_int
     lib.fcrkpm_nonlinear_force.argtypes = [V, C.c_double, C.c_int32, V, V, V]
+    lib.fcrkpm_gradient_force.restype = C.c_int
+    lib.fcrkpm_gradient_force.argtypes = [V, C.c_double, C.c_int32, V, V, V]
     lib.fcrkpm_solve_nonlinear.restype = C.c_int
     lib.fcrkpm_solve_nonlinear.argtypes = [V, C.c_int32, C.c_double, V, V, V, V, C.c_double,
                                            C.c_double, C.c_int32, C.c_int32, C.POINTER(Info), V]
@@ -337,6 +340,18 @@ class Problem:
             out = torch.empty_like(d)
         self._check(load_library().fcrkpm_nonlinear_force(self._h, float(kappa), nrhs, _ptr(d),
                                                           _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def gradient_force(self, d, kappa, out=None, stream=None):
+        """f^N = B^T (V o (1 + kappa |B d|^2) B d) for one or more fields d (FP64)."""
+        d = _dev(d, torch.float64, self.device)
+        nrhs = d.numel() // self.nn
+        if nrhs < 1 or nrhs * self.nn != d.numel():
+            raise ValueError("d does not hold whole fields")
+        if out is None:
+            out = torch.empty_like(d)
+        self._check(load_library().fcrkpm_gradient_force(self._h, float(kappa), nrhs, _ptr(d),
+                                                         _ptr(out), _stream_ptr(stream)))
         return out
 
     def solve_nonlinear(self, r, kappa, g=None, d0=None, mode="f64", tol=1e-12,
