@@ -149,9 +149,16 @@ fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* mask, int32_t
  *   nrhs    number of fields; field j starts at j * (nodes) in `in` and `out`
  *   in,out  device arrays; must not overlap
  *
- * K uses 2(s+1) 3D transforms per field (Alg 2); FR, UH, NT, VN use s+1
- * (Alg 3, Alg 4).  Errors: FCRKPM_ERR_ARG (bad op/dtype/nrhs, NULL or
- * overlapping pointers), FCRKPM_ERR_HIP.
+ * The kernel is a tensor product (Eq 6), so every 3D spectral product of
+ * Alg 2-4 is separable: instead of the paper's 3D transforms (2(s+1) per
+ * field for K, s+1 for FR, UH, NT, VN) each operator runs as line passes.  In
+ * 3D: part-1 passes along x and y (d -> its x-convolutions -> their
+ * y-convolutions), one middle pass along z (the part-1 z-convolutions, the
+ * pointwise stage and the part-2 z-convolutions, without leaving the chip),
+ * then part-2 passes along y and x.  FR and NT start at the middle pass, UH
+ * ends in it; 1D and 2D drop the absent axes.  The results equal the 3D
+ * transforms' (circular convolutions either way).  Errors: FCRKPM_ERR_ARG
+ * (bad op/dtype/nrhs, NULL or overlapping pointers), FCRKPM_ERR_HIP.
  */
 fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t nrhs,
                            const void* in, void* out, void* stream);
@@ -180,6 +187,18 @@ fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t n
  *
  * Blocks of 8 CG iterations are captured once into a HIP graph and replayed
  * (see FCRKPM_OPT_GRAPHS); the host polls convergence between blocks.
+ *
+ * Acceptance.  FCRKPM_MODE_F64 converges when the recursive residual reaches
+ * tol.  The refined modes converge on the FP64 true residual ||b - K d|| /
+ * ||b||: when it reaches tol, or when it has stopped improving (three
+ * replacements in a row above half of its best) with its best within 4 tol,
+ * which is then taken as the attainable accuracy (d is the best iterate).
+ * A stall above 4 tol, a breakdown or divergence of the FP32 recursion hands
+ * the right-hand side to FP64 CG from its best iterate.  At the end the true
+ * residual is recomputed; a refined solve whose final true residual exceeds
+ * 100 tol reports FCRKPM_ERR_NOCONV even if its last phase converged.
+ * info.true_rel_res always holds that final value.
+ *
  * Returns FCRKPM_ERR_NOCONV with the best d written when maxit is reached or
  * CG breaks down (p^T K p <= 0) for any right-hand side; FCRKPM_ERR_ARG for
  * NaN/Inf in r, g or the initial guess, or bad arguments.
@@ -366,9 +385,12 @@ const char* fcrkpm_kernel_name(int32_t kind);
 enum {
     FCRKPM_OPT_GRAPHS = 1,  /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
                                launches.  Graphs are never used while profiling is on. */
-    FCRKPM_OPT_REGPATH = 2,  /* 1 (default): FP32 K products on 64^3 and 128^3 boxes with the
-                                linear basis use register-resident line transforms; 0: the
-                                LDS-tiled passes used everywhere else */
+    FCRKPM_OPT_REGPATH = 2,  /* 1 (default): FP32 K-type products (K, the consistent mass and
+                                the shifted and Jacobian operators built from them) on 3D
+                                boxes whose axes are 64 or 128 nodes long use
+                                register-resident line transforms: linear basis for every
+                                such product, quadratic basis for K itself; 0: the LDS-tiled
+                                passes used everywhere else */
     FCRKPM_OPT_REGLAYOUT = 3, /* variant of those transforms, layout + 2 (tiles - 1): layout 0 =
                                  8 lanes per line, 1 = 16 lanes (128-point lines only); tiles =
                                  1 or 2 tiles per workgroup (the second tile's loads overlap the

@@ -183,6 +183,22 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_out(out, like):
+    """A caller-supplied output goes to the library as a raw pointer, so it must
+    match the input exactly: dtype, device, contiguity and element count."""
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a torch tensor")
+    if out.dtype != like.dtype:
+        raise ValueError(f"out has dtype {out.dtype}, expected {like.dtype}")
+    if out.device != like.device:
+        raise ValueError(f"out is on {out.device}, expected {like.device}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    if out.numel() != like.numel():
+        raise ValueError(f"out holds {out.numel()} values, expected {like.numel()}")
+    return out
+
+
 class Problem:
     """One FC-RKPM context: a box grid, a domain and its RK coefficients.
 
@@ -256,6 +272,8 @@ class Problem:
             raise ValueError("x does not hold whole fields")
         if out is None:
             out = torch.empty_like(x)
+        else:
+            _check_out(out, x)
         self._check(load_library().fcrkpm_apply(
             self._h, opc, F64 if x.dtype == torch.float64 else F32, nrhs, _ptr(x), _ptr(out),
             _stream_ptr(stream)))
@@ -298,6 +316,8 @@ class Problem:
         """dL/dr for a loss of u^h; returns (dL/dr, info dict)."""
         y = _dev(dl_duh, torch.float64, self.device)
         nrhs = y.numel() // self.nn
+        if nrhs < 1 or nrhs * self.nn != y.numel():
+            raise ValueError("dl_duh does not hold whole fields")
         g = torch.empty_like(y)
         infos = (Info * nrhs)()
         self._check(load_library().fcrkpm_adjoint(self._h, _MODES[mode], nrhs, _ptr(y), _ptr(g),
@@ -338,6 +358,8 @@ class Problem:
             raise ValueError("d does not hold whole fields")
         if out is None:
             out = torch.empty_like(d)
+        else:
+            _check_out(out, d)
         self._check(load_library().fcrkpm_nonlinear_force(self._h, float(kappa), nrhs, _ptr(d),
                                                           _ptr(out), _stream_ptr(stream)))
         return out
@@ -350,6 +372,8 @@ class Problem:
             raise ValueError("d does not hold whole fields")
         if out is None:
             out = torch.empty_like(d)
+        else:
+            _check_out(out, d)
         self._check(load_library().fcrkpm_gradient_force(self._h, float(kappa), nrhs, _ptr(d),
                                                          _ptr(out), _stream_ptr(stream)))
         return out

@@ -411,3 +411,56 @@ def test_oracle_dense_brute_force_1d():
     np.testing.assert_allclose(o.apply_k(d), K @ d, atol=1e-12 * np.abs(K @ d).max())
     np.testing.assert_allclose(o.apply_uh(d), Psi @ d, atol=1e-13)
     np.testing.assert_allclose(o.apply_fr(p.r), Psi.T @ (p.vol * p.r), atol=1e-13)
+
+
+# --- the sampled product (K d)_I against the whole-field product ---------------------
+
+@pytest.mark.parametrize("maker", [lambda: W.cube(3, 12, 2.5, 1), lambda: W.sphere(16, 0.4, 3.0, 2),
+                                   lambda: W.cube(1, 30, 2.5, 1)],
+                         ids=["cube12_linear", "ball16_quadratic", "line30"])
+def test_apply_k_at_matches_apply_k(maker):
+    # apply_k_at recomputes the implicit gradients around each requested node
+    # (Eq 26 with nodal integration, Eq 54) instead of sweeping the field; it is
+    # the reference of the sampled full-size checks, so it must agree with the
+    # pinned whole-field product at every node, boundary nodes included
+    p = maker()
+    o = make(p)
+    d = np.where(p.chi > 0, np.random.default_rng(11).standard_normal(p.shape), 0.0)
+    full = o.apply_k(d).reshape(-1)
+    idx = np.arange(p.nn)
+    at = o.apply_k_at(d, idx)
+    np.testing.assert_allclose(at, full, rtol=0, atol=1e-14 * np.abs(full).max())
+    # outside the domain both give 0
+    assert np.all(at[p.chi.reshape(-1) == 0] == 0.0)
+
+
+# --- conditioning of the quadratic ball with support 3.0h (config 3's operator) ------
+
+def _dense_k_free(p, o):
+    idx = np.flatnonzero(p.free)
+    K = np.empty((idx.size, idx.size))
+    for j, J in enumerate(idx):
+        e = np.zeros(p.nn)
+        e[J] = 1.0
+        K[:, j] = o.apply_k(e).reshape(-1)[idx]
+    return K, idx
+
+
+@pytest.mark.slow
+def test_ball_support_3_condition_number():
+    # the config-3 operator (quadratic basis, support 3.0h, ball of radius 0.4)
+    # on a 16^3 box: 691 free nodes.  Its K_ff is symmetric positive definite,
+    # with a condition number in the millions (3.56e6), 60x that of support
+    # 2.5h on the same ball (5.7e4): nodal integration leaves near-null modes
+    # that the wider support couples more weakly (Sec 3, the zero-energy issue)
+    kap = {}
+    for at in (3.0, 2.5):
+        p = W.sphere(16, 0.4, at, 2)
+        K, idx = _dense_k_free(p, make(p))
+        assert idx.size == 691
+        np.testing.assert_allclose(K, K.T, atol=1e-13 * np.abs(K).max())
+        ev = np.linalg.eigvalsh(0.5 * (K + K.T))
+        assert ev[0] > 0
+        kap[at] = ev[-1] / ev[0]
+    assert 2e6 < kap[3.0] < 6e6
+    assert 3e4 < kap[2.5] < 1e5
