@@ -164,6 +164,31 @@ fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t n
                            const void* in, void* out, void* stream);
 
 /*
+ * fcrkpm_apply_noalloc -- fcrkpm_apply for callers that cannot allocate device
+ * memory (work under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same operators, arguments, results and errors, but
+ * the passes keep their intermediate fields in a static scratch array of
+ * 64 MiB that every GPU the library runs on holds until the process ends,
+ * instead of the context's workspace.  The call allocates nothing.
+ *
+ * Scratch need: 2 x (pair fields of the widest intermediate set) x nodes x
+ * nrhs complex values, 8 bytes each in FP32 and 16 in FP64 -- for the linear
+ * basis in 3D, 32 bytes (FP32) or 64 bytes (FP64) per node and right-hand
+ * side: a 128^3 box fits in FP32 with one right-hand side, a 96^3 box in FP64
+ * with one.  A larger request returns FCRKPM_ERR_ARG (the message gives the
+ * need and the limit) before any work is enqueued.  FCRKPM_OP_M needs its
+ * coefficients built by one earlier fcrkpm_apply(FCRKPM_OP_M) call
+ * (FCRKPM_ERR_ARG otherwise).
+ *
+ * All calls on one GPU share its scratch array: calls that overlap in time on
+ * one GPU (different streams, threads or contexts) race and give wrong
+ * results; serialise them.  No value of the scratch survives into a result of
+ * a later call (every pass writes what it reads within the call).
+ */
+fcrkpm_status fcrkpm_apply_noalloc(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t nrhs,
+                                   const void* in, void* out, void* stream);
+
+/*
  * fcrkpm_solve -- static strong-Dirichlet solve (Sec 2.4, Eq 29; Sec 5.4.3,
  * Alg 5): d = g on Dirichlet nodes, f^r from r (Alg 4), right-hand side
  * b = chi_Omega o (f^r - K d_Gamma), CG on the free nodes (Eq 96) until

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <utility>
@@ -48,6 +49,35 @@ struct ArgFail {
 };
 
 [[noreturn]] void fail(fcrkpm_status st, const std::string& msg) { throw ArgFail{st, msg}; }
+
+// ------------------------------------------------- scratch of the allocation-free apply
+// fcrkpm_apply_noalloc runs the passes of fcrkpm_apply with their workspace in
+// this array instead of the context's.  Each GPU holds its own copy at its own
+// address until the process ends; every call on one GPU shares it, so calls
+// that overlap in time on one GPU race.  In host code `scratch` is a host-side
+// stand-in: its device address comes from hipGetSymbolAddress, taken once per
+// device by the setup call and kept per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch array
+void* scratch_address()
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(FCRKPM_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
 
 // ------------------------------------------------------ kernel-duration sampler
 // For each kernel kind, HIP events time the first kProfCap launches after
@@ -1586,6 +1616,9 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         for (int a = 0; a < c.dim; ++a) c.axes[c.naxes++] = a;
         const long nn = c.nn;
 
+        // the static scratch of fcrkpm_apply_noalloc on this device
+        c.scratch = scratch_address();
+
         // masks and volumes
         c.chi = dalloc<uint8_t>(nn);
         c.freem = dalloc<uint8_t>(nn);
@@ -1855,6 +1888,64 @@ extern "C" fcrkpm_status fcrkpm_apply(fcrkpm_ctx* ctx, int32_t op, int32_t dtype
         const char* b0 = (const char*)out;
         const size_t bytes = es * (size_t)c.nn * nrhs;
         if (a0 < b0 + bytes && b0 < a0 + bytes) fail(FCRKPM_ERR_ARG, "in and out overlap");
+        hipStream_t st = (hipStream_t)stream;
+        if (dtype == FCRKPM_F64)
+            apply_one<double>(c, op, (const double*)in, (double*)out, nrhs, st);
+        else
+            apply_one<float>(c, op, (const float*)in, (float*)out, nrhs, st);
+        HIPCHK(hipGetLastError());
+        return FCRKPM_OK;
+    });
+}
+
+extern "C" fcrkpm_status fcrkpm_apply_noalloc(fcrkpm_ctx* ctx, int32_t op, int32_t dtype, int32_t nrhs,
+                                              const void* in, void* out, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (op < FCRKPM_OP_K || op > FCRKPM_OP_FQ) fail(FCRKPM_ERR_ARG, "unknown operator");
+        if (dtype != FCRKPM_F64 && dtype != FCRKPM_F32) fail(FCRKPM_ERR_ARG, "unknown dtype");
+        if (nrhs < 1 || nrhs > 65535) fail(FCRKPM_ERR_ARG, "nrhs must be in [1, 65535]");
+        if (!in || !out) fail(FCRKPM_ERR_ARG, "NULL array");
+        // the first FCRKPM_OP_M product builds the mass coefficients, which allocates
+        if (op == FCRKPM_OP_M && !c.mass_set)
+            fail(FCRKPM_ERR_ARG, "the consistent mass is not built yet: call fcrkpm_apply with "
+                                 "FCRKPM_OP_M once first");
+        if (!c.scratch) fail(FCRKPM_ERR_ARG, "context has no scratch address");
+        const size_t es = dtype == FCRKPM_F64 ? 8 : 4;
+        const char* a0 = (const char*)in;
+        const char* b0 = (const char*)out;
+        const size_t bytes = es * (size_t)c.nn * nrhs;
+        if (a0 < b0 + bytes && b0 < a0 + bytes) fail(FCRKPM_ERR_ARG, "in and out overlap");
+        // two workspace slots of maxpairs complex fields per right-hand side
+        const size_t need = (size_t)2 * c.basis_plan.maxpairs * c.nn * nrhs * (2 * es);
+        if (need > kScratchBytes)
+            fail(FCRKPM_ERR_ARG, "the product needs " + std::to_string(need) +
+                                     " bytes of scratch; the static scratch holds " +
+                                     std::to_string(kScratchBytes));
+        // the passes take their workspace from the context: point it at the
+        // scratch for this call (no kernel reads a workspace value it has not
+        // written in the same call, so nothing needs clearing) and put the
+        // context's own workspace back afterwards
+        struct WorkSwap {
+            Ctx& c;
+            cplx<float>* w32;
+            cplx<double>* w64;
+            int cap;
+            WorkSwap(Ctx& c_, int nrhs) : c(c_), w32(c_.work32), w64(c_.work64), cap(c_.cap_work)
+            {
+                c.work32 = reinterpret_cast<cplx<float>*>(c.scratch);
+                c.work64 = reinterpret_cast<cplx<double>*>(c.scratch);
+                c.cap_work = nrhs;
+            }
+            ~WorkSwap()
+            {
+                c.work32 = w32;
+                c.work64 = w64;
+                c.cap_work = cap;
+            }
+        } swap(c, nrhs);
         hipStream_t st = (hipStream_t)stream;
         if (dtype == FCRKPM_F64)
             apply_one<double>(c, op, (const double*)in, (double*)out, nrhs, st);

@@ -164,6 +164,8 @@ struct Ctx {
     SepPlan basis_plan;                 // basis monomials (Alg 2-4)
     SepProg* dprog = nullptr;           // device copies of the pass programs
     int lds_budget = 65536;             // LDS bytes one workgroup may use
+    void* scratch = nullptr;            // device address of this device's static scratch array
+                                        // (fcrkpm_apply_noalloc), taken at setup
 };
 
 constexpr int kRedBlocks = 1024;   // reduction partials per right-hand side (at most)

@@ -39,7 +39,7 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
            "fcrkpm_get_option", "fcrkpm_transient", "fcrkpm_set_boundary",
            "fcrkpm_solve_flux", "fcrkpm_nonlinear_force", "fcrkpm_solve_nonlinear",
-           "fcrkpm_gradient_force")
+           "fcrkpm_gradient_force", "fcrkpm_apply_noalloc")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
                                  V, C.POINTER(V)]
     lib.fcrkpm_apply.restype = C.c_int
     lib.fcrkpm_apply.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, V, V, V]
+    lib.fcrkpm_apply_noalloc.restype = C.c_int
+    lib.fcrkpm_apply_noalloc.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, V, V, V]
     lib.fcrkpm_solve.restype = C.c_int
     lib.fcrkpm_solve.argtypes = [V, C.c_int32, C.c_int32, V, V, V, V, C.c_double, C.c_int32,
                                  C.POINTER(Info), V]
@@ -275,6 +277,25 @@ class Problem:
         else:
             _check_out(out, x)
         self._check(load_library().fcrkpm_apply(
+            self._h, opc, F64 if x.dtype == torch.float64 else F32, nrhs, _ptr(x), _ptr(out),
+            _stream_ptr(stream)))
+        return out
+
+    def apply_noalloc(self, op, x, out, stream=None):
+        """apply() for callers that cannot allocate: the library keeps the
+        intermediate fields in its static per-GPU scratch (64 MiB) and
+        allocates nothing.  `out` must be given (same dtype, device and size as
+        x); calls that overlap in time on one GPU race."""
+        opc = _OPS[op] if isinstance(op, str) else int(op)
+        if x.dtype not in (torch.float64, torch.float32):
+            raise TypeError("x must be float64 or float32")
+        if x.device != self.device or not x.is_contiguous():
+            raise ValueError("x must be a contiguous tensor on the problem's device")
+        nrhs = x.numel() // self.nn
+        if nrhs * self.nn != x.numel() or nrhs < 1:
+            raise ValueError("x does not hold whole fields")
+        _check_out(out, x)
+        self._check(load_library().fcrkpm_apply_noalloc(
             self._h, opc, F64 if x.dtype == torch.float64 else F32, nrhs, _ptr(x), _ptr(out),
             _stream_ptr(stream)))
         return out
