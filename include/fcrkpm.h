@@ -424,7 +424,15 @@ enum {
     FCRKPM_OPT_TUNE_NS0 = 4, /* read only: setup's time of one K product with variant 0, ns */
     FCRKPM_OPT_TUNE_NS1 = 5, /* read only: the same with variant 1 (0 where not timed) */
     FCRKPM_OPT_TUNE_NS2 = 6, /* read only: the same with variant 2 */
-    FCRKPM_OPT_TUNE_NS3 = 7  /* read only: the same with variant 3 */
+    FCRKPM_OPT_TUNE_NS3 = 7, /* read only: the same with variant 3 */
+    FCRKPM_OPT_LINECONST = 8 /* 1 (default): where every z line of the box has a constant
+                                pointwise matrix V B^T B away from the few nodes near the ends
+                                of the domain's z extent (cube-like domains, linear basis, K),
+                                the register path's middle pass applies that constant in the
+                                spectral domain and corrects the end nodes directly (the same
+                                sums as Alg 2, regrouped); 0: the middle pass with a pointwise
+                                stage at every node.  Reads 1 only where setup found the
+                                structure. */
 };
 /* Set an option; FCRKPM_ERR_ARG for an unknown option or a value out of range. */
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);

@@ -170,6 +170,7 @@ void free_set(OpSet*& s)
 
 void release(Ctx& c)
 {
+    sym_release(c);
     free_set(c.mass_set);
     free_set(c.shift_set);
     free_set(c.jac_set);
@@ -495,6 +496,7 @@ double reg_pass_bytes(const Ctx& c, int k)
         case 0: return nn * (4 + 1 + p0 * 4 + (c.prof_pupd ? 4 + 4 : 0));
         case 1: return nn * (p0 * 4 + p1 * 4);
         case 2: {
+            if (sym_active(c)) return sym_pass_bytes(c);
             const double words = (double)reg_bits_words(c, c.reg_layout);
             return nn * (p1 * 4 + p1 * 4) + 12.0 * words +
                    (double)c.nload[c.reg_layout] * reg_record_floats(c) * 4;
@@ -1792,6 +1794,8 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
 
         c.krows = c.dim;
         build_pointwise(c, st);
+        if (const char* e = getenv("FCRKPM_SYM")) c.use_sym = *e != '0';
+        sym_build(c, st);
 
         // workspace and solver buffers for one right-hand side; both grow on demand
         HIPCHK(hipStreamSynchronize(st));
@@ -2400,6 +2404,7 @@ extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int6
             case FCRKPM_OPT_TUNE_NS1: *value = (int64_t)(1e6 * c.tune_ms[1]); break;
             case FCRKPM_OPT_TUNE_NS2: *value = (int64_t)(1e6 * c.tune_ms[2]); break;
             case FCRKPM_OPT_TUNE_NS3: *value = (int64_t)(1e6 * c.tune_ms[3]); break;
+            case FCRKPM_OPT_LINECONST: *value = (c.use_sym && c.sym) ? 1 : 0; break;
             default: fail(FCRKPM_ERR_ARG, "unknown option");
         }
         return FCRKPM_OK;
@@ -2424,6 +2429,10 @@ extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int6
                 if (!(reg_path_ok(c) ? reg_variant_ok(c, (int)value) : value == 0))
                     fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGLAYOUT out of range for this box");
                 set_reg_variant(c, (int)value);
+                break;
+            case FCRKPM_OPT_LINECONST:
+                if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_LINECONST takes 0 or 1");
+                c.use_sym = value == 1;
                 break;
             default:
                 fail(FCRKPM_ERR_ARG, "unknown option");

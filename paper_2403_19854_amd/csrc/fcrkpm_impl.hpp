@@ -166,6 +166,9 @@ struct Ctx {
     int lds_budget = 65536;             // LDS bytes one workgroup may use
     void* scratch = nullptr;            // device address of this device's static scratch array
                                         // (fcrkpm_apply_noalloc), taken at setup
+    void* sym = nullptr;                // register path: line-constant middle pass of K (regpass.hip)
+    bool use_sym = true;                // use it where it applies
+    double* rtab64[3] = {};             // per axis [3][n]: Re T_0 / n, Im T_1 / n, Re T_2 / n (FP64)
 };
 
 constexpr int kRedBlocks = 1024;   // reduction partials per right-hand side (at most)
@@ -228,6 +231,18 @@ struct RegPupd {
     const int* act;
 };
 bool reg_path_ok(const Ctx& c);
+// Line-constant middle pass of the register path (linear basis, K only): along
+// every z line the pointwise matrix M = V B^T B is constant except at a few
+// nodes near the ends of the z extent, so the middle pass applies the line's
+// M in the spectral domain and corrects those nodes directly.  sym_build
+// analyses the coefficient rows in use (K's) and keeps the state in c.sym
+// when the geometry allows it; sym_active tells whether the current product
+// can use it; sym_release frees it.
+void sym_build(Ctx& c, hipStream_t st);
+bool sym_active(const Ctx& c);
+void sym_release(Ctx& c);
+// algorithmic bytes of one launch of that middle pass per right-hand side
+double sym_pass_bytes(const Ctx& c);
 int reg_path_blocks(const Ctx& c);
 int reg_layouts(const Ctx& c);
 bool reg_variant_ok(const Ctx& c, int v);

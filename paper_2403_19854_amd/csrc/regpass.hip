@@ -24,8 +24,12 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <math.h>
+
+#include <algorithm>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "fcrkpm_impl.hpp"
 
@@ -1141,6 +1145,384 @@ __global__ __launch_bounds__(kRT) void k_rmid2(RArgs a)
 
 template <class Lay>
 long blocks_of(const Ctx& c) { return c.nn / Lay::L / Lay::LINES; }
+// ------------------------------------------------ line-constant middle pass
+// Along a z line of a cube-like domain the node's support neighbourhood, and
+// so its moment matrix, b^a and V, only change within floor(a~) nodes of the
+// two ends of the domain's z extent (and outside it, where they vanish).
+// Away from those few nodes the pointwise matrix M = V B^T B of the line is a
+// constant M_L, and a constant pointwise stage commutes with the z
+// convolutions: the part-1 z convolutions, E = M_L D and the part-2 z
+// convolutions collapse into one 3 x 3 matrix of spectra applied to the three
+// input lines (Eq 90-91 with constant coefficients).  The nodes where M
+// differs get the difference directly: D_q there from the kernel taps (a few
+// neighbours), dE = (M - M_L) D, spread back with the reflected taps.  So the
+// middle pass runs 3 forward and 3 inverse transforms per line pair instead
+// of 3 + 4 + 4 + 3, and reads one small record per pair instead of records
+// per boundary element.  The two real lines of a complex line pair have the
+// same M_L except at the x ends of the domain; there the pair's spectra are
+// separated with X(k) and conj X(-k) (the packed lines are real).
+constexpr int kSymC = 8;                   // correction nodes per line at most
+constexpr int kSymW = 16;                  // their window (corrections +- m) at most
+constexpr int kSymRec = 20 + 20 * kSymC + 4;  // floats per pair record
+constexpr int kSymFlag = kSymRec - 1;      // record slot of the mismatch flag
+
+// Geometry of the corrections, shared by every line (device copy, staged in LDS)
+struct SymTab {
+    int nc, nw, m, pad;
+    int cz[kSymC];           // correction nodes (z), ascending
+    int wz[kSymW];           // window nodes: the correction nodes +- m, ascending
+    float tap0[8], tap1[8];  // t_0[o], t_1[o] for o = -m .. m
+    signed char widx[128];   // window index of every z (-1: not in the window)
+};
+static_assert(sizeof(SymTab) % 4 == 0, "SymTab is copied in words");
+
+struct SArgs {
+    const float* in;
+    float* out;
+    long fstride, in_rb, out_rb, st;
+    const float* tr;       // [2][L]: Re T_0 / L, Im T_1 / L of the axis
+    const cf* tw;
+    const int* pidx;       // per pair: its record
+    const float* rec;      // records: M-bar (10), dM' (10), per correction node the 10
+                           // entries of dM for both lines interleaved, ..., flag
+    const SymTab* tab;
+};
+
+// inverse of Lay::freq: the lane and slot that hold frequency k
+template <class Lay>
+__device__ __forceinline__ int freq_lane(int k) { return k % Lay::LANES; }
+template <class Lay>
+__device__ __forceinline__ int freq_slot(int k)
+{
+    if constexpr (Lay::LANES == 16) return k / 16;
+    else {
+        constexpr int Q = Lay::PTS / 8;
+        const int rem = k / 8;
+        return 8 * (rem % Q) + rem / Q;
+    }
+}
+
+// w[i] = conj X(-k) where v[i] = X(k), k = freq(t, i): the spectrum of the
+// pair's other orientation, from the lane that holds -k (through LDS)
+template <class Lay>
+__device__ __forceinline__ void conj_neg(const cf (&v)[Lay::PTS], cf (&w)[Lay::PTS], int t, cf* xb)
+{
+    constexpr int R = Lay::PTS, L = Lay::L;
+#pragma unroll
+    for (int i = 0; i < R; ++i) xb[i * Lay::LANES + t] = v[i];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int kn = (L - Lay::freq(t, i)) % L;
+        const cf z = xb[freq_slot<Lay>(kn) * Lay::LANES + freq_lane<Lay>(kn)];
+        w[i] = cf{z.x, -z.y};
+    }
+    wave_sync();
+}
+
+// Y_j (+)= S_j(M) X at the lane's frequencies: S is the part-1 spectra, the
+// constant pointwise matrix M (sym_index order) and the reflected part-2
+// spectra of the linear basis's z terms multiplied out.  With T_0 = a (real)
+// and T_1 = i b (imaginary), D = (a X0, a X1, a X2, i b X0), E = M D and
+// Z = (a E0 - i b E3, a E1, a E2); the products carry one factor 1/L (the
+// inverse transform's), the stored spectra one each.
+template <class Lay, class Sp, bool ADD>
+__device__ __forceinline__ void sym_apply(const cf (&X)[3][Lay::PTS], cf (&Y)[3][Lay::PTS], const float* M,
+                                          const Sp& sp)
+{
+#pragma unroll
+    for (int i = 0; i < Lay::PTS; ++i) {
+        const float a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
+        const float A2 = (float)Lay::L * a * a, AB = (float)Lay::L * a * b, B2 = (float)Lay::L * b * b;
+        const float s00 = M[0] * A2 + M[9] * B2;
+        const float r01 = M[1] * A2, i01 = -M[6] * AB;   // S_01 = M01 a^2 - i M13 a b
+        const float r02 = M[2] * A2, i02 = -M[8] * AB;   // S_02 = M02 a^2 - i M23 a b
+        const float s11 = M[4] * A2, s12 = M[5] * A2, s22 = M[7] * A2;
+        const cf x0 = X[0][i], x1 = X[1][i], x2 = X[2][i];
+        const cf y0 = {s00 * x0.x + r01 * x1.x - i01 * x1.y + r02 * x2.x - i02 * x2.y,
+                       s00 * x0.y + r01 * x1.y + i01 * x1.x + r02 * x2.y + i02 * x2.x};
+        const cf y1 = {r01 * x0.x + i01 * x0.y + s11 * x1.x + s12 * x2.x,
+                       r01 * x0.y - i01 * x0.x + s11 * x1.y + s12 * x2.y};
+        const cf y2 = {r02 * x0.x + i02 * x0.y + s12 * x1.x + s22 * x2.x,
+                       r02 * x0.y - i02 * x0.x + s12 * x1.y + s22 * x2.y};
+        if constexpr (ADD) {
+            Y[0][i] = cf{Y[0][i].x + y0.x, Y[0][i].y + y0.y};
+            Y[1][i] = cf{Y[1][i].x + y1.x, Y[1][i].y + y1.y};
+            Y[2][i] = cf{Y[2][i].x + y2.x, Y[2][i].y + y2.y};
+        } else {
+            Y[0][i] = y0;
+            Y[1][i] = y1;
+            Y[2][i] = y2;
+        }
+    }
+}
+
+template <class Lay>
+__global__ __launch_bounds__(kRT) void k_smid(SArgs a)
+{
+    constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr int CW = 3 * kSymW + 4 * kSymC;  // per group: window values (later the
+                                               // output corrections), then dE
+    __shared__ cf tw[L];
+    __shared__ float trl[Tables<Lay, Lin3::NE>::LDS_SPEC];
+    __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
+    __shared__ cf stage[2][Lay::STAGE];
+    __shared__ cf cbuf[Lay::GROUPS * CW];
+    __shared__ SymTab tb;
+    const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
+    const int gc = tid % Lay::GROUPS, tc = tid / Lay::GROUPS;
+    const long rhs = blockIdx.y;
+    const float* in = a.in + rhs * a.in_rb;
+    float* out = a.out + rhs * a.out_rb;
+    const long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const long base = tile_base<Lay, false>(tile, a.st);
+    cf* xb = xbuf + g * Lay::XS;
+    cf* cw = cbuf + g * CW;          // [3][kSymW] window values, then output corrections
+    cf* ce = cw + 3 * kSymW;         // [4][kSymC] dE at the correction nodes
+    RArgs ta{};
+    ta.tr = a.tr;
+    ta.tw = a.tw;
+    Tables<Lay, Lin3::NE> tabs;
+    tabs.fetch(ta);
+    typename Lay::template Spec<Lin3::NE> sp;
+    sp.template fetch<Lay>(a.tr, t);
+
+    cf X[3][R];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            X[f][m] = load_pair<L, false>(in + f * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st));
+    // the pair's record: the constant part for every lane, the correction
+    // node's entries for the correction lanes
+    const long pair = tile * Lay::GROUPS + g;
+    const float* rec = a.rec + (size_t)a.pidx[pair] * kSymRec;
+    if (tid < (int)(sizeof(SymTab) / 4))
+        reinterpret_cast<int*>(&tb)[tid] = reinterpret_cast<const int*>(a.tab)[tid];
+    tabs.put(tw, trl);  // its barrier also publishes tb
+    sp.template bind<Lay>(trl, t);
+    typename Lay::Tw lw;
+    lw.make(t, tw);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+    // window values of the three inputs
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int wi = tb.widx[Lay::row(t, m)];
+        if (wi >= 0) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) cw[f * kSymW + wi] = X[f][m];
+        }
+    }
+    float M[10];
+#pragma unroll
+    for (int e = 0; e < 10; ++e) M[e] = rec[e];
+    const bool mismatch = rec[kSymFlag] != 0.0f;
+    wave_sync();
+    // dE = (M - M_L) D at the correction nodes, D from the taps (part 1: D(c) =
+    // sum_o t[o] X(c - o)); each line of the pair with its own dM
+    for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
+        const int cz = tb.cz[ci];
+        cf D[4] = {};
+        for (int o = -tb.m; o <= tb.m; ++o) {
+            const int wi = tb.widx[(cz - o + L) % L];
+            const float t0 = tb.tap0[o + tb.m], t1 = tb.tap1[o + tb.m];
+            const cf x0 = cw[wi], x1 = cw[kSymW + wi], x2 = cw[2 * kSymW + wi];
+            D[0] = cf{D[0].x + t0 * x0.x, D[0].y + t0 * x0.y};
+            D[1] = cf{D[1].x + t0 * x1.x, D[1].y + t0 * x1.y};
+            D[2] = cf{D[2].x + t0 * x2.x, D[2].y + t0 * x2.y};
+            D[3] = cf{D[3].x + t1 * x0.x, D[3].y + t1 * x0.y};
+        }
+        const float* dm = rec + 20 + 20 * ci;
+        float e0[4], e1[4], MA[10], MB[10];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) {
+            MA[e] = dm[2 * e];
+            MB[e] = dm[2 * e + 1];
+        }
+        sym4_apply(MA, D[0].x, D[1].x, D[2].x, D[3].x, e0);
+        sym4_apply(MB, D[0].y, D[1].y, D[2].y, D[3].y, e1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) ce[p * kSymC + ci] = cf{e0[p], e1[p]};
+    }
+    // the three inputs, forward transformed (their wave_syncs also order the
+    // dE writes above before the reads below)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) Lay::fwd(X[f], t, xb, lw);
+    cf Y[3][R];
+    sym_apply<Lay, decltype(sp), false>(X, Y, M, sp);
+    if (mismatch) {
+        // lines of different M_L: (M_A + M_B)/2 on X(k) and (M_A - M_B)/2 on conj X(-k)
+        float dMp[10];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) dMp[e] = rec[10 + e];
+        cf W[3][R];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) conj_neg<Lay>(X[f], W[f], t, xb);
+        sym_apply<Lay, decltype(sp), true>(W, Y, dMp, sp);
+    }
+    // output corrections at the window nodes (part 2: dZ(z) = sum_c t[c - z] dE(c)),
+    // written over the window values, which are no longer needed
+    for (int wi = t; wi < tb.nw; wi += Lay::LANES) {
+        const int z = tb.wz[wi];
+        cf z0 = {}, z1 = {}, z2 = {};
+        for (int ci = 0; ci < tb.nc; ++ci) {
+            int d = tb.cz[ci] - z;
+            if (d > L / 2) d -= L;
+            if (d < -L / 2) d += L;
+            if (d < -tb.m || d > tb.m) continue;
+            const float t0 = tb.tap0[d + tb.m], t1 = tb.tap1[d + tb.m];
+            const cf e0 = ce[ci], e1 = ce[kSymC + ci], e2 = ce[2 * kSymC + ci], e3 = ce[3 * kSymC + ci];
+            z0 = cf{z0.x + t0 * e0.x + t1 * e3.x, z0.y + t0 * e0.y + t1 * e3.y};
+            z1 = cf{z1.x + t0 * e1.x, z1.y + t0 * e1.y};
+            z2 = cf{z2.x + t0 * e2.x, z2.y + t0 * e2.y};
+        }
+        cw[wi] = z0;
+        cw[kSymW + wi] = z1;
+        cw[2 * kSymW + wi] = z2;
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) Lay::inv(Y[o], t, xb, lw);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int wi = tb.widx[Lay::row(t, m)];
+        if (wi >= 0) {
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                const cf d = cw[o * kSymW + wi];
+                Y[o][m] = cf{Y[o][m].x + d.x, Y[o][m].y + d.y};
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
+#pragma unroll
+        for (int m = 0; m < R; ++m)
+            store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
+    }
+}
+
+// Setup of the line-constant middle pass, in FP64.  Line l = x + nx y: M(z)
+// at every z, the line's M_L = M(zref), a check that M(z) = M_L off the
+// correction nodes (to tol of the product's interior scale), and the line
+// record M_L, then dM = M(c) - M_L at each correction node c.
+__global__ void k_sym_lines(const double* __restrict__ ba, const double* __restrict__ vol, long nlines,
+                            int nz, long nn, int zref, int nc, const int* __restrict__ czl,
+                            double tol, double* __restrict__ lrec, int* __restrict__ bad)
+{
+    constexpr int S = 4;
+    const long l = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (l >= nlines) return;
+    auto mat = [&](int z, double (&Mz)[10]) {
+        const long node = l + (long)z * nlines;
+        const double v = vol[node];
+        for (int p = 0; p < S; ++p)
+            for (int q = p; q < S; ++q) {
+                double acc = 0.0;
+                for (int al = 0; al < 3; ++al)
+                    acc += ba[(long)(al * S + p) * nn + node] * ba[(long)(al * S + q) * nn + node];
+                Mz[sym_index(p, q)] = v * acc;
+            }
+    };
+    double ML[10], Mz[10];
+    mat(zref, ML);
+    double* o = lrec + l * (10 + 10 * kSymC);
+    for (int e = 0; e < 10; ++e) o[e] = ML[e];
+    int ci = 0;
+    for (int z = 0; z < nz; ++z) {
+        const bool corr = ci < nc && czl[ci] == z;
+        mat(z, Mz);
+        if (corr) {
+            for (int e = 0; e < 10; ++e) o[10 + 10 * ci + e] = Mz[e] - ML[e];
+            ++ci;
+        } else {
+            for (int e = 0; e < 10; ++e)
+                if (fabs(Mz[e] - ML[e]) > tol) atomicOr(bad, 1);
+        }
+    }
+}
+
+// Pair records (FP32): the mean and half difference of the two lines' M_L,
+// the correction entries of both lines interleaved, the mismatch flag.  Pairs
+// whose lines both equal the reference pair's (to tol) share record 0, which
+// the reference pair writes; every other pair owns record 1 + pair.
+__global__ void k_sym_pairs(const double* __restrict__ lrec, long npairs, int nc, long pref, double tol,
+                            int* __restrict__ pidx, float* __restrict__ rec, int* __restrict__ own)
+{
+    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    constexpr int LR = 10 + 10 * kSymC;
+    const double* A = lrec + (2 * p) * LR;
+    const double* B = A + LR;
+    auto write = [&](float* o) {
+        bool mism = false;
+        for (int e = 0; e < 10; ++e) {
+            o[e] = (float)(0.5 * (A[e] + B[e]));
+            const double hd = 0.5 * (A[e] - B[e]);
+            o[10 + e] = (float)hd;
+            mism = mism || fabs(hd) > tol;
+        }
+        for (int ci = 0; ci < kSymC; ++ci)
+            for (int e = 0; e < 10; ++e) {
+                o[20 + 20 * ci + 2 * e] = ci < nc ? (float)A[10 + 10 * ci + e] : 0.0f;
+                o[20 + 20 * ci + 2 * e + 1] = ci < nc ? (float)B[10 + 10 * ci + e] : 0.0f;
+            }
+        for (int k = 20 + 20 * kSymC; k < kSymRec; ++k) o[k] = 0.0f;
+        o[kSymFlag] = mism ? 1.0f : 0.0f;
+    };
+    bool same = pref >= 0;
+    if (same) {
+        const double* RA = lrec + (2 * pref) * LR;
+        for (int k = 0; k < 10 + 10 * nc && same; ++k)
+            same = fabs(A[k] - RA[k]) <= tol && fabs(B[k] - RA[LR + k]) <= tol;
+    }
+    write(rec + (size_t)(1 + p) * kSymRec);
+    if (p == pref) write(rec);
+    pidx[p] = same ? 0 : (int)(1 + p);
+    if (!same) atomicAdd(own, 1);
+}
+
+struct SymState {
+    const double* ba = nullptr;  // coefficient rows the records were built from
+    SymTab* tab = nullptr;       // device
+    int* pidx = nullptr;         // device, per pair
+    float* rec = nullptr;        // device, 1 + pairs records
+    long own = 0;                // pairs with a record of their own
+};
+
+// cubic B-spline of Eq 7 at z = |x| / a
+double bspline_d(double z)
+{
+    z = fabs(z);
+    if (z <= 0.5) return 2.0 / 3.0 - 4.0 * z * z + 4.0 * z * z * z;
+    if (z < 1.0) return 4.0 / 3.0 - 4.0 * z + 4.0 * z * z - 4.0 / 3.0 * z * z * z;
+    return 0.0;
+}
+
+template <class Lay>
+void run_smid(const Ctx& c, const float* in, long irb, float* out, long orb, int nrhs, hipStream_t st,
+              const RegProf& prof)
+{
+    const SymState& s = *(const SymState*)c.sym;
+    SArgs a{};
+    a.in = in;
+    a.in_rb = irb;
+    a.out = out;
+    a.out_rb = orb;
+    a.fstride = c.nn;
+    a.st = (long)c.n[0] * c.n[1];
+    a.tr = c.rtab32[2];
+    a.tw = c.tw32[2];
+    a.pidx = s.pidx;
+    a.rec = s.rec;
+    a.tab = s.tab;
+    const dim3 grid((unsigned)blocks_of<Lay>(c), (unsigned)nrhs), block(kRT);
+    hipEvent_t e0, e1;
+    prof.events(2, &e0, &e1);
+    if (e0) hipExtLaunchKernelGGL(k_smid<Lay>, grid, block, 0, st, e0, e1, 0, a);
+    else hipLaunchKernelGGL(k_smid<Lay>, grid, block, 0, st, a);
+}
 
 // launch of pass k, with the sampler's events recorded by the launch itself
 template <typename K>
@@ -1202,8 +1584,13 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.noff = c.noff[c.reg_layout];
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         if constexpr (B::DEGREE == 1) {
-            for (int k = 0; k < 10; ++k) a.ci[k] = c.reg_mi[k];
-            rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
+            constexpr bool SYM_LAYOUT = !std::is_same<Lay, G8<16>>::value;
+            if (SYM_LAYOUT && sym_active(c)) {
+                if constexpr (SYM_LAYOUT) run_smid<Lay>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
+            } else {
+                for (int k = 0; k < 10; ++k) a.ci[k] = c.reg_mi[k];
+                rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
+            }
         } else {
             for (int k = 0; k <= kMaxNodeConst; ++k) a.ci[k] = c.cint32[k];
             // same tile geometry; 16-lane lines read their twiddles and spectra from LDS here
@@ -1457,6 +1844,148 @@ void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask
         FC_RUN(G8<8>);
     }
 #undef FC_RUN
+}
+
+
+// ------------------------------------------------ line-constant middle pass: setup
+namespace {
+template <typename T>
+bool sym_alloc(T*& p, size_t count)
+{
+    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return false;
+    }
+    return true;
+}
+template <typename T>
+void sym_free(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+}  // namespace
+
+void sym_release(Ctx& c)
+{
+    if (!c.sym) return;
+    SymState* s = (SymState*)c.sym;
+    sym_free(s->tab);
+    sym_free(s->pidx);
+    sym_free(s->rec);
+    delete s;
+    c.sym = nullptr;
+}
+
+bool sym_active(const Ctx& c)
+{
+    return c.sym && c.use_sym && ((const SymState*)c.sym)->ba == c.ba_64 && c.degree == 1 &&
+           (c.n[0] == 64 || c.reg_layout == 1);
+}
+
+double sym_pass_bytes(const Ctx& c)
+{
+    const SymState& s = *(const SymState*)c.sym;
+    const double pairs = (double)c.nn / c.n[2] / 2.0;
+    // three fields in, three out; a record index per pair; the records
+    return (double)c.nn * 24.0 + pairs * 4.0 + (double)(s.own + 1) * kSymRec * 4.0;
+}
+
+// Builds the line-constant middle pass for K's coefficient rows when every z
+// line of the box is constant off the correction nodes (the nodes within
+// floor(a~) of the two ends of the domain's z extent, and those outside it);
+// leaves c.sym empty otherwise, and the middle pass with records per element
+// is used.  Synchronous.
+void sym_build(Ctx& c, hipStream_t st)
+{
+    sym_release(c);
+    if (!c.use_sym || c.degree != 1 || c.krows != c.dim || !reg_path_ok(c) || c.nconst.bmax < 0.0) return;
+    const int L = c.n[2], m = c.m[2];
+    if (L > 128 || m < 1 || m > 3) return;
+    const long nlines = (long)c.n[0] * c.n[1], npairs = nlines / 2;
+    // z extent of the domain
+    const int ntot = c.n[0] + c.n[1] + c.n[2];
+    int* occ = nullptr;
+    if (!sym_alloc(occ, ntot)) return;
+    std::vector<int> hocc(ntot);
+    (void)hipMemsetAsync(occ, 0, sizeof(int) * ntot, st);
+    launch_axis_extent(c, c.chi, occ, st);
+    (void)hipMemcpyAsync(hocc.data(), occ, sizeof(int) * ntot, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    sym_free(occ);
+    int zlo = -1, zhi = -1;
+    for (int z = 0; z < L; ++z)
+        if (hocc[c.n[0] + c.n[1] + z]) {
+            if (zlo < 0) zlo = z;
+            zhi = z;
+        }
+    if (zlo < 0) return;
+    SymTab tab{};
+    tab.m = m;
+    int zref = -1;
+    for (int z = 0; z < L; ++z) {
+        if (z < zlo + m || z > zhi - m) {
+            if (tab.nc == kSymC) return;
+            tab.cz[tab.nc++] = z;
+        } else if (zref < 0) {
+            zref = z;
+        }
+    }
+    if (zref < 0) return;
+    std::vector<char> inw(L, 0);
+    for (int i = 0; i < tab.nc; ++i)
+        for (int o = -m; o <= m; ++o) inw[(tab.cz[i] + o + L) % L] = 1;
+    for (int z = 0; z < 128; ++z) tab.widx[z] = -1;
+    for (int z = 0; z < L; ++z)
+        if (inw[z]) {
+            if (tab.nw == kSymW) return;
+            tab.widx[z] = (signed char)tab.nw;
+            tab.wz[tab.nw++] = z;
+        }
+    for (int o = -m; o <= m; ++o) {
+        const double w = bspline_d((double)o / c.at[2]);
+        tab.tap0[o + m] = (float)w;
+        tab.tap1[o + m] = (float)(o * w);
+    }
+    // the scale of M: the interior nodes' V B^T B
+    double mscale = 0.0;
+    for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 4; ++q) {
+            double acc = 0.0;
+            for (int al = 0; al < 3; ++al) acc += c.nconst.b[al * 4 + p] * c.nconst.b[al * 4 + q];
+            mscale = std::max(mscale, fabs(c.nconst.v * acc));
+        }
+    if (!(mscale > 0.0)) return;
+    const double tol = 1e-11 * mscale;
+
+    SymState* s = new SymState();
+    s->ba = c.ba_64;
+    double* lrec = nullptr;
+    int* czl = nullptr;
+    int* flag = nullptr;
+    bool ok = sym_alloc(s->tab, 1) && sym_alloc(s->pidx, npairs) && sym_alloc(s->rec, (size_t)(npairs + 1) * kSymRec) &&
+              sym_alloc(lrec, (size_t)nlines * (10 + 10 * kSymC)) && sym_alloc(czl, kSymC) && sym_alloc(flag, 2);
+    if (ok) {
+        int hflag[2] = {0, 0};
+        (void)hipMemcpyAsync(s->tab, &tab, sizeof(SymTab), hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(czl, tab.cz, sizeof(int) * kSymC, hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(flag, hflag, sizeof(hflag), hipMemcpyHostToDevice, st);
+        hipLaunchKernelGGL(k_sym_lines, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, c.ba_64, c.vol64,
+                           nlines, L, c.nn, zref, tab.nc, czl, tol, lrec, flag);
+        const long pref = ((long)(c.n[0] / 2) + (long)c.n[0] * (c.n[1] / 2)) / 2;
+        hipLaunchKernelGGL(k_sym_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec, npairs,
+                           tab.nc, pref, tol, s->pidx, s->rec, flag + 1);
+        (void)hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, st);
+        ok = hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess && hflag[0] == 0;
+        s->own = hflag[1];
+    }
+    (void)hipGetLastError();
+    sym_free(lrec);
+    sym_free(czl);
+    sym_free(flag);
+    c.sym = s;
+    if (!ok) sym_release(c);
 }
 
 }  // namespace fcrkpm

@@ -47,6 +47,7 @@ OPT_TUNE_NS0 = 4
 OPT_TUNE_NS1 = 5
 OPT_TUNE_NS2 = 6
 OPT_TUNE_NS3 = 7
+OPT_LINECONST = 8
 
 
 class Grid(C.Structure):
