@@ -192,6 +192,7 @@ void release(Ctx& c)
         dfree(c.spec64[a]);
         dfree(c.spec32[a]);
         dfree(c.rtab32[a]);
+        dfree(c.rtab64[a]);
     }
     dfree(c.work64);
     dfree(c.work32);
@@ -496,7 +497,7 @@ double reg_pass_bytes(const Ctx& c, int k)
         case 0: return nn * (4 + 1 + p0 * 4 + (c.prof_pupd ? 4 + 4 : 0));
         case 1: return nn * (p0 * 4 + p1 * 4);
         case 2: {
-            if (sym_active(c)) return sym_pass_bytes(c);
+            if (sym_active(c)) return sym_pass_bytes(c, 4);
             const double words = (double)reg_bits_words(c, c.reg_layout);
             return nn * (p1 * 4 + p1 * 4) + 12.0 * words +
                    (double)c.nload[c.reg_layout] * reg_record_floats(c) * 4;
@@ -518,6 +519,58 @@ void regprof_events(const void* cv, int k, hipEvent_t* e0, hipEvent_t* e1)
         *e1 = pk.ev[2 * pk.nrec + 1];
         ++pk.nrec;
     }
+}
+
+// the same for the FP64 register passes (8-byte fields)
+double reg_pass_bytes64(const Ctx& c, int k)
+{
+    const double nn = (double)c.nn;
+    const double p0 = c.basis_plan.size[0], p1 = c.basis_plan.size[1];
+    switch (k) {
+        case 0: return nn * (8 + 1 + p0 * 8);
+        case 1: return nn * (p0 * 8 + p1 * 8);
+        case 2: return sym_pass_bytes(c, 8);
+        case 3: return nn * (p1 * 8 + p0 * 8);
+        default: return nn * (p0 * 8 + 1 + 8 + (c.prof_dot ? 8 : 0));
+    }
+}
+
+void regprof_events64(const void* cv, int k, hipEvent_t* e0, hipEvent_t* e1)
+{
+    Ctx& c = *(Ctx*)cv;
+    static const int kinds[5] = {KD_P1_X, KD_P1_Y, KD_MID_K, KD_P2_Y, KD_P2_X};
+    ProfKind& pk = ((Prof*)c.prof)->k[kind_of<double>(kinds[k])];
+    ++pk.launches;
+    pk.bytes += reg_pass_bytes64(c, k) * c.prof_rhs;
+    if (pk.nrec < kProfCap) {
+        *e0 = pk.ev[2 * pk.nrec];
+        *e1 = pk.ev[2 * pk.nrec + 1];
+        ++pk.nrec;
+    }
+}
+
+bool use_reg_path64(const Ctx& c)
+{
+    static int env = -1;
+    if (env < 0) {
+        const char* e = getenv("FCRKPM_REGPATH64");
+        env = (e && *e == '0') ? 0 : 1;
+    }
+    return env == 1 && c.use_regpath && reg_path64_ok(c);
+}
+
+void reg_k64(Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs, hipStream_t st,
+             double* dot_part = nullptr, const double* dot_with = nullptr)
+{
+    ensure_work(c, nrhs);
+    RegProf rp;
+    if (c.prof_on && !c.capturing) {
+        rp.c = &c;
+        rp.events_fn = regprof_events64;
+        c.prof_rhs = nrhs;
+        c.prof_dot = dot_part != nullptr;
+    }
+    launch_reg_k64(c, in, out, mask, nrhs, dot_part, dot_with, st, rp);
 }
 
 void reg_k(Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs, hipStream_t st,
@@ -639,6 +692,12 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
             if constexpr (std::is_same_v<T, float> && std::is_same_v<Tio, float>) {
                 if (op != OP_KN && use_reg_path(c, nrhs)) {
                     reg_k(c, in, out, mk, nrhs, st);
+                    break;
+                }
+            }
+            if constexpr (std::is_same_v<T, double> && std::is_same_v<Tio, double>) {
+                if (op != OP_KN && use_reg_path64(c)) {
+                    reg_k64(c, in, out, mk, nrhs, st);
                     break;
                 }
             }
@@ -797,6 +856,15 @@ void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStrea
             RegPupd pu{r, rr_part, red_blocks(c.nn), c.scal, parity ^ 1, c.act};
             reg_k(c, p, q, c.freem, nrhs, st, pq_part, p, pend ? &pu : nullptr);
             npq = reg_path_blocks(c);
+        } else {
+            apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
+            launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
+        }
+    } else if constexpr (std::is_same_v<T, double> && std::is_same_v<TP, double>) {
+        if (use_reg_path64(c) && reg_path64_blocks(c) <= kRedBlocks) {
+            // the last pass of the product leaves the p.q partials
+            reg_k64(c, p, q, c.freem, nrhs, st, pq_part, p);
+            npq = (int)reg_path64_blocks(c);
         } else {
             apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
             launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
@@ -1716,6 +1784,14 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
                                                                   : sp[(size_t)e * L + kk].x) / L);
                 c.rtab32[a] = dalloc<float>(rt.size());
                 HIPCHK(hipMemcpyAsync(c.rtab32[a], rt.data(), sizeof(float) * rt.size(),
+                                      hipMemcpyHostToDevice, st));
+                std::vector<double> rt64((size_t)3 * L, 0.0);
+                for (int e = 0; e < 3 && e < ne; ++e)
+                    for (int kk = 0; kk < L; ++kk)
+                        rt64[(size_t)e * L + kk] = ((e & 1) ? sp[(size_t)e * L + kk].y
+                                                            : sp[(size_t)e * L + kk].x) / L;
+                c.rtab64[a] = dalloc<double>(rt64.size());
+                HIPCHK(hipMemcpyAsync(c.rtab64[a], rt64.data(), sizeof(double) * rt64.size(),
                                       hipMemcpyHostToDevice, st));
                 HIPCHK(hipStreamSynchronize(st));
             }

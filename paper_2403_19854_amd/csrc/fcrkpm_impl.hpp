@@ -242,7 +242,15 @@ void sym_build(Ctx& c, hipStream_t st);
 bool sym_active(const Ctx& c);
 void sym_release(Ctx& c);
 // algorithmic bytes of one launch of that middle pass per right-hand side
-double sym_pass_bytes(const Ctx& c);
+double sym_pass_bytes(const Ctx& c, int elem_bytes);
+// The FP64 K product on the register path (linear basis, 64^3 or 128^3 boxes
+// with the line-constant middle pass): reg_path64_ok tells whether it
+// applies; with dot_part the last pass also leaves the per-workgroup partials
+// of out . dot_with (reg_path64_blocks of them per right-hand side).
+bool reg_path64_ok(const Ctx& c);
+long reg_path64_blocks(const Ctx& c);
+void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
+                    double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof);
 int reg_path_blocks(const Ctx& c);
 int reg_layouts(const Ctx& c);
 bool reg_variant_ok(const Ctx& c, int v);

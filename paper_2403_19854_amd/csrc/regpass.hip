@@ -48,59 +48,70 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // a * e^{-DIR 2 pi i j / 16}, j a compile-time constant after unrolling
-template <int DIR>
-__device__ __forceinline__ cf mul_w16(cf a, int j)
+template <int DIR, typename T>
+__device__ __forceinline__ cplx<T> mul_w16(cplx<T> a, int j)
 {
-    constexpr float C[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
-                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
-                             -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
-                             0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
-    const float c = C[j & 15], s = C[(j + 12) & 15];  // sin(x) = cos(x - pi/2)
-    const float ds = DIR > 0 ? s : -s;
-    return cf{a.x * c + a.y * ds, a.y * c - a.x * ds};
+    T c, s;
+    if constexpr (sizeof(T) == 4) {
+        constexpr float C[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                                 0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                                 -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                                 0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+        c = C[j & 15];
+        s = C[(j + 12) & 15];  // sin(x) = cos(x - pi/2)
+    } else {
+        constexpr double C[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                  0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+                                  -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+                                  0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+        c = C[j & 15];
+        s = C[(j + 12) & 15];
+    }
+    const T ds = DIR > 0 ? s : -s;
+    return cplx<T>{a.x * c + a.y * ds, a.y * c - a.x * ds};
 }
 
 // in-place DFT-16 in natural order, as 4 x 4 with internal twiddles
-template <int DIR>
-__device__ __forceinline__ void dft16(cf* v)
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cplx<T>* v)
 {
-    cf a[4][4];
+    cplx<T> a[4][4];
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2) {
 #pragma unroll
         for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
-        dft4<float, DIR>(a[n2]);
+        dft4<T, DIR>(a[n2]);
 #pragma unroll
         for (int k1 = 1; k1 < 4; ++k1)
             if (n2 > 0) a[n2][k1] = mul_w16<DIR>(a[n2][k1], n2 * k1);
     }
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
-        cf b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
-        dft4<float, DIR>(b);
+        cplx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<T, DIR>(b);
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
     }
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dftR_reg(cf* v)
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR_reg(cplx<T>* v)
 {
     if constexpr (R == 16) dft16<DIR>(v);
-    else dft8<float, DIR>(v);
+    else dft8<T, DIR>(v);
 }
 
-template <int DIR>
-__device__ __forceinline__ cf twid(const cf* tw, int j)
+template <int DIR, typename T>
+__device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int j)
 {
-    const cf w = tw[j];
-    return DIR > 0 ? w : cf{w.x, -w.y};
+    const cplx<T> w = tw[j];
+    return DIR > 0 ? w : cplx<T>{w.x, -w.y};
 }
 
 // Forward transform of the group's line.  In: v[m] = x[t + 8m].  Out:
 // v[8j + k2] = X[t + 8j + R k2] (j < R/8, k2 < 8).
-template <int R>
-__device__ __forceinline__ void g8_fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
+template <int R, typename T>
+__device__ __forceinline__ void g8_fwd(cplx<T> (&v)[R], int t, cplx<T>* xb, const cplx<T>* tw)
 {
     constexpr int KPL = R / 8;
     dftR_reg<R, +1>(v);
@@ -115,17 +126,17 @@ __device__ __forceinline__ void g8_fwd(cf (&v)[R], int t, cf* xb, const cf* tw)
         for (int n = 0; n < 8; ++n) v[8 * j + n] = xb[(t + 8 * j) * 9 + n];
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < KPL; ++j) dft8<float, +1>(v + 8 * j);
+    for (int j = 0; j < KPL; ++j) dft8<T, +1>(v + 8 * j);
 }
 
 // Unnormalised inverse: the layout of fwd's output in, x[t + 8m] in v[m] out.
-template <int R>
-__device__ __forceinline__ void g8_inv(cf (&v)[R], int t, cf* xb, const cf* tw)
+template <int R, typename T>
+__device__ __forceinline__ void g8_inv(cplx<T> (&v)[R], int t, cplx<T>* xb, const cplx<T>* tw)
 {
     constexpr int KPL = R / 8;
 #pragma unroll
     for (int j = 0; j < KPL; ++j) {
-        dft8<float, -1>(v + 8 * j);
+        dft8<T, -1>(v + 8 * j);
 #pragma unroll
         for (int n1 = 1; n1 < 8; ++n1) v[8 * j + n1] = cmul(v[8 * j + n1], twid<-1>(tw, n1 * (t + 8 * j)));
 #pragma unroll
@@ -144,12 +155,21 @@ __device__ __forceinline__ float swap8(float x)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x128, 0xF, 0xF, true));
 }
+__device__ __forceinline__ double swap8(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x128, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x128, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 // The twiddles one G16 lane needs, fixed for the whole kernel: the forward
 // W_128^{t k1} (k1 = 1..7), the W_16^{tl h} of its half (1 on h = 0) and the
 // inverse W_128^{-(tl + 8h) (t & 7)} (tl = 0..7).  Computed once per lane from
 // the LDS table, so the transforms read no twiddles and select nothing.
+template <typename T = float>
 struct G16Tw {
+    typedef cplx<T> cf;
     cf f_[7], h_[7], i_[8];
     __device__ __forceinline__ void make(int t, const cf* tw)
     {
@@ -157,8 +177,8 @@ struct G16Tw {
 #pragma unroll
         for (int j = 1; j < 8; ++j) {
             f_[j - 1] = tw[t * j];
-            const cf w = mul_w16<+1>(cf{1.0f, 0.0f}, j);
-            h_[j - 1] = hh ? w : cf{1.0f, 0.0f};
+            const cf w = mul_w16<+1>(cf{T(1), T(0)}, j);
+            h_[j - 1] = hh ? w : cf{T(1), T(0)};
         }
 #pragma unroll
         for (int tl = 0; tl < 8; ++tl) i_[tl] = twid<-1>(tw, (tl + 8 * hh) * k1);
@@ -170,7 +190,9 @@ struct G16Tw {
 
 // The same twiddles read from the LDS table when needed (fewer registers, for
 // kernels that hold many fields)
+template <typename T = float>
 struct G16TwL {
+    typedef cplx<T> cf;
     const cf* tw;
     int t;
     __device__ __forceinline__ void make(int lane, const cf* table)
@@ -181,8 +203,8 @@ struct G16TwL {
     __device__ __forceinline__ cf f(int j) const { return tw[t * j]; }
     __device__ __forceinline__ cf h(int j) const
     {
-        const cf w = mul_w16<+1>(cf{1.0f, 0.0f}, j);
-        return (t >> 3) ? w : cf{1.0f, 0.0f};
+        const cf w = mul_w16<+1>(cf{T(1), T(0)}, j);
+        return (t >> 3) ? w : cf{T(1), T(0)};
     }
     __device__ __forceinline__ cf i(int tl) const { return twid<-1>(tw, (tl + 8 * (t >> 3)) * (t & 7)); }
 };
@@ -192,10 +214,11 @@ struct G16TwL {
 // W_128^{t k1}, a transpose giving lane (k1, h) the values of lanes
 // 8h .. 8h+7 at k1, a radix-2 step across h, the twiddle W_16^{tl h} and a
 // DFT-8 over the lane offset tl.
-template <class TW>
-__device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const TW& w)
+template <class TW, typename T>
+__device__ __forceinline__ void g16_fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w)
 {
-    dft8<float, +1>(v);
+    typedef cplx<T> cf;
+    dft8<T, +1>(v);
 #pragma unroll
     for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], w.f(k1));
 #pragma unroll
@@ -205,7 +228,7 @@ __device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const TW& w)
 #pragma unroll
     for (int tl = 0; tl < 8; ++tl) v[tl] = xb[k1 * 17 + 8 * h + tl];
     wave_sync();
-    const float s = h ? -1.0f : 1.0f;
+    const T s = h ? T(-1) : T(1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const cf u = {swap8(v[i].x), swap8(v[i].y)};
@@ -213,19 +236,20 @@ __device__ __forceinline__ void g16_fwd(cf (&v)[8], int t, cf* xb, const TW& w)
     }
 #pragma unroll
     for (int tl = 1; tl < 8; ++tl) v[tl] = cmul(v[tl], w.h(tl));
-    dft8<float, +1>(v);
+    dft8<T, +1>(v);
 }
 
 // G16 unnormalised inverse: v[i] = X[t + 16i] in, v[m] = x[t + 16m] out (the
 // steps of g16_fwd reversed, with conjugate twiddles).
-template <class TW>
-__device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const TW& w)
+template <class TW, typename T>
+__device__ __forceinline__ void g16_inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w)
 {
+    typedef cplx<T> cf;
     const int k1 = t & 7, h = t >> 3;
-    dft8<float, -1>(v);
+    dft8<T, -1>(v);
 #pragma unroll
     for (int tl = 1; tl < 8; ++tl) v[tl] = cmulc(v[tl], w.h(tl));
-    const float s = h ? -1.0f : 1.0f;
+    const T s = h ? T(-1) : T(1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const cf u = {swap8(v[i].x), swap8(v[i].y)};
@@ -237,7 +261,7 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const TW& w)
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = xb[j * 17 + t];
     wave_sync();
-    dft8<float, -1>(v);
+    dft8<T, -1>(v);
 }
 
 // The lane's values of the axis's kernel spectra T_e (e < NE), each divided
@@ -245,11 +269,11 @@ __device__ __forceinline__ void g16_inv(cf (&v)[8], int t, cf* xb, const TW& w)
 // imaginary for odd e (t_e is even or odd), so one float per frequency
 // describes it.  G16 holds its 8 frequencies of each in registers; G8 reads
 // them from the LDS copy.
-template <int NE>
+template <int NE, typename T = float>
 struct SpecRegs {
-    float s[NE][8];
+    T s[NE][8];
     template <class Lay>
-    __device__ __forceinline__ void fetch(const float* tab, int t)
+    __device__ __forceinline__ void fetch(const T* tab, int t)
     {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
@@ -257,23 +281,24 @@ struct SpecRegs {
             for (int i = 0; i < 8; ++i) s[e][i] = tab[e * Lay::L + Lay::freq(t, i)];
     }
     template <class Lay>
-    __device__ __forceinline__ void bind(const float*, int) {}
+    __device__ __forceinline__ void bind(const T*, int) {}
     template <class Lay, int E>
-    __device__ __forceinline__ float e(int i) const { return s[E][i]; }
+    __device__ __forceinline__ T e(int i) const { return s[E][i]; }
 };
+template <typename T = float>
 struct SpecLds {
-    const float* trl;
+    const T* trl;
     int t;
     template <class Lay>
-    __device__ __forceinline__ void fetch(const float*, int) {}
+    __device__ __forceinline__ void fetch(const T*, int) {}
     template <class Lay>
-    __device__ __forceinline__ void bind(const float* tab, int lane)
+    __device__ __forceinline__ void bind(const T* tab, int lane)
     {
         trl = tab;
         t = lane;
     }
     template <class Lay, int E>
-    __device__ __forceinline__ float e(int i) const { return trl[E * Lay::L + Lay::freq(t, i)]; }
+    __device__ __forceinline__ T e(int i) const { return trl[E * Lay::L + Lay::freq(t, i)]; }
 };
 
 // Line layouts: lanes per complex line, points per lane, the spatial row of
@@ -282,9 +307,10 @@ struct SpecLds {
 // 32 so the groups of a wave spread over the banks), and the geometry of the
 // staging buffer of strided passes (TP, SS, STAGE; see stage_move).
 // G8 reads its twiddles from the LDS table as it goes
+template <typename T = float>
 struct LdsTw {
-    const cf* tw;
-    __device__ __forceinline__ void make(int, const cf* table) { tw = table; }
+    const cplx<T>* tw;
+    __device__ __forceinline__ void make(int, const cplx<T>* table) { tw = table; }
 };
 
 template <int R>
@@ -292,25 +318,33 @@ struct G8 {
     static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
-    typedef LdsTw Tw;
-    template <int NE>
-    using Spec = SpecLds;
+    template <typename T = float>
+    using TwT = LdsTw<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecLds<T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
-    static __device__ __forceinline__ void fwd(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_fwd<R>(v, t, xb, w.tw); }
-    static __device__ __forceinline__ void inv(cf (&v)[R], int t, cf* xb, const Tw& w) { g8_inv<R>(v, t, xb, w.tw); }
+    template <typename T>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[R], int t, cplx<T>* xb, const LdsTw<T>& w) { g8_fwd<R>(v, t, xb, w.tw); }
+    template <typename T>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[R], int t, cplx<T>* xb, const LdsTw<T>& w) { g8_inv<R>(v, t, xb, w.tw); }
 };
 struct G16 {
     static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
-    typedef G16Tw Tw;
-    template <int NE>
-    using Spec = SpecRegs<NE>;
+    template <typename T = float>
+    using TwT = G16Tw<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecRegs<NE, T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
-    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
-    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
+    template <typename T, class TW>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_fwd(v, t, xb, w); }
+    template <typename T, class TW>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_inv(v, t, xb, w); }
 };
 // G16 geometry with twiddles and spectra read from LDS (for the kernel that
 // holds the most fields)
@@ -318,13 +352,17 @@ struct G16L {
     static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
-    typedef G16TwL Tw;
-    template <int NE>
-    using Spec = SpecLds;
+    template <typename T = float>
+    using TwT = G16TwL<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecLds<T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
-    static __device__ __forceinline__ void fwd(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_fwd(v, t, xb, w); }
-    static __device__ __forceinline__ void inv(cf (&v)[8], int t, cf* xb, const Tw& w) { g16_inv(v, t, xb, w); }
+    template <typename T, class TW>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_fwd(v, t, xb, w); }
+    template <typename T, class TW>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_inv(v, t, xb, w); }
 };
 
 // Term structure of the K d passes (Eq 55, 77-78): each term convolves input
@@ -386,14 +424,15 @@ constexpr int term_of()
 // Y (+)= the spectrum of term K applied to its input: T_e Z for part 1, the
 // reflected kernel's spectrum (T_e for even e, its conjugate for odd e) for
 // part 2.  T_e is real for even e and imaginary for odd e (one float each).
-template <class Lay, class B, int PART, int J, int K, bool FIRST, int NIN, int R, class Sp>
-__device__ __forceinline__ void apply_term(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp)
+template <class Lay, class B, int PART, int J, int K, bool FIRST, int NIN, int R, class Sp, typename T>
+__device__ __forceinline__ void apply_term(const cplx<T> (&Z)[NIN][R], cplx<T> (&Y)[R], const Sp& sp)
 {
+    typedef cplx<T> cf;
     constexpr RTerm tm = rpass<B, PART, J>().t[K];
     static_assert(tm.in >= 0 && tm.in < NIN, "term input");
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const float a = sp.template e<Lay, tm.e>(i);
+        const T a = sp.template e<Lay, tm.e>(i);
         const cf z = Z[tm.in][i];
         cf v;
         if constexpr ((tm.e & 1) == 0) v = cf{a * z.x, a * z.y};
@@ -404,8 +443,8 @@ __device__ __forceinline__ void apply_term(const cf (&Z)[NIN][R], cf (&Y)[R], co
     }
 }
 
-template <class Lay, class B, int PART, int J, int O, int NIN, int R, class Sp, int... N>
-__device__ __forceinline__ void combine_o(const cf (&Z)[NIN][R], cf (&Y)[R], const Sp& sp,
+template <class Lay, class B, int PART, int J, int O, int NIN, int R, class Sp, typename T, int... N>
+__device__ __forceinline__ void combine_o(const cplx<T> (&Z)[NIN][R], cplx<T> (&Y)[R], const Sp& sp,
                                           std::integer_sequence<int, N...>)
 {
     static_assert(term_of<B, PART, J, O, 0>() >= 0, "every output has a term");
@@ -416,8 +455,8 @@ __device__ __forceinline__ void combine_o(const cf (&Z)[NIN][R], cf (&Y)[R], con
      ...);
 }
 
-template <class Lay, class B, int PART, int J, int NIN, int R, class Sp, int... O>
-__device__ __forceinline__ void combine_sel(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp,
+template <class Lay, class B, int PART, int J, int NIN, int R, class Sp, typename T, int... O>
+__device__ __forceinline__ void combine_sel(const cplx<T> (&Z)[NIN][R], int o, cplx<T> (&Y)[R], const Sp& sp,
                                             std::integer_sequence<int, O...>)
 {
     ((o == O ? combine_o<Lay, B, PART, J, O>(Z, Y, sp, std::make_integer_sequence<int, 3>{}) : void()),
@@ -427,24 +466,25 @@ __device__ __forceinline__ void combine_sel(const cf (&Z)[NIN][R], int o, cf (&Y
 // Spectra of output o of pass (PART, J) from the input spectra Z (fwd's
 // layout).  o is constant once the caller's loop over the outputs is
 // unrolled, so the selection folds away.
-template <class Lay, class B, int PART, int J, int NIN, int R, class Sp>
-__device__ __forceinline__ void combine(const cf (&Z)[NIN][R], int o, cf (&Y)[R], const Sp& sp)
+template <class Lay, class B, int PART, int J, int NIN, int R, class Sp, typename T>
+__device__ __forceinline__ void combine(const cplx<T> (&Z)[NIN][R], int o, cplx<T> (&Y)[R], const Sp& sp)
 {
     combine_sel<Lay, B, PART, J>(Z, o, Y, sp, std::make_integer_sequence<int, rpass<B, PART, J>().nout>{});
 }
 
-struct RArgs {
-    const float* in;          // real fields fstride apart (or the field masked by mask_in)
+template <typename T>
+struct RArgsT {
+    const T* in;              // real fields fstride apart (or the field masked by mask_in)
     const uint8_t* mask_in;
-    float* out;
+    T* out;
     const uint8_t* mask_out;  // masked single-field store (and dot), else NULL
     long fstride;             // floats between fields
     long in_rb, out_rb;       // floats between right-hand sides (blockIdx.y)
     long st;                  // element stride of the axis; 1 for x
-    const float* tr;          // [3][L]: Re T_0 / L, Im T_1 / L, Re T_2 / L of the axis
-    const cf* tw;             // [L] e^{-2 pi i j / L}
+    const T* tr;              // [3][L]: Re T_0 / L, Im T_1 / L, Re T_2 / L of the axis
+    const cplx<T>* tw;        // [L] e^{-2 pi i j / L}
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
-    const float* dot_with;
+    const T* dot_with;
     const uint2* nbits;       // middle pass, per lane: .x bit 2m+c set if node c of element
                               // m is interior, .y bit m set if element m reads a record
     const uint32_t* noff;     // middle pass: per lane, its first record
@@ -453,13 +493,14 @@ struct RArgs {
                                   // order) or b^a (a-major) and V (quadratic basis)
     // first x pass inside CG (PUPD): the pending direction update p = r + beta p
     // with beta = (sum of rr_part) / scal[parity], written back to `in`
-    const float* rvec;
+    const T* rvec;
     const double* rr_part;
     int nrr;
     double* scal;
     int parity;
     const int* act;
 };
+typedef RArgsT<float> RArgs;
 
 // The pointwise stage of the middle pass (Eq 90-91) regrouped: with B the
 // 3 x 4 matrix b^a_q of a node, E_p = V sum_a b^a_p sum_q b^a_q D_q equals
@@ -477,8 +518,8 @@ __host__ __device__ constexpr int sym_index(int p, int q)
 }
 
 // e = M d for the symmetric M of one node
-__device__ __forceinline__ void sym4_apply(const float* M, float d0, float d1, float d2, float d3,
-                                           float (&e)[4])
+template <typename T>
+__device__ __forceinline__ void sym4_apply(const T* M, T d0, T d1, T d2, T d3, T (&e)[4])
 {
     e[0] = M[0] * d0 + M[1] * d1 + M[2] * d2 + M[3] * d3;
     e[1] = M[1] * d0 + M[4] * d1 + M[5] * d2 + M[6] * d3;
@@ -507,22 +548,25 @@ __device__ __forceinline__ long elem_index(long base, int g, int t, int m, long 
     return base + 2 * g + (long)i * st;
 }
 
-template <int L, bool CONTIG>
-__device__ __forceinline__ cf load_pair(const float* p, long idx)
+template <typename T>
+using vec2_of = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+
+template <int L, bool CONTIG, typename T>
+__device__ __forceinline__ cplx<T> load_pair(const T* p, long idx)
 {
-    if (CONTIG) return cf{p[idx], p[idx + L]};
-    const float2 v = *reinterpret_cast<const float2*>(p + idx);
-    return cf{v.x, v.y};
+    if (CONTIG) return cplx<T>{p[idx], p[idx + L]};
+    const vec2_of<T> v = *reinterpret_cast<const vec2_of<T>*>(p + idx);
+    return cplx<T>{v.x, v.y};
 }
 
-template <int L, bool CONTIG>
-__device__ __forceinline__ void store_pair(float* p, long idx, cf v)
+template <int L, bool CONTIG, typename T>
+__device__ __forceinline__ void store_pair(T* p, long idx, cplx<T> v)
 {
     if (CONTIG) {
         p[idx] = v.x;
         p[idx + L] = v.y;
     } else {
-        *reinterpret_cast<float2*>(p + idx) = float2{v.x, v.y};
+        *reinterpret_cast<vec2_of<T>*>(p + idx) = vec2_of<T>{v.x, v.y};
     }
 }
 
@@ -550,16 +594,17 @@ __device__ __forceinline__ long xcd_tile(long b, long nblocks)
 // LDS, the NE spectra: each thread loads its share into registers (fetch)
 // and writes it to LDS later (put), so these loads and those of the input
 // lines are in flight together.
-template <class Lay, int NE>
+template <class Lay, int NE, typename T = float>
 struct Tables {
     static constexpr int L = Lay::L;
-    static constexpr bool SPEC = std::is_same<typename Lay::template Spec<NE>, SpecLds>::value;
+    static constexpr bool SPEC = std::is_same<typename Lay::template Spec<NE, T>, SpecLds<T>>::value;
     static constexpr int NT = (L + kRT - 1) / kRT;                     // twiddles per thread
     static constexpr int NS = SPEC ? (NE * L + kRT - 1) / kRT : 0;     // spectrum values per thread
-    static constexpr int LDS_SPEC = SPEC ? NE * L : 1;                 // floats of the LDS copy
-    cf w[NT];
-    float s[NS > 0 ? NS : 1];
-    __device__ __forceinline__ void fetch(const RArgs& a)
+    static constexpr int LDS_SPEC = SPEC ? NE * L : 1;                 // values of the LDS copy
+    cplx<T> w[NT];
+    T s[NS > 0 ? NS : 1];
+    template <class A>
+    __device__ __forceinline__ void fetch(const A& a)
     {
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
@@ -572,7 +617,7 @@ struct Tables {
             if (e < NE * L) s[i] = a.tr[e];
         }
     }
-    __device__ __forceinline__ void put(cf* tw, float* trl) const
+    __device__ __forceinline__ void put(cplx<T>* tw, T* trl) const
     {
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
@@ -598,8 +643,8 @@ struct Tables {
 // (consecutive threads vary g) and the reads (consecutive lanes vary t) free
 // of bank conflicts.  Callers alternate two buffers, so the barrier of one
 // move also orders the reads of the move before it against the next writes.
-template <class Lay>
-__device__ __forceinline__ void stage_move(cf (&v)[Lay::PTS], cf* buf, int gw, int tw, int gr, int tr)
+template <class Lay, typename T>
+__device__ __forceinline__ void stage_move(cplx<T> (&v)[Lay::PTS], cplx<T>* buf, int gw, int tw, int gr, int tr)
 {
 #pragma unroll
     for (int m = 0; m < Lay::PTS; ++m) buf[m * Lay::SS + tw * Lay::TP + gw] = v[m];
@@ -614,21 +659,26 @@ __device__ __forceinline__ void stage_move(cf (&v)[Lay::PTS], cf* buf, int gw, i
 // TPW tiles per workgroup: the inputs of all of them are loaded up front, so
 // the later tiles' loads overlap the earlier tiles' transforms and stores.
 template <class Lay, class B, int TPW, bool CONTIG, bool LMASK, bool SMASK, int PART, int J,
-          bool PUPD = false>
-__global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
+          bool PUPD = false, typename T = float>
+__global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
 {
+    typedef cplx<T> cf;
     constexpr int L = Lay::L, R = Lay::PTS;
+    // FP32 strided passes stage global memory through LDS (row-major map);
+    // FP64 ones read their 16-byte pairs directly in the transform layout
+    // (64-byte row segments per wave), which keeps their LDS small
+    constexpr bool STG = !CONTIG && sizeof(T) == 4;
     constexpr int NIN = rpass<B, PART, J>().nin, NOUT = rpass<B, PART, J>().nout;
     __shared__ cf tw[L];
-    __shared__ float trl[Tables<Lay, B::NE>::LDS_SPEC];
+    __shared__ T trl[Tables<Lay, B::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
-    __shared__ cf stage[CONTIG ? 1 : 2][CONTIG ? 1 : Lay::STAGE];
+    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
-    const int gc = CONTIG ? g : tid % Lay::GROUPS, tc = CONTIG ? t : tid / Lay::GROUPS;
+    const int gc = STG ? tid % Lay::GROUPS : g, tc = STG ? tid / Lay::GROUPS : t;
     const long rhs = blockIdx.y;
-    const float* in = a.in + rhs * a.in_rb;
-    float* out = a.out + rhs * a.out_rb;
+    const T* in = a.in + rhs * a.in_rb;
+    T* out = a.out + rhs * a.out_rb;
     const long tile0 = xcd_tile(blockIdx.x, gridDim.x) * TPW;
     cf* xb = xbuf + g * Lay::XS;
     // the partials of the pending update's r.r are loaded first (all
@@ -640,9 +690,9 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 #pragma unroll
         for (int k = 0; k < NPART; ++k) part[k] = a.rr_part[rhs * kRedBlocks + tid + k * kRT];
     }
-    Tables<Lay, B::NE> tabs;
+    Tables<Lay, B::NE, T> tabs;
     tabs.fetch(a);
-    typename Lay::template Spec<B::NE> sp;
+    typename Lay::template Spec<B::NE, T> sp;
     sp.template fetch<Lay>(a.tr, t);
 
     cf Z[TPW][NIN][R];
@@ -685,7 +735,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
                 if (tid + k * kRT < a.nrr) v += part[k];
             const double rr_new = block_sum(v, sh);
             const double rr_old = a.scal[rhs * kScal + a.parity];
-            const float beta = rr_old > 0.0 ? float(rr_new / rr_old) : 0.0f;
+            const T beta = rr_old > 0.0 ? T(rr_new / rr_old) : T(0);
             if (blockIdx.x == 0 && tid == 0) a.scal[rhs * kScal + 1 - a.parity] = rr_new;
 #pragma unroll
             for (int tt = 0; tt < TPW; ++tt) {
@@ -694,7 +744,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
                 for (int m = 0; m < R; ++m) {
                     const cf pv = Z[tt][0][m], rv = Rv[tt][m];
                     Z[tt][0][m] = cf{rv.x + beta * pv.x, rv.y + beta * pv.y};
-                    store_pair<L, CONTIG>(const_cast<float*>(in), elem_index<Lay, CONTIG>(base, gc, tc, m, a.st),
+                    store_pair<L, CONTIG>(const_cast<T*>(in), elem_index<Lay, CONTIG>(base, gc, tc, m, a.st),
                                           Z[tt][0][m]);
                 }
             }
@@ -707,16 +757,16 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const cf v = Z[tt][0][m];
-                Z[tt][0][m] = cf{mk[tt][m][0] ? v.x : 0.0f, mk[tt][m][1] ? v.y : 0.0f};
+                Z[tt][0][m] = cf{mk[tt][m][0] ? v.x : T(0), mk[tt][m][1] ? v.y : T(0)};
             }
         }
     }
     // the masked store's mask bytes and the dot's other vector, loaded after
     // the fields (loads complete in order) so they arrive during the transforms
     uint8_t mo[SMASK ? TPW : 1][SMASK ? R : 1][2];
-    float dwv[SMASK ? TPW : 1][SMASK ? R : 1][2];
+    T dwv[SMASK ? TPW : 1][SMASK ? R : 1][2];
     if constexpr (SMASK) {
-        const float* dw = a.dot_with + rhs * a.out_rb;
+        const T* dw = a.dot_with + rhs * a.out_rb;
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt) {
             const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
@@ -735,7 +785,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     }
     tabs.put(tw, trl);
     sp.template bind<Lay>(trl, t);
-    typename Lay::Tw lw;
+    typename Lay::template TwT<T> lw;
     lw.make(t, tw);
     double dacc = 0.0;
 #pragma unroll
@@ -743,7 +793,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
     const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
-        if constexpr (!CONTIG) stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) & 1], gc, tc, g, t);
+        if constexpr (STG) stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) & 1], gc, tc, g, t);
         Lay::fwd(Z[tt][f], t, xb, lw);
     }
 #pragma unroll
@@ -751,13 +801,13 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgs a)
         cf Y[R];
         combine<Lay, B, PART, J>(Z[tt], o, Y, sp);
         Lay::inv(Y, t, xb, lw);
-        if constexpr (!CONTIG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
+        if constexpr (STG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
             if constexpr (SMASK) {
-                const float v0 = mo[tt][m][0] ? Y[m].x : 0.0f;
-                const float v1 = mo[tt][m][1] ? Y[m].y : 0.0f;
+                const T v0 = mo[tt][m][0] ? Y[m].x : T(0);
+                const T v1 = mo[tt][m][1] ? Y[m].y : T(0);
                 store_pair<L, CONTIG>(out, idx, cf{v0, v1});
                 if (a.dot_part)
                     dacc += (double)v0 * (double)dwv[tt][m][0] + (double)v1 * (double)dwv[tt][m][1];
@@ -1173,17 +1223,32 @@ struct SymTab {
     int wz[kSymW];           // window nodes: the correction nodes +- m, ascending
     float tap0[8], tap1[8];  // t_0[o], t_1[o] for o = -m .. m
     signed char widx[128];   // window index of every z (-1: not in the window)
+    double dtap0[8], dtap1[8];  // the same taps in FP64
 };
+
+template <typename T>
+__device__ __forceinline__ T tap0_of(const SymTab& tb, int k)
+{
+    if constexpr (sizeof(T) == 4) return tb.tap0[k];
+    else return tb.dtap0[k];
+}
+template <typename T>
+__device__ __forceinline__ T tap1_of(const SymTab& tb, int k)
+{
+    if constexpr (sizeof(T) == 4) return tb.tap1[k];
+    else return tb.dtap1[k];
+}
 static_assert(sizeof(SymTab) % 4 == 0, "SymTab is copied in words");
 
+template <typename T>
 struct SArgs {
-    const float* in;
-    float* out;
+    const T* in;
+    T* out;
     long fstride, in_rb, out_rb, st;
-    const float* tr;       // [2][L]: Re T_0 / L, Im T_1 / L of the axis
-    const cf* tw;
+    const T* tr;           // [2][L]: Re T_0 / L, Im T_1 / L of the axis
+    const cplx<T>* tw;
     const int* pidx;       // per pair: its record
-    const float* rec;      // records: M-bar (10), dM' (10), per correction node the 10
+    const T* rec;          // records: M-bar (10), dM' (10), per correction node the 10
                            // entries of dM for both lines interleaved, ..., flag
     const SymTab* tab;
 };
@@ -1204,9 +1269,10 @@ __device__ __forceinline__ int freq_slot(int k)
 
 // w[i] = conj X(-k) where v[i] = X(k), k = freq(t, i): the spectrum of the
 // pair's other orientation, from the lane that holds -k (through LDS)
-template <class Lay>
-__device__ __forceinline__ void conj_neg(const cf (&v)[Lay::PTS], cf (&w)[Lay::PTS], int t, cf* xb)
+template <class Lay, typename T>
+__device__ __forceinline__ void conj_neg(const cplx<T> (&v)[Lay::PTS], cplx<T> (&w)[Lay::PTS], int t, cplx<T>* xb)
 {
+    typedef cplx<T> cf;
     constexpr int R = Lay::PTS, L = Lay::L;
 #pragma unroll
     for (int i = 0; i < R; ++i) xb[i * Lay::LANES + t] = v[i];
@@ -1226,18 +1292,19 @@ __device__ __forceinline__ void conj_neg(const cf (&v)[Lay::PTS], cf (&w)[Lay::P
 // and T_1 = i b (imaginary), D = (a X0, a X1, a X2, i b X0), E = M D and
 // Z = (a E0 - i b E3, a E1, a E2); the products carry one factor 1/L (the
 // inverse transform's), the stored spectra one each.
-template <class Lay, class Sp, bool ADD>
-__device__ __forceinline__ void sym_apply(const cf (&X)[3][Lay::PTS], cf (&Y)[3][Lay::PTS], const float* M,
+template <class Lay, class Sp, bool ADD, typename T>
+__device__ __forceinline__ void sym_apply(const cplx<T> (&X)[3][Lay::PTS], cplx<T> (&Y)[3][Lay::PTS], const T* M,
                                           const Sp& sp)
 {
+    typedef cplx<T> cf;
 #pragma unroll
     for (int i = 0; i < Lay::PTS; ++i) {
-        const float a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
-        const float A2 = (float)Lay::L * a * a, AB = (float)Lay::L * a * b, B2 = (float)Lay::L * b * b;
-        const float s00 = M[0] * A2 + M[9] * B2;
-        const float r01 = M[1] * A2, i01 = -M[6] * AB;   // S_01 = M01 a^2 - i M13 a b
-        const float r02 = M[2] * A2, i02 = -M[8] * AB;   // S_02 = M02 a^2 - i M23 a b
-        const float s11 = M[4] * A2, s12 = M[5] * A2, s22 = M[7] * A2;
+        const T a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
+        const T A2 = (T)Lay::L * a * a, AB = (T)Lay::L * a * b, B2 = (T)Lay::L * b * b;
+        const T s00 = M[0] * A2 + M[9] * B2;
+        const T r01 = M[1] * A2, i01 = -M[6] * AB;   // S_01 = M01 a^2 - i M13 a b
+        const T r02 = M[2] * A2, i02 = -M[8] * AB;   // S_02 = M02 a^2 - i M23 a b
+        const T s11 = M[4] * A2, s12 = M[5] * A2, s22 = M[7] * A2;
         const cf x0 = X[0][i], x1 = X[1][i], x2 = X[2][i];
         const cf y0 = {s00 * x0.x + r01 * x1.x - i01 * x1.y + r02 * x2.x - i02 * x2.y,
                        s00 * x0.y + r01 * x1.y + i01 * x1.x + r02 * x2.y + i02 * x2.x};
@@ -1257,34 +1324,33 @@ __device__ __forceinline__ void sym_apply(const cf (&X)[3][Lay::PTS], cf (&Y)[3]
     }
 }
 
-template <class Lay>
-__global__ __launch_bounds__(kRT) void k_smid(SArgs a)
+template <class Lay, typename T = float>
+__global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
 {
+    typedef cplx<T> cf;
     constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr bool STG = sizeof(T) == 4;  // FP64: direct loads in the transform layout
     constexpr int CW = 3 * kSymW + 4 * kSymC;  // per group: window values (later the
                                                // output corrections), then dE
     __shared__ cf tw[L];
-    __shared__ float trl[Tables<Lay, Lin3::NE>::LDS_SPEC];
+    __shared__ T trl[Tables<Lay, Lin3::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
-    __shared__ cf stage[2][Lay::STAGE];
+    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
     __shared__ cf cbuf[Lay::GROUPS * CW];
     __shared__ SymTab tb;
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
-    const int gc = tid % Lay::GROUPS, tc = tid / Lay::GROUPS;
+    const int gc = STG ? tid % Lay::GROUPS : g, tc = STG ? tid / Lay::GROUPS : t;
     const long rhs = blockIdx.y;
-    const float* in = a.in + rhs * a.in_rb;
-    float* out = a.out + rhs * a.out_rb;
+    const T* in = a.in + rhs * a.in_rb;
+    T* out = a.out + rhs * a.out_rb;
     const long tile = xcd_tile(blockIdx.x, gridDim.x);
     const long base = tile_base<Lay, false>(tile, a.st);
     cf* xb = xbuf + g * Lay::XS;
     cf* cw = cbuf + g * CW;          // [3][kSymW] window values, then output corrections
     cf* ce = cw + 3 * kSymW;         // [4][kSymC] dE at the correction nodes
-    RArgs ta{};
-    ta.tr = a.tr;
-    ta.tw = a.tw;
-    Tables<Lay, Lin3::NE> tabs;
-    tabs.fetch(ta);
-    typename Lay::template Spec<Lin3::NE> sp;
+    Tables<Lay, Lin3::NE, T> tabs;
+    tabs.fetch(a);
+    typename Lay::template Spec<Lin3::NE, T> sp;
     sp.template fetch<Lay>(a.tr, t);
 
     cf X[3][R];
@@ -1296,15 +1362,17 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
     // the pair's record: the constant part for every lane, the correction
     // node's entries for the correction lanes
     const long pair = tile * Lay::GROUPS + g;
-    const float* rec = a.rec + (size_t)a.pidx[pair] * kSymRec;
+    const T* rec = a.rec + (size_t)a.pidx[pair] * kSymRec;
     if (tid < (int)(sizeof(SymTab) / 4))
         reinterpret_cast<int*>(&tb)[tid] = reinterpret_cast<const int*>(a.tab)[tid];
     tabs.put(tw, trl);  // its barrier also publishes tb
     sp.template bind<Lay>(trl, t);
-    typename Lay::Tw lw;
+    typename Lay::template TwT<T> lw;
     lw.make(t, tw);
+    if constexpr (STG) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+        for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+    }
     // window values of the three inputs
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -1314,10 +1382,10 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
             for (int f = 0; f < 3; ++f) cw[f * kSymW + wi] = X[f][m];
         }
     }
-    float M[10];
+    T M[10];
 #pragma unroll
     for (int e = 0; e < 10; ++e) M[e] = rec[e];
-    const bool mismatch = rec[kSymFlag] != 0.0f;
+    const bool mismatch = rec[kSymFlag] != T(0);
     wave_sync();
     // dE = (M - M_L) D at the correction nodes, D from the taps (part 1: D(c) =
     // sum_o t[o] X(c - o)); each line of the pair with its own dM
@@ -1326,15 +1394,15 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
         cf D[4] = {};
         for (int o = -tb.m; o <= tb.m; ++o) {
             const int wi = tb.widx[(cz - o + L) % L];
-            const float t0 = tb.tap0[o + tb.m], t1 = tb.tap1[o + tb.m];
+            const T t0 = tap0_of<T>(tb, o + tb.m), t1 = tap1_of<T>(tb, o + tb.m);
             const cf x0 = cw[wi], x1 = cw[kSymW + wi], x2 = cw[2 * kSymW + wi];
             D[0] = cf{D[0].x + t0 * x0.x, D[0].y + t0 * x0.y};
             D[1] = cf{D[1].x + t0 * x1.x, D[1].y + t0 * x1.y};
             D[2] = cf{D[2].x + t0 * x2.x, D[2].y + t0 * x2.y};
             D[3] = cf{D[3].x + t1 * x0.x, D[3].y + t1 * x0.y};
         }
-        const float* dm = rec + 20 + 20 * ci;
-        float e0[4], e1[4], MA[10], MB[10];
+        const T* dm = rec + 20 + 20 * ci;
+        T e0[4], e1[4], MA[10], MB[10];
 #pragma unroll
         for (int e = 0; e < 10; ++e) {
             MA[e] = dm[2 * e];
@@ -1353,7 +1421,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
     sym_apply<Lay, decltype(sp), false>(X, Y, M, sp);
     if (mismatch) {
         // lines of different M_L: (M_A + M_B)/2 on X(k) and (M_A - M_B)/2 on conj X(-k)
-        float dMp[10];
+        T dMp[10];
 #pragma unroll
         for (int e = 0; e < 10; ++e) dMp[e] = rec[10 + e];
         cf W[3][R];
@@ -1371,7 +1439,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
             if (d > L / 2) d -= L;
             if (d < -L / 2) d += L;
             if (d < -tb.m || d > tb.m) continue;
-            const float t0 = tb.tap0[d + tb.m], t1 = tb.tap1[d + tb.m];
+            const T t0 = tap0_of<T>(tb, d + tb.m), t1 = tap1_of<T>(tb, d + tb.m);
             const cf e0 = ce[ci], e1 = ce[kSymC + ci], e2 = ce[2 * kSymC + ci], e3 = ce[3 * kSymC + ci];
             z0 = cf{z0.x + t0 * e0.x + t1 * e3.x, z0.y + t0 * e0.y + t1 * e3.y};
             z1 = cf{z1.x + t0 * e1.x, z1.y + t0 * e1.y};
@@ -1396,7 +1464,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs a)
     }
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-        stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
+        if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < R; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
@@ -1448,28 +1516,30 @@ __global__ void k_sym_lines(const double* __restrict__ ba, const double* __restr
 // whose lines both equal the reference pair's (to tol) share record 0, which
 // the reference pair writes; every other pair owns record 1 + pair.
 __global__ void k_sym_pairs(const double* __restrict__ lrec, long npairs, int nc, long pref, double tol,
-                            int* __restrict__ pidx, float* __restrict__ rec, int* __restrict__ own)
+                            int* __restrict__ pidx, float* __restrict__ rec, double* __restrict__ rec64,
+                            int* __restrict__ own)
 {
     const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (p >= npairs) return;
     constexpr int LR = 10 + 10 * kSymC;
     const double* A = lrec + (2 * p) * LR;
     const double* B = A + LR;
-    auto write = [&](float* o) {
+    auto write = [&](float* o, double* o64) {
         bool mism = false;
         for (int e = 0; e < 10; ++e) {
-            o[e] = (float)(0.5 * (A[e] + B[e]));
+            o64[e] = 0.5 * (A[e] + B[e]);
             const double hd = 0.5 * (A[e] - B[e]);
-            o[10 + e] = (float)hd;
+            o64[10 + e] = hd;
             mism = mism || fabs(hd) > tol;
         }
         for (int ci = 0; ci < kSymC; ++ci)
             for (int e = 0; e < 10; ++e) {
-                o[20 + 20 * ci + 2 * e] = ci < nc ? (float)A[10 + 10 * ci + e] : 0.0f;
-                o[20 + 20 * ci + 2 * e + 1] = ci < nc ? (float)B[10 + 10 * ci + e] : 0.0f;
+                o64[20 + 20 * ci + 2 * e] = ci < nc ? A[10 + 10 * ci + e] : 0.0;
+                o64[20 + 20 * ci + 2 * e + 1] = ci < nc ? B[10 + 10 * ci + e] : 0.0;
             }
-        for (int k = 20 + 20 * kSymC; k < kSymRec; ++k) o[k] = 0.0f;
-        o[kSymFlag] = mism ? 1.0f : 0.0f;
+        for (int k = 20 + 20 * kSymC; k < kSymRec; ++k) o64[k] = 0.0;
+        o64[kSymFlag] = mism ? 1.0 : 0.0;
+        for (int k = 0; k < kSymRec; ++k) o[k] = (float)o64[k];
     };
     bool same = pref >= 0;
     if (same) {
@@ -1477,8 +1547,8 @@ __global__ void k_sym_pairs(const double* __restrict__ lrec, long npairs, int nc
         for (int k = 0; k < 10 + 10 * nc && same; ++k)
             same = fabs(A[k] - RA[k]) <= tol && fabs(B[k] - RA[LR + k]) <= tol;
     }
-    write(rec + (size_t)(1 + p) * kSymRec);
-    if (p == pref) write(rec);
+    write(rec + (size_t)(1 + p) * kSymRec, rec64 + (size_t)(1 + p) * kSymRec);
+    if (p == pref) write(rec, rec64);
     pidx[p] = same ? 0 : (int)(1 + p);
     if (!same) atomicAdd(own, 1);
 }
@@ -1488,6 +1558,7 @@ struct SymState {
     SymTab* tab = nullptr;       // device
     int* pidx = nullptr;         // device, per pair
     float* rec = nullptr;        // device, 1 + pairs records
+    double* rec64 = nullptr;     // the same in FP64
     long own = 0;                // pairs with a record of their own
 };
 
@@ -1500,33 +1571,39 @@ double bspline_d(double z)
     return 0.0;
 }
 
-template <class Lay>
-void run_smid(const Ctx& c, const float* in, long irb, float* out, long orb, int nrhs, hipStream_t st,
+template <class Lay, typename T>
+void run_smid(const Ctx& c, const T* in, long irb, T* out, long orb, int nrhs, hipStream_t st,
               const RegProf& prof)
 {
     const SymState& s = *(const SymState*)c.sym;
-    SArgs a{};
+    SArgs<T> a{};
     a.in = in;
     a.in_rb = irb;
     a.out = out;
     a.out_rb = orb;
     a.fstride = c.nn;
     a.st = (long)c.n[0] * c.n[1];
-    a.tr = c.rtab32[2];
-    a.tw = c.tw32[2];
+    if constexpr (sizeof(T) == 4) {
+        a.tr = c.rtab32[2];
+        a.tw = c.tw32[2];
+        a.rec = s.rec;
+    } else {
+        a.tr = c.rtab64[2];
+        a.tw = c.tw64[2];
+        a.rec = s.rec64;
+    }
     a.pidx = s.pidx;
-    a.rec = s.rec;
     a.tab = s.tab;
     const dim3 grid((unsigned)blocks_of<Lay>(c), (unsigned)nrhs), block(kRT);
     hipEvent_t e0, e1;
     prof.events(2, &e0, &e1);
-    if (e0) hipExtLaunchKernelGGL(k_smid<Lay>, grid, block, 0, st, e0, e1, 0, a);
-    else hipLaunchKernelGGL(k_smid<Lay>, grid, block, 0, st, a);
+    if (e0) hipExtLaunchKernelGGL((k_smid<Lay, T>), grid, block, 0, st, e0, e1, 0, a);
+    else hipLaunchKernelGGL((k_smid<Lay, T>), grid, block, 0, st, a);
 }
 
 // launch of pass k, with the sampler's events recorded by the launch itself
-template <typename K>
-void rlaunch(const RegProf& prof, int k, K kern, dim3 grid, dim3 block, hipStream_t st, const RArgs& a)
+template <typename K, typename A>
+void rlaunch(const RegProf& prof, int k, K kern, dim3 grid, dim3 block, hipStream_t st, const A& a)
 {
     hipEvent_t e0, e1;
     prof.events(k, &e0, &e1);
@@ -1586,7 +1663,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         if constexpr (B::DEGREE == 1) {
             constexpr bool SYM_LAYOUT = !std::is_same<Lay, G8<16>>::value;
             if (SYM_LAYOUT && sym_active(c)) {
-                if constexpr (SYM_LAYOUT) run_smid<Lay>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
+                if constexpr (SYM_LAYOUT) run_smid<Lay, float>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
             } else {
                 for (int k = 0; k < 10; ++k) a.ci[k] = c.reg_mi[k];
                 rlaunch(prof, 2, k_rmid<Lay, TPW, 3, 3>, grid, block, st, a);
@@ -1610,6 +1687,53 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.dot_part = dot_part;
         a.dot_with = dot_with;
         rlaunch(prof, 4, k_rpass<Lay, B, TPW, true, false, true, 2, 0>, grid, block, st, a);
+    }
+}
+
+// The FP64 K product on the register path: the same five passes with FP64
+// lines (the 16-lane layout reads its twiddles and spectra from LDS), the
+// line-constant middle pass, and the optional p.q partials in the last pass.
+template <class Lay>
+void run_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
+             double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof)
+{
+    const long nn = c.nn;
+    const long slot_rb = 2L * c.basis_plan.maxpairs * nn;  // doubles between rhs in a workspace slot
+    double* S1 = reinterpret_cast<double*>(c.work64);
+    double* S2 = S1 + slot_rb * c.cap_work;
+    const dim3 grid((unsigned)blocks_of<Lay>(c), (unsigned)nrhs), block(kRT);
+    auto args = [&](int axis, const double* i, long irb, double* o, long orb) {
+        RArgsT<double> a{};
+        a.in = i;
+        a.in_rb = irb;
+        a.out = o;
+        a.out_rb = orb;
+        a.fstride = nn;
+        a.st = axis == 0 ? 1 : (axis == 1 ? (long)c.n[0] : (long)c.n[0] * c.n[1]);
+        a.tr = c.rtab64[axis];
+        a.tw = c.tw64[axis];
+        return a;
+    };
+    {
+        RArgsT<double> a = args(0, in, nn, S1, slot_rb);
+        a.mask_in = mask;
+        rlaunch(prof, 0, k_rpass<Lay, Lin3, 1, true, true, false, 1, 0, false, double>, grid, block, st, a);
+    }
+    {
+        RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
+        rlaunch(prof, 1, k_rpass<Lay, Lin3, 1, false, false, false, 1, 1, false, double>, grid, block, st, a);
+    }
+    run_smid<Lay, double>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
+    {
+        RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
+        rlaunch(prof, 3, k_rpass<Lay, Lin3, 1, false, false, false, 2, 1, false, double>, grid, block, st, a);
+    }
+    {
+        RArgsT<double> a = args(0, S2, slot_rb, out, nn);
+        a.mask_out = mask;
+        a.dot_part = dot_part;
+        a.dot_with = dot_with;
+        rlaunch(prof, 4, k_rpass<Lay, Lin3, 1, true, false, true, 2, 0, false, double>, grid, block, st, a);
     }
 }
 
@@ -1825,6 +1949,22 @@ int reg_path_blocks(const Ctx& c)
     return (int)(b / c.reg_tpw);
 }
 
+bool sym_ready(const Ctx& c);
+
+bool reg_path64_ok(const Ctx& c)
+{
+    return c.degree == 1 && reg_path_ok(c) && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
+}
+
+long reg_path64_blocks(const Ctx& c) { return c.n[0] == 128 ? blocks_of<G16L>(c) : blocks_of<G8<8>>(c); }
+
+void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
+                    double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof)
+{
+    if (c.n[0] == 128) run_k64<G16L>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else run_k64<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+}
+
 void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int nrhs,
                   double* dot_part, const float* dot_with, hipStream_t st, const RegProf& prof,
                   const RegPupd* pu)
@@ -1874,22 +2014,27 @@ void sym_release(Ctx& c)
     sym_free(s->tab);
     sym_free(s->pidx);
     sym_free(s->rec);
+    sym_free(s->rec64);
     delete s;
     c.sym = nullptr;
 }
 
-bool sym_active(const Ctx& c)
+// the line-constant records exist for the coefficient rows in use (K's)
+bool sym_ready(const Ctx& c)
 {
-    return c.sym && c.use_sym && ((const SymState*)c.sym)->ba == c.ba_64 && c.degree == 1 &&
-           (c.n[0] == 64 || c.reg_layout == 1);
+    return c.sym && c.use_sym && ((const SymState*)c.sym)->ba == c.ba_64 && c.degree == 1;
 }
 
-double sym_pass_bytes(const Ctx& c)
+// ... and the FP32 product's line layout has the kernel (8-lane 128-point
+// lines hold too many values for it)
+bool sym_active(const Ctx& c) { return sym_ready(c) && (c.n[0] == 64 || c.reg_layout == 1); }
+
+double sym_pass_bytes(const Ctx& c, int elem_bytes)
 {
     const SymState& s = *(const SymState*)c.sym;
     const double pairs = (double)c.nn / c.n[2] / 2.0;
     // three fields in, three out; a record index per pair; the records
-    return (double)c.nn * 24.0 + pairs * 4.0 + (double)(s.own + 1) * kSymRec * 4.0;
+    return (double)c.nn * 6.0 * elem_bytes + pairs * 4.0 + (double)(s.own + 1) * kSymRec * elem_bytes;
 }
 
 // Builds the line-constant middle pass for K's coefficient rows when every z
@@ -1947,6 +2092,8 @@ void sym_build(Ctx& c, hipStream_t st)
         const double w = bspline_d((double)o / c.at[2]);
         tab.tap0[o + m] = (float)w;
         tab.tap1[o + m] = (float)(o * w);
+        tab.dtap0[o + m] = w;
+        tab.dtap1[o + m] = o * w;
     }
     // the scale of M: the interior nodes' V B^T B
     double mscale = 0.0;
@@ -1965,6 +2112,7 @@ void sym_build(Ctx& c, hipStream_t st)
     int* czl = nullptr;
     int* flag = nullptr;
     bool ok = sym_alloc(s->tab, 1) && sym_alloc(s->pidx, npairs) && sym_alloc(s->rec, (size_t)(npairs + 1) * kSymRec) &&
+              sym_alloc(s->rec64, (size_t)(npairs + 1) * kSymRec) &&
               sym_alloc(lrec, (size_t)nlines * (10 + 10 * kSymC)) && sym_alloc(czl, kSymC) && sym_alloc(flag, 2);
     if (ok) {
         int hflag[2] = {0, 0};
@@ -1975,7 +2123,7 @@ void sym_build(Ctx& c, hipStream_t st)
                            nlines, L, c.nn, zref, tab.nc, czl, tol, lrec, flag);
         const long pref = ((long)(c.n[0] / 2) + (long)c.n[0] * (c.n[1] / 2)) / 2;
         hipLaunchKernelGGL(k_sym_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec, npairs,
-                           tab.nc, pref, tol, s->pidx, s->rec, flag + 1);
+                           tab.nc, pref, tol, s->pidx, s->rec, s->rec64, flag + 1);
         (void)hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, st);
         ok = hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess && hflag[0] == 0;
         s->own = hflag[1];
