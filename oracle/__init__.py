@@ -120,6 +120,7 @@ class Oracle:
         hh[: self.dim] = h
         aa = np.zeros(3)
         aa[: self.dim] = at
+        self._hh = hh[: self.dim].copy()
         self.chi = np.ascontiguousarray(chi, dtype=np.uint8).reshape(self.shape)
         self._vol = None if vol is None else _f64(vol).reshape(self.shape)
         vptr = None if self._vol is None else self._vol.ctypes.data_as(C.c_void_p)
@@ -299,6 +300,99 @@ class Oracle:
             its += k
             d = d + np.where(f, delta, 0.0)
         return d, maxnewton, its
+
+    def solve_nonlinear_cg(self, free, dirichlet, r, kappa, kind="cubic", g=None, tol=1e-12,
+                           maxit=100000, ls_tol=1e-14, ls_maxit=50):
+        """Static nonlinear solve by nonlinear conjugate gradients (App. B.3,
+        Alg B.3): from d = d_G, repeated evaluations of the nonlinear force
+        update d until ||R(d)|| <= tol ||chi_Omega f^r|| on the free rows.
+
+        kind "cubic":    R(d) = K d + N^T (V kappa (N d)^3) - f^r  (force of
+                         Eq B.2/B.4 with N(u) = kappa u^3), the gradient of
+                         Pi(d) = d^T K d / 2 + sum_S V_S kappa u_S^4 / 4 - f^r . d;
+        kind "gradient": R(d) = B^T (V (1 + kappa |B d|^2) B d) - f^r  (force of
+                         Eq B.6/B.8 with N(g) = (1 + kappa |g|^2) g), the gradient of
+                         Pi(d) = sum_S V_S (|g_S|^2 / 2 + kappa |g_S|^4 / 4) - f^r . d.
+
+        Both energies are convex for kappa >= 0, so the minimiser is unique.
+        Directions are Polak-Ribiere with restarts (beta >= 0); the step along
+        p minimises Pi exactly: phi'(alpha) = R(d + alpha p) . p is a sum of
+        nodal terms in u + alpha w (w = N p) or g + alpha h (h = B p) plus a
+        linear part, and Newton's method on it runs to ls_tol.  Returns (d,
+        iterations, final ||R|| / ||chi_Omega f^r||)."""
+        shape = self.shape
+        f = np.asarray(free).reshape(shape).astype(bool)
+        dom = self.chi > 0
+        V = self._vol if self._vol is not None else np.where(dom, float(np.prod(self._hh)), 0.0)
+        V = np.where(dom, V, 0.0)
+        d = np.zeros(shape)
+        if g is not None:
+            d = np.where(np.asarray(dirichlet).reshape(shape).astype(bool), _f64(g).reshape(shape), 0.0)
+        fr = self.apply_fr(r)
+        fn = float(np.linalg.norm(np.where(f, fr, 0.0)))
+        if fn == 0.0:
+            return d, 0, 0.0
+        if kind == "cubic":
+            u = self.apply_uh(d)
+            kd = self.apply_k(d)
+
+            def resid():
+                return np.where(f, kd + self.apply_fr(kappa * u ** 3) - fr, 0.0)
+        elif kind == "gradient":
+            gd = self.apply_b(d)
+
+            def resid():
+                return np.where(f, self.apply_btv((1.0 + kappa * (gd ** 2).sum(axis=0)) * gd) - fr, 0.0)
+        else:
+            raise ValueError("kind must be 'cubic' or 'gradient'")
+        R = resid()
+        rr = -R
+        p = rr.copy()
+        rn = float(np.vdot(rr, rr))
+        for it in range(maxit + 1):
+            if math.sqrt(rn) <= tol * fn or it == maxit:
+                return d, it, math.sqrt(rn) / fn
+            # exact line search along p: phi'(alpha) = 0
+            if kind == "cubic":
+                w = self.apply_uh(p)
+                kp = self.apply_k(p)
+                c0 = float(np.vdot(kd - fr, p))
+                c1 = float(np.vdot(kp, p))
+
+                def dphi(a):
+                    ua = u + a * w
+                    return (c0 + a * c1 + float(np.sum(V * kappa * ua ** 3 * w)),
+                            c1 + float(np.sum(3.0 * V * kappa * ua ** 2 * w ** 2)))
+            else:
+                h = self.apply_b(p)
+                c0 = -float(np.vdot(fr, p))
+
+                def dphi(a):
+                    ga = gd + a * h
+                    s2 = (ga ** 2).sum(axis=0)
+                    gh = (ga * h).sum(axis=0)
+                    h2 = (h ** 2).sum(axis=0)
+                    return (c0 + float(np.sum(V * (1.0 + kappa * s2) * gh)),
+                            float(np.sum(V * ((1.0 + kappa * s2) * h2 + 2.0 * kappa * gh ** 2))))
+            a = 0.0
+            for _ in range(ls_maxit):
+                d1, d2 = dphi(a)
+                step = d1 / d2
+                a -= step
+                if abs(step) <= ls_tol * abs(a):
+                    break
+            d = d + a * p
+            if kind == "cubic":
+                u = u + a * w
+                kd = kd + a * kp
+            else:
+                gd = gd + a * h
+            rr_new = -resid()
+            rn_new = float(np.vdot(rr_new, rr_new))
+            beta = max(0.0, float(np.vdot(rr_new, rr_new - rr)) / rn)
+            p = rr_new + beta * p
+            rr, rn = rr_new, rn_new
+        return d, maxit, math.sqrt(rn) / fn
 
     # --- time-dependent problems (App. C) -----------------------------------
     def apply_m(self, d):
