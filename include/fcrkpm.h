@@ -309,6 +309,44 @@ fcrkpm_status fcrkpm_solve_nonlinear(fcrkpm_ctx* ctx, int32_t mode, double kappa
                                      double newton_tol, int32_t maxnewton, int32_t maxit,
                                      fcrkpm_info* info, void* stream);
 
+/* Nonlinear forces of fcrkpm_solve_nonlinear_cg (App. B.1). */
+enum {
+    FCRKPM_NONLIN_CUBIC = 0,    /* N(u) = kappa u^3 in the force N^T N(u^h)               (Eq B.2, B.4, B.9) */
+    FCRKPM_NONLIN_GRADIENT = 1  /* N(grad u) = (1 + kappa |grad u|^2) grad u in B^T N    (Eq B.6, B.8, B.10) */
+};
+
+/*
+ * fcrkpm_solve_nonlinear_cg -- the static nonlinear problem by nonlinear
+ * conjugate gradients (App. B.3, Alg B.3): from d_inout (d = g on the
+ * Dirichlet nodes), repeated force evaluations (Alg B.1/B.2) drive the
+ * residual over the free rows
+ *     FCRKPM_NONLIN_CUBIC:    R(d) = K d + N^T (V kappa (N d)^3) - f^r
+ *     FCRKPM_NONLIN_GRADIENT: R(d) = B^T (V (1 + kappa |B d|^2) B d) - f^r
+ * to ||R|| <= tol ||chi_Omega f^r||.  Both are gradients of convex energies
+ * (kappa >= 0), so the minimiser is unique; directions are Polak-Ribiere with
+ * restarts, steps an exact line search (Newton on the nodal sums of the
+ * energy's derivative along the direction).  FP64 throughout; one field.
+ *
+ *   kind        FCRKPM_NONLIN_*
+ *   kappa       >= 0
+ *   r, g        device FP64 source and Dirichlet values (g may be NULL)
+ *   d_inout     device FP64 initial guess on the free nodes in (zeros = Alg
+ *               B.3's start), solution out
+ *   uh_out      device FP64 u^h = N d, or NULL
+ *   tol, maxit  residual target and iteration cap
+ *   info        one record (may be NULL): iters = nonlinear CG iterations,
+ *               outer_iters = line-search Newton steps, rel_res = true_rel_res
+ *               = final ||R|| / ||chi_Omega f^r||, matvecs_f64 = K-type products
+ *
+ * Allocates its work vectors for the call (about 10 node fields).  Errors:
+ * FCRKPM_ERR_ARG (kind, kappa, tol, maxit, NULL or non-finite inputs);
+ * FCRKPM_ERR_NOCONV when tol is not reached within maxit (d holds the last
+ * iterate).
+ */
+fcrkpm_status fcrkpm_solve_nonlinear_cg(fcrkpm_ctx* ctx, int32_t kind, double kappa, const double* r,
+                                        const double* g, double* d_inout, double* uh_out, double tol,
+                                        int32_t maxit, fcrkpm_info* info, void* stream);
+
 /*
  * fcrkpm_transient -- time stepping of the diffusion problem (App. C, Eq C.1-
  * C.4): M d' + nu K d = f^r with strong Dirichlet values d = g held on the

@@ -2358,6 +2358,199 @@ extern "C" fcrkpm_status fcrkpm_gradient_force(fcrkpm_ctx* ctx, double kappa, in
     });
 }
 
+namespace {
+// B x: the implicit gradient at every node, component a from the u^h passes
+// with the coefficient rows b^a in place of b^0 (Eq 15-16, Alg 3 with b^a)
+void apply_grad(Ctx& c, const double* x, double* out, hipStream_t st)
+{
+    double* keep = c.b0_64;
+    struct Restore {
+        Ctx& c;
+        double* p;
+        ~Restore() { c.b0_64 = p; }
+    } restore{c, keep};
+    for (int a = 0; a < c.dim; ++a) {
+        c.b0_64 = c.ba_64 + (size_t)a * c.s * c.nn;
+        apply_one<double>(c, FCRKPM_OP_UH, x, out + (size_t)a * c.nn, 1, st);
+    }
+}
+}  // namespace
+
+// Alg B.3: the static nonlinear problem by nonlinear conjugate gradients.  The
+// forces of App. B (Eq B.2/B.4 with N(u) = kappa u^3, Eq B.6/B.8 with N(g) =
+// (1 + kappa |g|^2) g) are the gradients of convex energies, so the residual
+// R(d) is driven to zero by minimising along conjugate directions
+// (Polak-Ribiere, restarted when beta < 0) with an exact line search: phi'(alpha)
+// = R(d + alpha p) . p is a linear part plus nodal sums in u + alpha w or
+// g + alpha h (w = N p, h = B p), and Newton's method on it needs one
+// reduction kernel per step and no transform.  Every iteration costs one
+// force evaluation and the products of p (K p and N p, or B p).
+extern "C" fcrkpm_status fcrkpm_solve_nonlinear_cg(fcrkpm_ctx* ctx, int32_t kind, double kappa,
+                                                   const double* r, const double* g, double* d_inout,
+                                                   double* uh_out, double tol, int32_t maxit,
+                                                   fcrkpm_info* info, void* stream)
+{
+    if (!ctx) return FCRKPM_ERR_ARG;
+    Ctx& c = ctx->c;
+    std::vector<double*> bufs;
+    struct Free {
+        std::vector<double*>& b;
+        ~Free()
+        {
+            for (double*& p : b) dfree(p);
+        }
+    } release_bufs{bufs};
+    return run_guarded(c.err, [&]() -> fcrkpm_status {
+        if (kind != FCRKPM_NONLIN_CUBIC && kind != FCRKPM_NONLIN_GRADIENT) fail(FCRKPM_ERR_ARG, "unknown nonlinearity");
+        if (!r || !d_inout) fail(FCRKPM_ERR_ARG, "NULL array");
+        if (!(kappa >= 0.0) || !std::isfinite(kappa)) fail(FCRKPM_ERR_ARG, "kappa must be finite and >= 0");
+        if (!(tol > 0.0) || maxit < 1) fail(FCRKPM_ERR_ARG, "tol must be > 0 and maxit >= 1");
+        hipStream_t st = (hipStream_t)stream;
+        const long nn = c.nn;
+        const int dim = c.dim;
+        ensure_rhs(c, 1);
+        ensure_work(c, 1);
+        HIPCHK(hipMemsetAsync(c.dflag + 2, 0, sizeof(int), st));
+        launch_check_finite(r, nn, c.dflag + 2, st);
+        if (g) launch_check_finite(g, nn, c.dflag + 2, st);
+        launch_check_finite(d_inout, nn, c.dflag + 2, st);
+        int hf = 0;
+        HIPCHK(hipMemcpyAsync(&hf, c.dflag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hf) fail(FCRKPM_ERR_ARG, "non-finite value in r, g or d");
+        auto vec = [&](int count) {
+            double* p = dalloc<double>((size_t)count * nn);
+            bufs.push_back(p);
+            return p;
+        };
+        const bool cubic = kind == FCRKPM_NONLIN_CUBIC;
+        double* d = vec(1);
+        double* fr = vec(1);
+        double* R = vec(1);
+        double* rr = vec(1);
+        double* p = vec(1);
+        double* t = vec(1);
+        double* ro = vec(1);                 // the previous residual
+        double* a = vec(cubic ? 1 : dim);   // u = N d, or g = B d
+        double* b = vec(cubic ? 1 : dim);   // w = N p, or h = B p
+        double* kd = cubic ? vec(1) : nullptr;
+        double* kp = cubic ? vec(1) : nullptr;
+        int products = 0;
+
+        // d: g on the Dirichlet nodes, the initial guess on the free nodes
+        launch_lincomb_masked(d_inout, 1.0, nullptr, 0.0, nullptr, c.freem, d, nn, 1, st);
+        if (g) {
+            launch_lincomb_masked(g, 1.0, nullptr, 0.0, nullptr, c.dirm, t, nn, 1, st);
+            launch_lincomb_masked(d, 1.0, t, 1.0, nullptr, c.chi, d, nn, 1, st);
+        }
+        apply_one<double>(c, FCRKPM_OP_FR, r, fr, 1, st);
+        launch_lincomb_masked(fr, 1.0, nullptr, 0.0, nullptr, c.freem, t, nn, 1, st);
+        dots<double>(c, t, t, 1, S_BB, st);
+        const double fnorm = sqrt(read_scalars(c, 1, st)[S_BB]);
+        if (cubic) {
+            apply_one<double>(c, FCRKPM_OP_UH, d, a, 1, st);
+            apply_one<double>(c, FCRKPM_OP_K_FULL, d, kd, 1, st);
+            ++products;
+        } else {
+            apply_grad(c, d, a, st);
+        }
+        // rr = -R(d) on the free rows
+        auto residual = [&]() {
+            if (cubic) {
+                launch_pow_scaled(a, kappa, 3, t, nn, st);
+                apply_one<double>(c, FCRKPM_OP_FR, t, R, 1, st);
+                launch_lincomb_masked(kd, 1.0, R, 1.0, nullptr, c.freem, R, nn, 1, st);
+            } else {
+                c.pw_kappa = kappa;
+                apply_one<double>(c, OP_KN, d, R, 1, st);
+                ++products;
+            }
+            launch_lincomb_masked(fr, 1.0, R, -1.0, nullptr, c.freem, rr, nn, 1, st);
+        };
+        residual();
+        HIPCHK(hipMemcpyAsync(p, rr, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+        dots<double>(c, rr, rr, 1, S_NORM, st);
+        double rn = read_scalars(c, 1, st)[S_NORM];
+        int it = 0, lsteps = 0;
+        bool conv = fnorm == 0.0;
+        const double* vol = c.vol64;
+        while (!conv && it < maxit) {
+            if (sqrt(rn) <= tol * fnorm) {
+                conv = true;
+                break;
+            }
+            // exact line search along p
+            double c0, c1 = 0.0;
+            if (cubic) {
+                apply_one<double>(c, FCRKPM_OP_UH, p, b, 1, st);
+                apply_one<double>(c, FCRKPM_OP_K_FULL, p, kp, 1, st);
+                ++products;
+                launch_lincomb_masked(kd, 1.0, fr, -1.0, nullptr, c.chi, t, nn, 1, st);
+                dots<double>(c, t, p, 1, S_NORM, st);
+                dots<double>(c, kp, p, 1, S_BB, st);
+                const double* h = read_scalars(c, 1, st);
+                c0 = h[S_NORM];
+                c1 = h[S_BB];
+            } else {
+                apply_grad(c, p, b, st);
+                dots<double>(c, fr, p, 1, S_NORM, st);
+                c0 = -read_scalars(c, 1, st)[S_NORM];
+            }
+            // Newton on phi'(alpha) from alpha = 0; phi is convex along p, so the
+            // steps converge quadratically until the sums' rounding dominates
+            double alpha = 0.0;
+            for (int k = 0; k < 30; ++k) {
+                launch_ls_sums(cubic ? 0 : 1, dim, a, b, vol, c.chi, kappa, alpha, nn, c.partial, st);
+                launch_reduce_to(c.partial, nn, 1, c.scal + 6, st);
+                launch_reduce_to(c.partial + kRedBlocks, nn, 1, c.scal + 7, st);
+                const double* h = read_scalars(c, 1, st);
+                const double d1 = c0 + alpha * c1 + h[6], d2 = c1 + h[7];
+                ++lsteps;
+                if (!(d2 > 0.0) || !std::isfinite(d1)) break;
+                const double step = d1 / d2;
+                alpha -= step;
+                if (fabs(step) <= 1e-12 * fabs(alpha)) break;
+            }
+            if (!std::isfinite(alpha)) break;
+            launch_lincomb_masked(d, 1.0, p, alpha, nullptr, c.chi, d, nn, 1, st);
+            launch_lincomb_masked(a, 1.0, b, alpha, nullptr, c.chi, a, nn, cubic ? 1 : dim, st);
+            if (cubic) launch_lincomb_masked(kd, 1.0, kp, alpha, nullptr, c.chi, kd, nn, 1, st);
+            // the new residual, then the Polak-Ribiere direction
+            HIPCHK(hipMemcpyAsync(ro, rr, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+            residual();
+            dots<double>(c, rr, rr, 1, S_NORM, st);
+            dots<double>(c, rr, ro, 1, S_BB, st);
+            const double* h = read_scalars(c, 1, st);
+            const double rn_new = h[S_NORM];
+            const double beta = rn > 0.0 ? std::max(0.0, (rn_new - h[S_BB]) / rn) : 0.0;
+            launch_lincomb_masked(rr, 1.0, p, beta, nullptr, c.freem, p, nn, 1, st);
+            rn = rn_new;
+            ++it;
+            if (!std::isfinite(rn)) break;
+        }
+        conv = conv || sqrt(rn) <= tol * fnorm;
+        HIPCHK(hipMemcpyAsync(d_inout, d, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+        if (uh_out) apply_one<double>(c, FCRKPM_OP_UH, d, uh_out, 1, st);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->iters = it;
+            info->outer_iters = lsteps;
+            info->rel_res = info->true_rel_res = fnorm > 0.0 ? sqrt(rn) / fnorm : 0.0;
+            info->matvecs_f64 = products;
+        }
+        if (log_enabled())
+            fprintf(stderr, "[fcrkpm] nonlinear CG (%s): %d iterations, %d line-search steps, |R|/|f| %.3e\n",
+                    cubic ? "cubic" : "gradient", it, lsteps, fnorm > 0.0 ? sqrt(rn) / fnorm : 0.0);
+        if (!conv) {
+            c.err = "nonlinear CG did not reach tol within maxit iterations";
+            return FCRKPM_ERR_NOCONV;
+        }
+        return FCRKPM_OK;
+    });
+}
+
 // -lap u + kappa u^3 = r with d = g on the Dirichlet nodes (Eq 8 with the term
 // of Eq B.1): Newton's method on R(d) = K d + f^N(d) - f^r over the free rows,
 // each step one solve of (K + N^T diag(3 kappa V u^2) N) delta = -R with the

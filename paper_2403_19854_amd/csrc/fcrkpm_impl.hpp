@@ -287,6 +287,12 @@ void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32,
                     const double* wnode = nullptr);
 // out = kappa u^pw (pw 2 or 3) over n values
 void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long n, hipStream_t st);
+// nodal sums of the exact line search of the nonlinear CG (kind 0: kappa u^3 with
+// a = N d, b = N p; kind 1: (1 + kappa |g|^2) g with a = B d, b = B p, dim fields
+// each): per-block partials of phi' and phi'' in part[b], part[kRedBlocks + b]
+void launch_ls_sums(int kind, int dim, const double* a, const double* b, const double* vol,
+                    const uint8_t* chi, double kappa, double alpha, long n, double* part,
+                    hipStream_t st);
 // out = mask ? wa a + wb b + c : 0 (b and c may be NULL) over nrhs fields
 void launch_lincomb_masked(const double* a, double wa, const double* b, double wb, const double* cc,
                            const uint8_t* mask, double* out, long nn, int nrhs, hipStream_t st);

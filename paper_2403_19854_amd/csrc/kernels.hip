@@ -725,6 +725,60 @@ void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long 
                        pw == 3 ? 1 : 0, out, n);
 }
 
+// Nodal sums of the exact line search of the nonlinear CG (App. B.3) along
+// d + alpha p, over the domain nodes (weights V):
+//   kind 0, N(u) = kappa u^3, fields u = N d, w = N p, ua = u + alpha w:
+//     s1 = sum V kappa ua^3 w,  s2 = sum 3 V kappa ua^2 w^2;
+//   kind 1, N(g) = (1 + kappa |g|^2) g, fields g = B d, h = B p (dim
+//     components nn apart), ga = g + alpha h:
+//     s1 = sum V (1 + kappa |ga|^2) ga . h,
+//     s2 = sum V [(1 + kappa |ga|^2) |h|^2 + 2 kappa (ga . h)^2].
+// Per-block partials go to part[b] (s1) and part[kRedBlocks + b] (s2).
+__global__ __launch_bounds__(kRedThreads) void k_ls_sums(int kind, int dim, const double* __restrict__ a,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ vol,
+                                                         const uint8_t* __restrict__ chi, double kappa,
+                                                         double alpha, long n, double* __restrict__ part)
+{
+    __shared__ double sh[16];
+    double s1 = 0.0, s2 = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        if (!chi[i]) continue;
+        const double v = vol[i];
+        if (kind == 0) {
+            const double ua = a[i] + alpha * b[i], w = b[i];
+            s1 += v * kappa * ua * ua * ua * w;
+            s2 += 3.0 * v * kappa * ua * ua * w * w;
+        } else {
+            double g2 = 0.0, gh = 0.0, h2 = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                const double h = b[(long)k * n + i], ga = a[(long)k * n + i] + alpha * h;
+                g2 += ga * ga;
+                gh += ga * h;
+                h2 += h * h;
+            }
+            const double f = 1.0 + kappa * g2;
+            s1 += v * f * gh;
+            s2 += v * (f * h2 + 2.0 * kappa * gh * gh);
+        }
+    }
+    const double t1 = block_sum(s1, sh);
+    const double t2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t1;
+        part[kRedBlocks + blockIdx.x] = t2;
+    }
+}
+
+void launch_ls_sums(int kind, int dim, const double* a, const double* b, const double* vol,
+                    const uint8_t* chi, double kappa, double alpha, long n, double* part,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ls_sums, dim3(red_blocks(n)), dim3(kRedThreads), 0, st, kind, dim, a, b, vol,
+                       chi, kappa, alpha, n, part);
+}
+
 __global__ void k_lincomb_masked(const double* __restrict__ a, double wa,
                                  const double* __restrict__ b, double wb,
                                  const double* __restrict__ cc, const uint8_t* __restrict__ mask,

@@ -26,6 +26,7 @@ F64, F32 = 0, 1
 MODE_F64, MODE_F32_REFINED, MODE_F32_PRODUCTS = 0, 1, 2
 COEF_B0, COEF_BALPHA, COEF_FREE, COEF_LUMPED_MASS = 0, 1, 2, 3
 TIME_IMPLICIT, TIME_EXPLICIT_LUMPED = 0, 1
+NONLIN_CUBIC, NONLIN_GRADIENT = 0, 1
 KERNEL_CUBIC_BSPLINE = 0
 
 _OPS = {"K": OP_K, "K_FULL": OP_K_FULL, "FR": OP_FR, "UH": OP_UH, "NT": OP_NT, "VN": OP_VN,
@@ -39,7 +40,7 @@ EXPORTS = ("fcrkpm_setup", "fcrkpm_apply", "fcrkpm_solve", "fcrkpm_adjoint",
            "fcrkpm_kernel_name", "fcrkpm_solve_batch", "fcrkpm_set_option",
            "fcrkpm_get_option", "fcrkpm_transient", "fcrkpm_set_boundary",
            "fcrkpm_solve_flux", "fcrkpm_nonlinear_force", "fcrkpm_solve_nonlinear",
-           "fcrkpm_gradient_force", "fcrkpm_apply_noalloc")
+           "fcrkpm_gradient_force", "fcrkpm_apply_noalloc", "fcrkpm_solve_nonlinear_cg")
 OPT_GRAPHS = 1
 OPT_REGPATH = 2
 OPT_REGLAYOUT = 3
@@ -130,6 +131,9 @@ def load_library(path: str = LIB_PATH):
     lib.fcrkpm_solve_nonlinear.restype = C.c_int
     lib.fcrkpm_solve_nonlinear.argtypes = [V, C.c_int32, C.c_double, V, V, V, V, C.c_double,
                                            C.c_double, C.c_int32, C.c_int32, C.POINTER(Info), V]
+    lib.fcrkpm_solve_nonlinear_cg.restype = C.c_int
+    lib.fcrkpm_solve_nonlinear_cg.argtypes = [V, C.c_int32, C.c_double, V, V, V, V, C.c_double,
+                                              C.c_int32, C.POINTER(Info), V]
     lib.fcrkpm_transient.restype = C.c_int
     lib.fcrkpm_transient.argtypes = [V, C.POINTER(Time), C.c_int32, C.c_int32, V, V, V, V,
                                      C.c_double, C.c_int32, C.POINTER(Info), V]
@@ -416,6 +420,27 @@ class Problem:
                                                    _ptr(g), _ptr(d), _ptr(uh), float(tol),
                                                    float(newton_tol), int(maxnewton), int(maxit),
                                                    info, _stream_ptr(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            self._check(st)
+        return d, uh, _infos_dict(info, st)
+
+    def solve_nonlinear_cg(self, r, kappa, kind="cubic", g=None, d0=None, tol=1e-12, maxit=100000,
+                           want_uh=True, stream=None, raise_on_noconv=True):
+        """The static nonlinear problem by nonlinear CG (Alg B.3) with the force
+        of kind 'cubic' (kappa u^3) or 'gradient' ((1 + kappa |grad u|^2) grad u);
+        one field.  Returns (d, u^h or None, info dict: iters = CG iterations,
+        outer_iters = line-search steps)."""
+        r = _dev(r, torch.float64, self.device)
+        if r.numel() != self.nn:
+            raise ValueError("r must hold one field")
+        g = None if g is None else _dev(g, torch.float64, self.device)
+        d = torch.zeros_like(r) if d0 is None else _dev(d0, torch.float64, self.device).clone()
+        uh = torch.empty_like(r) if want_uh else None
+        code = {"cubic": NONLIN_CUBIC, "gradient": NONLIN_GRADIENT}[kind]
+        info = (Info * 1)()
+        st = load_library().fcrkpm_solve_nonlinear_cg(self._h, code, float(kappa), _ptr(r), _ptr(g),
+                                                      _ptr(d), _ptr(uh), float(tol), int(maxit), info,
+                                                      _stream_ptr(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             self._check(st)
         return d, uh, _infos_dict(info, st)

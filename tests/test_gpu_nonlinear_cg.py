@@ -1,0 +1,73 @@
+"""GPU parity of the nonlinear CG solver (App. B.3, Alg B.3) for both forms
+of nonlinear force (kappa u^3, Eq B.2/B.4; (1 + kappa |grad u|^2) grad u,
+Eq B.6/B.8) against the oracle: its own nonlinear CG and, for the cubic form,
+its Newton solve.  The energies are convex, so the discrete solution is
+unique: d and u^h must agree to 1e-10 relative L2 (tol 1e-13 on both sides,
+5e-13 in 1D); on the 64^3 box the oracle checks the residual of the GPU solution."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2403_19854_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def rel(a, b, m):
+    return np.linalg.norm((a - b)[m]) / np.linalg.norm(b[m])
+
+
+CASES = {
+    "1d_96": lambda: W.cube(1, 96, 2.5, 1),
+    "2d_32": lambda: W.cube(2, 32, 2.5, 1),
+    "3d_20": lambda: W.cube(3, 20, 2.5, 1),
+    "3d_64_register": lambda: W.cube(3, 64, 2.5, 1),
+    "2d_quadratic_24": lambda: W.cube(2, 24, 3.0, 2),
+}
+KAPPA = {"cubic": 20.0, "gradient": 0.05}
+
+
+@pytest.mark.parametrize("kind", ["cubic", "gradient"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_nonlinear_cg_matches_oracle(name, kind):
+    from paper_2403_19854_amd import fcrkpm
+    p = CASES[name]()
+    kappa = KAPPA[kind]
+    r = 5.0 * p.r if kind == "cubic" else p.r
+    print(f"\n[nonlinear CG {kind} {name}] dims={p.dims} kappa={kappa}", flush=True)
+    o = oracle.Oracle(p.dims, p.h, p.at, p.degree, p.chi, p.vol)
+    m = p.chi > 0
+    g = fcrkpm.Problem.from_workload(p, device=DEV)
+    # 1D reaches a slightly higher floor with the FP64 line search
+    tol = 5e-13 if p.dim == 1 else 1e-13
+    d, uh, info = g.solve_nonlinear_cg(torch.from_numpy(r).to(DEV), kappa, kind=kind, tol=tol,
+                                       maxit=20000)
+    d = d.cpu().numpy()
+    uh = uh.cpu().numpy()
+    ref = None
+    if p.nn <= 30000:
+        ref, its, res = o.solve_nonlinear_cg(p.free, p.dirichlet, r, kappa, kind=kind, tol=tol)
+        assert res <= tol
+    # larger boxes: the oracle's residual of the GPU solution (below)
+    if ref is not None:
+        e_d = rel(d, ref, m)
+        e_u = rel(uh, o.apply_uh(ref), m)
+        print(f"  GPU {info['iters']} iterations ({info['outer_iters']} line-search steps), residual "
+              f"{info['true_rel_res']:.2e}; rel-L2 d {e_d:.2e} u^h {e_u:.2e}", flush=True)
+        assert e_d <= 1e-10 and e_u <= 1e-10
+    f = p.free > 0
+    fr = o.apply_fr(r)
+    if kind == "cubic":
+        R = o.apply_k(d) + o.apply_fn(d, kappa) - fr
+    else:
+        R = o.apply_fn_grad(d, kappa) - fr
+    res_o = np.linalg.norm(R[f]) / np.linalg.norm(fr[f])
+    print(f"  oracle residual of the GPU solution {res_o:.2e}", flush=True)
+    assert info["true_rel_res"] <= tol and res_o <= 1e-11
+    if kind == "cubic" and p.nn <= 30000:
+        newton, _, _ = o.solve_nonlinear(p.free, p.dirichlet, r, kappa, tol=1e-14, newton_tol=1e-13)
+        assert rel(d, newton, m) <= 1e-10
