@@ -463,7 +463,7 @@ enum {
     FCRKPM_OPT_TUNE_NS1 = 5, /* read only: the same with variant 1 (0 where not timed) */
     FCRKPM_OPT_TUNE_NS2 = 6, /* read only: the same with variant 2 */
     FCRKPM_OPT_TUNE_NS3 = 7, /* read only: the same with variant 3 */
-    FCRKPM_OPT_LINECONST = 8 /* 1 (default): where every z line of the box has a constant
+    FCRKPM_OPT_LINECONST = 8, /* 1 (default): where every z line of the box has a constant
                                 pointwise matrix V B^T B away from the few nodes near the ends
                                 of the domain's z extent (cube-like domains, linear basis, K),
                                 the register path's middle pass applies that constant in the
@@ -471,6 +471,13 @@ enum {
                                 sums as Alg 2, regrouped); 0: the middle pass with a pointwise
                                 stage at every node.  Reads 1 only where setup found the
                                 structure. */
+    FCRKPM_OPT_SEP_LINES32 = 9,  /* LDS-tiled passes, FP32: most lines per workgroup (16, 8, 4) */
+    FCRKPM_OPT_SEP_LINES64 = 10, /* the same for FP64.  Setup times K products with each on the
+                                    precisions that run on these passes and keeps the fastest. */
+    FCRKPM_OPT_TUNE_CACHED = 11  /* read only: 1 if setup took its tuning choices from the file
+                                    named by FCRKPM_AUTOTUNE_CACHE (keyed by device, box, basis
+                                    and support) instead of timing; new choices are appended to
+                                    that file */
 };
 /* Set an option; FCRKPM_ERR_ARG for an unknown option or a value out of range. */
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);

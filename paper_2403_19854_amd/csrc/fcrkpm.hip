@@ -481,7 +481,11 @@ bool use_reg_path(const Ctx& c, int /*nrhs*/)
         const char* e = getenv("FCRKPM_REGPATH");
         env = (e && *e == '0') ? 0 : 1;
     }
-    return env == 1 && c.use_regpath && reg_path_ok(c) && c.nrec[c.reg_layout] != nullptr;
+    if (env != 1 || !c.use_regpath) return false;
+    // 64^3 and 128^3 boxes: per-node records or the line-constant middle pass;
+    // the other lengths of the P x Q layouts: the line-constant pass only
+    if (reg_path_ok(c)) return c.nrec[c.reg_layout] != nullptr;
+    return reg_gpq_ok(c) && sym_active(c);
 }
 
 // Algorithmic bytes of one launch of each register-resident pass: the FP32
@@ -1589,14 +1593,7 @@ void set_reg_variant(Ctx& c, int v)
 
 void tune_reg_layout(Ctx& c, hipStream_t st)
 {
-    if (!reg_path_ok(c)) return;
-    if (const char* e = getenv("FCRKPM_REGLAYOUT")) {
-        if (*e >= '0' && *e <= '3') {
-            const int v = *e - '0';
-            if (reg_variant_ok(c, v)) set_reg_variant(c, v);
-            return;
-        }
-    }
+    if (!use_reg_path(c, 1)) return;
     float* x = vec32(c, 2);
     float* y = vec32(c, 3);
     HIPCHK(hipMemsetAsync(x, 0, sizeof(float) * c.nn, st));
@@ -1634,6 +1631,135 @@ void tune_reg_layout(Ctx& c, hipStream_t st)
         fprintf(stderr, "[fcrkpm] register variants (8 lanes, 16 lanes; x2 tiles): %.1f %.1f %.1f %.1f us;"
                 " using %d\n", 1e3 * c.tune_ms[0], 1e3 * c.tune_ms[1], 1e3 * c.tune_ms[2],
                 1e3 * c.tune_ms[3], pick);
+}
+
+// Lines per workgroup of the LDS-tiled passes (16, 8 or 4), chosen by timing
+// K products of each precision that runs on them (not where the register path
+// serves that precision).
+void tune_sep_tiles(Ctx& c, hipStream_t st)
+{
+    const bool need[2] = {!use_reg_path(c, 1), !use_reg_path64(c)};
+    if (!need[0] && !need[1]) return;
+    const bool prof_on = c.prof_on;
+    c.prof_on = false;
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    double* x64 = vec64(c, V_T);
+    double* y64 = vec64(c, V_Q);
+    float* x32 = vec32(c, 2);
+    float* y32 = vec32(c, 3);
+    HIPCHK(hipMemsetAsync(x64, 0, sizeof(double) * c.nn, st));
+    HIPCHK(hipMemsetAsync(x32, 0, sizeof(float) * c.nn, st));
+    static const int caps[3] = {16, 8, 4};
+    for (int pr = 0; pr < 2; ++pr) {
+        if (!need[pr]) continue;
+        float best = 0.0f;
+        int pick = 16;
+        for (int cap : caps) {
+            c.sep_wcap[pr] = cap;
+            auto one = [&]() {
+                if (pr == 0) apply_one<float>(c, FCRKPM_OP_K, x32, y32, 1, st);
+                else apply_one<double>(c, FCRKPM_OP_K, x64, y64, 1, st);
+            };
+            one();
+            HIPCHK(hipEventRecord(ev[0], st));
+            for (int r = 0; r < 3; ++r) one();
+            HIPCHK(hipEventRecord(ev[1], st));
+            HIPCHK(hipEventSynchronize(ev[1]));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (best == 0.0f || ms < best) {
+                best = ms;
+                pick = cap;
+            }
+        }
+        c.sep_wcap[pr] = pick;
+        if (log_enabled())
+            fprintf(stderr, "[fcrkpm] LDS-tiled %s K product: %d lines per workgroup (%.1f us)\n",
+                    pr ? "FP64" : "FP32", pick, 1e3 * best / 3.0f);
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    c.prof_on = prof_on;
+}
+
+// The autotuner's key for this device and problem shape, "" without a cache
+std::string tune_key(const Ctx& c)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "";
+    }
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s/%dcu/n%dx%dx%d/d%d/deg%d/m%d.%d.%d/lc%d", prop.gcnArchName,
+             prop.multiProcessorCount, c.n[0], c.n[1], c.n[2], c.dim, c.degree, c.m[0], c.m[1], c.m[2],
+             (c.use_sym && c.sym) ? 1 : 0);
+    return buf;
+}
+
+// Setup-time autotuner: the register path's line layout and tiles per
+// workgroup, and the LDS-tiled passes' lines per workgroup.  With
+// FCRKPM_AUTOTUNE_CACHE naming a file, choices are looked up there by device
+// and problem shape (no timing on a hit) and new ones appended, one line each:
+// "<key> <register variant> <FP32 lines> <FP64 lines> <4 variant times, us>".
+void autotune(Ctx& c, hipStream_t st)
+{
+    const char* path = getenv("FCRKPM_AUTOTUNE_CACHE");
+    const std::string key = (path && *path) ? tune_key(c) : std::string();
+    if (!key.empty()) {
+        if (FILE* f = fopen(path, "r")) {
+            char line[512];
+            bool hit = false;
+            int v = 0, w32 = 16, w64 = 16;
+            float t[4] = {};
+            while (fgets(line, sizeof(line), f)) {
+                char k[256];
+                int vv, a32, a64;
+                float tt[4];
+                if (sscanf(line, "%255s %d %d %d %f %f %f %f", k, &vv, &a32, &a64, &tt[0], &tt[1], &tt[2],
+                           &tt[3]) == 8 &&
+                    key == k) {
+                    hit = true;
+                    v = vv;
+                    w32 = a32;
+                    w64 = a64;
+                    for (int i = 0; i < 4; ++i) t[i] = tt[i];
+                }
+            }
+            fclose(f);
+            const bool ok_caps = (w32 == 16 || w32 == 8 || w32 == 4) && (w64 == 16 || w64 == 8 || w64 == 4);
+            const bool ok_var = !(reg_path_ok(c) || reg_gpq_ok(c)) || reg_variant_ok(c, v);
+            if (hit && ok_caps && ok_var) {
+                if (reg_path_ok(c) || reg_gpq_ok(c)) set_reg_variant(c, v);
+                c.sep_wcap[0] = w32;
+                c.sep_wcap[1] = w64;
+                for (int i = 0; i < 4; ++i) c.tune_ms[i] = t[i] * 1e-3f;
+                c.tune_cached = true;
+                if (log_enabled()) fprintf(stderr, "[fcrkpm] autotune cache hit: %s\n", key.c_str());
+                return;
+            }
+        }
+    }
+    if (const char* e = getenv("FCRKPM_REGLAYOUT")) {
+        if (*e >= '0' && *e <= '3' && reg_variant_ok(c, *e - '0')) {
+            set_reg_variant(c, *e - '0');
+            tune_sep_tiles(c, st);
+            return;
+        }
+    }
+    tune_reg_layout(c, st);
+    tune_sep_tiles(c, st);
+    if (!key.empty()) {
+        if (FILE* f = fopen(path, "a")) {
+            fprintf(f, "%s %d %d %d %.3f %.3f %.3f %.3f\n", key.c_str(), c.reg_layout + 2 * (c.reg_tpw - 1),
+                    c.sep_wcap[0], c.sep_wcap[1], 1e3f * c.tune_ms[0], 1e3f * c.tune_ms[1], 1e3f * c.tune_ms[2],
+                    1e3f * c.tune_ms[3]);
+            fclose(f);
+        }
+    }
 }
 }  // namespace
 
@@ -1877,7 +2003,7 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         HIPCHK(hipStreamSynchronize(st));
         ensure_work(c, 1);
         ensure_rhs(c, 1);
-        tune_reg_layout(c, st);
+        autotune(c, st);
         HIPCHK(hipGetLastError());
         *out = h;
         h = nullptr;
@@ -2674,6 +2800,9 @@ extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int6
             case FCRKPM_OPT_TUNE_NS2: *value = (int64_t)(1e6 * c.tune_ms[2]); break;
             case FCRKPM_OPT_TUNE_NS3: *value = (int64_t)(1e6 * c.tune_ms[3]); break;
             case FCRKPM_OPT_LINECONST: *value = (c.use_sym && c.sym) ? 1 : 0; break;
+            case FCRKPM_OPT_SEP_LINES32: *value = c.sep_wcap[0]; break;
+            case FCRKPM_OPT_SEP_LINES64: *value = c.sep_wcap[1]; break;
+            case FCRKPM_OPT_TUNE_CACHED: *value = c.tune_cached ? 1 : 0; break;
             default: fail(FCRKPM_ERR_ARG, "unknown option");
         }
         return FCRKPM_OK;
@@ -2695,13 +2824,19 @@ extern "C" fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int6
                 c.use_regpath = value == 1;
                 break;
             case FCRKPM_OPT_REGLAYOUT:
-                if (!(reg_path_ok(c) ? reg_variant_ok(c, (int)value) : value == 0))
+                if (!((reg_path_ok(c) || reg_gpq_ok(c)) ? reg_variant_ok(c, (int)value) : value == 0))
                     fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_REGLAYOUT out of range for this box");
                 set_reg_variant(c, (int)value);
                 break;
             case FCRKPM_OPT_LINECONST:
                 if (value != 0 && value != 1) fail(FCRKPM_ERR_ARG, "FCRKPM_OPT_LINECONST takes 0 or 1");
                 c.use_sym = value == 1;
+                break;
+            case FCRKPM_OPT_SEP_LINES32:
+            case FCRKPM_OPT_SEP_LINES64:
+                if (value != 16 && value != 8 && value != 4)
+                    fail(FCRKPM_ERR_ARG, "lines per workgroup of the LDS-tiled passes: 16, 8 or 4");
+                c.sep_wcap[option == FCRKPM_OPT_SEP_LINES64 ? 1 : 0] = (int)value;
                 break;
             default:
                 fail(FCRKPM_ERR_ARG, "unknown option");

@@ -166,6 +166,9 @@ struct Ctx {
     int lds_budget = 65536;             // LDS bytes one workgroup may use
     void* scratch = nullptr;            // device address of this device's static scratch array
                                         // (fcrkpm_apply_noalloc), taken at setup
+    int sep_wcap[2] = {16, 16};         // LDS-tiled passes: most lines per workgroup (FP32, FP64),
+                                        // chosen at setup by timing K products
+    bool tune_cached = false;           // the autotuner's choices came from its cache file
     void* sym = nullptr;                // register path: line-constant middle pass of K (regpass.hip)
     bool use_sym = true;                // use it where it applies
     double* rtab64[3] = {};             // per axis [3][n]: Re T_0 / n, Im T_1 / n, Re T_2 / n (FP64)
@@ -231,6 +234,10 @@ struct RegPupd {
     const int* act;
 };
 bool reg_path_ok(const Ctx& c);
+// 3D cube boxes of 32, 48, 80, 96 or 256 nodes per axis, linear basis: the
+// register path with P x Q line layouts, which runs only with the
+// line-constant middle pass (sym_active)
+bool reg_gpq_ok(const Ctx& c);
 // Line-constant middle pass of the register path (linear basis, K only): along
 // every z line the pointwise matrix M = V B^T B is constant except at a few
 // nodes near the ends of the z extent, so the middle pass applies the line's

@@ -315,7 +315,7 @@ struct LdsTw {
 
 template <int R>
 struct G8 {
-    static constexpr int LANES = 8, PTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
+    static constexpr int LANES = 8, PTS = R, SPTS = R, L = 8 * R, XS = R == 16 ? 168 : 72;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     template <typename T = float>
@@ -325,13 +325,20 @@ struct G8 {
     using Spec = SpecLds<T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 8 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 8 * (i / 8) + R * (i % 8); }
+    static __device__ __forceinline__ int lane_of(int k) { return k % 8; }
+    static __device__ __forceinline__ int slot_of(int k)
+    {
+        constexpr int Q = R / 8;
+        const int rem = k / 8;
+        return 8 * (rem % Q) + rem / Q;
+    }
     template <typename T>
     static __device__ __forceinline__ void fwd(cplx<T> (&v)[R], int t, cplx<T>* xb, const LdsTw<T>& w) { g8_fwd<R>(v, t, xb, w.tw); }
     template <typename T>
     static __device__ __forceinline__ void inv(cplx<T> (&v)[R], int t, cplx<T>* xb, const LdsTw<T>& w) { g8_inv<R>(v, t, xb, w.tw); }
 };
 struct G16 {
-    static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
+    static constexpr int LANES = 16, PTS = 8, SPTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     template <typename T = float>
@@ -341,6 +348,8 @@ struct G16 {
     using Spec = SpecRegs<NE, T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
+    static __device__ __forceinline__ int lane_of(int k) { return k % 16; }
+    static __device__ __forceinline__ int slot_of(int k) { return k / 16; }
     template <typename T, class TW>
     static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_fwd(v, t, xb, w); }
     template <typename T, class TW>
@@ -349,7 +358,7 @@ struct G16 {
 // G16 geometry with twiddles and spectra read from LDS (for the kernel that
 // holds the most fields)
 struct G16L {
-    static constexpr int LANES = 16, PTS = 8, L = 128, XS = 136;
+    static constexpr int LANES = 16, PTS = 8, SPTS = 8, L = 128, XS = 136;
     static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
     static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = PTS * SS;
     template <typename T = float>
@@ -359,11 +368,141 @@ struct G16L {
     using Spec = SpecLds<T>;
     static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
     static __device__ __forceinline__ int freq(int t, int i) { return t + 16 * i; }
+    static __device__ __forceinline__ int lane_of(int k) { return k % 16; }
+    static __device__ __forceinline__ int slot_of(int k) { return k / 16; }
     template <typename T, class TW>
     static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_fwd(v, t, xb, w); }
     template <typename T, class TW>
     static __device__ __forceinline__ void inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const TW& w) { g16_inv(v, t, xb, w); }
 };
+
+// In-register DFT of P points in natural order, DIR = +1 forward.  Prime
+// sizes and 4, 8, 16 have their own butterflies; P = A B (6, 10, 12) takes
+// the DFT-A of the B interleaved subsequences, the twiddles W_P^(n2 k1)
+// (from the L-point table of the axis, P dividing L) and the DFT-Bs.
+template <int P, int DIR, typename T>
+__device__ __forceinline__ void dft_small(cplx<T>* v, const cplx<T>* twL, int L)
+{
+    if constexpr (P == 1) {
+        return;
+    } else if constexpr (P == 16) {
+        dft16<DIR>(v);
+    } else if constexpr (P == 2 || P == 3 || P == 4 || P == 5 || P == 7 || P == 8) {
+        dftR<T, DIR, P>(v);
+    } else {
+        constexpr int A = (P % 4 == 0) ? 4 : 2, B = P / A;
+        static_assert(A * B == P && (B == 3 || B == 5), "DFT size without a decomposition");
+        cplx<T> y[A][B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) {
+            cplx<T> a[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) a[n1] = v[B * n1 + n2];
+            dftR<T, DIR, A>(a);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1)
+                y[k1][n2] = (n2 * k1 == 0) ? a[k1] : cmul(a[k1], twid<DIR>(twL, n2 * k1 * (L / P)));
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            cplx<T> b[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) b[n2] = y[k1][n2];
+            dftR<T, DIR, B>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = b[k2];
+        }
+    }
+}
+
+// Line layout for L = P Q: Q lanes per complex line, lane t holding points
+// t + Q m (m < P).  Forward: a DFT-P over m in registers, the twiddle
+// W_L^(t k1), one transpose through LDS that hands lane t the Q values of
+// each k1 = t + Q j < P (j < J = ceil(P / Q)), and a DFT-Q per such k1: slot
+// j Q + k2 then holds X[k1 + P k2].  Slots with k1 >= P hold nothing during
+// the spectral stage (their results are never read); when P < Q some lanes
+// idle through the DFT-Q stage.  The inverse runs the steps backwards with
+// conjugate twiddles.  G8<8> is the square case P = Q = 8.
+template <int P_, int Q_>
+struct GPQ {
+    static constexpr int P = P_, Q = Q_;
+    static constexpr int LANES = Q, L = P * Q, J = (P + Q - 1) / Q;
+    static constexpr int SPTS = P, PTS = (P > J * Q) ? P : J * Q;
+    static constexpr int XP = Q + 1;  // transpose pitch (conflict-free rows)
+    static constexpr int XS = (P * XP > PTS * LANES) ? P * XP : PTS * LANES;
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = SPTS * SS;
+    template <typename T = float>
+    using TwT = LdsTw<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecLds<T>;
+    static __device__ __forceinline__ int row(int t, int m) { return t + Q * m; }
+    static __device__ __forceinline__ int freq(int t, int i)
+    {
+        const int k1 = t + Q * (i / Q);
+        return k1 < P ? k1 + P * (i % Q) : 0;
+    }
+    static __device__ __forceinline__ int lane_of(int k) { return (k % P) % Q; }
+    static __device__ __forceinline__ int slot_of(int k) { return ((k % P) / Q) * Q + k / P; }
+    template <typename T>
+    static __device__ __forceinline__ void dftq(cplx<T>* v)
+    {
+        if constexpr (Q == 16) dft16<+1>(v);
+        else dft8<T, +1>(v);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void idftq(cplx<T>* v)
+    {
+        if constexpr (Q == 16) dft16<-1>(v);
+        else dft8<T, -1>(v);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[PTS], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+        dft_small<P, +1>(v, w.tw, L);
+#pragma unroll
+        for (int k1 = 1; k1 < P; ++k1) v[k1] = cmul(v[k1], twid<+1>(w.tw, t * k1));
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) xb[k1 * XP + t] = v[k1];
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int k1 = t + Q * j;
+            if (k1 < P) {
+#pragma unroll
+                for (int n2 = 0; n2 < Q; ++n2) v[j * Q + n2] = xb[k1 * XP + n2];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < J; ++j) dftq(v + j * Q);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[PTS], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            idftq(v + j * Q);
+            const int k1 = t + Q * j;
+            if (k1 < P) {
+#pragma unroll
+                for (int n2 = 0; n2 < Q; ++n2)
+                    xb[k1 * XP + n2] = n2 == 0 ? v[j * Q] : cmul(v[j * Q + n2], twid<-1>(w.tw, n2 * k1));
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) v[k1] = xb[k1 * XP + t];
+        wave_sync();
+        dft_small<P, -1>(v, w.tw, L);
+    }
+};
+
+template <class Lay>
+struct is_gpq : std::false_type {};
+template <int P, int Q>
+struct is_gpq<GPQ<P, Q>> : std::true_type {};
 
 // Term structure of the K d passes (Eq 55, 77-78): each term convolves input
 // `in` of a pass with the kernel t_e (part 1) or the reflected t_e (part 2)
@@ -530,11 +669,17 @@ __device__ __forceinline__ void sym4_apply(const T* M, T d0, T d1, T d2, T d3, T
 // Position of the workgroup's Lay::LINES real lines: for a strided axis the
 // float index of line l0 at point 0 (the lines are adjacent in memory), for
 // x the index of line l0's first point.
+// A P x Q layout's tile may hold more lines than one row of a strided axis
+// (LINES > st on the y axis of 32- or 48-point boxes, or not dividing it), so
+// its strided tiles are positioned line by line: the base is the tile's first
+// line and each pair of lines (never split by a row end, the box lengths
+// being even) finds its own row.
 template <class Lay, bool CONTIG>
 __device__ __forceinline__ long tile_base(long tile, long st)
 {
     const long l0 = tile * Lay::LINES;
     if (CONTIG) return l0 * Lay::L;
+    if constexpr (is_gpq<Lay>::value) return l0;
     const long lo = l0 % st, hi = l0 / st;
     return lo + hi * st * Lay::L;
 }
@@ -545,6 +690,10 @@ __device__ __forceinline__ long elem_index(long base, int g, int t, int m, long 
 {
     const int i = Lay::row(t, m);
     if (CONTIG) return base + (long)(2 * g) * Lay::L + i;
+    if constexpr (is_gpq<Lay>::value) {
+        const uint32_t l = (uint32_t)(base + 2 * g), s = (uint32_t)st;
+        return (long)(l % s) + (long)(l / s) * st * Lay::L + (long)i * st;
+    }
     return base + 2 * g + (long)i * st;
 }
 
@@ -647,10 +796,10 @@ template <class Lay, typename T>
 __device__ __forceinline__ void stage_move(cplx<T> (&v)[Lay::PTS], cplx<T>* buf, int gw, int tw, int gr, int tr)
 {
 #pragma unroll
-    for (int m = 0; m < Lay::PTS; ++m) buf[m * Lay::SS + tw * Lay::TP + gw] = v[m];
+    for (int m = 0; m < Lay::SPTS; ++m) buf[m * Lay::SS + tw * Lay::TP + gw] = v[m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < Lay::PTS; ++m) v[m] = buf[m * Lay::SS + tr * Lay::TP + gr];
+    for (int m = 0; m < Lay::SPTS; ++m) v[m] = buf[m * Lay::SS + tr * Lay::TP + gr];
 }
 
 // One separable pass: NIN real fields -> NOUT real fields along the axis.
@@ -663,7 +812,7 @@ template <class Lay, class B, int TPW, bool CONTIG, bool LMASK, bool SMASK, int 
 __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
 {
     typedef cplx<T> cf;
-    constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr int L = Lay::L, R = Lay::PTS, SP = Lay::SPTS;  // register slots, points per lane
     // FP32 strided passes stage global memory through LDS (row-major map);
     // FP64 ones read their 16-byte pairs directly in the transform layout
     // (64-byte row segments per wave), which keeps their LDS small
@@ -703,7 +852,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
 #pragma unroll
         for (int f = 0; f < NIN; ++f)
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
+            for (int m = 0; m < SP; ++m) {
                 const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
                 Z[tt][f][m] = load_pair<L, CONTIG>(in + f * a.fstride, idx);
                 if constexpr (LMASK) {
@@ -724,7 +873,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
         for (int tt = 0; tt < TPW; ++tt) {
             const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
-            for (int m = 0; m < R; ++m)
+            for (int m = 0; m < SP; ++m)
                 Rv[tt][m] = load_pair<L, CONTIG>(a.rvec + rhs * a.in_rb,
                                                  elem_index<Lay, CONTIG>(base, gc, tc, m, a.st));
         }
@@ -741,7 +890,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
             for (int tt = 0; tt < TPW; ++tt) {
                 const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
-                for (int m = 0; m < R; ++m) {
+                for (int m = 0; m < SP; ++m) {
                     const cf pv = Z[tt][0][m], rv = Rv[tt][m];
                     Z[tt][0][m] = cf{rv.x + beta * pv.x, rv.y + beta * pv.y};
                     store_pair<L, CONTIG>(const_cast<T*>(in), elem_index<Lay, CONTIG>(base, gc, tc, m, a.st),
@@ -755,7 +904,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
+            for (int m = 0; m < SP; ++m) {
                 const cf v = Z[tt][0][m];
                 Z[tt][0][m] = cf{mk[tt][m][0] ? v.x : T(0), mk[tt][m][1] ? v.y : T(0)};
             }
@@ -771,7 +920,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
         for (int tt = 0; tt < TPW; ++tt) {
             const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
+            for (int m = 0; m < SP; ++m) {
                 const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
                 const long idx1 = idx + (CONTIG ? L : 1);
                 mo[tt][m][0] = a.mask_out[idx];
@@ -803,7 +952,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
         Lay::inv(Y, t, xb, lw);
         if constexpr (STG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
+        for (int m = 0; m < SP; ++m) {
             const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
             if constexpr (SMASK) {
                 const T v0 = mo[tt][m][0] ? Y[m].x : T(0);
@@ -1222,7 +1371,7 @@ struct SymTab {
     int cz[kSymC];           // correction nodes (z), ascending
     int wz[kSymW];           // window nodes: the correction nodes +- m, ascending
     float tap0[8], tap1[8];  // t_0[o], t_1[o] for o = -m .. m
-    signed char widx[128];   // window index of every z (-1: not in the window)
+    signed char widx[256];   // window index of every z (-1: not in the window)
     double dtap0[8], dtap1[8];  // the same taps in FP64
 };
 
@@ -1255,17 +1404,9 @@ struct SArgs {
 
 // inverse of Lay::freq: the lane and slot that hold frequency k
 template <class Lay>
-__device__ __forceinline__ int freq_lane(int k) { return k % Lay::LANES; }
+__device__ __forceinline__ int freq_lane(int k) { return Lay::lane_of(k); }
 template <class Lay>
-__device__ __forceinline__ int freq_slot(int k)
-{
-    if constexpr (Lay::LANES == 16) return k / 16;
-    else {
-        constexpr int Q = Lay::PTS / 8;
-        const int rem = k / 8;
-        return 8 * (rem % Q) + rem / Q;
-    }
-}
+__device__ __forceinline__ int freq_slot(int k) { return Lay::slot_of(k); }
 
 // w[i] = conj X(-k) where v[i] = X(k), k = freq(t, i): the spectrum of the
 // pair's other orientation, from the lane that holds -k (through LDS)
@@ -1328,7 +1469,7 @@ template <class Lay, typename T = float>
 __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
 {
     typedef cplx<T> cf;
-    constexpr int L = Lay::L, R = Lay::PTS;
+    constexpr int L = Lay::L, R = Lay::PTS, SP = Lay::SPTS;
     constexpr bool STG = sizeof(T) == 4;  // FP64: direct loads in the transform layout
     constexpr int CW = 3 * kSymW + 4 * kSymC;  // per group: window values (later the
                                                // output corrections), then dE
@@ -1357,7 +1498,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int m = 0; m < R; ++m)
+        for (int m = 0; m < SP; ++m)
             X[f][m] = load_pair<L, false>(in + f * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st));
     // the pair's record: the constant part for every lane, the correction
     // node's entries for the correction lanes
@@ -1375,7 +1516,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     }
     // window values of the three inputs
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
+    for (int m = 0; m < SP; ++m) {
         const int wi = tb.widx[Lay::row(t, m)];
         if (wi >= 0) {
 #pragma unroll
@@ -1452,7 +1593,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
 #pragma unroll
     for (int o = 0; o < 3; ++o) Lay::inv(Y[o], t, xb, lw);
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
+    for (int m = 0; m < SP; ++m) {
         const int wi = tb.widx[Lay::row(t, m)];
         if (wi >= 0) {
 #pragma unroll
@@ -1466,7 +1607,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     for (int o = 0; o < 3; ++o) {
         if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
 #pragma unroll
-        for (int m = 0; m < R; ++m)
+        for (int m = 0; m < SP; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
     }
 }
@@ -1662,7 +1803,10 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         if constexpr (B::DEGREE == 1) {
             constexpr bool SYM_LAYOUT = !std::is_same<Lay, G8<16>>::value;
-            if (SYM_LAYOUT && sym_active(c)) {
+            if constexpr (is_gpq<Lay>::value) {
+                // the other box lengths run only with the line-constant middle pass
+                run_smid<Lay, float>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
+            } else if (SYM_LAYOUT && sym_active(c)) {
                 if constexpr (SYM_LAYOUT) run_smid<Lay, float>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
             } else {
                 for (int k = 0; k < 10; ++k) a.ci[k] = c.reg_mi[k];
@@ -1886,8 +2030,25 @@ bool plan_matches(const Ctx& c)
 
 }  // namespace
 
-// layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only)
-int reg_layouts(const Ctx& c) { return c.n[0] == 128 ? 2 : 1; }
+// box lengths of the P x Q layouts (register path with the line-constant middle pass only)
+static bool gpq_length(int L) { return L == 32 || L == 48 || L == 80 || L == 96 || L == 256; }
+
+bool reg_gpq_ok(const Ctx& c)
+{
+    if (c.dim != 3 || c.naxes != 3 || c.degree != 1) return false;
+    const int L = c.n[0];
+    if (!gpq_length(L) || c.n[1] != L || c.n[2] != L) return false;
+    return plan_matches<Lin3>(c);
+}
+
+// layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only);
+// for the P x Q lengths, layout 0 has 16 lanes per line and layout 1 (80 and 96
+// only) 8 lanes
+int reg_layouts(const Ctx& c)
+{
+    if (reg_gpq_ok(c)) return (c.n[0] == 80 || c.n[0] == 96) ? 2 : 1;
+    return c.n[0] == 128 ? 2 : 1;
+}
 
 // variant v = layout + 2 (tiles - 1); 8-lane 128-point lines with 2 tiles
 // per workgroup need more registers than a wave has, so that one is absent.
@@ -1896,6 +2057,7 @@ int reg_layouts(const Ctx& c) { return c.n[0] == 128 ? 2 : 1; }
 bool reg_variant_ok(const Ctx& c, int v)
 {
     if (v < 0 || v > 3 || (v & 1) >= reg_layouts(c)) return false;
+    if (reg_gpq_ok(c)) return v < 2;
     if (c.degree == 2) return c.n[0] == 128 ? v == 1 : v == 0;
     return !(c.n[0] == 128 && v == 2);
 }
@@ -1940,10 +2102,28 @@ bool reg_path_ok(const Ctx& c)
     return c.degree == 1 ? plan_matches<Lin3>(c) : plan_matches<Quad3>(c);
 }
 
+// The P x Q layout of a box length: 32 = 4 x 8, 48 = 6 x 8, 80 = 5 x 16 or
+// 10 x 8, 96 = 6 x 16 or 12 x 8, 256 = 16 x 16.  F(LAY) is called with it.
+template <class F>
+static void with_gpq(const Ctx& c, F&& f)
+{
+    switch (c.n[0]) {
+        case 32: f(GPQ<4, 8>{}); break;
+        case 48: f(GPQ<6, 8>{}); break;
+        case 80: if (c.reg_layout) f(GPQ<10, 8>{}); else f(GPQ<5, 16>{}); break;
+        case 96: if (c.reg_layout) f(GPQ<12, 8>{}); else f(GPQ<6, 16>{}); break;
+        default: f(GPQ<16, 16>{}); break;
+    }
+}
+
 // workgroups of one launch (each covers reg_tpw tiles)
 int reg_path_blocks(const Ctx& c)
 {
     long b;
+    if (reg_gpq_ok(c)) {
+        with_gpq(c, [&](auto lay) { b = blocks_of<decltype(lay)>(c); });
+        return (int)b;
+    }
     if (c.n[0] == 128) b = c.reg_layout ? blocks_of<G16>(c) : blocks_of<G8<16>>(c);
     else b = blocks_of<G8<8>>(c);
     return (int)(b / c.reg_tpw);
@@ -1951,17 +2131,27 @@ int reg_path_blocks(const Ctx& c)
 
 bool sym_ready(const Ctx& c);
 
+// FP64 lines fit the registers where a lane holds at most 8 complex values:
+// 64^3 and 128^3 boxes and the 32- and 48-point P x Q layouts
 bool reg_path64_ok(const Ctx& c)
 {
-    return c.degree == 1 && reg_path_ok(c) && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
+    const bool lay = reg_path_ok(c) || (reg_gpq_ok(c) && (c.n[0] == 32 || c.n[0] == 48));
+    return c.degree == 1 && lay && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
 }
 
-long reg_path64_blocks(const Ctx& c) { return c.n[0] == 128 ? blocks_of<G16L>(c) : blocks_of<G8<8>>(c); }
+long reg_path64_blocks(const Ctx& c)
+{
+    if (c.n[0] == 32) return blocks_of<GPQ<4, 8>>(c);
+    if (c.n[0] == 48) return blocks_of<GPQ<6, 8>>(c);
+    return c.n[0] == 128 ? blocks_of<G16L>(c) : blocks_of<G8<8>>(c);
+}
 
 void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
                     double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof)
 {
     if (c.n[0] == 128) run_k64<G16L>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else if (c.n[0] == 32) run_k64<GPQ<4, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else if (c.n[0] == 48) run_k64<GPQ<6, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else run_k64<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
 }
 
@@ -1974,6 +2164,10 @@ void launch_reg_k(const Ctx& c, const float* in, float* out, const uint8_t* mask
         if (c.reg_tpw == 2) run_k<LAY, Lin3, 2>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu); \
         else run_k<LAY, Lin3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);        \
     } while (0)
+    if (reg_gpq_ok(c)) {
+        with_gpq(c, [&](auto lay) { run_k<decltype(lay), Lin3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu); });
+        return;
+    }
     if (c.degree == 2) {
         if (c.n[0] == 128) run_k<G16, Quad3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);
         else run_k<G8<8>, Quad3, 1>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof, pu);
@@ -2027,7 +2221,10 @@ bool sym_ready(const Ctx& c)
 
 // ... and the FP32 product's line layout has the kernel (8-lane 128-point
 // lines hold too many values for it)
-bool sym_active(const Ctx& c) { return sym_ready(c) && (c.n[0] == 64 || c.reg_layout == 1); }
+bool sym_active(const Ctx& c)
+{
+    return sym_ready(c) && (c.n[0] == 64 || (c.n[0] == 128 && c.reg_layout == 1) || gpq_length(c.n[0]));
+}
 
 double sym_pass_bytes(const Ctx& c, int elem_bytes)
 {
@@ -2045,9 +2242,11 @@ double sym_pass_bytes(const Ctx& c, int elem_bytes)
 void sym_build(Ctx& c, hipStream_t st)
 {
     sym_release(c);
-    if (!c.use_sym || c.degree != 1 || c.krows != c.dim || !reg_path_ok(c) || c.nconst.bmax < 0.0) return;
+    if (!c.use_sym || c.degree != 1 || c.krows != c.dim || !(reg_path_ok(c) || reg_gpq_ok(c)) ||
+        c.nconst.bmax < 0.0)
+        return;
     const int L = c.n[2], m = c.m[2];
-    if (L > 128 || m < 1 || m > 3) return;
+    if (L > 256 || m < 1 || m > 3) return;
     const long nlines = (long)c.n[0] * c.n[1], npairs = nlines / 2;
     // z extent of the domain
     const int ntot = c.n[0] + c.n[1] + c.n[2];
@@ -2081,7 +2280,7 @@ void sym_build(Ctx& c, hipStream_t st)
     std::vector<char> inw(L, 0);
     for (int i = 0; i < tab.nc; ++i)
         for (int o = -m; o <= m; ++o) inw[(tab.cz[i] + o + L) % L] = 1;
-    for (int z = 0; z < 128; ++z) tab.widx[z] = -1;
+    for (int z = 0; z < 256; ++z) tab.widx[z] = -1;
     for (int z = 0; z < L; ++z)
         if (inw[z]) {
             if (tab.nw == kSymW) return;

@@ -703,7 +703,7 @@ __global__ __launch_bounds__(kThreads) void k_sep_mid(MidArgs<T> m)
 
 // tile width: the largest power of two W <= 16 with W*L <= max_tile that
 // divides the line count (x axis) or the axis stride (other axes)
-static AxisGeom sep_geom(const Ctx& c, int a, int max_tile)
+static AxisGeom sep_geom(const Ctx& c, int a, int max_tile, int wcap = 16)
 {
     AxisGeom g;
     g.L = c.n[a];
@@ -713,7 +713,7 @@ static AxisGeom sep_geom(const Ctx& c, int a, int max_tile)
     g.contig = (g.st == 1);
     long div = g.contig ? g.nlines : g.st;
     int W = 16;
-    while (W > 1 && ((long)W * g.L > max_tile || div % W != 0)) W >>= 1;
+    while (W > 1 && (W > wcap || (long)W * g.L > max_tile || div % W != 0)) W >>= 1;
     g.W = W;
     g.wl = 0;
     while ((1 << g.wl) < W) ++g.wl;
@@ -740,7 +740,8 @@ static int max_tile(const Ctx& c, int a, int nbuf, size_t elem)
 template <typename T>
 static void fill_common(const Ctx& c, int a, SepArgs<T>& s, int nbuf)
 {
-    s.g = sep_geom(c, a, max_tile(c, a, nbuf, sizeof(cplx<T>)));
+    // lines per workgroup: at most the setup-time choice of this precision
+    s.g = sep_geom(c, a, max_tile(c, a, nbuf, sizeof(cplx<T>)), sizeof(T) == 8 ? c.sep_wcap[1] : c.sep_wcap[0]);
     s.p = c.plan[a];
     if constexpr (sizeof(T) == 8) {
         s.tw = c.tw64[a];

@@ -49,6 +49,9 @@ OPT_TUNE_NS1 = 5
 OPT_TUNE_NS2 = 6
 OPT_TUNE_NS3 = 7
 OPT_LINECONST = 8
+OPT_SEP_LINES32 = 9
+OPT_SEP_LINES64 = 10
+OPT_TUNE_CACHED = 11
 
 
 class Grid(C.Structure):

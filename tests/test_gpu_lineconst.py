@@ -9,7 +9,9 @@ LDS-tiled FP32 passes and the FP64 oracle at sampled nodes, on boxes of 64 and
 x and y extents end at other positions (pairs of complex lines whose two real
 lines have different line constants, lines outside the domain).  A domain
 whose z extent leaves too many nodes outside does not take the path (the
-option reads 0) and still gives the right product."""
+option reads 0) and still gives the right product.  Boxes of 32, 48, 80 and
+96 nodes run the register path with P x Q line layouts (4 x 8, 6 x 8, 5 x 16
+or 10 x 8, 6 x 16 or 12 x 8 points x lanes), which rely on this pass."""
 import numpy as np
 import pytest
 
@@ -59,6 +61,12 @@ CASES = {
     "box128_odd_extents": (lambda: box_domain(128, 2.5, (125, 111, 126)), 1),
     "box64_odd_extents": (lambda: box_domain(64, 2.5, (37, 60, 62)), 1),
     "box64_short_z": (lambda: box_domain(64, 2.5, (62, 62, 40)), 0),
+    "cube32_support2p5": (lambda: W.cube(3, 32, 2.5, 1), 1),
+    "cube48_support2p5": (lambda: W.cube(3, 48, 2.5, 1), 1),
+    "cube80_support2p5": (lambda: W.cube(3, 80, 2.5, 1), 1),
+    "cube96_support2p5": (lambda: W.cube(3, 96, 2.5, 1), 1),
+    "box96_odd_extents": (lambda: box_domain(96, 2.5, (93, 81, 94)), 1),
+    "cube48_paper_support1p5": (lambda: W.paper_shape(48), 1),
 }
 
 
@@ -95,13 +103,24 @@ def test_line_constant_middle_pass(name):
           f"vs oracle (sampled) {d_orc:.2e}", flush=True)
     assert d_off <= 2e-6 and d_lds <= 2e-5 and d_orc <= 2e-5
     assert np.all(on[p.free == 0] == 0.0)
+    if p.dims[0] in (80, 96):
+        # both line layouts of these lengths (16 lanes x 5 or 6 points, 8 lanes x 10 or 12)
+        chosen = g.get_option(f.OPT_REGLAYOUT)
+        for lay in (0, 1):
+            g.set_option(f.OPT_REGLAYOUT, lay)
+            other = to_np(g.apply("K", xt)).astype(np.float64)
+            d_lay = np.abs(other - off).max() / scale
+            print(f"  line layout {lay}: vs per-node pointwise {d_lay:.2e}", flush=True)
+            assert d_lay <= 2e-5
+        g.set_option(f.OPT_REGLAYOUT, chosen)
     # batched products in one launch equal the single ones bit for bit
     two = to_np(g.apply("K", torch.stack([xt, 2 * xt])))
     np.testing.assert_array_equal(two[0], on.astype(np.float32))
 
 
 @pytest.mark.parametrize("name", ["cube64_support2p5", "cube128_support2p5", "box128_odd_extents",
-                                  "paper_shape128_support1p5", "cube64_support2_config2"])
+                                  "paper_shape128_support1p5", "cube64_support2_config2",
+                                  "cube32_support2p5", "cube48_support2p5"])
 def test_fp64_register_path(name):
     """The FP64 K product on the register path (FP64 lines, the line-constant
     middle pass) against the FP64 LDS-tiled passes and the oracle, to the FP64
