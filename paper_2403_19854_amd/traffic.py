@@ -24,24 +24,41 @@ SOURCES = ["csrc/regpass.hip", "csrc/sepconv.hip", "csrc/kernels.hip", "csrc/fcr
            "csrc/fcrkpm_impl.hpp", "csrc/fft_core.hpp"]
 COPY_BYTES = 256 << 20
 
-# demangled kernel name -> the kind name the library's sampler reports
+# demangled kernel name -> the kind name the library's sampler reports; the
+# register passes are templates on the real type (", float>" / ", double>"
+# at the end; older builds had no type argument)
+_PASS = r"k_rpass<[^,]+(?:, \d+>)?, [^,]+, \d, "
+_T32 = r"(, (true|false))?(, float)?>"
+_T64 = r", (true|false), double>"
 _KINDS = [
     (r"k_rmid2?<", "sep_mid_k_f32"),
-    (r"k_rpass<[^,]+, [^,]+, \d, true, true, false, 1, 0(, (true|false))?>", "sep_part1_x_f32"),
-    (r"k_rpass<[^,]+, [^,]+, \d, false, false, false, 1, 1(, (true|false))?>", "sep_part1_y_f32"),
-    (r"k_rpass<[^,]+, [^,]+, \d, false, false, false, 2, 1(, (true|false))?>", "sep_part2_y_f32"),
-    (r"k_rpass<[^,]+, [^,]+, \d, true, false, true, 2, 0(, (true|false))?>", "sep_part2_x_f32"),
+    (r"k_smid<.*, float>", "sep_mid_k_f32"),
+    (r"k_smid<.*, double>", "sep_mid_k_f64"),
+    (_PASS + r"true, true, false, 1, 0" + _T32, "sep_part1_x_f32"),
+    (_PASS + r"false, false, false, 1, 1" + _T32, "sep_part1_y_f32"),
+    (_PASS + r"false, false, false, 2, 1" + _T32, "sep_part2_y_f32"),
+    (_PASS + r"true, false, true, 2, 0" + _T32, "sep_part2_x_f32"),
+    (_PASS + r"true, true, false, 1, 0" + _T64, "sep_part1_x_f64"),
+    (_PASS + r"false, false, false, 1, 1" + _T64, "sep_part1_y_f64"),
+    (_PASS + r"false, false, false, 2, 1" + _T64, "sep_part2_y_f64"),
+    (_PASS + r"true, false, true, 2, 0" + _T64, "sep_part2_x_f64"),
 ]
+
+_LAYOUT = r"(G16L?|G8<\d+>|GPQ<\d+, \d+>)"
 
 
 def _variant(name):
     """Register-path variant of a kernel name: layout + 2 (tiles - 1).  The pass
-    kernels carry the basis after the layout; the middle passes do not."""
-    m = re.search(r"k_rpass<[^,]*?(G16L?|G8<\d+>), [^,]+, (\d)", name) or \
-        re.search(r"k_rmid2?<[^,]*?(G16L?|G8<\d+>), (\d)", name)
-    if not m:
-        return None
-    return (1 if m.group(1).startswith("G16") else 0) + 2 * (int(m.group(2)) - 1)
+    kernels carry the basis after the layout; the middle passes do not, and the
+    line-constant middle pass has one tile per workgroup in every variant."""
+    m = re.search(r"k_rpass<[^<>]*?" + _LAYOUT + r", [^,]+, (\d)", name) or \
+        re.search(r"k_rmid2?<[^<>]*?" + _LAYOUT + r", (\d)", name)
+    if m:
+        return (1 if m.group(1).startswith("G16") else 0) + 2 * (int(m.group(2)) - 1)
+    m = re.search(r"k_smid<[^<>]*?" + _LAYOUT, name)
+    if m:
+        return 1 if m.group(1).startswith("G16") else 0
+    return None
 
 
 def source_hash() -> str:
@@ -108,8 +125,13 @@ def load(workload, kind, layout=None, path=None):
     if d.get("source_hash") != source_hash():
         return None
     k = d.get("kinds", {}).get(kind)
-    if k is None or (layout is not None and k.get("layout") != layout):
+    if k is None:
         return None
+    if layout is not None:
+        # the line-constant middle pass has one tile per workgroup in every variant
+        lay = layout & 1 if "smid" in k.get("kernel", "") else layout
+        if k.get("layout") != lay:
+            return None
     return k["bytes_per_launch"]
 
 

@@ -74,3 +74,34 @@ def test_variant_parsing():
     assert traffic._variant("k_rmid<fcrkpm::G16, 2, 3, 3>") == 3
     assert traffic._variant("k_rmid2<fcrkpm::G16L, 1>") == 1
     assert traffic._variant("k_cg_xr<float>") is None
+
+
+SMID = ("void fcrkpm::(anonymous namespace)::k_smid<fcrkpm::(anonymous namespace)::G16, float>"
+        "(fcrkpm::(anonymous namespace)::SArgs<float>)")
+X1_T = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G16, "
+        "fcrkpm::(anonymous namespace)::Lin3, 1, true, true, false, 1, 0, true, float>(x)")
+X1_64 = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::G16L, "
+         "fcrkpm::(anonymous namespace)::Lin3, 1, true, true, false, 1, 0, false, double>(x)")
+Y1_GPQ = ("void fcrkpm::(anonymous namespace)::k_rpass<fcrkpm::(anonymous namespace)::GPQ<6, 16>, "
+          "fcrkpm::(anonymous namespace)::Lin3, 1, false, false, false, 1, 1, false, float>(x)")
+
+
+def test_templated_kernel_names(tmp_path):
+    copy_kib = traffic.COPY_BYTES / 1024
+    _csv(tmp_path / "f.csv", "FETCH_SIZE",
+         [("__amd_rocclr_copyBuffer", copy_kib / 2), (SMID, 1000.0), (X1_T, 500.0), (X1_64, 800.0),
+          (Y1_GPQ, 300.0)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE",
+         [("__amd_rocclr_copyBuffer", copy_kib), (SMID, 400.0), (X1_T, 300.0), (X1_64, 600.0),
+          (Y1_GPQ, 100.0)])
+    out = tmp_path / "t.json"
+    d = traffic.summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(out), "wl", "cmd")
+    assert d["kinds"]["sep_mid_k_f32"]["layout"] == 1
+    assert d["kinds"]["sep_part1_x_f32"]["layout"] == 1
+    assert d["kinds"]["sep_part1_x_f64"]["fetch_bytes"] == 800.0 * 1024 * 2
+    assert d["kinds"]["sep_part1_y_f32"]["layout"] == 0
+    # the line-constant middle pass matches both tile counts of its layout
+    want = d["kinds"]["sep_mid_k_f32"]["bytes_per_launch"]
+    assert traffic.load("wl", "sep_mid_k_f32", 1, path=str(out)) == want
+    assert traffic.load("wl", "sep_mid_k_f32", 3, path=str(out)) == want
+    assert traffic.load("wl", "sep_mid_k_f32", 0, path=str(out)) is None
