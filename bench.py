@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=["c5", "paper", "c3", "c4", "c1", "c2"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "c5_256", "paper", "c3", "c4", "c1", "c2"])
     ap.add_argument("--c4-iters", type=int, default=240)
     ap.add_argument("--probe", type=int, default=0,
                     help="counter probe: setup, a refined solve capped at N CG iterations "
@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--maxit", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-cg-cap", type=int, default=10,
+                    help="iterations of the oracle's CG solve and adjoint on boxes above 64^3")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run exactly N CG iterations per step instead of solving to --tol "
                          "(throughput of workloads whose CG converges too slowly, e.g. c3)")
@@ -82,8 +84,8 @@ def main():
         a.mode = "f64" if a.workload in ("c1", "c2") else "f32_refined"
     if a.workload == "c4":
         return bench_c4(a)
-    wl = {"c5": W.config5, "paper": W.paper_shape, "c3": W.config3, "c1": W.config1,
-          "c2": W.config2}[a.workload]()
+    wl = {"c5": W.config5, "c5_256": W.config5_256, "paper": W.paper_shape, "c3": W.config3,
+          "c1": W.config1, "c2": W.config2}[a.workload]()
     if a.probe:
         return probe(a, wl)
     dev = torch.device("cuda:0")
@@ -108,7 +110,7 @@ def main():
             pb.profile(False)
             prof = pb.profile_read()
         pb.close()
-        return info, prof, uh
+        return info, prof, uh, d
 
     for _ in range(a.warmup):
         step(a.mode)
@@ -117,7 +119,7 @@ def main():
     infos = []
     prof_acc = {}
     for i in range(a.steps):
-        info, prof, uh = step(a.mode, profile=True)
+        info, prof, uh, d_final = step(a.mode, profile=True)
         infos.append(info)
         for k, (n, ms, by) in prof.items():
             n0, w0, b0 = prof_acc.get(k, (0, 0.0, 0.0))
@@ -178,7 +180,7 @@ def main():
     if not a.no_fp64_compare and a.mode != "f64":
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        info64, _, uh64 = step("f64")
+        info64, _, uh64, _ = step("f64")
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         e = float(np.linalg.norm((uh.cpu().numpy() - uh64.cpu().numpy())[m]) /
@@ -196,25 +198,90 @@ def main():
             out["transient"] = transient_time(a, wl, chi, dirm, vol, r, dev)
             out["flux"] = flux_time(a, wl, dev)
             out["nonlinear"] = nonlinear_time(a, wl, chi, dirm, vol, dev)
+            out["nonlinear_cg"] = nonlinear_cg_time(a, wl, chi, dirm, vol, dev)
 
     if not a.no_cpu_baseline:
-        import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        o = oracle.Oracle(wl.dims, wl.h, wl.at, wl.degree, wl.chi, wl.vol)
-        x = np.where(wl.free > 0, np.random.default_rng(0).standard_normal(wl.shape), 0.0)
-        n = 0
-        tc0 = time.perf_counter()
-        while True:
-            o.apply_k_free(x, wl.free)
-            n += 1
-            if time.perf_counter() - tc0 >= a.cpu_seconds:
-                break
-        tc = time.perf_counter() - tc0
-        out["cpu_baseline"] = {"value": n / tc, "unit": "matvec/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{n} oracle K products (neighbour-loop RKPM, FP64) on the "
-                                         f"same {wl.name} grid, {tc:.1f} s"}
+        gpu_iters = out.get("fp64_path", {}).get("iters")
+        out["cpu_baseline"] = cpu_baseline(a, wl, gpu_iters,
+                                           d_final.cpu().numpy() if a.fixed_iters else None)
+        if a.fixed_iters:
+            out["solve"]["oracle_rel_res"] = out["cpu_baseline"].pop("oracle_rel_res")
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(a, wl, gpu_iters=None, d_fixed=None):
+    """The oracle (FP64 neighbour-loop RKPM on the host cores) on the same grid:
+
+    * value: K products per second with all its threads, over about
+      --cpu-seconds of products;
+    * one_thread: one K product on one thread;
+    * solve / adjoint: its CG solve of the load (Alg 5) and its adjoint solve to
+      the bench tolerance; on boxes above 64^3 both are capped at --cpu-cg-cap
+      iterations and the time at the GPU's FP64 iteration count is extrapolated
+      from the time per iteration (stated as such);
+    * with d_fixed (a fixed-iteration GPU run), the relative residual
+      |chi_Omega (f^r - K d)| / |chi_Omega f^r| of that d under the oracle's
+      operator."""
+    import numpy as np
+
+    import oracle
+    from paper_2403_19854_amd import workloads as W
+
+    threads = oracle.threads(0)
+    t0 = time.perf_counter()
+    o = oracle.Oracle(wl.dims, wl.h, wl.at, wl.degree, wl.chi, wl.vol)
+    t_setup = time.perf_counter() - t0
+    x = np.where(wl.free > 0, np.random.default_rng(0).standard_normal(wl.shape), 0.0)
+    n = 0
+    tc0 = time.perf_counter()
+    while True:
+        o.apply_k_free(x, wl.free)
+        n += 1
+        if time.perf_counter() - tc0 >= a.cpu_seconds:
+            break
+    tc = time.perf_counter() - tc0
+    res = {"value": n / tc, "unit": "matvec/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} oracle K products (neighbour-loop RKPM, FP64) on the same {wl.name} "
+                     f"grid, {tc:.1f} s",
+           "setup_s": t_setup}
+    oracle.threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.apply_k_free(x, wl.free)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.threads(threads)
+    res["one_thread"] = {"value": 1.0 / t1, "unit": "matvec/s", "cores": 1,
+                         "sample": "one oracle K product on one thread"}
+    big = int(np.prod(wl.dims)) > 64 ** 3
+    cap = a.cpu_cg_cap if big else a.maxit
+    t0 = time.perf_counter()
+    _, it, rel = o.solve(wl.free, wl.dirichlet, wl.r, tol=a.tol, maxit=cap)
+    ts = time.perf_counter() - t0
+    sol = {"tol": a.tol, "iterations": it, "rel_res": rel, "seconds": ts, "cores": threads}
+    if rel > a.tol:
+        sol["capped_at"] = cap
+        sol["s_per_iteration"] = ts / max(it, 1)
+        if gpu_iters:
+            sol["est_seconds_at_gpu_fp64_iterations"] = ts / max(it, 1) * gpu_iters
+            sol["gpu_fp64_iterations"] = gpu_iters
+    res["solve"] = sol
+    rng = np.random.default_rng(7)
+    dl = (W.config5_target(wl) if wl.name.startswith("c5") else
+          np.where(wl.chi > 0, rng.standard_normal(wl.shape), 0.0))
+    t0 = time.perf_counter()
+    _, _, it = o.adjoint(wl.free, dl, tol=a.tol, maxit=cap)
+    ta = time.perf_counter() - t0
+    adj = {"tol": a.tol, "iterations": it, "seconds": ta, "cores": threads}
+    if big:
+        adj["capped_at"] = cap
+        adj["s_per_iteration"] = ta / max(it, 1)
+    res["adjoint"] = adj
+    if d_fixed is not None:
+        fr = np.where(wl.free > 0, o.apply_fr(wl.r), 0.0)
+        rr = np.where(wl.free > 0, fr - o.apply_k(d_fixed), 0.0)
+        res["oracle_rel_res"] = float(np.linalg.norm(rr) / np.linalg.norm(fr))
+    return res
 
 
 def time_to_solution(a, wl, chi, dirm, vol, r, dev):
@@ -380,6 +447,39 @@ def nonlinear_time(a, wl, chi, dirm, vol, dev, kappa=5.0):
     err = float(np.linalg.norm((uh.cpu().numpy() - wl.u_exact)[m]) / np.linalg.norm(wl.u_exact[m]))
     return {"kappa": kappa, "solve_ms": 1e3 * ts, "newton_steps": info["outer_iters"],
             "cg_iters": info["iters"], "residual": info["rel_res"], "uh_rel_l2_vs_exact": err}
+
+
+def nonlinear_cg_time(a, wl, chi, dirm, vol, dev, kappa=5.0, kappa_grad=0.5, tol=1e-10):
+    """Nonlinear CG (Alg B.3, FP64) on the same grid from d = 0, to relative
+    residual `tol`: the cubic force with r manufactured from the workload's u
+    (-lap u + kappa u^3 = r; u^h error reported), and the gradient force
+    (1 + kappa |grad u|^2) grad u with the workload's r."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+
+    pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+    m = wl.chi > 0
+    res = {"tol": tol}
+    for kind, kap, rr in (("cubic", kappa, wl.r + kappa * wl.u_exact ** 3),
+                          ("gradient", kappa_grad, wl.r)):
+        r = torch.from_numpy(rr).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, uh, info = pb.solve_nonlinear_cg(r, kap, kind=kind, tol=tol, maxit=a.maxit,
+                                            raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        e = {"kappa": kap, "solve_ms": 1e3 * ts, "cg_iters": info["iters"],
+             "line_search_steps": info["outer_iters"], "rel_res": info["true_rel_res"],
+             "status": info["status"]}
+        if kind == "cubic":
+            e["uh_rel_l2_vs_exact"] = float(np.linalg.norm((uh.cpu().numpy() - wl.u_exact)[m]) /
+                                            np.linalg.norm(wl.u_exact[m]))
+        res[kind] = e
+    pb.close()
+    return res
 
 
 def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5, op="K"):

@@ -32,24 +32,37 @@ _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc + OpenMP into ``oracle/liborc.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-             "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+# a copy built with AddressSanitizer + UBSan by clang (whose ASan runtime the
+# sanitized product library shares), loaded instead when FCRKPM_ORACLE_LIB names it
+_SAN_LIB = os.path.join(_HERE, "_build_san", "liborc.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc + OpenMP into ``oracle/liborc.so``, or with
+    sanitize=True with clang, ASan and UBSan into ``oracle/_build_san/liborc.so``."""
+    out = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(out):
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        tmp = out + ".tmp"
+        if sanitize:
+            cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                   "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                   "-fno-omit-frame-pointer", "-o", tmp, _SRC, "-lm"]
+        else:
+            cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    path = os.environ.get("FCRKPM_ORACLE_LIB") or _LIB
+    if path == _LIB and not os.path.exists(_LIB):
         build(force=True)
-    lib = C.CDLL(_LIB)
+    lib = C.CDLL(path)
     P = C.c_void_p
     dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
     up = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
@@ -57,6 +70,8 @@ def _load():
     ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
     lib.orc_phi1.restype = C.c_double
     lib.orc_phi1.argtypes = [C.c_double]
+    lib.orc_threads.restype = C.c_int
+    lib.orc_threads.argtypes = [C.c_int]
     lib.orc_basis_size.restype = C.c_int
     lib.orc_basis_size.argtypes = [C.c_int, C.c_int]
     lib.orc_create.restype = P
@@ -85,6 +100,11 @@ def _load():
                                 C.POINTER(C.c_double)]
     _lib = lib
     return lib
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0); return the count in force."""
+    return int(_load().orc_threads(int(n)))
 
 
 def phi1(z: float) -> float:

@@ -36,6 +36,7 @@
  * the 0/1 masks (uint8).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -99,6 +100,14 @@ static int make_basis(int dim, int degree, int ex[ORC_MAXS][3])
         }
     }
     return s;
+}
+
+/* Threads of the parallel loops below: n > 0 sets them, any n returns the
+ * count in force afterwards (timing plumbing; no arithmetic depends on it). */
+int orc_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 int orc_basis_size(int dim, int degree)

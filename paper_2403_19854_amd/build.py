@@ -25,15 +25,35 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2403_19854_amd/libfcrkpm.so."""
+# host-side AddressSanitizer + UBSan for a CPU-only check of the host code
+# (argument checks, planning, setup logic); the device code is built as usual.
+# Load the result with the clang ASan runtime preloaded (see SANITIZER_RUNTIME).
+SANITIZE_FLAGS = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined " \
+                 "-Xarch_host -fno-omit-frame-pointer -Xarch_host -fno-sanitize-recover=undefined"
+SAN_LIB = os.path.join(HERE, "_build_san", "libfcrkpm.so")
+
+
+def sanitizer_runtime() -> str:
+    """The clang ASan runtime that matches hipcc's host compiler."""
+    base = "/opt/rocm/llvm/lib/clang"
+    for v in sorted(os.listdir(base), reverse=True):
+        cand = os.path.join(base, v, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return cand
+    raise FileNotFoundError("libclang_rt.asan-x86_64.so not found under " + base)
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every HIP source into paper_2403_19854_amd/libfcrkpm.so, or with
+    sanitize=True the host-sanitized copy _build_san/libfcrkpm.so."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
     os.makedirs(bdir, exist_ok=True)
+    extra = SANITIZE_FLAGS.split() if sanitize else []
     procs = []
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
+        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -42,14 +62,15 @@ def build(verbose: bool = False) -> str:
     for p, cmd in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed: " + " ".join(cmd))
-    tmp = LIB + ".tmp"
+    out = SAN_LIB if sanitize else LIB
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

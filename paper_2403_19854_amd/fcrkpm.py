@@ -97,11 +97,14 @@ class FcrkpmError(RuntimeError):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libfcrkpm.so (raises if it has not been built)."""
+def load_library(path: str = None):
+    """Load libfcrkpm.so (raises if it has not been built).  FCRKPM_LIB names
+    another build of it (the host-sanitized one, for CPU checks)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("FCRKPM_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                            "(the FC-RKPM path has no CPU fallback)")

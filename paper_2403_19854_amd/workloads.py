@@ -274,6 +274,12 @@ def config5() -> Problem:
     return cube(3, 128, 2.5, 1, source="sin", name="c5_cube_128")
 
 
+def config5_256() -> Problem:
+    """Config 5's problem on a 256^3 box: the FP32 working set (about 0.9 GB)
+    is well above the 256 MB last-level cache, so counted bytes are HBM bytes."""
+    return cube(3, 256, 2.5, 1, source="sin", name="c5_cube_256")
+
+
 def config5_target(p: Problem) -> np.ndarray:
     """Smooth seeded target field u_t = sum_{k<8} a_k prod_j sin(l_kj pi x_j)."""
     rng = np.random.default_rng(5)
