@@ -272,8 +272,13 @@ fcrkpm_status fcrkpm_nonlinear_force(fcrkpm_ctx* ctx, double kappa, int32_t nrhs
  * fcrkpm_gradient_force -- f^N = B^T (V o N(B d)) with the gradient
  * nonlinearity N(g) = (1 + kappa |g|^2) g (App. B, Eq B.5-B.8, B.10; Alg B.1):
  * the passes of K with N applied to the implicit gradient at every node, so
- * kappa = 0 gives K d (domain mask in and out), FP64, asynchronous on `stream`;
- * d and out hold nrhs fields and must not overlap.
+ * kappa = 0 gives K d (domain mask in and out), FP64, asynchronous on `stream`
+ * (except the first call on the register path, which builds its records);
+ * d and out hold nrhs fields and must not overlap.  Where the FP64 register
+ * path serves the box (FCRKPM_OPT_KN_REGPATH), its middle pass applies each z
+ * line's constant gradient and divergence coefficients in the spectral domain
+ * with N between them and corrects the nodes near the domain's z ends directly
+ * (12 transforms per line pair; kappa = 0 then equals K d to rounding).
  * Errors: FCRKPM_ERR_ARG (NULL or overlapping arrays, nrhs, non-finite kappa),
  * FCRKPM_ERR_HIP.
  */
@@ -324,8 +329,11 @@ enum {
  *     FCRKPM_NONLIN_GRADIENT: R(d) = B^T (V (1 + kappa |B d|^2) B d) - f^r
  * to ||R|| <= tol ||chi_Omega f^r||.  Both are gradients of convex energies
  * (kappa >= 0), so the minimiser is unique; directions are Polak-Ribiere with
- * restarts, steps an exact line search (Newton on the nodal sums of the
- * energy's derivative along the direction).  FP64 throughout; one field.
+ * restarts, steps an exact line search: the energy's derivative along the
+ * direction is a cubic in the step whose coefficients one pass over the nodes
+ * gives, and its root is found on the host by safeguarded Newton steps.  FP64
+ * throughout (the gradient form on the FP64 register path where
+ * FCRKPM_OPT_KN_REGPATH reads 1); one field.
  *
  *   kind        FCRKPM_NONLIN_*
  *   kappa       >= 0
@@ -335,7 +343,8 @@ enum {
  *   uh_out      device FP64 u^h = N d, or NULL
  *   tol, maxit  residual target and iteration cap
  *   info        one record (may be NULL): iters = nonlinear CG iterations,
- *               outer_iters = line-search Newton steps, rel_res = true_rel_res
+ *               outer_iters = line-search Newton steps (host arithmetic on the
+ *               cubic), rel_res = true_rel_res
  *               = final ||R|| / ||chi_Omega f^r||, matvecs_f64 = K-type products
  *
  * Allocates its work vectors for the call (about 10 node fields).  Errors:
@@ -448,12 +457,15 @@ const char* fcrkpm_kernel_name(int32_t kind);
 enum {
     FCRKPM_OPT_GRAPHS = 1,  /* 1 (default): CG blocks replay captured HIP graphs; 0: direct
                                launches.  Graphs are never used while profiling is on. */
-    FCRKPM_OPT_REGPATH = 2,  /* 1 (default): FP32 K-type products (K, the consistent mass and
-                                the shifted and Jacobian operators built from them) on 3D
-                                boxes whose axes are 64 or 128 nodes long use
-                                register-resident line transforms: linear basis for every
-                                such product, quadratic basis for K itself; 0: the LDS-tiled
-                                passes used everywhere else */
+    FCRKPM_OPT_REGPATH = 2,  /* 1 (default): K-type products on 3D boxes whose axes are
+                                register-path lengths use register-resident line transforms:
+                                FP32 (K, the consistent mass and the shifted and Jacobian
+                                operators built from them) at 32, 48, 64, 80, 96, 128 and 256
+                                points with the linear basis and at 64 and 128 with the
+                                quadratic basis (K only); FP64 (K, the gradient force and the
+                                implicit gradient) at 32, 48, 64 and 128 points with the
+                                linear basis and the line-constant middle pass; 0: the
+                                LDS-tiled passes used everywhere else */
     FCRKPM_OPT_REGLAYOUT = 3, /* variant of those transforms, layout + 2 (tiles - 1): layout 0 =
                                  8 lanes per line, 1 = 16 lanes (128-point lines only); tiles =
                                  1 or 2 tiles per workgroup (the second tile's loads overlap the
@@ -474,10 +486,13 @@ enum {
     FCRKPM_OPT_SEP_LINES32 = 9,  /* LDS-tiled passes, FP32: most lines per workgroup (16, 8, 4) */
     FCRKPM_OPT_SEP_LINES64 = 10, /* the same for FP64.  Setup times K products with each on the
                                     precisions that run on these passes and keeps the fastest. */
-    FCRKPM_OPT_TUNE_CACHED = 11  /* read only: 1 if setup took its tuning choices from the file
+    FCRKPM_OPT_TUNE_CACHED = 11, /* read only: 1 if setup took its tuning choices from the file
                                     named by FCRKPM_AUTOTUNE_CACHE (keyed by device, box, basis
                                     and support) instead of timing; new choices are appended to
                                     that file */
+    FCRKPM_OPT_KN_REGPATH = 12   /* read only: 1 if fcrkpm_gradient_force (and the gradients of
+                                    fcrkpm_solve_nonlinear_cg) run on the FP64 register path;
+                                    the first read builds that path's records (synchronous) */
 };
 /* Set an option; FCRKPM_ERR_ARG for an unknown option or a value out of range. */
 fcrkpm_status fcrkpm_set_option(fcrkpm_ctx* ctx, int32_t option, int64_t value);

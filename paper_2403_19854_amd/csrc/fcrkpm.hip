@@ -704,6 +704,11 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
                     reg_k64(c, in, out, mk, nrhs, st);
                     break;
                 }
+                if (op == OP_KN && use_reg_path64(c) && reg_kn_ok(c, st)) {
+                    for (int j = 0; j < nrhs; ++j)
+                        launch_reg_kn(c, in + (size_t)j * c.nn, out + (size_t)j * c.nn, c.pw_kappa, false, st);
+                    break;
+                }
             }
             cplx<T>* cur = part1<T, Tio>(c, sp, in, mk, S1, S2, nrhs, st);
             cplx<T>* dst = (cur == S1) ? S2 : S1;
@@ -2489,6 +2494,10 @@ namespace {
 // with the coefficient rows b^a in place of b^0 (Eq 15-16, Alg 3 with b^a)
 void apply_grad(Ctx& c, const double* x, double* out, hipStream_t st)
 {
+    if (use_reg_path64(c) && reg_kn_ok(c, st)) {
+        launch_reg_kn(c, x, out, 0.0, true, st);
+        return;
+    }
     double* keep = c.b0_64;
     struct Restore {
         Ctx& c;
@@ -2561,6 +2570,10 @@ extern "C" fcrkpm_status fcrkpm_solve_nonlinear_cg(fcrkpm_ctx* ctx, int32_t kind
         double* b = vec(cubic ? 1 : dim);   // w = N p, or h = B p
         double* kd = cubic ? vec(1) : nullptr;
         double* kp = cubic ? vec(1) : nullptr;
+        // the line search's partials (4 x kRedBlocks) and its 4 sums (kScal apart)
+        double* lsb = dalloc<double>(4 * (size_t)kRedBlocks + 4 * (size_t)kScal);
+        bufs.push_back(lsb);
+        std::vector<double> hq(4 * (size_t)kScal);
         int products = 0;
 
         // d: g on the Dirichlet nodes, the initial guess on the free nodes
@@ -2622,20 +2635,33 @@ extern "C" fcrkpm_status fcrkpm_solve_nonlinear_cg(fcrkpm_ctx* ctx, int32_t kind
                 dots<double>(c, fr, p, 1, S_NORM, st);
                 c0 = -read_scalars(c, 1, st)[S_NORM];
             }
-            // Newton on phi'(alpha) from alpha = 0; phi is convex along p, so the
-            // steps converge quadratically until the sums' rounding dominates
-            double alpha = 0.0;
-            for (int k = 0; k < 30; ++k) {
-                launch_ls_sums(cubic ? 0 : 1, dim, a, b, vol, c.chi, kappa, alpha, nn, c.partial, st);
-                launch_reduce_to(c.partial, nn, 1, c.scal + 6, st);
-                launch_reduce_to(c.partial + kRedBlocks, nn, 1, c.scal + 7, st);
-                const double* h = read_scalars(c, 1, st);
-                const double d1 = c0 + alpha * c1 + h[6], d2 = c1 + h[7];
+            // phi'(alpha) = c0 + c1 alpha + q0 + q1 alpha + q2 alpha^2 + q3 alpha^3,
+            // the q_j from one pass over the nodes; its root by safeguarded Newton
+            // steps on the host (phi is convex along p: phi' increases, and
+            // phi'(0) < 0 along a descent direction)
+            launch_ls_poly(cubic ? 0 : 1, dim, a, b, vol, c.chi, kappa, nn, lsb, st);
+            launch_reduce_to(lsb, nn, 4, lsb + 4 * kRedBlocks, st);
+            double q[4];
+            HIPCHK(hipMemcpyAsync(hq.data(), lsb + 4 * kRedBlocks, sizeof(double) * 4 * kScal,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int j = 0; j < 4; ++j) q[j] = hq[j * kScal];
+            auto d1f = [&](double x) { return c0 + c1 * x + q[0] + x * (q[1] + x * (q[2] + x * q[3])); };
+            auto d2f = [&](double x) { return c1 + q[1] + x * (2.0 * q[2] + 3.0 * x * q[3]); };
+            double alpha = 0.0, lo = 0.0, hi = HUGE_VAL;
+            bool polish = false;  // one more step once the steps are at 1e-12 of alpha
+            for (int k = 0; k < 60; ++k) {
+                const double d1 = d1f(alpha), d2 = d2f(alpha);
                 ++lsteps;
-                if (!(d2 > 0.0) || !std::isfinite(d1)) break;
-                const double step = d1 / d2;
-                alpha -= step;
-                if (fabs(step) <= 1e-12 * fabs(alpha)) break;
+                if (!std::isfinite(d1) || !(d2 > 0.0) || d1 == 0.0) break;
+                if (d1 < 0.0) lo = alpha;
+                else hi = alpha;
+                double next = alpha - d1 / d2;
+                if (!(next > lo && next < hi)) next = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.0 * lo + 1.0;
+                const double step = next - alpha;
+                alpha = next;
+                if (polish) break;
+                polish = fabs(step) <= 1e-12 * fabs(alpha);
             }
             if (!std::isfinite(alpha)) break;
             launch_lincomb_masked(d, 1.0, p, alpha, nullptr, c.chi, d, nn, 1, st);
@@ -2803,6 +2829,7 @@ extern "C" fcrkpm_status fcrkpm_get_option(fcrkpm_ctx* ctx, int32_t option, int6
             case FCRKPM_OPT_SEP_LINES32: *value = c.sep_wcap[0]; break;
             case FCRKPM_OPT_SEP_LINES64: *value = c.sep_wcap[1]; break;
             case FCRKPM_OPT_TUNE_CACHED: *value = c.tune_cached ? 1 : 0; break;
+            case FCRKPM_OPT_KN_REGPATH: *value = (use_reg_path64(c) && reg_kn_ok(c, nullptr)) ? 1 : 0; break;
             default: fail(FCRKPM_ERR_ARG, "unknown option");
         }
         return FCRKPM_OK;

@@ -250,11 +250,17 @@ bool sym_active(const Ctx& c);
 void sym_release(Ctx& c);
 // algorithmic bytes of one launch of that middle pass per right-hand side
 double sym_pass_bytes(const Ctx& c, int elem_bytes);
-// The FP64 K product on the register path (linear basis, 64^3 or 128^3 boxes
+// The FP64 K product on the register path (linear basis, 32^3, 48^3, 64^3 or 128^3 boxes
 // with the line-constant middle pass): reg_path64_ok tells whether it
 // applies; with dot_part the last pass also leaves the per-workgroup partials
 // of out . dot_with (reg_path64_blocks of them per right-hand side).
 bool reg_path64_ok(const Ctx& c);
+// The force of the gradient nonlinearity and the implicit gradient B d on the
+// FP64 register path (line-constant middle pass with the nonlinearity between
+// its halves); reg_kn_ok builds its records on first use and tells whether
+// the path serves this problem.  One field per launch.
+bool reg_kn_ok(const Ctx& c, hipStream_t st);
+void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st);
 long reg_path64_blocks(const Ctx& c);
 void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
                     double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof);
@@ -294,12 +300,12 @@ void launch_op_rows(const Ctx& c, double ck, double cm, double* o64, float* o32,
                     const double* wnode = nullptr);
 // out = kappa u^pw (pw 2 or 3) over n values
 void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long n, hipStream_t st);
-// nodal sums of the exact line search of the nonlinear CG (kind 0: kappa u^3 with
-// a = N d, b = N p; kind 1: (1 + kappa |g|^2) g with a = B d, b = B p, dim fields
-// each): per-block partials of phi' and phi'' in part[b], part[kRedBlocks + b]
-void launch_ls_sums(int kind, int dim, const double* a, const double* b, const double* vol,
-                    const uint8_t* chi, double kappa, double alpha, long n, double* part,
-                    hipStream_t st);
+// coefficients of the nonlinear part of the nonlinear CG's line-search
+// derivative, a cubic in the step (kind 0: kappa u^3 with a = N d, b = N p;
+// kind 1: (1 + kappa |g|^2) g with a = B d, b = B p, dim fields each):
+// per-block partials of c_j in part[j kRedBlocks + b], j = 0..3
+void launch_ls_poly(int kind, int dim, const double* a, const double* b, const double* vol,
+                    const uint8_t* chi, double kappa, long n, double* part, hipStream_t st);
 // out = mask ? wa a + wb b + c : 0 (b and c may be NULL) over nrhs fields
 void launch_lincomb_masked(const double* a, double wa, const double* b, double wb, const double* cc,
                            const uint8_t* mask, double* out, long nn, int nrhs, hipStream_t st);

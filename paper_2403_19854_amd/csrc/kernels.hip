@@ -725,58 +725,64 @@ void launch_pow_scaled(const double* u, double kappa, int pw, double* out, long 
                        pw == 3 ? 1 : 0, out, n);
 }
 
-// Nodal sums of the exact line search of the nonlinear CG (App. B.3) along
-// d + alpha p, over the domain nodes (weights V):
-//   kind 0, N(u) = kappa u^3, fields u = N d, w = N p, ua = u + alpha w:
-//     s1 = sum V kappa ua^3 w,  s2 = sum 3 V kappa ua^2 w^2;
+// Line search of the nonlinear CG (App. B.3, Alg B.3): the nonlinear part of
+// phi'(alpha) = R(d + alpha p) . p is a nodal sum that is a cubic polynomial
+// in alpha, s(alpha) = c0 + c1 alpha + c2 alpha^2 + c3 alpha^3, over the
+// domain nodes (chi), so one pass gives its four coefficients:
+//   kind 0, N(u) = kappa u^3, fields u = N d, w = N p: V kappa (u + alpha w)^3 w,
+//     c0 = sum V kappa u^3 w, c1 = 3 sum V kappa u^2 w^2, c2 = 3 sum V kappa u w^3,
+//     c3 = sum V kappa w^4;
 //   kind 1, N(g) = (1 + kappa |g|^2) g, fields g = B d, h = B p (dim
-//     components nn apart), ga = g + alpha h:
-//     s1 = sum V (1 + kappa |ga|^2) ga . h,
-//     s2 = sum V [(1 + kappa |ga|^2) |h|^2 + 2 kappa (ga . h)^2].
-// Per-block partials go to part[b] (s1) and part[kRedBlocks + b] (s2).
-__global__ __launch_bounds__(kRedThreads) void k_ls_sums(int kind, int dim, const double* __restrict__ a,
+//     components nn apart): V (1 + kappa |g + alpha h|^2)(g + alpha h) . h with
+//     gg = |g|^2, gh = g . h, hh = |h|^2,
+//     c0 = sum V (1 + kappa gg) gh, c1 = sum V [(1 + kappa gg) hh + 2 kappa gh^2],
+//     c2 = 3 sum V kappa gh hh, c3 = sum V kappa hh^2.
+// Per-block partials of c_j go to part[j kRedBlocks + b].
+__global__ __launch_bounds__(kRedThreads) void k_ls_poly(int kind, int dim, const double* __restrict__ a,
                                                          const double* __restrict__ b,
                                                          const double* __restrict__ vol,
                                                          const uint8_t* __restrict__ chi, double kappa,
-                                                         double alpha, long n, double* __restrict__ part)
+                                                         long n, double* __restrict__ part)
 {
     __shared__ double sh[16];
-    double s1 = 0.0, s2 = 0.0;
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x) {
         if (!chi[i]) continue;
         const double v = vol[i];
         if (kind == 0) {
-            const double ua = a[i] + alpha * b[i], w = b[i];
-            s1 += v * kappa * ua * ua * ua * w;
-            s2 += 3.0 * v * kappa * ua * ua * w * w;
+            const double u = a[i], w = b[i], vk = v * kappa;
+            c[0] += vk * u * u * u * w;
+            c[1] += 3.0 * vk * u * u * w * w;
+            c[2] += 3.0 * vk * u * w * w * w;
+            c[3] += vk * w * w * w * w;
         } else {
-            double g2 = 0.0, gh = 0.0, h2 = 0.0;
+            double gg = 0.0, gh = 0.0, hh = 0.0;
             for (int k = 0; k < dim; ++k) {
-                const double h = b[(long)k * n + i], ga = a[(long)k * n + i] + alpha * h;
-                g2 += ga * ga;
-                gh += ga * h;
-                h2 += h * h;
+                const double g = a[(long)k * n + i], h = b[(long)k * n + i];
+                gg += g * g;
+                gh += g * h;
+                hh += h * h;
             }
-            const double f = 1.0 + kappa * g2;
-            s1 += v * f * gh;
-            s2 += v * (f * h2 + 2.0 * kappa * gh * gh);
+            const double f = 1.0 + kappa * gg;
+            c[0] += v * f * gh;
+            c[1] += v * (f * hh + 2.0 * kappa * gh * gh);
+            c[2] += 3.0 * v * kappa * gh * hh;
+            c[3] += v * kappa * hh * hh;
         }
     }
-    const double t1 = block_sum(s1, sh);
-    const double t2 = block_sum(s2, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = t1;
-        part[kRedBlocks + blockIdx.x] = t2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double t = block_sum(c[j], sh);
+        if (threadIdx.x == 0) part[(long)j * kRedBlocks + blockIdx.x] = t;
     }
 }
 
-void launch_ls_sums(int kind, int dim, const double* a, const double* b, const double* vol,
-                    const uint8_t* chi, double kappa, double alpha, long n, double* part,
-                    hipStream_t st)
+void launch_ls_poly(int kind, int dim, const double* a, const double* b, const double* vol,
+                    const uint8_t* chi, double kappa, long n, double* part, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ls_sums, dim3(red_blocks(n)), dim3(kRedThreads), 0, st, kind, dim, a, b, vol,
-                       chi, kappa, alpha, n, part);
+    hipLaunchKernelGGL(k_ls_poly, dim3(red_blocks(n)), dim3(kRedThreads), 0, st, kind, dim, a, b, vol,
+                       chi, kappa, n, part);
 }
 
 __global__ void k_lincomb_masked(const double* __restrict__ a, double wa,

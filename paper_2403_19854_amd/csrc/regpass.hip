@@ -1612,6 +1612,328 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     }
 }
 
+// ------------------------------------------------ gradient nonlinearity, line-constant
+// The force of N(g) = (1 + kappa |g|^2) g (Alg B.1) and the implicit gradient
+// B d on the register path.  Along a z line both halves of the pointwise stage
+// have constant coefficients away from the correction nodes: the gradient
+// A^a = sum_q b^a_q D_q (Eq 15-16) with the line's B_L, and E_p = V sum_a b^a_p
+// N^a with C_L = V_L B_L.  So the middle pass applies B_L to the part-1 z
+// spectra, transforms back, corrects A at the correction nodes with the taps,
+// applies N node by node, transforms N, applies C_L with the reflected part-2
+// spectra, and corrects the output at the window nodes -- 12 transforms per
+// line pair.  GRAD stops after A and stores its three components.
+constexpr int kKnC = 48;                            // record words per correction node
+constexpr int kKnRec = 48 + kKnC * kSymC + 4;       // words per pair record
+constexpr int kKnFlag = kKnRec - 1;
+constexpr int kKnLine = 24 + 24 * kSymC;            // FP64 words per line record
+
+template <typename T>
+struct KArgs {
+    const T* in;
+    T* out;
+    long fstride, in_rb, out_rb, st;
+    const T* tr;           // [2][L]: Re T_0 / L, Im T_1 / L of the axis
+    const cplx<T>* tw;
+    const int* pidx;       // per pair: its record
+    const T* rec;          // records: B mean (12), B half difference (12), C mean (12),
+                           // C half difference (12), per correction node 24 entries of dB
+                           // and dC for both lines interleaved, ..., flag
+    const SymTab* tab;
+    T kappa;
+};
+
+// Y_a (+)= G_a(B) x_f for input column F of the gradient operator: A^a(k) =
+// (B_a0 a + i B_a3 b) X0 + B_a1 a X1 + B_a2 a X2 (B row-major [a][q])
+template <class Lay, class Sp, int F, bool SET, typename T>
+__device__ __forceinline__ void kn_grad_col(const cplx<T> (&W)[Lay::PTS], cplx<T> (&Y)[3][Lay::PTS], const T* Bm,
+                                            const Sp& sp)
+{
+    typedef cplx<T> cf;
+#pragma unroll
+    for (int i = 0; i < Lay::PTS; ++i) {
+        const T a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
+        const cf w = W[i];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            cf c;
+            if constexpr (F == 0) c = cf{Bm[al * 4 + 0] * a, Bm[al * 4 + 3] * b};
+            else c = cf{Bm[al * 4 + F] * a, T(0)};
+            Y[al][i] = SET ? cf{c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x}
+                            : cf{Y[al][i].x + c.x * w.x - c.y * w.y, Y[al][i].y + c.x * w.y + c.y * w.x};
+        }
+    }
+}
+
+// Z_f += Q_f(C) n_a for input column a of the divergence operator: Z_0 =
+// sum_a (C_a0 a - i C_a3 b) N^a, Z_1 = sum_a C_a1 a N^a, Z_2 = sum_a C_a2 a N^a
+// (C row-major [a][p] = V b^a_p)
+template <class Lay, class Sp, typename T>
+__device__ __forceinline__ void kn_div_col(int al, const cplx<T> (&W)[Lay::PTS], cplx<T> (&Z)[3][Lay::PTS],
+                                           const T* Cm, const Sp& sp)
+{
+    typedef cplx<T> cf;
+    const T c0 = Cm[al * 4 + 0], c1 = Cm[al * 4 + 1], c2 = Cm[al * 4 + 2], c3 = Cm[al * 4 + 3];
+#pragma unroll
+    for (int i = 0; i < Lay::PTS; ++i) {
+        const T a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
+        const cf w = W[i];
+        const cf q0 = {c0 * a, -c3 * b};
+        Z[0][i] = cf{Z[0][i].x + q0.x * w.x - q0.y * w.y, Z[0][i].y + q0.x * w.y + q0.y * w.x};
+        Z[1][i] = cf{Z[1][i].x + c1 * a * w.x, Z[1][i].y + c1 * a * w.y};
+        Z[2][i] = cf{Z[2][i].x + c2 * a * w.x, Z[2][i].y + c2 * a * w.y};
+    }
+}
+
+// correction index of node z (or -1)
+__device__ __forceinline__ int corr_of(const SymTab& tb, int z)
+{
+    int ci = -1;
+    for (int k = 0; k < tb.nc; ++k)
+        if (tb.cz[k] == z) ci = k;
+    return ci;
+}
+
+template <class Lay, typename T, bool GRAD>
+__global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
+{
+    typedef cplx<T> cf;
+    constexpr int L = Lay::L, R = Lay::PTS, SP = Lay::SPTS;
+    constexpr bool STG = sizeof(T) == 4;
+    constexpr int CW = 3 * kSymW + 4 * kSymC + 3 * kSymC;  // window values (later output
+                                                          // corrections), dE, dA (later N)
+    __shared__ cf tw[L];
+    __shared__ T trl[Tables<Lay, Lin3::NE, T>::LDS_SPEC];
+    __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
+    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
+    __shared__ cf cbuf[Lay::GROUPS * CW];
+    __shared__ SymTab tb;
+    const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
+    const int gc = STG ? tid % Lay::GROUPS : g, tc = STG ? tid / Lay::GROUPS : t;
+    const long rhs = blockIdx.y;
+    const T* in = a.in + rhs * a.in_rb;
+    T* out = a.out + rhs * a.out_rb;
+    const long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const long base = tile_base<Lay, false>(tile, a.st);
+    cf* xb = xbuf + g * Lay::XS;
+    cf* cw = cbuf + g * CW;          // [3][kSymW] window values, then output corrections
+    cf* ce = cw + 3 * kSymW;         // [4][kSymC] dE at the correction nodes
+    cf* ca = ce + 4 * kSymC;         // [3][kSymC] dA, then N, at the correction nodes
+    Tables<Lay, Lin3::NE, T> tabs;
+    tabs.fetch(a);
+    typename Lay::template Spec<Lin3::NE, T> sp;
+    sp.template fetch<Lay>(a.tr, t);
+
+    cf X[3][R];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < SP; ++m)
+            X[f][m] = load_pair<L, false>(in + f * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st));
+    const long pair = tile * Lay::GROUPS + g;
+    const T* rec = a.rec + (size_t)a.pidx[pair] * kKnRec;
+    if (tid < (int)(sizeof(SymTab) / 4))
+        reinterpret_cast<int*>(&tb)[tid] = reinterpret_cast<const int*>(a.tab)[tid];
+    tabs.put(tw, trl);  // its barrier also publishes tb
+    sp.template bind<Lay>(trl, t);
+    typename Lay::template TwT<T> lw;
+    lw.make(t, tw);
+    if constexpr (STG) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+    }
+#pragma unroll
+    for (int m = 0; m < SP; ++m) {
+        const int wi = tb.widx[Lay::row(t, m)];
+        if (wi >= 0) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) cw[f * kSymW + wi] = X[f][m];
+        }
+    }
+    const bool mismatch = rec[kKnFlag] != T(0);
+    wave_sync();
+    // dA = (B - B_L) D at the correction nodes, D from the taps; each line of
+    // the pair with its own dB
+    for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
+        const int cz = tb.cz[ci];
+        cf D[4] = {};
+        for (int o = -tb.m; o <= tb.m; ++o) {
+            const int wi = tb.widx[(cz - o + L) % L];
+            const T t0 = tap0_of<T>(tb, o + tb.m), t1 = tap1_of<T>(tb, o + tb.m);
+            const cf x0 = cw[wi], x1 = cw[kSymW + wi], x2 = cw[2 * kSymW + wi];
+            D[0] = cf{D[0].x + t0 * x0.x, D[0].y + t0 * x0.y};
+            D[1] = cf{D[1].x + t0 * x1.x, D[1].y + t0 * x1.y};
+            D[2] = cf{D[2].x + t0 * x2.x, D[2].y + t0 * x2.y};
+            D[3] = cf{D[3].x + t1 * x0.x, D[3].y + t1 * x0.y};
+        }
+        const T* dm = rec + 48 + kKnC * ci;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            cf s = {};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = al * 4 + q;
+                s = cf{s.x + dm[2 * e] * D[q].x, s.y + dm[2 * e + 1] * D[q].y};
+            }
+            ca[al * kSymC + ci] = s;
+        }
+    }
+    // the gradient's constant part in the spectral domain
+#pragma unroll
+    for (int f = 0; f < 3; ++f) Lay::fwd(X[f], t, xb, lw);
+    cf Y[3][R];
+    {
+        T Bm[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) Bm[e] = rec[e];
+        kn_grad_col<Lay, decltype(sp), 0, true>(X[0], Y, Bm, sp);
+        kn_grad_col<Lay, decltype(sp), 1, false>(X[1], Y, Bm, sp);
+        kn_grad_col<Lay, decltype(sp), 2, false>(X[2], Y, Bm, sp);
+    }
+    if (mismatch) {
+        // lines of different B_L: the half difference on conj X(-k)
+        T Bd[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) Bd[e] = rec[12 + e];
+        cf W[R];
+        conj_neg<Lay>(X[0], W, t, xb);
+        kn_grad_col<Lay, decltype(sp), 0, false>(W, Y, Bd, sp);
+        conj_neg<Lay>(X[1], W, t, xb);
+        kn_grad_col<Lay, decltype(sp), 1, false>(W, Y, Bd, sp);
+        conj_neg<Lay>(X[2], W, t, xb);
+        kn_grad_col<Lay, decltype(sp), 2, false>(W, Y, Bd, sp);
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al) Lay::inv(Y[al], t, xb, lw);
+    wave_sync();
+    // A at the correction nodes
+#pragma unroll
+    for (int m = 0; m < SP; ++m) {
+        const int z = Lay::row(t, m);
+        if (tb.widx[z] >= 0) {
+            const int ci = corr_of(tb, z);
+            if (ci >= 0) {
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    const cf d = ca[al * kSymC + ci];
+                    Y[al][m] = cf{Y[al][m].x + d.x, Y[al][m].y + d.y};
+                }
+            }
+        }
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
+#pragma unroll
+            for (int m = 0; m < SP; ++m)
+                store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
+        }
+        return;
+    } else {
+        // N(A) node by node, each real line on its own; N at the correction
+        // nodes kept for their dE
+        wave_sync();  // the dA reads above before the N writes below
+#pragma unroll
+        for (int m = 0; m < SP; ++m) {
+            const T sx = T(1) + a.kappa * (Y[0][m].x * Y[0][m].x + Y[1][m].x * Y[1][m].x + Y[2][m].x * Y[2][m].x);
+            const T sy = T(1) + a.kappa * (Y[0][m].y * Y[0][m].y + Y[1][m].y * Y[1][m].y + Y[2][m].y * Y[2][m].y);
+#pragma unroll
+            for (int al = 0; al < 3; ++al) Y[al][m] = cf{sx * Y[al][m].x, sy * Y[al][m].y};
+            const int z = Lay::row(t, m);
+            if (tb.widx[z] >= 0) {
+                const int ci = corr_of(tb, z);
+                if (ci >= 0) {
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) ca[al * kSymC + ci] = Y[al][m];
+                }
+            }
+        }
+        wave_sync();
+        // dE = (C - C_L) N at the correction nodes
+        for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
+            const T* dm = rec + 48 + kKnC * ci + 24;
+            cf n[3];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) n[al] = ca[al * kSymC + ci];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                cf s = {};
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    const int e = al * 4 + p;
+                    s = cf{s.x + dm[2 * e] * n[al].x, s.y + dm[2 * e + 1] * n[al].y};
+                }
+                ce[p * kSymC + ci] = s;
+            }
+        }
+        // the divergence's constant part in the spectral domain
+#pragma unroll
+        for (int al = 0; al < 3; ++al) Lay::fwd(Y[al], t, xb, lw);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < R; ++i) X[f][i] = cf{};
+        {
+            T Cm[12];
+#pragma unroll
+            for (int e = 0; e < 12; ++e) Cm[e] = rec[24 + e];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) kn_div_col<Lay>(al, Y[al], X, Cm, sp);
+        }
+        if (mismatch) {
+            T Cd[12];
+#pragma unroll
+            for (int e = 0; e < 12; ++e) Cd[e] = rec[36 + e];
+            cf W[R];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                conj_neg<Lay>(Y[al], W, t, xb);
+                kn_div_col<Lay>(al, W, X, Cd, sp);
+            }
+        }
+        wave_sync();  // the dE writes (and the window reads) before what follows
+        // output corrections at the window nodes (part 2: dZ(z) = sum_c t[c - z] dE(c))
+        for (int wi = t; wi < tb.nw; wi += Lay::LANES) {
+            const int z = tb.wz[wi];
+            cf z0 = {}, z1 = {}, z2 = {};
+            for (int ci = 0; ci < tb.nc; ++ci) {
+                int d = tb.cz[ci] - z;
+                if (d > L / 2) d -= L;
+                if (d < -L / 2) d += L;
+                if (d < -tb.m || d > tb.m) continue;
+                const T t0 = tap0_of<T>(tb, d + tb.m), t1 = tap1_of<T>(tb, d + tb.m);
+                const cf e0 = ce[ci], e1 = ce[kSymC + ci], e2 = ce[2 * kSymC + ci], e3 = ce[3 * kSymC + ci];
+                z0 = cf{z0.x + t0 * e0.x + t1 * e3.x, z0.y + t0 * e0.y + t1 * e3.y};
+                z1 = cf{z1.x + t0 * e1.x, z1.y + t0 * e1.y};
+                z2 = cf{z2.x + t0 * e2.x, z2.y + t0 * e2.y};
+            }
+            cw[wi] = z0;
+            cw[kSymW + wi] = z1;
+            cw[2 * kSymW + wi] = z2;
+        }
+#pragma unroll
+        for (int o = 0; o < 3; ++o) Lay::inv(X[o], t, xb, lw);
+#pragma unroll
+        for (int m = 0; m < SP; ++m) {
+            const int wi = tb.widx[Lay::row(t, m)];
+            if (wi >= 0) {
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    const cf d = cw[o * kSymW + wi];
+                    X[o][m] = cf{X[o][m].x + d.x, X[o][m].y + d.y};
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            if constexpr (STG) stage_move<Lay>(X[o], stage[(3 + o) & 1], g, t, gc, tc);
+#pragma unroll
+            for (int m = 0; m < SP; ++m)
+                store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), X[o][m]);
+        }
+    }
+}
+
 // Setup of the line-constant middle pass, in FP64.  Line l = x + nx y: M(z)
 // at every z, the line's M_L = M(zref), a check that M(z) = M_L off the
 // correction nodes (to tol of the product's interior scale), and the line
@@ -1701,6 +2023,13 @@ struct SymState {
     float* rec = nullptr;        // device, 1 + pairs records
     double* rec64 = nullptr;     // the same in FP64
     long own = 0;                // pairs with a record of their own
+    SymTab htab{};               // host copy of the table
+    int zref = -1;               // the reference node of every line
+    double tol = 0.0;            // the records' equality tolerance (M's scale)
+    // the gradient nonlinearity's records (B_L, C_L = V_L B_L), built on first use
+    int kn = 0;                  // 0 not tried, 1 built, -1 unavailable
+    int* knpidx = nullptr;
+    double* knrec = nullptr;
 };
 
 // cubic B-spline of Eq 7 at z = |x| / a
@@ -2135,6 +2464,7 @@ bool sym_ready(const Ctx& c);
 // 64^3 and 128^3 boxes and the 32- and 48-point P x Q layouts
 bool reg_path64_ok(const Ctx& c)
 {
+    // (80, 96 and 256 points would hold 10-16 FP64 values per lane and field)
     const bool lay = reg_path_ok(c) || (reg_gpq_ok(c) && (c.n[0] == 32 || c.n[0] == 48));
     return c.degree == 1 && lay && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
 }
@@ -2209,6 +2539,8 @@ void sym_release(Ctx& c)
     sym_free(s->pidx);
     sym_free(s->rec);
     sym_free(s->rec64);
+    sym_free(s->knpidx);
+    sym_free(s->knrec);
     delete s;
     c.sym = nullptr;
 }
@@ -2331,8 +2663,216 @@ void sym_build(Ctx& c, hipStream_t st)
     sym_free(lrec);
     sym_free(czl);
     sym_free(flag);
+    s->htab = tab;
+    s->zref = zref;
+    s->tol = tol;
     c.sym = s;
     if (!ok) sym_release(c);
+}
+
+// ------------------------------------------------ gradient nonlinearity: records and launch
+// Line records (FP64): B_L (12, row-major [a][q]) and C_L = V_L B_L, then per
+// correction node B(c) - B_L and C(c) - C_L; any other node whose B or C
+// differs from the line's constant (to tol) flags the build as unusable.
+__global__ void k_kn_lines(const double* __restrict__ ba, const double* __restrict__ vol, long nlines,
+                           int nz, long nn, int zref, int nc, const int* __restrict__ czl,
+                           double tolb, double tolc, double* __restrict__ lrec, int* __restrict__ bad)
+{
+    constexpr int S = 4;
+    const long l = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (l >= nlines) return;
+    auto coef = [&](int z, double (&Bz)[12], double (&Cz)[12]) {
+        const long node = l + (long)z * nlines;
+        const double v = vol[node];
+        for (int al = 0; al < 3; ++al)
+            for (int q = 0; q < S; ++q) {
+                Bz[al * 4 + q] = ba[(long)(al * S + q) * nn + node];
+                Cz[al * 4 + q] = v * Bz[al * 4 + q];
+            }
+    };
+    double BL[12], CL[12], Bz[12], Cz[12];
+    coef(zref, BL, CL);
+    double* o = lrec + l * kKnLine;
+    for (int e = 0; e < 12; ++e) {
+        o[e] = BL[e];
+        o[12 + e] = CL[e];
+    }
+    int ci = 0;
+    for (int z = 0; z < nz; ++z) {
+        const bool corr = ci < nc && czl[ci] == z;
+        coef(z, Bz, Cz);
+        if (corr) {
+            for (int e = 0; e < 12; ++e) {
+                o[24 + 24 * ci + e] = Bz[e] - BL[e];
+                o[24 + 24 * ci + 12 + e] = Cz[e] - CL[e];
+            }
+            ++ci;
+        } else {
+            for (int e = 0; e < 12; ++e)
+                if (fabs(Bz[e] - BL[e]) > tolb || fabs(Cz[e] - CL[e]) > tolc) atomicOr(bad, 1);
+        }
+    }
+}
+
+// Pair records: the mean and half difference of the two lines' B_L and C_L,
+// the correction entries of both lines interleaved, the mismatch flag; pairs
+// equal to the reference pair share record 0, as for K's records.
+__global__ void k_kn_pairs(const double* __restrict__ lrec, long npairs, int nc, long pref, double tolb,
+                           double tolc, int* __restrict__ pidx, double* __restrict__ rec)
+{
+    const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const double* A = lrec + (2 * p) * kKnLine;
+    const double* B = A + kKnLine;
+    auto write = [&](double* o) {
+        bool mism = false;
+        for (int e = 0; e < 24; ++e) {
+            const double hd = 0.5 * (A[e] - B[e]);
+            const int k = e < 12 ? e : 12 + e;   // B mean/half at 0/12, C mean/half at 24/36
+            o[k] = 0.5 * (A[e] + B[e]);
+            o[k + 12] = hd;
+            mism = mism || fabs(hd) > (e < 12 ? tolb : tolc);
+        }
+        for (int ci = 0; ci < kSymC; ++ci)
+            for (int e = 0; e < 24; ++e) {
+                o[48 + kKnC * ci + 2 * e] = ci < nc ? A[24 + 24 * ci + e] : 0.0;
+                o[48 + kKnC * ci + 2 * e + 1] = ci < nc ? B[24 + 24 * ci + e] : 0.0;
+            }
+        for (int k = 48 + kKnC * kSymC; k < kKnRec; ++k) o[k] = 0.0;
+        o[kKnFlag] = mism ? 1.0 : 0.0;
+    };
+    bool same = pref >= 0;
+    if (same) {
+        const double* RA = lrec + (2 * pref) * kKnLine;
+        for (int k = 0; k < 24 + 24 * nc && same; ++k) {
+            const double tol = ((k < 24 ? k : k - 24) % 24) < 12 ? tolb : tolc;  // B or C entry
+            same = fabs(A[k] - RA[k]) <= tol && fabs(B[k] - RA[kKnLine + k]) <= tol;
+        }
+    }
+    write(rec + (size_t)(1 + p) * kKnRec);
+    if (p == pref) write(rec);
+    pidx[p] = same ? 0 : (int)(1 + p);
+}
+
+namespace {
+// builds the gradient records once (synchronous); false where they cannot be
+bool kn_build(const Ctx& c, hipStream_t st)
+{
+    SymState* s = (SymState*)c.sym;
+    if (s->kn != 0) return s->kn > 0;
+    s->kn = -1;
+    const SymTab& tab = s->htab;
+    const long nlines = (long)c.n[0] * c.n[1], npairs = nlines / 2;
+    double bscale = 0.0;
+    for (int e = 0; e < 12; ++e) bscale = std::max(bscale, fabs(c.nconst.b[e]));
+    if (!(bscale > 0.0) || !(c.nconst.v > 0.0)) return false;
+    const double tolb = 1e-11 * bscale, tolc = 1e-11 * bscale * c.nconst.v;
+    double* lrec = nullptr;
+    int* czl = nullptr;
+    int* flag = nullptr;
+    bool ok = sym_alloc(s->knpidx, npairs) && sym_alloc(s->knrec, (size_t)(npairs + 1) * kKnRec) &&
+              sym_alloc(lrec, (size_t)nlines * kKnLine) && sym_alloc(czl, kSymC) && sym_alloc(flag, 1);
+    if (ok) {
+        int hflag = 0;
+        (void)hipMemcpyAsync(czl, tab.cz, sizeof(int) * kSymC, hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(flag, &hflag, sizeof(int), hipMemcpyHostToDevice, st);
+        hipLaunchKernelGGL(k_kn_lines, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, c.ba_64,
+                           c.vol64, nlines, c.n[2], c.nn, s->zref, tab.nc, czl, tolb, tolc, lrec, flag);
+        const long pref = ((long)(c.n[0] / 2) + (long)c.n[0] * (c.n[1] / 2)) / 2;
+        hipLaunchKernelGGL(k_kn_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec, npairs,
+                           tab.nc, pref, tolb, tolc, s->knpidx, s->knrec);
+        (void)hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+        ok = hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess && hflag == 0;
+    }
+    (void)hipGetLastError();
+    sym_free(lrec);
+    sym_free(czl);
+    sym_free(flag);
+    if (!ok) {
+        sym_free(s->knpidx);
+        sym_free(s->knrec);
+        return false;
+    }
+    s->kn = 1;
+    return true;
+}
+
+template <class Lay>
+void run_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st)
+{
+    const SymState& s = *(const SymState*)c.sym;
+    const long nn = c.nn;
+    const long slot_rb = 2L * c.basis_plan.maxpairs * nn;
+    double* S1 = reinterpret_cast<double*>(c.work64);
+    double* S2 = S1 + slot_rb * c.cap_work;
+    const dim3 grid((unsigned)blocks_of<Lay>(c), 1u), block(kRT);
+    const RegProf prof{};
+    auto args = [&](int axis, const double* i, long irb, double* o, long orb) {
+        RArgsT<double> a{};
+        a.in = i;
+        a.in_rb = irb;
+        a.out = o;
+        a.out_rb = orb;
+        a.fstride = nn;
+        a.st = axis == 0 ? 1 : (axis == 1 ? (long)c.n[0] : (long)c.n[0] * c.n[1]);
+        a.tr = c.rtab64[axis];
+        a.tw = c.tw64[axis];
+        return a;
+    };
+    {
+        RArgsT<double> a = args(0, in, nn, S1, slot_rb);
+        a.mask_in = c.chi;
+        rlaunch(prof, 0, k_rpass<Lay, Lin3, 1, true, true, false, 1, 0, false, double>, grid, block, st, a);
+    }
+    {
+        RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
+        rlaunch(prof, 1, k_rpass<Lay, Lin3, 1, false, false, false, 1, 1, false, double>, grid, block, st, a);
+    }
+    KArgs<double> k{};
+    k.in = S2;
+    k.in_rb = slot_rb;
+    k.out = grad ? out : S1;
+    k.out_rb = grad ? nn : slot_rb;
+    k.fstride = nn;
+    k.st = (long)c.n[0] * c.n[1];
+    k.tr = c.rtab64[2];
+    k.tw = c.tw64[2];
+    k.pidx = s.knpidx;
+    k.rec = s.knrec;
+    k.tab = s.tab;
+    k.kappa = kappa;
+    if (grad) {
+        hipLaunchKernelGGL((k_smid_kn<Lay, double, true>), grid, block, 0, st, k);
+        return;
+    }
+    hipLaunchKernelGGL((k_smid_kn<Lay, double, false>), grid, block, 0, st, k);
+    {
+        RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
+        rlaunch(prof, 3, k_rpass<Lay, Lin3, 1, false, false, false, 2, 1, false, double>, grid, block, st, a);
+    }
+    {
+        RArgsT<double> a = args(0, S2, slot_rb, out, nn);
+        a.mask_out = c.chi;
+        rlaunch(prof, 4, k_rpass<Lay, Lin3, 1, true, false, true, 2, 0, false, double>, grid, block, st, a);
+    }
+}
+}  // namespace
+
+// the FP64 register path serves the gradient nonlinearity (records built on
+// first use)
+bool reg_kn_ok(const Ctx& c, hipStream_t st)
+{
+    return reg_path64_ok(c) && c.sym && kn_build(c, st);
+}
+
+// one field: the gradient force (grad = false) or the three components of
+// the implicit gradient B d (grad = true, out holds 3 fields)
+void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st)
+{
+    if (c.n[0] == 128) run_kn<G16L>(c, in, out, kappa, grad, st);
+    else if (c.n[0] == 32) run_kn<GPQ<4, 8>>(c, in, out, kappa, grad, st);
+    else if (c.n[0] == 48) run_kn<GPQ<6, 8>>(c, in, out, kappa, grad, st);
+    else run_kn<G8<8>>(c, in, out, kappa, grad, st);
 }
 
 }  // namespace fcrkpm

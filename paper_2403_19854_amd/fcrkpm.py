@@ -52,6 +52,7 @@ OPT_LINECONST = 8
 OPT_SEP_LINES32 = 9
 OPT_SEP_LINES64 = 10
 OPT_TUNE_CACHED = 11
+OPT_KN_REGPATH = 12
 
 
 class Grid(C.Structure):
