@@ -6,7 +6,9 @@
   finite differences with eps = 1e-6 on 20 seeded directions, to 1e-6 (see
   the test for how the perturbed solutions are formed), and the refined-FP32
   adjoint against the FP64 one. The FP64 CPU adjoint is compared at 20^3 in
-  test_gpu_parity.py; at 128^3 its CG would take hours on the host.
+  test_gpu_parity.py; at 128^3 its CG would take hours on the host;
+* config 5's problem on a 256^3 box: K in both precisions against the oracle
+  at sampled nodes and a refined solve checked by the oracle's residual.
 """
 import numpy as np
 import pytest
@@ -124,3 +126,43 @@ def test_config5_adjoint_against_finite_differences():
     e32 = np.linalg.norm((to_np(grad32) - grad)[m]) / np.linalg.norm(grad[m])
     print(f"  refined-FP32 adjoint ({info32['iters']} iterations) vs FP64: {e32:.2e}", flush=True)
     assert e32 <= 1e-8
+
+
+def test_256_box_products_and_refined_solve():
+    """Config 5's problem on a 256^3 box (working set above the last-level
+    cache; 256-point lines on the register path's 16 x 16 layout in FP32, the
+    LDS-tiled passes in FP64): K in both precisions against the oracle at
+    sampled nodes (Dirichlet faces included), FP32 against FP64 on the whole
+    field, and a refined solve whose solution the oracle's own operator
+    checks: ||chi_Omega (f^r - K d)|| / ||chi_Omega f^r|| on the free rows."""
+    p = W.config5_256()
+    print(f"\n[256^3] dims={p.dims}", flush=True)
+    g = lib_problem(p)
+    o = oracle.Oracle(p.dims, p.h, p.at, p.degree, p.chi, p.vol)
+    x = np.where(p.chi > 0, np.random.default_rng(256).standard_normal(p.shape), 0.0)
+    rng = np.random.default_rng(257)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(p.free.reshape(-1)), 48, replace=False),
+                                  rng.choice(np.flatnonzero(p.dirichlet.reshape(-1)), 16, replace=False)]))
+    xt = torch.from_numpy(x).to(DEV)
+    k64 = to_np(g.apply("K_FULL", xt))
+    k32 = to_np(g.apply("K_FULL", xt.float())).astype(np.float64)
+    ref = o.apply_k_at(x, idx)
+    scale = np.abs(ref).max()
+    e64 = np.abs(k64.reshape(-1)[idx] - ref).max() / scale
+    e32 = np.abs(k32.reshape(-1)[idx] - ref).max() / scale
+    e3264 = np.abs(k32 - k64).max() / np.abs(k64).max()
+    print(f"  K vs oracle at 64 nodes: FP64 {e64:.2e}, FP32 {e32:.2e}; FP32 vs FP64 field {e3264:.2e}",
+          flush=True)
+    assert e64 <= 1e-11 and e32 <= 2e-5 and e3264 <= 2e-5
+    r = torch.from_numpy(p.r).to(DEV)
+    d, uh, info = g.solve(r, mode="f32_refined", tol=1e-10, maxit=60000)
+    d = to_np(d)
+    f = p.free > 0
+    fr = np.where(f, o.apply_fr(p.r), 0.0)
+    res = np.linalg.norm(np.where(f, fr - o.apply_k(d), 0.0)) / np.linalg.norm(fr)
+    m = p.chi > 0
+    err = np.linalg.norm((to_np(uh) - p.u_exact)[m]) / np.linalg.norm(p.u_exact[m])
+    print(f"  refined solve: {info['iters']} iterations, own residual {info['true_rel_res']:.2e}, "
+          f"oracle residual {res:.2e}, u^h vs exact {err:.2e}", flush=True)
+    assert info["true_rel_res"] <= 1e-10 and res <= 2e-10
+    assert err <= 1e-3
