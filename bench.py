@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-cg-cap", type=int, default=10,
                     help="iterations of the oracle's CG solve and adjoint on boxes above 64^3")
+    ap.add_argument("--table1", action="store_true",
+                    help="the paper's timing table instead: setup, K (FP64 and FP32), f^r and u^h "
+                         "on the Eq 106 problem (support 1.5h) at boxes 8^3 .. 256^3")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run exactly N CG iterations per step instead of solving to --tol "
                          "(throughput of workloads whose CG converges too slowly, e.g. c3)")
@@ -82,6 +85,8 @@ def main():
     fcrkpm.load_library()
     if a.mode is None:
         a.mode = "f64" if a.workload in ("c1", "c2") else "f32_refined"
+    if a.table1:
+        return bench_table1(a)
     if a.workload == "c4":
         return bench_c4(a)
     wl = {"c5": W.config5, "c5_256": W.config5_256, "paper": W.paper_shape, "c3": W.config3,
@@ -542,6 +547,58 @@ def probe(a, wl):
     print(json.dumps({"probe": wl.name, "cg_iterations": info["iters"], "layout": layout,
                       "calibration_copy_bytes": 4 * src.numel()}), flush=True)
     pb.close()
+
+
+def bench_table1(a, sizes=(8, 16, 32, 64, 128, 256), reps=20):
+    """Per-operation times on the paper's timing problem (Eq 106 on [-1,1]^3,
+    support 1.5h, linear basis) at the box sizes of its timing table: setup
+    (moment convolutions, moment solves, the register path's records and the
+    autotuner, wall time of the call), and medians over `reps` launches (HIP
+    events) of K in FP64 and FP32, f^r and u^h in FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2403_19854_amd import fcrkpm
+    from paper_2403_19854_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    rows = []
+    for n in sizes:
+        wl = W.paper_shape(n)
+        chi = torch.from_numpy(wl.chi).to(dev)
+        dirm = torch.from_numpy(wl.dirichlet).to(dev)
+        vol = torch.from_numpy(wl.vol).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb = fcrkpm.Problem(wl.dims, wl.h, wl.at, wl.degree, chi, dirm, vol, device=dev)
+        torch.cuda.synchronize()
+        row = {"box": n, "omega_nodes": int(wl.chi.sum()), "setup_ms": 1e3 * (time.perf_counter() - t0)}
+        x = torch.from_numpy(np.where(wl.chi > 0, np.random.default_rng(0).standard_normal(wl.shape),
+                                      0.0)).to(dev)
+        for name, op, xt in (("k_f64", "K_FULL", x), ("k_f32", "K_FULL", x.float()),
+                             ("fr_f64", "FR", x), ("uh_f64", "UH", x)):
+            y = torch.empty_like(xt)
+            for _ in range(3):
+                pb.apply(op, xt, out=y, stream=st)
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                pb.apply(op, xt, out=y, stream=st)
+                e1.record(st)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            row[name + "_ms"] = float(np.median(ts))
+        pb.close()
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    out = {"metric": "per-operation time vs box size, Eq 106 problem, support 1.5h (the paper's timing table)",
+           "value": rows[-1]["k_f64_ms"], "unit": "ms (FP64 K at the largest box)", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "paper_eq106_table", "boxes": list(sizes), "reps": reps}, "rows": rows}
+    print(json.dumps(out), flush=True)
 
 
 def bench_c4(a):
