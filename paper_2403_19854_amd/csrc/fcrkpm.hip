@@ -164,6 +164,7 @@ void free_set(OpSet*& s)
         dfree(s->noff[l]);
         dfree(s->nrec[l]);
     }
+    sym_release_state(s->sym);
     delete s;
     s = nullptr;
 }
@@ -610,6 +611,7 @@ void swap_set(Ctx& c, OpSet& s)
     std::swap(c.nrec, s.nrec);
     std::swap(c.nload, s.nload);
     std::swap(c.nconst, s.nconst);
+    std::swap(c.sym, s.sym);
 }
 
 // The products of a scope use the set `s` (kernels take their arguments at
@@ -641,6 +643,8 @@ OpSet* make_set(Ctx& c, double ck, double cm, hipStream_t st, const double* wnod
         HIPCHK(hipGetLastError());
         SetScope use(c, s);
         build_pointwise(c, st);
+        // the line-constant middle pass, where this set's rows have the structure
+        sym_build(c, st);
         HIPCHK(hipStreamSynchronize(st));
     } catch (...) {
         free_set(s);

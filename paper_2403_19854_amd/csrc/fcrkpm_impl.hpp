@@ -82,6 +82,7 @@ struct OpSet {
     float* nrec[2] = {};
     long nload[2] = {-1, -1};
     NodeConst nconst = {};
+    void* sym = nullptr;                // line-constant records of this set's rows
 };
 
 struct Ctx {
@@ -248,6 +249,7 @@ bool reg_gpq_ok(const Ctx& c);
 void sym_build(Ctx& c, hipStream_t st);
 bool sym_active(const Ctx& c);
 void sym_release(Ctx& c);
+void sym_release_state(void*& sym);
 // algorithmic bytes of one launch of that middle pass per right-hand side
 double sym_pass_bytes(const Ctx& c, int elem_bytes);
 // The FP64 K product on the register path (linear basis, 32^3, 48^3, 64^3 or 128^3 boxes

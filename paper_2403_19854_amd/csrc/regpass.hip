@@ -1938,8 +1938,8 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
 // at every z, the line's M_L = M(zref), a check that M(z) = M_L off the
 // correction nodes (to tol of the product's interior scale), and the line
 // record M_L, then dM = M(c) - M_L at each correction node c.
-__global__ void k_sym_lines(const double* __restrict__ ba, const double* __restrict__ vol, long nlines,
-                            int nz, long nn, int zref, int nc, const int* __restrict__ czl,
+__global__ void k_sym_lines(const double* __restrict__ ba, int krows, const double* __restrict__ vol,
+                            long nlines, int nz, long nn, int zref, int nc, const int* __restrict__ czl,
                             double tol, double* __restrict__ lrec, int* __restrict__ bad)
 {
     constexpr int S = 4;
@@ -1951,7 +1951,7 @@ __global__ void k_sym_lines(const double* __restrict__ ba, const double* __restr
         for (int p = 0; p < S; ++p)
             for (int q = p; q < S; ++q) {
                 double acc = 0.0;
-                for (int al = 0; al < 3; ++al)
+                for (int al = 0; al < krows; ++al)
                     acc += ba[(long)(al * S + p) * nn + node] * ba[(long)(al * S + q) * nn + node];
                 Mz[sym_index(p, q)] = v * acc;
             }
@@ -2531,10 +2531,10 @@ void sym_free(T*& p)
 }
 }  // namespace
 
-void sym_release(Ctx& c)
+void sym_release_state(void*& p)
 {
-    if (!c.sym) return;
-    SymState* s = (SymState*)c.sym;
+    if (!p) return;
+    SymState* s = (SymState*)p;
     sym_free(s->tab);
     sym_free(s->pidx);
     sym_free(s->rec);
@@ -2542,10 +2542,13 @@ void sym_release(Ctx& c)
     sym_free(s->knpidx);
     sym_free(s->knrec);
     delete s;
-    c.sym = nullptr;
+    p = nullptr;
 }
 
-// the line-constant records exist for the coefficient rows in use (K's)
+void sym_release(Ctx& c) { sym_release_state(c.sym); }
+
+// the line-constant records exist for the coefficient rows in use (K's, or
+// those of an operator set swapped into the context)
 bool sym_ready(const Ctx& c)
 {
     return c.sym && c.use_sym && ((const SymState*)c.sym)->ba == c.ba_64 && c.degree == 1;
@@ -2574,7 +2577,7 @@ double sym_pass_bytes(const Ctx& c, int elem_bytes)
 void sym_build(Ctx& c, hipStream_t st)
 {
     sym_release(c);
-    if (!c.use_sym || c.degree != 1 || c.krows != c.dim || !(reg_path_ok(c) || reg_gpq_ok(c)) ||
+    if (!c.use_sym || c.degree != 1 || c.krows < 1 || !(reg_path_ok(c) || reg_gpq_ok(c)) ||
         c.nconst.bmax < 0.0)
         return;
     const int L = c.n[2], m = c.m[2];
@@ -2631,7 +2634,7 @@ void sym_build(Ctx& c, hipStream_t st)
     for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 4; ++q) {
             double acc = 0.0;
-            for (int al = 0; al < 3; ++al) acc += c.nconst.b[al * 4 + p] * c.nconst.b[al * 4 + q];
+            for (int al = 0; al < c.krows; ++al) acc += c.nconst.b[al * 4 + p] * c.nconst.b[al * 4 + q];
             mscale = std::max(mscale, fabs(c.nconst.v * acc));
         }
     if (!(mscale > 0.0)) return;
@@ -2650,7 +2653,7 @@ void sym_build(Ctx& c, hipStream_t st)
         (void)hipMemcpyAsync(s->tab, &tab, sizeof(SymTab), hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(czl, tab.cz, sizeof(int) * kSymC, hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(flag, hflag, sizeof(hflag), hipMemcpyHostToDevice, st);
-        hipLaunchKernelGGL(k_sym_lines, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, c.ba_64, c.vol64,
+        hipLaunchKernelGGL(k_sym_lines, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, c.ba_64, c.krows, c.vol64,
                            nlines, L, c.nn, zref, tab.nc, czl, tol, lrec, flag);
         const long pref = ((long)(c.n[0] / 2) + (long)c.n[0] * (c.n[1] / 2)) / 2;
         hipLaunchKernelGGL(k_sym_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec, npairs,
