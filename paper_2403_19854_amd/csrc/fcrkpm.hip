@@ -710,7 +710,7 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
                 }
                 if (op == OP_KN && use_reg_path64(c) && reg_kn_ok(c, st)) {
                     for (int j = 0; j < nrhs; ++j)
-                        launch_reg_kn(c, in + (size_t)j * c.nn, out + (size_t)j * c.nn, c.pw_kappa, false, st);
+                        launch_reg_kn(c, in + (size_t)j * c.nn, out + (size_t)j * c.nn, c.pw_kappa, RK_FORCE, st);
                     break;
                 }
             }
@@ -749,6 +749,15 @@ void apply_one(Ctx& c, int op, const Tio* in, Tio* out, int nrhs, hipStream_t st
             if constexpr (!std::is_same_v<T, Tio>) {
                 fail(FCRKPM_ERR_ARG, "mixed precisions are supported for K only");
             } else {
+                if constexpr (std::is_same_v<T, double>) {
+                    // u^h and f^r of one or more fields on the FP64 register path
+                    if ((op == FCRKPM_OP_UH || op == FCRKPM_OP_FR) && use_reg_path64(c) && reg_kn_ok(c, st)) {
+                        for (int j = 0; j < nrhs; ++j)
+                            launch_reg_kn(c, in + (size_t)j * c.nn, out + (size_t)j * c.nn, 0.0,
+                                          op == FCRKPM_OP_UH ? RK_UH : RK_LOAD, st);
+                        break;
+                    }
+                }
                 // f^q is the load pass of f^r with the boundary areas A in place
                 // of V (Eq A.5, Alg A.1)
                 if (op == FCRKPM_OP_FQ && !c.area64)
@@ -2007,6 +2016,9 @@ extern "C" fcrkpm_status fcrkpm_setup(const fcrkpm_grid* grid, const uint8_t* ma
         build_pointwise(c, st);
         if (const char* e = getenv("FCRKPM_SYM")) c.use_sym = *e != '0';
         sym_build(c, st);
+        // the FP64 register path's records of u^h, f^r and the gradient force,
+        // built here so that no later product allocates them
+        (void)reg_kn_ok(c, st);
 
         // workspace and solver buffers for one right-hand side; both grow on demand
         HIPCHK(hipStreamSynchronize(st));
@@ -2499,7 +2511,7 @@ namespace {
 void apply_grad(Ctx& c, const double* x, double* out, hipStream_t st)
 {
     if (use_reg_path64(c) && reg_kn_ok(c, st)) {
-        launch_reg_kn(c, x, out, 0.0, true, st);
+        launch_reg_kn(c, x, out, 0.0, RK_GRAD, st);
         return;
     }
     double* keep = c.b0_64;

@@ -257,12 +257,14 @@ double sym_pass_bytes(const Ctx& c, int elem_bytes);
 // applies; with dot_part the last pass also leaves the per-workgroup partials
 // of out . dot_with (reg_path64_blocks of them per right-hand side).
 bool reg_path64_ok(const Ctx& c);
-// The force of the gradient nonlinearity and the implicit gradient B d on the
-// FP64 register path (line-constant middle pass with the nonlinearity between
-// its halves); reg_kn_ok builds its records on first use and tells whether
-// the path serves this problem.  One field per launch.
+// The force of the gradient nonlinearity, the implicit gradient B d, u^h and the
+// load f^r on the FP64 register path (line-constant middle passes; the force
+// with the nonlinearity between its halves); reg_kn_ok builds their records on
+// first use and tells whether the path serves this problem.  One field per
+// launch.
+enum { RK_FORCE = 0, RK_GRAD = 1, RK_UH = 2, RK_LOAD = 3 };
 bool reg_kn_ok(const Ctx& c, hipStream_t st);
-void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st);
+void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, int mode, hipStream_t st);
 long reg_path64_blocks(const Ctx& c);
 void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
                     double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof);

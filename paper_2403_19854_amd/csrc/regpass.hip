@@ -1613,19 +1613,30 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
 }
 
 // ------------------------------------------------ gradient nonlinearity, line-constant
-// The force of N(g) = (1 + kappa |g|^2) g (Alg B.1) and the implicit gradient
-// B d on the register path.  Along a z line both halves of the pointwise stage
-// have constant coefficients away from the correction nodes: the gradient
-// A^a = sum_q b^a_q D_q (Eq 15-16) with the line's B_L, and E_p = V sum_a b^a_p
-// N^a with C_L = V_L B_L.  So the middle pass applies B_L to the part-1 z
-// spectra, transforms back, corrects A at the correction nodes with the taps,
-// applies N node by node, transforms N, applies C_L with the reflected part-2
-// spectra, and corrects the output at the window nodes -- 12 transforms per
-// line pair.  GRAD stops after A and stores its three components.
-constexpr int kKnC = 48;                            // record words per correction node
-constexpr int kKnRec = 48 + kKnC * kSymC + 4;       // words per pair record
-constexpr int kKnFlag = kKnRec - 1;
-constexpr int kKnLine = 24 + 24 * kSymC;            // FP64 words per line record
+// The force of N(g) = (1 + kappa |g|^2) g (Alg B.1), the implicit gradient B d,
+// u^h (Alg 3) and the load f^r (Alg 4) on the FP64 register path.  Along a z
+// line the pointwise stages of these products have constant coefficients away
+// from the correction nodes: the gradient A^a = sum_q b^a_q D_q (Eq 15-16)
+// with the line's rows B_L (b^a, or the single row b^0 for u^h), and E_p =
+// V sum_a b^a_p N^a with C_L = V_L B_L.  So the middle pass applies B_L to the
+// part-1 z spectra, transforms back, corrects A at the correction nodes with
+// the taps, applies N node by node, transforms N, applies C_L with the
+// reflected part-2 spectra, and corrects the output at the window nodes -- 12
+// transforms per line pair for the force.  GRAD stops after A and stores its
+// ROWS components (B d, or u^h with the row b^0); LOAD starts from a nodal
+// field in place of N (f^r with the row b^0: E_p = V b^0_p r).
+enum { KN_FORCE = 0, KN_GRAD = 1, KN_LOAD = 2 };
+
+// record geometry for ROWS coefficient rows of 4 entries
+template <int ROWS>
+struct KnRec {
+    static constexpr int NB = 4 * ROWS;                // entries of B_L, and of C_L
+    static constexpr int CORR = 4 * NB;                // per correction node: dB, dC of both lines
+    static constexpr int HEAD = 4 * NB;                // B mean, B half difference, C mean, C half
+    static constexpr int REC = HEAD + CORR * kSymC + 4;
+    static constexpr int FLAG = REC - 1;
+    static constexpr int LINE = 2 * NB + 2 * NB * kSymC;  // FP64 line record: B_L, C_L, per node dB, dC
+};
 
 template <typename T>
 struct KArgs {
@@ -1635,18 +1646,19 @@ struct KArgs {
     const T* tr;           // [2][L]: Re T_0 / L, Im T_1 / L of the axis
     const cplx<T>* tw;
     const int* pidx;       // per pair: its record
-    const T* rec;          // records: B mean (12), B half difference (12), C mean (12),
-                           // C half difference (12), per correction node 24 entries of dB
-                           // and dC for both lines interleaved, ..., flag
+    const T* rec;          // records (KnRec): B mean, B half difference, C mean, C half
+                           // difference, per correction node the entries of dB and dC for
+                           // both lines interleaved, ..., flag
     const SymTab* tab;
     T kappa;
+    const uint8_t* mask;   // GRAD: the output's mask (zero outside the domain)
 };
 
 // Y_a (+)= G_a(B) x_f for input column F of the gradient operator: A^a(k) =
 // (B_a0 a + i B_a3 b) X0 + B_a1 a X1 + B_a2 a X2 (B row-major [a][q])
-template <class Lay, class Sp, int F, bool SET, typename T>
-__device__ __forceinline__ void kn_grad_col(const cplx<T> (&W)[Lay::PTS], cplx<T> (&Y)[3][Lay::PTS], const T* Bm,
-                                            const Sp& sp)
+template <class Lay, class Sp, int F, bool SET, int ROWS, typename T>
+__device__ __forceinline__ void kn_grad_col(const cplx<T> (&W)[Lay::PTS], cplx<T> (&Y)[ROWS][Lay::PTS],
+                                            const T* Bm, const Sp& sp)
 {
     typedef cplx<T> cf;
 #pragma unroll
@@ -1654,12 +1666,12 @@ __device__ __forceinline__ void kn_grad_col(const cplx<T> (&W)[Lay::PTS], cplx<T
         const T a = sp.template e<Lay, 0>(i), b = sp.template e<Lay, 1>(i);
         const cf w = W[i];
 #pragma unroll
-        for (int al = 0; al < 3; ++al) {
+        for (int al = 0; al < ROWS; ++al) {
             cf c;
             if constexpr (F == 0) c = cf{Bm[al * 4 + 0] * a, Bm[al * 4 + 3] * b};
             else c = cf{Bm[al * 4 + F] * a, T(0)};
             Y[al][i] = SET ? cf{c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x}
-                            : cf{Y[al][i].x + c.x * w.x - c.y * w.y, Y[al][i].y + c.x * w.y + c.y * w.x};
+                           : cf{Y[al][i].x + c.x * w.x - c.y * w.y, Y[al][i].y + c.x * w.y + c.y * w.x};
         }
     }
 }
@@ -1693,14 +1705,17 @@ __device__ __forceinline__ int corr_of(const SymTab& tb, int z)
     return ci;
 }
 
-template <class Lay, typename T, bool GRAD>
+template <class Lay, typename T, int MODE, int ROWS>
 __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
 {
     typedef cplx<T> cf;
+    typedef KnRec<ROWS> KR;
     constexpr int L = Lay::L, R = Lay::PTS, SP = Lay::SPTS;
     constexpr bool STG = sizeof(T) == 4;
+    constexpr int NB = KR::NB;
     constexpr int CW = 3 * kSymW + 4 * kSymC + 3 * kSymC;  // window values (later output
                                                           // corrections), dE, dA (later N)
+    static_assert(MODE != KN_FORCE || ROWS == 3, "the force acts on the gradient");
     __shared__ cf tw[L];
     __shared__ T trl[Tables<Lay, Lin3::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
@@ -1717,20 +1732,21 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
     cf* xb = xbuf + g * Lay::XS;
     cf* cw = cbuf + g * CW;          // [3][kSymW] window values, then output corrections
     cf* ce = cw + 3 * kSymW;         // [4][kSymC] dE at the correction nodes
-    cf* ca = ce + 4 * kSymC;         // [3][kSymC] dA, then N, at the correction nodes
+    cf* ca = ce + 4 * kSymC;         // [ROWS][kSymC] dA, then N, at the correction nodes
     Tables<Lay, Lin3::NE, T> tabs;
     tabs.fetch(a);
     typename Lay::template Spec<Lin3::NE, T> sp;
     sp.template fetch<Lay>(a.tr, t);
 
+    constexpr int NIN = MODE == KN_LOAD ? 1 : 3;
     cf X[3][R];
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+    for (int f = 0; f < NIN; ++f)
 #pragma unroll
         for (int m = 0; m < SP; ++m)
             X[f][m] = load_pair<L, false>(in + f * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st));
     const long pair = tile * Lay::GROUPS + g;
-    const T* rec = a.rec + (size_t)a.pidx[pair] * kKnRec;
+    const T* rec = a.rec + (size_t)a.pidx[pair] * KR::REC;
     if (tid < (int)(sizeof(SymTab) / 4))
         reinterpret_cast<int*>(&tb)[tid] = reinterpret_cast<const int*>(a.tab)[tid];
     tabs.put(tw, trl);  // its barrier also publishes tb
@@ -1739,127 +1755,142 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
     lw.make(t, tw);
     if constexpr (STG) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+        for (int f = 0; f < NIN; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
     }
+    const bool mismatch = rec[KR::FLAG] != T(0);
+    // the gradient's (or u^h's) values, or the nodal input of the load
+    cf Y[ROWS][R];
+    if constexpr (MODE == KN_LOAD) {
 #pragma unroll
-    for (int m = 0; m < SP; ++m) {
-        const int wi = tb.widx[Lay::row(t, m)];
-        if (wi >= 0) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) cw[f * kSymW + wi] = X[f][m];
-        }
-    }
-    const bool mismatch = rec[kKnFlag] != T(0);
-    wave_sync();
-    // dA = (B - B_L) D at the correction nodes, D from the taps; each line of
-    // the pair with its own dB
-    for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
-        const int cz = tb.cz[ci];
-        cf D[4] = {};
-        for (int o = -tb.m; o <= tb.m; ++o) {
-            const int wi = tb.widx[(cz - o + L) % L];
-            const T t0 = tap0_of<T>(tb, o + tb.m), t1 = tap1_of<T>(tb, o + tb.m);
-            const cf x0 = cw[wi], x1 = cw[kSymW + wi], x2 = cw[2 * kSymW + wi];
-            D[0] = cf{D[0].x + t0 * x0.x, D[0].y + t0 * x0.y};
-            D[1] = cf{D[1].x + t0 * x1.x, D[1].y + t0 * x1.y};
-            D[2] = cf{D[2].x + t0 * x2.x, D[2].y + t0 * x2.y};
-            D[3] = cf{D[3].x + t1 * x0.x, D[3].y + t1 * x0.y};
-        }
-        const T* dm = rec + 48 + kKnC * ci;
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-            cf s = {};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = al * 4 + q;
-                s = cf{s.x + dm[2 * e] * D[q].x, s.y + dm[2 * e + 1] * D[q].y};
-            }
-            ca[al * kSymC + ci] = s;
-        }
-    }
-    // the gradient's constant part in the spectral domain
-#pragma unroll
-    for (int f = 0; f < 3; ++f) Lay::fwd(X[f], t, xb, lw);
-    cf Y[3][R];
-    {
-        T Bm[12];
-#pragma unroll
-        for (int e = 0; e < 12; ++e) Bm[e] = rec[e];
-        kn_grad_col<Lay, decltype(sp), 0, true>(X[0], Y, Bm, sp);
-        kn_grad_col<Lay, decltype(sp), 1, false>(X[1], Y, Bm, sp);
-        kn_grad_col<Lay, decltype(sp), 2, false>(X[2], Y, Bm, sp);
-    }
-    if (mismatch) {
-        // lines of different B_L: the half difference on conj X(-k)
-        T Bd[12];
-#pragma unroll
-        for (int e = 0; e < 12; ++e) Bd[e] = rec[12 + e];
-        cf W[R];
-        conj_neg<Lay>(X[0], W, t, xb);
-        kn_grad_col<Lay, decltype(sp), 0, false>(W, Y, Bd, sp);
-        conj_neg<Lay>(X[1], W, t, xb);
-        kn_grad_col<Lay, decltype(sp), 1, false>(W, Y, Bd, sp);
-        conj_neg<Lay>(X[2], W, t, xb);
-        kn_grad_col<Lay, decltype(sp), 2, false>(W, Y, Bd, sp);
-    }
-#pragma unroll
-    for (int al = 0; al < 3; ++al) Lay::inv(Y[al], t, xb, lw);
-    wave_sync();
-    // A at the correction nodes
-#pragma unroll
-    for (int m = 0; m < SP; ++m) {
-        const int z = Lay::row(t, m);
-        if (tb.widx[z] >= 0) {
-            const int ci = corr_of(tb, z);
-            if (ci >= 0) {
-#pragma unroll
-                for (int al = 0; al < 3; ++al) {
-                    const cf d = ca[al * kSymC + ci];
-                    Y[al][m] = cf{Y[al][m].x + d.x, Y[al][m].y + d.y};
-                }
-            }
-        }
-    }
-    if constexpr (GRAD) {
-#pragma unroll
-        for (int o = 0; o < 3; ++o) {
-            if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
-#pragma unroll
-            for (int m = 0; m < SP; ++m)
-                store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
-        }
-        return;
+        for (int m = 0; m < SP; ++m) Y[0][m] = X[0][m];
     } else {
-        // N(A) node by node, each real line on its own; N at the correction
-        // nodes kept for their dE
-        wave_sync();  // the dA reads above before the N writes below
 #pragma unroll
         for (int m = 0; m < SP; ++m) {
-            const T sx = T(1) + a.kappa * (Y[0][m].x * Y[0][m].x + Y[1][m].x * Y[1][m].x + Y[2][m].x * Y[2][m].x);
-            const T sy = T(1) + a.kappa * (Y[0][m].y * Y[0][m].y + Y[1][m].y * Y[1][m].y + Y[2][m].y * Y[2][m].y);
+            const int wi = tb.widx[Lay::row(t, m)];
+            if (wi >= 0) {
 #pragma unroll
-            for (int al = 0; al < 3; ++al) Y[al][m] = cf{sx * Y[al][m].x, sy * Y[al][m].y};
+                for (int f = 0; f < 3; ++f) cw[f * kSymW + wi] = X[f][m];
+            }
+        }
+        wave_sync();
+        // dA = (B - B_L) D at the correction nodes, D from the taps; each line of
+        // the pair with its own dB
+        for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
+            const int cz = tb.cz[ci];
+            cf D[4] = {};
+            for (int o = -tb.m; o <= tb.m; ++o) {
+                const int wi = tb.widx[(cz - o + L) % L];
+                const T t0 = tap0_of<T>(tb, o + tb.m), t1 = tap1_of<T>(tb, o + tb.m);
+                const cf x0 = cw[wi], x1 = cw[kSymW + wi], x2 = cw[2 * kSymW + wi];
+                D[0] = cf{D[0].x + t0 * x0.x, D[0].y + t0 * x0.y};
+                D[1] = cf{D[1].x + t0 * x1.x, D[1].y + t0 * x1.y};
+                D[2] = cf{D[2].x + t0 * x2.x, D[2].y + t0 * x2.y};
+                D[3] = cf{D[3].x + t1 * x0.x, D[3].y + t1 * x0.y};
+            }
+            const T* dm = rec + KR::HEAD + KR::CORR * ci;
+#pragma unroll
+            for (int al = 0; al < ROWS; ++al) {
+                cf s = {};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = al * 4 + q;
+                    s = cf{s.x + dm[2 * e] * D[q].x, s.y + dm[2 * e + 1] * D[q].y};
+                }
+                ca[al * kSymC + ci] = s;
+            }
+        }
+        // the constant part in the spectral domain
+#pragma unroll
+        for (int f = 0; f < 3; ++f) Lay::fwd(X[f], t, xb, lw);
+        {
+            T Bm[NB];
+#pragma unroll
+            for (int e = 0; e < NB; ++e) Bm[e] = rec[e];
+            kn_grad_col<Lay, decltype(sp), 0, true, ROWS>(X[0], Y, Bm, sp);
+            kn_grad_col<Lay, decltype(sp), 1, false, ROWS>(X[1], Y, Bm, sp);
+            kn_grad_col<Lay, decltype(sp), 2, false, ROWS>(X[2], Y, Bm, sp);
+        }
+        if (mismatch) {
+            // lines of different B_L: the half difference on conj X(-k)
+            T Bd[NB];
+#pragma unroll
+            for (int e = 0; e < NB; ++e) Bd[e] = rec[NB + e];
+            cf W[R];
+            conj_neg<Lay>(X[0], W, t, xb);
+            kn_grad_col<Lay, decltype(sp), 0, false, ROWS>(W, Y, Bd, sp);
+            conj_neg<Lay>(X[1], W, t, xb);
+            kn_grad_col<Lay, decltype(sp), 1, false, ROWS>(W, Y, Bd, sp);
+            conj_neg<Lay>(X[2], W, t, xb);
+            kn_grad_col<Lay, decltype(sp), 2, false, ROWS>(W, Y, Bd, sp);
+        }
+#pragma unroll
+        for (int al = 0; al < ROWS; ++al) Lay::inv(Y[al], t, xb, lw);
+        wave_sync();
+        // the values at the correction nodes
+#pragma unroll
+        for (int m = 0; m < SP; ++m) {
             const int z = Lay::row(t, m);
             if (tb.widx[z] >= 0) {
                 const int ci = corr_of(tb, z);
                 if (ci >= 0) {
 #pragma unroll
-                    for (int al = 0; al < 3; ++al) ca[al * kSymC + ci] = Y[al][m];
+                    for (int al = 0; al < ROWS; ++al) {
+                        const cf d = ca[al * kSymC + ci];
+                        Y[al][m] = cf{Y[al][m].x + d.x, Y[al][m].y + d.y};
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == KN_GRAD) {
+#pragma unroll
+        for (int o = 0; o < ROWS; ++o) {
+            if constexpr (STG) stage_move<Lay>(Y[o], stage[(NIN + o) & 1], g, t, gc, tc);
+#pragma unroll
+            for (int m = 0; m < SP; ++m) {
+                // the pair's lines are adjacent: elements idx and idx + 1
+                const long idx = elem_index<Lay, false>(base, gc, tc, m, a.st);
+                const cf v = Y[o][m];
+                store_pair<L, false>(out + o * a.fstride, idx,
+                                     cf{a.mask[idx] ? v.x : T(0), a.mask[idx + 1] ? v.y : T(0)});
+            }
+        }
+        return;
+    } else {
+        // N(A) node by node (each real line on its own), or the nodal input;
+        // its values at the correction nodes kept for their dE
+        wave_sync();  // the dA reads above before the writes below
+#pragma unroll
+        for (int m = 0; m < SP; ++m) {
+            if constexpr (MODE == KN_FORCE) {
+                const T sx = T(1) + a.kappa * (Y[0][m].x * Y[0][m].x + Y[1][m].x * Y[1][m].x +
+                                               Y[2][m].x * Y[2][m].x);
+                const T sy = T(1) + a.kappa * (Y[0][m].y * Y[0][m].y + Y[1][m].y * Y[1][m].y +
+                                               Y[2][m].y * Y[2][m].y);
+#pragma unroll
+                for (int al = 0; al < ROWS; ++al) Y[al][m] = cf{sx * Y[al][m].x, sy * Y[al][m].y};
+            }
+            const int z = Lay::row(t, m);
+            if (tb.widx[z] >= 0) {
+                const int ci = corr_of(tb, z);
+                if (ci >= 0) {
+#pragma unroll
+                    for (int al = 0; al < ROWS; ++al) ca[al * kSymC + ci] = Y[al][m];
                 }
             }
         }
         wave_sync();
         // dE = (C - C_L) N at the correction nodes
         for (int ci = t; ci < tb.nc; ci += Lay::LANES) {
-            const T* dm = rec + 48 + kKnC * ci + 24;
-            cf n[3];
+            const T* dm = rec + KR::HEAD + KR::CORR * ci + 2 * NB;
+            cf n[ROWS];
 #pragma unroll
-            for (int al = 0; al < 3; ++al) n[al] = ca[al * kSymC + ci];
+            for (int al = 0; al < ROWS; ++al) n[al] = ca[al * kSymC + ci];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 cf s = {};
 #pragma unroll
-                for (int al = 0; al < 3; ++al) {
+                for (int al = 0; al < ROWS; ++al) {
                     const int e = al * 4 + p;
                     s = cf{s.x + dm[2 * e] * n[al].x, s.y + dm[2 * e + 1] * n[al].y};
                 }
@@ -1868,25 +1899,25 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
         }
         // the divergence's constant part in the spectral domain
 #pragma unroll
-        for (int al = 0; al < 3; ++al) Lay::fwd(Y[al], t, xb, lw);
+        for (int al = 0; al < ROWS; ++al) Lay::fwd(Y[al], t, xb, lw);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int i = 0; i < R; ++i) X[f][i] = cf{};
         {
-            T Cm[12];
+            T Cm[NB];
 #pragma unroll
-            for (int e = 0; e < 12; ++e) Cm[e] = rec[24 + e];
+            for (int e = 0; e < NB; ++e) Cm[e] = rec[2 * NB + e];
 #pragma unroll
-            for (int al = 0; al < 3; ++al) kn_div_col<Lay>(al, Y[al], X, Cm, sp);
+            for (int al = 0; al < ROWS; ++al) kn_div_col<Lay>(al, Y[al], X, Cm, sp);
         }
         if (mismatch) {
-            T Cd[12];
+            T Cd[NB];
 #pragma unroll
-            for (int e = 0; e < 12; ++e) Cd[e] = rec[36 + e];
+            for (int e = 0; e < NB; ++e) Cd[e] = rec[3 * NB + e];
             cf W[R];
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
+            for (int al = 0; al < ROWS; ++al) {
                 conj_neg<Lay>(Y[al], W, t, xb);
                 kn_div_col<Lay>(al, W, X, Cd, sp);
             }
@@ -1926,7 +1957,7 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
         }
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
-            if constexpr (STG) stage_move<Lay>(X[o], stage[(3 + o) & 1], g, t, gc, tc);
+            if constexpr (STG) stage_move<Lay>(X[o], stage[(NIN + o) & 1], g, t, gc, tc);
 #pragma unroll
             for (int m = 0; m < SP; ++m)
                 store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), X[o][m]);
@@ -2030,6 +2061,8 @@ struct SymState {
     int kn = 0;                  // 0 not tried, 1 built, -1 unavailable
     int* knpidx = nullptr;
     double* knrec = nullptr;
+    int* b0pidx = nullptr;       // the same for the single row b^0 (u^h, f^r)
+    double* b0rec = nullptr;
 };
 
 // cubic B-spline of Eq 7 at z = |x| / a
@@ -2541,6 +2574,8 @@ void sym_release_state(void*& p)
     sym_free(s->rec64);
     sym_free(s->knpidx);
     sym_free(s->knrec);
+    sym_free(s->b0pidx);
+    sym_free(s->b0rec);
     delete s;
     p = nullptr;
 }
@@ -2673,45 +2708,47 @@ void sym_build(Ctx& c, hipStream_t st)
     if (!ok) sym_release(c);
 }
 
-// ------------------------------------------------ gradient nonlinearity: records and launch
-// Line records (FP64): B_L (12, row-major [a][q]) and C_L = V_L B_L, then per
-// correction node B(c) - B_L and C(c) - C_L; any other node whose B or C
-// differs from the line's constant (to tol) flags the build as unusable.
-__global__ void k_kn_lines(const double* __restrict__ ba, const double* __restrict__ vol, long nlines,
+// ------------------------------------------------ gradient nonlinearity, u^h, f^r: records and launch
+// Line records (FP64) for ROWS coefficient rows: B_L (row-major [a][q]) and
+// C_L = V_L B_L, then per correction node B(c) - B_L and C(c) - C_L; any other
+// node whose B or C differs from the line's constant (to tol) flags the build
+// as unusable.  rows: ROWS x 4 fields nn apart (b^a, or b^0).
+template <int ROWS>
+__global__ void k_kn_lines(const double* __restrict__ rows, const double* __restrict__ vol, long nlines,
                            int nz, long nn, int zref, int nc, const int* __restrict__ czl,
                            double tolb, double tolc, double* __restrict__ lrec, int* __restrict__ bad)
 {
-    constexpr int S = 4;
+    typedef KnRec<ROWS> KR;
+    constexpr int NB = KR::NB;
     const long l = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (l >= nlines) return;
-    auto coef = [&](int z, double (&Bz)[12], double (&Cz)[12]) {
+    auto coef = [&](int z, double (&Bz)[NB], double (&Cz)[NB]) {
         const long node = l + (long)z * nlines;
         const double v = vol[node];
-        for (int al = 0; al < 3; ++al)
-            for (int q = 0; q < S; ++q) {
-                Bz[al * 4 + q] = ba[(long)(al * S + q) * nn + node];
-                Cz[al * 4 + q] = v * Bz[al * 4 + q];
-            }
+        for (int e = 0; e < NB; ++e) {
+            Bz[e] = rows[(long)e * nn + node];
+            Cz[e] = v * Bz[e];
+        }
     };
-    double BL[12], CL[12], Bz[12], Cz[12];
+    double BL[NB], CL[NB], Bz[NB], Cz[NB];
     coef(zref, BL, CL);
-    double* o = lrec + l * kKnLine;
-    for (int e = 0; e < 12; ++e) {
+    double* o = lrec + l * KR::LINE;
+    for (int e = 0; e < NB; ++e) {
         o[e] = BL[e];
-        o[12 + e] = CL[e];
+        o[NB + e] = CL[e];
     }
     int ci = 0;
     for (int z = 0; z < nz; ++z) {
         const bool corr = ci < nc && czl[ci] == z;
         coef(z, Bz, Cz);
         if (corr) {
-            for (int e = 0; e < 12; ++e) {
-                o[24 + 24 * ci + e] = Bz[e] - BL[e];
-                o[24 + 24 * ci + 12 + e] = Cz[e] - CL[e];
+            for (int e = 0; e < NB; ++e) {
+                o[2 * NB + 2 * NB * ci + e] = Bz[e] - BL[e];
+                o[2 * NB + 2 * NB * ci + NB + e] = Cz[e] - CL[e];
             }
             ++ci;
         } else {
-            for (int e = 0; e < 12; ++e)
+            for (int e = 0; e < NB; ++e)
                 if (fabs(Bz[e] - BL[e]) > tolb || fabs(Cz[e] - CL[e]) > tolc) atomicOr(bad, 1);
         }
     }
@@ -2720,70 +2757,72 @@ __global__ void k_kn_lines(const double* __restrict__ ba, const double* __restri
 // Pair records: the mean and half difference of the two lines' B_L and C_L,
 // the correction entries of both lines interleaved, the mismatch flag; pairs
 // equal to the reference pair share record 0, as for K's records.
+template <int ROWS>
 __global__ void k_kn_pairs(const double* __restrict__ lrec, long npairs, int nc, long pref, double tolb,
                            double tolc, int* __restrict__ pidx, double* __restrict__ rec)
 {
+    typedef KnRec<ROWS> KR;
+    constexpr int NB = KR::NB;
     const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (p >= npairs) return;
-    const double* A = lrec + (2 * p) * kKnLine;
-    const double* B = A + kKnLine;
+    const double* A = lrec + (2 * p) * KR::LINE;
+    const double* B = A + KR::LINE;
+    // B or C entry of a line record word
+    auto tol_of = [&](int k) { return ((k < 2 * NB ? k : k - 2 * NB) % (2 * NB)) < NB ? tolb : tolc; };
     auto write = [&](double* o) {
         bool mism = false;
-        for (int e = 0; e < 24; ++e) {
+        for (int e = 0; e < 2 * NB; ++e) {
             const double hd = 0.5 * (A[e] - B[e]);
-            const int k = e < 12 ? e : 12 + e;   // B mean/half at 0/12, C mean/half at 24/36
+            const int k = e < NB ? e : NB + e;   // B mean/half at 0/NB, C mean/half at 2NB/3NB
             o[k] = 0.5 * (A[e] + B[e]);
-            o[k + 12] = hd;
-            mism = mism || fabs(hd) > (e < 12 ? tolb : tolc);
+            o[k + NB] = hd;
+            mism = mism || fabs(hd) > tol_of(e);
         }
         for (int ci = 0; ci < kSymC; ++ci)
-            for (int e = 0; e < 24; ++e) {
-                o[48 + kKnC * ci + 2 * e] = ci < nc ? A[24 + 24 * ci + e] : 0.0;
-                o[48 + kKnC * ci + 2 * e + 1] = ci < nc ? B[24 + 24 * ci + e] : 0.0;
+            for (int e = 0; e < 2 * NB; ++e) {
+                o[KR::HEAD + KR::CORR * ci + 2 * e] = ci < nc ? A[2 * NB + 2 * NB * ci + e] : 0.0;
+                o[KR::HEAD + KR::CORR * ci + 2 * e + 1] = ci < nc ? B[2 * NB + 2 * NB * ci + e] : 0.0;
             }
-        for (int k = 48 + kKnC * kSymC; k < kKnRec; ++k) o[k] = 0.0;
-        o[kKnFlag] = mism ? 1.0 : 0.0;
+        for (int k = KR::HEAD + KR::CORR * kSymC; k < KR::REC; ++k) o[k] = 0.0;
+        o[KR::FLAG] = mism ? 1.0 : 0.0;
     };
     bool same = pref >= 0;
     if (same) {
-        const double* RA = lrec + (2 * pref) * kKnLine;
-        for (int k = 0; k < 24 + 24 * nc && same; ++k) {
-            const double tol = ((k < 24 ? k : k - 24) % 24) < 12 ? tolb : tolc;  // B or C entry
-            same = fabs(A[k] - RA[k]) <= tol && fabs(B[k] - RA[kKnLine + k]) <= tol;
-        }
+        const double* RA = lrec + (2 * pref) * KR::LINE;
+        for (int k = 0; k < 2 * NB + 2 * NB * nc && same; ++k)
+            same = fabs(A[k] - RA[k]) <= tol_of(k) && fabs(B[k] - RA[KR::LINE + k]) <= tol_of(k);
     }
-    write(rec + (size_t)(1 + p) * kKnRec);
+    write(rec + (size_t)(1 + p) * KR::REC);
     if (p == pref) write(rec);
     pidx[p] = same ? 0 : (int)(1 + p);
 }
 
 namespace {
-// builds the gradient records once (synchronous); false where they cannot be
-bool kn_build(const Ctx& c, hipStream_t st)
+// builds one record set (synchronous); false where it cannot be
+template <int ROWS>
+bool kn_records(const Ctx& c, const double* rows, double bscale, double vscale, int*& pidx, double*& recs,
+                hipStream_t st)
 {
-    SymState* s = (SymState*)c.sym;
-    if (s->kn != 0) return s->kn > 0;
-    s->kn = -1;
-    const SymTab& tab = s->htab;
+    typedef KnRec<ROWS> KR;
+    const SymState& s = *(const SymState*)c.sym;
+    const SymTab& tab = s.htab;
     const long nlines = (long)c.n[0] * c.n[1], npairs = nlines / 2;
-    double bscale = 0.0;
-    for (int e = 0; e < 12; ++e) bscale = std::max(bscale, fabs(c.nconst.b[e]));
-    if (!(bscale > 0.0) || !(c.nconst.v > 0.0)) return false;
-    const double tolb = 1e-11 * bscale, tolc = 1e-11 * bscale * c.nconst.v;
+    if (!(bscale > 0.0) || !(vscale > 0.0)) return false;
+    const double tolb = 1e-11 * bscale, tolc = 1e-11 * bscale * vscale;
     double* lrec = nullptr;
     int* czl = nullptr;
     int* flag = nullptr;
-    bool ok = sym_alloc(s->knpidx, npairs) && sym_alloc(s->knrec, (size_t)(npairs + 1) * kKnRec) &&
-              sym_alloc(lrec, (size_t)nlines * kKnLine) && sym_alloc(czl, kSymC) && sym_alloc(flag, 1);
+    bool ok = sym_alloc(pidx, npairs) && sym_alloc(recs, (size_t)(npairs + 1) * KR::REC) &&
+              sym_alloc(lrec, (size_t)nlines * KR::LINE) && sym_alloc(czl, kSymC) && sym_alloc(flag, 1);
     if (ok) {
         int hflag = 0;
         (void)hipMemcpyAsync(czl, tab.cz, sizeof(int) * kSymC, hipMemcpyHostToDevice, st);
         (void)hipMemcpyAsync(flag, &hflag, sizeof(int), hipMemcpyHostToDevice, st);
-        hipLaunchKernelGGL(k_kn_lines, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, c.ba_64,
-                           c.vol64, nlines, c.n[2], c.nn, s->zref, tab.nc, czl, tolb, tolc, lrec, flag);
+        hipLaunchKernelGGL((k_kn_lines<ROWS>), dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, rows,
+                           c.vol64, nlines, c.n[2], c.nn, s.zref, tab.nc, czl, tolb, tolc, lrec, flag);
         const long pref = ((long)(c.n[0] / 2) + (long)c.n[0] * (c.n[1] / 2)) / 2;
-        hipLaunchKernelGGL(k_kn_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec, npairs,
-                           tab.nc, pref, tolb, tolc, s->knpidx, s->knrec);
+        hipLaunchKernelGGL((k_kn_pairs<ROWS>), dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, lrec,
+                           npairs, tab.nc, pref, tolb, tolc, pidx, recs);
         (void)hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st);
         ok = hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess && hflag == 0;
     }
@@ -2792,6 +2831,33 @@ bool kn_build(const Ctx& c, hipStream_t st)
     sym_free(czl);
     sym_free(flag);
     if (!ok) {
+        sym_free(pidx);
+        sym_free(recs);
+    }
+    return ok;
+}
+
+// the gradient's records (rows b^a) and those of b^0, built once
+bool kn_build(const Ctx& c, hipStream_t st)
+{
+    SymState* s = (SymState*)c.sym;
+    if (s->kn != 0) return s->kn > 0;
+    s->kn = -1;
+    double bscale = 0.0;
+    for (int e = 0; e < 12; ++e) bscale = std::max(bscale, fabs(c.nconst.b[e]));
+    if (!kn_records<3>(c, c.ba_64, bscale, c.nconst.v, s->knpidx, s->knrec, st)) return false;
+    // b^0 at the box centre gives its scale (interior node of a cube-like domain)
+    const long centre = (long)(c.n[0] / 2) + (long)c.n[0] * ((c.n[1] / 2) + (long)c.n[1] * (c.n[2] / 2));
+    double b0c[4] = {0, 0, 0, 0};
+    for (int q = 0; q < 4; ++q)
+        if (hipMemcpy(&b0c[q], c.b0_64 + (size_t)q * c.nn + centre, sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+    double b0scale = 0.0;
+    for (int q = 0; q < 4; ++q) b0scale = std::max(b0scale, fabs(b0c[q]));
+    if (!kn_records<1>(c, c.b0_64, b0scale, c.nconst.v, s->b0pidx, s->b0rec, st)) {
         sym_free(s->knpidx);
         sym_free(s->knrec);
         return false;
@@ -2801,7 +2867,7 @@ bool kn_build(const Ctx& c, hipStream_t st)
 }
 
 template <class Lay>
-void run_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st)
+void run_kn(const Ctx& c, const double* in, double* out, double kappa, int mode, hipStream_t st)
 {
     const SymState& s = *(const SymState*)c.sym;
     const long nn = c.nn;
@@ -2822,33 +2888,38 @@ void run_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad
         a.tw = c.tw64[axis];
         return a;
     };
-    {
-        RArgsT<double> a = args(0, in, nn, S1, slot_rb);
-        a.mask_in = c.chi;
-        rlaunch(prof, 0, k_rpass<Lay, Lin3, 1, true, true, false, 1, 0, false, double>, grid, block, st, a);
-    }
-    {
+    const bool part1 = mode != RK_LOAD, part2 = mode == RK_FORCE || mode == RK_LOAD;
+    if (part1) {
+        {
+            RArgsT<double> a = args(0, in, nn, S1, slot_rb);
+            a.mask_in = c.chi;
+            rlaunch(prof, 0, k_rpass<Lay, Lin3, 1, true, true, false, 1, 0, false, double>, grid, block, st, a);
+        }
         RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
         rlaunch(prof, 1, k_rpass<Lay, Lin3, 1, false, false, false, 1, 1, false, double>, grid, block, st, a);
     }
     KArgs<double> k{};
-    k.in = S2;
-    k.in_rb = slot_rb;
-    k.out = grad ? out : S1;
-    k.out_rb = grad ? nn : slot_rb;
+    k.in = part1 ? S2 : in;
+    k.in_rb = part1 ? slot_rb : nn;
+    k.out = part2 ? S1 : out;
+    k.out_rb = part2 ? slot_rb : nn;
     k.fstride = nn;
     k.st = (long)c.n[0] * c.n[1];
     k.tr = c.rtab64[2];
     k.tw = c.tw64[2];
-    k.pidx = s.knpidx;
-    k.rec = s.knrec;
     k.tab = s.tab;
     k.kappa = kappa;
-    if (grad) {
-        hipLaunchKernelGGL((k_smid_kn<Lay, double, true>), grid, block, 0, st, k);
-        return;
+    k.mask = c.chi;
+    const bool b0 = mode == RK_UH || mode == RK_LOAD;
+    k.pidx = b0 ? s.b0pidx : s.knpidx;
+    k.rec = b0 ? s.b0rec : s.knrec;
+    switch (mode) {
+        case RK_FORCE: hipLaunchKernelGGL((k_smid_kn<Lay, double, KN_FORCE, 3>), grid, block, 0, st, k); break;
+        case RK_GRAD: hipLaunchKernelGGL((k_smid_kn<Lay, double, KN_GRAD, 3>), grid, block, 0, st, k); break;
+        case RK_UH: hipLaunchKernelGGL((k_smid_kn<Lay, double, KN_GRAD, 1>), grid, block, 0, st, k); break;
+        default: hipLaunchKernelGGL((k_smid_kn<Lay, double, KN_LOAD, 1>), grid, block, 0, st, k); break;
     }
-    hipLaunchKernelGGL((k_smid_kn<Lay, double, false>), grid, block, 0, st, k);
+    if (!part2) return;
     {
         RArgsT<double> a = args(1, S1, slot_rb, S2, slot_rb);
         rlaunch(prof, 3, k_rpass<Lay, Lin3, 1, false, false, false, 2, 1, false, double>, grid, block, st, a);
@@ -2861,21 +2932,25 @@ void run_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad
 }
 }  // namespace
 
-// the FP64 register path serves the gradient nonlinearity (records built on
-// first use)
+// the FP64 register path serves the gradient nonlinearity, u^h and f^r
+// (records built on first use)
 bool reg_kn_ok(const Ctx& c, hipStream_t st)
 {
-    return reg_path64_ok(c) && c.sym && kn_build(c, st);
+    // K's own rows (every operator set has dim + 1 rows or one); setup builds
+    // the records, so a product under graph capture never does
+    if (c.krows != c.dim || !reg_path64_ok(c) || !c.sym) return false;
+    if (((const SymState*)c.sym)->kn == 0 && c.capturing) return false;
+    return kn_build(c, st);
 }
 
-// one field: the gradient force (grad = false) or the three components of
-// the implicit gradient B d (grad = true, out holds 3 fields)
-void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, bool grad, hipStream_t st)
+// one field: the gradient force, the three components of the implicit
+// gradient B d (out holds 3 fields), u^h, or the load f^r (mode RK_*)
+void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, int mode, hipStream_t st)
 {
-    if (c.n[0] == 128) run_kn<G16L>(c, in, out, kappa, grad, st);
-    else if (c.n[0] == 32) run_kn<GPQ<4, 8>>(c, in, out, kappa, grad, st);
-    else if (c.n[0] == 48) run_kn<GPQ<6, 8>>(c, in, out, kappa, grad, st);
-    else run_kn<G8<8>>(c, in, out, kappa, grad, st);
+    if (c.n[0] == 128) run_kn<G16L>(c, in, out, kappa, mode, st);
+    else if (c.n[0] == 32) run_kn<GPQ<4, 8>>(c, in, out, kappa, mode, st);
+    else if (c.n[0] == 48) run_kn<GPQ<6, 8>>(c, in, out, kappa, mode, st);
+    else run_kn<G8<8>>(c, in, out, kappa, mode, st);
 }
 
 }  // namespace fcrkpm

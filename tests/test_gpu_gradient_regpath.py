@@ -1,4 +1,4 @@
-"""The gradient nonlinearity on the FP64 register path: the force
+"""The gradient nonlinearity, u^h and the load f^r on the FP64 register path: the force
 B^T (V o N(B d)) with N(g) = (1 + kappa |g|^2) g (App. B, Eq B.5-B.8, B.10;
 Alg B.1), whose middle pass applies each z line's constant gradient
 coefficients B_L and divergence coefficients V_L B_L in the spectral domain,
@@ -7,7 +7,8 @@ with the kernel's taps.  Checked against the LDS-tiled FP64 pass (register
 path off), against the oracle's force on the whole field, at kappa = 0 against
 K d, on cubes of 32, 48, 64 and 128 points, supports 1.5h-2.5h, and on box
 domains whose x and y extents end at other positions (line pairs whose two
-lines have different constants)."""
+lines have different constants).  u^h and f^r run the same machinery with the
+single row b^0 and are checked the same way."""
 import numpy as np
 import pytest
 
@@ -107,4 +108,36 @@ def test_gradient_force_register_path_batched_fields():
     for j in range(2):
         one = to_np(g.gradient_force(dt[j].contiguous(), kappa))
         np.testing.assert_array_equal(both[j], one)
+    g.close()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_uh_and_load_register_path(name):
+    """u^h = N d (Alg 3) and the load f^r = N^T (V r) (Alg 4) in FP64 on the
+    register path (the same middle-pass machinery with the single row b^0)
+    against the LDS-tiled FP64 passes and the oracle."""
+    f = fc()
+    p = CASES[name]()
+    print(f"\n[u^h and f^r, register path] {name} dims={p.dims}", flush=True)
+    g = f.Problem.from_workload(p, device=DEV)
+    assert g.get_option(f.OPT_KN_REGPATH) == 1
+    rng = np.random.default_rng(73)
+    d = np.where(p.chi > 0, rng.standard_normal(p.shape), 0.0)
+    r = rng.standard_normal(p.shape)          # the load masks r itself
+    dt, rt = torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)
+    uh, fr = to_np(g.apply("UH", dt)), to_np(g.apply("FR", rt))
+    g.set_regpath(False)
+    uh_l, fr_l = to_np(g.apply("UH", dt)), to_np(g.apply("FR", rt))
+    g.set_regpath(True)
+    e_uh = np.abs(uh - uh_l).max() / np.abs(uh_l).max()
+    e_fr = np.abs(fr - fr_l).max() / np.abs(fr_l).max()
+    print(f"  vs LDS-tiled passes: u^h {e_uh:.2e}, f^r {e_fr:.2e}", flush=True)
+    assert e_uh <= 1e-12 and e_fr <= 1e-12
+    if np.prod(p.dims) <= 64 ** 3:
+        o = oracle.Oracle(p.dims, p.h, p.at, p.degree, p.chi, p.vol)
+        ru, rf = o.apply_uh(d), o.apply_fr(r)
+        e_ou = np.abs(uh - ru).max() / np.abs(ru).max()
+        e_of = np.abs(fr - rf).max() / np.abs(rf).max()
+        print(f"  vs oracle: u^h {e_ou:.2e}, f^r {e_of:.2e}", flush=True)
+        assert e_ou <= 1e-11 and e_of <= 1e-11
     g.close()
