@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--maxit", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the short runs of the other configurations in the default c5 line")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-cg-cap", type=int, default=10,
                     help="iterations of the oracle's CG solve and adjoint on boxes above 64^3")
@@ -204,6 +206,8 @@ def main():
             out["flux"] = flux_time(a, wl, dev)
             out["nonlinear"] = nonlinear_time(a, wl, chi, dirm, vol, dev)
             out["nonlinear_cg"] = nonlinear_cg_time(a, wl, chi, dirm, vol, dev)
+            if not a.no_other_configs:
+                out["other_configs"] = other_configs(a, dev)
 
     if not a.no_cpu_baseline:
         gpu_iters = out.get("fp64_path", {}).get("iters")
@@ -601,15 +605,68 @@ def bench_table1(a, sizes=(8, 16, 32, 64, 128, 256), reps=20):
     print(json.dumps(out), flush=True)
 
 
-def bench_c4(a):
-    """Ragged batch: aggregate node-rhs matvecs/s of one batched solve."""
+def other_configs(a, dev):
+    """Short runs of the other configurations beside the c5 line (each from its
+    own setup, times of the solve calls): config 1 and 2 (FP64 CG to the bench
+    tolerance), the paper's Eq 106 problem at 128^3 (refined), config 3 (500
+    refined CG iterations, with the oracle's residual of the iterate), the
+    config-4 batch (one step of 240 iterations, graphs) and config 5's problem
+    on a 256^3 box (refined, to 1e-10)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2403_19854_amd import fcrkpm
+    from paper_2403_19854_amd import workloads as W
+
+    res = {}
+
+    def solve(wl, mode, tol, maxit, fixed=False):
+        pb = fcrkpm.Problem.from_workload(wl, device=dev)
+        r = torch.from_numpy(wl.r).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, uh, info = pb.solve(r, mode=mode, tol=1e-300 if fixed else tol, maxit=maxit,
+                               raise_on_noconv=not fixed)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        pb.close()
+        mv = info["matvecs_f32"] + info["matvecs_f64"]
+        e = {"mode": mode, "solve_ms": 1e3 * ts, "iters": info["iters"], "matvecs_per_s": mv / ts,
+             "true_rel_res": info["true_rel_res"]}
+        if wl.u_exact is not None:
+            m = wl.chi > 0
+            e["uh_rel_l2_vs_exact"] = float(np.linalg.norm((uh.cpu().numpy() - wl.u_exact)[m]) /
+                                            np.linalg.norm(wl.u_exact[m]))
+        return e, d
+
+    for name, wl, mode, tol in (("c1", W.config1(), "f64", a.tol), ("c2", W.config2(), "f64", a.tol),
+                                ("paper_eq106_128", W.paper_shape(128), "f32_refined", a.tol)):
+        res[name], _ = solve(wl, mode, tol, a.maxit)
+    wl = W.config3()
+    e, d = solve(wl, "f32_refined", a.tol, 500, fixed=True)
+    o = oracle.Oracle(wl.dims, wl.h, wl.at, wl.degree, wl.chi, wl.vol)
+    fr = np.where(wl.free > 0, o.apply_fr(wl.r), 0.0)
+    e["oracle_rel_res"] = float(np.linalg.norm(np.where(wl.free > 0, fr - o.apply_k(d.cpu().numpy()), 0.0)) /
+                                np.linalg.norm(fr))
+    res["c3_500_iterations"] = e
+    del o
+    c4 = run_c4(a, dev, steps=1, warmup=1, direct=False)
+    res["c4"] = {"node_matvecs_per_s": c4["value"], "ms_per_step": c4["ms_per_step"],
+                 "cg_iterations": a.c4_iters}
+    res["c5_256"], _ = solve(W.config5_256(), "f32_refined", 1e-10, a.maxit)
+    return res
+
+
+def run_c4(a, dev, steps, warmup, direct=True):
+    """The config-4 batch: node-rhs K products/s with graphs (and with direct
+    launches), and the ms per batched step."""
     import numpy as np
     import torch
 
     from paper_2403_19854_amd import fcrkpm
     from paper_2403_19854_amd import workloads as W
 
-    dev = torch.device("cuda:0")
     probs = W.config4() + [W.config4_rhs_problem()]
     rs = [torch.from_numpy(p.r[None]).to(dev) for p in probs[:-1]]
     rs.append(torch.from_numpy(np.stack(W.config4_rhs(probs[-1]))).to(dev))
@@ -632,10 +689,27 @@ def bench_c4(a):
         torch.cuda.synchronize()
         return node_mv / (time.perf_counter() - t0), (time.perf_counter() - t0) / steps
 
-    if a.warmup > 0:
-        run(True, a.warmup)
-    v_graph, t_graph = run(True, a.steps)
-    v_direct, t_direct = run(False, a.steps)
+    if warmup > 0:
+        run(True, warmup)
+    v_graph, t_graph = run(True, steps)
+    res = {"value": v_graph, "ms_per_step": 1e3 * t_graph, "problems": len(probs),
+           "boxes": [p.dims[0] for p in probs], "rhs": nrhs,
+           "box_nodes_total": int(sum(np.prod(p.dims) * k for p, k in zip(probs, nrhs)))}
+    if direct:
+        v_direct, t_direct = run(False, steps)
+        res["direct"] = (v_direct, t_direct)
+    for g in libs:
+        g.close()
+    return res
+
+
+def bench_c4(a):
+    """Ragged batch: aggregate node-rhs matvecs/s of one batched solve."""
+    import torch
+
+    c = run_c4(a, torch.device("cuda:0"), a.steps, a.warmup)
+    v_graph, t_graph = c["value"], c["ms_per_step"] / 1e3
+    v_direct, t_direct = c["direct"]
     out = {
         "metric": "node-rhs K products/s of a ragged batched CG solve (C4)",
         "value": v_graph,
@@ -649,9 +723,8 @@ def bench_c4(a):
         "vs_baseline": None,
         "dtype": "f32+f64" if a.mode == "f32_refined" else "f64",
         "data": "synthetic",
-        "config": {"workload": "c4_ragged_batch", "problems": len(probs),
-                   "boxes": [p.dims[0] for p in probs], "rhs": nrhs,
-                   "box_nodes_total": int(sum(np.prod(p.dims) * k for p, k in zip(probs, nrhs))),
+        "config": {"workload": "c4_ragged_batch", "problems": c["problems"],
+                   "boxes": c["boxes"], "rhs": c["rhs"], "box_nodes_total": c["box_nodes_total"],
                    "cg_iterations": a.c4_iters, "mode": a.mode,
                    "step": "fcrkpm_solve_batch from zero: f^r, CG blocks, residuals (no setup)"},
         "direct_launches": {"value": v_direct, "ms_per_step": 1e3 * t_direct,
