@@ -176,6 +176,7 @@ def main():
                   "matvecs_f64": infos[-1]["matvecs_f64"],
                   "true_rel_res": infos[-1]["true_rel_res"],
                   "fallback_used": infos[-1]["fallback_used"],
+                  "register_variant": infos[-1]["layout"],
                   "uh_rel_l2_vs_exact": uh_err},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

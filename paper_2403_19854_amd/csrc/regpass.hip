@@ -499,10 +499,101 @@ struct GPQ {
     }
 };
 
+// Line layout for L = 256 with 32 lanes per complex line: lane t holds points
+// t + 32m (m < 8) and, after the forward transform, frequencies t + 32i.
+// With t = t1 + 8 t2 (t1 < 8, t2 < 4) and k = k1 + 8 ka + 32 kb (k1 < 8,
+// ka < 4, kb < 8) the kernel W_256^(n k) of n = t + 32m factors into
+// W_8^(m k1) W_256^(t k1) W_4^(t2 ka) W_32^(t1 ka) W_8^(t1 kb).  Forward: a
+// DFT-8 over m in registers, the twiddle W_256^(t k1), a transpose through
+// LDS after which lane t1 + 8c holds the four t2 values of k1 = 2c and
+// 2c + 1, two DFT-4s over t2, the twiddle W_32^(t1 ka), a second transpose
+// after which lane k1 + 8 ka holds the eight t1 values, and a DFT-8 over t1.
+// The inverse runs the steps backwards with conjugate twiddles.  A lane keeps
+// 8 values per field throughout (the 16 x 16 layout keeps 16), so the
+// kernels that hold three or more fields fit twice the waves per SIMD.
+struct G32 {
+    static constexpr int LANES = 32, PTS = 8, SPTS = 8, L = 256;
+    static constexpr int S1 = 36, S2 = 33;  // pitches of the two transposes
+    static constexpr int XS = 8 * S1;       // covers both and PTS * LANES
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = SPTS * SS;
+    template <typename T = float>
+    using TwT = LdsTw<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecLds<T>;
+    static __device__ __forceinline__ int row(int t, int m) { return t + 32 * m; }
+    static __device__ __forceinline__ int freq(int t, int i) { return t + 32 * i; }
+    static __device__ __forceinline__ int lane_of(int k) { return k % 32; }
+    static __device__ __forceinline__ int slot_of(int k) { return k / 32; }
+    template <typename T>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+        dft8<T, +1>(v);
+#pragma unroll
+        for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], twid<+1>(w.tw, t * k1));
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) xb[k1 * S1 + t] = v[k1];
+        wave_sync();
+        const int t1 = t & 7, c = t >> 3;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) v[4 * e + t2] = xb[(2 * c + e) * S1 + t1 + 8 * t2];
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            dft4<T, +1>(v + 4 * e);
+#pragma unroll
+            for (int ka = 1; ka < 4; ++ka) v[4 * e + ka] = cmul(v[4 * e + ka], twid<+1>(w.tw, 8 * t1 * ka));
+#pragma unroll
+            for (int ka = 0; ka < 4; ++ka) xb[t1 * S2 + 2 * c + e + 8 * ka] = v[4 * e + ka];
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = xb[j * S2 + t];
+        wave_sync();
+        dft8<T, +1>(v);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+        dft8<T, -1>(v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xb[j * S2 + t] = v[j];
+        wave_sync();
+        const int t1 = t & 7, c = t >> 3;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+#pragma unroll
+            for (int ka = 0; ka < 4; ++ka) v[4 * e + ka] = xb[t1 * S2 + 2 * c + e + 8 * ka];
+        }
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+#pragma unroll
+            for (int ka = 1; ka < 4; ++ka) v[4 * e + ka] = cmul(v[4 * e + ka], twid<-1>(w.tw, 8 * t1 * ka));
+            dft4<T, -1>(v + 4 * e);
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) xb[(2 * c + e) * S1 + t1 + 8 * t2] = v[4 * e + t2];
+        }
+        wave_sync();
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) v[k1] = xb[k1 * S1 + t];
+        wave_sync();
+#pragma unroll
+        for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], twid<-1>(w.tw, t * k1));
+        dft8<T, -1>(v);
+    }
+};
+
 template <class Lay>
 struct is_gpq : std::false_type {};
 template <int P, int Q>
 struct is_gpq<GPQ<P, Q>> : std::true_type {};
+// layouts that run only with the line-constant middle pass
+template <class Lay>
+struct lineconst_only : std::integral_constant<bool, is_gpq<Lay>::value || std::is_same<Lay, G32>::value> {};
 
 // Term structure of the K d passes (Eq 55, 77-78): each term convolves input
 // `in` of a pass with the kernel t_e (part 1) or the reflected t_e (part 2)
@@ -2165,7 +2256,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.rec = reinterpret_cast<const float4*>(c.nrec[c.reg_layout]);
         if constexpr (B::DEGREE == 1) {
             constexpr bool SYM_LAYOUT = !std::is_same<Lay, G8<16>>::value;
-            if constexpr (is_gpq<Lay>::value) {
+            if constexpr (lineconst_only<Lay>::value) {
                 // the other box lengths run only with the line-constant middle pass
                 run_smid<Lay, float>(c, S2, slot_rb, S1, slot_rb, nrhs, st, prof);
             } else if (SYM_LAYOUT && sym_active(c)) {
@@ -2405,10 +2496,10 @@ bool reg_gpq_ok(const Ctx& c)
 
 // layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only);
 // for the P x Q lengths, layout 0 has 16 lanes per line and layout 1 (80 and 96
-// only) 8 lanes
+// only) 8 lanes; 256-point lines: layout 0 is 16 x 16, layout 1 the 32-lane G32
 int reg_layouts(const Ctx& c)
 {
-    if (reg_gpq_ok(c)) return (c.n[0] == 80 || c.n[0] == 96) ? 2 : 1;
+    if (reg_gpq_ok(c)) return (c.n[0] == 80 || c.n[0] == 96 || c.n[0] == 256) ? 2 : 1;
     return c.n[0] == 128 ? 2 : 1;
 }
 
@@ -2465,7 +2556,7 @@ bool reg_path_ok(const Ctx& c)
 }
 
 // The P x Q layout of a box length: 32 = 4 x 8, 48 = 6 x 8, 80 = 5 x 16 or
-// 10 x 8, 96 = 6 x 16 or 12 x 8, 256 = 16 x 16.  F(LAY) is called with it.
+// 10 x 8, 96 = 6 x 16 or 12 x 8, 256 = 16 x 16 or G32.  F(LAY) is called with it.
 template <class F>
 static void with_gpq(const Ctx& c, F&& f)
 {
@@ -2474,7 +2565,7 @@ static void with_gpq(const Ctx& c, F&& f)
         case 48: f(GPQ<6, 8>{}); break;
         case 80: if (c.reg_layout) f(GPQ<10, 8>{}); else f(GPQ<5, 16>{}); break;
         case 96: if (c.reg_layout) f(GPQ<12, 8>{}); else f(GPQ<6, 16>{}); break;
-        default: f(GPQ<16, 16>{}); break;
+        default: if (c.reg_layout) f(G32{}); else f(GPQ<16, 16>{}); break;
     }
 }
 
@@ -2494,11 +2585,11 @@ int reg_path_blocks(const Ctx& c)
 bool sym_ready(const Ctx& c);
 
 // FP64 lines fit the registers where a lane holds at most 8 complex values:
-// 64^3 and 128^3 boxes and the 32- and 48-point P x Q layouts
+// 64^3 and 128^3 boxes, the 32- and 48-point P x Q layouts and G32 at 256
 bool reg_path64_ok(const Ctx& c)
 {
-    // (80, 96 and 256 points would hold 10-16 FP64 values per lane and field)
-    const bool lay = reg_path_ok(c) || (reg_gpq_ok(c) && (c.n[0] == 32 || c.n[0] == 48));
+    // (80 and 96 points would hold 10-12 FP64 values per lane and field)
+    const bool lay = reg_path_ok(c) || (reg_gpq_ok(c) && (c.n[0] == 32 || c.n[0] == 48 || c.n[0] == 256));
     return c.degree == 1 && lay && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
 }
 
@@ -2506,6 +2597,7 @@ long reg_path64_blocks(const Ctx& c)
 {
     if (c.n[0] == 32) return blocks_of<GPQ<4, 8>>(c);
     if (c.n[0] == 48) return blocks_of<GPQ<6, 8>>(c);
+    if (c.n[0] == 256) return blocks_of<G32>(c);
     return c.n[0] == 128 ? blocks_of<G16L>(c) : blocks_of<G8<8>>(c);
 }
 
@@ -2515,6 +2607,7 @@ void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* 
     if (c.n[0] == 128) run_k64<G16L>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else if (c.n[0] == 32) run_k64<GPQ<4, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else if (c.n[0] == 48) run_k64<GPQ<6, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else if (c.n[0] == 256) run_k64<G32>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else run_k64<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
 }
 
@@ -2950,6 +3043,7 @@ void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, in
     if (c.n[0] == 128) run_kn<G16L>(c, in, out, kappa, mode, st);
     else if (c.n[0] == 32) run_kn<GPQ<4, 8>>(c, in, out, kappa, mode, st);
     else if (c.n[0] == 48) run_kn<GPQ<6, 8>>(c, in, out, kappa, mode, st);
+    else if (c.n[0] == 256) run_kn<G32>(c, in, out, kappa, mode, st);
     else run_kn<G8<8>>(c, in, out, kappa, mode, st);
 }
 

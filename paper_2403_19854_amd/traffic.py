@@ -44,7 +44,16 @@ _KINDS = [
     (_PASS + r"true, false, true, 2, 0" + _T64, "sep_part2_x_f64"),
 ]
 
-_LAYOUT = r"(G16L?|G8<\d+>|GPQ<\d+, \d+>)"
+_LAYOUT = r"(G16L?|G32|G8<\d+>|GPQ<\d+, \d+>)"
+
+
+def _layout_index(lay):
+    """Layout 1 is the 16-lane layout of 128-point lines, the 32-lane one of
+    256-point lines and the 8-lane P x Q layouts of 80 and 96 points."""
+    if lay.startswith(("G16", "G32")):
+        return 1
+    m = re.match(r"GPQ<\d+, (\d+)>", lay)
+    return 1 if m and m.group(1) == "8" and lay not in ("GPQ<4, 8>", "GPQ<6, 8>") else 0
 
 
 def _variant(name):
@@ -54,10 +63,10 @@ def _variant(name):
     m = re.search(r"k_rpass<[^<>]*?" + _LAYOUT + r", [^,]+, (\d)", name) or \
         re.search(r"k_rmid2?<[^<>]*?" + _LAYOUT + r", (\d)", name)
     if m:
-        return (1 if m.group(1).startswith("G16") else 0) + 2 * (int(m.group(2)) - 1)
+        return _layout_index(m.group(1)) + 2 * (int(m.group(2)) - 1)
     m = re.search(r"k_smid<[^<>]*?" + _LAYOUT, name)
     if m:
-        return 1 if m.group(1).startswith("G16") else 0
+        return _layout_index(m.group(1))
     return None
 
 

@@ -130,11 +130,13 @@ def test_config5_adjoint_against_finite_differences():
 
 def test_256_box_products_and_refined_solve():
     """Config 5's problem on a 256^3 box (working set above the last-level
-    cache; 256-point lines on the register path's 16 x 16 layout in FP32, the
-    LDS-tiled passes in FP64): K in both precisions against the oracle at
-    sampled nodes (Dirichlet faces included), FP32 against FP64 on the whole
-    field, and a refined solve whose solution the oracle's own operator
-    checks: ||chi_Omega (f^r - K d)|| / ||chi_Omega f^r|| on the free rows."""
+    cache; 256-point lines on the register path in both precisions, FP32 on
+    the 16 x 16 and the 32-lane layouts, FP64 on the 32-lane one): K in both
+    precisions against the oracle at sampled nodes (Dirichlet faces
+    included), FP32 (each layout) against FP64 on the whole field, the FP64
+    register path against the FP64 LDS-tiled passes, and a refined solve
+    whose solution the oracle's own operator checks: ||chi_Omega (f^r - K d)||
+    / ||chi_Omega f^r|| on the free rows."""
     p = W.config5_256()
     print(f"\n[256^3] dims={p.dims}", flush=True)
     g = lib_problem(p)
@@ -144,16 +146,29 @@ def test_256_box_products_and_refined_solve():
     idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(p.free.reshape(-1)), 48, replace=False),
                                   rng.choice(np.flatnonzero(p.dirichlet.reshape(-1)), 16, replace=False)]))
     xt = torch.from_numpy(x).to(DEV)
+    from paper_2403_19854_amd import fcrkpm
     k64 = to_np(g.apply("K_FULL", xt))
-    k32 = to_np(g.apply("K_FULL", xt.float())).astype(np.float64)
+    g.set_regpath(False)
+    k64_lds = to_np(g.apply("K_FULL", xt))
+    g.set_regpath(True)
     ref = o.apply_k_at(x, idx)
     scale = np.abs(ref).max()
     e64 = np.abs(k64.reshape(-1)[idx] - ref).max() / scale
-    e32 = np.abs(k32.reshape(-1)[idx] - ref).max() / scale
-    e3264 = np.abs(k32 - k64).max() / np.abs(k64).max()
-    print(f"  K vs oracle at 64 nodes: FP64 {e64:.2e}, FP32 {e32:.2e}; FP32 vs FP64 field {e3264:.2e}",
+    e64_lds = np.abs(k64 - k64_lds).max() / np.abs(k64_lds).max()
+    print(f"  K FP64 vs oracle at 64 nodes {e64:.2e}; register vs LDS-tiled FP64 field {e64_lds:.2e}",
           flush=True)
-    assert e64 <= 1e-11 and e32 <= 2e-5 and e3264 <= 2e-5
+    assert e64 <= 1e-11 and e64_lds <= 1e-12
+    assert np.all(k64[p.chi == 0] == 0.0)
+    chosen = g.get_option(fcrkpm.OPT_REGLAYOUT)
+    for lay in (0, 1):
+        g.set_option(fcrkpm.OPT_REGLAYOUT, lay)
+        k32 = to_np(g.apply("K_FULL", xt.float())).astype(np.float64)
+        e32 = np.abs(k32.reshape(-1)[idx] - ref).max() / scale
+        e3264 = np.abs(k32 - k64).max() / np.abs(k64).max()
+        print(f"  FP32 line layout {lay}: vs oracle at 64 nodes {e32:.2e}, vs FP64 field {e3264:.2e}",
+              flush=True)
+        assert e32 <= 2e-5 and e3264 <= 2e-5
+    g.set_option(fcrkpm.OPT_REGLAYOUT, chosen)
     r = torch.from_numpy(p.r).to(DEV)
     d, uh, info = g.solve(r, mode="f32_refined", tol=1e-10, maxit=60000)
     d = to_np(d)

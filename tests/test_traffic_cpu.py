@@ -74,6 +74,10 @@ def test_variant_parsing():
     assert traffic._variant("k_rmid<fcrkpm::G16, 2, 3, 3>") == 3
     assert traffic._variant("k_rmid2<fcrkpm::G16L, 1>") == 1
     assert traffic._variant("k_cg_xr<float>") is None
+    assert traffic._variant("k_smid<fcrkpm::G32, float>") == 1
+    assert traffic._variant("k_smid<fcrkpm::GPQ<16, 16>, float>") == 0
+    assert traffic._variant("k_rpass<fcrkpm::GPQ<10, 8>, fcrkpm::Lin3, 1, x>") == 1
+    assert traffic._variant("k_rpass<fcrkpm::GPQ<5, 16>, fcrkpm::Lin3, 1, x>") == 0
 
 
 SMID = ("void fcrkpm::(anonymous namespace)::k_smid<fcrkpm::(anonymous namespace)::G16, float>"
