@@ -851,12 +851,13 @@ void dots(Ctx& c, const T* a, const T* b, int nrhs, int idx, hipStream_t st)
 }
 
 // the register-resident product can fold the CG direction update into its
-// first pass (FP32 vectors and products only)
+// first pass (FP32 vectors and products only), and the p.q partials into its
+// last pass where its workgroups fit the partial slots
 template <typename T, typename TP>
 bool fused_cg(Ctx& c, int nrhs)
 {
     if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>)
-        return use_reg_path(c, nrhs) && reg_path_blocks(c) <= kRedBlocks;
+        return use_reg_path(c, nrhs);
     else
         return false;
 }
@@ -874,10 +875,13 @@ void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStrea
     int npq = red_blocks(c.nn);
     if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>) {
         if (fused) {
-            // the last pass of the product also leaves the p.q partials
+            // the last pass of the product also leaves the p.q partials when
+            // its workgroups fit the slots (else the dot runs on its own)
             RegPupd pu{r, rr_part, red_blocks(c.nn), c.scal, parity ^ 1, c.act};
-            reg_k(c, p, q, c.freem, nrhs, st, pq_part, p, pend ? &pu : nullptr);
-            npq = reg_path_blocks(c);
+            const bool dot = reg_path_blocks(c) <= kRedBlocks;
+            reg_k(c, p, q, c.freem, nrhs, st, dot ? pq_part : nullptr, dot ? p : nullptr, pend ? &pu : nullptr);
+            if (dot) npq = reg_path_blocks(c);
+            else launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
         } else {
             apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
             launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
