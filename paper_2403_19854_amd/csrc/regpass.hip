@@ -873,6 +873,12 @@ struct Tables {
     }
 };
 
+// Staging buffers of a layout's strided passes: two, alternated, so one
+// barrier per move suffices; one for the 32-lane layout, whose 256-point
+// tiles would otherwise hold the LDS to two workgroups per CU.
+template <class Lay>
+constexpr int stage_bufs() { return std::is_same<Lay, G32>::value ? 1 : 2; }
+
 // Strided passes move global memory in a row-major map: thread (gc, tc) =
 // (tid % GROUPS, tid / GROUPS) loads and stores the values of layout lane
 // (gc, tc), so GROUPS consecutive threads cover a whole row segment of the
@@ -886,6 +892,8 @@ struct Tables {
 template <class Lay, typename T>
 __device__ __forceinline__ void stage_move(cplx<T> (&v)[Lay::PTS], cplx<T>* buf, int gw, int tw, int gr, int tr)
 {
+    // with one buffer, the reads of the move before must finish first
+    if constexpr (stage_bufs<Lay>() == 1) __syncthreads();
 #pragma unroll
     for (int m = 0; m < Lay::SPTS; ++m) buf[m * Lay::SS + tw * Lay::TP + gw] = v[m];
     __syncthreads();
@@ -913,7 +921,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
     __shared__ T trl[Tables<Lay, B::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
     __shared__ double sh[kRT / 64];
-    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
+    __shared__ cf stage[STG ? stage_bufs<Lay>() : 1][STG ? Lay::STAGE : 1];
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
     const int gc = STG ? tid % Lay::GROUPS : g, tc = STG ? tid / Lay::GROUPS : t;
     const long rhs = blockIdx.y;
@@ -1033,7 +1041,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
     const long base = tile_base<Lay, CONTIG>(tile0 + tt, a.st);
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
-        if constexpr (STG) stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) & 1], gc, tc, g, t);
+        if constexpr (STG) stage_move<Lay>(Z[tt][f], stage[(tt * (NIN + NOUT) + f) % stage_bufs<Lay>()], gc, tc, g, t);
         Lay::fwd(Z[tt][f], t, xb, lw);
     }
 #pragma unroll
@@ -1041,7 +1049,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
         cf Y[R];
         combine<Lay, B, PART, J>(Z[tt], o, Y, sp);
         Lay::inv(Y, t, xb, lw);
-        if constexpr (STG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) & 1], g, t, gc, tc);
+        if constexpr (STG) stage_move<Lay>(Y, stage[(tt * (NIN + NOUT) + NIN + o) % stage_bufs<Lay>()], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < SP; ++m) {
             const long idx = elem_index<Lay, CONTIG>(base, gc, tc, m, a.st);
@@ -1567,7 +1575,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     __shared__ cf tw[L];
     __shared__ T trl[Tables<Lay, Lin3::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
-    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
+    __shared__ cf stage[STG ? stage_bufs<Lay>() : 1][STG ? Lay::STAGE : 1];
     __shared__ cf cbuf[Lay::GROUPS * CW];
     __shared__ SymTab tb;
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
@@ -1603,7 +1611,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     lw.make(t, tw);
     if constexpr (STG) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+        for (int f = 0; f < 3; ++f) stage_move<Lay>(X[f], stage[f % stage_bufs<Lay>()], gc, tc, g, t);
     }
     // window values of the three inputs
 #pragma unroll
@@ -1696,7 +1704,7 @@ __global__ __launch_bounds__(kRT) void k_smid(SArgs<T> a)
     }
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-        if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) & 1], g, t, gc, tc);
+        if constexpr (STG) stage_move<Lay>(Y[o], stage[(3 + o) % stage_bufs<Lay>()], g, t, gc, tc);
 #pragma unroll
         for (int m = 0; m < SP; ++m)
             store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), Y[o][m]);
@@ -1810,7 +1818,7 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
     __shared__ cf tw[L];
     __shared__ T trl[Tables<Lay, Lin3::NE, T>::LDS_SPEC];
     __shared__ cf xbuf[Lay::GROUPS * Lay::XS];
-    __shared__ cf stage[STG ? 2 : 1][STG ? Lay::STAGE : 1];
+    __shared__ cf stage[STG ? stage_bufs<Lay>() : 1][STG ? Lay::STAGE : 1];
     __shared__ cf cbuf[Lay::GROUPS * CW];
     __shared__ SymTab tb;
     const int tid = threadIdx.x, g = tid / Lay::LANES, t = tid % Lay::LANES;
@@ -1846,7 +1854,7 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
     lw.make(t, tw);
     if constexpr (STG) {
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) stage_move<Lay>(X[f], stage[f & 1], gc, tc, g, t);
+        for (int f = 0; f < NIN; ++f) stage_move<Lay>(X[f], stage[f % stage_bufs<Lay>()], gc, tc, g, t);
     }
     const bool mismatch = rec[KR::FLAG] != T(0);
     // the gradient's (or u^h's) values, or the nodal input of the load
@@ -1936,7 +1944,7 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
     if constexpr (MODE == KN_GRAD) {
 #pragma unroll
         for (int o = 0; o < ROWS; ++o) {
-            if constexpr (STG) stage_move<Lay>(Y[o], stage[(NIN + o) & 1], g, t, gc, tc);
+            if constexpr (STG) stage_move<Lay>(Y[o], stage[(NIN + o) % stage_bufs<Lay>()], g, t, gc, tc);
 #pragma unroll
             for (int m = 0; m < SP; ++m) {
                 // the pair's lines are adjacent: elements idx and idx + 1
@@ -2048,7 +2056,7 @@ __global__ __launch_bounds__(kRT) void k_smid_kn(KArgs<T> a)
         }
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
-            if constexpr (STG) stage_move<Lay>(X[o], stage[(NIN + o) & 1], g, t, gc, tc);
+            if constexpr (STG) stage_move<Lay>(X[o], stage[(NIN + o) % stage_bufs<Lay>()], g, t, gc, tc);
 #pragma unroll
             for (int m = 0; m < SP; ++m)
                 store_pair<L, false>(out + o * a.fstride, elem_index<Lay, false>(base, gc, tc, m, a.st), X[o][m]);
