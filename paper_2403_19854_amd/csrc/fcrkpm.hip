@@ -200,6 +200,7 @@ void release(Ctx& c)
     dfree(c.v64);
     dfree(c.v32);
     dfree(c.partial);
+    dfree(c.partial_wide);
     dfree(c.scal);
     dfree(c.act);
     dfree(c.nbits[0]);
@@ -822,6 +823,8 @@ void ensure_rhs(Ctx& c, int nrhs)
     c.v64 = dalloc<double>(6 * nn * nrhs);
     c.v32 = dalloc<float>(5 * nn * nrhs);
     c.partial = dalloc<double>((size_t)2 * kRedBlocks * nrhs);
+    dfree(c.partial_wide);
+    if (reg_dot_slots(c) > kRedBlocks) c.partial_wide = dalloc<double>((size_t)reg_dot_slots(c) * nrhs);
     c.scal = dalloc<double>((size_t)kScal * nrhs);
     c.act = dalloc<int>(nrhs);
     HIPCHK(hipMemset(c.scal, 0, sizeof(double) * kScal * nrhs));
@@ -875,22 +878,28 @@ void cg_iteration(Ctx& c, T* x, T* r, T* p, T* q, int nrhs, int parity, hipStrea
     int npq = red_blocks(c.nn);
     if constexpr (std::is_same_v<T, float> && std::is_same_v<TP, float>) {
         if (fused) {
-            // the last pass of the product also leaves the p.q partials when
-            // its workgroups fit the slots (else the dot runs on its own)
+            // the last pass of the product also leaves the p.q partials (in
+            // the wide slots, summed to one, when its workgroups outnumber
+            // kRedBlocks)
             RegPupd pu{r, rr_part, red_blocks(c.nn), c.scal, parity ^ 1, c.act};
-            const bool dot = reg_path_blocks(c) <= kRedBlocks;
-            reg_k(c, p, q, c.freem, nrhs, st, dot ? pq_part : nullptr, dot ? p : nullptr, pend ? &pu : nullptr);
-            if (dot) npq = reg_path_blocks(c);
-            else launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
+            const int nb = reg_path_blocks(c);
+            const bool wide = nb > kRedBlocks;
+            reg_k(c, p, q, c.freem, nrhs, st, wide ? c.partial_wide : pq_part, p, pend ? &pu : nullptr);
+            npq = wide ? 1 : nb;
+            if (wide) launch_reduce_wide(c.partial_wide, nb, reg_dot_slots(c), nrhs, pq_part, st);
         } else {
             apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
             launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);
         }
     } else if constexpr (std::is_same_v<T, double> && std::is_same_v<TP, double>) {
-        if (use_reg_path64(c) && reg_path64_blocks(c) <= kRedBlocks) {
-            // the last pass of the product leaves the p.q partials
-            reg_k64(c, p, q, c.freem, nrhs, st, pq_part, p);
-            npq = (int)reg_path64_blocks(c);
+        if (use_reg_path64(c)) {
+            // the last pass of the product leaves the p.q partials (wide
+            // slots as in FP32)
+            const int nb = (int)reg_path64_blocks(c);
+            const bool wide = nb > kRedBlocks;
+            reg_k64(c, p, q, c.freem, nrhs, st, wide ? c.partial_wide : pq_part, p);
+            npq = wide ? 1 : nb;
+            if (wide) launch_reduce_wide(c.partial_wide, nb, reg_dot_slots(c), nrhs, pq_part, st);
         } else {
             apply_one<TP, T>(c, FCRKPM_OP_K, p, q, nrhs, st);
             launch_dot_partial<T>(p, q, c.nn, nrhs, pq_part, c.act, st);

@@ -150,6 +150,8 @@ struct Ctx {
     double* v64 = nullptr;              // 6 FP64 vectors of cap_rhs fields
     float* v32 = nullptr;               // 5 FP32 vectors of cap_rhs fields
     double* partial = nullptr;          // reduction partials (2 x cap_rhs x kRedBlocks)
+    double* partial_wide = nullptr;     // p.q partials of a last pass with more workgroups
+                                        // than kRedBlocks (cap_rhs x reg_dot_slots)
     double* scal = nullptr;             // device scalars (cap_rhs x kScal)
     double* hscal = nullptr;            // pinned host mirror (2 poll slots + 1 read slot)
     int* act = nullptr;                 // per right-hand side: still iterating
@@ -269,6 +271,12 @@ long reg_path64_blocks(const Ctx& c);
 void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, int nrhs,
                     double* dot_part, const double* dot_with, hipStream_t st, const RegProf& prof);
 int reg_path_blocks(const Ctx& c);
+// partial slots per right-hand side of the register path's last-pass dot:
+// kRedBlocks where every variant's last pass fits them, else the most
+// workgroups any variant launches (no layout holds fewer than 16 lines per
+// workgroup); the dot partials of a launch with more workgroups than
+// kRedBlocks lie reg_dot_slots apart between right-hand sides
+long reg_dot_slots(const Ctx& c);
 int reg_layouts(const Ctx& c);
 bool reg_variant_ok(const Ctx& c, int v);
 long reg_bits_words(const Ctx& c, int layout);
@@ -327,6 +335,9 @@ template <typename T>
 void launch_dot_partial(const T* a, const T* b, long n, int nrhs, double* part, const int* act,
                         hipStream_t st);
 void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStream_t st);
+// dst[j * kRedBlocks] = the sum of nb partials at part + j * stride, in the
+// fixed order of the other reductions
+void launch_reduce_wide(const double* part, int nb, long stride, int nrhs, double* dst, hipStream_t st);
 template <typename T>
 void launch_cg_xr(T* x, T* r, const T* p, const T* q, long n, int nrhs, const double* pq_part,
                   int npq, double* scal, int parity, double* rr_part, const int* act,

@@ -390,6 +390,20 @@ void launch_reduce_to(const double* part, long n, int nrhs, double* dst, hipStre
                        dst);
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_reduce_wide(const double* __restrict__ part, int nb,
+                                                             long stride, double* dst)
+{
+    __shared__ double sh[16];
+    const int j = blockIdx.y;
+    double s = sum_partials(part + (long)j * stride, nb, sh);
+    if (threadIdx.x == 0) dst[(long)j * kRedBlocks] = s;
+}
+
+void launch_reduce_wide(const double* part, int nb, long stride, int nrhs, double* dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_wide, dim3(1, nrhs), dim3(kRedThreads), 0, st, part, nb, stride, dst);
+}
+
 // scalars of one right-hand side: [0], [1] = r.r (double-buffered by
 // parity), [3] = breakdown flag.  Right-hand sides with act[j] == 0 are
 // frozen: x, r, p and their scalars stay as they are.

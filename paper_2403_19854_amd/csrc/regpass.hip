@@ -715,6 +715,7 @@ struct RArgsT {
     const cplx<T>* tw;        // [L] e^{-2 pi i j / L}
     double* dot_part;         // masked store: per-workgroup partial of out . dot_with
     const T* dot_with;
+    long dot_stride;          // dot_part slots between right-hand sides
     const uint2* nbits;       // middle pass, per lane: .x bit 2m+c set if node c of element
                               // m is interior, .y bit m set if element m reads a record
     const uint32_t* noff;     // middle pass: per lane, its first record
@@ -1068,7 +1069,7 @@ __global__ __launch_bounds__(kRT) void k_rpass(RArgsT<T> a)
     if constexpr (SMASK) {
         if (a.dot_part) {
             const double s = block_sum(dacc, sh);
-            if (tid == 0) a.dot_part[rhs * kRedBlocks + blockIdx.x] = s;
+            if (tid == 0) a.dot_part[rhs * a.dot_stride + blockIdx.x] = s;
         }
     }
 }
@@ -2291,6 +2292,7 @@ void run_k(const Ctx& c, const float* in, float* out, const uint8_t* mask, int n
         a.mask_out = mask;
         a.dot_part = dot_part;
         a.dot_with = dot_with;
+        a.dot_stride = (long)grid.x <= kRedBlocks ? kRedBlocks : reg_dot_slots(c);
         rlaunch(prof, 4, k_rpass<Lay, B, TPW, true, false, true, 2, 0>, grid, block, st, a);
     }
 }
@@ -2338,6 +2340,7 @@ void run_k64(const Ctx& c, const double* in, double* out, const uint8_t* mask, i
         a.mask_out = mask;
         a.dot_part = dot_part;
         a.dot_with = dot_with;
+        a.dot_stride = (long)grid.x <= kRedBlocks ? kRedBlocks : reg_dot_slots(c);
         rlaunch(prof, 4, k_rpass<Lay, Lin3, 1, true, false, true, 2, 0, false, double>, grid, block, st, a);
     }
 }
@@ -2591,6 +2594,12 @@ int reg_path_blocks(const Ctx& c)
 }
 
 bool sym_ready(const Ctx& c);
+
+long reg_dot_slots(const Ctx& c)
+{
+    if (c.dim != 3) return kRedBlocks;
+    return std::max<long>(kRedBlocks, c.nn / c.n[0] / 16);
+}
 
 // FP64 lines fit the registers where a lane holds at most 8 complex values:
 // 64^3 and 128^3 boxes, the 32- and 48-point P x Q layouts and G32 at 256
