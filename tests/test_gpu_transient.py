@@ -214,7 +214,7 @@ def test_register_path_mass_and_implicit_step(n):
     """The register-resident passes with the mass rows and the shifted rows
     (linear basis; the sets carry their own line-constant records, so the P x Q
     boxes take the register path too, and FP64 runs on the FP64 register path
-    at 32-128 points except 96): M in FP32 and FP64 against the oracle over the
+    at 32-128 points except 96; 256 points in the test below): M in FP32 and FP64 against the oracle over the
     whole box, and one refined implicit step against the FP64 step, which the
     small cases pin to the oracle."""
     p = W.cube(3, n, 2.5, 1)
@@ -243,3 +243,32 @@ def test_register_path_mass_and_implicit_step(n):
           f"{i64['iters']} FP64 iterations")
     assert err <= 1e-8
     assert info["fallback_used"] == 0
+
+
+def test_register_path_mass_256():
+    """The consistent mass on a 256^3 box: FP32 on both 256-point layouts (16 x
+    16 and 32 lanes x 8) and FP64 on the 32-lane FP64 register path, against
+    the oracle over the whole box and against the LDS-tiled passes."""
+    from paper_2403_19854_amd import fcrkpm
+    p = W.cube(3, 256, 2.5, 1)
+    print("\n[register path mass 256^3]", flush=True)
+    o = orc(p)
+    g = lib_problem(p)
+    x = rand_field(p, 61)
+    xt = torch.from_numpy(x).to(DEV)
+    ref = o.apply_m(x)
+    m64 = to_np(g.apply("M", xt))
+    g.set_regpath(False)
+    lds64 = to_np(g.apply("M", xt))
+    g.set_regpath(True)
+    e64, e64_lds = rel_max(m64, ref), rel_max(m64, lds64)
+    print(f"  M fp64: vs oracle {e64:.2e}, vs LDS-tiled {e64_lds:.2e} (rel-max)", flush=True)
+    assert e64 <= 1e-11 and e64_lds <= 1e-12
+    chosen = g.get_option(fcrkpm.OPT_REGLAYOUT)
+    for lay in (0, 1):
+        g.set_option(fcrkpm.OPT_REGLAYOUT, lay)
+        m32 = to_np(g.apply("M", xt.float())).astype(np.float64)
+        e32 = rel_max(m32, ref)
+        print(f"  M fp32, line layout {lay}: vs oracle {e32:.2e}", flush=True)
+        assert e32 <= 2e-5
+    g.set_option(fcrkpm.OPT_REGLAYOUT, chosen)
