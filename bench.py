@@ -125,8 +125,11 @@ def main():
     t0 = time.perf_counter()
     infos = []
     prof_acc = {}
+    step_ms = []
     for i in range(a.steps):
+        ts = time.perf_counter()
         info, prof, uh, d_final = step(a.mode, profile=True)
+        step_ms.append(1e3 * (time.perf_counter() - ts))
         infos.append(info)
         for k, (n, ms, by) in prof.items():
             n0, w0, b0 = prof_acc.get(k, (0, 0.0, 0.0))
@@ -134,6 +137,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    clocks = gpu_clocks()
     matvecs = sum(i["matvecs_f32"] + i["matvecs_f64"] for i in infos)
     value = matvecs / elapsed
     n_free = wl.n_free
@@ -158,6 +162,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": 1e3 * elapsed / a.steps,
+        "step_ms_median_iqr": [float(np.median(step_ms))] + [float(v) for v in np.percentile(step_ms, [25, 75])],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -183,6 +188,7 @@ def main():
                      "traffic": traffic.load(wl.name, dom, infos[-1]["layout"]),
                      "mean_ms": dk["mean_ms"], "bytes_per_launch": dk["bytes_per_launch"]},
         "kernels": kernels,
+        "gpu_clocks": clocks,
     }
 
     if not a.no_fp64_compare and a.mode != "f64":
@@ -520,9 +526,27 @@ def apply_loop(wl, chi, dirm, vol, dev, reps=20, warm=5, op="K"):
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         med = float(np.median(ts))
-        res[name] = {"median_ms": med, "matvecs_per_s": 1e3 / med}
+        q1, q3 = (float(v) for v in np.percentile(ts, [25, 75]))
+        res[name] = {"median_ms": med, "iqr_ms": [q1, q3], "matvecs_per_s": 1e3 / med}
     pb.close()
     return res
+
+
+def gpu_clocks():
+    """The GPU's current clocks as rocm-smi reports them (None where it is not
+    available): read right after the timed region."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        d = json.loads(r.stdout)
+    except Exception:
+        return None
+    card = next(iter(d.values()), {}) if isinstance(d, dict) and d else {}
+    if not isinstance(card, dict):
+        return None
+    clk = {k.rstrip(":").strip(): v for k, v in card.items() if "clk" in k.lower() or "clock" in k.lower()}
+    return clk or None
 
 
 def probe(a, wl):
