@@ -231,6 +231,7 @@ def cpu_baseline(a, wl, gpu_iters=None, d_fixed=None):
     * value: K products per second with all its threads, over about
       --cpu-seconds of products;
     * one_thread: one K product on one thread;
+    * fr_s, uh_s: one f^r and one u^h with all its threads;
     * solve / adjoint: its CG solve of the load (Alg 5) and its adjoint solve to
       the bench tolerance; on boxes above 64^3 both are capped at --cpu-cg-cap
       iterations and the time at the GPU's FP64 iteration count is extrapolated
@@ -269,6 +270,13 @@ def cpu_baseline(a, wl, gpu_iters=None, d_fixed=None):
         oracle.threads(threads)
     res["one_thread"] = {"value": 1.0 / t1, "unit": "matvec/s", "cores": 1,
                          "sample": "one oracle K product on one thread"}
+    # the load f^r (Alg 4) and the field u^h (Alg 3), once each, all threads
+    t0 = time.perf_counter()
+    o.apply_fr(wl.r)
+    t_fr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.apply_uh(x)
+    res["fr_s"], res["uh_s"] = t_fr, time.perf_counter() - t0
     big = int(np.prod(wl.dims)) > 64 ** 3
     cap = a.cpu_cg_cap if big else a.maxit
     t0 = time.perf_counter()

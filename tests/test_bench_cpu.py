@@ -19,6 +19,7 @@ def test_cpu_baseline_fields():
     assert res["kind"] == "oracle" and res["unit"] == "matvec/s"
     assert res["value"] > 0 and res["cores"] == threads
     assert res["one_thread"]["cores"] == 1 and res["one_thread"]["value"] > 0
+    assert res["fr_s"] > 0 and res["uh_s"] > 0
     assert oracle.threads(0) == threads          # the thread count is restored
     sol = res["solve"]
     assert sol["rel_res"] <= 1e-12 and "capped_at" not in sol
