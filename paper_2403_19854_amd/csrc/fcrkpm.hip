@@ -473,9 +473,9 @@ void part2(Ctx& c, const SepPlan& sp, cplx<T>* cur, cplx<T>* S1, cplx<T>* S2, Ti
     }
 }
 
-// The register-resident FP32 K product applies to 64^3 and 128^3 boxes with
-// the linear basis (the choice never depends on nrhs, so a batched product
-// equals the single ones bit for bit).
+// The register-resident FP32 K product applies to cubic boxes of the
+// register-path lengths (the choice never depends on nrhs, so a batched
+// product equals the single ones bit for bit).
 bool use_reg_path(const Ctx& c, int /*nrhs*/)
 {
     static int env = -1;
@@ -485,7 +485,8 @@ bool use_reg_path(const Ctx& c, int /*nrhs*/)
     }
     if (env != 1 || !c.use_regpath) return false;
     // 64^3 and 128^3 boxes: per-node records or the line-constant middle pass;
-    // the other lengths of the P x Q layouts: the line-constant pass only
+    // the other lengths (P x Q layouts, the 32-lane 256-point layout): the
+    // line-constant pass only
     if (reg_path_ok(c)) return c.nrec[c.reg_layout] != nullptr;
     return reg_gpq_ok(c) && sym_active(c);
 }

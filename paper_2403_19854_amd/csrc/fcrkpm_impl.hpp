@@ -209,9 +209,9 @@ void launch_sep_mid(const Ctx& c, int a, const SepProg& pr1, const SepProg* dpr1
                     const T* vol, double* dot_part, const void* dot_with, hipStream_t st,
                     const RhsBatch& rb = RhsBatch{});
 
-// Register-resident passes of the FP32 K product (regpass.hip) for 3D boxes
-// of 64^3 or 128^3 nodes and the linear basis.  `prof` brackets the five
-// launches (x, y, middle z, y, x) for the kernel-duration sampler.
+// Register-resident passes of the K-type products (regpass.hip) for cubic 3D
+// boxes of the register-path lengths.  `prof` brackets the five launches (x,
+// y, middle z, y, x) for the kernel-duration sampler.
 // Duration sampling of the register passes: for pass k (0..4) of a launch,
 // events() counts the launch and either leaves both events null or hands out
 // the pair that the launch itself records (hipExtLaunchKernelGGL), so the
@@ -254,10 +254,11 @@ void sym_release(Ctx& c);
 void sym_release_state(void*& sym);
 // algorithmic bytes of one launch of that middle pass per right-hand side
 double sym_pass_bytes(const Ctx& c, int elem_bytes);
-// The FP64 K product on the register path (linear basis, 32^3, 48^3, 64^3 or 128^3 boxes
-// with the line-constant middle pass): reg_path64_ok tells whether it
-// applies; with dot_part the last pass also leaves the per-workgroup partials
-// of out . dot_with (reg_path64_blocks of them per right-hand side).
+// The FP64 K product on the register path (linear basis, 32^3, 48^3, 64^3,
+// 128^3 or 256^3 boxes with the line-constant middle pass): reg_path64_ok
+// tells whether it applies; with dot_part the last pass also leaves the
+// per-workgroup partials of out . dot_with (reg_path64_blocks of them per
+// right-hand side, kRedBlocks or reg_dot_slots apart).
 bool reg_path64_ok(const Ctx& c);
 // The force of the gradient nonlinearity, the implicit gradient B d, u^h and the
 // load f^r on the FP64 register path (line-constant middle passes; the force

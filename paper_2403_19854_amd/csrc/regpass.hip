@@ -1,6 +1,9 @@
-// regpass.hip -- register-resident separable passes of the FP32 stiffness
-// product K d (Alg 2) on 3D boxes whose axes are 64 or 128 nodes long, for
-// the linear basis.
+// regpass.hip -- register-resident separable passes of the K-type products
+// (Alg 2; the consistent mass and the other operator sets with their own
+// coefficient rows), u^h (Alg 3), the load f^r (Alg 4) and the gradient force
+// (Alg B.1) on cubic 3D boxes of 32, 48, 64, 80, 96, 128 and 256 points per
+// axis: FP32 with the linear basis at every one of them and the quadratic
+// basis at 64 and 128, FP64 with the linear basis at 32, 48, 64, 128 and 256.
 //
 // A complex line packs two adjacent real lines of one field: the real part is
 // line w, the imaginary part line w+1.  Every 1D kernel array t_e is real
@@ -9,7 +12,7 @@
 // spectrum is real or imaginary and one float per frequency describes it.
 //
 // A complex line of L points is owned by a group of lanes that hold it in
-// registers, in one of two layouts:
+// registers; the layouts of 64 and 128 points are:
 //   G8<R>: 8 lanes, lane t holds points t + 8m (m < R, L = 8R).  A transform
 //          is a DFT-R in registers, a twiddle, one transpose through LDS and
 //          DFT-8s in registers (four-step FFT).
@@ -20,7 +23,9 @@
 //          is hidden; a setup-time measurement picks between the two.
 // Either way the data crosses LDS once per transform instead of once per
 // radix stage, and the spectral products, the inverse transforms and the
-// pointwise stage of the middle pass all act on registers.
+// pointwise stage of the middle pass all act on registers.  The other lengths
+// use the P x Q layouts (GPQ) and, at 256 points, also a 32-lane layout with
+// two transposes (G32); they run only with the line-constant middle pass.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
