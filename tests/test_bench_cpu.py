@@ -26,3 +26,25 @@ def test_cpu_baseline_fields():
     assert res["adjoint"]["iterations"] > 0
     # d = 0 leaves the whole load as the residual
     assert abs(res["oracle_rel_res"] - 1.0) < 1e-12
+
+
+def test_gpu_clocks_parsing(monkeypatch):
+    """The bench's clock report keeps rocm-smi's clock entries of the first
+    card and gives None when the tool is missing or prints no JSON."""
+    import subprocess
+
+    sample = ('{"card0": {"mclk clock speed:": "(2000Mhz)", "mclk clock level:": "0", '
+              '"sclk clock speed:": "(2400Mhz)", "sclk clock level:": "1", "PCI Bus": "x"}}')
+    monkeypatch.setattr(subprocess, "run",
+                        lambda *a, **k: types.SimpleNamespace(stdout=sample, returncode=0))
+    got = bench.gpu_clocks()
+    assert got == {"mclk clock speed": "(2000Mhz)", "mclk clock level": "0",
+                   "sclk clock speed": "(2400Mhz)", "sclk clock level": "1"}
+    monkeypatch.setattr(subprocess, "run",
+                        lambda *a, **k: types.SimpleNamespace(stdout="not json", returncode=1))
+    assert bench.gpu_clocks() is None
+
+    def missing(*a, **k):
+        raise FileNotFoundError("rocm-smi")
+    monkeypatch.setattr(subprocess, "run", missing)
+    assert bench.gpu_clocks() is None
