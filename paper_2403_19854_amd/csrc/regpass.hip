@@ -504,6 +504,88 @@ struct GPQ {
     }
 };
 
+// Line layout for L = 16 P (P = 5, 6: 80 and 96 points) with 16 lanes per
+// complex line, the 16-lane layout's transform with a DFT-P first: lane t
+// holds points t + 16m (m < P); a DFT-P over m, the twiddle W_L^(t k1), a
+// transpose through LDS that gives lane k1 + 8h (k1 < P) the values of lanes
+// 8h .. 8h+7 at k1, a radix-2 step between the lane halves (DPP row
+// rotation), the twiddle W_16^(tl h) and a DFT-8: lane k1 + 8h then holds
+// frequencies k1 + P (h + 2i).  Lanes with k1 >= P idle through the second
+// stage.  A lane holds 8 values per field where the 6 x 16 and 5 x 16 P x Q
+// layouts hold 16, so FP64 lines fit; tiles are positioned pair by pair as
+// the P x Q layouts' are (32 lines do not divide 80 or 96).
+template <int P_>
+struct G16P {
+    static constexpr int P = P_, LANES = 16, PTS = 8, SPTS = P, L = 16 * P, XS = 136;
+    static constexpr int GROUPS = kRT / LANES, LINES = 2 * GROUPS;
+    static constexpr int TP = GROUPS + 1, SS = LANES * TP, STAGE = SPTS * SS;
+    template <typename T = float>
+    using TwT = LdsTw<T>;
+    typedef TwT<float> Tw;
+    template <int NE, typename T = float>
+    using Spec = SpecLds<T>;
+    static __device__ __forceinline__ int row(int t, int m) { return t + 16 * m; }
+    static __device__ __forceinline__ int freq(int t, int i)
+    {
+        const int k1 = t & 7;
+        return k1 < P ? k1 + P * ((t >> 3) + 2 * i) : 0;
+    }
+    static __device__ __forceinline__ int lane_of(int k) { return k % P + 8 * ((k / P) & 1); }
+    static __device__ __forceinline__ int slot_of(int k) { return (k / P) >> 1; }
+    template <typename T>
+    static __device__ __forceinline__ void fwd(cplx<T> (&v)[8], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+        typedef cplx<T> cf;
+        dft_small<P, +1>(v, w.tw, L);
+#pragma unroll
+        for (int k1 = 1; k1 < P; ++k1) v[k1] = cmul(v[k1], twid<+1>(w.tw, t * k1));
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) xb[k1 * 17 + t] = v[k1];
+        wave_sync();
+        const int k1 = t & 7, h = t >> 3;
+#pragma unroll
+        for (int tl = 0; tl < 8; ++tl) v[tl] = xb[k1 * 17 + 8 * h + tl];
+        wave_sync();
+        const T s = h ? T(-1) : T(1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const cf u = {swap8(v[i].x), swap8(v[i].y)};
+            v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
+        }
+        if (h) {
+#pragma unroll
+            for (int tl = 1; tl < 8; ++tl) v[tl] = mul_w16<+1>(v[tl], tl);
+        }
+        dft8<T, +1>(v);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void inv(cplx<T> (&v)[8], int t, cplx<T>* xb, const LdsTw<T>& w)
+    {
+        typedef cplx<T> cf;
+        const int k1 = t & 7, h = t >> 3;
+        dft8<T, -1>(v);
+        if (h) {
+#pragma unroll
+            for (int tl = 1; tl < 8; ++tl) v[tl] = mul_w16<-1>(v[tl], tl);
+        }
+        const T s = h ? T(-1) : T(1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const cf u = {swap8(v[i].x), swap8(v[i].y)};
+            v[i] = cf{u.x + s * v[i].x, u.y + s * v[i].y};
+        }
+        // lanes with k1 >= P carry nothing; their rows are never read
+        const int kk = k1 < P ? k1 : 0;
+#pragma unroll
+        for (int tl = 0; tl < 8; ++tl) xb[k1 * 17 + tl + 8 * h] = cmul(v[tl], twid<-1>(w.tw, (tl + 8 * h) * kk));
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = xb[j * 17 + t];
+        wave_sync();
+        dft_small<P, -1>(v, w.tw, L);
+    }
+};
+
 // Line layout for L = 256 with 32 lanes per complex line: lane t holds points
 // t + 32m (m < 8) and, after the forward transform, frequencies t + 32i.
 // With t = t1 + 8 t2 (t1 < 8, t2 < 4) and k = k1 + 8 ka + 32 kb (k1 < 8,
@@ -596,6 +678,8 @@ template <class Lay>
 struct is_gpq : std::false_type {};
 template <int P, int Q>
 struct is_gpq<GPQ<P, Q>> : std::true_type {};
+template <int P>
+struct is_gpq<G16P<P>> : std::true_type {};
 // layouts that run only with the line-constant middle pass
 template <class Lay>
 struct lineconst_only : std::integral_constant<bool, is_gpq<Lay>::value || std::is_same<Lay, G32>::value> {};
@@ -2511,8 +2595,9 @@ bool reg_gpq_ok(const Ctx& c)
 }
 
 // layout 0: G8 (8 lanes per line), layout 1: G16 (16 lanes, 128-point lines only);
-// for the P x Q lengths, layout 0 has 16 lanes per line and layout 1 (80 and 96
-// only) 8 lanes; 256-point lines: layout 0 is 16 x 16, layout 1 the 32-lane G32
+// for the P x Q lengths, layout 0 has 16 lanes per line (G16P at 80 and 96) and
+// layout 1 (80 and 96 only) 8 lanes; 256-point lines: layout 0 is 16 x 16,
+// layout 1 the 32-lane G32
 int reg_layouts(const Ctx& c)
 {
     if (reg_gpq_ok(c)) return (c.n[0] == 80 || c.n[0] == 96 || c.n[0] == 256) ? 2 : 1;
@@ -2571,16 +2656,16 @@ bool reg_path_ok(const Ctx& c)
     return c.degree == 1 ? plan_matches<Lin3>(c) : plan_matches<Quad3>(c);
 }
 
-// The P x Q layout of a box length: 32 = 4 x 8, 48 = 6 x 8, 80 = 5 x 16 or
-// 10 x 8, 96 = 6 x 16 or 12 x 8, 256 = 16 x 16 or G32.  F(LAY) is called with it.
+// The layout of a box length: 32 = 4 x 8, 48 = 6 x 8, 80 = G16P<5> or 10 x 8,
+// 96 = G16P<6> or 12 x 8, 256 = 16 x 16 or G32.  F(LAY) is called with it.
 template <class F>
 static void with_gpq(const Ctx& c, F&& f)
 {
     switch (c.n[0]) {
         case 32: f(GPQ<4, 8>{}); break;
         case 48: f(GPQ<6, 8>{}); break;
-        case 80: if (c.reg_layout) f(GPQ<10, 8>{}); else f(GPQ<5, 16>{}); break;
-        case 96: if (c.reg_layout) f(GPQ<12, 8>{}); else f(GPQ<6, 16>{}); break;
+        case 80: if (c.reg_layout) f(GPQ<10, 8>{}); else f(G16P<5>{}); break;
+        case 96: if (c.reg_layout) f(GPQ<12, 8>{}); else f(G16P<6>{}); break;
         default: if (c.reg_layout) f(G32{}); else f(GPQ<16, 16>{}); break;
     }
 }
@@ -2607,11 +2692,11 @@ long reg_dot_slots(const Ctx& c)
 }
 
 // FP64 lines fit the registers where a lane holds at most 8 complex values:
-// 64^3 and 128^3 boxes, the 32- and 48-point P x Q layouts and G32 at 256
+// 64^3 and 128^3 boxes, the 32- and 48-point P x Q layouts, the 16-lane
+// layouts of 80 and 96 points (G16P) and G32 at 256
 bool reg_path64_ok(const Ctx& c)
 {
-    // (80 and 96 points would hold 10-12 FP64 values per lane and field)
-    const bool lay = reg_path_ok(c) || (reg_gpq_ok(c) && (c.n[0] == 32 || c.n[0] == 48 || c.n[0] == 256));
+    const bool lay = reg_path_ok(c) || reg_gpq_ok(c);
     return c.degree == 1 && lay && sym_ready(c) && c.rtab64[0] && c.rtab64[1] && c.rtab64[2];
 }
 
@@ -2619,6 +2704,8 @@ long reg_path64_blocks(const Ctx& c)
 {
     if (c.n[0] == 32) return blocks_of<GPQ<4, 8>>(c);
     if (c.n[0] == 48) return blocks_of<GPQ<6, 8>>(c);
+    if (c.n[0] == 80) return blocks_of<G16P<5>>(c);
+    if (c.n[0] == 96) return blocks_of<G16P<6>>(c);
     if (c.n[0] == 256) return blocks_of<G32>(c);
     return c.n[0] == 128 ? blocks_of<G16L>(c) : blocks_of<G8<8>>(c);
 }
@@ -2629,6 +2716,8 @@ void launch_reg_k64(const Ctx& c, const double* in, double* out, const uint8_t* 
     if (c.n[0] == 128) run_k64<G16L>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else if (c.n[0] == 32) run_k64<GPQ<4, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else if (c.n[0] == 48) run_k64<GPQ<6, 8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else if (c.n[0] == 80) run_k64<G16P<5>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
+    else if (c.n[0] == 96) run_k64<G16P<6>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else if (c.n[0] == 256) run_k64<G32>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
     else run_k64<G8<8>>(c, in, out, mask, nrhs, dot_part, dot_with, st, prof);
 }
@@ -3065,6 +3154,8 @@ void launch_reg_kn(const Ctx& c, const double* in, double* out, double kappa, in
     if (c.n[0] == 128) run_kn<G16L>(c, in, out, kappa, mode, st);
     else if (c.n[0] == 32) run_kn<GPQ<4, 8>>(c, in, out, kappa, mode, st);
     else if (c.n[0] == 48) run_kn<GPQ<6, 8>>(c, in, out, kappa, mode, st);
+    else if (c.n[0] == 80) run_kn<G16P<5>>(c, in, out, kappa, mode, st);
+    else if (c.n[0] == 96) run_kn<G16P<6>>(c, in, out, kappa, mode, st);
     else if (c.n[0] == 256) run_kn<G32>(c, in, out, kappa, mode, st);
     else run_kn<G8<8>>(c, in, out, kappa, mode, st);
 }

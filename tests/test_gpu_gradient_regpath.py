@@ -5,7 +5,7 @@ coefficients B_L and divergence coefficients V_L B_L in the spectral domain,
 N node by node between them, and corrects the nodes near the domain's z ends
 with the kernel's taps.  Checked against the LDS-tiled FP64 pass (register
 path off), against the oracle's force on the whole field, at kappa = 0 against
-K d, on cubes of 32, 48, 64, 128 and 256 points, supports 1.5h-2.5h, and on box
+K d, on cubes of 32, 48, 64, 80, 128 and 256 points, supports 1.5h-2.5h, and on box
 domains whose x and y extents end at other positions (line pairs whose two
 lines have different constants).  u^h and f^r run the same machinery with the
 single row b^0 and are checked the same way."""
@@ -59,6 +59,8 @@ CASES = {
     "box48_odd_extents": lambda: box_domain(48, 2.5, (45, 33, 46)),
     "cube128_support2p5": lambda: W.cube(3, 128, 2.5, 1),
     "cube256_support2p5": lambda: W.cube(3, 256, 2.5, 1),
+    "cube80_support2p5": lambda: W.cube(3, 80, 2.5, 1),
+    "box96_odd_extents": lambda: box_domain(96, 2.5, (93, 81, 94)),
 }
 
 

@@ -120,7 +120,8 @@ def test_line_constant_middle_pass(name):
 
 @pytest.mark.parametrize("name", ["cube64_support2p5", "cube128_support2p5", "box128_odd_extents",
                                   "paper_shape128_support1p5", "cube64_support2_config2",
-                                  "cube32_support2p5", "cube48_support2p5"])
+                                  "cube32_support2p5", "cube48_support2p5", "cube80_support2p5",
+                                  "cube96_support2p5", "box96_odd_extents"])
 def test_fp64_register_path(name):
     """The FP64 K product on the register path (FP64 lines, the line-constant
     middle pass) against the FP64 LDS-tiled passes and the oracle, to the FP64

@@ -213,8 +213,8 @@ def test_transient_argument_errors():
 def test_register_path_mass_and_implicit_step(n):
     """The register-resident passes with the mass rows and the shifted rows
     (linear basis; the sets carry their own line-constant records, so the P x Q
-    boxes take the register path too, and FP64 runs on the FP64 register path
-    at 32-128 points except 96; 256 points in the test below): M in FP32 and FP64 against the oracle over the
+    boxes take the register path too, and FP64 runs on the FP64 register path;
+    256 points in the test below): M in FP32 and FP64 against the oracle over the
     whole box, and one refined implicit step against the FP64 step, which the
     small cases pin to the oracle."""
     p = W.cube(3, n, 2.5, 1)
