@@ -464,17 +464,19 @@ enum {
                                 points with the linear basis and at 64 and 128 with the
                                 quadratic basis (K only); FP64 (K, the consistent mass, the
                                 gradient force, the implicit gradient, u^h and f^r) at 32, 48,
-                                64, 128 and 256 points with the linear basis and the
+                                64, 80, 96, 128 and 256 points with the linear basis and the
                                 line-constant middle pass; 0: the LDS-tiled passes used
                                 everywhere else */
     FCRKPM_OPT_REGLAYOUT = 3, /* variant of those transforms, layout + 2 (tiles - 1): layout 0 =
                                  8 lanes per line, 1 = 16 lanes (128-point lines only); at 80
-                                 and 96 points layout 0 = 16 lanes, 1 = 8 lanes; at 256 points
+                                 and 96 points layout 0 = 16 lanes x 8 values (a DFT-5 or
+                                 DFT-6 first stage), 1 = 8 lanes; at 256 points
                                  layout 0 = 16 lanes x 16 points, 1 = 32 lanes x 8 points;
                                  tiles = 1 or 2 tiles per workgroup (64 and 128 points; the
                                  second tile's loads overlap the first tile's work).  Setup
                                  times a K product with each variant and keeps the fastest.
-                                 FP64 products at 256 points use the 32-lane layout. */
+                                 FP64 products use the 16-lane layout at 80 and 96 points and
+                                 the 32-lane one at 256. */
     FCRKPM_OPT_TUNE_NS0 = 4, /* read only: setup's time of one K product with variant 0, ns */
     FCRKPM_OPT_TUNE_NS1 = 5, /* read only: the same with variant 1 (0 where not timed) */
     FCRKPM_OPT_TUNE_NS2 = 6, /* read only: the same with variant 2 */
